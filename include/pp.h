@@ -1,0 +1,161 @@
+/*
+ * pp.h - C ABI of the MI355X pressure-Poisson tree-code library.
+ *
+ * The library evaluates the free-space Green's-function solution of the 2-D
+ * pressure Poisson equation (Verma et al., "Computing the force distribution on
+ * the surface of complex, deforming geometries using vortex methods and
+ * Brinkman penalization", Appendix A):
+ *
+ *     P(t_j) = sum_i G(t_j, s_i) f(s_i) h^2,      G(x, x') = (1/2pi) ln|x - x'|
+ *
+ * (eq. greenSum with the kernel of eq. green2D) for sources f on a uniform
+ * Cartesian grid and arbitrary target points: grid nodes (the full-field
+ * evaluation of Sec. 3.3), body-surface points (Sec. 2.3.1) or lifted-surface
+ * points (Sec. 2.3.2).  The sum is evaluated with a quadtree and multipole /
+ * local expansions (eq. alphaK, eq. pressTruncated, eq. expandedShift) plus a
+ * direct near field, all in hand-written HIP kernels for gfx950.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * - Grid: f is ny*nx doubles, row-major (f[j*nx + i]); node (i, j) lies at
+ *   (x0 + (i + 1/2) h, y0 + (j + 1/2) h).  Nodes with f == 0 are skipped.
+ *   Limits: 1 <= nx, ny <= 65536 and nx*ny < 2^31.
+ * - Root square: anchored at (x0, y0), side 2^k h with 2^k >= max(nx, ny).
+ *   Every target must lie inside it (half-open), else PP_ERR_DOMAIN.
+ * - Pointers: every input and output may be host memory or device memory of
+ *   the context's device (detected with hipPointerGetAttributes).  The caller
+ *   owns all buffers; inputs are only read; p_out (m doubles, the caller's
+ *   target order) is written only when the call returns PP_OK.
+ * - Streams: work is enqueued on `hip_stream` (a hipStream_t, or NULL for the
+ *   default stream) and the call returns after it has completed.
+ * - Self-interaction (a target that coincides exactly, in FP64, with a grid
+ *   node x0 + (i + 1/2) h; the paper does not treat it): PP_SELF_SKIP drops the
+ *   node, PP_SELF_CELLAVG adds w (ln h - kappa) / 2pi, the mean of the kernel
+ *   over the node's h x h cell (kappa = 3/2 - pi/4 + ln(2)/2).
+ * - Errors: functions never throw; they return a pp_status and leave a message
+ *   for pp_last_error().  PP_ERR_DEVICE poisons the context (destroy it).
+ * - Threads: a context serves one host thread at a time.
+ */
+#ifndef PP_H_
+#define PP_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pp_ctx pp_ctx;
+typedef int32_t pp_status;
+
+enum {
+  PP_OK = 0,
+  PP_ERR_ARG = -1,     /* null pointer, bad size, non-finite input, bad parameter */
+  PP_ERR_DOMAIN = -2,  /* a target lies outside the root square */
+  PP_ERR_NOMEM = -3,   /* the solve would exceed the context's device-memory budget */
+  PP_ERR_DEVICE = -4,  /* a HIP call failed; the context is unusable */
+  PP_ERR_LIMIT = -5    /* the tree exceeded an internal limit (e.g. traversal frontier) */
+};
+
+enum { PP_FP64 = 0, PP_MIXED = 1 };            /* MIXED: P2P and L2P in FP32 (Kahan), expansions FP64 */
+enum { PP_SELF_SKIP = 0, PP_SELF_CELLAVG = 1 };
+
+/*
+ * Parameters of the tree-code (Appendix A):
+ *   p         expansion order: p terms after the log term (eq. pressTruncated), 1..20
+ *   theta     acceptance: target cell A and source cell B interact through
+ *             expansions when (r_A + r_B) < theta * d, r = half-diagonal, d =
+ *             centre distance (the paper's "sufficiently large distances");
+ *             read as round(1000 theta)/1000, 0 < theta < 1
+ *   leaf_max  a cell is split while it holds more than leaf_max sources or
+ *             more than leaf_max targets (1..4096)
+ *   precision PP_FP64 or PP_MIXED
+ *   self_mode PP_SELF_SKIP or PP_SELF_CELLAVG
+ */
+typedef struct {
+  int32_t p;
+  double theta;
+  int32_t leaf_max;
+  int32_t precision;
+  int32_t self_mode;
+} pp_params;
+
+/* Per-solve statistics of the last successful call on a context. */
+typedef struct {
+  int32_t depth;          /* deepest tree level */
+  int32_t ncells;         /* cells in the tree */
+  int32_t nsrc_leaves;    /* leaves holding sources */
+  int32_t ntgt_leaves;    /* leaves holding targets */
+  int64_t nsources;       /* grid nodes with f != 0 */
+  int64_t ntargets;
+  int64_t n_m2l;          /* M2L (cell, cell) pairs */
+  int64_t n_p2p_lists;    /* P2P (leaf, leaf) pairs */
+  int64_t n_p2p_pairs;    /* P2P (target, source) interactions */
+  double ms_total;        /* wall time of the call on the host, ms */
+} pp_stats;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context may hold (0 = no bound).  *out receives the
+ * context; returns PP_ERR_DEVICE if the device cannot be used. */
+pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out);
+void pp_destroy(pp_ctx* ctx);
+
+/* Tree-code solve (P2M, M2M, M2L, L2L, L2P, P2P) of eq. greenSum for grid
+ * sources f at the m targets (tx, ty).  Writes P to p_out[0..m). */
+pp_status pp_solve_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
+                        int64_t m, const double* tx, const double* ty, const pp_params* params, double* p_out,
+                        void* hip_stream);
+
+/* All-pairs direct sum of eq. greenSum on the GPU (no expansions): the
+ * baseline the tree-code is measured against.  Uses params->precision,
+ * params->self_mode and params->leaf_max (tiling); p and theta are ignored. */
+pp_status pp_direct_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
+                         int64_t m, const double* tx, const double* ty, const pp_params* params, double* p_out,
+                         void* hip_stream);
+
+pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
+
+/*
+ * Introspection of the last successful solve on a context, for testing: copy
+ * one of its device arrays to host memory.  `what` selects the array (below);
+ * dst receives min(capacity, length) elements; *length (may be NULL) receives
+ * the full element count.  Element types: int32 unless noted.
+ */
+enum {
+  PP_ARR_SRC_KEY = 0,    /* uint32 Morton key per source, in key order */
+  PP_ARR_SRC_INDEX = 1,  /* packed node index i | (j << 16) per source */
+  PP_ARR_TGT_KEY = 2,    /* uint32 key per target, sorted */
+  PP_ARR_TGT_PERM = 3,   /* caller index of each sorted target */
+  PP_ARR_CELL_LEVEL = 4,
+  PP_ARR_CELL_IX = 5,
+  PP_ARR_CELL_IY = 6,
+  PP_ARR_CELL_SB = 7,
+  PP_ARR_CELL_SE = 8,
+  PP_ARR_CELL_TB = 9,
+  PP_ARR_CELL_TE = 10,
+  PP_ARR_CELL_CHILD = 11, /* first child or -1 */
+  PP_ARR_CELL_NCHILD = 12,
+  PP_ARR_CELL_PARENT = 13,
+  PP_ARR_M2L_OFF = 14,    /* per cell: begin of its M2L source list */
+  PP_ARR_M2L_CNT = 15,    /* per cell: length */
+  PP_ARR_M2L_SRC = 16,
+  PP_ARR_P2P_OFF = 17,
+  PP_ARR_P2P_CNT = 18,
+  PP_ARR_P2P_SRC = 19,
+  PP_ARR_MULTIPOLE = 20,  /* double, per cell (p+1) complex: scaled a'_k = a_k / s^k */
+  PP_ARR_LOCAL = 21,      /* double, per cell (p+1) complex: scaled L'_l = L_l s^l */
+  PP_ARR_FAR = 22,        /* double per sorted target: Re sum_l L'_l u^l (far field times 2pi) */
+  PP_ARR_NEAR = 23,       /* double per sorted target: sum over near sources of w ln(r^2 / h^2) */
+  PP_ARR_LEAF_WNEAR = 24, /* double per cell: sum of w over a target leaf's near sources */
+  PP_ARR_TGT_LEAF = 25    /* leaf cell of each sorted target */
+};
+pp_status pp_debug_copy(const pp_ctx* ctx, int32_t what, void* dst, int64_t capacity, int64_t* length);
+
+const char* pp_status_string(pp_status s);
+const char* pp_last_error(const pp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PP_H_ */

@@ -1,0 +1,140 @@
+"""MI355X pressure-Poisson tree-code: Python binding of the HIP library.
+
+The library computes P(t) = (1/2pi) sum_i f_i h^2 ln|t - s_i| (Appendix A, eq.
+greenSum with eq. green2D) for grid sources and arbitrary targets with a
+quadtree fast multipole scheme in hand-written HIP kernels for gfx950.  This
+module only marshals arguments: torch CUDA tensors (device pointers plus the
+current stream) or NumPy arrays (host pointers) go straight to the C ABI of
+``include/pp.h``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _binding as B
+from ._binding import (  # noqa: F401  (same names as the C ABI)
+    PPError,
+    pp_create,
+    pp_debug_copy,
+    pp_destroy,
+    pp_direct_grid,
+    pp_get_stats,
+    pp_last_error,
+    pp_solve_grid,
+    pp_status_string,
+    pp_params,
+    PP_FP64,
+    PP_MIXED,
+    PP_SELF_SKIP,
+    PP_SELF_CELLAVG,
+)
+
+_PREC = {"fp64": B.PP_FP64, "mixed": B.PP_MIXED}
+_SELF = {"skip": B.PP_SELF_SKIP, "cellavg": B.PP_SELF_CELLAVG}
+
+
+def make_params(p: int = 12, theta: float = 0.5, leaf_max: int = 64, precision="mixed", self_mode="skip"):
+    prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+    selfm = _SELF[self_mode] if isinstance(self_mode, str) else int(self_mode)
+    return B.pp_params(int(p), float(theta), int(leaf_max), prec, selfm)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, name: str):
+    """(pointer, keep-alive object) for a float64 contiguous torch tensor or NumPy array."""
+    if _is_torch(x):
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float64 tensor")
+        return x.data_ptr(), x
+    a = np.ascontiguousarray(np.asarray(x), dtype=np.float64)
+    return a.ctypes.data, a
+
+
+class Solver:
+    """One library context on one GPU (not thread-safe; one host thread per Solver)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._ctx = pp_create(device, hbm_budget_bytes)
+        self.device = device
+
+    def close(self):
+        if self._ctx:
+            pp_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _run(self, fn, f, h, tx, ty, x0, y0, params, out, stream):
+        torch_mode = _is_torch(tx)
+        fshape = tuple(f.shape)
+        if len(fshape) != 2:
+            raise ValueError("f must have shape (ny, nx)")
+        ny, nx = fshape
+        fp, fk = _ptr(f, "f")
+        xp, xk = _ptr(tx, "tx")
+        yp, yk = _ptr(ty, "ty")
+        m = int(np.prod(tuple(tx.shape)))
+        if int(np.prod(tuple(ty.shape))) != m:
+            raise ValueError("tx and ty differ in length")
+        if out is None:
+            if torch_mode:
+                import torch
+                out = torch.empty(m, dtype=torch.float64, device=tx.device)
+            else:
+                out = np.empty(m, dtype=np.float64)
+        op, ok = _ptr(out, "out")
+        if stream is None:
+            stream = 0
+            if torch_mode and tx.is_cuda:
+                import torch
+                stream = torch.cuda.current_stream(tx.device).cuda_stream
+        st = fn(self._ctx, nx, ny, float(x0), float(y0), float(h), fp, m, xp, yp, params, op, stream)
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del fk, xk, yk, ok
+        return out
+
+    def solve_grid(self, f, h, tx, ty, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
+                   self_mode="skip", out=None, stream=None):
+        """Tree-code pressure at the targets (caller order); see pp_solve_grid in include/pp.h."""
+        prm = make_params(p, theta, leaf_max, precision, self_mode)
+        return self._run(pp_solve_grid, f, h, tx, ty, x0, y0, prm, out, stream)
+
+    def direct_grid(self, f, h, tx, ty, x0=0.0, y0=0.0, leaf_max=64, precision="mixed", self_mode="skip",
+                    out=None, stream=None):
+        """All-pairs GPU direct sum; see pp_direct_grid in include/pp.h."""
+        prm = make_params(1, 0.5, leaf_max, precision, self_mode)
+        return self._run(pp_direct_grid, f, h, tx, ty, x0, y0, prm, out, stream)
+
+    def stats(self) -> dict:
+        s = pp_get_stats(self._ctx)
+        return {name: getattr(s, name) for name, _ in B.pp_stats._fields_}
+
+    def debug_array(self, name: str) -> np.ndarray:
+        """A device array of the last solve (see PP_ARR_* in include/pp.h), copied to the host."""
+        what = B.ARRAYS[name]
+        st, n = pp_debug_copy(self._ctx, what, None, 0)
+        if st != B.PP_OK:
+            raise PPError(st, pp_last_error(self._ctx))
+        if name in B.DOUBLE_ARRAYS:
+            dt = np.float64
+        elif name in B.UNSIGNED_ARRAYS:
+            dt = np.uint32
+        else:
+            dt = np.int32
+        a = np.empty(max(n, 1), dtype=dt)
+        st, _ = pp_debug_copy(self._ctx, what, ctypes.c_void_p(a.ctypes.data), n)
+        if st != B.PP_OK:
+            raise PPError(st, pp_last_error(self._ctx))
+        return a[:n]

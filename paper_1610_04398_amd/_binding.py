@@ -1,0 +1,142 @@
+"""ctypes binding of the C ABI declared in include/pp.h.
+
+Argument marshalling only: every step of a solve runs in the HIP library
+``libpp_hip.so``.  If the library has not been built the import fails; there is
+no fallback of any kind.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpp_hip.so")
+
+PP_OK = 0
+PP_ERR_ARG = -1
+PP_ERR_DOMAIN = -2
+PP_ERR_NOMEM = -3
+PP_ERR_DEVICE = -4
+PP_ERR_LIMIT = -5
+
+PP_FP64 = 0
+PP_MIXED = 1
+PP_SELF_SKIP = 0
+PP_SELF_CELLAVG = 1
+
+ARRAYS = dict(
+    SRC_KEY=0, SRC_INDEX=1, TGT_KEY=2, TGT_PERM=3, CELL_LEVEL=4, CELL_IX=5, CELL_IY=6, CELL_SB=7, CELL_SE=8,
+    CELL_TB=9, CELL_TE=10, CELL_CHILD=11, CELL_NCHILD=12, CELL_PARENT=13, M2L_OFF=14, M2L_CNT=15, M2L_SRC=16,
+    P2P_OFF=17, P2P_CNT=18, P2P_SRC=19, MULTIPOLE=20, LOCAL=21, FAR=22, NEAR=23, LEAF_WNEAR=24, TGT_LEAF=25,
+)
+DOUBLE_ARRAYS = {"MULTIPOLE", "LOCAL", "FAR", "NEAR", "LEAF_WNEAR"}
+UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
+
+#: C symbols the header declares (checked by the CPU test suite)
+EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_get_stats", "pp_debug_copy",
+            "pp_status_string", "pp_last_error")
+
+
+class pp_params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("theta", ctypes.c_double), ("leaf_max", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("self_mode", ctypes.c_int32)]
+
+
+class pp_stats(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("ncells", ctypes.c_int32), ("nsrc_leaves", ctypes.c_int32),
+                ("ntgt_leaves", ctypes.c_int32), ("nsources", ctypes.c_int64), ("ntargets", ctypes.c_int64),
+                ("n_m2l", ctypes.c_int64), ("n_p2p_lists", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
+                ("ms_total", ctypes.c_double)]
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library and declare the C signatures."""
+    if not os.path.exists(path):
+        raise LibraryMissing(f"{path} is not built; run `python -m paper_1610_04398_amd.build` "
+                             "(the library has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.pp_create.argtypes = [i32, ctypes.c_uint64, ctypes.POINTER(vp)]
+    lib.pp_create.restype = i32
+    lib.pp_destroy.argtypes = [vp]
+    lib.pp_destroy.restype = None
+    solve_args = [vp, i32, i32, f64, f64, f64, vp, i64, vp, vp, ctypes.POINTER(pp_params), vp, vp]
+    lib.pp_solve_grid.argtypes = solve_args
+    lib.pp_solve_grid.restype = i32
+    lib.pp_direct_grid.argtypes = solve_args
+    lib.pp_direct_grid.restype = i32
+    lib.pp_get_stats.argtypes = [vp, ctypes.POINTER(pp_stats)]
+    lib.pp_get_stats.restype = i32
+    lib.pp_debug_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
+    lib.pp_debug_copy.restype = i32
+    lib.pp_status_string.argtypes = [i32]
+    lib.pp_status_string.restype = ctypes.c_char_p
+    lib.pp_last_error.argtypes = [vp]
+    lib.pp_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def pp_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    h = ctypes.c_void_p()
+    st = lib().pp_create(device, hbm_budget_bytes, ctypes.byref(h))
+    if st != PP_OK:
+        raise PPError(st, "pp_create failed")
+    return h.value
+
+
+def pp_destroy(ctx: int) -> None:
+    lib().pp_destroy(ctx)
+
+
+def pp_solve_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:
+    return lib().pp_solve_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params), out_ptr,
+                               stream)
+
+
+def pp_direct_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:
+    return lib().pp_direct_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params), out_ptr,
+                                stream)
+
+
+def pp_get_stats(ctx) -> pp_stats:
+    s = pp_stats()
+    st = lib().pp_get_stats(ctx, ctypes.byref(s))
+    if st != PP_OK:
+        raise PPError(st, "pp_get_stats failed")
+    return s
+
+
+def pp_debug_copy(ctx, what: int, dst_ptr, capacity: int) -> tuple[int, int]:
+    n = ctypes.c_int64(0)
+    st = lib().pp_debug_copy(ctx, what, dst_ptr, capacity, ctypes.byref(n))
+    return st, n.value
+
+
+def pp_status_string(st: int) -> str:
+    return lib().pp_status_string(st).decode()
+
+
+def pp_last_error(ctx) -> str:
+    return lib().pp_last_error(ctx).decode()
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status

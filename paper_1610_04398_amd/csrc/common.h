@@ -1,0 +1,88 @@
+// Internal definitions shared by the HIP kernels and the host pipeline of the
+// pressure-Poisson tree-code library.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pp {
+
+// Largest supported expansion order; kernels are instantiated for the order
+// buckets below and take the exact order p <= bucket at run time.
+constexpr int kMaxP = 20;
+constexpr int kMaxDepth = 16;  // finest level; keys are 2*16 bits
+
+// 1/(2 pi), ln 2, and the cell-average constant kappa = 3/2 - pi/4 + ln(2)/2
+constexpr double kInv2Pi = 0.15915494309189533577;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kKappa = 1.0611754268825244;
+
+// Error flags raised by kernels (bit mask in a device word).
+enum : int {
+  kFlagNonFiniteSource = 1,
+  kFlagNonFiniteTarget = 2,
+  kFlagTargetOutside = 4,
+  kFlagFrontierOverflow = 8,
+};
+
+struct cplx {
+  double x, y;
+};
+
+__host__ __device__ inline cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__host__ __device__ inline cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
+
+// Morton bit spreading: bit b of v goes to bit 2b.
+__host__ __device__ inline uint32_t spread_bits(uint32_t v) {
+  v &= 0xFFFFu;
+  v = (v | (v << 8)) & 0x00FF00FFu;
+  v = (v | (v << 4)) & 0x0F0F0F0Fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+__host__ __device__ inline uint32_t compact_bits(uint32_t v) {
+  v &= 0x55555555u;
+  v = (v | (v >> 1)) & 0x33333333u;
+  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+  v = (v | (v >> 4)) & 0x00FF00FFu;
+  v = (v | (v >> 8)) & 0x0000FFFFu;
+  return v;
+}
+__host__ __device__ inline uint32_t morton(uint32_t ix, uint32_t iy) { return spread_bits(ix) | (spread_bits(iy) << 1); }
+
+// Device view of the quadtree: structure-of-arrays over all cells, numbered
+// level by level (root = 0), children of a cell contiguous and in quadrant
+// order q = qx + 2 qy.
+struct TreeView {
+  int D;               // finest level
+  int ncells;
+  const int* lvl;
+  const int* ix;
+  const int* iy;
+  const int* sb;       // source range [sb, se) into the Morton-ordered sources
+  const int* se;
+  const int* tb;       // target range [tb, te) into the sorted targets
+  const int* te;
+  const int* child;    // first child, or -1 for a leaf
+  const int* nchild;
+  const int* parent;   // -1 for the root
+};
+
+// Exact acceptance test (r_A + r_B) < theta d with theta = num/den, all in
+// units of half a finest cell: (S_A + S_B)^2 den^2 < 2 num^2 d^2.
+__host__ __device__ inline bool mac_accept(int D, int la, int ixa, int iya, int lb, int ixb, int iyb, int num,
+                                           int den) {
+  const int64_t cax = (int64_t)(2 * ixa + 1) << (D - la);
+  const int64_t cay = (int64_t)(2 * iya + 1) << (D - la);
+  const int64_t cbx = (int64_t)(2 * ixb + 1) << (D - lb);
+  const int64_t cby = (int64_t)(2 * iyb + 1) << (D - lb);
+  const int64_t s = ((int64_t)1 << (D - la + 1)) + ((int64_t)1 << (D - lb + 1));
+  const int64_t dx = cax - cbx, dy = cay - cby;
+  const int64_t lhs = s * s * (int64_t)den * (int64_t)den;
+  const int64_t rhs = 2 * (int64_t)num * (int64_t)num * (dx * dx + dy * dy);
+  return lhs < rhs;
+}
+
+}  // namespace pp

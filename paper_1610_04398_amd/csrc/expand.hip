@@ -1,0 +1,310 @@
+// Expansion passes in FP64: P2M, M2M, M2L, L2L, L2P.
+//
+// Notation: the sources of a cell with centre z_c and side s have the
+// multipole expansion  Phi(z) = a_0 log(z - z_c) + sum_{k=1..p} a_k (z - z_c)^-k
+// with a_0 = S = sum w and a_k = -alpha_k = -sum w (z_i - z_c)^k / k
+// (Appendix A, eq. alphaK and eq. pressTruncated; P = Re Phi / 2pi).  Stored
+// coefficients are scaled by the cell side, a'_k = a_k / s^k, and locals
+// L'_l = L_l s^l, so every operator acts on O(1) numbers and depends only on
+// offsets measured in cell sides.  Positions are in units of the finest cell
+// (h), where every cell centre is exact in FP64.
+//
+// M2M is the re-centring of eq. expandedShift with the S term's sign derived
+// from eq. logExpansion (+S z0^k / k in the paper's alpha convention; the
+// printed minus sign does not reproduce the parent's expansion).  M2L, L2L and
+// L2P are the local-expansion operators of the fast multipole method that the
+// paper cites, derived from the same series:
+//   M2L (z0 = z_B - z_A, t = s_A / z0, r = s_B / z0):
+//     L'_0 = a_0 ln|z0| + sum_k a'_k (-r)^k
+//     L'_l = t^l [ -a_0 / l + sum_k C(l+k-1, k-1) a'_k (-r)^k ],  l >= 1
+//   L2L (d = (z_child - z_parent) / s_parent):
+//     L'_m(child) = 2^-m sum_{k>=m} C(k, m) d^(k-m) L'_k(parent)
+//   M2M (d as above):
+//     a'_l(parent) += -a_0 d^l / l + sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k(child)
+//   L2P: far(z) = Re sum_l L'_l u^l,  u = (z - z_c) / s.
+#include "internal.h"
+
+namespace pp {
+
+namespace {
+
+struct BinomTable {
+  double v[2 * kMaxP + 1][2 * kMaxP + 1];
+};
+constexpr BinomTable make_binom() {
+  BinomTable b{};
+  for (int n = 0; n <= 2 * kMaxP; ++n) {
+    b.v[n][0] = 1.0;
+    for (int k = 1; k <= n; ++k) b.v[n][k] = b.v[n - 1][k - 1] + (k <= n - 1 ? b.v[n - 1][k] : 0.0);
+  }
+  return b;
+}
+__constant__ BinomTable c_binom = make_binom();
+
+__device__ inline double binom(int n, int k) { return c_binom.v[n][k]; }
+
+__device__ inline double cell_side(int D, int l) { return (double)(1 << (D - l)); }
+
+// Offset of child quadrant from its parent's centre, in parent sides.
+__device__ inline cplx quadrant_offset(int ix, int iy) {
+  return {(ix & 1) ? 0.25 : -0.25, (iy & 1) ? 0.25 : -0.25};
+}
+
+template <int PM>
+__global__ void k_p2m(TreeView t, const int* __restrict__ sleaves, int n, const float4* __restrict__ src4,
+                      const double* __restrict__ w64, int p, double2* __restrict__ mp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = sleaves[i];
+  const int l = t.lvl[c];
+  const double side = cell_side(t.D, l);
+  const double inv = 1.0 / side;
+  cplx acc[PM + 1];
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
+  double a0 = 0.0;
+  const int sb = t.sb[c], se = t.se[c];
+  for (int s = sb; s < se; ++s) {
+    const float4 q = src4[s];
+    const double w = w64[s];
+    const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
+    a0 += w;
+    cplx zk = {w * z.x, w * z.y};
+#pragma unroll
+    for (int k = 1; k <= PM; ++k) {
+      acc[k] = cadd(acc[k], zk);
+      zk = cmul(zk, z);
+    }
+  }
+  double2* out = mp + (int64_t)c * (p + 1);
+  out[0] = make_double2(a0, 0.0);
+#pragma unroll
+  for (int k = 1; k <= PM; ++k)
+    if (k <= p) out[k] = make_double2(-acc[k].x / k, -acc[k].y / k);
+}
+
+template <int PM>
+__global__ void k_m2m(TreeView t, const int* __restrict__ cells, int n, int p, double2* __restrict__ mp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cells[i];
+  cplx b[PM + 1];
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) b[k] = {0.0, 0.0};
+  const int k0 = t.child[c], nk = t.nchild[c];
+  for (int q = 0; q < nk; ++q) {
+    const int ch = k0 + q;
+    if (t.se[ch] <= t.sb[ch]) continue;
+    const cplx d = quadrant_offset(t.ix[ch], t.iy[ch]);
+    const double2* a = mp + (int64_t)ch * (p + 1);
+    cplx dp[PM + 1];
+    dp[0] = {1.0, 0.0};
+#pragma unroll
+    for (int k = 1; k <= PM; ++k) dp[k] = cmul(dp[k - 1], d);
+    cplx as[PM + 1];  // a'_k 2^-k
+    double half = 1.0;
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) {
+      if (k <= p) {
+        const double2 v = a[k];
+        as[k] = {v.x * half, v.y * half};
+      } else {
+        as[k] = {0.0, 0.0};
+      }
+      half *= 0.5;
+    }
+    const double a0 = as[0].x;
+    b[0].x += a0;
+#pragma unroll
+    for (int l = 1; l <= PM; ++l) {
+      cplx s = cscale(dp[l], -a0 / l);
+#pragma unroll
+      for (int k = 1; k <= l; ++k) s = cadd(s, cscale(cmul(as[k], dp[l - k]), binom(l - 1, k - 1)));
+      b[l] = cadd(b[l], s);
+    }
+  }
+  double2* out = mp + (int64_t)c * (p + 1);
+#pragma unroll
+  for (int k = 0; k <= PM; ++k)
+    if (k <= p) out[k] = make_double2(b[k].x, b[k].y);
+}
+
+template <int PM>
+__global__ void k_m2l(TreeView t, const int* __restrict__ tcells, int n, const int* __restrict__ off,
+                      const int* __restrict__ cnt, const int* __restrict__ src, int p, double lnh,
+                      const double2* __restrict__ mp, double2* __restrict__ loc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int A = tcells[i];
+  const int D = t.D;
+  const int lA = t.lvl[A];
+  const double sA = cell_side(D, lA);
+  const double cax = (t.ix[A] + 0.5) * sA, cay = (t.iy[A] + 0.5) * sA;
+  cplx L[PM + 1];
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) L[k] = {0.0, 0.0};
+  const int e0 = off[A], ne = cnt[A];
+  for (int e = 0; e < ne; ++e) {
+    const int B = src[e0 + e];
+    const int lB = t.lvl[B];
+    const double sB = cell_side(D, lB);
+    const cplx z0 = {(t.ix[B] + 0.5) * sB - cax, (t.iy[B] + 0.5) * sB - cay};
+    const double r2 = z0.x * z0.x + z0.y * z0.y;
+    const cplx inv = {z0.x / r2, -z0.y / r2};  // 1 / z0
+    const cplx tt = cscale(inv, sA);
+    const cplx mr = cscale(inv, -sB);           // -s_B / z0
+    const double2* a = mp + (int64_t)B * (p + 1);
+    const double a0 = a[0].x;
+    cplx bk[PM + 1];
+    cplx pw = mr;
+    cplx sum0 = {a0 * (0.5 * log(r2) + lnh), 0.0};
+#pragma unroll
+    for (int k = 1; k <= PM; ++k) {
+      if (k <= p) {
+        const double2 v = a[k];
+        bk[k] = cmul({v.x, v.y}, pw);
+      } else {
+        bk[k] = {0.0, 0.0};
+      }
+      pw = cmul(pw, mr);
+      sum0 = cadd(sum0, bk[k]);
+    }
+    L[0] = cadd(L[0], sum0);
+    cplx tl = tt;
+#pragma unroll
+    for (int l = 1; l <= PM; ++l) {
+      cplx s = {-a0 / l, 0.0};
+#pragma unroll
+      for (int k = 1; k <= PM; ++k) s = cadd(s, cscale(bk[k], binom(l + k - 1, k - 1)));
+      L[l] = cadd(L[l], cmul(tl, s));
+      tl = cmul(tl, tt);
+    }
+  }
+  double2* out = loc + (int64_t)A * (p + 1);
+#pragma unroll
+  for (int k = 0; k <= PM; ++k)
+    if (k <= p) out[k] = make_double2(L[k].x, L[k].y);
+}
+
+template <int PM>
+__global__ void k_l2l(TreeView t, const int* __restrict__ cells, int n, int p, double2* __restrict__ loc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = cells[i];
+  const int par = t.parent[c];
+  if (par < 0) return;
+  const cplx d = quadrant_offset(t.ix[c], t.iy[c]);
+  const double2* pc = loc + (int64_t)par * (p + 1);
+  cplx P[PM + 1], dp[PM + 1];
+  dp[0] = {1.0, 0.0};
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) {
+    if (k <= p) {
+      const double2 v = pc[k];
+      P[k] = {v.x, v.y};
+    } else {
+      P[k] = {0.0, 0.0};
+    }
+    if (k > 0) dp[k] = cmul(dp[k - 1], d);
+  }
+  double2* out = loc + (int64_t)c * (p + 1);
+  double half = 1.0;
+#pragma unroll
+  for (int m = 0; m <= PM; ++m) {
+    if (m <= p) {
+      cplx s = {0.0, 0.0};
+#pragma unroll
+      for (int k = m; k <= PM; ++k) s = cadd(s, cscale(cmul(P[k], dp[k - m]), binom(k, m)));
+      const double2 v = out[m];
+      out[m] = make_double2(v.x + s.x * half, v.y + s.y * half);
+    }
+    half *= 0.5;
+  }
+}
+
+__global__ void k_l2p64(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
+                        const double2* __restrict__ rel64, double* __restrict__ far) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int c = tleaf[k];
+  const double side = cell_side(t.D, t.lvl[c]);
+  const double2 r = rel64[k];
+  const cplx u = {(r.x - 0.5 * side) / side, (r.y - 0.5 * side) / side};
+  const double2* L = loc + (int64_t)c * (p + 1);
+  cplx acc = {0.0, 0.0};
+  for (int l = p; l >= 0; --l) {
+    const double2 v = L[l];
+    acc = cadd(cmul(acc, u), {v.x, v.y});
+  }
+  far[k] = acc.x;
+}
+
+__global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
+                        const double2* __restrict__ rel64, double* __restrict__ far) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int c = tleaf[k];
+  const double side = cell_side(t.D, t.lvl[c]);
+  const double2 r = rel64[k];
+  const float ux = (float)((r.x - 0.5 * side) / side), uy = (float)((r.y - 0.5 * side) / side);
+  const double2* L = loc + (int64_t)c * (p + 1);
+  float ax = 0.f, ay = 0.f;
+  for (int l = p; l >= 0; --l) {
+    const double2 v = L[l];
+    const float nx = ax * ux - ay * uy + (float)v.x;
+    const float ny = ax * uy + ay * ux + (float)v.y;
+    ax = nx;
+    ay = ny;
+  }
+  far[k] = (double)ax;
+}
+
+#define PP_DISPATCH(p, KERNEL, GRID, BLOCK, STREAM, ...)                      \
+  do {                                                                        \
+    if ((p) <= 4)                                                             \
+      KERNEL<4><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                     \
+    else if ((p) <= 8)                                                        \
+      KERNEL<8><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                     \
+    else if ((p) <= 12)                                                       \
+      KERNEL<12><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                    \
+    else if ((p) <= 16)                                                       \
+      KERNEL<16><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                    \
+    else                                                                      \
+      KERNEL<20><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                    \
+  } while (0)
+
+}  // namespace
+
+void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
+         hipStream_t s) {
+  if (n <= 0) return;
+  PP_DISPATCH(p, k_p2m, (n + 127) / 128, 128, s, t, sleaves, n, src4, w64, p, mp);
+}
+
+void m2m_level(TreeView t, const int* cells, int n, int p, double2* mp, hipStream_t s) {
+  if (n <= 0) return;
+  PP_DISPATCH(p, k_m2m, (n + 127) / 128, 128, s, t, cells, n, p, mp);
+}
+
+void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
+         double h, const double2* mp, double2* loc, hipStream_t s) {
+  if (n <= 0) return;
+  PP_DISPATCH(p, k_m2l, (n + 127) / 128, 128, s, t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, log(h), mp, loc);
+}
+
+void l2l_level(TreeView t, const int* cells, int n, int p, double2* loc, hipStream_t s) {
+  if (n <= 0) return;
+  PP_DISPATCH(p, k_l2l, (n + 127) / 128, 128, s, t, cells, n, p, loc);
+}
+
+void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,
+         double* far, hipStream_t s) {
+  if (m <= 0) return;
+  const unsigned g = (unsigned)((m + 255) / 256);
+  if (fp32)
+    k_l2p32<<<g, 256, 0, s>>>(t, m, tleaf, p, loc, rel64, far);
+  else
+    k_l2p64<<<g, 256, 0, s>>>(t, m, tleaf, p, loc, rel64, far);
+}
+
+}  // namespace pp

@@ -1,0 +1,119 @@
+// Host-side launchers of the HIP kernels (one translation unit each) and the
+// mutable tree arrays the pipeline owns.  Internal: not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace pp {
+
+// ---- scan.hip: exclusive prefix sums and fills --------------------------------
+size_t scan_temp_ints(int64_t n);
+// out[i] = sum_{j<i} in[j]; *total_dev = sum of all (may be null). in == out allowed.
+void scan_exclusive(const int* in, int* out, int64_t n, int* temp, int* total_dev, hipStream_t s);
+void fill_i32(int* p, int v, int64_t n, hipStream_t s);
+
+// ---- ingest.hip: sources in Morton order, target keys ------------------------------
+// Morton tiles of 1024 indices cover [0, 4^k).
+int64_t ingest_num_tiles(int k);
+void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s);
+void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, uint32_t* key,
+                      uint32_t* ij, double* w64, hipStream_t s);
+void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
+                 uint32_t* key, int* idx, int* flags, hipStream_t s);
+
+// ---- sort.hip: stable LSD radix sort of (uint32 key, int32 value) pairs -----------
+size_t radix_temp_ints(int64_t n);
+// Sorts the low `bits` bits of keys; results end in (keys, vals).  tmp arrays of n.
+void radix_sort_pairs(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int64_t n, int bits,
+                      int* temp, hipStream_t s);
+
+// ---- tree.hip: top-down construction, per-leaf packing ------------------------------
+struct TreeArrays {
+  int* lvl;
+  int* ix;
+  int* iy;
+  int* sb;
+  int* se;
+  int* tb;
+  int* te;
+  int* child;
+  int* nchild;
+  int* parent;
+};
+// Root cell: all sources (count read from device memory) and all targets.
+void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, hipStream_t s);
+// For the cells [c0, c1) of one level: child counts (0 for leaves) and the
+// candidate children's ranges (4 per cell, in scratch `cr`, 16 ints per cell).
+void tree_level_count(TreeArrays t, int c0, int c1, int level, int D, int leaf_max, const uint32_t* skey,
+                      const uint32_t* tkey, int* cnt, int* cr, hipStream_t s);
+// Writes the children of [c0, c1) at first_child + off[c - c0] (cnt from the count pass).
+void tree_level_emit(TreeArrays t, int c0, int c1, int level, const int* cnt, const int* off, const int* cr,
+                     int first_child, hipStream_t s);
+// Flags cells matching a predicate, for compaction: kind 0 = leaf with sources,
+// 1 = leaf with targets, 2 = any cell with targets, 3 = non-leaf with sources.
+void cell_flags(TreeArrays t, int c0, int c1, int kind, int* flag, hipStream_t s);
+void compact_indices(const int* flag, const int* off, int c0, int c1, int* out, hipStream_t s);
+// Per source leaf: FP32 source records relative to the leaf corner, in finest
+// cell units, and the FP64 leaf weight.
+void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
+                       float4* src4, double* leaf_w, hipStream_t s);
+// Per target leaf: offsets relative to the leaf corner (FP32 and FP64, in units
+// of h), owning leaf, and the coincident-node information for the self rule.
+void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
+                       const int* perm, double x0, double y0, double h, int nx, int ny, float2* rel32, double2* rel64,
+                       int* tleaf, int* self_idx, double* self_logd, hipStream_t s);
+
+// ---- lists.hip: dual-tree interaction lists ------------------------------------
+// One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p
+// (indexed by cell id), pass 1 writes the lists at off_m2l / off_p2p (by cell id).
+void lists_pass(TreeView t, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l, int* cnt_p2p,
+                const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags, hipStream_t s);
+// Total (target, source) pairs of the P2P lists (statistics).
+void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
+                    unsigned long long* out, hipStream_t s);
+
+// ---- expand.hip: multipole and local passes (FP64) ---------------------------------
+void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
+         hipStream_t s);
+void m2m_level(TreeView t, const int* cells, int n, int p, double2* mp, hipStream_t s);
+void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
+         double h, const double2* mp, double2* loc, hipStream_t s);
+void l2l_level(TreeView t, const int* cells, int n, int p, double2* loc, hipStream_t s);
+// far[k] = Re sum_l c'_l u^l for every sorted target k (u: offset from its
+// leaf centre over the leaf side); fp32 != 0 evaluates in FP32.
+void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,
+         double* far, hipStream_t s);
+
+// ---- p2p.hip: near field --------------------------------------------------------------
+struct P2PArgs {
+  TreeView t;
+  const int* tleaves;   // target leaves (work: one wave per 64-target chunk)
+  int ntleaves;
+  const int* list_off;  // per cell id: P2P list begin
+  const int* list_cnt;  // and length; null => all source leaves (direct mode)
+  const int* list_src;  // source leaf ids
+  const int* sleaves;   // all source leaves (direct mode)
+  int nsleaves;
+  const float4* src4;
+  const double* w64;
+  const double* leaf_w;
+  const float2* rel32;
+  const double2* rel64;
+  double* near_sum;     // per sorted target: sum w ln(r^2 / h^2)
+  double* leaf_wnear;   // per cell id (target leaves): sum of the near sources' weights
+};
+// Work items (target leaf, first target of a 64-target chunk), built from tleaves.
+void p2p_chunks_count(TreeView t, const int* tleaves, int n, int* cnt, hipStream_t s);
+void p2p_chunks_emit(TreeView t, const int* tleaves, int n, const int* off, int2* items, hipStream_t s);
+void p2p(const P2PArgs& a, const int2* items, int nitems, int fp64, hipStream_t s);
+
+// ---- finalize.hip ----------------------------------------------------------------------
+// P at every target, scattered to the caller's order; writes nothing if *flags != 0.
+void finalize(int64_t m, const int* perm, const int* tleaf, const double* far, const double* near_sum,
+              const double* leaf_wnear, const int* self_idx, const double* self_logd, const double* f, double h,
+              int self_mode, const int* flags, double* out, hipStream_t s);
+
+}  // namespace pp

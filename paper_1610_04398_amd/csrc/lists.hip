@@ -1,0 +1,165 @@
+// Interaction lists of the dual-tree traversal.
+//
+// The paper sums group contributions, treating a group through its expansion
+// "at sufficiently large distances" and the rest directly (Appendix A, the
+// superposition equation after Fig. multipole).  The traversal read here pairs
+// a target cell A with a source cell B starting from the roots: accepted by
+// the exact integer test -> M2L; both leaves -> P2P; A leaf -> split B; B leaf
+// -> split A; otherwise split both.  Only cells with sources are used as
+// sources and only cells with targets as targets.
+//
+// GPU form: one wave per target cell A walks the traversal restricted to A's
+// ancestor path.  The pairs (X, B) with X the current path cell form a
+// frontier of source cells kept in LDS; the 64 lanes classify 64 candidates at
+// a time and compact what they emit with ballots, so each cell's lists come out
+// in a fixed order without atomics.  A count pass sizes the lists, an emit pass
+// writes them.
+#include "blockscan.h"
+#include "internal.h"
+
+namespace pp {
+
+namespace {
+constexpr int kListWaves = 4;
+constexpr int kFrontierCap = 2048;
+
+__global__ __launch_bounds__(kListWaves * kWave) void k_lists(TreeView t, const int* __restrict__ tcells, int ntcells,
+                                                               int num, int den, int emit, int* __restrict__ cnt_m2l,
+                                                               int* __restrict__ cnt_p2p,
+                                                               const int* __restrict__ off_m2l,
+                                                               const int* __restrict__ off_p2p,
+                                                               int* __restrict__ m2l_src, int* __restrict__ p2p_src,
+                                                               int* __restrict__ flags) {
+  __shared__ int front[kListWaves][2][kFrontierCap];
+  __shared__ int path[kListWaves][kMaxDepth + 1];
+  const int w = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kListWaves + w);
+  if (wid >= ntcells) return;
+  const int A = tcells[wid];
+  const int D = t.D;
+  const int lA = t.lvl[A];
+  if (lane == 0) {
+    int c = A;
+    for (int l = lA; l >= 0; --l) {
+      path[w][l] = c;
+      c = t.parent[c];
+    }
+  }
+  __syncwarp();
+  const bool leafA = t.child[A] < 0;
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
+  int* cur = front[w][0];
+  int* nxt = front[w][1];
+  int ncur = 0;
+  if (t.se[0] > t.sb[0]) {
+    if (lane == 0) cur[0] = 0;
+    ncur = 1;
+  }
+  __syncwarp();
+  int xl = 0;  // index on the path of the current target cell X
+  int nm = 0, np = 0;
+  const int mbase = emit ? off_m2l[A] : 0;
+  const int pbase = emit ? off_p2p[A] : 0;
+  bool overflow = false;
+  while (ncur > 0) {
+    const int X = path[w][xl];
+    const bool atA = (X == A);
+    const bool leafX = t.child[X] < 0;
+    const int lX = t.lvl[X], ixX = t.ix[X], iyX = t.iy[X];
+    int nnext = 0;
+    for (int base = 0; base < ncur; base += kWave) {
+      const int i = base + lane;
+      const bool valid = i < ncur;
+      const int B = valid ? cur[i] : 0;
+      bool acc = false, leafB = false;
+      int nkids = 0, kid0 = 0;
+      if (valid) {
+        acc = mac_accept(D, lX, ixX, iyX, t.lvl[B], t.ix[B], t.iy[B], num, den);
+        kid0 = t.child[B];
+        leafB = kid0 < 0;
+        if (!leafB) nkids = t.nchild[B];
+      }
+      const bool em2l = valid && acc && atA;
+      const bool ep2p = valid && !acc && leafX && leafB && atA;
+      const bool push_self = valid && !acc && !leafX && leafB && !atA;
+      const bool push_kids = valid && !acc && !leafB && (leafX ? atA : !atA);
+      const uint64_t bm = __ballot(em2l);
+      const uint64_t bp = __ballot(ep2p);
+      if (emit) {
+        if (em2l) m2l_src[mbase + nm + __popcll(bm & lt_mask)] = B;
+        if (ep2p) p2p_src[pbase + np + __popcll(bp & lt_mask)] = B;
+      }
+      nm += __popcll(bm);
+      np += __popcll(bp);
+      // children of B that hold sources
+      int npush = 0;
+      if (push_self) npush = 1;
+      if (push_kids) {
+        for (int q = 0; q < nkids; ++q) npush += (t.se[kid0 + q] > t.sb[kid0 + q]) ? 1 : 0;
+      }
+      const int incl = wave_incl_scan(npush);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      int pos = nnext + incl - npush;
+      if (nnext + total > kFrontierCap) {
+        overflow = true;
+      } else {
+        if (push_self) nxt[pos] = B;
+        if (push_kids) {
+          for (int q = 0; q < nkids; ++q) {
+            const int k = kid0 + q;
+            if (t.se[k] > t.sb[k]) nxt[pos++] = k;
+          }
+        }
+        nnext += total;
+      }
+    }
+    __syncwarp();
+    if (overflow) break;
+    int* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    ncur = nnext;
+    if (!atA) {
+      ++xl;
+    } else if (!leafA) {
+      break;
+    }
+  }
+  if (overflow && lane == 0) atomicOr(flags, kFlagFrontierOverflow);
+  if (!emit && lane == 0) {
+    cnt_m2l[A] = nm;
+    cnt_p2p[A] = np;
+  }
+}
+
+__global__ void k_pair_count(TreeView t, const int* __restrict__ tleaves, int n, const int* __restrict__ off,
+                             const int* __restrict__ cnt, const int* __restrict__ src, unsigned long long* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int A = tleaves[i];
+  long long acc = 0;
+  const int e0 = off[A], ne = cnt[A];
+  for (int e = 0; e < ne; ++e) {
+    const int B = src[e0 + e];
+    acc += (long long)(t.se[B] - t.sb[B]);
+  }
+  acc *= (long long)(t.te[A] - t.tb[A]);
+  if (acc) atomicAdd(out, (unsigned long long)acc);
+}
+}  // namespace
+
+void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
+                    unsigned long long* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_pair_count<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, off, cnt, src, out);
+}
+
+void lists_pass(TreeView t, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l, int* cnt_p2p,
+                const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags, hipStream_t s) {
+  if (ntcells <= 0) return;
+  k_lists<<<(ntcells + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
+      t, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src, flags);
+}
+
+}  // namespace pp

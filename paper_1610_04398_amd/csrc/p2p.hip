@@ -1,0 +1,175 @@
+// Near field (P2P): the direct part of the group superposition, Appendix A,
+// eq. greenSum restricted to the source leaves that are not accepted for an
+// expansion.  Also serves as the all-pairs direct sum when every source leaf
+// is listed for every target leaf.
+//
+// Work item: one wave per (target leaf, 64-target chunk); lane j owns target j
+// of the chunk.  Every lane of a wave needs the same source at the same time,
+// so sources are read with wave-uniform addresses (scalar loads, no LDS
+// staging) and each source costs one pass of ~10 VALU instructions over the
+// 64 lanes.
+//
+// Coordinates are offsets in units of h: sources relative to their own leaf
+// corner (exact half-integers for grid nodes), targets relative to their leaf
+// corner, shifted per source leaf by the integer corner difference.  This keeps
+// FP32 positions accurate to ~1e-6 h however large the grid.  The kernel sums
+// w log2(r^2 / h^2); the finalize step adds ln(h) times the near weight and the
+// factor ln 2 / 2.
+//
+// Mixed precision: FP32 with Kahan-compensated accumulation in a fixed order.
+// The pair of a target with a coincident node only occurs inside its own leaf;
+// that leaf is processed by a guarded loop where r^2 = 0 contributes 0.
+#include "blockscan.h"
+#include "internal.h"
+
+namespace pp {
+
+namespace {
+constexpr int kP2PWaves = 4;
+
+__global__ void k_chunk_count(TreeView t, const int* __restrict__ tleaves, int n, int* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = tleaves[i];
+  cnt[i] = (t.te[c] - t.tb[c] + kWave - 1) / kWave;
+}
+
+__global__ void k_chunk_emit(TreeView t, const int* __restrict__ tleaves, int n, const int* __restrict__ off,
+                             int2* __restrict__ items) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = tleaves[i];
+  const int nch = (t.te[c] - t.tb[c] + kWave - 1) / kWave;
+  for (int q = 0; q < nch; ++q) items[off[i] + q] = make_int2(c, q * kWave);
+}
+
+template <bool GUARD>
+__device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s1, float tx, float ty, float& sum,
+                                  float& comp) {
+#pragma unroll 4
+  for (int s = s0; s < s1; ++s) {
+    const float4 q = src4[s];
+    const float dx = tx - q.x;
+    const float dy = ty - q.y;
+    float r2 = fmaf(dy, dy, dx * dx);
+    if (GUARD) r2 = (r2 == 0.0f) ? 1.0f : r2;
+    const float lg = __builtin_amdgcn_logf(r2);  // log2
+    const float y = fmaf(q.z, lg, -comp);
+    const float tt = sum + y;
+    comp = (tt - sum) - y;
+    sum = tt;
+  }
+}
+
+template <bool DIRECT>
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int2* __restrict__ items, int nitems) {
+  // wave-uniform work index (keeps all per-item data in scalar registers)
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
+  if (wid >= nitems) return;
+  const int lane = threadIdx.x % kWave;
+  const TreeView& t = a.t;
+  const int2 it = items[wid];
+  const int A = it.x;
+  const int k = t.tb[A] + it.y + lane;
+  const bool active = k < t.te[A];
+  const float2 r = active ? a.rel32[k] : make_float2(0.0f, 0.0f);
+  const int shA = t.D - t.lvl[A];
+  const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
+  const int nb = DIRECT ? a.nsleaves : a.list_cnt[A];
+  const int* lst = DIRECT ? a.sleaves : a.list_src + a.list_off[A];
+  float sum = 0.0f, comp = 0.0f;
+  double wn = 0.0;
+  for (int e = 0; e < nb; ++e) {
+    const int B = lst[e];
+    const int shB = t.D - t.lvl[B];
+    const float tx = r.x + (float)(cax - (t.ix[B] << shB));
+    const float ty = r.y + (float)(cay - (t.iy[B] << shB));
+    const int s0 = t.sb[B], s1 = t.se[B];
+    wn += a.leaf_w[B];
+    if (B == A)
+      p2p32_leaf<true>(a.src4, s0, s1, tx, ty, sum, comp);
+    else
+      p2p32_leaf<false>(a.src4, s0, s1, tx, ty, sum, comp);
+  }
+  if (active) a.near_sum[k] = ((double)sum - (double)comp) * kLn2;
+  if (lane == 0 && it.y == 0) a.leaf_wnear[A] = wn;
+}
+
+template <bool GUARD>
+__device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double* __restrict__ w64, int s0, int s1,
+                                  double tx, double ty, double& sum) {
+#pragma unroll 2
+  for (int s = s0; s < s1; ++s) {
+    const float4 q = src4[s];
+    const double w = w64[s];
+    const double dx = tx - (double)q.x;
+    const double dy = ty - (double)q.y;
+    const double r2 = fma(dy, dy, dx * dx);
+    if (GUARD && r2 == 0.0) continue;
+    sum = fma(w, log(r2), sum);
+  }
+}
+
+template <bool DIRECT>
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int2* __restrict__ items, int nitems) {
+  // wave-uniform work index (keeps all per-item data in scalar registers)
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
+  if (wid >= nitems) return;
+  const int lane = threadIdx.x % kWave;
+  const TreeView& t = a.t;
+  const int2 it = items[wid];
+  const int A = it.x;
+  const int k = t.tb[A] + it.y + lane;
+  const bool active = k < t.te[A];
+  const double2 r = active ? a.rel64[k] : make_double2(0.0, 0.0);
+  const int shA = t.D - t.lvl[A];
+  const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
+  const int nb = DIRECT ? a.nsleaves : a.list_cnt[A];
+  const int* lst = DIRECT ? a.sleaves : a.list_src + a.list_off[A];
+  double sum = 0.0;
+  double wn = 0.0;
+  for (int e = 0; e < nb; ++e) {
+    const int B = lst[e];
+    const int shB = t.D - t.lvl[B];
+    const double tx = r.x + (double)(cax - (t.ix[B] << shB));
+    const double ty = r.y + (double)(cay - (t.iy[B] << shB));
+    const int s0 = t.sb[B], s1 = t.se[B];
+    wn += a.leaf_w[B];
+    if (B == A)
+      p2p64_leaf<true>(a.src4, a.w64, s0, s1, tx, ty, sum);
+    else
+      p2p64_leaf<false>(a.src4, a.w64, s0, s1, tx, ty, sum);
+  }
+  if (active) a.near_sum[k] = sum;
+  if (lane == 0 && it.y == 0) a.leaf_wnear[A] = wn;
+}
+}  // namespace
+
+void p2p_chunks_count(TreeView t, const int* tleaves, int n, int* cnt, hipStream_t s) {
+  if (n <= 0) return;
+  k_chunk_count<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, cnt);
+}
+
+void p2p_chunks_emit(TreeView t, const int* tleaves, int n, const int* off, int2* items, hipStream_t s) {
+  if (n <= 0) return;
+  k_chunk_emit<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, off, items);
+}
+
+void p2p(const P2PArgs& a, const int2* items, int nitems, int fp64, hipStream_t s) {
+  if (nitems <= 0) return;
+  const unsigned g = (unsigned)((nitems + kP2PWaves - 1) / kP2PWaves);
+  const bool direct = a.list_cnt == nullptr;
+  if (fp64) {
+    if (direct)
+      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+    else
+      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+  } else {
+    if (direct)
+      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+    else
+      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+  }
+}
+
+}  // namespace pp

@@ -1,0 +1,547 @@
+// Host pipeline and C ABI of the pressure-Poisson tree-code library.
+//
+// One solve (eq. greenSum of Appendix A evaluated with a quadtree):
+//   ingest (w = f h^2, Morton order) -> target keys + radix sort -> tree levels
+//   -> cell lists -> interaction lists -> P2M -> M2M (levels up) -> M2L ->
+//   L2L (levels down) -> L2P -> P2P -> finalize (1/2pi, self rule, caller order).
+// Every step runs on the GPU; the host only sizes buffers from counts the
+// kernels produce (a few small read-backs per solve) and sequences launches on
+// the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/pp.h"
+#include "internal.h"
+
+using namespace pp;
+
+namespace {
+
+struct PPError {
+  pp_status code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                             \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess) throw PPError{PP_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+enum BufId {
+  B_F, B_TX, B_TY, B_OUT, B_MISC, B_PAIRS, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
+  B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
+  B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
+  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR,
+  B_COUNT
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Metadata of the last successful solve (for pp_debug_copy).
+struct Last {
+  bool valid = false;
+  int64_t n_src = 0, m = 0;
+  int ncells = 0, p = 0;
+  int64_t n_m2l = 0, n_p2p = 0;
+  bool has_expansions = false;
+};
+
+constexpr int kMiscInts = 128;
+// misc layout: [0] flags, [1] source count, [2] scratch total, [4..] totals of the
+// cell compactions and list scans, [32..] per-level M2M counts, [64..] per-level L2L counts.
+constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7, M_NP2P = 8,
+              M_NITEMS = 9, M_M2M = 32, M_L2L = 64;
+
+}  // namespace
+
+struct pp_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  size_t held = 0;
+  DevBuf bufs[B_COUNT];
+  int* pinned = nullptr;  // kMiscInts ints of pinned host memory for read-backs
+  std::string err;
+  bool dead = false;
+  Last last;
+  pp_stats stats{};
+};
+
+namespace {
+
+void release(pp_ctx& c, int id) {
+  DevBuf& b = c.bufs[id];
+  if (b.p) {
+    (void)hipFree(b.p);
+    c.held -= b.bytes;
+  }
+  b = DevBuf{};
+}
+
+template <class T>
+T* ensure(pp_ctx& c, int id, int64_t count) {
+  const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  DevBuf& b = c.bufs[id];
+  if (b.bytes >= bytes) return (T*)b.p;
+  size_t want = bytes + bytes / 4;
+  const size_t others = c.held - b.bytes;
+  if (c.budget && others + want > c.budget) want = bytes;
+  if (c.budget && others + want > c.budget)
+    throw PPError{PP_ERR_NOMEM, "device-memory budget exceeded (" + std::to_string(others + want) + " > " +
+                                    std::to_string(c.budget) + " bytes)"};
+  release(c, id);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    throw PPError{PP_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed"};
+  }
+  HIPCHK(e);
+  b.p = p;
+  b.bytes = want;
+  c.held += want;
+  return (T*)p;
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  const hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+template <class T>
+const T* stage_in(pp_ctx& c, int id, const T* src, int64_t n, hipStream_t s) {
+  if (n <= 0 || is_device_ptr(src)) return src;
+  T* d = ensure<T>(c, id, n);
+  HIPCHK(hipMemcpyAsync(d, src, (size_t)n * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+
+void readback(pp_ctx& c, const int* dev, int first, int count, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(c.pinned + first, dev + first, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+int root_exponent(int nx, int ny) {
+  int n = std::max(nx, ny), k = 0;
+  while ((1 << k) < n) ++k;
+  return k;
+}
+
+void check_flags(int flags) {
+  if (flags & (kFlagNonFiniteSource | kFlagNonFiniteTarget))
+    throw PPError{PP_ERR_ARG, "non-finite source value or target coordinate"};
+  if (flags & kFlagTargetOutside) throw PPError{PP_ERR_DOMAIN, "a target lies outside the root square"};
+  if (flags & kFlagFrontierOverflow) throw PPError{PP_ERR_LIMIT, "traversal frontier exceeded its capacity"};
+  if (flags) throw PPError{PP_ERR_DEVICE, "unknown kernel flag"};
+}
+
+void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m, const double* tx,
+              const double* ty, const pp_params* prm, const double* p_out) {
+  if (!prm) throw PPError{PP_ERR_ARG, "params is null"};
+  if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536 || (int64_t)nx * ny >= ((int64_t)1 << 31))
+    throw PPError{PP_ERR_ARG, "grid size out of range"};
+  if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(x0) || !std::isfinite(y0))
+    throw PPError{PP_ERR_ARG, "h must be positive and finite, x0/y0 finite"};
+  if (!f) throw PPError{PP_ERR_ARG, "f is null"};
+  if (m < 0 || m >= ((int64_t)1 << 31)) throw PPError{PP_ERR_ARG, "target count out of range"};
+  if (m > 0 && (!tx || !ty || !p_out)) throw PPError{PP_ERR_ARG, "target or output pointer is null"};
+  if (prm->p < 1 || prm->p > kMaxP) throw PPError{PP_ERR_ARG, "p must lie in [1, 20]"};
+  if (!(prm->theta > 0.0 && prm->theta < 1.0)) throw PPError{PP_ERR_ARG, "theta must lie in (0, 1)"};
+  const int num = (int)std::lround(prm->theta * 1000.0);
+  if (num < 1 || num > 999) throw PPError{PP_ERR_ARG, "theta rounds to 0 or 1"};
+  if (prm->leaf_max < 1 || prm->leaf_max > 4096) throw PPError{PP_ERR_ARG, "leaf_max must lie in [1, 4096]"};
+  if (prm->precision != PP_FP64 && prm->precision != PP_MIXED) throw PPError{PP_ERR_ARG, "unknown precision"};
+  if (prm->self_mode != PP_SELF_SKIP && prm->self_mode != PP_SELF_CELLAVG) throw PPError{PP_ERR_ARG, "unknown self mode"};
+}
+
+// Compact the cells of [c0, c1) satisfying `kind` into out[dst..]; count to misc[slot].
+void compact_cells(pp_ctx& c, TreeArrays ta, int c0, int c1, int kind, int* out, int* misc, int slot, hipStream_t s) {
+  const int n = c1 - c0;
+  if (n <= 0) {
+    fill_i32(misc + slot, 0, 1, s);
+    return;
+  }
+  int* flag = ensure<int>(c, B_FLAG, n);
+  int* off = ensure<int>(c, B_FOFF, n);
+  int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(n));
+  cell_flags(ta, c0, c1, kind, flag, s);
+  scan_exclusive(flag, off, n, scan, misc + slot, s);
+  compact_indices(flag, off, c0, c1, out, s);
+}
+
+pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
+                    int64_t m, const double* tx, const double* ty, const pp_params& prm, double* p_out,
+                    hipStream_t s) {
+  const auto t_start = std::chrono::steady_clock::now();
+  HIPCHK(hipSetDevice(c.device));
+  c.last.valid = false;
+  const int k = root_exponent(nx, ny);
+  const int D = k;
+  const int64_t ngrid = (int64_t)nx * ny;
+  const int p = prm.p;
+  const int g = std::gcd((int)std::lround(prm.theta * 1000.0), 1000);
+  const int num = (int)std::lround(prm.theta * 1000.0) / g, den = 1000 / g;
+  const bool mixed = prm.precision == PP_MIXED;
+
+  const double* f_d = stage_in(c, B_F, f, ngrid, s);
+  const double* tx_d = stage_in(c, B_TX, tx, m, s);
+  const double* ty_d = stage_in(c, B_TY, ty, m, s);
+  const bool out_on_device = is_device_ptr(p_out);
+  double* out_d = out_on_device ? p_out : ensure<double>(c, B_OUT, m);
+
+  int* misc = ensure<int>(c, B_MISC, kMiscInts);
+  // one scratch size for every prefix sum of the solve (tiles, cells, lists, targets)
+  unsigned long long* pairs = ensure<unsigned long long>(c, B_PAIRS, 1);
+  fill_i32(misc, 0, kMiscInts, s);
+  fill_i32((int*)pairs, 0, 2, s);
+
+  const int64_t ntiles = ingest_num_tiles(k);
+  int64_t geo = 0;
+  for (int l = 0; l <= D; ++l) geo += (int64_t)1 << (2 * l);
+  const int64_t cap_bound = std::min<int64_t>(geo, 1 + 4 * (int64_t)std::max(D, 1) *
+                                                           (ngrid / (prm.leaf_max + 1) + m / (prm.leaf_max + 1) + 1)) + 1;
+  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max<int64_t>({ntiles, cap_bound, m, 1})));
+
+  // ---- ingest: sources in Morton order (no sort needed for a grid) ----
+  int* tile = ensure<int>(c, B_TILE, ntiles);
+  ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
+  scan_exclusive(tile, tile, ntiles, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ntiles)), misc + M_NSRC, s);
+  uint32_t* skey = ensure<uint32_t>(c, B_SKEY, ngrid);
+  uint32_t* sij = ensure<uint32_t>(c, B_SIJ, ngrid);
+  double* sw = ensure<double>(c, B_SW, ngrid);
+  ingest_grid_emit(f_d, nx, ny, k, h * h, tile, skey, sij, sw, s);
+
+  // ---- targets: Morton keys and a stable radix sort ----
+  uint32_t* tkey = ensure<uint32_t>(c, B_TKEY, m);
+  int* tperm = ensure<int>(c, B_TPERM, m);
+  target_keys(tx_d, ty_d, m, x0, y0, h, k, tkey, tperm, misc + M_FLAGS, s);
+  radix_sort_pairs(tkey, tperm, ensure<uint32_t>(c, B_TKEY2, m), ensure<int>(c, B_TPERM2, m), m, 2 * k,
+                   ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(m)), s);
+  readback(c, misc, 0, 2, s);
+  check_flags(c.pinned[M_FLAGS]);
+  const int64_t N = c.pinned[M_NSRC];
+
+  // ---- tree, top down ----
+  const int64_t cap = std::min<int64_t>(geo, 1 + 4 * (int64_t)std::max(D, 1) *
+                                                     (N / (prm.leaf_max + 1) + m / (prm.leaf_max + 1) + 1)) + 1;
+  TreeArrays ta{ensure<int>(c, B_LVL, cap),   ensure<int>(c, B_IX, cap),     ensure<int>(c, B_IY, cap),
+                ensure<int>(c, B_SB, cap),    ensure<int>(c, B_SE, cap),     ensure<int>(c, B_TB, cap),
+                ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
+                ensure<int>(c, B_PARENT, cap)};
+  tree_init_root(ta, misc + M_NSRC, (int)m, s);
+  std::vector<int> lstart = {0, 1};
+  for (int l = 0;; ++l) {
+    const int c0 = lstart[l], c1 = lstart[l + 1], n = c1 - c0;
+    int* cnt = ensure<int>(c, B_CNT, n);
+    int* off = ensure<int>(c, B_OFF, n);
+    int* cr = ensure<int>(c, B_CR, 16 * (int64_t)n);
+    tree_level_count(ta, c0, c1, l, D, prm.leaf_max, skey, tkey, cnt, cr, s);
+    scan_exclusive(cnt, off, n, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(n)), misc + M_TOT, s);
+    readback(c, misc, M_TOT, 1, s);
+    const int total = c.pinned[M_TOT];
+    if ((int64_t)c1 + total > cap) throw PPError{PP_ERR_LIMIT, "cell capacity exceeded"};
+    tree_level_emit(ta, c0, c1, l, cnt, off, cr, c1, s);
+    if (total == 0) break;
+    lstart.push_back(c1 + total);
+  }
+  const int ncells = lstart.back();
+  const int depth = (int)lstart.size() - 2;
+  const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
+
+  // ---- cell lists: source leaves, target leaves, target cells, per-level M2M / L2L cells ----
+  int* sleaves = ensure<int>(c, B_SLEAF, ncells);
+  int* tleaves = ensure<int>(c, B_TLEAF, ncells);
+  int* tcells = ensure<int>(c, B_TCELL, ncells);
+  int* m2mc = ensure<int>(c, B_M2MC, ncells);
+  int* l2lc = ensure<int>(c, B_L2LC, ncells);
+  compact_cells(c, ta, 0, ncells, 0, sleaves, misc, M_NSL, s);
+  compact_cells(c, ta, 0, ncells, 1, tleaves, misc, M_NTL, s);
+  if (!direct) {
+    compact_cells(c, ta, 0, ncells, 2, tcells, misc, M_NTC, s);
+    for (int l = 0; l <= depth; ++l) {
+      compact_cells(c, ta, lstart[l], lstart[l + 1], 3, m2mc + lstart[l], misc, M_M2M + l, s);
+      compact_cells(c, ta, lstart[l], lstart[l + 1], 2, l2lc + lstart[l], misc, M_L2L + l, s);
+    }
+  }
+  readback(c, misc, 0, kMiscInts, s);
+  const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
+  std::vector<int> n_m2m(depth + 1), n_l2l(depth + 1);
+  for (int l = 0; l <= depth; ++l) {
+    n_m2m[l] = c.pinned[M_M2M + l];
+    n_l2l[l] = c.pinned[M_L2L + l];
+  }
+
+  // ---- interaction lists and near-field work items ----
+  int* cm2l = ensure<int>(c, B_CM2L, ncells);
+  int* om2l = ensure<int>(c, B_OM2L, ncells);
+  int* cp2p = ensure<int>(c, B_CP2P, ncells);
+  int* op2p = ensure<int>(c, B_OP2P, ncells);
+  int* chcnt = ensure<int>(c, B_CHCNT, std::max(ntl, 1));
+  int* choff = ensure<int>(c, B_CHOFF, std::max(ntl, 1));
+  if (!direct) {
+    fill_i32(cm2l, 0, ncells, s);
+    fill_i32(cp2p, 0, ncells, s);
+    lists_pass(tv, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, misc + M_FLAGS, s);
+    int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
+    scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
+    scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
+  }
+  p2p_chunks_count(tv, tleaves, ntl, chcnt, s);
+  scan_exclusive(chcnt, choff, ntl, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max(ntl, 1))),
+                 misc + M_NITEMS, s);
+  readback(c, misc, 0, 16, s);
+  check_flags(c.pinned[M_FLAGS]);
+  const int n_m2l = direct ? 0 : c.pinned[M_NM2L];
+  const int n_p2pl = direct ? 0 : c.pinned[M_NP2P];
+  const int nitems = c.pinned[M_NITEMS];
+  int* m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
+  int* p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
+  if (!direct) {
+    lists_pass(tv, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, misc + M_FLAGS, s);
+    p2p_pair_count(tv, tleaves, ntl, op2p, cp2p, p2p_src, pairs, s);
+  }
+  int2* items = ensure<int2>(c, B_ITEMS, nitems);
+  p2p_chunks_emit(tv, tleaves, ntl, choff, items, s);
+
+  // ---- per-leaf packing ----
+  float4* src4 = ensure<float4>(c, B_SRC4, N);
+  double* leaf_w = ensure<double>(c, B_LEAFW, ncells);
+  leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
+  float2* rel32 = ensure<float2>(c, B_REL32, m);
+  double2* rel64 = ensure<double2>(c, B_REL64, m);
+  int* tgtleaf = ensure<int>(c, B_TGTLEAF, m);
+  int* selfi = ensure<int>(c, B_SELFI, m);
+  double* selfd = ensure<double>(c, B_SELFD, m);
+  leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, h, nx, ny, rel32, rel64, tgtleaf, selfi, selfd, s);
+
+  // ---- expansions: upward and downward passes ----
+  double* far = nullptr;
+  if (!direct) {
+    double2* mp = ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
+    double2* loc = ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
+    p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
+    for (int l = depth - 1; l >= 0; --l) m2m_level(tv, m2mc + lstart[l], n_m2m[l], p, mp, s);
+    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, loc, s);
+    for (int l = 1; l <= depth; ++l) l2l_level(tv, l2lc + lstart[l], n_l2l[l], p, loc, s);
+    far = ensure<double>(c, B_FAR, m);
+    l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+  }
+
+  // ---- near field ----
+  double* near = ensure<double>(c, B_NEAR, m);
+  double* wnear = ensure<double>(c, B_WNEAR, ncells);
+  P2PArgs pa{};
+  pa.t = tv;
+  pa.tleaves = tleaves;
+  pa.ntleaves = ntl;
+  pa.list_off = direct ? nullptr : op2p;
+  pa.list_cnt = direct ? nullptr : cp2p;
+  pa.list_src = direct ? nullptr : p2p_src;
+  pa.sleaves = sleaves;
+  pa.nsleaves = nsl;
+  pa.src4 = src4;
+  pa.w64 = sw;
+  pa.leaf_w = leaf_w;
+  pa.rel32 = rel32;
+  pa.rel64 = rel64;
+  pa.near_sum = near;
+  pa.leaf_wnear = wnear;
+  p2p(pa, items, nitems, mixed ? 0 : 1, s);
+
+  // ---- finalize ----
+  finalize(m, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS, out_d, s);
+  readback(c, misc, 0, 1, s);
+  check_flags(c.pinned[M_FLAGS]);
+  if (!out_on_device && m > 0) {
+    HIPCHK(hipMemcpyAsync(p_out, out_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  unsigned long long npairs = 0;
+  if (!direct) {
+    HIPCHK(hipMemcpyAsync(&npairs, pairs, sizeof(npairs), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    npairs = (unsigned long long)N * (unsigned long long)m;
+  }
+
+  c.stats.depth = depth;
+  c.stats.ncells = ncells;
+  c.stats.nsrc_leaves = nsl;
+  c.stats.ntgt_leaves = ntl;
+  c.stats.nsources = N;
+  c.stats.ntargets = m;
+  c.stats.n_m2l = n_m2l;
+  c.stats.n_p2p_lists = direct ? (int64_t)nsl * ntl : n_p2pl;
+  c.stats.n_p2p_pairs = (int64_t)npairs;
+  c.stats.ms_total =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  c.last.valid = true;
+  c.last.n_src = N;
+  c.last.m = m;
+  c.last.ncells = ncells;
+  c.last.p = p;
+  c.last.n_m2l = n_m2l;
+  c.last.n_p2p = n_p2pl;
+  c.last.has_expansions = !direct;
+  return PP_OK;
+}
+
+pp_status guard(pp_ctx* c, bool direct, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
+                int64_t m, const double* tx, const double* ty, const pp_params* prm, double* p_out, void* stream) {
+  if (!c) return PP_ERR_ARG;
+  if (c->dead) {
+    c->err = "context is unusable after a device error";
+    return PP_ERR_DEVICE;
+  }
+  try {
+    validate(nx, ny, x0, y0, h, f, m, tx, ty, prm, p_out);
+    if (m == 0) return PP_OK;
+    pp_status st = run_solve(*c, direct, nx, ny, x0, y0, h, f, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+    c->err.clear();
+    return st;
+  } catch (const PPError& e) {
+    c->err = e.msg;
+    if (e.code == PP_ERR_DEVICE) c->dead = true;
+    c->last.valid = false;
+    return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    c->last.valid = false;
+    return PP_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
+  if (!out) return PP_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return PP_ERR_DEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) return PP_ERR_DEVICE;
+  pp_ctx* c = new pp_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (hipHostMalloc((void**)&c->pinned, kMiscInts * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return PP_ERR_DEVICE;
+  }
+  *out = c;
+  return PP_OK;
+}
+
+void pp_destroy(pp_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (int i = 0; i < B_COUNT; ++i) release(*c, i);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+}
+
+pp_status pp_solve_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
+                        const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
+  return guard(c, false, nx, ny, x0, y0, h, f, m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_direct_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
+                         const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
+  return guard(c, true, nx, ny, x0, y0, h, f, m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_get_stats(const pp_ctx* c, pp_stats* out) {
+  if (!c || !out) return PP_ERR_ARG;
+  *out = c->stats;
+  return PP_OK;
+}
+
+pp_status pp_debug_copy(const pp_ctx* cc, int32_t what, void* dst, int64_t capacity, int64_t* length) {
+  if (!cc || (capacity > 0 && !dst)) return PP_ERR_ARG;
+  pp_ctx* c = const_cast<pp_ctx*>(cc);
+  if (!c->last.valid) {
+    c->err = "no successful solve to inspect";
+    return PP_ERR_ARG;
+  }
+  const Last& L = c->last;
+  int id = -1;
+  int64_t n = 0;
+  size_t esz = 4;
+  switch (what) {
+    case PP_ARR_SRC_KEY: id = B_SKEY; n = L.n_src; break;
+    case PP_ARR_SRC_INDEX: id = B_SIJ; n = L.n_src; break;
+    case PP_ARR_TGT_KEY: id = B_TKEY; n = L.m; break;
+    case PP_ARR_TGT_PERM: id = B_TPERM; n = L.m; break;
+    case PP_ARR_CELL_LEVEL: id = B_LVL; n = L.ncells; break;
+    case PP_ARR_CELL_IX: id = B_IX; n = L.ncells; break;
+    case PP_ARR_CELL_IY: id = B_IY; n = L.ncells; break;
+    case PP_ARR_CELL_SB: id = B_SB; n = L.ncells; break;
+    case PP_ARR_CELL_SE: id = B_SE; n = L.ncells; break;
+    case PP_ARR_CELL_TB: id = B_TB; n = L.ncells; break;
+    case PP_ARR_CELL_TE: id = B_TE; n = L.ncells; break;
+    case PP_ARR_CELL_CHILD: id = B_CHILD; n = L.ncells; break;
+    case PP_ARR_CELL_NCHILD: id = B_NCHILD; n = L.ncells; break;
+    case PP_ARR_CELL_PARENT: id = B_PARENT; n = L.ncells; break;
+    case PP_ARR_M2L_OFF: id = L.has_expansions ? B_OM2L : -1; n = L.ncells; break;
+    case PP_ARR_M2L_CNT: id = L.has_expansions ? B_CM2L : -1; n = L.ncells; break;
+    case PP_ARR_M2L_SRC: id = L.has_expansions ? B_M2LSRC : -1; n = L.n_m2l; break;
+    case PP_ARR_P2P_OFF: id = L.has_expansions ? B_OP2P : -1; n = L.ncells; break;
+    case PP_ARR_P2P_CNT: id = L.has_expansions ? B_CP2P : -1; n = L.ncells; break;
+    case PP_ARR_P2P_SRC: id = L.has_expansions ? B_P2PSRC : -1; n = L.n_p2p; break;
+    case PP_ARR_MULTIPOLE: id = L.has_expansions ? B_MP : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
+    case PP_ARR_LOCAL: id = L.has_expansions ? B_LOC : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
+    case PP_ARR_FAR: id = L.has_expansions ? B_FAR : -1; n = L.m; esz = 8; break;
+    case PP_ARR_NEAR: id = B_NEAR; n = L.m; esz = 8; break;
+    case PP_ARR_LEAF_WNEAR: id = B_WNEAR; n = L.ncells; esz = 8; break;
+    case PP_ARR_TGT_LEAF: id = B_TGTLEAF; n = L.m; break;
+    default: c->err = "unknown array id"; return PP_ERR_ARG;
+  }
+  if (id < 0) {
+    c->err = "array not produced by the last call";
+    return PP_ERR_ARG;
+  }
+  if (length) *length = n;
+  const int64_t cnt = std::min(n, std::max<int64_t>(capacity, 0));
+  if (cnt <= 0) return PP_OK;
+  if (hipSetDevice(c->device) != hipSuccess ||
+      hipMemcpy(dst, c->bufs[id].p, (size_t)cnt * esz, hipMemcpyDeviceToHost) != hipSuccess) {
+    c->err = "copy failed";
+    return PP_ERR_DEVICE;
+  }
+  return PP_OK;
+}
+
+const char* pp_status_string(pp_status s) {
+  switch (s) {
+    case PP_OK: return "ok";
+    case PP_ERR_ARG: return "invalid argument";
+    case PP_ERR_DOMAIN: return "target outside the root square";
+    case PP_ERR_NOMEM: return "device-memory budget exceeded";
+    case PP_ERR_DEVICE: return "device error";
+    case PP_ERR_LIMIT: return "internal limit exceeded";
+    default: return "unknown status";
+  }
+}
+
+const char* pp_last_error(const pp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

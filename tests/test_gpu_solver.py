@@ -1,0 +1,235 @@
+"""GPU parity of the HIP tree-code against the CPU oracle (called through the C ABI).
+
+Tolerances: FP64-expansion runs rel-L2 <= 1e-6 against the FP64 direct sum,
+mixed runs (FP32 + Kahan near field and local evaluation) rel-L2 <= 1e-4; the
+GPU all-pairs direct sum itself is held to 1e-12 (FP64) and 1e-6 (mixed).
+Tree indexing is compared bit for bit with the reference quadtree.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import direct, fmm_ref, tree_ref
+from workloads import generators as G
+
+from gpu_common import rel_l2, rel_max, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_04398_amd as pp
+    s = pp.Solver(0)
+    yield s
+    s.close()
+
+
+def _case_random(seed, n=40, nt=500, zero_frac=0.3, h=None):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = rng.standard_normal((n, n))
+    f[rng.uniform(size=f.shape) < zero_frac] = 0.0
+    h = h or 1.0 / n
+    g = G.GridSpec(n, n, h)
+    x, y = G.grid_nodes(g)
+    tx = np.concatenate([x.ravel()[::3], 0.3 * n * h + 0.02 * n * h * rng.standard_normal(nt // 4),
+                         rng.uniform(0, n * h, nt)])
+    ty = np.concatenate([y.ravel()[::3], 0.6 * n * h + 0.02 * n * h * rng.standard_normal(nt // 4),
+                         rng.uniform(0, n * h, nt)])
+    tx = np.clip(tx, 0, n * h * (1 - 1e-12))
+    ty = np.clip(ty, 0, n * h * (1 - 1e-12))
+    return f, h, tx, ty
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_direct_gaussian64(solver, precision, tol):
+    w = G.workload("gaussian64")
+    g = w["grid"]
+    ref = direct.direct_grid(w["f"], g.h, w["tx"], w["ty"])
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    P = to_host(solver.direct_grid(f, g.h, tx, ty, precision=precision))
+    assert rel_l2(P, ref) < tol, rel_l2(P, ref)
+
+
+@pytest.mark.parametrize("mode", ["skip", "cellavg"])
+def test_direct_random_offgrid(solver, mode):
+    f, h, tx, ty = _case_random(1)
+    ref = direct.direct_grid(f, h, tx, ty, self_mode=1 if mode == "cellavg" else 0)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
+        P = solver.direct_grid(f, h, tx, ty, precision=prec, self_mode=mode, leaf_max=16)
+        assert rel_l2(P, ref) < tol, (prec, rel_l2(P, ref))
+
+
+def test_tree_bit_exact_gaussian64(solver):
+    w = G.workload("gaussian64")
+    g = w["grid"]
+    solver.solve_grid(w["f"], g.h, w["tx"], w["ty"], p=8, theta=0.5, precision="fp64")
+    info = tree_ref.grid_tree(w["f"], w["tx"], w["ty"], g.h, leaf_max=64)
+    _compare_tree(solver, info, 0.5, 64)
+
+
+def _compare_tree(solver, info, theta, nx):
+    t = info["tree"]
+    np.testing.assert_array_equal(solver.debug_array("SRC_KEY").astype(np.uint64), info["src_keys"])
+    ij = solver.debug_array("SRC_INDEX").astype(np.int64)
+    # packed (i | j << 16) versus the reference's flat j * nx + i
+    assert np.array_equal((ij >> 16) * nx + (ij & 0xFFFF), info["src_flat"])
+    np.testing.assert_array_equal(solver.debug_array("TGT_KEY").astype(np.uint64), info["tgt_keys"])
+    np.testing.assert_array_equal(solver.debug_array("TGT_PERM"), info["tgt_perm"])
+    for name, ref in (("CELL_LEVEL", t.level), ("CELL_IX", t.ix), ("CELL_IY", t.iy), ("CELL_SB", t.sb),
+                      ("CELL_SE", t.se), ("CELL_TB", t.tb), ("CELL_TE", t.te), ("CELL_CHILD", t.child_begin),
+                      ("CELL_NCHILD", t.nchild), ("CELL_PARENT", t.parent)):
+        np.testing.assert_array_equal(solver.debug_array(name), ref, err_msg=name)
+    m2l, p2p = tree_ref.interaction_lists(t, theta)
+    for kind, ref_pairs in (("M2L", m2l), ("P2P", p2p)):
+        off = solver.debug_array(kind + "_OFF")
+        cnt = solver.debug_array(kind + "_CNT")
+        src = solver.debug_array(kind + "_SRC")
+        got = sorted((a, int(b)) for a in range(t.ncells) for b in src[off[a]:off[a] + cnt[a]])
+        assert got == sorted(ref_pairs), kind
+
+
+@pytest.mark.parametrize("seed,leaf_max,theta", [(1, 8, 0.5), (2, 16, 0.4), (3, 4, 0.6)])
+def test_tree_bit_exact_adaptive(solver, seed, leaf_max, theta):
+    f, h, tx, ty = _case_random(seed, n=48 if seed != 3 else 37)
+    solver.solve_grid(f, h, tx, ty, p=6, theta=theta, leaf_max=leaf_max, precision="fp64")
+    info = tree_ref.grid_tree(f, tx, ty, h, leaf_max=leaf_max)
+    _compare_tree(solver, info, theta, f.shape[1])
+
+
+def test_fmm_gaussian64_fp64(solver):
+    w = G.workload("gaussian64")
+    g = w["grid"]
+    ref = direct.direct_grid(w["f"], g.h, w["tx"], w["ty"])
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    P = to_host(solver.solve_grid(f, g.h, tx, ty, p=8, theta=0.5, precision="fp64"))
+    e = rel_l2(P, ref)
+    assert e < 1e-6, e
+    # same approximation as the FP64 reference tree-code, to rounding
+    r = fmm_ref.fmm_grid(w["f"], w["tx"], w["ty"], g.h, 8, 0.5)
+    assert rel_l2(P, r["P"]) < 1e-12
+
+
+def test_fmm_per_pass_against_reference(solver):
+    f, h, tx, ty = _case_random(4, n=32, nt=300)
+    p = 10
+    solver.solve_grid(f, h, tx, ty, p=p, theta=0.5, leaf_max=16, precision="fp64")
+    r = fmm_ref.fmm_grid(f, tx, ty, h, p, 0.5, leaf_max=16)
+    t = r["tree"]
+    k = r["info"]["k"]
+    mp = solver.debug_array("MULTIPOLE").reshape(t.ncells, p + 1, 2)
+    loc = solver.debug_array("LOCAL").reshape(t.ncells, p + 1, 2)
+    mpc = mp[..., 0] + 1j * mp[..., 1]
+    locc = loc[..., 0] + 1j * loc[..., 1]
+    for c in range(t.ncells):
+        s = h * 2.0 ** (k - t.level[c])
+        kk = np.arange(p + 1)
+        if t.nsrc(c) > 0:
+            # scaled a'_k = a_k / s^k with a_0 = S, a_k = -alpha_k
+            ref_a = np.concatenate([[r["S"][c]], -r["alpha"][c][1:]]) / s**kk
+            assert np.allclose(mpc[c], ref_a, rtol=1e-11, atol=1e-13 * abs(ref_a).max() + 1e-300), c
+        if t.ntgt(c) > 0:
+            ref_l = r["L"][c] * s**kk
+            scale = np.abs(ref_l).max() + 1e-300
+            assert np.max(np.abs(locc[c] - ref_l)) < 1e-10 * scale, c
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_fmm_random_cases(solver, precision, tol):
+    for seed in (5, 6):
+        for mode in ("skip", "cellavg"):
+            f, h, tx, ty = _case_random(seed, n=64, nt=800)
+            ref = direct.direct_grid(f, h, tx, ty, self_mode=1 if mode == "cellavg" else 0)
+            P = solver.solve_grid(f, h, tx, ty, p=12, theta=0.5, leaf_max=32, precision=precision, self_mode=mode)
+            assert rel_l2(P, ref) < tol, (seed, mode, rel_l2(P, ref))
+
+
+def test_host_and_device_pointers_agree_and_deterministic(solver):
+    f, h, tx, ty = _case_random(7, n=64)
+    P1 = solver.solve_grid(f, h, tx, ty, precision="mixed")
+    fd, txd, tyd = to_dev(f, tx, ty)
+    P2 = to_host(solver.solve_grid(fd, h, txd, tyd, precision="mixed"))
+    P3 = to_host(solver.solve_grid(fd, h, txd, tyd, precision="mixed"))
+    assert np.array_equal(P1, P2) and np.array_equal(P2, P3)
+
+
+def test_vortex512_sampled(solver):
+    """The 512^2 vortex workload at full size; targets sampled for the oracle."""
+    w = G.workload("vortex512")
+    g = w["grid"]
+    rng = np.random.Generator(np.random.PCG64(12))
+    sel = np.concatenate([rng.choice(w["n_grid_targets"], 1500, replace=False),
+                          w["n_grid_targets"] + rng.choice(2048, 500, replace=False)])
+    ref = direct.direct_grid(w["f"], g.h, w["tx"][sel], w["ty"][sel])
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    for prec, tol in (("fp64", 1e-6), ("mixed", 1e-4)):
+        P = to_host(solver.solve_grid(f, g.h, tx, ty, p=12, theta=0.5, precision=prec))
+        e_grid = rel_l2(P[sel[:1500]], ref[:1500])
+        e_surf = rel_l2(P[sel[1500:]], ref[1500:])
+        assert e_grid < tol and e_surf < tol, (prec, e_grid, e_surf)
+
+
+def test_error_paths_leave_output_untouched(solver):
+    import paper_1610_04398_amd as pp
+    f, h, tx, ty = _case_random(8, n=16, nt=20)
+    out = np.full(tx.size, 7.0)
+    with pytest.raises(pp.PPError) as e:
+        solver.solve_grid(f, h, np.concatenate([tx[:-1], [2.0]]), ty, out=out)
+    assert e.value.status == -2 and np.all(out == 7.0)
+    bad = f.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(pp.PPError) as e:
+        solver.solve_grid(bad, h, tx, ty, out=out)
+    assert e.value.status == -1 and np.all(out == 7.0)
+    with pytest.raises(pp.PPError) as e:
+        solver.solve_grid(f, h, tx, ty, p=0, out=out)
+    assert e.value.status == -1
+    with pytest.raises(pp.PPError) as e:
+        solver.solve_grid(f, h, tx, ty, theta=1.0, out=out)
+    assert e.value.status == -1
+    with pytest.raises(pp.PPError) as e:
+        solver.solve_grid(f, -h, tx, ty, out=out)
+    assert e.value.status == -1
+    assert np.all(out == 7.0)
+
+
+def test_degenerate_inputs(solver):
+    # all-zero sources: P == 0
+    f = np.zeros((8, 8))
+    tx = np.array([0.1, 0.5, 0.93])
+    ty = np.array([0.2, 0.5, 0.01])
+    assert np.all(solver.solve_grid(f, 1 / 8, tx, ty) == 0.0)
+    # single node, single target on it (skip -> 0, cellavg -> w (ln h - kappa) / 2pi)
+    f1 = np.array([[2.0]])
+    assert solver.solve_grid(f1, 0.5, [0.25], [0.25], precision="fp64")[0] == 0.0
+    v = solver.solve_grid(f1, 0.5, [0.25], [0.25], precision="fp64", self_mode="cellavg")[0]
+    kappa = 1.5 - math.pi / 4 + 0.5 * math.log(2)
+    assert abs(v - 0.5 * (math.log(0.5) - kappa) / (2 * math.pi)) < 1e-15
+    # no targets
+    assert solver.solve_grid(f1, 0.5, np.zeros(0), np.zeros(0)).size == 0
+    # non-square, non-power-of-two grid with a ragged tail
+    rng = np.random.Generator(np.random.PCG64(9))
+    f2 = rng.standard_normal((37, 101))
+    h = 0.01
+    tx = rng.uniform(0, 1.27, 400)
+    ty = rng.uniform(0, 1.27, 400)
+    ref = direct.direct_grid(f2, h, tx, ty)
+    for prec, tol in (("fp64", 1e-6), ("mixed", 1e-4)):
+        P = solver.solve_grid(f2, h, tx, ty, precision=prec, leaf_max=16)
+        assert rel_l2(P, ref) < tol
+    # targets within 2^-20 h of a node but not on it, and exactly on it
+    g = G.GridSpec(16, 16, 1 / 16)
+    f3 = rng.standard_normal((16, 16))
+    x, y = G.grid_nodes(g)
+    tx = np.array([x[3, 5], x[3, 5] + 1e-9, x[7, 2] - 3e-12, 0.5])
+    ty = np.array([y[3, 5], y[3, 5], y[7, 2] + 1e-10, 0.5])
+    ref = direct.direct_grid(f3, 1 / 16, tx, ty)
+    P = solver.solve_grid(f3, 1 / 16, tx, ty, precision="fp64", leaf_max=8)
+    assert rel_max(P, ref) < 1e-9
+    P = solver.solve_grid(f3, 1 / 16, tx, ty, precision="mixed", leaf_max=8)
+    assert rel_max(P, ref) < 1e-5
