@@ -92,7 +92,25 @@ typedef struct {
   int64_t n_p2p_lists;    /* P2P (leaf, leaf) pairs */
   int64_t n_p2p_pairs;    /* P2P (target, source) interactions */
   double ms_total;        /* wall time of the call on the host, ms */
+  /* GPU time per phase (HIP events on the call's stream), filled only while
+   * profiling is enabled with pp_set_profiling; indices PP_PHASE_*. */
+  double ms_phase[12];
 } pp_stats;
+
+enum {
+  PP_PHASE_INGEST = 0,   /* input staging, source weights in Morton order */
+  PP_PHASE_SORT = 1,     /* target keys and radix sort */
+  PP_PHASE_TREE = 2,     /* quadtree levels */
+  PP_PHASE_LISTS = 3,    /* cell lists, interaction lists, near-field work items */
+  PP_PHASE_PACK = 4,     /* per-leaf source records and target offsets */
+  PP_PHASE_P2M = 5,
+  PP_PHASE_M2M = 6,
+  PP_PHASE_M2L = 7,
+  PP_PHASE_L2L = 8,
+  PP_PHASE_L2P = 9,
+  PP_PHASE_P2P = 10,
+  PP_PHASE_FINALIZE = 11
+};
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
  * device memory the context may hold (0 = no bound).  *out receives the
@@ -114,6 +132,11 @@ pp_status pp_direct_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double 
                          void* hip_stream);
 
 pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
+
+/* Enable (on != 0) or disable per-phase GPU timing of later calls.  Timing
+ * records HIP events between phases on the call's stream; it adds no
+ * synchronisation beyond the call's own. */
+pp_status pp_set_profiling(pp_ctx* ctx, int32_t on);
 
 /*
  * Introspection of the last successful solve on a context, for testing: copy

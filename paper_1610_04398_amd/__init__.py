@@ -23,6 +23,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_direct_grid,
     pp_get_stats,
     pp_last_error,
+    pp_set_profiling,
     pp_solve_grid,
     pp_status_string,
     pp_params,
@@ -77,15 +78,15 @@ class Solver:
 
     def _run(self, fn, f, h, tx, ty, x0, y0, params, out, stream):
         torch_mode = _is_torch(tx)
-        fshape = tuple(f.shape)
+        fp, fk = _ptr(f, "f")
+        fshape = tuple(fk.shape)
         if len(fshape) != 2:
             raise ValueError("f must have shape (ny, nx)")
         ny, nx = fshape
-        fp, fk = _ptr(f, "f")
         xp, xk = _ptr(tx, "tx")
         yp, yk = _ptr(ty, "ty")
-        m = int(np.prod(tuple(tx.shape)))
-        if int(np.prod(tuple(ty.shape))) != m:
+        m = int(np.prod(tuple(xk.shape)))
+        if int(np.prod(tuple(yk.shape))) != m:
             raise ValueError("tx and ty differ in length")
         if out is None:
             if torch_mode:
@@ -117,9 +118,16 @@ class Solver:
         prm = make_params(1, 0.5, leaf_max, precision, self_mode)
         return self._run(pp_direct_grid, f, h, tx, ty, x0, y0, prm, out, stream)
 
+    def set_profiling(self, on: bool = True) -> None:
+        st = pp_set_profiling(self._ctx, on)
+        if st != B.PP_OK:
+            raise PPError(st, pp_last_error(self._ctx))
+
     def stats(self) -> dict:
         s = pp_get_stats(self._ctx)
-        return {name: getattr(s, name) for name, _ in B.pp_stats._fields_}
+        d = {name: getattr(s, name) for name, _ in B.pp_stats._fields_ if name != "ms_phase"}
+        d["ms_phase"] = dict(zip(B.PHASES, list(s.ms_phase)))
+        return d
 
     def debug_array(self, name: str) -> np.ndarray:
         """A device array of the last solve (see PP_ARR_* in include/pp.h), copied to the host."""

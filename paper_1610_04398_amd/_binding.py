@@ -34,8 +34,8 @@ DOUBLE_ARRAYS = {"MULTIPOLE", "LOCAL", "FAR", "NEAR", "LEAF_WNEAR"}
 UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
-EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_get_stats", "pp_debug_copy",
-            "pp_status_string", "pp_last_error")
+EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_get_stats", "pp_set_profiling",
+            "pp_debug_copy", "pp_status_string", "pp_last_error")
 
 
 class pp_params(ctypes.Structure):
@@ -47,7 +47,9 @@ class pp_stats(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("ncells", ctypes.c_int32), ("nsrc_leaves", ctypes.c_int32),
                 ("ntgt_leaves", ctypes.c_int32), ("nsources", ctypes.c_int64), ("ntargets", ctypes.c_int64),
                 ("n_m2l", ctypes.c_int64), ("n_p2p_lists", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 12)]
+
+PHASES = ("ingest", "sort", "tree", "lists", "pack", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "finalize")
 
 
 class LibraryMissing(ImportError):
@@ -73,6 +75,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_direct_grid.restype = i32
     lib.pp_get_stats.argtypes = [vp, ctypes.POINTER(pp_stats)]
     lib.pp_get_stats.restype = i32
+    lib.pp_set_profiling.argtypes = [vp, i32]
+    lib.pp_set_profiling.restype = i32
     lib.pp_debug_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
     lib.pp_debug_copy.restype = i32
     lib.pp_status_string.argtypes = [i32]
@@ -120,6 +124,10 @@ def pp_get_stats(ctx) -> pp_stats:
     if st != PP_OK:
         raise PPError(st, "pp_get_stats failed")
     return s
+
+
+def pp_set_profiling(ctx, on: bool) -> int:
+    return lib().pp_set_profiling(ctx, 1 if on else 0)
 
 
 def pp_debug_copy(ctx, what: int, dst_ptr, capacity: int) -> tuple[int, int]:

@@ -67,6 +67,8 @@ constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_NSL = 4, M_NTL = 5, M_NTC = 
 
 struct pp_ctx {
   int device = 0;
+  bool profiling = false;
+  hipEvent_t ev[13] = {};
   uint64_t budget = 0;
   size_t held = 0;
   DevBuf bufs[B_COUNT];
@@ -199,6 +201,10 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   const int num = (int)std::lround(prm.theta * 1000.0) / g, den = 1000 / g;
   const bool mixed = prm.precision == PP_MIXED;
 
+  auto mark = [&](int i) {
+    if (c.profiling) HIPCHK(hipEventRecord(c.ev[i], s));
+  };
+  mark(PP_PHASE_INGEST);
   const double* f_d = stage_in(c, B_F, f, ngrid, s);
   const double* tx_d = stage_in(c, B_TX, tx, m, s);
   const double* ty_d = stage_in(c, B_TY, ty, m, s);
@@ -228,6 +234,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   ingest_grid_emit(f_d, nx, ny, k, h * h, tile, skey, sij, sw, s);
 
   // ---- targets: Morton keys and a stable radix sort ----
+  mark(PP_PHASE_SORT);
   uint32_t* tkey = ensure<uint32_t>(c, B_TKEY, m);
   int* tperm = ensure<int>(c, B_TPERM, m);
   target_keys(tx_d, ty_d, m, x0, y0, h, k, tkey, tperm, misc + M_FLAGS, s);
@@ -238,6 +245,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   const int64_t N = c.pinned[M_NSRC];
 
   // ---- tree, top down ----
+  mark(PP_PHASE_TREE);
   const int64_t cap = std::min<int64_t>(geo, 1 + 4 * (int64_t)std::max(D, 1) *
                                                      (N / (prm.leaf_max + 1) + m / (prm.leaf_max + 1) + 1)) + 1;
   TreeArrays ta{ensure<int>(c, B_LVL, cap),   ensure<int>(c, B_IX, cap),     ensure<int>(c, B_IY, cap),
@@ -265,6 +273,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
   // ---- cell lists: source leaves, target leaves, target cells, per-level M2M / L2L cells ----
+  mark(PP_PHASE_LISTS);
   int* sleaves = ensure<int>(c, B_SLEAF, ncells);
   int* tleaves = ensure<int>(c, B_TLEAF, ncells);
   int* tcells = ensure<int>(c, B_TCELL, ncells);
@@ -320,6 +329,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   p2p_chunks_emit(tv, tleaves, ntl, choff, items, s);
 
   // ---- per-leaf packing ----
+  mark(PP_PHASE_PACK);
   float4* src4 = ensure<float4>(c, B_SRC4, N);
   double* leaf_w = ensure<double>(c, B_LEAFW, ncells);
   leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
@@ -335,17 +345,25 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   if (!direct) {
     double2* mp = ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
     double2* loc = ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
-    p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
-    for (int l = depth - 1; l >= 0; --l) m2m_level(tv, m2mc + lstart[l], n_m2m[l], p, mp, s);
-    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, loc, s);
-    for (int l = 1; l <= depth; ++l) l2l_level(tv, l2lc + lstart[l], n_l2l[l], p, loc, s);
     far = ensure<double>(c, B_FAR, m);
+    mark(PP_PHASE_P2M);
+    p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
+    mark(PP_PHASE_M2M);
+    for (int l = depth - 1; l >= 0; --l) m2m_level(tv, m2mc + lstart[l], n_m2m[l], p, mp, s);
+    mark(PP_PHASE_M2L);
+    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, loc, s);
+    mark(PP_PHASE_L2L);
+    for (int l = 1; l <= depth; ++l) l2l_level(tv, l2lc + lstart[l], n_l2l[l], p, loc, s);
+    mark(PP_PHASE_L2P);
     l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+  } else {
+    for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
   }
 
   // ---- near field ----
   double* near = ensure<double>(c, B_NEAR, m);
   double* wnear = ensure<double>(c, B_WNEAR, ncells);
+  mark(PP_PHASE_P2P);
   P2PArgs pa{};
   pa.t = tv;
   pa.tleaves = tleaves;
@@ -365,9 +383,20 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   p2p(pa, items, nitems, mixed ? 0 : 1, s);
 
   // ---- finalize ----
+  mark(PP_PHASE_FINALIZE);
   finalize(m, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS, out_d, s);
+  mark(12);
   readback(c, misc, 0, 1, s);
   check_flags(c.pinned[M_FLAGS]);
+  if (c.profiling) {
+    for (int i = 0; i < 12; ++i) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c.ev[i], c.ev[i + 1]));
+      c.stats.ms_phase[i] = ms;
+    }
+  } else {
+    for (int i = 0; i < 12; ++i) c.stats.ms_phase[i] = 0.0;
+  }
   if (!out_on_device && m > 0) {
     HIPCHK(hipMemcpyAsync(p_out, out_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -455,6 +484,8 @@ void pp_destroy(pp_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   for (int i = 0; i < B_COUNT; ++i) release(*c, i);
+  for (int i = 0; i < 13; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }
@@ -467,6 +498,18 @@ pp_status pp_solve_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0,
 pp_status pp_direct_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                          const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
   return guard(c, true, nx, ny, x0, y0, h, f, m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_set_profiling(pp_ctx* c, int32_t on) {
+  if (!c) return PP_ERR_ARG;
+  if (on && !c->profiling) {
+    if (hipSetDevice(c->device) != hipSuccess) return PP_ERR_DEVICE;
+    for (int i = 0; i < 13; ++i) {
+      if (!c->ev[i] && hipEventCreate(&c->ev[i]) != hipSuccess) return PP_ERR_DEVICE;
+    }
+  }
+  c->profiling = on != 0;
+  return PP_OK;
 }
 
 pp_status pp_get_stats(const pp_ctx* c, pp_stats* out) {

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     # pp_params: int32 p; double theta; int32 leaf_max, precision, self_mode (natural alignment)
     assert ctypes.sizeof(_binding.pp_params) == 32
     assert _binding.pp_params.theta.offset == 8
-    assert ctypes.sizeof(_binding.pp_stats) == 4 * 4 + 5 * 8 + 8
+    assert ctypes.sizeof(_binding.pp_stats) == 4 * 4 + 5 * 8 + 8 + 12 * 8
 
 
 def test_status_strings_without_gpu():
