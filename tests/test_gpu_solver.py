@@ -229,7 +229,13 @@ def test_degenerate_inputs(solver):
     tx = np.array([x[3, 5], x[3, 5] + 1e-9, x[7, 2] - 3e-12, 0.5])
     ty = np.array([y[3, 5], y[3, 5], y[7, 2] + 1e-10, 0.5])
     ref = direct.direct_grid(f3, 1 / 16, tx, ty)
+    # all-pairs GPU sum: the snapped node's exact FP64 term is restored
+    P = solver.direct_grid(f3, 1 / 16, tx, ty, precision="fp64", leaf_max=8)
+    assert rel_max(P, ref) < 1e-12
+    P = solver.direct_grid(f3, 1 / 16, tx, ty, precision="mixed", leaf_max=8)
+    assert rel_max(P, ref) < 1e-6
+    # tree-code: truncation error only
     P = solver.solve_grid(f3, 1 / 16, tx, ty, precision="fp64", leaf_max=8)
-    assert rel_max(P, ref) < 1e-9
+    assert rel_max(P, ref) < 1e-7
     P = solver.solve_grid(f3, 1 / 16, tx, ty, precision="mixed", leaf_max=8)
     assert rel_max(P, ref) < 1e-5
