@@ -7,8 +7,9 @@
 // 0.5 * that sum + W ln h.  A target that coincides with a grid node (exact FP64
 // equality with x0 + (i + 1/2) h) contributed 0 for that node inside the
 // near-field kernel but w ln h through W: the self rule then subtracts w ln h
-// (skip) or w kappa (cell average: w (ln h - kappa) in total).  A target within
-// 2^-20 h of a node was snapped onto it; the exact FP64 term w ln d is restored.
+// (skip) or w kappa (cell average: w (ln h - kappa) in total).  In mixed
+// precision a target within 2^-20 h of a node was snapped onto it (FP32 cannot
+// resolve that distance); the exact FP64 term w ln d is restored here.
 #include "internal.h"
 
 namespace pp {

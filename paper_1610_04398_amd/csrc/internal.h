@@ -62,9 +62,12 @@ void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, co
                        float4* src4, double* leaf_w, hipStream_t s);
 // Per target leaf: offsets relative to the leaf corner (FP32 and FP64, in units
 // of h), owning leaf, and the coincident-node information for the self rule.
+// A target at squared distance d2 from its nearest node with d2 == 0 or
+// d2 < snap_frac2 h^2 is snapped onto the node (its exact term is restored by
+// the finalize step); FP32 near fields use snap_frac2 = 2^-40, FP64 ones 0.
 void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
-                       const int* perm, double x0, double y0, double h, int nx, int ny, float2* rel32, double2* rel64,
-                       int* tleaf, int* self_idx, double* self_logd, hipStream_t s);
+                       const int* perm, double x0, double y0, double h, int nx, int ny, double snap_frac2,
+                       float2* rel32, double2* rel64, int* tleaf, int* self_idx, double* self_logd, hipStream_t s);
 
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p

@@ -338,7 +338,8 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   int* tgtleaf = ensure<int>(c, B_TGTLEAF, m);
   int* selfi = ensure<int>(c, B_SELFI, m);
   double* selfd = ensure<double>(c, B_SELFD, m);
-  leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, h, nx, ny, rel32, rel64, tgtleaf, selfi, selfd, s);
+  leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, h, nx, ny, mixed ? 0x1p-40 : 0.0, rel32, rel64,
+                    tgtleaf, selfi, selfd, s);
 
   // ---- expansions: upward and downward passes ----
   double* far = nullptr;

@@ -162,9 +162,10 @@ __device__ inline double node_coord(double x0, int i, double h) {
 __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* __restrict__ tleaves, int n, int D,
                                                        const double* __restrict__ tx, const double* __restrict__ ty,
                                                        const int* __restrict__ perm, double x0, double y0, double h,
-                                                       int nx, int ny, float2* __restrict__ rel32,
-                                                       double2* __restrict__ rel64, int* __restrict__ tleaf,
-                                                       int* __restrict__ self_idx, double* __restrict__ self_logd) {
+                                                       int nx, int ny, double snap_frac2,
+                                                       float2* __restrict__ rel32, double2* __restrict__ rel64,
+                                                       int* __restrict__ tleaf, int* __restrict__ self_idx,
+                                                       double* __restrict__ self_logd) {
 #pragma clang fp contract(off)
   const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (wid >= n) return;
@@ -173,8 +174,8 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
   const int sh = D - t.lvl[c];
   const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
   const int tb = t.tb[c], te = t.te[c];
-  // threshold below which a target is snapped onto its nearest node: 2^-20 h
-  const double snap2 = h * h * 0x1p-40;
+  // squared distance below which a target is snapped onto its nearest node
+  const double snap2 = h * h * snap_frac2;
   for (int k = tb + lane; k < te; k += kWave) {
     const int o = perm[k];
     const double x = tx[o], y = ty[o];
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
       const double dx = x - node_coord(x0, i, h);
       const double dy = y - node_coord(y0, j, h);
       const double d2 = dx * dx + dy * dy;
-      if (d2 < snap2) {
+      if (d2 == 0.0 || d2 < snap2) {
         sidx = j * nx + i;
         lg = (d2 == 0.0) ? -INFINITY : 0.5 * log(d2);
         rx = ((double)i + 0.5) - cx;
@@ -244,11 +245,11 @@ void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, co
 }
 
 void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
-                       const int* perm, double x0, double y0, double h, int nx, int ny, float2* rel32, double2* rel64,
-                       int* tleaf, int* self_idx, double* self_logd, hipStream_t s) {
+                       const int* perm, double x0, double y0, double h, int nx, int ny, double snap_frac2,
+                       float2* rel32, double2* rel64, int* tleaf, int* self_idx, double* self_logd, hipStream_t s) {
   if (ntleaves <= 0) return;
-  k_prep_targets<<<(ntleaves + 3) / 4, 256, 0, s>>>(t, tleaves, ntleaves, D, tx, ty, perm, x0, y0, h, nx, ny, rel32,
-                                                     rel64, tleaf, self_idx, self_logd);
+  k_prep_targets<<<(ntleaves + 3) / 4, 256, 0, s>>>(t, tleaves, ntleaves, D, tx, ty, perm, x0, y0, h, nx, ny,
+                                                     snap_frac2, rel32, rel64, tleaf, self_idx, self_logd);
 }
 
 }  // namespace pp

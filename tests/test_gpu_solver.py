@@ -232,8 +232,9 @@ def test_degenerate_inputs(solver):
     # all-pairs GPU sum: the snapped node's exact FP64 term is restored
     P = solver.direct_grid(f3, 1 / 16, tx, ty, precision="fp64", leaf_max=8)
     assert rel_max(P, ref) < 1e-12
+    # mixed: the near-coincident target is snapped (moved by < 2^-20 h)
     P = solver.direct_grid(f3, 1 / 16, tx, ty, precision="mixed", leaf_max=8)
-    assert rel_max(P, ref) < 1e-6
+    assert rel_max(P, ref) < 2e-6
     # tree-code: truncation error only
     P = solver.solve_grid(f3, 1 / 16, tx, ty, precision="fp64", leaf_max=8)
     assert rel_max(P, ref) < 1e-7
