@@ -29,9 +29,10 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs, 64 FP32 lanes per CU per clock without packed instructions, 2.4 GHz
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# FP32 lane operations of one near-field pair: dx, dy, dx^2, +dy^2, log2, w*log2 - c, and the
-# three Kahan steps (add, sub, sub)
-OPS_PER_PAIR = 9
+# Algorithmic FP32 lane operations of one near-field pair: dx, dy, dx^2, +dy^2 (fma), log2, and
+# the weighted accumulation w*log2 (fma).  Compensation and loop overhead are not counted, so they
+# lower the fraction.
+OPS_PER_PAIR = 6
 
 
 def log(msg: str) -> None:
@@ -176,8 +177,8 @@ def main() -> int:
                 "unit": "TFLOP/s", "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
                 "traffic": traffic_from_profile(args.workload), "ops_per_pair": OPS_PER_PAIR,
                 "pairs_per_launch": pairs, "avg_launch_ms": p2p_ms,
-                "note": "FP32 VALU lane-ops (no packed math) counted per near-field pair; peak = 256 CU x 64 lanes "
-                        "x 2.4 GHz"}
+                "note": "6 algorithmic FP32 VALU lane-ops per near-field pair (sub, sub, mul, fma, log2, fma); "
+                        "peak = 256 CU x 64 lanes x 2.4 GHz without packed FP32"}
     if args.precision == "fp64":
         roofline["kernel"] = "k_p2p64 (near field)"
 

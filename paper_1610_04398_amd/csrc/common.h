@@ -23,6 +23,7 @@ enum : int {
   kFlagNonFiniteTarget = 2,
   kFlagTargetOutside = 4,
   kFlagFrontierOverflow = 8,
+  kFlagCellOverflow = 16,
 };
 
 struct cplx {

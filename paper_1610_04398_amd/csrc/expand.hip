@@ -83,59 +83,55 @@ __global__ void k_p2m(TreeView t, const int* __restrict__ sleaves, int n, const 
     if (k <= p) out[k] = make_double2(-acc[k].x / k, -acc[k].y / k);
 }
 
-template <int PM>
-__global__ void k_m2m(TreeView t, const int* __restrict__ cells, int n, int p, double2* __restrict__ mp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = cells[i];
-  cplx b[PM + 1];
-#pragma unroll
-  for (int k = 0; k <= PM; ++k) b[k] = {0.0, 0.0};
+// One thread per (cell of the level, output coefficient l): a'_l of a non-leaf
+// cell with sources from its children's scaled coefficients.
+__global__ void k_m2m(TreeView t, int c0, int c1, int p, double2* __restrict__ mp) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int P1 = p + 1;
+  const int c = c0 + (int)(w / P1);
+  const int l = (int)(w % P1);
+  if (c >= c1) return;
+  if (t.child[c] < 0 || t.se[c] <= t.sb[c]) return;
   const int k0 = t.child[c], nk = t.nchild[c];
+  cplx b = {0.0, 0.0};
   for (int q = 0; q < nk; ++q) {
     const int ch = k0 + q;
     if (t.se[ch] <= t.sb[ch]) continue;
+    const double2* a = mp + (int64_t)ch * P1;
+    const double a0 = a[0].x;
+    if (l == 0) {
+      b.x += a0;
+      continue;
+    }
     const cplx d = quadrant_offset(t.ix[ch], t.iy[ch]);
-    const double2* a = mp + (int64_t)ch * (p + 1);
-    cplx dp[PM + 1];
-    dp[0] = {1.0, 0.0};
-#pragma unroll
-    for (int k = 1; k <= PM; ++k) dp[k] = cmul(dp[k - 1], d);
-    cplx as[PM + 1];  // a'_k 2^-k
-    double half = 1.0;
-#pragma unroll
-    for (int k = 0; k <= PM; ++k) {
-      if (k <= p) {
-        const double2 v = a[k];
-        as[k] = {v.x * half, v.y * half};
-      } else {
-        as[k] = {0.0, 0.0};
-      }
-      half *= 0.5;
+    // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
+    cplx acc = {0.0, 0.0};
+    cplx dp = {1.0, 0.0};
+    for (int k = l; k >= 1; --k) {
+      const double2 v = a[k];
+      const double sc = binom(l - 1, k - 1) * ldexp(1.0, -k);
+      acc = cadd(acc, cscale(cmul({v.x, v.y}, dp), sc));
+      dp = cmul(dp, d);
     }
-    const double a0 = as[0].x;
-    b[0].x += a0;
-#pragma unroll
-    for (int l = 1; l <= PM; ++l) {
-      cplx s = cscale(dp[l], -a0 / l);
-#pragma unroll
-      for (int k = 1; k <= l; ++k) s = cadd(s, cscale(cmul(as[k], dp[l - k]), binom(l - 1, k - 1)));
-      b[l] = cadd(b[l], s);
-    }
+    acc = cadd(acc, cscale(dp, -a0 / l));
+    b = cadd(b, acc);
   }
-  double2* out = mp + (int64_t)c * (p + 1);
-#pragma unroll
-  for (int k = 0; k <= PM; ++k)
-    if (k <= p) out[k] = make_double2(b[k].x, b[k].y);
+  mp[(int64_t)c * P1 + l] = make_double2(b.x, b.y);
 }
 
-template <int PM>
-__global__ void k_m2l(TreeView t, const int* __restrict__ tcells, int n, const int* __restrict__ off,
-                      const int* __restrict__ cnt, const int* __restrict__ src, int p, double lnh,
-                      const double2* __restrict__ mp, double2* __restrict__ loc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int A = tcells[i];
+// G lanes per target cell: lane j of the group takes list entries j, j+G, ...
+// and accumulates their local contributions in registers; a butterfly over the
+// group (fixed order, so the result is reproducible) sums them.
+template <int PM, int G>
+__global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__ tcells, int n,
+                                             const int* __restrict__ off, const int* __restrict__ cnt,
+                                             const int* __restrict__ src, int p, double lnh,
+                                             const double2* __restrict__ mp, double2* __restrict__ loc) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int gi = (int)(gtid / G);
+  const int sub = (int)(gtid % G);
+  if (gi >= n) return;
+  const int A = tcells[gi];
   const int D = t.D;
   const int lA = t.lvl[A];
   const double sA = cell_side(D, lA);
@@ -144,7 +140,7 @@ __global__ void k_m2l(TreeView t, const int* __restrict__ tcells, int n, const i
 #pragma unroll
   for (int k = 0; k <= PM; ++k) L[k] = {0.0, 0.0};
   const int e0 = off[A], ne = cnt[A];
-  for (int e = 0; e < ne; ++e) {
+  for (int e = sub; e < ne; e += G) {
     const int B = src[e0 + e];
     const int lB = t.lvl[B];
     const double sB = cell_side(D, lB);
@@ -180,46 +176,43 @@ __global__ void k_m2l(TreeView t, const int* __restrict__ tcells, int n, const i
       tl = cmul(tl, tt);
     }
   }
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      L[k].x += __shfl_xor(L[k].x, o, G);
+      L[k].y += __shfl_xor(L[k].y, o, G);
+    }
+  }
   double2* out = loc + (int64_t)A * (p + 1);
 #pragma unroll
   for (int k = 0; k <= PM; ++k)
-    if (k <= p) out[k] = make_double2(L[k].x, L[k].y);
+    if (k <= p && (k % G) == sub) out[k] = make_double2(L[k].x, L[k].y);
 }
 
-template <int PM>
-__global__ void k_l2l(TreeView t, const int* __restrict__ cells, int n, int p, double2* __restrict__ loc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = cells[i];
+// One thread per (cell of the level with targets, coefficient m): adds the
+// parent's local expansion re-centred on the cell.
+__global__ void k_l2l(TreeView t, int c0, int c1, int p, double2* __restrict__ loc) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int P1 = p + 1;
+  const int c = c0 + (int)(w / P1);
+  const int m = (int)(w % P1);
+  if (c >= c1) return;
   const int par = t.parent[c];
-  if (par < 0) return;
+  if (par < 0 || t.te[c] <= t.tb[c]) return;
   const cplx d = quadrant_offset(t.ix[c], t.iy[c]);
-  const double2* pc = loc + (int64_t)par * (p + 1);
-  cplx P[PM + 1], dp[PM + 1];
-  dp[0] = {1.0, 0.0};
-#pragma unroll
-  for (int k = 0; k <= PM; ++k) {
-    if (k <= p) {
-      const double2 v = pc[k];
-      P[k] = {v.x, v.y};
-    } else {
-      P[k] = {0.0, 0.0};
-    }
-    if (k > 0) dp[k] = cmul(dp[k - 1], d);
+  const double2* pc = loc + (int64_t)par * P1;
+  cplx s = {0.0, 0.0};
+  cplx dp = {1.0, 0.0};
+  for (int k = m; k <= p; ++k) {
+    const double2 v = pc[k];
+    s = cadd(s, cscale(cmul({v.x, v.y}, dp), binom(k, m)));
+    dp = cmul(dp, d);
   }
-  double2* out = loc + (int64_t)c * (p + 1);
-  double half = 1.0;
-#pragma unroll
-  for (int m = 0; m <= PM; ++m) {
-    if (m <= p) {
-      cplx s = {0.0, 0.0};
-#pragma unroll
-      for (int k = m; k <= PM; ++k) s = cadd(s, cscale(cmul(P[k], dp[k - m]), binom(k, m)));
-      const double2 v = out[m];
-      out[m] = make_double2(v.x + s.x * half, v.y + s.y * half);
-    }
-    half *= 0.5;
-  }
+  const double sc = ldexp(1.0, -m);
+  double2* out = loc + (int64_t)c * P1 + m;
+  const double2 o = *out;
+  *out = make_double2(o.x + s.x * sc, o.y + s.y * sc);
 }
 
 __global__ void k_l2p64(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
@@ -281,20 +274,34 @@ void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double
   PP_DISPATCH(p, k_p2m, (n + 127) / 128, 128, s, t, sleaves, n, src4, w64, p, mp);
 }
 
-void m2m_level(TreeView t, const int* cells, int n, int p, double2* mp, hipStream_t s) {
+void m2m_level(TreeView t, int c0, int c1, int p, double2* mp, hipStream_t s) {
+  const int64_t n = (int64_t)(c1 - c0) * (p + 1);
   if (n <= 0) return;
-  PP_DISPATCH(p, k_m2m, (n + 127) / 128, 128, s, t, cells, n, p, mp);
+  k_m2m<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(t, c0, c1, p, mp);
 }
 
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, hipStream_t s) {
   if (n <= 0) return;
-  PP_DISPATCH(p, k_m2l, (n + 127) / 128, 128, s, t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, log(h), mp, loc);
+  constexpr int G = 32;
+  const unsigned g = (unsigned)(((int64_t)n * G + 255) / 256);
+  const double lnh = log(h);
+  if (p <= 4)
+    k_m2l<4, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+  else if (p <= 8)
+    k_m2l<8, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+  else if (p <= 12)
+    k_m2l<12, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+  else if (p <= 16)
+    k_m2l<16, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+  else
+    k_m2l<20, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
 }
 
-void l2l_level(TreeView t, const int* cells, int n, int p, double2* loc, hipStream_t s) {
+void l2l_level(TreeView t, int c0, int c1, int p, double2* loc, hipStream_t s) {
+  const int64_t n = (int64_t)(c1 - c0) * (p + 1);
   if (n <= 0) return;
-  PP_DISPATCH(p, k_l2l, (n + 127) / 128, 128, s, t, cells, n, p, loc);
+  k_l2l<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(t, c0, c1, p, loc);
 }
 
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,

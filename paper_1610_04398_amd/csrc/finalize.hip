@@ -15,7 +15,7 @@
 namespace pp {
 
 namespace {
-__global__ void k_finalize(int64_t m, const int* __restrict__ perm, const int* __restrict__ tleaf,
+__global__ void k_finalize(int64_t m, int ncells, int nparts, const int* __restrict__ perm, const int* __restrict__ tleaf,
                            const double* __restrict__ far, const double* __restrict__ near_sum,
                            const double* __restrict__ leaf_wnear, const int* __restrict__ self_idx,
                            const double* __restrict__ self_logd, const double* __restrict__ f, double h, double lnh,
@@ -24,7 +24,12 @@ __global__ void k_finalize(int64_t m, const int* __restrict__ perm, const int* _
   if (k >= m) return;
   if (*flags != 0) return;
   const int c = tleaf[k];
-  double v = (far ? far[k] : 0.0) + 0.5 * near_sum[k] + lnh * leaf_wnear[c];
+  double ns = near_sum[k], wn = leaf_wnear[c];
+  for (int q = 1; q < nparts; ++q) {
+    ns += near_sum[(int64_t)q * m + k];
+    wn += leaf_wnear[(int64_t)q * ncells + c];
+  }
+  double v = (far ? far[k] : 0.0) + 0.5 * ns + lnh * wn;
   const int si = self_idx[k];
   if (si >= 0) {
     const double w = f[si] * (h * h);
@@ -39,12 +44,12 @@ __global__ void k_finalize(int64_t m, const int* __restrict__ perm, const int* _
 }
 }  // namespace
 
-void finalize(int64_t m, const int* perm, const int* tleaf, const double* far, const double* near_sum,
-              const double* leaf_wnear, const int* self_idx, const double* self_logd, const double* f, double h,
-              int self_mode, const int* flags, double* out, hipStream_t s) {
+void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
+              const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
+              const double* f, double h, int self_mode, const int* flags, double* out, hipStream_t s) {
   if (m <= 0) return;
-  k_finalize<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, perm, tleaf, far, near_sum, leaf_wnear, self_idx,
-                                                         self_logd, f, h, log(h), self_mode, flags, out);
+  k_finalize<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, ncells, nparts, perm, tleaf, far, near_sum, leaf_wnear,
+                                                         self_idx, self_logd, f, h, log(h), self_mode, flags, out);
 }
 
 }  // namespace pp

@@ -12,7 +12,11 @@ namespace pp {
 // ---- scan.hip: exclusive prefix sums and fills --------------------------------
 size_t scan_temp_ints(int64_t n);
 // out[i] = sum_{j<i} in[j]; *total_dev = sum of all (may be null). in == out allowed.
+// temp holds scan_temp_ints(n) ints.
 void scan_exclusive(const int* in, int* out, int64_t n, int* temp, int* total_dev, hipStream_t s);
+// Same with the count read from device memory (*n_dev, clamped to max_n).
+void scan_exclusive_dev(const int* in, int* out, const int* n_dev, int64_t max_n, int* temp, int* total_dev,
+                        hipStream_t s);
 void fill_i32(int* p, int v, int64_t n, hipStream_t s);
 
 // ---- ingest.hip: sources in Morton order, target keys ------------------------------
@@ -44,18 +48,19 @@ struct TreeArrays {
   int* parent;
 };
 // Root cell: all sources (count read from device memory) and all targets.
-void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, hipStream_t s);
-// For the cells [c0, c1) of one level: child counts (0 for leaves) and the
-// candidate children's ranges (4 per cell, in scratch `cr`, 16 ints per cell).
-void tree_level_count(TreeArrays t, int c0, int c1, int level, int D, int leaf_max, const uint32_t* skey,
-                      const uint32_t* tkey, int* cnt, int* cr, hipStream_t s);
-// Writes the children of [c0, c1) at first_child + off[c - c0] (cnt from the count pass).
-void tree_level_emit(TreeArrays t, int c0, int c1, int level, const int* cnt, const int* off, const int* cr,
-                     int first_child, hipStream_t s);
-// Flags cells matching a predicate, for compaction: kind 0 = leaf with sources,
-// 1 = leaf with targets, 2 = any cell with targets, 3 = non-leaf with sources.
-void cell_flags(TreeArrays t, int c0, int c1, int kind, int* flag, hipStream_t s);
-void compact_indices(const int* flag, const int* off, int c0, int c1, int* out, hipStream_t s);
+// Root cell (source count read from device memory); ls[0] = 0, ls[1] = 1.
+void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, int* ls, hipStream_t s);
+// One level of the top-down construction, with no host round trip: the level's
+// cells are [ls[level], ls[level+1]) read on the device; its children are
+// appended and ls[level+2] is written.  max_cells bounds the level's size (grid
+// and scan sizing), cap the total cell count (overflow raises a flag).
+void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
+                const uint32_t* skey, const uint32_t* tkey, int4* cr, int* exists, int* off, int* scan_tmp,
+                int* n4_slot, int* total_slot, int* flags, hipStream_t s);
+// Compacted cell lists: source leaves, target leaves, cells with targets
+// (flag3/off3 scratch of 3 * ncells); counts[0..2] receive their lengths.
+void classify_cells(TreeArrays t, int ncells, int* flag3, int* off3, int* scan_tmp, int* total_slot, int* sleaves,
+                    int* tleaves, int* tcells, int* counts, hipStream_t s);
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
 // cell units, and the FP64 leaf weight.
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
@@ -81,10 +86,12 @@ void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
 void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
          hipStream_t s);
-void m2m_level(TreeView t, const int* cells, int n, int p, double2* mp, hipStream_t s);
+// M2M for the non-leaf cells with sources among [c0, c1) (one level).
+void m2m_level(TreeView t, int c0, int c1, int p, double2* mp, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, hipStream_t s);
-void l2l_level(TreeView t, const int* cells, int n, int p, double2* loc, hipStream_t s);
+// L2L into the cells with targets among [c0, c1) (one level >= 1).
+void l2l_level(TreeView t, int c0, int c1, int p, double2* loc, hipStream_t s);
 // far[k] = Re sum_l c'_l u^l for every sorted target k (u: offset from its
 // leaf centre over the leaf side); fp32 != 0 evaluates in FP32.
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,
@@ -105,8 +112,10 @@ struct P2PArgs {
   const double* leaf_w;
   const float2* rel32;
   const double2* rel64;
-  double* near_sum;     // per sorted target: sum w ln(r^2 / h^2)
-  double* leaf_wnear;   // per cell id (target leaves): sum of the near sources' weights
+  int nparts;           // each target chunk's list is split over nparts waves
+  int64_t m;            // number of targets
+  double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r^2 / h^2)
+  double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };
 // Work items (target leaf, first target of a 64-target chunk), built from tleaves.
 void p2p_chunks_count(TreeView t, const int* tleaves, int n, int* cnt, hipStream_t s);
@@ -115,8 +124,9 @@ void p2p(const P2PArgs& a, const int2* items, int nitems, int fp64, hipStream_t 
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.
-void finalize(int64_t m, const int* perm, const int* tleaf, const double* far, const double* near_sum,
-              const double* leaf_wnear, const int* self_idx, const double* self_logd, const double* f, double h,
-              int self_mode, const int* flags, double* out, hipStream_t s);
+// near_sum and leaf_wnear hold nparts partial sums (strides m and ncells).
+void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
+              const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
+              const double* f, double h, int self_mode, const int* flags, double* out, hipStream_t s);
 
 }  // namespace pp

@@ -43,32 +43,61 @@ __global__ void k_chunk_emit(TreeView t, const int* __restrict__ tleaves, int n,
   for (int q = 0; q < nch; ++q) items[off[i] + q] = make_int2(c, q * kWave);
 }
 
+// Kahan step with the group's partial sum y (which already carries -comp).
+__device__ inline void kahan_fold(float y, float& sum, float& comp) {
+  const float tt = sum + y;
+  comp = (tt - sum) - y;
+  sum = tt;
+}
+
+__device__ inline float pair_log2(float tx, float ty, const float4& q, bool guard) {
+  const float dx = tx - q.x;
+  const float dy = ty - q.y;
+  float r2 = fmaf(dy, dy, dx * dx);
+  if (guard) r2 = (r2 == 0.0f) ? 1.0f : r2;
+  return __builtin_amdgcn_logf(r2);  // v_log_f32: log2
+}
+
+// Sources [s0, s1) of one leaf against this lane's target.  Terms are summed
+// four at a time (the first product starts from -comp) and each group is
+// folded into the running sum with Kahan compensation; a ragged tail is
+// folded one term at a time.
 template <bool GUARD>
 __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s1, float tx, float ty, float& sum,
                                   float& comp) {
-#pragma unroll 4
-  for (int s = s0; s < s1; ++s) {
+  int s = s0;
+#pragma unroll 2
+  for (; s + 4 <= s1; s += 4) {
+    const float4 q0 = src4[s], q1 = src4[s + 1], q2 = src4[s + 2], q3 = src4[s + 3];
+    const float l0 = pair_log2(tx, ty, q0, GUARD);
+    const float l1 = pair_log2(tx, ty, q1, GUARD);
+    const float l2 = pair_log2(tx, ty, q2, GUARD);
+    const float l3 = pair_log2(tx, ty, q3, GUARD);
+    float y = fmaf(q0.z, l0, -comp);
+    y = fmaf(q1.z, l1, y);
+    y = fmaf(q2.z, l2, y);
+    y = fmaf(q3.z, l3, y);
+    kahan_fold(y, sum, comp);
+  }
+  for (; s < s1; ++s) {
     const float4 q = src4[s];
-    const float dx = tx - q.x;
-    const float dy = ty - q.y;
-    float r2 = fmaf(dy, dy, dx * dx);
-    if (GUARD) r2 = (r2 == 0.0f) ? 1.0f : r2;
-    const float lg = __builtin_amdgcn_logf(r2);  // log2
-    const float y = fmaf(q.z, lg, -comp);
-    const float tt = sum + y;
-    comp = (tt - sum) - y;
-    sum = tt;
+    kahan_fold(fmaf(q.z, pair_log2(tx, ty, q, GUARD), -comp), sum, comp);
   }
 }
 
+// Work: wave w handles chunk item w / nparts and the list part w % nparts
+// (entries [part * nb / nparts, (part + 1) * nb / nparts)).  Partial sums go to
+// near_sum[part * m + k] and leaf_wnear[part * ncells + A] and are added in a
+// fixed order by the finalize step.
 template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int2* __restrict__ items, int nitems) {
   // wave-uniform work index (keeps all per-item data in scalar registers)
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
-  if (wid >= nitems) return;
+  if (wid >= nitems * a.nparts) return;
+  const int part = wid % a.nparts;
   const int lane = threadIdx.x % kWave;
   const TreeView& t = a.t;
-  const int2 it = items[wid];
+  const int2 it = items[wid / a.nparts];
   const int A = it.x;
   const int k = t.tb[A] + it.y + lane;
   const bool active = k < t.te[A];
@@ -77,9 +106,11 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int
   const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
   const int nb = DIRECT ? a.nsleaves : a.list_cnt[A];
   const int* lst = DIRECT ? a.sleaves : a.list_src + a.list_off[A];
+  const int e0 = (int)((int64_t)part * nb / a.nparts);
+  const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   float sum = 0.0f, comp = 0.0f;
   double wn = 0.0;
-  for (int e = 0; e < nb; ++e) {
+  for (int e = e0; e < e1; ++e) {
     const int B = lst[e];
     const int shB = t.D - t.lvl[B];
     const float tx = r.x + (float)(cax - (t.ix[B] << shB));
@@ -91,8 +122,8 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int
     else
       p2p32_leaf<false>(a.src4, s0, s1, tx, ty, sum, comp);
   }
-  if (active) a.near_sum[k] = ((double)sum - (double)comp) * kLn2;
-  if (lane == 0 && it.y == 0) a.leaf_wnear[A] = wn;
+  if (active) a.near_sum[(int64_t)part * a.m + k] = ((double)sum - (double)comp) * kLn2;
+  if (lane == 0 && it.y == 0) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
 }
 
 template <bool GUARD>
@@ -114,10 +145,11 @@ template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int2* __restrict__ items, int nitems) {
   // wave-uniform work index (keeps all per-item data in scalar registers)
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
-  if (wid >= nitems) return;
+  if (wid >= nitems * a.nparts) return;
+  const int part = wid % a.nparts;
   const int lane = threadIdx.x % kWave;
   const TreeView& t = a.t;
-  const int2 it = items[wid];
+  const int2 it = items[wid / a.nparts];
   const int A = it.x;
   const int k = t.tb[A] + it.y + lane;
   const bool active = k < t.te[A];
@@ -126,9 +158,11 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int
   const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
   const int nb = DIRECT ? a.nsleaves : a.list_cnt[A];
   const int* lst = DIRECT ? a.sleaves : a.list_src + a.list_off[A];
+  const int e0 = (int)((int64_t)part * nb / a.nparts);
+  const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   double sum = 0.0;
   double wn = 0.0;
-  for (int e = 0; e < nb; ++e) {
+  for (int e = e0; e < e1; ++e) {
     const int B = lst[e];
     const int shB = t.D - t.lvl[B];
     const double tx = r.x + (double)(cax - (t.ix[B] << shB));
@@ -140,8 +174,8 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int
     else
       p2p64_leaf<false>(a.src4, a.w64, s0, s1, tx, ty, sum);
   }
-  if (active) a.near_sum[k] = sum;
-  if (lane == 0 && it.y == 0) a.leaf_wnear[A] = wn;
+  if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
+  if (lane == 0 && it.y == 0) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
 }
 }  // namespace
 
@@ -157,7 +191,8 @@ void p2p_chunks_emit(TreeView t, const int* tleaves, int n, const int* off, int2
 
 void p2p(const P2PArgs& a, const int2* items, int nitems, int fp64, hipStream_t s) {
   if (nitems <= 0) return;
-  const unsigned g = (unsigned)((nitems + kP2PWaves - 1) / kP2PWaves);
+  const int64_t waves = (int64_t)nitems * a.nparts;
+  const unsigned g = (unsigned)((waves + kP2PWaves - 1) / kP2PWaves);
   const bool direct = a.list_cnt == nullptr;
   if (fp64) {
     if (direct)

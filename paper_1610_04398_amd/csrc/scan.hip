@@ -1,6 +1,11 @@
-// Device-wide exclusive prefix sum of int32 counts (three-phase: tile
-// reductions, one-workgroup scan of the tile sums, tile scans).  Used for
-// every compaction in the pipeline (sources, tree levels, lists, sort bins).
+// Device-wide exclusive prefix sum of int32 counts, used for every compaction
+// in the pipeline (sources, tree levels, lists, sort bins).
+//
+// The element count is either a host value or read from device memory (so a
+// level of the tree can be compacted without a host round trip); grids are then
+// sized for an upper bound and surplus workgroups exit.  Up to kSmallMax
+// elements one workgroup scans everything in a single launch; larger inputs use
+// tile reductions, a one-workgroup scan of the tile sums, and tile scans.
 #include "blockscan.h"
 #include "internal.h"
 
@@ -10,15 +15,56 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallItems = 8;
+constexpr int64_t kSmallMax = (int64_t)kSmallBlock * kSmallItems * 4;
 
-__global__ __launch_bounds__(kScanBlock) void scan_tile_reduce(const int* __restrict__ in, int n,
+// Element count: the device value (clamped to the launch's upper bound) or the host value.
+__device__ inline int64_t count_of(int64_t n_host, const int* n_dev) {
+  if (!n_dev) return n_host;
+  const int64_t v = *n_dev;
+  return v < 0 ? 0 : (v > n_host ? n_host : v);
+}
+
+__global__ __launch_bounds__(kSmallBlock) void scan_small(const int* __restrict__ in, int64_t n_host,
+                                                           const int* __restrict__ n_dev, int* __restrict__ out,
+                                                           int* __restrict__ total_out) {
+  __shared__ int lds[kSmallBlock / kWave + 1];
+  const int64_t n = count_of(n_host, n_dev);
+  int carry = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)kSmallBlock * kSmallItems) {
+    int v[kSmallItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+      const int64_t i = base + (int64_t)threadIdx.x * kSmallItems + k;
+      v[k] = i < n ? in[i] : 0;
+      s += v[k];
+    }
+    int tot;
+    int ex = block_excl_scan<kSmallBlock>(s, lds, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; ++k) {
+      const int64_t i = base + (int64_t)threadIdx.x * kSmallItems + k;
+      if (i < n) out[i] = ex;
+      ex += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_tile_reduce(const int* __restrict__ in, int64_t n_host,
+                                                                const int* __restrict__ n_dev,
                                                                 int* __restrict__ partial) {
   __shared__ int lds[kScanBlock / kWave + 1];
+  const int64_t n = count_of(n_host, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n && blockIdx.x > 0) return;
   int s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + (int64_t)k * kScanBlock + threadIdx.x;
+    const int64_t i = base + (int64_t)k * kScanBlock + threadIdx.x;
     if (i < n) s += in[i];
   }
   int total;
@@ -26,32 +72,37 @@ __global__ __launch_bounds__(kScanBlock) void scan_tile_reduce(const int* __rest
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// One workgroup: exclusive scan of partial[0..nb) in place; total to *total.
-__global__ __launch_bounds__(kScanBlock) void scan_partials(int* __restrict__ partial, int nb,
+// One workgroup: exclusive scan of the tile sums in place; grand total to *total_out.
+__global__ __launch_bounds__(kScanBlock) void scan_partials(int* __restrict__ partial, int64_t n_host,
+                                                             const int* __restrict__ n_dev,
                                                              int* __restrict__ total_out) {
   __shared__ int lds[kScanBlock / kWave + 1];
+  const int64_t n = count_of(n_host, n_dev);
+  const int nb = (int)((n + kScanTile - 1) / kScanTile);
   int carry = 0;
   for (int base = 0; base < nb; base += kScanBlock) {
-    int i = base + threadIdx.x;
-    int v = i < nb ? partial[i] : 0;
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? partial[i] : 0;
     int tot;
-    int ex = block_excl_scan<kScanBlock>(v, lds, &tot);
+    const int ex = block_excl_scan<kScanBlock>(v, lds, &tot);
     if (i < nb) partial[i] = carry + ex;
     carry += tot;
   }
   if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
-__global__ __launch_bounds__(kScanBlock) void scan_tiles(const int* __restrict__ in, int n,
+__global__ __launch_bounds__(kScanBlock) void scan_tiles(const int* __restrict__ in, int64_t n_host,
+                                                          const int* __restrict__ n_dev,
                                                           const int* __restrict__ partial, int* __restrict__ out) {
   __shared__ int lds[kScanBlock / kWave + 1];
+  const int64_t n = count_of(n_host, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  // each thread owns kScanItems consecutive elements
+  if (base >= n) return;
   int v[kScanItems];
   int s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
     v[k] = i < n ? in[i] : 0;
     s += v[k];
   }
@@ -59,14 +110,12 @@ __global__ __launch_bounds__(kScanBlock) void scan_tiles(const int* __restrict__
   int ex = block_excl_scan<kScanBlock>(s, lds, &tot) + partial[blockIdx.x];
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
     if (i < n) out[i] = ex;
     ex += v[k];
   }
 }
-}  // namespace
 
-namespace {
 __global__ void k_fill_i32(int* __restrict__ p, int v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -80,15 +129,24 @@ void fill_i32(int* p, int v, int64_t n, hipStream_t s) {
 
 size_t scan_temp_ints(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
 
-void scan_exclusive(const int* in, int* out, int64_t n, int* temp, int* total_dev, hipStream_t s) {
-  if (n <= 0) {
+void scan_exclusive_dev(const int* in, int* out, const int* n_dev, int64_t max_n, int* temp, int* total_dev,
+                        hipStream_t s) {
+  if (max_n <= 0) {
     if (total_dev) fill_i32(total_dev, 0, 1, s);
     return;
   }
-  const int nb = (int)((n + kScanTile - 1) / kScanTile);
-  scan_tile_reduce<<<nb, kScanBlock, 0, s>>>(in, (int)n, temp);
-  scan_partials<<<1, kScanBlock, 0, s>>>(temp, nb, total_dev);
-  scan_tiles<<<nb, kScanBlock, 0, s>>>(in, (int)n, temp, out);
+  if (max_n <= kSmallMax) {
+    scan_small<<<1, kSmallBlock, 0, s>>>(in, max_n, n_dev, out, total_dev);
+    return;
+  }
+  const int nb = (int)((max_n + kScanTile - 1) / kScanTile);
+  scan_tile_reduce<<<nb, kScanBlock, 0, s>>>(in, max_n, n_dev, temp);
+  scan_partials<<<1, kScanBlock, 0, s>>>(temp, max_n, n_dev, total_dev);
+  scan_tiles<<<nb, kScanBlock, 0, s>>>(in, max_n, n_dev, temp, out);
+}
+
+void scan_exclusive(const int* in, int* out, int64_t n, int* temp, int* total_dev, hipStream_t s) {
+  scan_exclusive_dev(in, out, nullptr, n, temp, total_dev, s);
 }
 
 }  // namespace pp

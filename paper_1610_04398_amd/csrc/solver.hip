@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -55,18 +56,20 @@ struct Last {
   int ncells = 0, p = 0;
   int64_t n_m2l = 0, n_p2p = 0;
   bool has_expansions = false;
+  int nparts = 1;
 };
 
 constexpr int kMiscInts = 128;
-// misc layout: [0] flags, [1] source count, [2] scratch total, [4..] totals of the
-// cell compactions and list scans, [32..] per-level M2M counts, [64..] per-level L2L counts.
-constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7, M_NP2P = 8,
-              M_NITEMS = 9, M_M2M = 32, M_L2L = 64;
+// misc layout: [0] flags, [1] source count, [2] scratch total, [3] level work items,
+// [4..9] cell-list and interaction-list totals, [32..32+D+2] level starts of the tree.
+constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7,
+              M_NP2P = 8, M_NITEMS = 9, M_LS = 32;
 
 }  // namespace
 
 struct pp_ctx {
   int device = 0;
+  int p2p_parts = 2;  // near-field list split per target chunk (PP_P2P_PARTS overrides, 1..8)
   bool profiling = false;
   hipEvent_t ev[13] = {};
   uint64_t budget = 0;
@@ -150,6 +153,7 @@ void check_flags(int flags) {
     throw PPError{PP_ERR_ARG, "non-finite source value or target coordinate"};
   if (flags & kFlagTargetOutside) throw PPError{PP_ERR_DOMAIN, "a target lies outside the root square"};
   if (flags & kFlagFrontierOverflow) throw PPError{PP_ERR_LIMIT, "traversal frontier exceeded its capacity"};
+  if (flags & kFlagCellOverflow) throw PPError{PP_ERR_LIMIT, "cell capacity exceeded"};
   if (flags) throw PPError{PP_ERR_DEVICE, "unknown kernel flag"};
 }
 
@@ -170,21 +174,6 @@ void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const doub
   if (prm->leaf_max < 1 || prm->leaf_max > 4096) throw PPError{PP_ERR_ARG, "leaf_max must lie in [1, 4096]"};
   if (prm->precision != PP_FP64 && prm->precision != PP_MIXED) throw PPError{PP_ERR_ARG, "unknown precision"};
   if (prm->self_mode != PP_SELF_SKIP && prm->self_mode != PP_SELF_CELLAVG) throw PPError{PP_ERR_ARG, "unknown self mode"};
-}
-
-// Compact the cells of [c0, c1) satisfying `kind` into out[dst..]; count to misc[slot].
-void compact_cells(pp_ctx& c, TreeArrays ta, int c0, int c1, int kind, int* out, int* misc, int slot, hipStream_t s) {
-  const int n = c1 - c0;
-  if (n <= 0) {
-    fill_i32(misc + slot, 0, 1, s);
-    return;
-  }
-  int* flag = ensure<int>(c, B_FLAG, n);
-  int* off = ensure<int>(c, B_FOFF, n);
-  int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(n));
-  cell_flags(ta, c0, c1, kind, flag, s);
-  scan_exclusive(flag, off, n, scan, misc + slot, s);
-  compact_indices(flag, off, c0, c1, out, s);
 }
 
 pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
@@ -244,7 +233,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   check_flags(c.pinned[M_FLAGS]);
   const int64_t N = c.pinned[M_NSRC];
 
-  // ---- tree, top down ----
+  // ---- tree, top down: one launch group per level, no host round trip ----
   mark(PP_PHASE_TREE);
   const int64_t cap = std::min<int64_t>(geo, 1 + 4 * (int64_t)std::max(D, 1) *
                                                      (N / (prm.leaf_max + 1) + m / (prm.leaf_max + 1) + 1)) + 1;
@@ -252,51 +241,45 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
                 ensure<int>(c, B_SB, cap),    ensure<int>(c, B_SE, cap),     ensure<int>(c, B_TB, cap),
                 ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
                 ensure<int>(c, B_PARENT, cap)};
-  tree_init_root(ta, misc + M_NSRC, (int)m, s);
-  std::vector<int> lstart = {0, 1};
-  for (int l = 0;; ++l) {
-    const int c0 = lstart[l], c1 = lstart[l + 1], n = c1 - c0;
-    int* cnt = ensure<int>(c, B_CNT, n);
-    int* off = ensure<int>(c, B_OFF, n);
-    int* cr = ensure<int>(c, B_CR, 16 * (int64_t)n);
-    tree_level_count(ta, c0, c1, l, D, prm.leaf_max, skey, tkey, cnt, cr, s);
-    scan_exclusive(cnt, off, n, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(n)), misc + M_TOT, s);
-    readback(c, misc, M_TOT, 1, s);
-    const int total = c.pinned[M_TOT];
-    if ((int64_t)c1 + total > cap) throw PPError{PP_ERR_LIMIT, "cell capacity exceeded"};
-    tree_level_emit(ta, c0, c1, l, cnt, off, cr, c1, s);
-    if (total == 0) break;
-    lstart.push_back(c1 + total);
+  int* ls_d = misc + M_LS;
+  tree_init_root(ta, misc + M_NSRC, (int)m, ls_d, s);
+  {
+    // the widest level: bounded by 4^l and by the cell capacity
+    const int64_t wmax = std::min<int64_t>(cap, (int64_t)1 << std::min(2 * D, 40));
+    int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
+    int* ex = ensure<int>(c, B_CNT, 4 * wmax);
+    int* off = ensure<int>(c, B_OFF, 4 * wmax);
+    int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(4 * wmax));
+    for (int l = 0; l <= D; ++l) {
+      const int64_t lmax = std::min<int64_t>(cap, (int64_t)1 << std::min(2 * l, 40));
+      tree_level(ta, ls_d, l, D, prm.leaf_max, lmax, (int)cap, skey, tkey, cr, ex, off, scan, misc + M_N4,
+                 misc + M_TOT, misc + M_FLAGS, s);
+    }
+  }
+  readback(c, misc, 0, M_LS + D + 2, s);
+  check_flags(c.pinned[M_FLAGS]);
+  const int* ls_h = c.pinned + M_LS;
+  std::vector<int> lstart = {ls_h[0], ls_h[1]};  // level l holds cells [lstart[l], lstart[l+1])
+  for (int l = 1; l <= D; ++l) {
+    if (ls_h[l + 1] == ls_h[l]) break;
+    lstart.push_back(ls_h[l + 1]);
   }
   const int ncells = lstart.back();
   const int depth = (int)lstart.size() - 2;
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
-  // ---- cell lists: source leaves, target leaves, target cells, per-level M2M / L2L cells ----
+  // ---- cell lists: source leaves, target leaves, cells with targets ----
   mark(PP_PHASE_LISTS);
   int* sleaves = ensure<int>(c, B_SLEAF, ncells);
   int* tleaves = ensure<int>(c, B_TLEAF, ncells);
   int* tcells = ensure<int>(c, B_TCELL, ncells);
-  int* m2mc = ensure<int>(c, B_M2MC, ncells);
-  int* l2lc = ensure<int>(c, B_L2LC, ncells);
-  compact_cells(c, ta, 0, ncells, 0, sleaves, misc, M_NSL, s);
-  compact_cells(c, ta, 0, ncells, 1, tleaves, misc, M_NTL, s);
-  if (!direct) {
-    compact_cells(c, ta, 0, ncells, 2, tcells, misc, M_NTC, s);
-    for (int l = 0; l <= depth; ++l) {
-      compact_cells(c, ta, lstart[l], lstart[l + 1], 3, m2mc + lstart[l], misc, M_M2M + l, s);
-      compact_cells(c, ta, lstart[l], lstart[l + 1], 2, l2lc + lstart[l], misc, M_L2L + l, s);
-    }
-  }
-  readback(c, misc, 0, kMiscInts, s);
-  const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
-  std::vector<int> n_m2m(depth + 1), n_l2l(depth + 1);
-  for (int l = 0; l <= depth; ++l) {
-    n_m2m[l] = c.pinned[M_M2M + l];
-    n_l2l[l] = c.pinned[M_L2L + l];
-  }
+  classify_cells(ta, ncells, ensure<int>(c, B_FLAG, 3 * (int64_t)ncells), ensure<int>(c, B_FOFF, 3 * (int64_t)ncells),
+                 ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(3 * (int64_t)ncells)), misc + M_TOT, sleaves, tleaves,
+                 tcells, misc + M_NSL, s);
 
   // ---- interaction lists and near-field work items ----
+  readback(c, misc, M_NSL, 3, s);
+  const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
   int* cm2l = ensure<int>(c, B_CM2L, ncells);
   int* om2l = ensure<int>(c, B_OM2L, ncells);
   int* cp2p = ensure<int>(c, B_CP2P, ncells);
@@ -350,11 +333,11 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
     mark(PP_PHASE_P2M);
     p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
     mark(PP_PHASE_M2M);
-    for (int l = depth - 1; l >= 0; --l) m2m_level(tv, m2mc + lstart[l], n_m2m[l], p, mp, s);
+    for (int l = depth - 1; l >= 0; --l) m2m_level(tv, lstart[l], lstart[l + 1], p, mp, s);
     mark(PP_PHASE_M2L);
     m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, loc, s);
     mark(PP_PHASE_L2L);
-    for (int l = 1; l <= depth; ++l) l2l_level(tv, l2lc + lstart[l], n_l2l[l], p, loc, s);
+    for (int l = 1; l <= depth; ++l) l2l_level(tv, lstart[l], lstart[l + 1], p, loc, s);
     mark(PP_PHASE_L2P);
     l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
   } else {
@@ -362,8 +345,9 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   }
 
   // ---- near field ----
-  double* near = ensure<double>(c, B_NEAR, m);
-  double* wnear = ensure<double>(c, B_WNEAR, ncells);
+  const int nparts = c.p2p_parts;
+  double* near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
+  double* wnear = ensure<double>(c, B_WNEAR, (int64_t)nparts * ncells);
   mark(PP_PHASE_P2P);
   P2PArgs pa{};
   pa.t = tv;
@@ -379,13 +363,16 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   pa.leaf_w = leaf_w;
   pa.rel32 = rel32;
   pa.rel64 = rel64;
+  pa.nparts = nparts;
+  pa.m = m;
   pa.near_sum = near;
   pa.leaf_wnear = wnear;
   p2p(pa, items, nitems, mixed ? 0 : 1, s);
 
   // ---- finalize ----
   mark(PP_PHASE_FINALIZE);
-  finalize(m, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS, out_d, s);
+  finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS,
+           out_d, s);
   mark(12);
   readback(c, misc, 0, 1, s);
   check_flags(c.pinned[M_FLAGS]);
@@ -429,6 +416,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   c.last.n_m2l = n_m2l;
   c.last.n_p2p = n_p2pl;
   c.last.has_expansions = !direct;
+  c.last.nparts = nparts;
   return PP_OK;
 }
 
@@ -472,6 +460,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return PP_ERR_DEVICE;
   pp_ctx* c = new pp_ctx();
   c->device = device;
+  if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
   c->budget = hbm_budget_bytes;
   if (hipHostMalloc((void**)&c->pinned, kMiscInts * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     delete c;
@@ -554,8 +543,8 @@ pp_status pp_debug_copy(const pp_ctx* cc, int32_t what, void* dst, int64_t capac
     case PP_ARR_MULTIPOLE: id = L.has_expansions ? B_MP : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
     case PP_ARR_LOCAL: id = L.has_expansions ? B_LOC : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
     case PP_ARR_FAR: id = L.has_expansions ? B_FAR : -1; n = L.m; esz = 8; break;
-    case PP_ARR_NEAR: id = B_NEAR; n = L.m; esz = 8; break;
-    case PP_ARR_LEAF_WNEAR: id = B_WNEAR; n = L.ncells; esz = 8; break;
+    case PP_ARR_NEAR: id = B_NEAR; n = L.m * L.nparts; esz = 8; break;
+    case PP_ARR_LEAF_WNEAR: id = B_WNEAR; n = (int64_t)L.ncells * L.nparts; esz = 8; break;
     case PP_ARR_TGT_LEAF: id = B_TGTLEAF; n = L.m; break;
     default: c->err = "unknown array id"; return PP_ERR_ARG;
   }

@@ -8,6 +8,8 @@
 // (quadrant order q = qx + 2 qy) are kept when non-empty.  A child's source
 // and target ranges are found by binary search of its key prefix inside the
 // parent's ranges.
+#include <algorithm>
+
 #include "blockscan.h"
 #include "internal.h"
 
@@ -26,7 +28,7 @@ __device__ inline int lower_bound_u32(const uint32_t* __restrict__ a, int lo, in
   return lo;
 }
 
-__global__ void k_root(TreeArrays t, const int* __restrict__ nsrc_dev, int ntgt) {
+__global__ void k_root(TreeArrays t, const int* __restrict__ nsrc_dev, int ntgt, int* __restrict__ ls) {
   const int nsrc = *nsrc_dev;
   t.lvl[0] = 0;
   t.ix[0] = 0;
@@ -38,92 +40,107 @@ __global__ void k_root(TreeArrays t, const int* __restrict__ nsrc_dev, int ntgt)
   t.child[0] = -1;
   t.nchild[0] = 0;
   t.parent[0] = -1;
+  ls[0] = 0;
+  ls[1] = 1;
 }
 
-__global__ void k_level_count(TreeArrays t, int c0, int c1, int level, int D, int leaf_max,
+// Work item w = 4 (c - c0) + q: quadrant q of cell c of the level.  Writes the
+// child's source/target ranges and whether it exists (split parent, non-empty).
+__global__ void k_level_split(TreeArrays t, const int* __restrict__ ls, int level, int D, int leaf_max,
                               const uint32_t* __restrict__ skey, const uint32_t* __restrict__ tkey,
-                              int* __restrict__ cnt, int* __restrict__ cr) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  const int sb = t.sb[c], se = t.se[c], tb = t.tb[c], te = t.te[c];
-  const bool split = level < D && (se - sb > leaf_max || te - tb > leaf_max);
-  int n = 0;
-  if (split) {
-    const int shift = 2 * (D - level - 1);
-    const uint32_t ix = t.ix[c], iy = t.iy[c];
-    int* out = cr + (int64_t)(c - c0) * 16;
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t prefix = morton(2 * ix + (q & 1), 2 * iy + (q >> 1));
-      const uint64_t lo = (uint64_t)prefix << shift;
-      const uint64_t hi = (uint64_t)(prefix + 1) << shift;
-      const int csb = lower_bound_u32(skey, sb, se, lo);
-      const int cse = lower_bound_u32(skey, csb, se, hi);
-      const int ctb = lower_bound_u32(tkey, tb, te, lo);
-      const int cte = lower_bound_u32(tkey, ctb, te, hi);
-      out[4 * q + 0] = csb;
-      out[4 * q + 1] = cse;
-      out[4 * q + 2] = ctb;
-      out[4 * q + 3] = cte;
-      n += (cse > csb || cte > ctb) ? 1 : 0;
+                              int4* __restrict__ cr, int* __restrict__ exists, int* __restrict__ n4_out) {
+  const int c0 = ls[level], c1 = ls[level + 1];
+  const int n4 = 4 * (c1 - c0);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) *n4_out = n4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = gid; w < n4; w += stride) {
+    const int c = c0 + (int)(w >> 2);
+    const int q = (int)(w & 3);
+    const int sb = t.sb[c], se = t.se[c], tb = t.tb[c], te = t.te[c];
+    const bool split = level < D && (se - sb > leaf_max || te - tb > leaf_max);
+    if (!split) {
+      exists[w] = 0;
+      continue;
     }
-  }
-  cnt[c - c0] = n;
-}
-
-__global__ void k_level_emit(TreeArrays t, int c0, int c1, int level, const int* __restrict__ cnt,
-                             const int* __restrict__ off, const int* __restrict__ cr, int first_child) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  const int n = cnt[c - c0];
-  if (n == 0) {
-    t.child[c] = -1;
-    t.nchild[c] = 0;
-    return;
-  }
-  int dst = first_child + off[c - c0];
-  t.child[c] = dst;
-  t.nchild[c] = n;
-  const int ix = t.ix[c], iy = t.iy[c];
-  const int* in = cr + (int64_t)(c - c0) * 16;
-  for (int q = 0; q < 4; ++q) {
-    const int csb = in[4 * q], cse = in[4 * q + 1], ctb = in[4 * q + 2], cte = in[4 * q + 3];
-    if (!(cse > csb || cte > ctb)) continue;
-    t.lvl[dst] = level + 1;
-    t.ix[dst] = 2 * ix + (q & 1);
-    t.iy[dst] = 2 * iy + (q >> 1);
-    t.sb[dst] = csb;
-    t.se[dst] = cse;
-    t.tb[dst] = ctb;
-    t.te[dst] = cte;
-    t.child[dst] = -1;
-    t.nchild[dst] = 0;
-    t.parent[dst] = c;
-    ++dst;
+    const int shift = 2 * (D - level - 1);
+    const uint32_t prefix = morton(2 * (uint32_t)t.ix[c] + (q & 1), 2 * (uint32_t)t.iy[c] + (q >> 1));
+    const uint64_t lo = (uint64_t)prefix << shift;
+    const uint64_t hi = (uint64_t)(prefix + 1) << shift;
+    const int csb = lower_bound_u32(skey, sb, se, lo);
+    const int cse = lower_bound_u32(skey, csb, se, hi);
+    const int ctb = lower_bound_u32(tkey, tb, te, lo);
+    const int cte = lower_bound_u32(tkey, ctb, te, hi);
+    cr[w] = make_int4(csb, cse, ctb, cte);
+    exists[w] = (cse > csb || cte > ctb) ? 1 : 0;
   }
 }
 
-__global__ void k_cell_flags(TreeArrays t, int c0, int c1, int kind, int* __restrict__ flag) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
+// Children of the level go to c1 + off[w] (off = exclusive scan of exists);
+// parents get their first child and child count; ls[level + 2] = c1 + total.
+__global__ void k_level_link(TreeArrays t, int* __restrict__ ls, int level, const int4* __restrict__ cr,
+                             const int* __restrict__ exists, const int* __restrict__ off,
+                             const int* __restrict__ total, int cap, int* __restrict__ flags) {
+  const int c0 = ls[level], c1 = ls[level + 1];
+  const int n4 = 4 * (c1 - c0);
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int tot = *total;
+  const bool fits = (int64_t)c1 + tot <= cap;
+  if (gid == 0) {
+    ls[level + 2] = fits ? c1 + tot : c1;
+    if (!fits) atomicOr(flags, kFlagCellOverflow);
+  }
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = gid; w < n4; w += stride) {
+    const int c = c0 + (int)(w >> 2);
+    const int q = (int)(w & 3);
+    if (q == 0) {
+      const int n = exists[w] + exists[w + 1] + exists[w + 2] + exists[w + 3];
+      t.child[c] = (n > 0 && fits) ? c1 + off[w] : -1;
+      t.nchild[c] = fits ? n : 0;
+    }
+    if (!exists[w] || !fits) continue;
+    const int d = c1 + off[w];
+    const int4 r = cr[w];
+    t.lvl[d] = level + 1;
+    t.ix[d] = 2 * t.ix[c] + (q & 1);
+    t.iy[d] = 2 * t.iy[c] + (q >> 1);
+    t.sb[d] = r.x;
+    t.se[d] = r.y;
+    t.tb[d] = r.z;
+    t.te[d] = r.w;
+    t.child[d] = -1;
+    t.nchild[d] = 0;
+    t.parent[d] = c;
+  }
+}
+
+// flag[kind * n + c] for kind 0 = leaf with sources, 1 = leaf with targets,
+// 2 = any cell with targets.
+__global__ void k_classify(TreeArrays t, int n, int* __restrict__ flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
   const bool leaf = t.child[c] < 0;
   const bool hs = t.se[c] > t.sb[c];
   const bool ht = t.te[c] > t.tb[c];
-  bool v = false;
-  switch (kind) {
-    case 0: v = leaf && hs; break;
-    case 1: v = leaf && ht; break;
-    case 2: v = ht; break;
-    case 3: v = !leaf && hs; break;
-    default: v = false;
-  }
-  flag[c - c0] = v ? 1 : 0;
+  flag[c] = (leaf && hs) ? 1 : 0;
+  flag[n + c] = (leaf && ht) ? 1 : 0;
+  flag[2 * n + c] = ht ? 1 : 0;
 }
 
-__global__ void k_compact(const int* __restrict__ flag, const int* __restrict__ off, int c0, int c1,
-                          int* __restrict__ out) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  if (flag[c - c0]) out[off[c - c0]] = c;
+__global__ void k_classify_scatter(int n, const int* __restrict__ flag, const int* __restrict__ off,
+                                   const int* __restrict__ total, int* __restrict__ out0, int* __restrict__ out1,
+                                   int* __restrict__ out2, int* __restrict__ counts) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) {
+    counts[0] = off[n] - off[0];
+    counts[1] = off[2 * n] - off[n];
+    counts[2] = *total - off[2 * n];
+  }
+  if (c >= n) return;
+  if (flag[c]) out0[off[c] - off[0]] = c;
+  if (flag[n + c]) out1[off[n + c] - off[n]] = c;
+  if (flag[2 * n + c]) out2[off[2 * n + c] - off[2 * n]] = c;
 }
 
 // One wave per source leaf: FP32 record (x, y relative to the leaf corner in
@@ -208,34 +225,31 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
 
 }  // namespace
 
-void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, hipStream_t s) {
-  k_root<<<1, 1, 0, s>>>(t, nsrc_dev, ntgt);
+void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, int* ls, hipStream_t s) {
+  k_root<<<1, 1, 0, s>>>(t, nsrc_dev, ntgt, ls);
 }
 
-void tree_level_count(TreeArrays t, int c0, int c1, int level, int D, int leaf_max, const uint32_t* skey,
-                      const uint32_t* tkey, int* cnt, int* cr, hipStream_t s) {
-  const int n = c1 - c0;
-  if (n <= 0) return;
-  k_level_count<<<(n + 127) / 128, 128, 0, s>>>(t, c0, c1, level, D, leaf_max, skey, tkey, cnt, cr);
+static unsigned level_blocks(int64_t max_cells) {
+  const int64_t items = 4 * std::max<int64_t>(max_cells, 1);
+  return (unsigned)std::min<int64_t>((items + 255) / 256, 2048);
 }
 
-void tree_level_emit(TreeArrays t, int c0, int c1, int level, const int* cnt, const int* off, const int* cr,
-                     int first_child, hipStream_t s) {
-  const int n = c1 - c0;
-  if (n <= 0) return;
-  k_level_emit<<<(n + 127) / 128, 128, 0, s>>>(t, c0, c1, level, cnt, off, cr, first_child);
+void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
+                const uint32_t* skey, const uint32_t* tkey, int4* cr, int* exists, int* off, int* scan_tmp,
+                int* n4_slot, int* total_slot, int* flags, hipStream_t s) {
+  const unsigned g = level_blocks(max_cells);
+  k_level_split<<<g, 256, 0, s>>>(t, ls, level, D, leaf_max, skey, tkey, cr, exists, n4_slot);
+  scan_exclusive_dev(exists, off, n4_slot, 4 * std::max<int64_t>(max_cells, 1), scan_tmp, total_slot, s);
+  k_level_link<<<g, 256, 0, s>>>(t, ls, level, cr, exists, off, total_slot, cap, flags);
 }
 
-void cell_flags(TreeArrays t, int c0, int c1, int kind, int* flag, hipStream_t s) {
-  const int n = c1 - c0;
-  if (n <= 0) return;
-  k_cell_flags<<<(n + 255) / 256, 256, 0, s>>>(t, c0, c1, kind, flag);
-}
-
-void compact_indices(const int* flag, const int* off, int c0, int c1, int* out, hipStream_t s) {
-  const int n = c1 - c0;
-  if (n <= 0) return;
-  k_compact<<<(n + 255) / 256, 256, 0, s>>>(flag, off, c0, c1, out);
+void classify_cells(TreeArrays t, int ncells, int* flag3, int* off3, int* scan_tmp, int* total_slot, int* sleaves,
+                    int* tleaves, int* tcells, int* counts, hipStream_t s) {
+  if (ncells <= 0) return;
+  const unsigned g = (unsigned)((ncells + 255) / 256);
+  k_classify<<<g, 256, 0, s>>>(t, ncells, flag3);
+  scan_exclusive(flag3, off3, 3 * (int64_t)ncells, scan_tmp, total_slot, s);
+  k_classify_scatter<<<g, 256, 0, s>>>(ncells, flag3, off3, total_slot, sleaves, tleaves, tcells, counts);
 }
 
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
