@@ -103,10 +103,10 @@ enum {
   PP_PHASE_TREE = 2,     /* quadtree levels */
   PP_PHASE_LISTS = 3,    /* cell lists, interaction lists, near-field work items */
   PP_PHASE_PACK = 4,     /* per-leaf source records and target offsets */
-  PP_PHASE_P2M = 5,
-  PP_PHASE_M2M = 6,
+  PP_PHASE_P2M = 5,      /* P2M and the bottom-up M2M recursion (one fused launch) */
+  PP_PHASE_M2M = 6,      /* (empty: M2M runs inside the P2M phase) */
   PP_PHASE_M2L = 7,
-  PP_PHASE_L2L = 8,
+  PP_PHASE_L2L = 8,      /* final locals: own M2L plus exact shifts of every ancestor's */
   PP_PHASE_L2P = 9,
   PP_PHASE_P2P = 10,
   PP_PHASE_FINALIZE = 11

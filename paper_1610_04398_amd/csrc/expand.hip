@@ -22,6 +22,7 @@
 //   M2M (d as above):
 //     a'_l(parent) += -a_0 d^l / l + sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k(child)
 //   L2P: far(z) = Re sum_l L'_l u^l,  u = (z - z_c) / s.
+#include "blockscan.h"
 #include "internal.h"
 
 namespace pp {
@@ -50,73 +51,102 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
   return {(ix & 1) ? 0.25 : -0.25, (iy & 1) ? 0.25 : -0.25};
 }
 
+// Upward pass in one launch.  One wave per source leaf computes its P2M
+// (lanes stride over the leaf's sources; a fixed-order butterfly sums them).
+// The M2M recursion of eq. expandedShift then runs bottom-up without level
+// barriers: a cell's expansion is final once all of its children with sources
+// are; each child announces completion on a per-cell device-scope counter, and
+// the wave that completes a parent computes the parent's expansion from all of
+// its children (lanes = child x coefficient, children summed in a fixed order)
+// and continues with the grandparent.  No wave ever waits on another.
 template <int PM>
-__global__ void k_p2m(TreeView t, const int* __restrict__ sleaves, int n, const float4* __restrict__ src4,
-                      const double* __restrict__ w64, int p, double2* __restrict__ mp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = sleaves[i];
-  const int l = t.lvl[c];
-  const double side = cell_side(t.D, l);
-  const double inv = 1.0 / side;
-  cplx acc[PM + 1];
-#pragma unroll
-  for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
-  double a0 = 0.0;
-  const int sb = t.sb[c], se = t.se[c];
-  for (int s = sb; s < se; ++s) {
-    const float4 q = src4[s];
-    const double w = w64[s];
-    const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
-    a0 += w;
-    cplx zk = {w * z.x, w * z.y};
-#pragma unroll
-    for (int k = 1; k <= PM; ++k) {
-      acc[k] = cadd(acc[k], zk);
-      zk = cmul(zk, z);
-    }
-  }
-  double2* out = mp + (int64_t)c * (p + 1);
-  out[0] = make_double2(a0, 0.0);
-#pragma unroll
-  for (int k = 1; k <= PM; ++k)
-    if (k <= p) out[k] = make_double2(-acc[k].x / k, -acc[k].y / k);
-}
-
-// One thread per (cell of the level, output coefficient l): a'_l of a non-leaf
-// cell with sources from its children's scaled coefficients.
-__global__ void k_m2m(TreeView t, int c0, int c1, int p, double2* __restrict__ mp) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_upward(TreeView t, const int* __restrict__ sleaves, int n,
+                                                const float4* __restrict__ src4, const double* __restrict__ w64,
+                                                int p, double2* __restrict__ mp, int* __restrict__ counters) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / kWave);
+  if (wid >= n) return;
+  const int lane = threadIdx.x % kWave;
+  int c = sleaves[wid];
   const int P1 = p + 1;
-  const int c = c0 + (int)(w / P1);
-  const int l = (int)(w % P1);
-  if (c >= c1) return;
-  if (t.child[c] < 0 || t.se[c] <= t.sb[c]) return;
-  const int k0 = t.child[c], nk = t.nchild[c];
-  cplx b = {0.0, 0.0};
-  for (int q = 0; q < nk; ++q) {
-    const int ch = k0 + q;
-    if (t.se[ch] <= t.sb[ch]) continue;
-    const double2* a = mp + (int64_t)ch * P1;
-    const double a0 = a[0].x;
-    if (l == 0) {
-      b.x += a0;
-      continue;
+  {
+    const double side = cell_side(t.D, t.lvl[c]);
+    const double inv = 1.0 / side;
+    cplx acc[PM + 1];
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
+    const int sb = t.sb[c], se = t.se[c];
+    for (int s = sb + lane; s < se; s += kWave) {
+      const float4 q = src4[s];
+      const double w = w64[s];
+      const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
+      acc[0].x += w;
+      cplx zk = {w * z.x, w * z.y};
+#pragma unroll
+      for (int k = 1; k <= PM; ++k) {
+        acc[k] = cadd(acc[k], zk);
+        zk = cmul(zk, z);
+      }
     }
-    const cplx d = quadrant_offset(t.ix[ch], t.iy[ch]);
-    // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
-    cplx acc = {0.0, 0.0};
-    cplx dp = {1.0, 0.0};
-    for (int k = l; k >= 1; --k) {
-      const double2 v = a[k];
-      const double sc = binom(l - 1, k - 1) * ldexp(1.0, -k);
-      acc = cadd(acc, cscale(cmul({v.x, v.y}, dp), sc));
-      dp = cmul(dp, d);
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) {
+#pragma unroll
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        acc[k].x += __shfl_xor(acc[k].x, o, kWave);
+        acc[k].y += __shfl_xor(acc[k].y, o, kWave);
+      }
     }
-    acc = cadd(acc, cscale(dp, -a0 / l));
-    b = cadd(b, acc);
+    double2* out = mp + (int64_t)c * P1;
+#pragma unroll
+    for (int k = 0; k <= PM; ++k)
+      if (k <= p && lane == k) out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
   }
-  mp[(int64_t)c * P1 + l] = make_double2(b.x, b.y);
+  // bottom-up M2M
+  const int q = lane >> 4;     // child slot
+  const int lsub = lane & 15;  // coefficient within a chunk of 16
+  while (true) {
+    const int par = t.parent[c];
+    if (par < 0) break;
+    const int k0 = t.child[par], nk = t.nchild[par];
+    int need = 0;
+    for (int j = 0; j < nk; ++j) need += (t.se[k0 + j] > t.sb[k0 + j]) ? 1 : 0;
+    __threadfence();  // this cell's expansion is visible device-wide before it is announced
+    int old = 0;
+    if (lane == 0) old = atomicAdd(&counters[par], 1);
+    old = __shfl(old, 0, kWave);
+    if (old + 1 < need) break;  // another child finishes later and carries on
+    __threadfence();            // see the other children's expansions
+    c = par;
+    for (int lb = 0; lb <= p; lb += 16) {
+      const int l = lb + lsub;
+      cplx b = {0.0, 0.0};
+      if (q < nk && l <= p) {
+        const int ch = k0 + q;
+        if (t.se[ch] > t.sb[ch]) {
+          const double2* a = mp + (int64_t)ch * P1;
+          const double a0 = a[0].x;
+          if (l == 0) {
+            b.x = a0;
+          } else {
+            // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
+            const cplx d = quadrant_offset(t.ix[ch], t.iy[ch]);
+            cplx dp = {1.0, 0.0};
+            for (int k = l; k >= 1; --k) {
+              const double2 v = a[k];
+              b = cadd(b, cscale(cmul({v.x, v.y}, dp), binom(l - 1, k - 1) * ldexp(1.0, -k)));
+              dp = cmul(dp, d);
+            }
+            b = cadd(b, cscale(dp, -a0 / l));
+          }
+        }
+      }
+      // children 0+1 and 2+3, then the two pairs
+      b.x += __shfl_xor(b.x, 16, kWave);
+      b.y += __shfl_xor(b.y, 16, kWave);
+      b.x += __shfl_xor(b.x, 32, kWave);
+      b.y += __shfl_xor(b.y, 32, kWave);
+      if (q == 0 && l <= p) mp[(int64_t)c * P1 + l] = make_double2(b.x, b.y);
+    }
+  }
 }
 
 // G lanes per target cell: lane j of the group takes list entries j, j+G, ...
@@ -190,29 +220,41 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
     if (k <= p && (k % G) == sub) out[k] = make_double2(L[k].x, L[k].y);
 }
 
-// One thread per (cell of the level with targets, coefficient m): adds the
-// parent's local expansion re-centred on the cell.
-__global__ void k_l2l(TreeView t, int c0, int c1, int p, double2* __restrict__ loc) {
+// Downward pass in one launch.  L2L is exact for a degree-p polynomial, so the
+// recursion "local(child) = own M2L + L2L(local(parent))" equals the sum, over
+// the cell and each of its ancestors X, of X's own M2L local shifted from X's
+// centre to the cell:  L'_m = sum_X 2^{-m (l_c - l_X)} sum_{k>=m} C(k, m) d_X^{k-m} L'_k(X),
+// d_X = (z_c - z_X) / s_X.  One thread per (cell with targets, coefficient m).
+__global__ void k_downward(TreeView t, const int* __restrict__ tcells, int n, int p,
+                           const double2* __restrict__ own, double2* __restrict__ loc) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int P1 = p + 1;
-  const int c = c0 + (int)(w / P1);
+  const int i = (int)(w / P1);
   const int m = (int)(w % P1);
-  if (c >= c1) return;
-  const int par = t.parent[c];
-  if (par < 0 || t.te[c] <= t.tb[c]) return;
-  const cplx d = quadrant_offset(t.ix[c], t.iy[c]);
-  const double2* pc = loc + (int64_t)par * P1;
-  cplx s = {0.0, 0.0};
-  cplx dp = {1.0, 0.0};
-  for (int k = m; k <= p; ++k) {
-    const double2 v = pc[k];
-    s = cadd(s, cscale(cmul({v.x, v.y}, dp), binom(k, m)));
-    dp = cmul(dp, d);
+  if (i >= n) return;
+  const int c = tcells[i];
+  const int D = t.D;
+  const int lc = t.lvl[c];
+  const double sc = cell_side(D, lc);
+  const double cx = (t.ix[c] + 0.5) * sc, cy = (t.iy[c] + 0.5) * sc;
+  cplx acc = {own[(int64_t)c * P1 + m].x, own[(int64_t)c * P1 + m].y};
+  int X = t.parent[c];
+  while (X >= 0) {
+    const int lX = t.lvl[X];
+    const double sX = cell_side(D, lX);
+    const cplx d = {(cx - (t.ix[X] + 0.5) * sX) / sX, (cy - (t.iy[X] + 0.5) * sX) / sX};
+    const double2* L = own + (int64_t)X * P1;
+    cplx s = {0.0, 0.0};
+    cplx dp = {1.0, 0.0};
+    for (int k = m; k <= p; ++k) {
+      const double2 v = L[k];
+      s = cadd(s, cscale(cmul({v.x, v.y}, dp), binom(k, m)));
+      dp = cmul(dp, d);
+    }
+    acc = cadd(acc, cscale(s, ldexp(1.0, -m * (lc - lX))));
+    X = t.parent[X];
   }
-  const double sc = ldexp(1.0, -m);
-  double2* out = loc + (int64_t)c * P1 + m;
-  const double2 o = *out;
-  *out = make_double2(o.x + s.x * sc, o.y + s.y * sc);
+  loc[(int64_t)c * P1 + m] = make_double2(acc.x, acc.y);
 }
 
 __global__ void k_l2p64(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
@@ -268,16 +310,11 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
 
 }  // namespace
 
-void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
-         hipStream_t s) {
+void upward(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
+            int* counters, hipStream_t s) {
   if (n <= 0) return;
-  PP_DISPATCH(p, k_p2m, (n + 127) / 128, 128, s, t, sleaves, n, src4, w64, p, mp);
-}
-
-void m2m_level(TreeView t, int c0, int c1, int p, double2* mp, hipStream_t s) {
-  const int64_t n = (int64_t)(c1 - c0) * (p + 1);
-  if (n <= 0) return;
-  k_m2m<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(t, c0, c1, p, mp);
+  fill_i32(counters, 0, t.ncells, s);
+  PP_DISPATCH(p, k_upward, (n + 3) / 4, 256, s, t, sleaves, n, src4, w64, p, mp, counters);
 }
 
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
@@ -298,10 +335,10 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
     k_m2l<20, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
 }
 
-void l2l_level(TreeView t, int c0, int c1, int p, double2* loc, hipStream_t s) {
-  const int64_t n = (int64_t)(c1 - c0) * (p + 1);
-  if (n <= 0) return;
-  k_l2l<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(t, c0, c1, p, loc);
+void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s) {
+  const int64_t w = (int64_t)n * (p + 1);
+  if (w <= 0) return;
+  k_downward<<<(unsigned)((w + 255) / 256), 256, 0, s>>>(t, tcells, n, p, own, loc);
 }
 
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,

@@ -55,7 +55,7 @@ void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, int* ls, hipStr
 // appended and ls[level+2] is written.  max_cells bounds the level's size (grid
 // and scan sizing), cap the total cell count (overflow raises a flag).
 void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
-                const uint32_t* skey, const uint32_t* tkey, int4* cr, int* exists, int* off, int* scan_tmp,
+                const uint32_t* skey, const uint32_t* tkey, int* sp, int4* cr, int* exists, int* off, int* scan_tmp,
                 int* n4_slot, int* total_slot, int* flags, hipStream_t s);
 // Compacted cell lists: source leaves, target leaves, cells with targets
 // (flag3/off3 scratch of 3 * ncells); counts[0..2] receive their lengths.
@@ -77,21 +77,25 @@ void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, co
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p
 // (indexed by cell id), pass 1 writes the lists at off_m2l / off_p2p (by cell id).
-void lists_pass(TreeView t, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l, int* cnt_p2p,
-                const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags, hipStream_t s);
+// Packed per-cell records used by the traversal (ncells int4).
+void cell_records(TreeView t, int4* rec, hipStream_t s);
+void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
+                int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags,
+                hipStream_t s);
 // Total (target, source) pairs of the P2P lists (statistics).
 void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
                     unsigned long long* out, hipStream_t s);
 
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
-void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
-         hipStream_t s);
-// M2M for the non-leaf cells with sources among [c0, c1) (one level).
-void m2m_level(TreeView t, int c0, int c1, int p, double2* mp, hipStream_t s);
+// P2M of every source leaf and the bottom-up M2M to the root, one launch
+// (counters: ncells ints of scratch).
+void upward(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
+            int* counters, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, hipStream_t s);
-// L2L into the cells with targets among [c0, c1) (one level >= 1).
-void l2l_level(TreeView t, int c0, int c1, int p, double2* loc, hipStream_t s);
+// Final local expansion of every cell with targets from its own M2L local
+// (`own`) and its ancestors' (exact L2L shifts), one launch.
+void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s);
 // far[k] = Re sum_l c'_l u^l for every sorted target k (u: offset from its
 // leaf centre over the leaf side); fp32 != 0 evaluates in FP32.
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,

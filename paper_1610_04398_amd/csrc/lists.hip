@@ -23,8 +23,27 @@ namespace {
 constexpr int kListWaves = 4;
 constexpr int kFrontierCap = 2048;
 
-__global__ __launch_bounds__(kListWaves * kWave) void k_lists(TreeView t, const int* __restrict__ tcells, int ntcells,
-                                                               int num, int den, int emit, int* __restrict__ cnt_m2l,
+// Packed per-cell record for the traversal: {ix, iy, first child, meta} with
+// meta = level | nchild << 5 | (children-with-sources mask) << 8 | has_src << 12.
+__device__ inline int rec_level(int4 r) { return r.w & 31; }
+__device__ inline int rec_nchild(int4 r) { return (r.w >> 5) & 7; }
+__device__ inline int rec_kidmask(int4 r) { return (r.w >> 8) & 15; }
+__device__ inline bool rec_has_src(int4 r) { return (r.w >> 12) & 1; }
+
+__global__ void k_records(TreeView t, int n, int4* __restrict__ rec) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int k0 = t.child[c], nk = t.nchild[c];
+  int mask = 0;
+  for (int q = 0; q < nk; ++q) mask |= (t.se[k0 + q] > t.sb[k0 + q]) ? (1 << q) : 0;
+  const int meta = t.lvl[c] | (nk << 5) | (mask << 8) | ((t.se[c] > t.sb[c]) ? (1 << 12) : 0);
+  rec[c] = make_int4(t.ix[c], t.iy[c], k0, meta);
+}
+
+__global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4* __restrict__ rec,
+                                                               const int* __restrict__ parent,
+                                                               const int* __restrict__ tcells, int ntcells, int num,
+                                                               int den, int emit, int* __restrict__ cnt_m2l,
                                                                int* __restrict__ cnt_p2p,
                                                                const int* __restrict__ off_m2l,
                                                                const int* __restrict__ off_p2p,
@@ -37,22 +56,21 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(TreeView t, const 
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kListWaves + w);
   if (wid >= ntcells) return;
   const int A = tcells[wid];
-  const int D = t.D;
-  const int lA = t.lvl[A];
+  const int4 rA = rec[A];
+  const int lA = rec_level(rA);
   if (lane == 0) {
     int c = A;
     for (int l = lA; l >= 0; --l) {
       path[w][l] = c;
-      c = t.parent[c];
+      c = parent[c];
     }
   }
-  __syncwarp();
-  const bool leafA = t.child[A] < 0;
+  const bool leafA = rA.z < 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
   int* cur = front[w][0];
   int* nxt = front[w][1];
   int ncur = 0;
-  if (t.se[0] > t.sb[0]) {
+  if (rec_has_src(rec[0])) {
     if (lane == 0) cur[0] = 0;
     ncur = 1;
   }
@@ -65,20 +83,22 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(TreeView t, const 
   while (ncur > 0) {
     const int X = path[w][xl];
     const bool atA = (X == A);
-    const bool leafX = t.child[X] < 0;
-    const int lX = t.lvl[X], ixX = t.ix[X], iyX = t.iy[X];
+    const int4 rX = (X == A) ? rA : rec[X];
+    const bool leafX = rX.z < 0;
+    const int lX = rec_level(rX);
     int nnext = 0;
     for (int base = 0; base < ncur; base += kWave) {
       const int i = base + lane;
       const bool valid = i < ncur;
       const int B = valid ? cur[i] : 0;
       bool acc = false, leafB = false;
-      int nkids = 0, kid0 = 0;
+      int kid0 = 0, kmask = 0;
       if (valid) {
-        acc = mac_accept(D, lX, ixX, iyX, t.lvl[B], t.ix[B], t.iy[B], num, den);
-        kid0 = t.child[B];
+        const int4 rB = rec[B];
+        acc = mac_accept(D, lX, rX.x, rX.y, rec_level(rB), rB.x, rB.y, num, den);
+        kid0 = rB.z;
         leafB = kid0 < 0;
-        if (!leafB) nkids = t.nchild[B];
+        kmask = rec_kidmask(rB);
       }
       const bool em2l = valid && acc && atA;
       const bool ep2p = valid && !acc && leafX && leafB && atA;
@@ -92,12 +112,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(TreeView t, const 
       }
       nm += __popcll(bm);
       np += __popcll(bp);
-      // children of B that hold sources
-      int npush = 0;
-      if (push_self) npush = 1;
-      if (push_kids) {
-        for (int q = 0; q < nkids; ++q) npush += (t.se[kid0 + q] > t.sb[kid0 + q]) ? 1 : 0;
-      }
+      const int npush = push_self ? 1 : (push_kids ? __popc(kmask) : 0);
       const int incl = wave_incl_scan(npush);
       const int total = __shfl(incl, kWave - 1, kWave);
       int pos = nnext + incl - npush;
@@ -106,10 +121,8 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(TreeView t, const 
       } else {
         if (push_self) nxt[pos] = B;
         if (push_kids) {
-          for (int q = 0; q < nkids; ++q) {
-            const int k = kid0 + q;
-            if (t.se[k] > t.sb[k]) nxt[pos++] = k;
-          }
+          for (int q = 0; q < 4; ++q)
+            if ((kmask >> q) & 1) nxt[pos++] = kid0 + q;
         }
         nnext += total;
       }
@@ -155,11 +168,18 @@ void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const
   k_pair_count<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, off, cnt, src, out);
 }
 
-void lists_pass(TreeView t, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l, int* cnt_p2p,
-                const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags, hipStream_t s) {
+void cell_records(TreeView t, int4* rec, hipStream_t s) {
+  if (t.ncells <= 0) return;
+  k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(t, t.ncells, rec);
+}
+
+void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
+                int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags,
+                hipStream_t s) {
   if (ntcells <= 0) return;
   k_lists<<<(ntcells + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
-      t, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src, flags);
+      t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
+      flags);
 }
 
 }  // namespace pp

@@ -17,7 +17,7 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kSmallBlock = 1024;
 constexpr int kSmallItems = 8;
-constexpr int64_t kSmallMax = (int64_t)kSmallBlock * kSmallItems * 4;
+constexpr int64_t kSmallMax = (int64_t)kSmallBlock * kSmallItems;
 
 // Element count: the device value (clamped to the launch's upper bound) or the host value.
 __device__ inline int64_t count_of(int64_t n_host, const int* n_dev) {

@@ -40,7 +40,7 @@ enum BufId {
   B_F, B_TX, B_TY, B_OUT, B_MISC, B_PAIRS, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
-  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR,
+  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_COUNTERS, B_SPLIT, B_REC,
   B_COUNT
 };
 
@@ -247,12 +247,13 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
     // the widest level: bounded by 4^l and by the cell capacity
     const int64_t wmax = std::min<int64_t>(cap, (int64_t)1 << std::min(2 * D, 40));
     int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
+    int* sp = ensure<int>(c, B_SPLIT, 6 * wmax);
     int* ex = ensure<int>(c, B_CNT, 4 * wmax);
     int* off = ensure<int>(c, B_OFF, 4 * wmax);
     int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(4 * wmax));
     for (int l = 0; l <= D; ++l) {
       const int64_t lmax = std::min<int64_t>(cap, (int64_t)1 << std::min(2 * l, 40));
-      tree_level(ta, ls_d, l, D, prm.leaf_max, lmax, (int)cap, skey, tkey, cr, ex, off, scan, misc + M_N4,
+      tree_level(ta, ls_d, l, D, prm.leaf_max, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4,
                  misc + M_TOT, misc + M_FLAGS, s);
     }
   }
@@ -284,12 +285,14 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   int* om2l = ensure<int>(c, B_OM2L, ncells);
   int* cp2p = ensure<int>(c, B_CP2P, ncells);
   int* op2p = ensure<int>(c, B_OP2P, ncells);
+  int4* rec = ensure<int4>(c, B_REC, ncells);
   int* chcnt = ensure<int>(c, B_CHCNT, std::max(ntl, 1));
   int* choff = ensure<int>(c, B_CHOFF, std::max(ntl, 1));
   if (!direct) {
     fill_i32(cm2l, 0, ncells, s);
     fill_i32(cp2p, 0, ncells, s);
-    lists_pass(tv, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, misc + M_FLAGS, s);
+    cell_records(tv, rec, s);
+    lists_pass(tv, rec, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, misc + M_FLAGS, s);
     int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
     scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
     scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
@@ -305,7 +308,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   int* m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
   int* p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
   if (!direct) {
-    lists_pass(tv, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, misc + M_FLAGS, s);
+    lists_pass(tv, rec, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, misc + M_FLAGS, s);
     p2p_pair_count(tv, tleaves, ntl, op2p, cp2p, p2p_src, pairs, s);
   }
   int2* items = ensure<int2>(c, B_ITEMS, nitems);
@@ -329,15 +332,16 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   if (!direct) {
     double2* mp = ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
     double2* loc = ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
+    double2* own = ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
+    int* counters = ensure<int>(c, B_COUNTERS, ncells);
     far = ensure<double>(c, B_FAR, m);
     mark(PP_PHASE_P2M);
-    p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
+    upward(tv, sleaves, nsl, src4, sw, p, mp, counters, s);  // P2M and the M2M recursion, fused
     mark(PP_PHASE_M2M);
-    for (int l = depth - 1; l >= 0; --l) m2m_level(tv, lstart[l], lstart[l + 1], p, mp, s);
     mark(PP_PHASE_M2L);
-    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, loc, s);
+    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, own, s);
     mark(PP_PHASE_L2L);
-    for (int l = 1; l <= depth; ++l) l2l_level(tv, lstart[l], lstart[l + 1], p, loc, s);
+    downward(tv, tcells, ntc, p, own, loc, s);
     mark(PP_PHASE_L2P);
     l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
   } else {

@@ -44,33 +44,73 @@ __global__ void k_root(TreeArrays t, const int* __restrict__ nsrc_dev, int ntgt,
   ls[1] = 1;
 }
 
-// Work item w = 4 (c - c0) + q: quadrant q of cell c of the level.  Writes the
-// child's source/target ranges and whether it exists (split parent, non-empty).
-__global__ void k_level_split(TreeArrays t, const int* __restrict__ ls, int level, int D, int leaf_max,
-                              const uint32_t* __restrict__ skey, const uint32_t* __restrict__ tkey,
-                              int4* __restrict__ cr, int* __restrict__ exists, int* __restrict__ n4_out) {
+// lower_bound of key in a[lo, hi) by one wave: 64 probes per step shrink the
+// range 64-fold, so a range of 2^18 keys takes three dependent loads instead
+// of eighteen.  All lanes return the same index.
+__device__ inline int wave_lower_bound(const uint32_t* __restrict__ a, int lo, int hi, uint64_t key) {
+  const int lane = threadIdx.x % kWave;
+  while (hi > lo) {
+    const int L = hi - lo;
+    if (L <= kWave) {
+      const bool lt = lane < L && (uint64_t)a[lo + lane] < key;
+      return lo + __popcll(__ballot(lt));
+    }
+    const int step = (L + kWave - 1) / kWave;
+    const int pos = min(lo + (lane + 1) * step - 1, hi - 1);
+    const int cnt = __popcll(__ballot((uint64_t)a[pos] < key));
+    if (cnt == kWave) return hi;  // the last probe is hi - 1
+    // a[lo + cnt*step - 1] < key <= a[min(lo + (cnt+1)*step - 1, hi - 1)]
+    const int newhi = min(lo + (cnt + 1) * step - 1, hi - 1);
+    lo = lo + cnt * step;
+    hi = newhi;
+  }
+  return lo;
+}
+
+// One wave per (cell of the level, split point j): j = 0..2 find where source
+// quadrants 1..3 of the cell begin, j = 3..5 the same for targets.
+__global__ __launch_bounds__(256) void k_level_split(TreeArrays t, const int* __restrict__ ls, int level, int D,
+                                                      int leaf_max, const uint32_t* __restrict__ skey,
+                                                      const uint32_t* __restrict__ tkey, int* __restrict__ sp,
+                                                      int* __restrict__ n4_out) {
+  const int c0 = ls[level], c1 = ls[level + 1];
+  const int gw = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + threadIdx.x / kWave));
+  if (gw == 0 && threadIdx.x % kWave == 0) *n4_out = 4 * (c1 - c0);
+  const int nw = 6 * (c1 - c0);
+  for (int w = gw; w < nw; w += gridDim.x * 4) {
+    const int ci = w / 6, j = w % 6;
+    const int c = c0 + ci;
+    const int sb = t.sb[c], se = t.se[c], tb = t.tb[c], te = t.te[c];
+    const bool split = level < D && (se - sb > leaf_max || te - tb > leaf_max);
+    if (!split) continue;
+    const int q = j % 3 + 1;
+    const int shift = 2 * (D - level - 1);
+    const uint32_t prefix = morton(2 * (uint32_t)t.ix[c] + (q & 1), 2 * (uint32_t)t.iy[c] + (q >> 1));
+    const uint64_t lo = (uint64_t)prefix << shift;
+    const int r = j < 3 ? wave_lower_bound(skey, sb, se, lo) : wave_lower_bound(tkey, tb, te, lo);
+    if (threadIdx.x % kWave == 0) sp[6 * ci + j] = r;
+  }
+}
+
+// Work item w = 4 (c - c0) + q: child quadrant q's source/target ranges from
+// the split points, and whether it exists (split parent, non-empty child).
+__global__ void k_level_exists(TreeArrays t, const int* __restrict__ ls, int level, int D, int leaf_max,
+                               const int* __restrict__ sp, int4* __restrict__ cr, int* __restrict__ exists) {
   const int c0 = ls[level], c1 = ls[level + 1];
   const int n4 = 4 * (c1 - c0);
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid == 0) *n4_out = n4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t w = gid; w < n4; w += stride) {
-    const int c = c0 + (int)(w >> 2);
-    const int q = (int)(w & 3);
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n4; w += stride) {
+    const int ci = (int)(w >> 2), q = (int)(w & 3);
+    const int c = c0 + ci;
     const int sb = t.sb[c], se = t.se[c], tb = t.tb[c], te = t.te[c];
     const bool split = level < D && (se - sb > leaf_max || te - tb > leaf_max);
     if (!split) {
       exists[w] = 0;
       continue;
     }
-    const int shift = 2 * (D - level - 1);
-    const uint32_t prefix = morton(2 * (uint32_t)t.ix[c] + (q & 1), 2 * (uint32_t)t.iy[c] + (q >> 1));
-    const uint64_t lo = (uint64_t)prefix << shift;
-    const uint64_t hi = (uint64_t)(prefix + 1) << shift;
-    const int csb = lower_bound_u32(skey, sb, se, lo);
-    const int cse = lower_bound_u32(skey, csb, se, hi);
-    const int ctb = lower_bound_u32(tkey, tb, te, lo);
-    const int cte = lower_bound_u32(tkey, ctb, te, hi);
+    const int* v = sp + 6 * ci;
+    const int csb = q == 0 ? sb : v[q - 1], cse = q == 3 ? se : v[q];
+    const int ctb = q == 0 ? tb : v[3 + q - 1], cte = q == 3 ? te : v[3 + q];
     cr[w] = make_int4(csb, cse, ctb, cte);
     exists[w] = (cse > csb || cte > ctb) ? 1 : 0;
   }
@@ -235,11 +275,14 @@ static unsigned level_blocks(int64_t max_cells) {
 }
 
 void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
-                const uint32_t* skey, const uint32_t* tkey, int4* cr, int* exists, int* off, int* scan_tmp,
+                const uint32_t* skey, const uint32_t* tkey, int* sp, int4* cr, int* exists, int* off, int* scan_tmp,
                 int* n4_slot, int* total_slot, int* flags, hipStream_t s) {
-  const unsigned g = level_blocks(max_cells);
-  k_level_split<<<g, 256, 0, s>>>(t, ls, level, D, leaf_max, skey, tkey, cr, exists, n4_slot);
-  scan_exclusive_dev(exists, off, n4_slot, 4 * std::max<int64_t>(max_cells, 1), scan_tmp, total_slot, s);
+  const int64_t mc = std::max<int64_t>(max_cells, 1);
+  const unsigned gs = (unsigned)std::min<int64_t>((6 * mc + 3) / 4, 4096);
+  k_level_split<<<gs, 256, 0, s>>>(t, ls, level, D, leaf_max, skey, tkey, sp, n4_slot);
+  const unsigned g = level_blocks(mc);
+  k_level_exists<<<g, 256, 0, s>>>(t, ls, level, D, leaf_max, sp, cr, exists);
+  scan_exclusive_dev(exists, off, n4_slot, 4 * mc, scan_tmp, total_slot, s);
   k_level_link<<<g, 256, 0, s>>>(t, ls, level, cr, exists, off, total_slot, cap, flags);
 }
 

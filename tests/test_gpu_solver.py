@@ -240,3 +240,46 @@ def test_degenerate_inputs(solver):
     assert rel_max(P, ref) < 1e-7
     P = solver.solve_grid(f3, 1 / 16, tx, ty, precision="mixed", leaf_max=8)
     assert rel_max(P, ref) < 1e-5
+
+
+def _sampled_check(solver, name, n_samples=600, seed=21):
+    w = G.workload(name)
+    g = w["grid"]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sel = rng.choice(w["tx"].size, n_samples, replace=False)
+    ref = direct.direct_grid(w["f"], g.h, w["tx"][sel], w["ty"][sel])
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    errs = {}
+    for prec in ("fp64", "mixed"):
+        P = to_host(solver.solve_grid(f, g.h, tx, ty, p=w["p"], theta=w["theta"], precision=prec))
+        errs[prec] = rel_l2(P[sel], ref)
+    return w, errs
+
+
+def test_band2048_sampled(solver):
+    """2048^2 band-masked vortex source, 16,384 surface/lifted targets, p=16, theta=0.4."""
+    w, errs = _sampled_check(solver, "band2048")
+    assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-4, errs
+    # the tree of this adaptive case against the reference: arrays in full, lists on sampled cells
+    info = tree_ref.grid_tree(w["f"], w["tx"], w["ty"], w["grid"].h, leaf_max=64)
+    t = info["tree"]
+    np.testing.assert_array_equal(solver.debug_array("TGT_PERM"), info["tgt_perm"])
+    for name, ref in (("CELL_LEVEL", t.level), ("CELL_IX", t.ix), ("CELL_IY", t.iy), ("CELL_SB", t.sb),
+                      ("CELL_SE", t.se), ("CELL_TB", t.tb), ("CELL_TE", t.te), ("CELL_CHILD", t.child_begin)):
+        np.testing.assert_array_equal(solver.debug_array(name), ref, err_msg=name)
+    rng = np.random.Generator(np.random.PCG64(3))
+    tc = np.flatnonzero(t.te > t.tb)
+    off = {k: solver.debug_array(k) for k in ("M2L_OFF", "M2L_CNT", "M2L_SRC", "P2P_OFF", "P2P_CNT", "P2P_SRC")}
+    for a in rng.choice(tc, min(150, tc.size), replace=False):
+        lm, lp = tree_ref.lists_for_cell(t, int(a), w["theta"])
+        got_m = sorted(off["M2L_SRC"][off["M2L_OFF"][a]:off["M2L_OFF"][a] + off["M2L_CNT"][a]].tolist())
+        got_p = sorted(off["P2P_SRC"][off["P2P_OFF"][a]:off["P2P_OFF"][a] + off["P2P_CNT"][a]].tolist())
+        assert got_m == lm and got_p == lp, a
+
+
+def test_envelope4096_sampled(solver):
+    """4096^2 two-band envelope source (6.16M nonzero), 32,768 surface/lifted targets, p=12, theta=0.5."""
+    w, errs = _sampled_check(solver, "envelope4096", n_samples=400)
+    assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-4, errs
+    st = solver.stats()
+    assert st["nsources"] == int(np.count_nonzero(w["f"]))
