@@ -57,6 +57,77 @@ def traffic_from_profile(workload: str):
     return rec.get("bytes_per_launch")
 
 
+def _percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def serving_run(pp, G, args, log):
+    """Serving stream: the same Poisson arrival trace fed to a one-slot server (the plain
+    one-solve-at-a-time path) and to a multi-slot server (continuous batching)."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    log(f"[bench] serving: generating {args.serve_requests} requests")
+    reqs = G.serving_requests(args.serve_requests, seed=4, device="cuda")
+    torch.cuda.synchronize()
+    # sequential throughput and the reference (alone) results
+    s = pp.Solver(0)
+    alone = []
+    for r in reqs[:4]:
+        s.solve_grid(r["f"], r["grid"].h, r["tx"], r["ty"], p=r["p"], theta=r["theta"], precision=r["precision"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in reqs:
+        alone.append(s.solve_grid(r["f"], r["grid"].h, r["tx"], r["ty"], p=r["p"], theta=r["theta"],
+                                  precision=r["precision"]))
+    torch.cuda.synchronize()
+    seq_rate = len(reqs) / (time.perf_counter() - t0)
+    s.close()
+    lam = args.serve_load * seq_rate
+    rng = np.random.Generator(np.random.PCG64(4))
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(reqs)))
+    arrivals -= arrivals[0]
+
+    def run(slots):
+        srv = pp.Server(0, max_slots=slots)
+        outs = [torch.empty(r["tx"].numel(), dtype=torch.float64, device="cuda") for r in reqs]
+        tickets = [None] * len(reqs)
+        start = time.perf_counter()
+
+        def submitter():
+            for i, r in enumerate(reqs):
+                delay = arrivals[i] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = srv.submit(r["f"], r["grid"].h, r["tx"], r["ty"], outs[i], p=r["p"], theta=r["theta"],
+                                        precision=r["precision"])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        infos = [srv.wait(t) for t in tickets]
+        makespan = max(i["end_us"] for i in infos) - min(i["start_us"] - i["queue_us"] for i in infos)
+        srv.close()
+        lat = [i["total_us"] / 1e3 for i in infos]
+        same = all(bool(torch.equal(o, a)) for o, a in zip(outs, alone))
+        return {"p50_ms": _percentile(lat, 50), "p99_ms": _percentile(lat, 99), "mean_ms": float(np.mean(lat)),
+                "solves_per_s": len(reqs) / (makespan * 1e-6), "slots": slots, "identical_to_alone": same}
+
+    log("[bench] serving: one-slot (sequential) path")
+    seq = run(1)
+    log(f"[bench] serving: {args.serve_slots}-slot path")
+    srv = run(args.serve_slots)
+    sizes = [r["grid"].nx for r in reqs]
+    return {"requests": len(reqs), "arrival": f"Poisson, rate {lam:.1f}/s = {args.serve_load} x sequential "
+                                               f"throughput ({seq_rate:.1f} solves/s)",
+            "grid_sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))},
+            "sequential": seq, "served": srv,
+            "p99_speedup": seq["p99_ms"] / srv["p99_ms"] if srv["p99_ms"] > 0 else None}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +139,9 @@ def main() -> int:
     ap.add_argument("--samples", type=int, default=2000, help="targets checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / sequential solves per second")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -171,6 +245,10 @@ def main() -> int:
                "sample": f"FP64 direct sum over all {N} nonzero sources at {n_sample} of the {M} targets "
                          f"(seeded), {t_cpu:.2f} s; rate scaled to whole solves"}
 
+    served = None
+    if args.serve_requests > 0:
+        served = serving_run(pp, G, args, log)
+
     p2p_ms = phases["p2p"]
     achieved = OPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None
     roofline = {"bound": "alu", "kernel": "k_p2p32 (near field)", "achieved": achieved, "peak": VALU_PEAK_TOPS,
@@ -205,7 +283,7 @@ def main() -> int:
         "phases_ms": phases,
         "tree": {k: st[k] for k in ("depth", "ncells", "nsrc_leaves", "ntgt_leaves", "n_m2l", "n_p2p_lists",
                                      "n_p2p_pairs")},
-        "served": None,
+        "served": served,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -54,7 +54,8 @@ enum {
   PP_ERR_DOMAIN = -2,  /* a target lies outside the root square */
   PP_ERR_NOMEM = -3,   /* the solve would exceed the context's device-memory budget */
   PP_ERR_DEVICE = -4,  /* a HIP call failed; the context is unusable */
-  PP_ERR_LIMIT = -5    /* the tree exceeded an internal limit (e.g. traversal frontier) */
+  PP_ERR_LIMIT = -5,   /* the tree exceeded an internal limit (e.g. traversal frontier) */
+  PP_ERR_TIMEOUT = -6  /* pp_server_wait: the request did not finish in time (ticket stays valid) */
 };
 
 enum { PP_FP64 = 0, PP_MIXED = 1 };            /* MIXED: P2P and L2P in FP32 (Kahan), expansions FP64 */
@@ -103,8 +104,8 @@ enum {
   PP_PHASE_TREE = 2,     /* quadtree levels */
   PP_PHASE_LISTS = 3,    /* cell lists, interaction lists, near-field work items */
   PP_PHASE_PACK = 4,     /* per-leaf source records and target offsets */
-  PP_PHASE_P2M = 5,      /* P2M and the bottom-up M2M recursion (one fused launch) */
-  PP_PHASE_M2M = 6,      /* (empty: M2M runs inside the P2M phase) */
+  PP_PHASE_P2M = 5,
+  PP_PHASE_M2M = 6,      /* bottom-up recursion, three levels per launch */
   PP_PHASE_M2L = 7,
   PP_PHASE_L2L = 8,      /* final locals: own M2L plus exact shifts of every ancestor's */
   PP_PHASE_L2P = 9,
@@ -176,6 +177,59 @@ pp_status pp_debug_copy(const pp_ctx* ctx, int32_t what, void* dst, int64_t capa
 
 const char* pp_status_string(pp_status s);
 const char* pp_last_error(const pp_ctx* ctx);
+
+/*
+ * Serving: a persistent pool of solve slots fed from a FIFO of requests
+ * (continuous batching of independent solves on one GPU).  Each slot owns a
+ * context (device buffers stay resident between requests), a HIP stream and a
+ * host thread.  The head of the queue is admitted as soon as a slot is free
+ * and the estimated device footprints of the requests in flight plus its own
+ * fit in hbm_budget_bytes (0 = no bound; a request always runs when nothing
+ * else is in flight).  Requests admitted together run concurrently and their
+ * kernels overlap on the device.  A request's result is bitwise the result of
+ * pp_solve_grid on the same inputs: slots share nothing.
+ *
+ * Ownership: host inputs (f, tx, ty) are copied at submission; device inputs
+ * and p_out must stay valid until pp_server_wait has returned for the ticket.
+ * All server functions are thread-safe.
+ */
+typedef struct pp_server pp_server;
+typedef struct {
+  int32_t device;
+  int32_t max_slots;          /* concurrent solves, 1..64 */
+  uint64_t hbm_budget_bytes;  /* admission bound on in-flight footprints (0 = none) */
+} pp_server_cfg;
+typedef struct {              /* the arguments of pp_solve_grid */
+  int32_t nx, ny;
+  double x0, y0, h;
+  const double* f;
+  int64_t m;
+  const double* tx;
+  const double* ty;
+  pp_params params;
+  double* p_out;
+} pp_request;
+typedef struct {
+  pp_status status;           /* the solve's own status */
+  int32_t slot;               /* slot that ran it */
+  double queue_us;            /* submission to start */
+  double run_us;              /* start to completion */
+  double total_us;            /* submission to completion */
+  double start_us, end_us;    /* start and completion, microseconds since pp_server_create */
+} pp_ticket_info;
+
+pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out);
+/* Queue one solve; *ticket identifies it for pp_server_wait. */
+pp_status pp_server_submit(pp_server* s, const pp_request* req, uint64_t* ticket);
+/* Block until the ticket's solve has finished (timeout_us < 0: no limit);
+ * returns its status (PP_ERR_TIMEOUT leaves the ticket valid) and releases
+ * the ticket; info (may be NULL) receives its timings. */
+pp_status pp_server_wait(pp_server* s, uint64_t ticket, int64_t timeout_us, pp_ticket_info* info);
+/* Finish every queued request, then stop the slots and free their memory. */
+pp_status pp_server_destroy(pp_server* s);
+const char* pp_server_last_error(const pp_server* s);
+/* Device bytes a request of this shape may use (the admission estimate). */
+uint64_t pp_footprint_estimate(int32_t nx, int32_t ny, int64_t m, int32_t p, int32_t leaf_max);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,12 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_get_stats,
     pp_last_error,
     pp_set_profiling,
+    pp_server_create,
+    pp_server_destroy,
+    pp_server_last_error,
+    pp_server_submit,
+    pp_server_wait,
+    pp_footprint_estimate,
     pp_solve_grid,
     pp_status_string,
     pp_params,
@@ -146,3 +152,53 @@ class Solver:
         if st != B.PP_OK:
             raise PPError(st, pp_last_error(self._ctx))
         return a[:n]
+
+
+class Server:
+    """Continuous-batching request loop (pp_server_* in include/pp.h).
+
+    ``submit`` queues one solve and returns a ticket; ``wait`` blocks until it
+    is done and returns its timing record.  Inputs: NumPy arrays (copied at
+    submission) or CUDA tensors (kept alive here until the ticket is waited on).
+    """
+
+    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0):
+        self._srv = pp_server_create(device, max_slots, hbm_budget_bytes)
+        self._keep = {}
+
+    def submit(self, f, h, tx, ty, out, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
+               self_mode="skip") -> int:
+        fp, fk = _ptr(f, "f")
+        xp, xk = _ptr(tx, "tx")
+        yp, yk = _ptr(ty, "ty")
+        op, ok = _ptr(out, "out")
+        if ok is not out:
+            raise TypeError("out must be a contiguous float64 array or tensor")
+        ny, nx = tuple(fk.shape)
+        m = int(np.prod(tuple(xk.shape)))
+        req = B.pp_request(nx, ny, float(x0), float(y0), float(h), fp, m, xp, yp,
+                           make_params(p, theta, leaf_max, precision, self_mode), op)
+        t = pp_server_submit(self._srv, req)
+        self._keep[t] = (fk, xk, yk, ok)
+        return t
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> dict:
+        st, info = pp_server_wait(self._srv, ticket, timeout_us)
+        if st == B.PP_ERR_TIMEOUT:
+            raise TimeoutError(f"ticket {ticket} not finished")
+        self._keep.pop(ticket, None)
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_server_last_error(self._srv)}")
+        return {name: getattr(info, name) for name, _ in B.pp_ticket_info._fields_}
+
+    def close(self):
+        if self._srv:
+            pp_server_destroy(self._srv)
+            self._srv = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

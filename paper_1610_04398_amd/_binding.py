@@ -35,7 +35,9 @@ UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
 EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_get_stats", "pp_set_profiling",
-            "pp_debug_copy", "pp_status_string", "pp_last_error")
+            "pp_debug_copy", "pp_status_string", "pp_last_error", "pp_server_create", "pp_server_submit",
+            "pp_server_wait", "pp_server_destroy", "pp_server_last_error", "pp_footprint_estimate")
+PP_ERR_TIMEOUT = -6
 
 
 class pp_params(ctypes.Structure):
@@ -48,6 +50,22 @@ class pp_stats(ctypes.Structure):
                 ("ntgt_leaves", ctypes.c_int32), ("nsources", ctypes.c_int64), ("ntargets", ctypes.c_int64),
                 ("n_m2l", ctypes.c_int64), ("n_p2p_lists", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 12)]
+
+class pp_server_cfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class pp_request(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("x0", ctypes.c_double), ("y0", ctypes.c_double),
+                ("h", ctypes.c_double), ("f", ctypes.c_void_p), ("m", ctypes.c_int64), ("tx", ctypes.c_void_p),
+                ("ty", ctypes.c_void_p), ("params", pp_params), ("p_out", ctypes.c_void_p)]
+
+
+class pp_ticket_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("slot", ctypes.c_int32), ("queue_us", ctypes.c_double),
+                ("run_us", ctypes.c_double), ("total_us", ctypes.c_double), ("start_us", ctypes.c_double),
+                ("end_us", ctypes.c_double)]
+
 
 PHASES = ("ingest", "sort", "tree", "lists", "pack", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "finalize")
 
@@ -79,6 +97,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_set_profiling.restype = i32
     lib.pp_debug_copy.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
     lib.pp_debug_copy.restype = i32
+    lib.pp_server_create.argtypes = [ctypes.POINTER(pp_server_cfg), ctypes.POINTER(vp)]
+    lib.pp_server_create.restype = i32
+    lib.pp_server_submit.argtypes = [vp, ctypes.POINTER(pp_request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.pp_server_submit.restype = i32
+    lib.pp_server_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(pp_ticket_info)]
+    lib.pp_server_wait.restype = i32
+    lib.pp_server_destroy.argtypes = [vp]
+    lib.pp_server_destroy.restype = i32
+    lib.pp_server_last_error.argtypes = [vp]
+    lib.pp_server_last_error.restype = ctypes.c_char_p
+    lib.pp_footprint_estimate.argtypes = [i32, i32, i64, i32, i32]
+    lib.pp_footprint_estimate.restype = ctypes.c_uint64
     lib.pp_status_string.argtypes = [i32]
     lib.pp_status_string.restype = ctypes.c_char_p
     lib.pp_last_error.argtypes = [vp]
@@ -142,6 +172,41 @@ def pp_status_string(st: int) -> str:
 
 def pp_last_error(ctx) -> str:
     return lib().pp_last_error(ctx).decode()
+
+
+def pp_server_create(device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0) -> int:
+    cfg = pp_server_cfg(device, max_slots, hbm_budget_bytes)
+    h = ctypes.c_void_p()
+    st = lib().pp_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    if st != PP_OK:
+        raise PPError(st, "pp_server_create failed")
+    return h.value
+
+
+def pp_server_submit(server, req: pp_request) -> int:
+    t = ctypes.c_uint64(0)
+    st = lib().pp_server_submit(server, ctypes.byref(req), ctypes.byref(t))
+    if st != PP_OK:
+        raise PPError(st, "pp_server_submit failed")
+    return t.value
+
+
+def pp_server_wait(server, ticket: int, timeout_us: int = -1) -> tuple[int, pp_ticket_info]:
+    info = pp_ticket_info()
+    st = lib().pp_server_wait(server, ticket, timeout_us, ctypes.byref(info))
+    return st, info
+
+
+def pp_server_destroy(server) -> int:
+    return lib().pp_server_destroy(server)
+
+
+def pp_server_last_error(server) -> str:
+    return lib().pp_server_last_error(server).decode()
+
+
+def pp_footprint_estimate(nx: int, ny: int, m: int, p: int, leaf_max: int) -> int:
+    return int(lib().pp_footprint_estimate(nx, ny, m, p, leaf_max))
 
 
 class PPError(RuntimeError):

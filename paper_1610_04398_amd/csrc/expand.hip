@@ -22,6 +22,8 @@
 //   M2M (d as above):
 //     a'_l(parent) += -a_0 d^l / l + sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k(child)
 //   L2P: far(z) = Re sum_l L'_l u^l,  u = (z - z_c) / s.
+#include <algorithm>
+
 #include "blockscan.h"
 #include "internal.h"
 
@@ -51,101 +53,133 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
   return {(ix & 1) ? 0.25 : -0.25, (iy & 1) ? 0.25 : -0.25};
 }
 
-// Upward pass in one launch.  One wave per source leaf computes its P2M
-// (lanes stride over the leaf's sources; a fixed-order butterfly sums them).
-// The M2M recursion of eq. expandedShift then runs bottom-up without level
-// barriers: a cell's expansion is final once all of its children with sources
-// are; each child announces completion on a per-cell device-scope counter, and
-// the wave that completes a parent computes the parent's expansion from all of
-// its children (lanes = child x coefficient, children summed in a fixed order)
-// and continues with the grandparent.  No wave ever waits on another.
+// P2M: one wave per source leaf; lanes stride over the leaf's sources and a
+// fixed-order butterfly sums the per-lane powers.
 template <int PM>
-__global__ __launch_bounds__(256) void k_upward(TreeView t, const int* __restrict__ sleaves, int n,
-                                                const float4* __restrict__ src4, const double* __restrict__ w64,
-                                                int p, double2* __restrict__ mp, int* __restrict__ counters) {
+__global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
+                                             const float4* __restrict__ src4, const double* __restrict__ w64, int p,
+                                             double2* __restrict__ mp) {
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / kWave);
   if (wid >= n) return;
   const int lane = threadIdx.x % kWave;
-  int c = sleaves[wid];
-  const int P1 = p + 1;
-  {
-    const double side = cell_side(t.D, t.lvl[c]);
-    const double inv = 1.0 / side;
-    cplx acc[PM + 1];
+  const int c = sleaves[wid];
+  const double side = cell_side(t.D, t.lvl[c]);
+  const double inv = 1.0 / side;
+  cplx acc[PM + 1];
 #pragma unroll
-    for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
-    const int sb = t.sb[c], se = t.se[c];
-    for (int s = sb + lane; s < se; s += kWave) {
-      const float4 q = src4[s];
-      const double w = w64[s];
-      const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
-      acc[0].x += w;
-      cplx zk = {w * z.x, w * z.y};
+  for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
+  const int sb = t.sb[c], se = t.se[c];
+  for (int s = sb + lane; s < se; s += kWave) {
+    const float4 q = src4[s];
+    const double w = w64[s];
+    const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
+    acc[0].x += w;
+    cplx zk = {w * z.x, w * z.y};
 #pragma unroll
-      for (int k = 1; k <= PM; ++k) {
-        acc[k] = cadd(acc[k], zk);
-        zk = cmul(zk, z);
-      }
+    for (int k = 1; k <= PM; ++k) {
+      acc[k] = cadd(acc[k], zk);
+      zk = cmul(zk, z);
     }
-#pragma unroll
-    for (int k = 0; k <= PM; ++k) {
-#pragma unroll
-      for (int o = kWave / 2; o > 0; o >>= 1) {
-        acc[k].x += __shfl_xor(acc[k].x, o, kWave);
-        acc[k].y += __shfl_xor(acc[k].y, o, kWave);
-      }
-    }
-    double2* out = mp + (int64_t)c * P1;
-#pragma unroll
-    for (int k = 0; k <= PM; ++k)
-      if (k <= p && lane == k) out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
   }
-  // bottom-up M2M
-  const int q = lane >> 4;     // child slot
-  const int lsub = lane & 15;  // coefficient within a chunk of 16
-  while (true) {
-    const int par = t.parent[c];
-    if (par < 0) break;
-    const int k0 = t.child[par], nk = t.nchild[par];
-    int need = 0;
-    for (int j = 0; j < nk; ++j) need += (t.se[k0 + j] > t.sb[k0 + j]) ? 1 : 0;
-    __threadfence();  // this cell's expansion is visible device-wide before it is announced
-    int old = 0;
-    if (lane == 0) old = atomicAdd(&counters[par], 1);
-    old = __shfl(old, 0, kWave);
-    if (old + 1 < need) break;  // another child finishes later and carries on
-    __threadfence();            // see the other children's expansions
-    c = par;
-    for (int lb = 0; lb <= p; lb += 16) {
-      const int l = lb + lsub;
-      cplx b = {0.0, 0.0};
-      if (q < nk && l <= p) {
-        const int ch = k0 + q;
-        if (t.se[ch] > t.sb[ch]) {
-          const double2* a = mp + (int64_t)ch * P1;
-          const double a0 = a[0].x;
-          if (l == 0) {
-            b.x = a0;
-          } else {
-            // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
-            const cplx d = quadrant_offset(t.ix[ch], t.iy[ch]);
-            cplx dp = {1.0, 0.0};
-            for (int k = l; k >= 1; --k) {
-              const double2 v = a[k];
-              b = cadd(b, cscale(cmul({v.x, v.y}, dp), binom(l - 1, k - 1) * ldexp(1.0, -k)));
-              dp = cmul(dp, d);
-            }
-            b = cadd(b, cscale(dp, -a0 / l));
-          }
-        }
-      }
-      // children 0+1 and 2+3, then the two pairs
-      b.x += __shfl_xor(b.x, 16, kWave);
-      b.y += __shfl_xor(b.y, 16, kWave);
-      b.x += __shfl_xor(b.x, 32, kWave);
-      b.y += __shfl_xor(b.y, 32, kWave);
-      if (q == 0 && l <= p) mp[(int64_t)c * P1 + l] = make_double2(b.x, b.y);
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      acc[k].x += __shfl_xor(acc[k].x, o, kWave);
+      acc[k].y += __shfl_xor(acc[k].y, o, kWave);
     }
+  }
+  double2* out = mp + (int64_t)c * (p + 1);
+#pragma unroll
+  for (int k = 0; k <= PM; ++k)
+    if (k <= p && lane == k) out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
+}
+
+// One M2M output coefficient: a'_l of a parent from up to four children whose
+// scaled coefficients are at ch[q] (q-th child's array, stride 1), d_q their
+// centre offsets in parent sides.
+__device__ inline cplx m2m_coeff(int l, int nk, const double2* const* ch, const cplx* d) {
+  cplx b = {0.0, 0.0};
+  for (int q = 0; q < nk; ++q) {
+    const double2* a = ch[q];
+    if (!a) continue;
+    const double a0 = a[0].x;
+    if (l == 0) {
+      b.x += a0;
+      continue;
+    }
+    // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
+    cplx acc = {0.0, 0.0};
+    cplx dp = {1.0, 0.0};
+    for (int k = l; k >= 1; --k) {
+      const double2 v = a[k];
+      acc = cadd(acc, cscale(cmul({v.x, v.y}, dp), binom(l - 1, k - 1) * ldexp(1.0, -k)));
+      dp = cmul(dp, d[q]);
+    }
+    b = cadd(b, cadd(acc, cscale(dp, -a0 / l)));
+  }
+  return b;
+}
+
+// M2M for three levels per launch (eq. expandedShift applied recursively from
+// the finest level up).  One workgroup per cell R at level L computes, bottom
+// up, the expansions of R's grandchildren (level L+2), children (L+1) and R
+// itself from the final expansions one level below (global memory), keeping
+// the intermediate levels in LDS.  Leaves keep their P2M expansions.
+constexpr int kM2MThreads = 256;
+__global__ __launch_bounds__(kM2MThreads) void k_m2m3(TreeView t, int c0, int c1, int levels, int p,
+                                                       double2* __restrict__ mp) {
+  __shared__ int cells[21];           // [0] = R, [1..4] children, [5..20] grandchildren (4 per child)
+  __shared__ double2 co[21][kMaxP + 1];
+  __shared__ int tmp_child[21], tmp_n[21];
+  const int R = c0 + blockIdx.x;
+  if (R >= c1) return;
+  const int P1 = p + 1;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 21; ++i) cells[i] = -1;
+    cells[0] = R;
+    for (int i = 0; i < 5; ++i) {
+      const int c = cells[i];
+      if (c < 0) continue;
+      const int k0 = t.child[c], nk = t.nchild[c];
+      for (int q = 0; q < nk; ++q) cells[1 + 4 * i + q] = k0 + q;
+    }
+    for (int i = 0; i < 21; ++i) {
+      const int c = cells[i];
+      tmp_child[i] = c >= 0 ? t.child[c] : -1;
+      tmp_n[i] = c >= 0 ? t.nchild[c] : 0;
+      if (c >= 0 && t.se[c] <= t.sb[c]) cells[i] = -1;  // no sources: nothing to expand
+    }
+  }
+  __syncthreads();
+  // level offsets within `cells`: depth 2 -> [5, 21), depth 1 -> [1, 5), depth 0 -> [0, 1)
+  for (int depth = levels - 1; depth >= 0; --depth) {
+    const int b = depth == 2 ? 5 : (depth == 1 ? 1 : 0);
+    const int e = depth == 2 ? 21 : (depth == 1 ? 5 : 1);
+    for (int w = threadIdx.x; w < (e - b) * P1; w += blockDim.x) {
+      const int i = b + w / P1, l = w % P1;
+      const int c = cells[i];
+      if (c < 0) continue;
+      if (tmp_child[i] < 0) {  // a leaf: its P2M expansion is final
+        co[i][l] = mp[(int64_t)c * P1 + l];
+        continue;
+      }
+      const double2* ch[4] = {nullptr, nullptr, nullptr, nullptr};
+      cplx d[4];
+      const int nk = tmp_n[i];
+      for (int q = 0; q < nk; ++q) {
+        const int kid = tmp_child[i] + q;
+        if (t.se[kid] <= t.sb[kid]) continue;
+        d[q] = quadrant_offset(t.ix[kid], t.iy[kid]);
+        // children inside this block's subtree come from LDS, the level below it from memory
+        const int slot = (depth == 0) ? 1 + q : 5 + 4 * (i - 1) + q;
+        ch[q] = (depth < levels - 1) ? &co[slot][0] : mp + (int64_t)kid * P1;
+      }
+      const cplx v = m2m_coeff(l, nk, ch, d);
+      co[i][l] = make_double2(v.x, v.y);
+      mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
+    }
+    __syncthreads();
   }
 }
 
@@ -310,11 +344,15 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
 
 }  // namespace
 
-void upward(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
-            int* counters, hipStream_t s) {
+void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
+         hipStream_t s) {
   if (n <= 0) return;
-  fill_i32(counters, 0, t.ncells, s);
-  PP_DISPATCH(p, k_upward, (n + 3) / 4, 256, s, t, sleaves, n, src4, w64, p, mp, counters);
+  PP_DISPATCH(p, k_p2m, (n + 3) / 4, 256, s, t, sleaves, n, src4, w64, p, mp);
+}
+
+void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s) {
+  if (c1 <= c0 || levels < 1) return;
+  k_m2m3<<<c1 - c0, kM2MThreads, 0, s>>>(t, c0, c1, std::min(levels, 3), p, mp);
 }
 
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,

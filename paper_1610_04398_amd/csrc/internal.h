@@ -82,15 +82,13 @@ void cell_records(TreeView t, int4* rec, hipStream_t s);
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags,
                 hipStream_t s);
-// Total (target, source) pairs of the P2P lists (statistics).
-void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
-                    unsigned long long* out, hipStream_t s);
-
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
-// P2M of every source leaf and the bottom-up M2M to the root, one launch
-// (counters: ncells ints of scratch).
-void upward(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
-            int* counters, hipStream_t s);
+// P2M of every source leaf (one wave per leaf).
+void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
+         hipStream_t s);
+// M2M for the `levels` (1..3) levels starting at the level whose cells are
+// [c0, c1): one workgroup per cell computes its subtree bottom up.
+void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, hipStream_t s);
 // Final local expansion of every cell with targets from its own M2L local
@@ -118,6 +116,7 @@ struct P2PArgs {
   const double2* rel64;
   int nparts;           // each target chunk's list is split over nparts waves
   int64_t m;            // number of targets
+  unsigned long long* pairs;  // if set, receives the number of (target, source) pairs evaluated
   double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r^2 / h^2)
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };

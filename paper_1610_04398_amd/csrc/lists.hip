@@ -146,27 +146,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   }
 }
 
-__global__ void k_pair_count(TreeView t, const int* __restrict__ tleaves, int n, const int* __restrict__ off,
-                             const int* __restrict__ cnt, const int* __restrict__ src, unsigned long long* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int A = tleaves[i];
-  long long acc = 0;
-  const int e0 = off[A], ne = cnt[A];
-  for (int e = 0; e < ne; ++e) {
-    const int B = src[e0 + e];
-    acc += (long long)(t.se[B] - t.sb[B]);
-  }
-  acc *= (long long)(t.te[A] - t.tb[A]);
-  if (acc) atomicAdd(out, (unsigned long long)acc);
-}
 }  // namespace
-
-void p2p_pair_count(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
-                    unsigned long long* out, hipStream_t s) {
-  if (n <= 0) return;
-  k_pair_count<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, off, cnt, src, out);
-}
 
 void cell_records(TreeView t, int4* rec, hipStream_t s) {
   if (t.ncells <= 0) return;

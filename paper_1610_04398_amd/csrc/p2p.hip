@@ -110,12 +110,14 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   float sum = 0.0f, comp = 0.0f;
   double wn = 0.0;
+  int64_t nsrc = 0;
   for (int e = e0; e < e1; ++e) {
     const int B = lst[e];
     const int shB = t.D - t.lvl[B];
     const float tx = r.x + (float)(cax - (t.ix[B] << shB));
     const float ty = r.y + (float)(cay - (t.iy[B] << shB));
     const int s0 = t.sb[B], s1 = t.se[B];
+    nsrc += s1 - s0;
     wn += a.leaf_w[B];
     if (B == A)
       p2p32_leaf<true>(a.src4, s0, s1, tx, ty, sum, comp);
@@ -124,6 +126,10 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int
   }
   if (active) a.near_sum[(int64_t)part * a.m + k] = ((double)sum - (double)comp) * kLn2;
   if (lane == 0 && it.y == 0) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
+  if (lane == 0 && a.pairs) {
+    const int nact = min(kWave, t.te[A] - (t.tb[A] + it.y));
+    atomicAdd(a.pairs, (unsigned long long)(nact * nsrc));
+  }
 }
 
 template <bool GUARD>
@@ -162,12 +168,14 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   double sum = 0.0;
   double wn = 0.0;
+  int64_t nsrc = 0;
   for (int e = e0; e < e1; ++e) {
     const int B = lst[e];
     const int shB = t.D - t.lvl[B];
     const double tx = r.x + (double)(cax - (t.ix[B] << shB));
     const double ty = r.y + (double)(cay - (t.iy[B] << shB));
     const int s0 = t.sb[B], s1 = t.se[B];
+    nsrc += s1 - s0;
     wn += a.leaf_w[B];
     if (B == A)
       p2p64_leaf<true>(a.src4, a.w64, s0, s1, tx, ty, sum);
@@ -176,6 +184,10 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int
   }
   if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
   if (lane == 0 && it.y == 0) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
+  if (lane == 0 && a.pairs) {
+    const int nact = min(kWave, t.te[A] - (t.tb[A] + it.y));
+    atomicAdd(a.pairs, (unsigned long long)(nact * nsrc));
+  }
 }
 }  // namespace
 

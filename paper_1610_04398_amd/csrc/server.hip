@@ -1,0 +1,249 @@
+// Serving loop: a persistent pool of solve slots fed from a FIFO of requests.
+//
+// Each slot owns a library context (its device buffers stay resident between
+// requests) and a HIP stream, and is driven by its own host thread; a request
+// is admitted to a free slot as soon as the sum of the estimated device
+// footprints of the requests in flight leaves room for it.  Requests that
+// arrive while others are running therefore start immediately and their
+// kernels overlap on the GPU with the others'.  A request's result does not
+// depend on which slot ran it or on what ran beside it: every slot runs the
+// same deterministic kernels on its own buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pp.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Job {
+  uint64_t ticket = 0;
+  pp_request req{};
+  std::vector<double> f_copy, tx_copy, ty_copy;  // host inputs copied at submission
+  uint64_t footprint = 0;
+  clk::time_point t_submit, t_start, t_end;
+  int slot = -1;
+  pp_status status = PP_OK;
+  bool done = false;
+  std::string err;
+};
+
+bool host_memory(const void* p) {
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return !(a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged);
+}
+
+}  // namespace
+
+struct pp_server {
+  pp_server_cfg cfg{};
+  clk::time_point t0 = clk::now();
+  std::mutex mu;
+  std::condition_variable cv_work;  // workers: queue changed or memory freed
+  std::condition_variable cv_done;  // waiters: a job finished
+  std::deque<std::shared_ptr<Job>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
+  uint64_t next_ticket = 1;
+  uint64_t inflight_bytes = 0;
+  int inflight = 0;
+  bool stopping = false;
+  std::vector<std::thread> workers;
+  std::vector<pp_ctx*> ctxs;
+  std::vector<hipStream_t> streams;
+  std::string err;
+};
+
+extern "C" uint64_t pp_footprint_estimate(int32_t nx, int32_t ny, int64_t m, int32_t p, int32_t leaf_max) {
+  if (nx < 1 || ny < 1 || m < 0 || p < 1 || leaf_max < 1) return 0;
+  const uint64_t g = (uint64_t)nx * (uint64_t)ny;
+  int k = 0;
+  while ((1 << k) < std::max(nx, ny)) ++k;
+  // per grid node: f staging, key, packed index, weight, 16-byte record, ingest tiles
+  const uint64_t src = g * (8 + 4 + 4 + 8 + 16 + 1);
+  // per target: coordinates, keys/permutations (x2), offsets, leaf, self data, far, near parts, output
+  const uint64_t tgt = (uint64_t)m * (16 + 16 + 8 + 16 + 4 + 4 + 8 + 8 + 8 * 8 + 8);
+  // cells: bounded by the tree capacity; arrays, records, expansions, lists
+  const uint64_t cells = std::min<uint64_t>(((uint64_t)1 << (2 * k + 2)) / 3 + 1,
+                                            1 + 4 * (uint64_t)std::max(k, 1) * ((g + m) / (leaf_max + 1) + 1));
+  const uint64_t cell = cells * (uint64_t)(15 * 4 + 16 + 4 * 16 + 3 * 16 * (p + 1) + 64 * 4 + 27 * 4);
+  return src + tgt + cell + (64u << 10);
+}
+
+namespace {
+
+void worker_loop(pp_server* s, int slot) {
+  (void)hipSetDevice(s->cfg.device);
+  pp_ctx* ctx = s->ctxs[slot];
+  hipStream_t stream = s->streams[slot];
+  for (;;) {
+    std::shared_ptr<Job> job;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] {
+        if (s->stopping && s->queue.empty()) return true;
+        if (s->queue.empty()) return false;
+        const uint64_t fp = s->queue.front()->footprint;
+        // FIFO admission: the head runs when the memory bound leaves room for it
+        // (always when nothing else is in flight)
+        return s->inflight == 0 || s->cfg.hbm_budget_bytes == 0 ||
+               s->inflight_bytes + fp <= s->cfg.hbm_budget_bytes;
+      });
+      if (s->queue.empty()) return;  // stopping and drained
+      job = s->queue.front();
+      s->queue.pop_front();
+      s->inflight += 1;
+      s->inflight_bytes += job->footprint;
+      job->slot = slot;
+      job->t_start = clk::now();
+    }
+    const pp_request& r = job->req;
+    const double* f = job->f_copy.empty() ? r.f : job->f_copy.data();
+    const double* tx = job->tx_copy.empty() ? r.tx : job->tx_copy.data();
+    const double* ty = job->ty_copy.empty() ? r.ty : job->ty_copy.data();
+    const pp_status st =
+        pp_solve_grid(ctx, r.nx, r.ny, r.x0, r.y0, r.h, f, r.m, tx, ty, &r.params, r.p_out, (void*)stream);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      job->status = st;
+      if (st != PP_OK) job->err = pp_last_error(ctx);
+      job->t_end = clk::now();
+      job->done = true;
+      job->f_copy.clear();
+      job->f_copy.shrink_to_fit();
+      job->tx_copy.clear();
+      job->tx_copy.shrink_to_fit();
+      job->ty_copy.clear();
+      job->ty_copy.shrink_to_fit();
+      s->inflight -= 1;
+      s->inflight_bytes -= job->footprint;
+    }
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+    if (st == PP_ERR_DEVICE) {
+      // this slot's context is unusable; replace it so the slot keeps serving
+      pp_destroy(ctx);
+      ctx = nullptr;
+      if (pp_create(s->cfg.device, 0, &ctx) != PP_OK) return;
+      s->ctxs[slot] = ctx;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out) {
+  if (!cfg || !out || cfg->max_slots < 1 || cfg->max_slots > 64) return PP_ERR_ARG;
+  *out = nullptr;
+  auto* s = new pp_server();
+  s->cfg = *cfg;
+  if (hipSetDevice(cfg->device) != hipSuccess) {
+    delete s;
+    return PP_ERR_DEVICE;
+  }
+  for (int i = 0; i < cfg->max_slots; ++i) {
+    pp_ctx* c = nullptr;
+    hipStream_t st = nullptr;
+    if (pp_create(cfg->device, 0, &c) != PP_OK || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      if (c) pp_destroy(c);
+      for (auto* x : s->ctxs) pp_destroy(x);
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      delete s;
+      return PP_ERR_DEVICE;
+    }
+    s->ctxs.push_back(c);
+    s->streams.push_back(st);
+  }
+  for (int i = 0; i < cfg->max_slots; ++i) s->workers.emplace_back(worker_loop, s, i);
+  *out = s;
+  return PP_OK;
+}
+
+pp_status pp_server_submit(pp_server* s, const pp_request* r, uint64_t* ticket) {
+  if (!s || !r || !ticket) return PP_ERR_ARG;
+  if (r->m < 0 || r->nx < 1 || r->ny < 1 || !r->f || (r->m > 0 && (!r->tx || !r->ty || !r->p_out)))
+    return PP_ERR_ARG;
+  auto job = std::make_shared<Job>();
+  job->req = *r;
+  const int64_t ng = (int64_t)r->nx * r->ny;
+  if (host_memory(r->f)) job->f_copy.assign(r->f, r->f + ng);
+  if (r->m > 0 && host_memory(r->tx)) job->tx_copy.assign(r->tx, r->tx + r->m);
+  if (r->m > 0 && host_memory(r->ty)) job->ty_copy.assign(r->ty, r->ty + r->m);
+  job->footprint = pp_footprint_estimate(r->nx, r->ny, r->m, r->params.p, r->params.leaf_max);
+  job->t_submit = clk::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return PP_ERR_ARG;
+    job->ticket = s->next_ticket++;
+    *ticket = job->ticket;
+    s->jobs[job->ticket] = job;
+    s->queue.push_back(job);
+  }
+  s->cv_work.notify_all();
+  return PP_OK;
+}
+
+pp_status pp_server_wait(pp_server* s, uint64_t ticket, int64_t timeout_us, pp_ticket_info* info) {
+  if (!s) return PP_ERR_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return PP_ERR_ARG;
+  std::shared_ptr<Job> job = it->second;
+  auto ready = [&] { return job->done; };
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    return PP_ERR_TIMEOUT;
+  }
+  if (info) {
+    using us = std::chrono::duration<double, std::micro>;
+    info->status = job->status;
+    info->slot = job->slot;
+    info->queue_us = us(job->t_start - job->t_submit).count();
+    info->run_us = us(job->t_end - job->t_start).count();
+    info->total_us = us(job->t_end - job->t_submit).count();
+    info->start_us = us(job->t_start - s->t0).count();
+    info->end_us = us(job->t_end - s->t0).count();
+  }
+  const pp_status st = job->status;
+  if (st != PP_OK) s->err = job->err;
+  s->jobs.erase(it);
+  return st;
+}
+
+pp_status pp_server_destroy(pp_server* s) {
+  if (!s) return PP_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& w : s->workers) w.join();
+  for (auto* c : s->ctxs)
+    if (c) pp_destroy(c);
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  delete s;
+  return PP_OK;
+}
+
+const char* pp_server_last_error(const pp_server* s) { return s ? s->err.c_str() : "null server"; }
+
+}  // extern "C"

@@ -37,10 +37,10 @@ struct PPError {
   } while (0)
 
 enum BufId {
-  B_F, B_TX, B_TY, B_OUT, B_MISC, B_PAIRS, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
+  B_F, B_TX, B_TY, B_OUT, B_MISC, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
-  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_COUNTERS, B_SPLIT, B_REC,
+  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC,
   B_COUNT
 };
 
@@ -61,9 +61,10 @@ struct Last {
 
 constexpr int kMiscInts = 128;
 // misc layout: [0] flags, [1] source count, [2] scratch total, [3] level work items,
-// [4..9] cell-list and interaction-list totals, [32..32+D+2] level starts of the tree.
+// [4..9] cell-list and interaction-list totals, [16..17] near-field pair count (u64),
+// [32..32+D+2] level starts of the tree.
 constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7,
-              M_NP2P = 8, M_NITEMS = 9, M_LS = 32;
+              M_NP2P = 8, M_NITEMS = 9, M_PAIRS = 16, M_LS = 32;
 
 }  // namespace
 
@@ -202,9 +203,8 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
 
   int* misc = ensure<int>(c, B_MISC, kMiscInts);
   // one scratch size for every prefix sum of the solve (tiles, cells, lists, targets)
-  unsigned long long* pairs = ensure<unsigned long long>(c, B_PAIRS, 1);
+  unsigned long long* pairs = (unsigned long long*)(misc + M_PAIRS);  // 8-byte aligned slot
   fill_i32(misc, 0, kMiscInts, s);
-  fill_i32((int*)pairs, 0, 2, s);
 
   const int64_t ntiles = ingest_num_tiles(k);
   int64_t geo = 0;
@@ -309,7 +309,6 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   int* p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
   if (!direct) {
     lists_pass(tv, rec, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, misc + M_FLAGS, s);
-    p2p_pair_count(tv, tleaves, ntl, op2p, cp2p, p2p_src, pairs, s);
   }
   int2* items = ensure<int2>(c, B_ITEMS, nitems);
   p2p_chunks_emit(tv, tleaves, ntl, choff, items, s);
@@ -333,11 +332,15 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
     double2* mp = ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
     double2* loc = ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
     double2* own = ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
-    int* counters = ensure<int>(c, B_COUNTERS, ncells);
     far = ensure<double>(c, B_FAR, m);
     mark(PP_PHASE_P2M);
-    upward(tv, sleaves, nsl, src4, sw, p, mp, counters, s);  // P2M and the M2M recursion, fused
+    p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
     mark(PP_PHASE_M2M);
+    // the recursion from the finest level up, three levels per launch
+    for (int top = depth - 1; top >= 0; top -= 3) {
+      const int L = std::max(top - 2, 0);
+      m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
+    }
     mark(PP_PHASE_M2L);
     m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, own, s);
     mark(PP_PHASE_L2L);
@@ -368,6 +371,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   pa.rel32 = rel32;
   pa.rel64 = rel64;
   pa.nparts = nparts;
+  pa.pairs = pairs;
   pa.m = m;
   pa.near_sum = near;
   pa.leaf_wnear = wnear;
@@ -378,7 +382,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS,
            out_d, s);
   mark(12);
-  readback(c, misc, 0, 1, s);
+  readback(c, misc, 0, M_PAIRS + 2, s);
   check_flags(c.pinned[M_FLAGS]);
   if (c.profiling) {
     for (int i = 0; i < 12; ++i) {
@@ -394,12 +398,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
     HIPCHK(hipStreamSynchronize(s));
   }
   unsigned long long npairs = 0;
-  if (!direct) {
-    HIPCHK(hipMemcpyAsync(&npairs, pairs, sizeof(npairs), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-  } else {
-    npairs = (unsigned long long)N * (unsigned long long)m;
-  }
+  std::memcpy(&npairs, c.pinned + M_PAIRS, sizeof(npairs));
 
   c.stats.depth = depth;
   c.stats.ncells = ncells;

@@ -306,3 +306,78 @@ WORKLOADS = {
     "band2048": _band2048,
     "envelope4096": _envelope4096,
 }
+
+
+def vortex_source_device(g: GridSpec, seed, n_vortices: int = 64, rho: float = 1.0, device="cuda"):
+    """``vortex_source`` evaluated with torch in FP64 on a device (same parameters and formulas).
+
+    Used where many fields are needed quickly (the serving stream); values agree
+    with the NumPy version to rounding.  Returns a (ny, nx) float64 tensor.
+    """
+    import torch
+
+    centres, gamma, rc = lamb_oseen_params(seed, n_vortices)
+    i = torch.arange(g.nx, dtype=torch.float64, device=device)
+    j = torch.arange(g.ny, dtype=torch.float64, device=device)
+    x = (g.x0 + (i + 0.5) * g.h)[None, :].expand(g.ny, g.nx)
+    y = (g.y0 + (j + 0.5) * g.h)[:, None].expand(g.ny, g.nx)
+    ux = torch.zeros((g.ny, g.nx), dtype=torch.float64, device=device)
+    uy = torch.zeros_like(ux)
+    vx = torch.zeros_like(ux)
+    vy = torch.zeros_like(ux)
+    for (xc, yc), gm, r in zip(centres, gamma, rc):
+        K = float(gm) / (2.0 * math.pi)
+        a = float(r) * float(r)
+        X = x - float(xc)
+        Y = y - float(yc)
+        s = X * X + Y * Y
+        xs = s / a
+        small = xs < 1e-3
+        xsafe = torch.where(small, torch.ones_like(xs), xs)
+        ssafe = torch.where(small, torch.full_like(s, a), s)
+        om = -torch.expm1(-xsafe)
+        gg = om / ssafe
+        gp = (ssafe * torch.exp(-xsafe) / a - om) / (ssafe * ssafe)
+        g_ser = (1.0 - xs / 2.0 + xs * xs / 6.0 - xs ** 3 / 24.0) / a
+        gp_ser = (-0.5 + xs / 3.0 - xs * xs / 8.0 + xs ** 3 / 30.0) / (a * a)
+        gg = torch.where(small, g_ser, gg)
+        gp = torch.where(small, gp_ser, gp)
+        ux += -2.0 * K * X * Y * gp
+        uy += -K * (gg + 2.0 * Y * Y * gp)
+        vx += K * (gg + 2.0 * X * X * gp)
+        vy += 2.0 * K * X * Y * gp
+    return 2.0 * rho * (ux * vy - uy * vx)
+
+
+def serving_requests(n_requests: int = 256, seed: int = 4, device="cuda"):
+    """The serving stream: independent solves of uneven size.
+
+    Request k draws, from PCG64((seed, k)): grid n uniform in {128, 256, 512, 1024}
+    (h = 1/n on the unit square), a fresh Lamb-Oseen field with U{16..128}
+    vortices (field seed (seed, k, 1)), U{1024..8192} targets that are either
+    an ellipse (semi-axes 0.2, 0.05) or a fish surface plus its 2h-lifted copy
+    (random phase), each with probability 1/2.  Parameters p = 12, theta = 0.5,
+    mixed precision.  Returns a list of dicts with device tensors f, tx, ty.
+    """
+    import torch
+
+    out = []
+    for k in range(n_requests):
+        rng = np.random.Generator(np.random.PCG64((seed, k)))
+        n = int(rng.choice([128, 256, 512, 1024]))
+        nv = int(rng.integers(16, 129))
+        m = int(rng.integers(1024, 8193))
+        fish = bool(rng.uniform() < 0.5)
+        phase = float(rng.uniform())
+        g = GridSpec(n, n, 1.0 / n)
+        f = vortex_source_device(g, (seed, k, 1), nv, device=device)
+        if fish:
+            nps = max(1, m // 4)
+            sx, sy, lx, ly = fish_surface_targets(nps, g.h, phase=phase)
+            tx, ty = np.concatenate([sx, lx]), np.concatenate([sy, ly])
+        else:
+            tx, ty = ellipse_targets(m)
+        out.append(dict(k=k, grid=g, f=f, tx=torch.as_tensor(tx, device=device),
+                        ty=torch.as_tensor(ty, device=device), p=12, theta=0.5, precision="mixed",
+                        shape="fish" if fish else "ellipse", vortices=nv))
+    return out
