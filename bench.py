@@ -199,21 +199,23 @@ def main() -> int:
     # the same solve without profiling events, for the record
     s.set_profiling(False)
 
-    log(f"[bench] GPU all-pairs direct sum x{args.direct_steps}")
-    s.direct_grid(f, g.h, tx, ty, out=torch.empty_like(out), precision=args.precision)
-    torch.cuda.synchronize()
-    td0 = time.perf_counter()
-    for _ in range(args.direct_steps):
+    direct_s = None
+    if args.direct_steps > 0:
+        log(f"[bench] GPU all-pairs direct sum x{args.direct_steps}")
         s.direct_grid(f, g.h, tx, ty, out=torch.empty_like(out), precision=args.precision)
-    torch.cuda.synchronize()
-    direct_s = (time.perf_counter() - td0) / args.direct_steps
+        torch.cuda.synchronize()
+        td0 = time.perf_counter()
+        for _ in range(args.direct_steps):
+            s.direct_grid(f, g.h, tx, ty, out=torch.empty_like(out), precision=args.precision)
+        torch.cuda.synchronize()
+        direct_s = (time.perf_counter() - td0) / args.direct_steps
 
     # accuracy on sampled targets against the FP64 oracle
     from oracle import direct as oracle_direct
     rng = np.random.Generator(np.random.PCG64(2024))
     ng = int(w["n_grid_targets"])
     ns = M - ng
-    k_grid = min(args.samples * 3 // 4, ng)
+    k_grid = min(args.samples * 3 // 4, ng) if ns > 0 else min(args.samples, ng)
     k_surf = min(args.samples - k_grid, ns)
     sel_g = rng.choice(ng, k_grid, replace=False) if k_grid else np.zeros(0, int)
     sel_s = ng + rng.choice(ns, k_surf, replace=False) if k_surf else np.zeros(0, int)
@@ -277,8 +279,9 @@ def main() -> int:
                    "p": w["p"], "theta": w["theta"], "leaf_max": 64, "precision": args.precision,
                    "seed": w["seed"], "parallelism": "single GPU"},
         "interactions_per_s": N * M / (ms_per_step * 1e-3),
-        "direct": {"ms_per_solve": direct_s * 1e3, "interactions_per_s": N * M / direct_s,
-                   "speedup_tree_vs_direct": direct_s / (ms_per_step * 1e-3)},
+        "direct": None if direct_s is None else {
+            "ms_per_solve": direct_s * 1e3, "interactions_per_s": N * M / direct_s,
+            "speedup_tree_vs_direct": direct_s / (ms_per_step * 1e-3)},
         "accuracy_vs_oracle": acc,
         "phases_ms": phases,
         "tree": {k: st[k] for k in ("depth", "ncells", "nsrc_leaves", "ntgt_leaves", "n_m2l", "n_p2p_lists",

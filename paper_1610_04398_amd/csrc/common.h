@@ -24,6 +24,7 @@ enum : int {
   kFlagTargetOutside = 4,
   kFlagFrontierOverflow = 8,
   kFlagCellOverflow = 16,
+  kFlagListOverflow = 32,
 };
 
 struct cplx {

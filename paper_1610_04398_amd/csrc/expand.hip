@@ -53,23 +53,26 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
   return {(ix & 1) ? 0.25 : -0.25, (iy & 1) ? 0.25 : -0.25};
 }
 
-// P2M: one wave per source leaf; lanes stride over the leaf's sources and a
-// fixed-order butterfly sums the per-lane powers.
+// P2M: 16 lanes per source leaf (four leaves per wave); lanes stride over the
+// leaf's sources and a fixed-order butterfly over the 16 lanes sums the
+// per-lane powers.
+constexpr int kP2MLanes = 16;
 template <int PM>
 __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
                                              const float4* __restrict__ src4, const double* __restrict__ w64, int p,
                                              double2* __restrict__ mp) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + threadIdx.x / kWave);
-  if (wid >= n) return;
-  const int lane = threadIdx.x % kWave;
-  const int c = sleaves[wid];
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int li = (int)(gtid / kP2MLanes);
+  const int sub = (int)(gtid % kP2MLanes);
+  if (li >= n) return;
+  const int c = sleaves[li];
   const double side = cell_side(t.D, t.lvl[c]);
   const double inv = 1.0 / side;
   cplx acc[PM + 1];
 #pragma unroll
   for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
   const int sb = t.sb[c], se = t.se[c];
-  for (int s = sb + lane; s < se; s += kWave) {
+  for (int s = sb + sub; s < se; s += kP2MLanes) {
     const float4 q = src4[s];
     const double w = w64[s];
     const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
@@ -84,15 +87,16 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
 #pragma unroll
   for (int k = 0; k <= PM; ++k) {
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-      acc[k].x += __shfl_xor(acc[k].x, o, kWave);
-      acc[k].y += __shfl_xor(acc[k].y, o, kWave);
+    for (int o = kP2MLanes / 2; o > 0; o >>= 1) {
+      acc[k].x += __shfl_xor(acc[k].x, o, kP2MLanes);
+      acc[k].y += __shfl_xor(acc[k].y, o, kP2MLanes);
     }
   }
   double2* out = mp + (int64_t)c * (p + 1);
 #pragma unroll
   for (int k = 0; k <= PM; ++k)
-    if (k <= p && lane == k) out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
+    if (k <= p && (k % kP2MLanes) == sub)
+      out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
 }
 
 // One M2M output coefficient: a'_l of a parent from up to four children whose
@@ -121,61 +125,68 @@ __device__ inline cplx m2m_coeff(int l, int nk, const double2* const* ch, const 
   return b;
 }
 
-// M2M for three levels per launch (eq. expandedShift applied recursively from
-// the finest level up).  One workgroup per cell R at level L computes, bottom
-// up, the expansions of R's grandchildren (level L+2), children (L+1) and R
-// itself from the final expansions one level below (global memory), keeping
-// the intermediate levels in LDS.  Leaves keep their P2M expansions.
+// M2M for up to three levels per launch (eq. expandedShift applied
+// recursively from the finest level up).  One workgroup per cell R at level L
+// computes, bottom up, the expansions of R's grandchildren (level L+2),
+// children (L+1) and R itself from the final expansions one level below
+// (global memory), keeping the intermediate levels in LDS.  The subtree's
+// structure is read level by level with one thread per cell.  Leaves keep
+// their P2M expansions.
 constexpr int kM2MThreads = 256;
 __global__ __launch_bounds__(kM2MThreads) void k_m2m3(TreeView t, int c0, int c1, int levels, int p,
                                                        double2* __restrict__ mp) {
-  __shared__ int cells[21];           // [0] = R, [1..4] children, [5..20] grandchildren (4 per child)
+  // slots: [0] = R, [1..4] its children, [5..20] grandchildren (4 per child),
+  // [21..84] the level below the subtree (children of the deepest computed slots)
+  __shared__ int cell[85], kid0[85], nkid[85], hsrc[85], quad[85];
   __shared__ double2 co[21][kMaxP + 1];
-  __shared__ int tmp_child[21], tmp_n[21];
   const int R = c0 + blockIdx.x;
   if (R >= c1) return;
   const int P1 = p + 1;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < 21; ++i) cells[i] = -1;
-    cells[0] = R;
-    for (int i = 0; i < 5; ++i) {
-      const int c = cells[i];
-      if (c < 0) continue;
-      const int k0 = t.child[c], nk = t.nchild[c];
-      for (int q = 0; q < nk; ++q) cells[1 + 4 * i + q] = k0 + q;
+  const int tid = threadIdx.x;
+  // read the subtree one level at a time: slot ranges per depth
+  const int first[5] = {0, 1, 5, 21, 85};
+  for (int d = 0; d <= levels; ++d) {
+    const int lo = first[d], hi = d == levels ? lo + (first[d + 1] - first[d]) : first[d + 1];
+    for (int i = lo + tid; i < hi; i += blockDim.x) {
+      int c = -1;
+      if (d == 0) {
+        c = R;
+      } else {
+        const int par = (d == 1) ? 0 : first[d - 1] + (i - lo) / 4;
+        const int q = (i - lo) % 4;
+        if (cell[par] >= 0 && hsrc[par] && q < nkid[par] && kid0[par] >= 0) c = kid0[par] + q;
+      }
+      cell[i] = c;
+      kid0[i] = c >= 0 ? t.child[c] : -1;
+      nkid[i] = c >= 0 ? t.nchild[c] : 0;
+      hsrc[i] = c >= 0 ? (t.se[c] > t.sb[c]) : 0;
+      quad[i] = c >= 0 ? ((t.ix[c] & 1) | ((t.iy[c] & 1) << 1)) : 0;
     }
-    for (int i = 0; i < 21; ++i) {
-      const int c = cells[i];
-      tmp_child[i] = c >= 0 ? t.child[c] : -1;
-      tmp_n[i] = c >= 0 ? t.nchild[c] : 0;
-      if (c >= 0 && t.se[c] <= t.sb[c]) cells[i] = -1;  // no sources: nothing to expand
-    }
+    __syncthreads();
   }
-  __syncthreads();
-  // level offsets within `cells`: depth 2 -> [5, 21), depth 1 -> [1, 5), depth 0 -> [0, 1)
-  for (int depth = levels - 1; depth >= 0; --depth) {
-    const int b = depth == 2 ? 5 : (depth == 1 ? 1 : 0);
-    const int e = depth == 2 ? 21 : (depth == 1 ? 5 : 1);
-    for (int w = threadIdx.x; w < (e - b) * P1; w += blockDim.x) {
-      const int i = b + w / P1, l = w % P1;
-      const int c = cells[i];
-      if (c < 0) continue;
-      if (tmp_child[i] < 0) {  // a leaf: its P2M expansion is final
+  // compute depths levels-1 .. 0; the children of depth `levels - 1` are the
+  // slots of depth `levels` (memory), the others are LDS slots
+  for (int d = levels - 1; d >= 0; --d) {
+    const int lo = first[d], hi = first[d + 1];
+    for (int w = tid; w < (hi - lo) * P1; w += blockDim.x) {
+      const int i = lo + w / P1, l = w % P1;
+      const int c = cell[i];
+      if (c < 0 || !hsrc[i]) continue;
+      if (kid0[i] < 0) {  // a leaf: its P2M expansion is final
         co[i][l] = mp[(int64_t)c * P1 + l];
         continue;
       }
       const double2* ch[4] = {nullptr, nullptr, nullptr, nullptr};
-      cplx d[4];
-      const int nk = tmp_n[i];
+      cplx dq[4];
+      const int nk = nkid[i];
       for (int q = 0; q < nk; ++q) {
-        const int kid = tmp_child[i] + q;
-        if (t.se[kid] <= t.sb[kid]) continue;
-        d[q] = quadrant_offset(t.ix[kid], t.iy[kid]);
-        // children inside this block's subtree come from LDS, the level below it from memory
-        const int slot = (depth == 0) ? 1 + q : 5 + 4 * (i - 1) + q;
-        ch[q] = (depth < levels - 1) ? &co[slot][0] : mp + (int64_t)kid * P1;
+        const int slot = first[d + 1] + 4 * (i - lo) + q;
+        if (!hsrc[slot]) continue;
+        const int qd = quad[slot];
+        dq[q] = {(qd & 1) ? 0.25 : -0.25, (qd & 2) ? 0.25 : -0.25};
+        ch[q] = (d == levels - 1) ? mp + (int64_t)cell[slot] * P1 : &co[slot][0];
       }
-      const cplx v = m2m_coeff(l, nk, ch, d);
+      const cplx v = m2m_coeff(l, nk, ch, dq);
       co[i][l] = make_double2(v.x, v.y);
       mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
     }
@@ -347,7 +358,8 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
 void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
          hipStream_t s) {
   if (n <= 0) return;
-  PP_DISPATCH(p, k_p2m, (n + 3) / 4, 256, s, t, sleaves, n, src4, w64, p, mp);
+  const unsigned g = (unsigned)(((int64_t)n * kP2MLanes + 255) / 256);
+  PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, src4, w64, p, mp);
 }
 
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s) {

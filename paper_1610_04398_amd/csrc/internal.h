@@ -57,10 +57,12 @@ void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, int* ls, hipStr
 void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
                 const uint32_t* skey, const uint32_t* tkey, int* sp, int4* cr, int* exists, int* off, int* scan_tmp,
                 int* n4_slot, int* total_slot, int* flags, hipStream_t s);
-// Compacted cell lists: source leaves, target leaves, cells with targets
-// (flag3/off3 scratch of 3 * ncells); counts[0..2] receive their lengths.
-void classify_cells(TreeArrays t, int ncells, int* flag3, int* off3, int* scan_tmp, int* total_slot, int* sleaves,
-                    int* tleaves, int* tcells, int* counts, hipStream_t s);
+// Compacted cell lists: source leaves, target leaves, cells with targets, for
+// the *ncells_dev cells of the tree (cap = allocated cells; flag3/off3 scratch
+// of 3 * cap); counts[0..2] receive their lengths.
+void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, int* off3, int* scan_tmp,
+                    int* total_slot, int* n3_slot, int* sleaves, int* tleaves, int* tcells, int* counts,
+                    hipStream_t s);
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
 // cell units, and the FP64 leaf weight.
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
@@ -79,9 +81,14 @@ void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, co
 // (indexed by cell id), pass 1 writes the lists at off_m2l / off_p2p (by cell id).
 // Packed per-cell records used by the traversal (ncells int4).
 void cell_records(TreeView t, int4* rec, hipStream_t s);
+// emit 0: counts only; 1: write at the exact offsets of a count pass;
+// 2: one pass, counts plus lists at cell * cap (kFlagListOverflow if a list
+// is longer than its capacity; its tail is then dropped).
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
-                int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags,
-                hipStream_t s);
+                int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
+                int* flags, hipStream_t s);
+// off_m[c] = c * cap_m, off_p[c] = c * cap_p (CSR view of the fixed-capacity lists).
+void capacity_offsets(int ncells, int cap_m, int cap_p, int* off_m, int* off_p, hipStream_t s);
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
 // P2M of every source leaf (one wave per leaf).
 void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
@@ -102,7 +109,7 @@ void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, con
 // ---- p2p.hip: near field --------------------------------------------------------------
 struct P2PArgs {
   TreeView t;
-  const int* tleaves;   // target leaves (work: one wave per 64-target chunk)
+  const int* tleaves;   // target leaves (work: one wave per leaf and list part)
   int ntleaves;
   const int* list_off;  // per cell id: P2P list begin
   const int* list_cnt;  // and length; null => all source leaves (direct mode)
@@ -116,14 +123,12 @@ struct P2PArgs {
   const double2* rel64;
   int nparts;           // each target chunk's list is split over nparts waves
   int64_t m;            // number of targets
-  unsigned long long* pairs;  // if set, receives the number of (target, source) pairs evaluated
+  long long* pair_counts;     // per wave: (target, source) pairs evaluated (may be null)
+  unsigned long long* pairs;  // if set with pair_counts, receives their sum
   double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r^2 / h^2)
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };
-// Work items (target leaf, first target of a 64-target chunk), built from tleaves.
-void p2p_chunks_count(TreeView t, const int* tleaves, int n, int* cnt, hipStream_t s);
-void p2p_chunks_emit(TreeView t, const int* tleaves, int n, const int* off, int2* items, hipStream_t s);
-void p2p(const P2PArgs& a, const int2* items, int nitems, int fp64, hipStream_t s);
+void p2p(const P2PArgs& a, int fp64, hipStream_t s);
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.

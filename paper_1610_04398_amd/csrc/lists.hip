@@ -14,6 +14,8 @@
 // a time and compact what they emit with ballots, so each cell's lists come out
 // in a fixed order without atomics.  A count pass sizes the lists, an emit pass
 // writes them.
+#include <climits>
+
 #include "blockscan.h"
 #include "internal.h"
 
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
                                                                const int* __restrict__ off_m2l,
                                                                const int* __restrict__ off_p2p,
                                                                int* __restrict__ m2l_src, int* __restrict__ p2p_src,
-                                                               int* __restrict__ flags) {
+                                                               int cap_m, int cap_p, int* __restrict__ flags) {
   __shared__ int front[kListWaves][2][kFrontierCap];
   __shared__ int path[kListWaves][kMaxDepth + 1];
   const int w = threadIdx.x / kWave;
@@ -77,8 +79,11 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   __syncwarp();
   int xl = 0;  // index on the path of the current target cell X
   int nm = 0, np = 0;
-  const int mbase = emit ? off_m2l[A] : 0;
-  const int pbase = emit ? off_p2p[A] : 0;
+  // emit 1: exact offsets from a count pass; emit 2: fixed capacity per cell
+  const int64_t mbase = emit == 1 ? off_m2l[A] : (int64_t)A * cap_m;
+  const int64_t pbase = emit == 1 ? off_p2p[A] : (int64_t)A * cap_p;
+  const int mlim = emit == 2 ? cap_m : INT_MAX;
+  const int plim = emit == 2 ? cap_p : INT_MAX;
   bool overflow = false;
   while (ncur > 0) {
     const int X = path[w][xl];
@@ -107,8 +112,9 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
       const uint64_t bm = __ballot(em2l);
       const uint64_t bp = __ballot(ep2p);
       if (emit) {
-        if (em2l) m2l_src[mbase + nm + __popcll(bm & lt_mask)] = B;
-        if (ep2p) p2p_src[pbase + np + __popcll(bp & lt_mask)] = B;
+        const int im = nm + __popcll(bm & lt_mask), ip = np + __popcll(bp & lt_mask);
+        if (em2l && im < mlim) m2l_src[mbase + im] = B;
+        if (ep2p && ip < plim) p2p_src[pbase + ip] = B;
       }
       nm += __popcll(bm);
       np += __popcll(bp);
@@ -140,7 +146,8 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
     }
   }
   if (overflow && lane == 0) atomicOr(flags, kFlagFrontierOverflow);
-  if (!emit && lane == 0) {
+  if (emit == 2 && (nm > cap_m || np > cap_p) && lane == 0) atomicOr(flags, kFlagListOverflow);
+  if (emit != 1 && lane == 0) {
     cnt_m2l[A] = nm;
     cnt_p2p[A] = np;
   }
@@ -154,12 +161,26 @@ void cell_records(TreeView t, int4* rec, hipStream_t s) {
 }
 
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
-                int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int* flags,
-                hipStream_t s) {
+                int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
+                int* flags, hipStream_t s) {
   if (ntcells <= 0) return;
   k_lists<<<(ntcells + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
       t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
-      flags);
+      cap_m, cap_p, flags);
+}
+
+namespace {
+__global__ void k_capacity_offsets(int n, int cap_m, int cap_p, int* __restrict__ off_m, int* __restrict__ off_p) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  off_m[c] = c * cap_m;
+  off_p[c] = c * cap_p;
+}
+}  // namespace
+
+void capacity_offsets(int ncells, int cap_m, int cap_p, int* off_m, int* off_p, hipStream_t s) {
+  if (ncells <= 0) return;
+  k_capacity_offsets<<<(ncells + 255) / 256, 256, 0, s>>>(ncells, cap_m, cap_p, off_m, off_p);
 }
 
 }  // namespace pp

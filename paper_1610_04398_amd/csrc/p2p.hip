@@ -3,8 +3,8 @@
 // expansion.  Also serves as the all-pairs direct sum when every source leaf
 // is listed for every target leaf.
 //
-// Work item: one wave per (target leaf, 64-target chunk); lane j owns target j
-// of the chunk.  Every lane of a wave needs the same source at the same time,
+// Work item: one wave per (target leaf, part of its source list); lane j owns
+// target j of each 64-target chunk.  Every lane of a wave needs the same source at the same time,
 // so sources are read with wave-uniform addresses (scalar loads, no LDS
 // staging) and each source costs one pass of ~10 VALU instructions over the
 // 64 lanes.
@@ -26,22 +26,6 @@ namespace pp {
 
 namespace {
 constexpr int kP2PWaves = 4;
-
-__global__ void k_chunk_count(TreeView t, const int* __restrict__ tleaves, int n, int* __restrict__ cnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = tleaves[i];
-  cnt[i] = (t.te[c] - t.tb[c] + kWave - 1) / kWave;
-}
-
-__global__ void k_chunk_emit(TreeView t, const int* __restrict__ tleaves, int n, const int* __restrict__ off,
-                             int2* __restrict__ items) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int c = tleaves[i];
-  const int nch = (t.te[c] - t.tb[c] + kWave - 1) / kWave;
-  for (int q = 0; q < nch; ++q) items[off[i] + q] = make_int2(c, q * kWave);
-}
 
 // Kahan step with the group's partial sum y (which already carries -comp).
 __device__ inline void kahan_fold(float y, float& sum, float& comp) {
@@ -85,51 +69,54 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
   }
 }
 
-// Work: wave w handles chunk item w / nparts and the list part w % nparts
-// (entries [part * nb / nparts, (part + 1) * nb / nparts)).  Partial sums go to
+// Work: wave w handles target leaf tleaves[w / nparts] and the list part
+// w % nparts (entries [part * nb / nparts, (part + 1) * nb / nparts)), looping
+// over the leaf's targets 64 at a time.  Partial sums go to
 // near_sum[part * m + k] and leaf_wnear[part * ncells + A] and are added in a
-// fixed order by the finalize step.
+// fixed order by the finalize step; pair_counts[w] receives the number of
+// (target, source) pairs the wave evaluated.
 template <bool DIRECT>
-__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const int2* __restrict__ items, int nitems) {
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a) {
   // wave-uniform work index (keeps all per-item data in scalar registers)
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
-  if (wid >= nitems * a.nparts) return;
+  if (wid >= a.ntleaves * a.nparts) return;
   const int part = wid % a.nparts;
   const int lane = threadIdx.x % kWave;
   const TreeView& t = a.t;
-  const int2 it = items[wid / a.nparts];
-  const int A = it.x;
-  const int k = t.tb[A] + it.y + lane;
-  const bool active = k < t.te[A];
-  const float2 r = active ? a.rel32[k] : make_float2(0.0f, 0.0f);
+  const int A = a.tleaves[wid / a.nparts];
   const int shA = t.D - t.lvl[A];
   const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
   const int nb = DIRECT ? a.nsleaves : a.list_cnt[A];
   const int* lst = DIRECT ? a.sleaves : a.list_src + a.list_off[A];
   const int e0 = (int)((int64_t)part * nb / a.nparts);
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
-  float sum = 0.0f, comp = 0.0f;
-  double wn = 0.0;
-  int64_t nsrc = 0;
-  for (int e = e0; e < e1; ++e) {
-    const int B = lst[e];
-    const int shB = t.D - t.lvl[B];
-    const float tx = r.x + (float)(cax - (t.ix[B] << shB));
-    const float ty = r.y + (float)(cay - (t.iy[B] << shB));
-    const int s0 = t.sb[B], s1 = t.se[B];
-    nsrc += s1 - s0;
-    wn += a.leaf_w[B];
-    if (B == A)
-      p2p32_leaf<true>(a.src4, s0, s1, tx, ty, sum, comp);
-    else
-      p2p32_leaf<false>(a.src4, s0, s1, tx, ty, sum, comp);
+  const int tb = t.tb[A], te = t.te[A];
+  int64_t pairs = 0;
+  for (int chunk = tb; chunk < te; chunk += kWave) {
+    const int k = chunk + lane;
+    const bool active = k < te;
+    const float2 r = active ? a.rel32[k] : make_float2(0.0f, 0.0f);
+    float sum = 0.0f, comp = 0.0f;
+    double wn = 0.0;
+    int64_t nsrc = 0;
+    for (int e = e0; e < e1; ++e) {
+      const int B = lst[e];
+      const int shB = t.D - t.lvl[B];
+      const float tx = r.x + (float)(cax - (t.ix[B] << shB));
+      const float ty = r.y + (float)(cay - (t.iy[B] << shB));
+      const int s0 = t.sb[B], s1 = t.se[B];
+      nsrc += s1 - s0;
+      wn += a.leaf_w[B];
+      if (B == A)
+        p2p32_leaf<true>(a.src4, s0, s1, tx, ty, sum, comp);
+      else
+        p2p32_leaf<false>(a.src4, s0, s1, tx, ty, sum, comp);
+    }
+    if (active) a.near_sum[(int64_t)part * a.m + k] = ((double)sum - (double)comp) * kLn2;
+    if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
+    pairs += (int64_t)min(kWave, te - chunk) * nsrc;
   }
-  if (active) a.near_sum[(int64_t)part * a.m + k] = ((double)sum - (double)comp) * kLn2;
-  if (lane == 0 && it.y == 0) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
-  if (lane == 0 && a.pairs) {
-    const int nact = min(kWave, t.te[A] - (t.tb[A] + it.y));
-    atomicAdd(a.pairs, (unsigned long long)(nact * nsrc));
-  }
+  if (lane == 0 && a.pair_counts) a.pair_counts[wid] = pairs;
 }
 
 template <bool GUARD>
@@ -148,75 +135,81 @@ __device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double*
 }
 
 template <bool DIRECT>
-__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const int2* __restrict__ items, int nitems) {
-  // wave-uniform work index (keeps all per-item data in scalar registers)
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a) {
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
-  if (wid >= nitems * a.nparts) return;
+  if (wid >= a.ntleaves * a.nparts) return;
   const int part = wid % a.nparts;
   const int lane = threadIdx.x % kWave;
   const TreeView& t = a.t;
-  const int2 it = items[wid / a.nparts];
-  const int A = it.x;
-  const int k = t.tb[A] + it.y + lane;
-  const bool active = k < t.te[A];
-  const double2 r = active ? a.rel64[k] : make_double2(0.0, 0.0);
+  const int A = a.tleaves[wid / a.nparts];
   const int shA = t.D - t.lvl[A];
   const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
   const int nb = DIRECT ? a.nsleaves : a.list_cnt[A];
   const int* lst = DIRECT ? a.sleaves : a.list_src + a.list_off[A];
   const int e0 = (int)((int64_t)part * nb / a.nparts);
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
-  double sum = 0.0;
-  double wn = 0.0;
-  int64_t nsrc = 0;
-  for (int e = e0; e < e1; ++e) {
-    const int B = lst[e];
-    const int shB = t.D - t.lvl[B];
-    const double tx = r.x + (double)(cax - (t.ix[B] << shB));
-    const double ty = r.y + (double)(cay - (t.iy[B] << shB));
-    const int s0 = t.sb[B], s1 = t.se[B];
-    nsrc += s1 - s0;
-    wn += a.leaf_w[B];
-    if (B == A)
-      p2p64_leaf<true>(a.src4, a.w64, s0, s1, tx, ty, sum);
-    else
-      p2p64_leaf<false>(a.src4, a.w64, s0, s1, tx, ty, sum);
+  const int tb = t.tb[A], te = t.te[A];
+  int64_t pairs = 0;
+  for (int chunk = tb; chunk < te; chunk += kWave) {
+    const int k = chunk + lane;
+    const bool active = k < te;
+    const double2 r = active ? a.rel64[k] : make_double2(0.0, 0.0);
+    double sum = 0.0;
+    double wn = 0.0;
+    int64_t nsrc = 0;
+    for (int e = e0; e < e1; ++e) {
+      const int B = lst[e];
+      const int shB = t.D - t.lvl[B];
+      const double tx = r.x + (double)(cax - (t.ix[B] << shB));
+      const double ty = r.y + (double)(cay - (t.iy[B] << shB));
+      const int s0 = t.sb[B], s1 = t.se[B];
+      nsrc += s1 - s0;
+      wn += a.leaf_w[B];
+      if (B == A)
+        p2p64_leaf<true>(a.src4, a.w64, s0, s1, tx, ty, sum);
+      else
+        p2p64_leaf<false>(a.src4, a.w64, s0, s1, tx, ty, sum);
+    }
+    if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
+    if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
+    pairs += (int64_t)min(kWave, te - chunk) * nsrc;
   }
-  if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
-  if (lane == 0 && it.y == 0) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
-  if (lane == 0 && a.pairs) {
-    const int nact = min(kWave, t.te[A] - (t.tb[A] + it.y));
-    atomicAdd(a.pairs, (unsigned long long)(nact * nsrc));
+  if (lane == 0 && a.pair_counts) a.pair_counts[wid] = pairs;
+}
+
+// Sum of the per-wave pair counts (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void k_sum_pairs(const long long* __restrict__ v, int n,
+                                                    unsigned long long* __restrict__ out) {
+  __shared__ long long part[1024];
+  long long acc = 0;
+  for (int i = threadIdx.x; i < n; i += 1024) acc += v[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = (unsigned long long)part[0];
 }
 }  // namespace
 
-void p2p_chunks_count(TreeView t, const int* tleaves, int n, int* cnt, hipStream_t s) {
-  if (n <= 0) return;
-  k_chunk_count<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, cnt);
-}
-
-void p2p_chunks_emit(TreeView t, const int* tleaves, int n, const int* off, int2* items, hipStream_t s) {
-  if (n <= 0) return;
-  k_chunk_emit<<<(n + 255) / 256, 256, 0, s>>>(t, tleaves, n, off, items);
-}
-
-void p2p(const P2PArgs& a, const int2* items, int nitems, int fp64, hipStream_t s) {
-  if (nitems <= 0) return;
-  const int64_t waves = (int64_t)nitems * a.nparts;
+void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
+  const int64_t waves = (int64_t)a.ntleaves * a.nparts;
+  if (waves <= 0) return;
   const unsigned g = (unsigned)((waves + kP2PWaves - 1) / kP2PWaves);
   const bool direct = a.list_cnt == nullptr;
   if (fp64) {
     if (direct)
-      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a);
     else
-      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a);
   } else {
     if (direct)
-      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a);
     else
-      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a, items, nitems);
+      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a);
   }
+  if (a.pair_counts && a.pairs) k_sum_pairs<<<1, 1024, 0, s>>>(a.pair_counts, (int)waves, a.pairs);
 }
 
 }  // namespace pp

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -40,7 +41,7 @@ enum BufId {
   B_F, B_TX, B_TY, B_OUT, B_MISC, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
-  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC,
+  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_COUNT
 };
 
@@ -70,7 +71,10 @@ constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5
 
 struct pp_ctx {
   int device = 0;
-  int p2p_parts = 2;  // near-field list split per target chunk (PP_P2P_PARTS overrides, 1..8)
+  int p2p_parts = 4;  // near-field list split per target leaf (PP_P2P_PARTS overrides, 1..8)
+  int cap_m2l = 128;  // per-cell list capacities of the one-pass lists (doubled on overflow)
+  int cap_p2p = 64;
+  bool exact_lists = false;  // PP_EXACT_LISTS=1 forces the two-pass lists
   bool profiling = false;
   hipEvent_t ev[13] = {};
   uint64_t budget = 0;
@@ -177,8 +181,14 @@ void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const doub
   if (prm->self_mode != PP_SELF_SKIP && prm->self_mode != PP_SELF_CELLAVG) throw PPError{PP_ERR_ARG, "unknown self mode"};
 }
 
-pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
-                    int64_t m, const double* tx, const double* ty, const pp_params& prm, double* p_out,
+// One solve.  Two host round trips: after the tree (its level starts and the
+// cell-list counts size the later launches) and at the end (flags, statistics).
+// `exact_lists` selects the two-pass interaction lists (count, scan, emit);
+// otherwise the lists are written in one pass into a fixed capacity per cell,
+// and a list that does not fit makes the solve report kFlagListOverflow (the
+// caller then repeats it with exact lists).
+pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_t ny, double x0, double y0, double h,
+                    const double* f, int64_t m, const double* tx, const double* ty, const pp_params& prm, double* p_out,
                     hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
   HIPCHK(hipSetDevice(c.device));
@@ -190,6 +200,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   const int g = std::gcd((int)std::lround(prm.theta * 1000.0), 1000);
   const int num = (int)std::lround(prm.theta * 1000.0) / g, den = 1000 / g;
   const bool mixed = prm.precision == PP_MIXED;
+  const int lm = prm.leaf_max;
 
   auto mark = [&](int i) {
     if (c.profiling) HIPCHK(hipEventRecord(c.ev[i], s));
@@ -202,16 +213,17 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   double* out_d = out_on_device ? p_out : ensure<double>(c, B_OUT, m);
 
   int* misc = ensure<int>(c, B_MISC, kMiscInts);
-  // one scratch size for every prefix sum of the solve (tiles, cells, lists, targets)
   unsigned long long* pairs = (unsigned long long*)(misc + M_PAIRS);  // 8-byte aligned slot
   fill_i32(misc, 0, kMiscInts, s);
 
+  // capacities from the grid size (the source count is only known on the device)
   const int64_t ntiles = ingest_num_tiles(k);
   int64_t geo = 0;
   for (int l = 0; l <= D; ++l) geo += (int64_t)1 << (2 * l);
-  const int64_t cap_bound = std::min<int64_t>(geo, 1 + 4 * (int64_t)std::max(D, 1) *
-                                                           (ngrid / (prm.leaf_max + 1) + m / (prm.leaf_max + 1) + 1)) + 1;
-  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max<int64_t>({ntiles, cap_bound, m, 1})));
+  const int64_t per_level = 4 * (ngrid / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
+  const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
+  if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
+  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max<int64_t>({ntiles, 4 * per_level, 3 * cap, m, 1})));
 
   // ---- ingest: sources in Morton order (no sort needed for a grid) ----
   int* tile = ensure<int>(c, B_TILE, ntiles);
@@ -229,14 +241,9 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   target_keys(tx_d, ty_d, m, x0, y0, h, k, tkey, tperm, misc + M_FLAGS, s);
   radix_sort_pairs(tkey, tperm, ensure<uint32_t>(c, B_TKEY2, m), ensure<int>(c, B_TPERM2, m), m, 2 * k,
                    ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(m)), s);
-  readback(c, misc, 0, 2, s);
-  check_flags(c.pinned[M_FLAGS]);
-  const int64_t N = c.pinned[M_NSRC];
 
   // ---- tree, top down: one launch group per level, no host round trip ----
   mark(PP_PHASE_TREE);
-  const int64_t cap = std::min<int64_t>(geo, 1 + 4 * (int64_t)std::max(D, 1) *
-                                                     (N / (prm.leaf_max + 1) + m / (prm.leaf_max + 1) + 1)) + 1;
   TreeArrays ta{ensure<int>(c, B_LVL, cap),   ensure<int>(c, B_IX, cap),     ensure<int>(c, B_IY, cap),
                 ensure<int>(c, B_SB, cap),    ensure<int>(c, B_SE, cap),     ensure<int>(c, B_TB, cap),
                 ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
@@ -244,21 +251,28 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   int* ls_d = misc + M_LS;
   tree_init_root(ta, misc + M_NSRC, (int)m, ls_d, s);
   {
-    // the widest level: bounded by 4^l and by the cell capacity
-    const int64_t wmax = std::min<int64_t>(cap, (int64_t)1 << std::min(2 * D, 40));
+    const int64_t wmax = std::min<int64_t>(cap, per_level);
     int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
     int* sp = ensure<int>(c, B_SPLIT, 6 * wmax);
     int* ex = ensure<int>(c, B_CNT, 4 * wmax);
     int* off = ensure<int>(c, B_OFF, 4 * wmax);
     int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(4 * wmax));
     for (int l = 0; l <= D; ++l) {
-      const int64_t lmax = std::min<int64_t>(cap, (int64_t)1 << std::min(2 * l, 40));
-      tree_level(ta, ls_d, l, D, prm.leaf_max, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4,
-                 misc + M_TOT, misc + M_FLAGS, s);
+      const int64_t lmax = std::min<int64_t>(wmax, (int64_t)1 << std::min(2 * l, 40));
+      tree_level(ta, ls_d, l, D, lm, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4, misc + M_TOT,
+                 misc + M_FLAGS, s);
     }
   }
+  // cell lists over the whole tree (its size is the last level start, on the device)
+  int* sleaves = ensure<int>(c, B_SLEAF, cap);
+  int* tleaves = ensure<int>(c, B_TLEAF, cap);
+  int* tcells = ensure<int>(c, B_TCELL, cap);
+  classify_cells(ta, ls_d + D + 1, (int)cap, ensure<int>(c, B_FLAG, 3 * cap), ensure<int>(c, B_FOFF, 3 * cap),
+                 ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(3 * cap)), misc + M_TOT, misc + M_N4, sleaves,
+                 tleaves, tcells, misc + M_NSL, s);
   readback(c, misc, 0, M_LS + D + 2, s);
   check_flags(c.pinned[M_FLAGS]);
+  const int64_t N = c.pinned[M_NSRC];
   const int* ls_h = c.pinned + M_LS;
   std::vector<int> lstart = {ls_h[0], ls_h[1]};  // level l holds cells [lstart[l], lstart[l+1])
   for (int l = 1; l <= D; ++l) {
@@ -267,51 +281,50 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   }
   const int ncells = lstart.back();
   const int depth = (int)lstart.size() - 2;
+  const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
-  // ---- cell lists: source leaves, target leaves, cells with targets ----
+  // ---- interaction lists ----
   mark(PP_PHASE_LISTS);
-  int* sleaves = ensure<int>(c, B_SLEAF, ncells);
-  int* tleaves = ensure<int>(c, B_TLEAF, ncells);
-  int* tcells = ensure<int>(c, B_TCELL, ncells);
-  classify_cells(ta, ncells, ensure<int>(c, B_FLAG, 3 * (int64_t)ncells), ensure<int>(c, B_FOFF, 3 * (int64_t)ncells),
-                 ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(3 * (int64_t)ncells)), misc + M_TOT, sleaves, tleaves,
-                 tcells, misc + M_NSL, s);
-
-  // ---- interaction lists and near-field work items ----
-  readback(c, misc, M_NSL, 3, s);
-  const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
   int* cm2l = ensure<int>(c, B_CM2L, ncells);
   int* om2l = ensure<int>(c, B_OM2L, ncells);
   int* cp2p = ensure<int>(c, B_CP2P, ncells);
   int* op2p = ensure<int>(c, B_OP2P, ncells);
-  int4* rec = ensure<int4>(c, B_REC, ncells);
-  int* chcnt = ensure<int>(c, B_CHCNT, std::max(ntl, 1));
-  int* choff = ensure<int>(c, B_CHOFF, std::max(ntl, 1));
+  int* m2l_src = nullptr;
+  int* p2p_src = nullptr;
+  int64_t n_m2l = 0, n_p2pl = 0;
   if (!direct) {
     fill_i32(cm2l, 0, ncells, s);
     fill_i32(cp2p, 0, ncells, s);
+    int4* rec = ensure<int4>(c, B_REC, ncells);
     cell_records(tv, rec, s);
-    lists_pass(tv, rec, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, misc + M_FLAGS, s);
-    int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
-    scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
-    scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
+    if (exact_lists) {
+      lists_pass(tv, rec, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, 0, 0,
+                 misc + M_FLAGS, s);
+      int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
+      scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
+      scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
+      readback(c, misc, 0, 16, s);
+      check_flags(c.pinned[M_FLAGS]);
+      n_m2l = c.pinned[M_NM2L];
+      n_p2pl = c.pinned[M_NP2P];
+      m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
+      p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
+      lists_pass(tv, rec, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, 0, 0, misc + M_FLAGS,
+                 s);
+    } else {
+      m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * c.cap_m2l);
+      p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * c.cap_p2p);
+      capacity_offsets(ncells, c.cap_m2l, c.cap_p2p, om2l, op2p, s);
+      lists_pass(tv, rec, tcells, ntc, num, den, 2, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, c.cap_m2l, c.cap_p2p,
+                 misc + M_FLAGS, s);
+      // list totals for the statistics, read with the final flags
+      int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
+      int* tmp = ensure<int>(c, B_FOFF, ncells);
+      scan_exclusive(cm2l, tmp, ncells, scan, misc + M_NM2L, s);
+      scan_exclusive(cp2p, tmp, ncells, scan, misc + M_NP2P, s);
+    }
   }
-  p2p_chunks_count(tv, tleaves, ntl, chcnt, s);
-  scan_exclusive(chcnt, choff, ntl, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max(ntl, 1))),
-                 misc + M_NITEMS, s);
-  readback(c, misc, 0, 16, s);
-  check_flags(c.pinned[M_FLAGS]);
-  const int n_m2l = direct ? 0 : c.pinned[M_NM2L];
-  const int n_p2pl = direct ? 0 : c.pinned[M_NP2P];
-  const int nitems = c.pinned[M_NITEMS];
-  int* m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
-  int* p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
-  if (!direct) {
-    lists_pass(tv, rec, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, misc + M_FLAGS, s);
-  }
-  int2* items = ensure<int2>(c, B_ITEMS, nitems);
-  p2p_chunks_emit(tv, tleaves, ntl, choff, items, s);
 
   // ---- per-leaf packing ----
   mark(PP_PHASE_PACK);
@@ -355,6 +368,7 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   const int nparts = c.p2p_parts;
   double* near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
   double* wnear = ensure<double>(c, B_WNEAR, (int64_t)nparts * ncells);
+  long long* pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
   mark(PP_PHASE_P2P);
   P2PArgs pa{};
   pa.t = tv;
@@ -371,11 +385,12 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   pa.rel32 = rel32;
   pa.rel64 = rel64;
   pa.nparts = nparts;
-  pa.pairs = pairs;
   pa.m = m;
+  pa.pair_counts = pcount;
+  pa.pairs = pairs;
   pa.near_sum = near;
   pa.leaf_wnear = wnear;
-  p2p(pa, items, nitems, mixed ? 0 : 1, s);
+  p2p(pa, mixed ? 0 : 1, s);
 
   // ---- finalize ----
   mark(PP_PHASE_FINALIZE);
@@ -383,7 +398,9 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
            out_d, s);
   mark(12);
   readback(c, misc, 0, M_PAIRS + 2, s);
-  check_flags(c.pinned[M_FLAGS]);
+  const int flags = c.pinned[M_FLAGS];
+  if (flags & kFlagListOverflow) return PP_ERR_LIMIT;  // nothing written; repeat with exact lists
+  check_flags(flags);
   if (c.profiling) {
     for (int i = 0; i < 12; ++i) {
       float ms = 0.f;
@@ -399,6 +416,10 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   }
   unsigned long long npairs = 0;
   std::memcpy(&npairs, c.pinned + M_PAIRS, sizeof(npairs));
+  if (!direct && !exact_lists) {
+    n_m2l = c.pinned[M_NM2L];
+    n_p2pl = c.pinned[M_NP2P];
+  }
 
   c.stats.depth = depth;
   c.stats.ncells = ncells;
@@ -416,8 +437,8 @@ pp_status run_solve(pp_ctx& c, bool direct, int32_t nx, int32_t ny, double x0, d
   c.last.m = m;
   c.last.ncells = ncells;
   c.last.p = p;
-  c.last.n_m2l = n_m2l;
-  c.last.n_p2p = n_p2pl;
+  c.last.n_m2l = exact_lists ? n_m2l : (int64_t)ncells * c.cap_m2l;
+  c.last.n_p2p = exact_lists ? n_p2pl : (int64_t)ncells * c.cap_p2p;
   c.last.has_expansions = !direct;
   c.last.nparts = nparts;
   return PP_OK;
@@ -433,7 +454,14 @@ pp_status guard(pp_ctx* c, bool direct, int32_t nx, int32_t ny, double x0, doubl
   try {
     validate(nx, ny, x0, y0, h, f, m, tx, ty, prm, p_out);
     if (m == 0) return PP_OK;
-    pp_status st = run_solve(*c, direct, nx, ny, x0, y0, h, f, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+    pp_status st = run_solve(*c, direct, c->exact_lists, nx, ny, x0, y0, h, f, m, tx, ty, *prm, p_out,
+                             (hipStream_t)stream);
+    if (st == PP_ERR_LIMIT) {
+      // a list outgrew its per-cell capacity: make room for next time and redo this solve exactly
+      c->cap_m2l *= 2;
+      c->cap_p2p *= 2;
+      st = run_solve(*c, direct, true, nx, ny, x0, y0, h, f, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+    }
     c->err.clear();
     return st;
   } catch (const PPError& e) {
@@ -464,6 +492,14 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   pp_ctx* c = new pp_ctx();
   c->device = device;
   if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
+  if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p" initial capacities
+    int a = 0, b = 0;
+    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && b > 0) {
+      c->cap_m2l = a;
+      c->cap_p2p = b;
+    }
+  }
   c->budget = hbm_budget_bytes;
   if (hipHostMalloc((void**)&c->pinned, kMiscInts * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     delete c;

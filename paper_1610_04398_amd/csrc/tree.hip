@@ -156,9 +156,12 @@ __global__ void k_level_link(TreeArrays t, int* __restrict__ ls, int level, cons
 }
 
 // flag[kind * n + c] for kind 0 = leaf with sources, 1 = leaf with targets,
-// 2 = any cell with targets.
-__global__ void k_classify(TreeArrays t, int n, int* __restrict__ flag) {
+// 2 = any cell with targets; the cell count n is read on the device (the
+// tree's last level start) and 3n is left in *n3 for the scan.
+__global__ void k_classify(TreeArrays t, const int* __restrict__ n_dev, int* __restrict__ flag, int* __restrict__ n3) {
+  const int n = *n_dev;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) *n3 = 3 * n;
   if (c >= n) return;
   const bool leaf = t.child[c] < 0;
   const bool hs = t.se[c] > t.sb[c];
@@ -168,14 +171,16 @@ __global__ void k_classify(TreeArrays t, int n, int* __restrict__ flag) {
   flag[2 * n + c] = ht ? 1 : 0;
 }
 
-__global__ void k_classify_scatter(int n, const int* __restrict__ flag, const int* __restrict__ off,
-                                   const int* __restrict__ total, int* __restrict__ out0, int* __restrict__ out1,
-                                   int* __restrict__ out2, int* __restrict__ counts) {
+__global__ void k_classify_scatter(const int* __restrict__ n_dev, const int* __restrict__ flag,
+                                   const int* __restrict__ off, const int* __restrict__ total,
+                                   int* __restrict__ out0, int* __restrict__ out1, int* __restrict__ out2,
+                                   int* __restrict__ counts) {
+  const int n = *n_dev;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c == 0) {
-    counts[0] = off[n] - off[0];
-    counts[1] = off[2 * n] - off[n];
-    counts[2] = *total - off[2 * n];
+    counts[0] = n > 0 ? off[n] - off[0] : 0;
+    counts[1] = n > 0 ? off[2 * n] - off[n] : 0;
+    counts[2] = n > 0 ? *total - off[2 * n] : 0;
   }
   if (c >= n) return;
   if (flag[c]) out0[off[c] - off[0]] = c;
@@ -286,13 +291,14 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
   k_level_link<<<g, 256, 0, s>>>(t, ls, level, cr, exists, off, total_slot, cap, flags);
 }
 
-void classify_cells(TreeArrays t, int ncells, int* flag3, int* off3, int* scan_tmp, int* total_slot, int* sleaves,
-                    int* tleaves, int* tcells, int* counts, hipStream_t s) {
-  if (ncells <= 0) return;
-  const unsigned g = (unsigned)((ncells + 255) / 256);
-  k_classify<<<g, 256, 0, s>>>(t, ncells, flag3);
-  scan_exclusive(flag3, off3, 3 * (int64_t)ncells, scan_tmp, total_slot, s);
-  k_classify_scatter<<<g, 256, 0, s>>>(ncells, flag3, off3, total_slot, sleaves, tleaves, tcells, counts);
+void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, int* off3, int* scan_tmp,
+                    int* total_slot, int* n3_slot, int* sleaves, int* tleaves, int* tcells, int* counts,
+                    hipStream_t s) {
+  if (cap <= 0) return;
+  const unsigned g = (unsigned)((cap + 255) / 256);
+  k_classify<<<g, 256, 0, s>>>(t, ncells_dev, flag3, n3_slot);
+  scan_exclusive_dev(flag3, off3, n3_slot, 3 * (int64_t)cap, scan_tmp, total_slot, s);
+  k_classify_scatter<<<g, 256, 0, s>>>(ncells_dev, flag3, off3, total_slot, sleaves, tleaves, tcells, counts);
 }
 
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,

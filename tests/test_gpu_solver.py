@@ -283,3 +283,20 @@ def test_envelope4096_sampled(solver):
     assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-4, errs
     st = solver.stats()
     assert st["nsources"] == int(np.count_nonzero(w["f"]))
+
+
+def test_list_modes_agree_bitwise(solver, monkeypatch):
+    """One-pass lists (fixed capacity), their overflow fallback and two-pass lists give identical bits."""
+    import paper_1610_04398_amd as pp
+    f, h, tx, ty = _case_random(11, n=64, nt=900)
+    ref = solver.solve_grid(f, h, tx, ty, p=10, theta=0.5, leaf_max=16, precision="mixed")
+    for env in ({"PP_EXACT_LISTS": "1"}, {"PP_LIST_CAPS": "3,2"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        s2 = pp.Solver(0)
+        got = s2.solve_grid(f, h, tx, ty, p=10, theta=0.5, leaf_max=16, precision="mixed")
+        again = s2.solve_grid(f, h, tx, ty, p=10, theta=0.5, leaf_max=16, precision="mixed")
+        s2.close()
+        for k in env:
+            monkeypatch.delenv(k)
+        assert np.array_equal(got, ref) and np.array_equal(again, ref), env
