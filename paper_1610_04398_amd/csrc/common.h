@@ -25,6 +25,7 @@ enum : int {
   kFlagFrontierOverflow = 8,
   kFlagCellOverflow = 16,
   kFlagListOverflow = 32,
+  kFlagBadIndex = 64,  // a list entry outside the tree (an internal error); the entry is skipped
 };
 
 struct cplx {

@@ -201,7 +201,8 @@ template <int PM, int G>
 __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__ tcells, int n,
                                              const int* __restrict__ off, const int* __restrict__ cnt,
                                              const int* __restrict__ src, int p, double lnh,
-                                             const double2* __restrict__ mp, double2* __restrict__ loc) {
+                                             const double2* __restrict__ mp, double2* __restrict__ loc,
+                                             int* __restrict__ flags) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int gi = (int)(gtid / G);
   const int sub = (int)(gtid % G);
@@ -217,6 +218,10 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
   const int e0 = off[A], ne = cnt[A];
   for (int e = sub; e < ne; e += G) {
     const int B = src[e0 + e];
+    if ((unsigned)B >= (unsigned)t.ncells) {
+      atomicOr(flags, kFlagBadIndex);
+      continue;
+    }
     const int lB = t.lvl[B];
     const double sB = cell_side(D, lB);
     const cplx z0 = {(t.ix[B] + 0.5) * sB - cax, (t.iy[B] + 0.5) * sB - cay};
@@ -368,21 +373,21 @@ void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipS
 }
 
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
-         double h, const double2* mp, double2* loc, hipStream_t s) {
+         double h, const double2* mp, double2* loc, int* flags, hipStream_t s) {
   if (n <= 0) return;
   constexpr int G = 32;
   const unsigned g = (unsigned)(((int64_t)n * G + 255) / 256);
   const double lnh = log(h);
   if (p <= 4)
-    k_m2l<4, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+    k_m2l<4, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else if (p <= 8)
-    k_m2l<8, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+    k_m2l<8, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else if (p <= 12)
-    k_m2l<12, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+    k_m2l<12, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else if (p <= 16)
-    k_m2l<16, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+    k_m2l<16, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else
-    k_m2l<20, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc);
+    k_m2l<20, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
 }
 
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s) {

@@ -97,7 +97,7 @@ void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double
 // [c0, c1): one workgroup per cell computes its subtree bottom up.
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
-         double h, const double2* mp, double2* loc, hipStream_t s);
+         double h, const double2* mp, double2* loc, int* flags, hipStream_t s);
 // Final local expansion of every cell with targets from its own M2L local
 // (`own`) and its ancestors' (exact L2L shifts), one launch.
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s);
@@ -124,6 +124,7 @@ struct P2PArgs {
   int nparts;           // each target chunk's list is split over nparts waves
   int64_t m;            // number of targets
   long long* pair_counts;     // per wave: (target, source) pairs evaluated (may be null)
+  int* flags;                 // error flags (kFlagBadIndex for a list entry outside the tree)
   unsigned long long* pairs;  // if set with pair_counts, receives their sum
   double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r^2 / h^2)
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights

@@ -148,8 +148,11 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   if (overflow && lane == 0) atomicOr(flags, kFlagFrontierOverflow);
   if (emit == 2 && (nm > cap_m || np > cap_p) && lane == 0) atomicOr(flags, kFlagListOverflow);
   if (emit != 1 && lane == 0) {
-    cnt_m2l[A] = nm;
-    cnt_p2p[A] = np;
+    // in the capacity layout a list never reaches past its cell's slots: an
+    // overflowing list is cut at the capacity (and flagged for an exact re-run),
+    // so the kernels that read it stay inside the allocation
+    cnt_m2l[A] = emit == 2 ? min(nm, cap_m) : nm;
+    cnt_p2p[A] = emit == 2 ? min(np, cap_p) : np;
   }
 }
 

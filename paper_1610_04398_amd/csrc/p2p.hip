@@ -101,6 +101,10 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a) {
     int64_t nsrc = 0;
     for (int e = e0; e < e1; ++e) {
       const int B = lst[e];
+      if ((unsigned)B >= (unsigned)t.ncells) {
+        if (lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
+        continue;
+      }
       const int shB = t.D - t.lvl[B];
       const float tx = r.x + (float)(cax - (t.ix[B] << shB));
       const float ty = r.y + (float)(cay - (t.iy[B] << shB));
@@ -159,6 +163,10 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a) {
     int64_t nsrc = 0;
     for (int e = e0; e < e1; ++e) {
       const int B = lst[e];
+      if ((unsigned)B >= (unsigned)t.ncells) {
+        if (lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
+        continue;
+      }
       const int shB = t.D - t.lvl[B];
       const double tx = r.x + (double)(cax - (t.ix[B] << shB));
       const double ty = r.y + (double)(cay - (t.iy[B] << shB));

@@ -159,6 +159,7 @@ void check_flags(int flags) {
   if (flags & kFlagTargetOutside) throw PPError{PP_ERR_DOMAIN, "a target lies outside the root square"};
   if (flags & kFlagFrontierOverflow) throw PPError{PP_ERR_LIMIT, "traversal frontier exceeded its capacity"};
   if (flags & kFlagCellOverflow) throw PPError{PP_ERR_LIMIT, "cell capacity exceeded"};
+  if (flags & kFlagBadIndex) throw PPError{PP_ERR_LIMIT, "internal index check failed"};
   if (flags) throw PPError{PP_ERR_DEVICE, "unknown kernel flag"};
 }
 
@@ -355,7 +356,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
       m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
     }
     mark(PP_PHASE_M2L);
-    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, own, s);
+    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, own, misc + M_FLAGS, s);
     mark(PP_PHASE_L2L);
     downward(tv, tcells, ntc, p, own, loc, s);
     mark(PP_PHASE_L2P);
@@ -387,6 +388,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   pa.nparts = nparts;
   pa.m = m;
   pa.pair_counts = pcount;
+  pa.flags = misc + M_FLAGS;
   pa.pairs = pairs;
   pa.near_sum = near;
   pa.leaf_wnear = wnear;

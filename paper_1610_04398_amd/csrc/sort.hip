@@ -1,11 +1,12 @@
-// Stable LSD radix sort of (uint32 Morton key, int32 index) pairs, 8-bit
-// digits.  Used to order the targets along the quadtree's Morton curve; ties
-// keep their input order, so the permutation is unique.
+// Stable LSD radix sort of (uint32 Morton key, int32 index) pairs with digits
+// of up to 9 bits (the 18-bit keys of a 512^2 root take two passes).  Used to
+// order the targets along the quadtree's Morton curve; ties keep their input
+// order, so the permutation is unique.
 //
 // Per digit pass: per-tile digit histograms -> one device-wide exclusive scan
 // of the digit-major histogram table -> stable scatter.  Within a tile the
 // scatter ranks keys round by round (256 keys per round, in thread order),
-// matching equal digits across a wave with eight ballots.
+// matching equal digits across a wave with one ballot per digit bit.
 #include "blockscan.h"
 #include "internal.h"
 
@@ -16,34 +17,41 @@ constexpr int kRsBlock = 256;
 constexpr int kRsItems = 8;
 constexpr int kRsTile = kRsBlock * kRsItems;
 constexpr int kRsWaves = kRsBlock / kWave;
+constexpr int kRsMaxBits = 9;
 
+template <int BITS>
 __global__ __launch_bounds__(kRsBlock) void k_radix_hist(const uint32_t* __restrict__ keys, int n, int shift,
                                                           int nblocks, int* __restrict__ hist) {
-  __shared__ int h[256];
-  h[threadIdx.x] = 0;
+  constexpr int BINS = 1 << BITS;
+  __shared__ int h[BINS];
+  for (int b = threadIdx.x; b < BINS; b += kRsBlock) h[b] = 0;
   __syncthreads();
   const int base = blockIdx.x * kRsTile;
   for (int q = 0; q < kRsItems; ++q) {
     const int i = base + q * kRsBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFF], 1);
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (BINS - 1)], 1);
   }
   __syncthreads();
-  hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  for (int b = threadIdx.x; b < BINS; b += kRsBlock) hist[b * nblocks + blockIdx.x] = h[b];
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                              const int* __restrict__ vin, int n, int shift, int nblocks,
                                                              const int* __restrict__ off, uint32_t* __restrict__ kout,
                                                              int* __restrict__ vout) {
-  __shared__ int goff[256];
-  __shared__ int run[256];
-  __shared__ int wcnt[kRsWaves][256];
+  constexpr int BINS = 1 << BITS;
+  __shared__ int goff[BINS];
+  __shared__ int run[BINS];
+  __shared__ int wcnt[kRsWaves][BINS];
   const int t = threadIdx.x;
   const int lane = t % kWave;
   const int w = t / kWave;
-  goff[t] = off[t * nblocks + blockIdx.x];
-  run[t] = 0;
-  for (int ww = 0; ww < kRsWaves; ++ww) wcnt[ww][t] = 0;
+  for (int b = t; b < BINS; b += kRsBlock) {
+    goff[b] = off[b * nblocks + blockIdx.x];
+    run[b] = 0;
+    for (int ww = 0; ww < kRsWaves; ++ww) wcnt[ww][b] = 0;
+  }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
   const int base = blockIdx.x * kRsTile;
@@ -56,11 +64,11 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __re
       key = kin[i];
       val = vin[i];
     }
-    const int d = (key >> shift) & 0xFF;
-    // lanes holding the same digit (valid lanes only)
+    const int d = (key >> shift) & (BINS - 1);
+    // lanes holding the same digit (valid lanes only), in lane order
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -77,12 +85,14 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __re
       vout[pos] = val;
     }
     __syncthreads();
-    int add = 0;
-    for (int ww = 0; ww < kRsWaves; ++ww) {
-      add += wcnt[ww][t];
-      wcnt[ww][t] = 0;
+    for (int b = t; b < BINS; b += kRsBlock) {
+      int add = 0;
+      for (int ww = 0; ww < kRsWaves; ++ww) {
+        add += wcnt[ww][b];
+        wcnt[ww][b] = 0;
+      }
+      run[b] += add;
     }
-    run[t] += add;
     __syncthreads();
   }
 }
@@ -95,30 +105,48 @@ __global__ void k_copy_pairs(const uint32_t* __restrict__ ks, const int* __restr
     vd[i] = vs[i];
   }
 }
+
+template <int BITS>
+void radix_pass(const uint32_t* ka, const int* va, uint32_t* kb, int* vb, int n, int shift, int nb, int* table,
+                int* scan_tmp, hipStream_t s) {
+  k_radix_hist<BITS><<<nb, kRsBlock, 0, s>>>(ka, n, shift, nb, table);
+  scan_exclusive(table, table, (int64_t)(1 << BITS) * nb, scan_tmp, nullptr, s);
+  k_radix_scatter<BITS><<<nb, kRsBlock, 0, s>>>(ka, va, n, shift, nb, table, kb, vb);
+}
 }  // namespace
 
 size_t radix_temp_ints(int64_t n) {
   const int64_t nb = (n + kRsTile - 1) / kRsTile;
-  const int64_t table = 256 * nb;
+  const int64_t table = (1 << kRsMaxBits) * nb;
   return (size_t)(table + scan_temp_ints(table) + 1);
 }
 
+// Digits of up to 9 bits: the fewest passes that cover `bits`, equal widths.
 void radix_sort_pairs(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int64_t n, int bits, int* temp,
                       hipStream_t s) {
   if (n <= 1 || bits <= 0) return;
   const int nb = (int)((n + kRsTile - 1) / kRsTile);
   int* table = temp;
-  int* scan_tmp = temp + 256 * (int64_t)nb;
+  int* scan_tmp = temp + (1 << kRsMaxBits) * (int64_t)nb;
   uint32_t* ka = keys;
   int* va = vals;
   uint32_t* kb = keys_tmp;
   int* vb = vals_tmp;
-  const int passes = (bits + 7) / 8;
+  const int passes = (bits + kRsMaxBits - 1) / kRsMaxBits;
+  const int width = (bits + passes - 1) / passes;
   for (int ps = 0; ps < passes; ++ps) {
-    const int shift = 8 * ps;
-    k_radix_hist<<<nb, kRsBlock, 0, s>>>(ka, (int)n, shift, nb, table);
-    scan_exclusive(table, table, 256 * (int64_t)nb, scan_tmp, nullptr, s);
-    k_radix_scatter<<<nb, kRsBlock, 0, s>>>(ka, va, (int)n, shift, nb, table, kb, vb);
+    const int shift = width * ps;
+    switch (width) {
+      case 1: radix_pass<1>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 2: radix_pass<2>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 3: radix_pass<3>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 4: radix_pass<4>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 5: radix_pass<5>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 6: radix_pass<6>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 7: radix_pass<7>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      case 8: radix_pass<8>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+      default: radix_pass<9>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
+    }
     uint32_t* tk = ka;
     ka = kb;
     kb = tk;
