@@ -142,6 +142,9 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / sequential solves per second")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the known-size kernel that scales "
+                         "the HBM byte counters of a profile) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -159,6 +162,16 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 1
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 17  # doubles
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}}))
+        return 0
 
     log(f"[bench] generating workload {args.workload}")
     w = G.workload(args.workload)

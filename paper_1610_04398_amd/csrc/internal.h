@@ -130,6 +130,8 @@ struct P2PArgs {
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };
 void p2p(const P2PArgs& a, int fp64, hipStream_t s);
+// Total (target, source) pairs of the last p2p launch into a.pairs.
+void p2p_count_pairs(const P2PArgs& a, hipStream_t s);
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.

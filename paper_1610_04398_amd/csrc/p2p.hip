@@ -75,8 +75,11 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
 // near_sum[part * m + k] and leaf_wnear[part * ncells + A] and are added in a
 // fixed order by the finalize step; pair_counts[w] receives the number of
 // (target, source) pairs the wave evaluated.
+// The source records come in as a separate __restrict__ argument: with no
+// possible aliasing the compiler keeps their wave-uniform loads on the scalar
+// path although the kernel stores partial sums between chunks.
 template <bool DIRECT>
-__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a) {
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const float4* __restrict__ src4) {
   // wave-uniform work index (keeps all per-item data in scalar registers)
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
   if (wid >= a.ntleaves * a.nparts) return;
@@ -92,6 +95,7 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a) {
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   const int tb = t.tb[A], te = t.te[A];
   int64_t pairs = 0;
+  bool bad = false;
   for (int chunk = tb; chunk < te; chunk += kWave) {
     const int k = chunk + lane;
     const bool active = k < te;
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a) {
     for (int e = e0; e < e1; ++e) {
       const int B = lst[e];
       if ((unsigned)B >= (unsigned)t.ncells) {
-        if (lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
+        bad = true;
         continue;
       }
       const int shB = t.D - t.lvl[B];
@@ -112,15 +116,16 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a) {
       nsrc += s1 - s0;
       wn += a.leaf_w[B];
       if (B == A)
-        p2p32_leaf<true>(a.src4, s0, s1, tx, ty, sum, comp);
+        p2p32_leaf<true>(src4, s0, s1, tx, ty, sum, comp);
       else
-        p2p32_leaf<false>(a.src4, s0, s1, tx, ty, sum, comp);
+        p2p32_leaf<false>(src4, s0, s1, tx, ty, sum, comp);
     }
     if (active) a.near_sum[(int64_t)part * a.m + k] = ((double)sum - (double)comp) * kLn2;
     if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
   }
   if (lane == 0 && a.pair_counts) a.pair_counts[wid] = pairs;
+  if (bad && lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
 }
 
 template <bool GUARD>
@@ -139,7 +144,8 @@ __device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double*
 }
 
 template <bool DIRECT>
-__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a) {
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const float4* __restrict__ src4,
+                                                             const double* __restrict__ w64) {
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
   if (wid >= a.ntleaves * a.nparts) return;
   const int part = wid % a.nparts;
@@ -154,6 +160,7 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a) {
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   const int tb = t.tb[A], te = t.te[A];
   int64_t pairs = 0;
+  bool bad = false;
   for (int chunk = tb; chunk < te; chunk += kWave) {
     const int k = chunk + lane;
     const bool active = k < te;
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a) {
     for (int e = e0; e < e1; ++e) {
       const int B = lst[e];
       if ((unsigned)B >= (unsigned)t.ncells) {
-        if (lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
+        bad = true;
         continue;
       }
       const int shB = t.D - t.lvl[B];
@@ -174,15 +181,16 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a) {
       nsrc += s1 - s0;
       wn += a.leaf_w[B];
       if (B == A)
-        p2p64_leaf<true>(a.src4, a.w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<true>(src4, w64, s0, s1, tx, ty, sum);
       else
-        p2p64_leaf<false>(a.src4, a.w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<false>(src4, w64, s0, s1, tx, ty, sum);
     }
     if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
     if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
   }
   if (lane == 0 && a.pair_counts) a.pair_counts[wid] = pairs;
+  if (bad && lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
 }
 
 // Sum of the per-wave pair counts (one workgroup, fixed order).
@@ -208,16 +216,21 @@ void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
   const bool direct = a.list_cnt == nullptr;
   if (fp64) {
     if (direct)
-      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a);
+      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.w64);
     else
-      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a);
+      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.w64);
   } else {
     if (direct)
-      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a);
+      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4);
     else
-      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a);
+      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4);
   }
-  if (a.pair_counts && a.pairs) k_sum_pairs<<<1, 1024, 0, s>>>(a.pair_counts, (int)waves, a.pairs);
+}
+
+void p2p_count_pairs(const P2PArgs& a, hipStream_t s) {
+  const int64_t waves = (int64_t)a.ntleaves * a.nparts;
+  if (waves <= 0 || !a.pair_counts || !a.pairs) return;
+  k_sum_pairs<<<1, 1024, 0, s>>>(a.pair_counts, (int)waves, a.pairs);
 }
 
 }  // namespace pp

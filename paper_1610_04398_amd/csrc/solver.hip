@@ -396,6 +396,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
 
   // ---- finalize ----
   mark(PP_PHASE_FINALIZE);
+  p2p_count_pairs(pa, s);
   finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS,
            out_d, s);
   mark(12);
