@@ -58,6 +58,17 @@ __host__ __device__ inline uint32_t morton(uint32_t ix, uint32_t iy) { return sp
 // Device view of the quadtree: structure-of-arrays over all cells, numbered
 // level by level (root = 0), children of a cell contiguous and in quadrant
 // order q = qx + 2 qy.
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b % 8), and each XCD has its own L2.  This maps the hardware index to a
+// logical one so that each XCD receives one contiguous 1/8 of the logical
+// range: work that is close in the logical order (neighbouring leaves) shares
+// an L2.  A bijection of [0, G).
+constexpr int kXcds = 8;
+__device__ inline int xcd_contiguous(int b, int G) {
+  const int q = G / kXcds, r = G % kXcds, x = b % kXcds;
+  return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 struct TreeView {
   int D;               // finest level
   int ncells;

@@ -99,26 +99,30 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
       out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
 }
 
-// One M2M output coefficient: a'_l of a parent from up to four children whose
-// scaled coefficients are at ch[q] (q-th child's array, stride 1), d_q their
-// centre offsets in parent sides.
-__device__ inline cplx m2m_coeff(int l, int nk, const double2* const* ch, const cplx* d) {
+// One M2M output coefficient: a'_l of a parent from its children's scaled
+// coefficients a = e + stride * slot (LDS), q-th child at slot0 + q with
+// centre offset d_q (in parent sides) given by its quadrant.
+__device__ inline cplx m2m_coeff(int l, int nk, const double2* __restrict__ e, int stride, int slot0,
+                                 const int* __restrict__ hsrc, const int* __restrict__ quad) {
   cplx b = {0.0, 0.0};
   for (int q = 0; q < nk; ++q) {
-    const double2* a = ch[q];
-    if (!a) continue;
+    const int slot = slot0 + q;
+    if (!hsrc[slot]) continue;
+    const double2* a = e + (int64_t)slot * stride;
     const double a0 = a[0].x;
     if (l == 0) {
       b.x += a0;
       continue;
     }
+    const int qd = quad[slot];
+    const cplx d = {(qd & 1) ? 0.25 : -0.25, (qd & 2) ? 0.25 : -0.25};
     // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
     cplx acc = {0.0, 0.0};
     cplx dp = {1.0, 0.0};
     for (int k = l; k >= 1; --k) {
       const double2 v = a[k];
       acc = cadd(acc, cscale(cmul({v.x, v.y}, dp), binom(l - 1, k - 1) * ldexp(1.0, -k)));
-      dp = cmul(dp, d[q]);
+      dp = cmul(dp, d);
     }
     b = cadd(b, cadd(acc, cscale(dp, -a0 / l)));
   }
@@ -128,25 +132,27 @@ __device__ inline cplx m2m_coeff(int l, int nk, const double2* const* ch, const 
 // M2M for up to three levels per launch (eq. expandedShift applied
 // recursively from the finest level up).  One workgroup per cell R at level L
 // computes, bottom up, the expansions of R's grandchildren (level L+2),
-// children (L+1) and R itself from the final expansions one level below
-// (global memory), keeping the intermediate levels in LDS.  The subtree's
-// structure is read level by level with one thread per cell.  Leaves keep
-// their P2M expansions.
+// children (L+1) and R itself from the final expansions one level below the
+// subtree.  The subtree's structure is read level by level with one thread
+// per cell; then every expansion the subtree needs from global memory (the
+// level below it and the leaves inside it) is staged into LDS in one parallel
+// sweep, so the arithmetic never waits on a global load.  Leaves keep their
+// P2M expansions.
 constexpr int kM2MThreads = 256;
+constexpr int kM2MSlots = 85;
 __global__ __launch_bounds__(kM2MThreads) void k_m2m3(TreeView t, int c0, int c1, int levels, int p,
                                                        double2* __restrict__ mp) {
   // slots: [0] = R, [1..4] its children, [5..20] grandchildren (4 per child),
   // [21..84] the level below the subtree (children of the deepest computed slots)
-  __shared__ int cell[85], kid0[85], nkid[85], hsrc[85], quad[85];
-  __shared__ double2 co[21][kMaxP + 1];
+  __shared__ int cell[kM2MSlots], kid0[kM2MSlots], nkid[kM2MSlots], hsrc[kM2MSlots], quad[kM2MSlots];
+  __shared__ double2 e[kM2MSlots * (kMaxP + 1)];
   const int R = c0 + blockIdx.x;
   if (R >= c1) return;
   const int P1 = p + 1;
   const int tid = threadIdx.x;
-  // read the subtree one level at a time: slot ranges per depth
   const int first[5] = {0, 1, 5, 21, 85};
   for (int d = 0; d <= levels; ++d) {
-    const int lo = first[d], hi = d == levels ? lo + (first[d + 1] - first[d]) : first[d + 1];
+    const int lo = first[d], hi = first[d + 1];
     for (int i = lo + tid; i < hi; i += blockDim.x) {
       int c = -1;
       if (d == 0) {
@@ -164,30 +170,24 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m3(TreeView t, int c0, int c1
     }
     __syncthreads();
   }
-  // compute depths levels-1 .. 0; the children of depth `levels - 1` are the
-  // slots of depth `levels` (memory), the others are LDS slots
+  // stage: slots of depth `levels`, and leaves above it, hold final expansions
+  const int nstage = first[levels + 1];
+  for (int w = tid; w < nstage * P1; w += blockDim.x) {
+    const int i = w / P1, l = w % P1;
+    const int c = cell[i];
+    if (c < 0 || !hsrc[i]) continue;
+    if (i >= first[levels] || kid0[i] < 0) e[i * P1 + l] = mp[(int64_t)c * P1 + l];
+  }
+  __syncthreads();
   for (int d = levels - 1; d >= 0; --d) {
     const int lo = first[d], hi = first[d + 1];
     for (int w = tid; w < (hi - lo) * P1; w += blockDim.x) {
       const int i = lo + w / P1, l = w % P1;
       const int c = cell[i];
-      if (c < 0 || !hsrc[i]) continue;
-      if (kid0[i] < 0) {  // a leaf: its P2M expansion is final
-        co[i][l] = mp[(int64_t)c * P1 + l];
-        continue;
-      }
-      const double2* ch[4] = {nullptr, nullptr, nullptr, nullptr};
-      cplx dq[4];
-      const int nk = nkid[i];
-      for (int q = 0; q < nk; ++q) {
-        const int slot = first[d + 1] + 4 * (i - lo) + q;
-        if (!hsrc[slot]) continue;
-        const int qd = quad[slot];
-        dq[q] = {(qd & 1) ? 0.25 : -0.25, (qd & 2) ? 0.25 : -0.25};
-        ch[q] = (d == levels - 1) ? mp + (int64_t)cell[slot] * P1 : &co[slot][0];
-      }
-      const cplx v = m2m_coeff(l, nk, ch, dq);
-      co[i][l] = make_double2(v.x, v.y);
+      if (c < 0 || !hsrc[i] || kid0[i] < 0) continue;
+      const int slot0 = first[d + 1] + 4 * (i - lo);
+      const cplx v = m2m_coeff(l, nkid[i], e, P1, slot0, hsrc, quad);
+      e[i * P1 + l] = make_double2(v.x, v.y);
       mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
     }
     __syncthreads();

@@ -49,11 +49,19 @@ struct TreeArrays {
 };
 // Root cell: all sources (count read from device memory) and all targets.
 // Root cell (source count read from device memory); ls[0] = 0, ls[1] = 1.
-void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, int* ls, hipStream_t s);
 // One level of the top-down construction, with no host round trip: the level's
 // cells are [ls[level], ls[level+1]) read on the device; its children are
 // appended and ls[level+2] is written.  max_cells bounds the level's size (grid
 // and scan sizing), cap the total cell count (overflow raises a flag).
+// Levels 0..Ld of the tree in one pass over a dense table of Morton prefixes
+// (4^Ld + 1 range starts per key array, tree_dense_cells(Ld) flags); writes
+// ls[0..Ld+1] on the device, and level Ld's cells are left as leaves for
+// tree_level to continue from.  Gives the same cells and numbering as
+// building the levels one at a time from the root.
+int64_t tree_dense_cells(int Ld);
+void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
+                    const int* nsrc_dev, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag, int* off,
+                    int* scan_tmp, int* total_slot, int* flags, hipStream_t s);
 void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
                 const uint32_t* skey, const uint32_t* tkey, int* sp, int4* cr, int* exists, int* off, int* scan_tmp,
                 int* n4_slot, int* total_slot, int* flags, hipStream_t s);

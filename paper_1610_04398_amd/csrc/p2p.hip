@@ -69,7 +69,9 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
   }
 }
 
-// Work: wave w handles target leaf tleaves[w / nparts] and the list part
+// Work: wave w (workgroups spread over the XCDs in contiguous runs, so an
+// XCD's L2 holds the sources of a compact region) handles target leaf
+// tleaves[w / nparts] and the list part
 // w % nparts (entries [part * nb / nparts, (part + 1) * nb / nparts)), looping
 // over the leaf's targets 64 at a time.  Partial sums go to
 // near_sum[part * m + k] and leaf_wnear[part * ncells + A] and are added in a
@@ -81,7 +83,8 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
 template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const float4* __restrict__ src4) {
   // wave-uniform work index (keeps all per-item data in scalar registers)
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
+  const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
+                                                    threadIdx.x / kWave);
   if (wid >= a.ntleaves * a.nparts) return;
   const int part = wid % a.nparts;
   const int lane = threadIdx.x % kWave;
@@ -146,7 +149,8 @@ __device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double*
 template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const float4* __restrict__ src4,
                                                              const double* __restrict__ w64) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kP2PWaves + threadIdx.x / kWave);
+  const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
+                                                    threadIdx.x / kWave);
   if (wid >= a.ntleaves * a.nparts) return;
   const int part = wid % a.nparts;
   const int lane = threadIdx.x % kWave;

@@ -42,6 +42,7 @@ enum BufId {
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
+  B_DSS, B_DTS, B_DFLAG, B_DOFF,
   B_COUNT
 };
 
@@ -75,6 +76,7 @@ struct pp_ctx {
   int cap_m2l = 128;  // per-cell list capacities of the one-pass lists (doubled on overflow)
   int cap_p2p = 64;
   bool exact_lists = false;  // PP_EXACT_LISTS=1 forces the two-pass lists
+  int dense_levels = 8;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
   bool profiling = false;
   hipEvent_t ev[13] = {};
   uint64_t budget = 0;
@@ -224,7 +226,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   const int64_t per_level = 4 * (ngrid / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
   const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
   if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
-  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max<int64_t>({ntiles, 4 * per_level, 3 * cap, m, 1})));
+  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(
+                            std::max<int64_t>({ntiles, 4 * per_level, 3 * cap, m, tree_dense_cells(std::min(D, c.dense_levels)), 1})));
 
   // ---- ingest: sources in Morton order (no sort needed for a grid) ----
   int* tile = ensure<int>(c, B_TILE, ntiles);
@@ -250,7 +253,15 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
                 ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
                 ensure<int>(c, B_PARENT, cap)};
   int* ls_d = misc + M_LS;
-  tree_init_root(ta, misc + M_NSRC, (int)m, ls_d, s);
+  // levels 0..Ld from the dense prefix table, the rest one level at a time
+  const int Ld = std::min(D, c.dense_levels);
+  {
+    const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
+    const int64_t F = tree_dense_cells(Ld);
+    tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, tkey, (int)m, ensure<int>(c, B_DSS, np),
+                   ensure<int>(c, B_DTS, np), ensure<int>(c, B_DFLAG, F), ensure<int>(c, B_DOFF, F),
+                   ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(F)), misc + M_TOT, misc + M_FLAGS, s);
+  }
   {
     const int64_t wmax = std::min<int64_t>(cap, per_level);
     int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
@@ -258,7 +269,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
     int* ex = ensure<int>(c, B_CNT, 4 * wmax);
     int* off = ensure<int>(c, B_OFF, 4 * wmax);
     int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(4 * wmax));
-    for (int l = 0; l <= D; ++l) {
+    for (int l = Ld; l < D; ++l) {
       const int64_t lmax = std::min<int64_t>(wmax, (int64_t)1 << std::min(2 * l, 40));
       tree_level(ta, ls_d, l, D, lm, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4, misc + M_TOT,
                  misc + M_FLAGS, s);
@@ -496,6 +507,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   c->device = device;
   if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p" initial capacities
     int a = 0, b = 0;
     if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && b > 0) {

@@ -2,12 +2,14 @@
 // and the per-leaf packing of sources and targets for the evaluation passes.
 //
 // The paper groups sources hierarchically in a quadtree (Appendix A, Fig.
-// multipole) without saying how it is built.  Here the tree is built top
-// down, one level per launch pair: a cell at level l < D is split when it holds
-// more than leaf_max sources or more than leaf_max targets, and its children
-// (quadrant order q = qx + 2 qy) are kept when non-empty.  A child's source
-// and target ranges are found by binary search of its key prefix inside the
-// parent's ranges.
+// multipole) without saying how it is built.  Here a cell at level l < D is
+// split when it holds more than leaf_max sources or more than leaf_max
+// targets, and its children (quadrant order q = qx + 2 qy) are kept when
+// non-empty.  Cells are numbered level by level, in Morton order within a
+// level.  The top levels (up to 8) come from one dense table of Morton
+// prefixes in a fixed number of launches; deeper levels are built top down,
+// one launch group per level, a child's source and target ranges found by
+// binary search of its key prefix inside the parent's ranges.
 #include <algorithm>
 
 #include "blockscan.h"
@@ -26,22 +28,6 @@ __device__ inline int lower_bound_u32(const uint32_t* __restrict__ a, int lo, in
       hi = mid;
   }
   return lo;
-}
-
-__global__ void k_root(TreeArrays t, const int* __restrict__ nsrc_dev, int ntgt, int* __restrict__ ls) {
-  const int nsrc = *nsrc_dev;
-  t.lvl[0] = 0;
-  t.ix[0] = 0;
-  t.iy[0] = 0;
-  t.sb[0] = 0;
-  t.se[0] = nsrc;
-  t.tb[0] = 0;
-  t.te[0] = ntgt;
-  t.child[0] = -1;
-  t.nchild[0] = 0;
-  t.parent[0] = -1;
-  ls[0] = 0;
-  ls[1] = 1;
 }
 
 // lower_bound of key in a[lo, hi) by one wave: 64 probes per step shrink the
@@ -153,6 +139,91 @@ __global__ void k_level_link(TreeArrays t, int* __restrict__ ls, int level, cons
     t.nchild[d] = 0;
     t.parent[d] = c;
   }
+}
+
+// Dense top of the tree.  For the levels L <= Ld every Morton prefix of the
+// level is a candidate cell; its source and target ranges come from one table
+// of range starts at level Ld (a binary search per prefix), read at stride
+// 4^(Ld - L) for the coarser levels.  A candidate exists when its parent was
+// split (the parent holds more than leaf_max sources or targets; counts only
+// shrink going down, so every further ancestor was split too) and it is not
+// empty.  An exclusive scan of the existence flags in (level, prefix) order
+// numbers the cells exactly as the level-by-level construction does (level
+// major, Morton order within a level), so both give the same tree.
+__device__ inline int64_t dense_level_offset(int L) { return (((int64_t)1 << (2 * L)) - 1) / 3; }
+
+__device__ inline int dense_level_of(int64_t idx) {
+  int L = 0;
+  while (dense_level_offset(L + 1) <= idx) ++L;
+  return L;
+}
+
+__global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __restrict__ nsrc_dev,
+                               const uint32_t* __restrict__ tkey, int ntgt, int D, int Ld, int* __restrict__ ss,
+                               int* __restrict__ ts) {
+  const int64_t np = (int64_t)1 << (2 * Ld);
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P > np) return;
+  const uint64_t key = (uint64_t)P << (2 * (D - Ld));
+  ss[P] = lower_bound_u32(skey, 0, *nsrc_dev, key);
+  ts[P] = lower_bound_u32(tkey, 0, ntgt, key);
+}
+
+__global__ void k_dense_flags(const int* __restrict__ ss, const int* __restrict__ ts, int D, int Ld, int leaf_max,
+                              int* __restrict__ flag) {
+  const int64_t F = dense_level_offset(Ld + 1);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= F) return;
+  const int L = dense_level_of(idx);
+  if (L == 0) {
+    flag[idx] = 1;
+    return;
+  }
+  const int64_t P = idx - dense_level_offset(L);
+  const int sh = 2 * (Ld - L), shp = sh + 2;
+  const int64_t Q = P >> 2;
+  const int ns = ss[(P + 1) << sh] - ss[P << sh], nt = ts[(P + 1) << sh] - ts[P << sh];
+  const int nps = ss[(Q + 1) << shp] - ss[Q << shp], npt = ts[(Q + 1) << shp] - ts[Q << shp];
+  const bool split = L - 1 < D && (nps > leaf_max || npt > leaf_max);
+  flag[idx] = (split && (ns > 0 || nt > 0)) ? 1 : 0;
+}
+
+__global__ void k_dense_write(TreeArrays t, const int* __restrict__ flag, const int* __restrict__ off,
+                              const int* __restrict__ total_dev, const int* __restrict__ ss,
+                              const int* __restrict__ ts, int Ld, int cap, int* __restrict__ ls,
+                              int* __restrict__ flags) {
+  const int64_t F = dense_level_offset(Ld + 1);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = *total_dev;
+  if (idx == 0) {
+    // level starts; clamped to the capacity so later launches stay in bounds
+    for (int L = 0; L <= Ld; ++L) ls[L] = min(off[dense_level_offset(L)], cap);
+    ls[Ld + 1] = min(total, cap);
+    if (total > cap) atomicOr(flags, kFlagCellOverflow);
+  }
+  if (idx >= F || !flag[idx]) return;
+  const int id = off[idx];
+  if (id >= cap) return;
+  const int L = dense_level_of(idx);
+  const int64_t P = idx - dense_level_offset(L);
+  const int sh = 2 * (Ld - L);
+  t.lvl[id] = L;
+  t.ix[id] = (int)compact_bits((uint32_t)P);
+  t.iy[id] = (int)compact_bits((uint32_t)(P >> 1));
+  t.sb[id] = ss[P << sh];
+  t.se[id] = ss[(P + 1) << sh];
+  t.tb[id] = ts[P << sh];
+  t.te[id] = ts[(P + 1) << sh];
+  t.parent[id] = L == 0 ? -1 : off[dense_level_offset(L - 1) + (P >> 2)];
+  int n = 0, first = -1;
+  if (L < Ld) {
+    const int64_t c0 = dense_level_offset(L + 1) + 4 * P;
+    n = flag[c0] + flag[c0 + 1] + flag[c0 + 2] + flag[c0 + 3];
+    first = n > 0 && off[c0] + n <= cap ? off[c0] : -1;
+    if (first < 0) n = 0;
+  }
+  t.child[id] = first;
+  t.nchild[id] = n;
 }
 
 // flag[kind * n + c] for kind 0 = leaf with sources, 1 = leaf with targets,
@@ -270,10 +341,6 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
 
 }  // namespace
 
-void tree_init_root(TreeArrays t, const int* nsrc_dev, int ntgt, int* ls, hipStream_t s) {
-  k_root<<<1, 1, 0, s>>>(t, nsrc_dev, ntgt, ls);
-}
-
 static unsigned level_blocks(int64_t max_cells) {
   const int64_t items = 4 * std::max<int64_t>(max_cells, 1);
   return (unsigned)std::min<int64_t>((items + 255) / 256, 2048);
@@ -289,6 +356,20 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
   k_level_exists<<<g, 256, 0, s>>>(t, ls, level, D, leaf_max, sp, cr, exists);
   scan_exclusive_dev(exists, off, n4_slot, 4 * mc, scan_tmp, total_slot, s);
   k_level_link<<<g, 256, 0, s>>>(t, ls, level, cr, exists, off, total_slot, cap, flags);
+}
+
+int64_t tree_dense_cells(int Ld) { return ((((int64_t)1) << (2 * (Ld + 1))) - 1) / 3; }
+
+void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
+                    const int* nsrc_dev, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag, int* off,
+                    int* scan_tmp, int* total_slot, int* flags, hipStream_t s) {
+  const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
+  k_dense_starts<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(skey, nsrc_dev, tkey, ntgt, D, Ld, ss, ts);
+  const int64_t F = tree_dense_cells(Ld);
+  const unsigned g = (unsigned)((F + 255) / 256);
+  k_dense_flags<<<g, 256, 0, s>>>(ss, ts, D, Ld, leaf_max, flag);
+  scan_exclusive(flag, off, F, scan_tmp, total_slot, s);
+  k_dense_write<<<g, 256, 0, s>>>(t, flag, off, total_slot, ss, ts, Ld, cap, ls, flags);
 }
 
 void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, int* off3, int* scan_tmp,

@@ -102,6 +102,21 @@ def test_tree_bit_exact_adaptive(solver, seed, leaf_max, theta):
     _compare_tree(solver, info, theta, f.shape[1])
 
 
+@pytest.mark.parametrize("dense_levels", ["0", "3"])
+def test_tree_bit_exact_levelwise(monkeypatch, dense_levels):
+    """The level-by-level construction (from the root, or below a shallow dense top) gives the same tree."""
+    import paper_1610_04398_amd as pp
+    monkeypatch.setenv("PP_DENSE_LEVELS", dense_levels)
+    s = pp.Solver(0)
+    try:
+        f, h, tx, ty = _case_random(2, n=48)
+        s.solve_grid(f, h, tx, ty, p=6, theta=0.4, leaf_max=16, precision="fp64")
+        info = tree_ref.grid_tree(f, tx, ty, h, leaf_max=16)
+        _compare_tree(s, info, 0.4, f.shape[1])
+    finally:
+        s.close()
+
+
 def test_fmm_gaussian64_fp64(solver):
     w = G.workload("gaussian64")
     g = w["grid"]
