@@ -20,8 +20,15 @@
  * - Grid: f is ny*nx doubles, row-major (f[j*nx + i]); node (i, j) lies at
  *   (x0 + (i + 1/2) h, y0 + (j + 1/2) h).  Nodes with f == 0 are skipped.
  *   Limits: 1 <= nx, ny <= 65536 and nx*ny < 2^31.
- * - Root square: anchored at (x0, y0), side 2^k h with 2^k >= max(nx, ny).
- *   Every target must lie inside it (half-open), else PP_ERR_DOMAIN.
+ * - Root square (grid): anchored at (x0, y0), side 2^k h with 2^k >= max(nx,
+ *   ny).  Every target must lie inside it (half-open), else PP_ERR_DOMAIN.
+ * - Scattered sources (pp_solve_points): n points (sx, sy) with weights w =
+ *   f h^2 given per source, so each source may carry its own cell area (the
+ *   paper allows h to vary from source to source).  Sources with w == 0 are
+ *   skipped.  The root square is anchored at the lower-left corner of the
+ *   bounding box of the weighted sources and the targets, with finest cells
+ *   of the power-of-two side u for which 2^15 u first exceeds the box's
+ *   extent; no target can lie outside it.
  * - Pointers: every input and output may be host memory or device memory of
  *   the context's device (detected with hipPointerGetAttributes).  The caller
  *   owns all buffers; inputs are only read; p_out (m doubles, the caller's
@@ -31,7 +38,12 @@
  * - Self-interaction (a target that coincides exactly, in FP64, with a grid
  *   node x0 + (i + 1/2) h; the paper does not treat it): PP_SELF_SKIP drops the
  *   node, PP_SELF_CELLAVG adds w (ln h - kappa) / 2pi, the mean of the kernel
- *   over the node's h x h cell (kappa = 3/2 - pi/4 + ln(2)/2).
+ *   over the node's h x h cell (kappa = 3/2 - pi/4 + ln(2)/2).  Scattered
+ *   sources that coincide exactly with a target are dropped (PP_SELF_SKIP is
+ *   the only mode there).  In PP_MIXED, a grid target within 2^-20 h of a node
+ *   is treated exactly (its FP64 term is restored); scattered points closer
+ *   than FP32 resolves (about 1e-7 of their leaf's side) are not, and their
+ *   pair is evaluated at that resolution.
  * - Errors: functions never throw; they return a pp_status and leave a message
  *   for pp_last_error().  PP_ERR_DEVICE poisons the context (destroy it).
  * - Threads: a context serves one host thread at a time.
@@ -55,7 +67,9 @@ enum {
   PP_ERR_NOMEM = -3,   /* the solve would exceed the context's device-memory budget */
   PP_ERR_DEVICE = -4,  /* a HIP call failed; the context is unusable */
   PP_ERR_LIMIT = -5,   /* the tree exceeded an internal limit (e.g. traversal frontier) */
-  PP_ERR_TIMEOUT = -6  /* pp_server_wait: the request did not finish in time (ticket stays valid) */
+  PP_ERR_TIMEOUT = -6, /* pp_server_wait: the request did not finish in time (ticket stays valid) */
+  PP_ERR_CANCELLED = -7, /* pp_server_wait: the request was cancelled before it started */
+  PP_ERR_BUSY = -8     /* pp_server_cancel: the request has already started (or finished) */
 };
 
 enum { PP_FP64 = 0, PP_MIXED = 1 };            /* MIXED: P2P and L2P in FP32 (Kahan), expansions FP64 */
@@ -87,7 +101,7 @@ typedef struct {
   int32_t ncells;         /* cells in the tree */
   int32_t nsrc_leaves;    /* leaves holding sources */
   int32_t ntgt_leaves;    /* leaves holding targets */
-  int64_t nsources;       /* grid nodes with f != 0 */
+  int64_t nsources;       /* sources with a nonzero weight */
   int64_t ntargets;
   int64_t n_m2l;          /* M2L (cell, cell) pairs */
   int64_t n_p2p_lists;    /* P2P (leaf, leaf) pairs */
@@ -132,6 +146,20 @@ pp_status pp_direct_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double 
                          int64_t m, const double* tx, const double* ty, const pp_params* params, double* p_out,
                          void* hip_stream);
 
+/* Tree-code solve of eq. greenSum for n scattered sources (sx, sy) with
+ * weights w (w_i = f_i h_i^2) at the m targets (tx, ty): the same passes as
+ * pp_solve_grid.  Writes P to p_out[0..m).  params->self_mode must be
+ * PP_SELF_SKIP (else PP_ERR_ARG). */
+pp_status pp_solve_points(pp_ctx* ctx, int64_t n, const double* sx, const double* sy, const double* w, int64_t m,
+                          const double* tx, const double* ty, const pp_params* params, double* p_out,
+                          void* hip_stream);
+
+/* All-pairs direct sum for scattered sources on the GPU (the baseline of
+ * pp_solve_points); as pp_direct_grid otherwise. */
+pp_status pp_direct_points(pp_ctx* ctx, int64_t n, const double* sx, const double* sy, const double* w, int64_t m,
+                           const double* tx, const double* ty, const pp_params* params, double* p_out,
+                           void* hip_stream);
+
 pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
 
 /* Enable (on != 0) or disable per-phase GPU timing of later calls.  Timing
@@ -147,7 +175,7 @@ pp_status pp_set_profiling(pp_ctx* ctx, int32_t on);
  */
 enum {
   PP_ARR_SRC_KEY = 0,    /* uint32 Morton key per source, in key order */
-  PP_ARR_SRC_INDEX = 1,  /* packed node index i | (j << 16) per source */
+  PP_ARR_SRC_INDEX = 1,  /* per source: packed node index i | (j << 16) (grid), caller index (points) */
   PP_ARR_TGT_KEY = 2,    /* uint32 key per target, sorted */
   PP_ARR_TGT_PERM = 3,   /* caller index of each sorted target */
   PP_ARR_CELL_LEVEL = 4,
@@ -182,12 +210,16 @@ const char* pp_last_error(const pp_ctx* ctx);
  * Serving: a persistent pool of solve slots fed from a FIFO of requests
  * (continuous batching of independent solves on one GPU).  Each slot owns a
  * context (device buffers stay resident between requests), a HIP stream and a
- * host thread.  The head of the queue is admitted as soon as a slot is free
- * and the estimated device footprints of the requests in flight plus its own
- * fit in hbm_budget_bytes (0 = no bound; a request always runs when nothing
- * else is in flight).  Requests admitted together run concurrently and their
- * kernels overlap on the device.  A request's result is bitwise the result of
- * pp_solve_grid on the same inputs: slots share nothing.
+ * host thread.  The head of the queue is admitted as soon as a slot is free,
+ * the estimated device footprints of the requests in flight plus its own fit
+ * in hbm_budget_bytes, and their work (grid nodes plus targets) fits in
+ * work_budget_points (0 = no bound for either; a request always runs when
+ * nothing else is in flight).  The work bound keeps large requests from
+ * sharing the GPU with each other, which would stretch all of their
+ * latencies, while small ones still overlap.  Requests admitted together run
+ * concurrently and their kernels overlap on the device.  A request's result
+ * is bitwise the result of pp_solve_grid on the same inputs: slots share
+ * nothing.
  *
  * Ownership: host inputs (f, tx, ty) are copied at submission; device inputs
  * and p_out must stay valid until pp_server_wait has returned for the ticket.
@@ -198,6 +230,7 @@ typedef struct {
   int32_t device;
   int32_t max_slots;          /* concurrent solves, 1..64 */
   uint64_t hbm_budget_bytes;  /* admission bound on in-flight footprints (0 = none) */
+  uint64_t work_budget_points; /* admission bound on in-flight nx*ny + m (0 = none) */
 } pp_server_cfg;
 typedef struct {              /* the arguments of pp_solve_grid */
   int32_t nx, ny;
@@ -225,6 +258,11 @@ pp_status pp_server_submit(pp_server* s, const pp_request* req, uint64_t* ticket
  * returns its status (PP_ERR_TIMEOUT leaves the ticket valid) and releases
  * the ticket; info (may be NULL) receives its timings. */
 pp_status pp_server_wait(pp_server* s, uint64_t ticket, int64_t timeout_us, pp_ticket_info* info);
+/* Withdraw a request that has not started: returns PP_OK and its wait then
+ * returns PP_ERR_CANCELLED (p_out untouched); PP_ERR_BUSY if it has already
+ * started or finished (wait for it as usual); PP_ERR_ARG for an unknown
+ * ticket. */
+pp_status pp_server_cancel(pp_server* s, uint64_t ticket);
 /* Finish every queued request, then stop the slots and free their memory. */
 pp_status pp_server_destroy(pp_server* s);
 const char* pp_server_last_error(const pp_server* s);

@@ -1,7 +1,7 @@
 """MI355X pressure-Poisson tree-code: Python binding of the HIP library.
 
 The library computes P(t) = (1/2pi) sum_i f_i h^2 ln|t - s_i| (Appendix A, eq.
-greenSum with eq. green2D) for grid sources and arbitrary targets with a
+greenSum with eq. green2D) for grid or scattered sources and arbitrary targets with a
 quadtree fast multipole scheme in hand-written HIP kernels for gfx950.  This
 module only marshals arguments: torch CUDA tensors (device pointers plus the
 current stream) or NumPy arrays (host pointers) go straight to the C ABI of
@@ -21,9 +21,11 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_debug_copy,
     pp_destroy,
     pp_direct_grid,
+    pp_direct_points,
     pp_get_stats,
     pp_last_error,
     pp_set_profiling,
+    pp_server_cancel,
     pp_server_create,
     pp_server_destroy,
     pp_server_last_error,
@@ -31,6 +33,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_server_wait,
     pp_footprint_estimate,
     pp_solve_grid,
+    pp_solve_points,
     pp_status_string,
     pp_params,
     PP_FP64,
@@ -124,6 +127,48 @@ class Solver:
         prm = make_params(1, 0.5, leaf_max, precision, self_mode)
         return self._run(pp_direct_grid, f, h, tx, ty, x0, y0, prm, out, stream)
 
+    def _run_points(self, fn, sx, sy, w, tx, ty, params, out, stream):
+        torch_mode = _is_torch(tx)
+        sxp, sxk = _ptr(sx, "sx")
+        syp, syk = _ptr(sy, "sy")
+        wp, wk = _ptr(w, "w")
+        n = int(np.prod(tuple(sxk.shape)))
+        if int(np.prod(tuple(syk.shape))) != n or int(np.prod(tuple(wk.shape))) != n:
+            raise ValueError("sx, sy and w differ in length")
+        xp, xk = _ptr(tx, "tx")
+        yp, yk = _ptr(ty, "ty")
+        m = int(np.prod(tuple(xk.shape)))
+        if int(np.prod(tuple(yk.shape))) != m:
+            raise ValueError("tx and ty differ in length")
+        if out is None:
+            if torch_mode:
+                import torch
+                out = torch.empty(m, dtype=torch.float64, device=tx.device)
+            else:
+                out = np.empty(m, dtype=np.float64)
+        op, ok = _ptr(out, "out")
+        if stream is None:
+            stream = 0
+            if torch_mode and tx.is_cuda:
+                import torch
+                stream = torch.cuda.current_stream(tx.device).cuda_stream
+        st = fn(self._ctx, n, sxp, syp, wp, m, xp, yp, params, op, stream)
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del sxk, syk, wk, xk, yk, ok
+        return out
+
+    def solve_points(self, sx, sy, w, tx, ty, p=12, theta=0.5, leaf_max=64, precision="mixed", out=None,
+                     stream=None):
+        """Tree-code pressure of scattered weighted sources at the targets; see pp_solve_points."""
+        prm = make_params(p, theta, leaf_max, precision, "skip")
+        return self._run_points(pp_solve_points, sx, sy, w, tx, ty, prm, out, stream)
+
+    def direct_points(self, sx, sy, w, tx, ty, leaf_max=64, precision="mixed", out=None, stream=None):
+        """All-pairs GPU direct sum for scattered sources; see pp_direct_points."""
+        prm = make_params(1, 0.5, leaf_max, precision, "skip")
+        return self._run_points(pp_direct_points, sx, sy, w, tx, ty, prm, out, stream)
+
     def set_profiling(self, on: bool = True) -> None:
         st = pp_set_profiling(self._ctx, on)
         if st != B.PP_OK:
@@ -162,8 +207,8 @@ class Server:
     submission) or CUDA tensors (kept alive here until the ticket is waited on).
     """
 
-    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0):
-        self._srv = pp_server_create(device, max_slots, hbm_budget_bytes)
+    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0, work_budget_points: int = 0):
+        self._srv = pp_server_create(device, max_slots, hbm_budget_bytes, work_budget_points)
         self._keep = {}
 
     def submit(self, f, h, tx, ty, out, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
@@ -190,6 +235,16 @@ class Server:
         if st != B.PP_OK:
             raise PPError(st, f"{pp_status_string(st)}: {pp_server_last_error(self._srv)}")
         return {name: getattr(info, name) for name, _ in B.pp_ticket_info._fields_}
+
+    def cancel(self, ticket: int) -> bool:
+        """Withdraw a queued request: True if it had not started (its wait then raises PPError with
+        status PP_ERR_CANCELLED), False if it is already running or done."""
+        st = pp_server_cancel(self._srv, ticket)
+        if st == B.PP_OK:
+            return True
+        if st == B.PP_ERR_BUSY:
+            return False
+        raise PPError(st, f"{pp_status_string(st)}: {pp_server_last_error(self._srv)}")
 
     def close(self):
         if self._srv:

@@ -34,10 +34,13 @@ DOUBLE_ARRAYS = {"MULTIPOLE", "LOCAL", "FAR", "NEAR", "LEAF_WNEAR"}
 UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
-EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_get_stats", "pp_set_profiling",
-            "pp_debug_copy", "pp_status_string", "pp_last_error", "pp_server_create", "pp_server_submit",
-            "pp_server_wait", "pp_server_destroy", "pp_server_last_error", "pp_footprint_estimate")
+EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
+            "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
+            "pp_server_create", "pp_server_submit", "pp_server_wait", "pp_server_cancel", "pp_server_destroy",
+            "pp_server_last_error", "pp_footprint_estimate")
 PP_ERR_TIMEOUT = -6
+PP_ERR_CANCELLED = -7
+PP_ERR_BUSY = -8
 
 
 class pp_params(ctypes.Structure):
@@ -51,8 +54,10 @@ class pp_stats(ctypes.Structure):
                 ("n_m2l", ctypes.c_int64), ("n_p2p_lists", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 12)]
 
+
 class pp_server_cfg(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+    _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("work_budget_points", ctypes.c_uint64)]
 
 
 class pp_request(ctypes.Structure):
@@ -91,6 +96,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_solve_grid.restype = i32
     lib.pp_direct_grid.argtypes = solve_args
     lib.pp_direct_grid.restype = i32
+    points_args = [vp, i64, vp, vp, vp, i64, vp, vp, ctypes.POINTER(pp_params), vp, vp]
+    lib.pp_solve_points.argtypes = points_args
+    lib.pp_solve_points.restype = i32
+    lib.pp_direct_points.argtypes = points_args
+    lib.pp_direct_points.restype = i32
     lib.pp_get_stats.argtypes = [vp, ctypes.POINTER(pp_stats)]
     lib.pp_get_stats.restype = i32
     lib.pp_set_profiling.argtypes = [vp, i32]
@@ -103,6 +113,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_server_submit.restype = i32
     lib.pp_server_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(pp_ticket_info)]
     lib.pp_server_wait.restype = i32
+    lib.pp_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.pp_server_cancel.restype = i32
     lib.pp_server_destroy.argtypes = [vp]
     lib.pp_server_destroy.restype = i32
     lib.pp_server_last_error.argtypes = [vp]
@@ -148,6 +160,16 @@ def pp_direct_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, params: pp_
                                 stream)
 
 
+def pp_solve_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:
+    return lib().pp_solve_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params), out_ptr,
+                                 stream)
+
+
+def pp_direct_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:
+    return lib().pp_direct_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params), out_ptr,
+                                  stream)
+
+
 def pp_get_stats(ctx) -> pp_stats:
     s = pp_stats()
     st = lib().pp_get_stats(ctx, ctypes.byref(s))
@@ -174,8 +196,9 @@ def pp_last_error(ctx) -> str:
     return lib().pp_last_error(ctx).decode()
 
 
-def pp_server_create(device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0) -> int:
-    cfg = pp_server_cfg(device, max_slots, hbm_budget_bytes)
+def pp_server_create(device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0,
+                     work_budget_points: int = 0) -> int:
+    cfg = pp_server_cfg(device, max_slots, hbm_budget_bytes, work_budget_points)
     h = ctypes.c_void_p()
     st = lib().pp_server_create(ctypes.byref(cfg), ctypes.byref(h))
     if st != PP_OK:
@@ -195,6 +218,10 @@ def pp_server_wait(server, ticket: int, timeout_us: int = -1) -> tuple[int, pp_t
     info = pp_ticket_info()
     st = lib().pp_server_wait(server, ticket, timeout_us, ctypes.byref(info))
     return st, info
+
+
+def pp_server_cancel(server, ticket: int) -> int:
+    return lib().pp_server_cancel(server, ticket)
 
 
 def pp_server_destroy(server) -> int:

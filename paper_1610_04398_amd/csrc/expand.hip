@@ -59,8 +59,8 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
 constexpr int kP2MLanes = 16;
 template <int PM>
 __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
-                                             const float4* __restrict__ src4, const double* __restrict__ w64, int p,
-                                             double2* __restrict__ mp) {
+                                             const float4* __restrict__ src4, const double2* __restrict__ s64,
+                                             const double* __restrict__ w64, int p, double2* __restrict__ mp) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int li = (int)(gtid / kP2MLanes);
   const int sub = (int)(gtid % kP2MLanes);
@@ -73,9 +73,18 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
   for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
   const int sb = t.sb[c], se = t.se[c];
   for (int s = sb + sub; s < se; s += kP2MLanes) {
-    const float4 q = src4[s];
+    double ox, oy;
+    if (s64) {
+      const double2 o = s64[s];
+      ox = o.x;
+      oy = o.y;
+    } else {
+      const float4 q = src4[s];
+      ox = (double)q.x;
+      oy = (double)q.y;
+    }
     const double w = w64[s];
-    const cplx z = {(double)q.x * inv - 0.5, (double)q.y * inv - 0.5};
+    const cplx z = {ox * inv - 0.5, oy * inv - 0.5};
     acc[0].x += w;
     cplx zk = {w * z.x, w * z.y};
 #pragma unroll
@@ -360,11 +369,11 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
 
 }  // namespace
 
-void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
-         hipStream_t s) {
+void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double2* s64, const double* w64, int p,
+         double2* mp, hipStream_t s) {
   if (n <= 0) return;
   const unsigned g = (unsigned)(((int64_t)n * kP2MLanes + 255) / 256);
-  PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, src4, w64, p, mp);
+  PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, src4, s64, w64, p, mp);
 }
 
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s) {

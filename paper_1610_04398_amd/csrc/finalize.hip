@@ -10,6 +10,9 @@
 // (skip) or w kappa (cell average: w (ln h - kappa) in total).  In mixed
 // precision a target within 2^-20 h of a node was snapped onto it (FP32 cannot
 // resolve that distance); the exact FP64 term w ln d is restored here.
+// Scattered sources that coincide exactly with a target were skipped by the
+// near-field kernel the same way; their share w ln u of the near weight term
+// is removed here (G(0) := 0).
 #include "internal.h"
 
 namespace pp {
@@ -18,7 +21,8 @@ namespace {
 __global__ void k_finalize(int64_t m, int ncells, int nparts, const int* __restrict__ perm, const int* __restrict__ tleaf,
                            const double* __restrict__ far, const double* __restrict__ near_sum,
                            const double* __restrict__ leaf_wnear, const int* __restrict__ self_idx,
-                           const double* __restrict__ self_logd, const double* __restrict__ f, double h, double lnh,
+                           const double* __restrict__ self_logd, const double* __restrict__ self_w,
+                           const double* __restrict__ f, double h, double lnh,
                            int self_mode, const int* __restrict__ flags, double* __restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
@@ -30,7 +34,8 @@ __global__ void k_finalize(int64_t m, int ncells, int nparts, const int* __restr
     wn += leaf_wnear[(int64_t)q * ncells + c];
   }
   double v = (far ? far[k] : 0.0) + 0.5 * ns + lnh * wn;
-  const int si = self_idx[k];
+  if (self_w) v -= self_w[k] * lnh;
+  const int si = self_idx ? self_idx[k] : -1;
   if (si >= 0) {
     const double w = f[si] * (h * h);
     const double lg = self_logd[k];
@@ -46,10 +51,12 @@ __global__ void k_finalize(int64_t m, int ncells, int nparts, const int* __restr
 
 void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
               const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
-              const double* f, double h, int self_mode, const int* flags, double* out, hipStream_t s) {
+              const double* self_w, const double* f, double h, int self_mode, const int* flags, double* out,
+              hipStream_t s) {
   if (m <= 0) return;
   k_finalize<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, ncells, nparts, perm, tleaf, far, near_sum, leaf_wnear,
-                                                         self_idx, self_logd, f, h, log(h), self_mode, flags, out);
+                                                         self_idx, self_logd, self_w, f, h, log(h), self_mode, flags,
+                                                         out);
 }
 
 }  // namespace pp

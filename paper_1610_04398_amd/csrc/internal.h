@@ -28,6 +28,21 @@ void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const i
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
                  uint32_t* key, int* idx, int* flags, hipStream_t s);
 
+// ---- points.hip: scattered sources -----------------------------------------------
+// Finest level of the root for scattered input: keys use 2 * 15 bits, so the
+// key of a zero-weight source (0xFFFFFFFF) sorts after every cell key.
+constexpr int kPointsDepth = 15;
+int points_box_blocks(int64_t n_total);
+// box[0..3] = xmin, xmax, ymin, ymax of the weighted sources and the targets;
+// *nsrc = number of sources with w != 0.  part/cnt: points_box_blocks entries.
+void points_box(const double* sx, const double* sy, const double* w, int64_t n, const double* tx, const double* ty,
+                int64_t m, double4* part, int* cnt, double* box, int* nsrc, int* flags, hipStream_t s);
+void points_keys(const double* sx, const double* sy, const double* w, int64_t n, double x0, double y0, double u,
+                 int D, uint32_t* key, int* idx, hipStream_t s);
+// Sorted copies of the first *nsrc_dev sources in the order perm.
+void points_gather(const int* perm, const int* nsrc_dev, int64_t nmax, const double* sx, const double* sy,
+                   const double* w, double* xs, double* ys, double* ws, hipStream_t s);
+
 // ---- sort.hip: stable LSD radix sort of (uint32 key, int32 value) pairs -----------
 size_t radix_temp_ints(int64_t n);
 // Sorts the low `bits` bits of keys; results end in (keys, vals).  tmp arrays of n.
@@ -47,12 +62,6 @@ struct TreeArrays {
   int* nchild;
   int* parent;
 };
-// Root cell: all sources (count read from device memory) and all targets.
-// Root cell (source count read from device memory); ls[0] = 0, ls[1] = 1.
-// One level of the top-down construction, with no host round trip: the level's
-// cells are [ls[level], ls[level+1]) read on the device; its children are
-// appended and ls[level+2] is written.  max_cells bounds the level's size (grid
-// and scan sizing), cap the total cell count (overflow raises a flag).
 // Levels 0..Ld of the tree in one pass over a dense table of Morton prefixes
 // (4^Ld + 1 range starts per key array, tree_dense_cells(Ld) flags); writes
 // ls[0..Ld+1] on the device, and level Ld's cells are left as leaves for
@@ -62,6 +71,10 @@ int64_t tree_dense_cells(int Ld);
 void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
                     const int* nsrc_dev, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag, int* off,
                     int* scan_tmp, int* total_slot, int* flags, hipStream_t s);
+// One level of the top-down construction, with no host round trip: the level's
+// cells are [ls[level], ls[level+1]) read on the device; its children are
+// appended and ls[level+2] is written.  max_cells bounds the level's size (grid
+// and scan sizing), cap the total cell count (overflow raises a flag).
 void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t max_cells, int cap,
                 const uint32_t* skey, const uint32_t* tkey, int* sp, int4* cr, int* exists, int* off, int* scan_tmp,
                 int* n4_slot, int* total_slot, int* flags, hipStream_t s);
@@ -75,6 +88,15 @@ void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, in
 // cell units, and the FP64 leaf weight.
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
                        float4* src4, double* leaf_w, hipStream_t s);
+// Scattered-source counterparts: FP32 records and FP64 offsets (units of u)
+// per source leaf; per target leaf the offsets, owning leaf, and the weight of
+// the sources that coincide exactly with the target.
+void leaf_pack_points(TreeArrays t, const int* sleaves, int nsleaves, int D, const double* xs, const double* ys,
+                      const double* ws, double x0, double y0, double u, float4* src4, double2* s64, double* leaf_w,
+                      hipStream_t s);
+void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
+                      const int* perm, double x0, double y0, double u, const double* xs, const double* ys,
+                      const double* ws, float2* rel32, double2* rel64, int* tleaf, double* self_w, hipStream_t s);
 // Per target leaf: offsets relative to the leaf corner (FP32 and FP64, in units
 // of h), owning leaf, and the coincident-node information for the self rule.
 // A target at squared distance d2 from its nearest node with d2 == 0 or
@@ -99,8 +121,10 @@ void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int
 void capacity_offsets(int ncells, int cap_m, int cap_p, int* off_m, int* off_p, hipStream_t s);
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
 // P2M of every source leaf (one wave per leaf).
-void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double* w64, int p, double2* mp,
-         hipStream_t s);
+// s64 (may be null): FP64 source offsets; without it the FP32 offsets of src4
+// are used (exact for grid nodes).
+void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double2* s64, const double* w64, int p,
+         double2* mp, hipStream_t s);
 // M2M for the `levels` (1..3) levels starting at the level whose cells are
 // [c0, c1): one workgroup per cell computes its subtree bottom up.
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s);
@@ -125,6 +149,7 @@ struct P2PArgs {
   const int* sleaves;   // all source leaves (direct mode)
   int nsleaves;
   const float4* src4;
+  const double2* s64;   // FP64 source offsets for the FP64 kernel (null: those of src4, exact for grid nodes)
   const double* w64;
   const double* leaf_w;
   const float2* rel32;
@@ -144,8 +169,11 @@ void p2p_count_pairs(const P2PArgs& a, hipStream_t s);
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.
 // near_sum and leaf_wnear hold nparts partial sums (strides m and ncells).
+// self_idx/self_logd: grid-node coincidence (may be null); self_w: per target
+// the weight of exactly coincident scattered sources (may be null).
 void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
               const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
-              const double* f, double h, int self_mode, const int* flags, double* out, hipStream_t s);
+              const double* self_w, const double* f, double h, int self_mode, const int* flags, double* out,
+              hipStream_t s);
 
 }  // namespace pp

@@ -132,14 +132,23 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const flo
 }
 
 template <bool GUARD>
-__device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double* __restrict__ w64, int s0, int s1,
-                                  double tx, double ty, double& sum) {
+__device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double2* __restrict__ s64,
+                                  const double* __restrict__ w64, int s0, int s1, double tx, double ty, double& sum) {
 #pragma unroll 2
   for (int s = s0; s < s1; ++s) {
-    const float4 q = src4[s];
+    double sx, sy;
+    if (s64) {
+      const double2 o = s64[s];
+      sx = o.x;
+      sy = o.y;
+    } else {
+      const float4 q = src4[s];
+      sx = (double)q.x;
+      sy = (double)q.y;
+    }
     const double w = w64[s];
-    const double dx = tx - (double)q.x;
-    const double dy = ty - (double)q.y;
+    const double dx = tx - sx;
+    const double dy = ty - sy;
     const double r2 = fma(dy, dy, dx * dx);
     if (GUARD && r2 == 0.0) continue;
     sum = fma(w, log(r2), sum);
@@ -148,6 +157,7 @@ __device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double*
 
 template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const float4* __restrict__ src4,
+                                                             const double2* __restrict__ s64,
                                                              const double* __restrict__ w64) {
   const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
                                                     threadIdx.x / kWave);
@@ -185,9 +195,9 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
       nsrc += s1 - s0;
       wn += a.leaf_w[B];
       if (B == A)
-        p2p64_leaf<true>(src4, w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<true>(src4, s64, w64, s0, s1, tx, ty, sum);
       else
-        p2p64_leaf<false>(src4, w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<false>(src4, s64, w64, s0, s1, tx, ty, sum);
     }
     if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
     if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
@@ -220,9 +230,9 @@ void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
   const bool direct = a.list_cnt == nullptr;
   if (fp64) {
     if (direct)
-      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.w64);
+      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.s64, a.w64);
     else
-      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.w64);
+      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.s64, a.w64);
   } else {
     if (direct)
       k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4);

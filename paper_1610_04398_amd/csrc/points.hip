@@ -1,0 +1,251 @@
+// Ingest of scattered sources (w_i = f_i h_i^2 given per source, so a source
+// may carry its own cell area, eq. greenSum with a varying h) and the per-leaf
+// packing of those sources and of the targets.
+//
+// The root square is anchored at the lower-left corner (x0, y0) of the
+// bounding box of the weighted sources and the targets, and its finest cells
+// have the power-of-two side u for which 2^D u first exceeds the box's extent
+// (D = kPointsDepth).  Keys are floor((x - x0) / u) interleaved, the same FP64
+// operations as for grid targets, so every point falls inside the root.
+// Sources with w = 0 take the key 0xFFFFFFFF, above every cell key, and sort
+// to the end where the tree does not see them.
+#include <cmath>
+
+#include "blockscan.h"
+#include "internal.h"
+
+namespace pp {
+
+namespace {
+constexpr int kBoxBlock = 256;
+
+// Per-block bounding box of the weighted sources and the targets, the number
+// of weighted sources, and flags for non-finite input.
+__global__ __launch_bounds__(kBoxBlock) void k_box_partial(const double* __restrict__ sx,
+                                                            const double* __restrict__ sy,
+                                                            const double* __restrict__ w, int64_t n,
+                                                            const double* __restrict__ tx,
+                                                            const double* __restrict__ ty, int64_t m,
+                                                            double4* __restrict__ part, int* __restrict__ cnt,
+                                                            int* __restrict__ flags) {
+  __shared__ double red[4][kBoxBlock];
+  __shared__ int rc[kBoxBlock];
+  double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+  int c = 0, bad_s = 0, bad_t = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + m; i += stride) {
+    double x, y;
+    if (i < n) {
+      const double wi = w[i];
+      x = sx[i];
+      y = sy[i];
+      if (!isfinite(wi) || !isfinite(x) || !isfinite(y)) {
+        bad_s = 1;
+        continue;
+      }
+      if (wi == 0.0) continue;
+      ++c;
+    } else {
+      x = tx[i - n];
+      y = ty[i - n];
+      if (!isfinite(x) || !isfinite(y)) {
+        bad_t = 1;
+        continue;
+      }
+    }
+    x0 = fmin(x0, x);
+    x1 = fmax(x1, x);
+    y0 = fmin(y0, y);
+    y1 = fmax(y1, y);
+  }
+  if (bad_s) atomicOr(flags, kFlagNonFiniteSource);
+  if (bad_t) atomicOr(flags, kFlagNonFiniteTarget);
+  const int t = threadIdx.x;
+  red[0][t] = x0;
+  red[1][t] = -x1;
+  red[2][t] = y0;
+  red[3][t] = -y1;
+  rc[t] = c;
+  __syncthreads();
+  for (int o = kBoxBlock / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      for (int q = 0; q < 4; ++q) red[q][t] = fmin(red[q][t], red[q][t + o]);
+      rc[t] += rc[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[blockIdx.x] = make_double4(red[0][0], -red[1][0], red[2][0], -red[3][0]);
+    cnt[blockIdx.x] = rc[0];
+  }
+}
+
+__global__ __launch_bounds__(kBoxBlock) void k_box_final(const double4* __restrict__ part,
+                                                          const int* __restrict__ cnt, int nparts,
+                                                          double* __restrict__ box, int* __restrict__ nsrc) {
+  __shared__ double red[4][kBoxBlock];
+  __shared__ int rc[kBoxBlock];
+  const int t = threadIdx.x;
+  double v[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  int c = 0;
+  for (int i = t; i < nparts; i += kBoxBlock) {
+    const double4 p = part[i];
+    v[0] = fmin(v[0], p.x);
+    v[1] = fmin(v[1], -p.y);
+    v[2] = fmin(v[2], p.z);
+    v[3] = fmin(v[3], -p.w);
+    c += cnt[i];
+  }
+  for (int q = 0; q < 4; ++q) red[q][t] = v[q];
+  rc[t] = c;
+  __syncthreads();
+  for (int o = kBoxBlock / 2; o > 0; o >>= 1) {
+    if (t < o) {
+      for (int q = 0; q < 4; ++q) red[q][t] = fmin(red[q][t], red[q][t + o]);
+      rc[t] += rc[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    box[0] = red[0][0];
+    box[1] = -red[1][0];
+    box[2] = red[2][0];
+    box[3] = -red[3][0];
+    *nsrc = rc[0];
+  }
+}
+
+__global__ void k_point_keys(const double* __restrict__ sx, const double* __restrict__ sy,
+                             const double* __restrict__ w, int64_t n, double x0, double y0, double u, int D,
+                             uint32_t* __restrict__ key, int* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t k = 0xFFFFFFFFu;
+  if (w[i] != 0.0) {
+    const double lim = (double)(1u << D);
+    const double qx = floor((sx[i] - x0) / u);
+    const double qy = floor((sy[i] - y0) / u);
+    // inside by construction of the root; clamp defensively
+    const uint32_t ix = (uint32_t)fmin(fmax(qx, 0.0), lim - 1.0);
+    const uint32_t iy = (uint32_t)fmin(fmax(qy, 0.0), lim - 1.0);
+    k = morton(ix, iy);
+  }
+  key[i] = k;
+  idx[i] = (int)i;
+}
+
+__global__ void k_gather_points(const int* __restrict__ perm, const int* __restrict__ nsrc_dev,
+                                const double* __restrict__ sx, const double* __restrict__ sy,
+                                const double* __restrict__ w, double* __restrict__ xs, double* __restrict__ ys,
+                                double* __restrict__ ws) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *nsrc_dev) return;
+  const int o = perm[i];
+  xs[i] = sx[o];
+  ys[i] = sy[o];
+  ws[i] = w[o];
+}
+
+// One wave per source leaf: offsets from the leaf corner in units of u, FP32
+// (with the weight) and FP64, and the FP64 leaf weight in a fixed order.
+__global__ __launch_bounds__(256) void k_pack_points(TreeArrays t, const int* __restrict__ sleaves, int n, int D,
+                                                      const double* __restrict__ xs, const double* __restrict__ ys,
+                                                      const double* __restrict__ ws, double x0, double y0, double u,
+                                                      float4* __restrict__ src4, double2* __restrict__ s64,
+                                                      double* __restrict__ leaf_w) {
+  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (wid >= n) return;
+  const int lane = threadIdx.x % kWave;
+  const int c = sleaves[wid];
+  const int sh = D - t.lvl[c];
+  const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
+  const int sb = t.sb[c], se = t.se[c];
+  double acc = 0.0;
+  for (int s = sb + lane; s < se; s += kWave) {
+    const double rx = (xs[s] - x0) / u - cx;
+    const double ry = (ys[s] - y0) / u - cy;
+    const double w = ws[s];
+    src4[s] = make_float4((float)rx, (float)ry, (float)w, 0.0f);
+    s64[s] = make_double2(rx, ry);
+    acc += w;
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+  if (lane == 0) leaf_w[c] = acc;
+}
+
+// One wave per target leaf: offsets from the leaf corner (the same FP64
+// operations as for the sources, so coincident points get identical offsets),
+// the owning leaf, and the summed weight of the sources that coincide exactly
+// with the target (they are skipped by the near-field kernel, and the finalize
+// step removes their share of the near weight).
+__global__ __launch_bounds__(256) void k_prep_points(TreeArrays t, const int* __restrict__ tleaves, int n, int D,
+                                                      const double* __restrict__ tx, const double* __restrict__ ty,
+                                                      const int* __restrict__ perm, double x0, double y0, double u,
+                                                      const double* __restrict__ xs, const double* __restrict__ ys,
+                                                      const double* __restrict__ ws, float2* __restrict__ rel32,
+                                                      double2* __restrict__ rel64, int* __restrict__ tleaf,
+                                                      double* __restrict__ self_w) {
+  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (wid >= n) return;
+  const int lane = threadIdx.x % kWave;
+  const int c = tleaves[wid];
+  const int sh = D - t.lvl[c];
+  const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
+  const int tb = t.tb[c], te = t.te[c], sb = t.sb[c], se = t.se[c];
+  for (int k = tb + lane; k < te; k += kWave) {
+    const int o = perm[k];
+    const double x = tx[o], y = ty[o];
+    const double rx = (x - x0) / u - cx;
+    const double ry = (y - y0) / u - cy;
+    double sw = 0.0;
+    for (int s = sb; s < se; ++s)
+      if (xs[s] == x && ys[s] == y) sw += ws[s];
+    rel64[k] = make_double2(rx, ry);
+    rel32[k] = make_float2((float)rx, (float)ry);
+    tleaf[k] = c;
+    self_w[k] = sw;
+  }
+}
+}  // namespace
+
+int points_box_blocks(int64_t n_total) {
+  const int64_t b = (n_total + kBoxBlock * 8 - 1) / (kBoxBlock * 8);
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), 1024);
+}
+
+void points_box(const double* sx, const double* sy, const double* w, int64_t n, const double* tx, const double* ty,
+                int64_t m, double4* part, int* cnt, double* box, int* nsrc, int* flags, hipStream_t s) {
+  const int g = points_box_blocks(n + m);
+  k_box_partial<<<g, kBoxBlock, 0, s>>>(sx, sy, w, n, tx, ty, m, part, cnt, flags);
+  k_box_final<<<1, kBoxBlock, 0, s>>>(part, cnt, g, box, nsrc);
+}
+
+void points_keys(const double* sx, const double* sy, const double* w, int64_t n, double x0, double y0, double u,
+                 int D, uint32_t* key, int* idx, hipStream_t s) {
+  if (n <= 0) return;
+  k_point_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(sx, sy, w, n, x0, y0, u, D, key, idx);
+}
+
+void points_gather(const int* perm, const int* nsrc_dev, int64_t nmax, const double* sx, const double* sy,
+                   const double* w, double* xs, double* ys, double* ws, hipStream_t s) {
+  if (nmax <= 0) return;
+  k_gather_points<<<(unsigned)((nmax + 255) / 256), 256, 0, s>>>(perm, nsrc_dev, sx, sy, w, xs, ys, ws);
+}
+
+void leaf_pack_points(TreeArrays t, const int* sleaves, int nsleaves, int D, const double* xs, const double* ys,
+                      const double* ws, double x0, double y0, double u, float4* src4, double2* s64, double* leaf_w,
+                      hipStream_t s) {
+  if (nsleaves <= 0) return;
+  k_pack_points<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, xs, ys, ws, x0, y0, u, src4, s64, leaf_w);
+}
+
+void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
+                      const int* perm, double x0, double y0, double u, const double* xs, const double* ys,
+                      const double* ws, float2* rel32, double2* rel64, int* tleaf, double* self_w, hipStream_t s) {
+  if (ntleaves <= 0) return;
+  k_prep_points<<<(ntleaves + 3) / 4, 256, 0, s>>>(t, tleaves, ntleaves, D, tx, ty, perm, x0, y0, u, xs, ys, ws,
+                                                    rel32, rel64, tleaf, self_w);
+}
+
+}  // namespace pp

@@ -3,11 +3,13 @@
 // Each slot owns a library context (its device buffers stay resident between
 // requests) and a HIP stream, and is driven by its own host thread; a request
 // is admitted to a free slot as soon as the sum of the estimated device
-// footprints of the requests in flight leaves room for it.  Requests that
-// arrive while others are running therefore start immediately and their
-// kernels overlap on the GPU with the others'.  A request's result does not
-// depend on which slot ran it or on what ran beside it: every slot runs the
-// same deterministic kernels on its own buffers.
+// footprints of the requests in flight leaves room for it, and so does the
+// sum of their work (grid nodes plus targets).  Requests that arrive while
+// others are running therefore start immediately and their kernels overlap on
+// the GPU with the others'; the work bound stops several large requests from
+// dividing the GPU between them, which would stretch each one's latency.  A
+// request's result does not depend on which slot ran it or on what ran beside
+// it: every slot runs the same deterministic kernels on its own buffers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,10 +35,12 @@ struct Job {
   pp_request req{};
   std::vector<double> f_copy, tx_copy, ty_copy;  // host inputs copied at submission
   uint64_t footprint = 0;
+  uint64_t work = 0;
   clk::time_point t_submit, t_start, t_end;
   int slot = -1;
   pp_status status = PP_OK;
   bool done = false;
+  bool cancelled = false;
   std::string err;
 };
 
@@ -62,6 +66,7 @@ struct pp_server {
   std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
   uint64_t next_ticket = 1;
   uint64_t inflight_bytes = 0;
+  uint64_t inflight_work = 0;
   int inflight = 0;
   bool stopping = false;
   std::vector<std::thread> workers;
@@ -99,17 +104,21 @@ void worker_loop(pp_server* s, int slot) {
       s->cv_work.wait(lk, [&] {
         if (s->stopping && s->queue.empty()) return true;
         if (s->queue.empty()) return false;
-        const uint64_t fp = s->queue.front()->footprint;
-        // FIFO admission: the head runs when the memory bound leaves room for it
-        // (always when nothing else is in flight)
-        return s->inflight == 0 || s->cfg.hbm_budget_bytes == 0 ||
-               s->inflight_bytes + fp <= s->cfg.hbm_budget_bytes;
+        const Job& head = *s->queue.front();
+        // FIFO admission: the head runs when the memory and work bounds leave
+        // room for it (always when nothing else is in flight)
+        if (s->inflight == 0) return true;
+        const bool mem_ok = s->cfg.hbm_budget_bytes == 0 || s->inflight_bytes + head.footprint <= s->cfg.hbm_budget_bytes;
+        const bool work_ok =
+            s->cfg.work_budget_points == 0 || s->inflight_work + head.work <= s->cfg.work_budget_points;
+        return mem_ok && work_ok;
       });
       if (s->queue.empty()) return;  // stopping and drained
       job = s->queue.front();
       s->queue.pop_front();
       s->inflight += 1;
       s->inflight_bytes += job->footprint;
+      s->inflight_work += job->work;
       job->slot = slot;
       job->t_start = clk::now();
     }
@@ -133,6 +142,7 @@ void worker_loop(pp_server* s, int slot) {
       job->ty_copy.shrink_to_fit();
       s->inflight -= 1;
       s->inflight_bytes -= job->footprint;
+      s->inflight_work -= job->work;
     }
     s->cv_done.notify_all();
     s->cv_work.notify_all();
@@ -188,6 +198,7 @@ pp_status pp_server_submit(pp_server* s, const pp_request* r, uint64_t* ticket) 
   if (r->m > 0 && host_memory(r->tx)) job->tx_copy.assign(r->tx, r->tx + r->m);
   if (r->m > 0 && host_memory(r->ty)) job->ty_copy.assign(r->ty, r->ty + r->m);
   job->footprint = pp_footprint_estimate(r->nx, r->ny, r->m, r->params.p, r->params.leaf_max);
+  job->work = (uint64_t)ng + (uint64_t)r->m;
   job->t_submit = clk::now();
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -227,6 +238,30 @@ pp_status pp_server_wait(pp_server* s, uint64_t ticket, int64_t timeout_us, pp_t
   if (st != PP_OK) s->err = job->err;
   s->jobs.erase(it);
   return st;
+}
+
+pp_status pp_server_cancel(pp_server* s, uint64_t ticket) {
+  if (!s) return PP_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return PP_ERR_ARG;
+    std::shared_ptr<Job> job = it->second;
+    auto q = std::find(s->queue.begin(), s->queue.end(), job);
+    if (q == s->queue.end()) return PP_ERR_BUSY;  // running or finished
+    s->queue.erase(q);
+    job->cancelled = true;
+    job->done = true;
+    job->status = PP_ERR_CANCELLED;
+    job->err = "cancelled before it started";
+    job->t_start = job->t_end = clk::now();
+    job->f_copy.clear();
+    job->tx_copy.clear();
+    job->ty_copy.clear();
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();  // the next request may now be the head
+  return PP_OK;
 }
 
 pp_status pp_server_destroy(pp_server* s) {

@@ -42,7 +42,8 @@ enum BufId {
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
-  B_DSS, B_DTS, B_DFLAG, B_DOFF,
+  B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
+  B_S64, B_SELFW,
   B_COUNT
 };
 
@@ -66,7 +67,7 @@ constexpr int kMiscInts = 128;
 // [4..9] cell-list and interaction-list totals, [16..17] near-field pair count (u64),
 // [32..32+D+2] level starts of the tree.
 constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7,
-              M_NP2P = 8, M_NITEMS = 9, M_PAIRS = 16, M_LS = 32;
+              M_NP2P = 8, M_NITEMS = 9, M_PAIRS = 16, M_LS = 32, M_BOX = 96;
 
 }  // namespace
 
@@ -165,14 +166,8 @@ void check_flags(int flags) {
   if (flags) throw PPError{PP_ERR_DEVICE, "unknown kernel flag"};
 }
 
-void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m, const double* tx,
-              const double* ty, const pp_params* prm, const double* p_out) {
+void validate_common(int64_t m, const double* tx, const double* ty, const pp_params* prm, const double* p_out) {
   if (!prm) throw PPError{PP_ERR_ARG, "params is null"};
-  if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536 || (int64_t)nx * ny >= ((int64_t)1 << 31))
-    throw PPError{PP_ERR_ARG, "grid size out of range"};
-  if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(x0) || !std::isfinite(y0))
-    throw PPError{PP_ERR_ARG, "h must be positive and finite, x0/y0 finite"};
-  if (!f) throw PPError{PP_ERR_ARG, "f is null"};
   if (m < 0 || m >= ((int64_t)1 << 31)) throw PPError{PP_ERR_ARG, "target count out of range"};
   if (m > 0 && (!tx || !ty || !p_out)) throw PPError{PP_ERR_ARG, "target or output pointer is null"};
   if (prm->p < 1 || prm->p > kMaxP) throw PPError{PP_ERR_ARG, "p must lie in [1, 20]"};
@@ -184,21 +179,52 @@ void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const doub
   if (prm->self_mode != PP_SELF_SKIP && prm->self_mode != PP_SELF_CELLAVG) throw PPError{PP_ERR_ARG, "unknown self mode"};
 }
 
+void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m, const double* tx,
+              const double* ty, const pp_params* prm, const double* p_out) {
+  if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536 || (int64_t)nx * ny >= ((int64_t)1 << 31))
+    throw PPError{PP_ERR_ARG, "grid size out of range"};
+  if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(x0) || !std::isfinite(y0))
+    throw PPError{PP_ERR_ARG, "h must be positive and finite, x0/y0 finite"};
+  if (!f) throw PPError{PP_ERR_ARG, "f is null"};
+  validate_common(m, tx, ty, prm, p_out);
+}
+
+// The two source forms: grid nodes (f on an nx x ny grid of spacing h, weight
+// f h^2) or scattered points with their own weights.
+struct Sources {
+  bool grid = true;
+  int32_t nx = 0, ny = 0;
+  double x0 = 0.0, y0 = 0.0, h = 0.0;
+  const double* f = nullptr;
+  int64_t n = 0;
+  const double* sx = nullptr;
+  const double* sy = nullptr;
+  const double* w = nullptr;
+};
+
+void validate_points(int64_t n, const double* sx, const double* sy, const double* w, int64_t m, const double* tx,
+                     const double* ty, const pp_params* prm, const double* p_out) {
+  if (n < 0 || n >= ((int64_t)1 << 31)) throw PPError{PP_ERR_ARG, "source count out of range"};
+  if (n > 0 && (!sx || !sy || !w)) throw PPError{PP_ERR_ARG, "source pointer is null"};
+  validate_common(m, tx, ty, prm, p_out);
+  if (prm->self_mode != PP_SELF_SKIP)
+    throw PPError{PP_ERR_ARG, "scattered sources support only the skip self rule (there is no cell to average over)"};
+}
+
 // One solve.  Two host round trips: after the tree (its level starts and the
 // cell-list counts size the later launches) and at the end (flags, statistics).
 // `exact_lists` selects the two-pass interaction lists (count, scan, emit);
 // otherwise the lists are written in one pass into a fixed capacity per cell,
 // and a list that does not fit makes the solve report kFlagListOverflow (the
 // caller then repeats it with exact lists).
-pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_t ny, double x0, double y0, double h,
-                    const double* f, int64_t m, const double* tx, const double* ty, const pp_params& prm, double* p_out,
-                    hipStream_t s) {
+pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src, int64_t m, const double* tx,
+                    const double* ty, const pp_params& prm, double* p_out, hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
   HIPCHK(hipSetDevice(c.device));
   c.last.valid = false;
-  const int k = root_exponent(nx, ny);
-  const int D = k;
-  const int64_t ngrid = (int64_t)nx * ny;
+  const int32_t nx = src.grid ? src.nx : 0, ny = src.grid ? src.ny : 0;
+  const int64_t ngrid = src.grid ? (int64_t)nx * ny : 0;
+  const int64_t nmax = src.grid ? ngrid : src.n;  // sources before culling zeros
   const int p = prm.p;
   const int g = std::gcd((int)std::lround(prm.theta * 1000.0), 1000);
   const int num = (int)std::lround(prm.theta * 1000.0) / g, den = 1000 / g;
@@ -209,7 +235,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
     if (c.profiling) HIPCHK(hipEventRecord(c.ev[i], s));
   };
   mark(PP_PHASE_INGEST);
-  const double* f_d = stage_in(c, B_F, f, ngrid, s);
+  const double* f_d = src.grid ? stage_in(c, B_F, src.f, ngrid, s) : nullptr;
   const double* tx_d = stage_in(c, B_TX, tx, m, s);
   const double* ty_d = stage_in(c, B_TY, ty, m, s);
   const bool out_on_device = is_device_ptr(p_out);
@@ -219,30 +245,78 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   unsigned long long* pairs = (unsigned long long*)(misc + M_PAIRS);  // 8-byte aligned slot
   fill_i32(misc, 0, kMiscInts, s);
 
-  // capacities from the grid size (the source count is only known on the device)
-  const int64_t ntiles = ingest_num_tiles(k);
+  // root square: anchor (x0, y0), finest cell side `unit`, finest level D
+  int D = 0;
+  double x0 = 0.0, y0 = 0.0, unit = 1.0;
+  const double *psx = nullptr, *psy = nullptr, *pw = nullptr;
+  if (src.grid) {
+    D = root_exponent(nx, ny);
+    x0 = src.x0;
+    y0 = src.y0;
+    unit = src.h;
+  } else {
+    psx = stage_in(c, B_PSX, src.sx, src.n, s);
+    psy = stage_in(c, B_PSY, src.sy, src.n, s);
+    pw = stage_in(c, B_PW, src.w, src.n, s);
+    const int nb = points_box_blocks(src.n + m);
+    double* box = (double*)(misc + M_BOX);
+    points_box(psx, psy, pw, src.n, tx_d, ty_d, m, ensure<double4>(c, B_BOXP, nb), ensure<int>(c, B_BOXC, nb), box,
+               misc + M_NSRC, misc + M_FLAGS, s);
+    readback(c, misc, 0, M_BOX + 8, s);
+    check_flags(c.pinned[M_FLAGS]);
+    double bx[4];
+    std::memcpy(bx, c.pinned + M_BOX, sizeof(bx));
+    D = kPointsDepth;
+    x0 = bx[0];
+    y0 = bx[2];
+    // the same FP64 differences the key kernels form for the extreme points
+    const double ext = std::max(bx[1] - bx[0], bx[3] - bx[2]);
+    unit = 1.0;
+    if (ext > 0.0) {
+      int e = std::ilogb(ext) - D;
+      while (std::ldexp(1.0, e + D) <= ext) ++e;
+      while (e > -1000 && std::ldexp(1.0, e + D - 1) > ext) --e;
+      unit = std::ldexp(1.0, e);
+    }
+  }
+  const int k = D;
+
+  // capacities from the input sizes (the source count is only known on the device)
+  const int64_t ntiles = src.grid ? ingest_num_tiles(k) : 1;
   int64_t geo = 0;
   for (int l = 0; l <= D; ++l) geo += (int64_t)1 << (2 * l);
-  const int64_t per_level = 4 * (ngrid / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
+  const int64_t per_level = 4 * (nmax / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
   const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
   if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
-  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(
-                            std::max<int64_t>({ntiles, 4 * per_level, 3 * cap, m, tree_dense_cells(std::min(D, c.dense_levels)), 1})));
+  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max<int64_t>(
+                            {ntiles, 4 * per_level, 3 * cap, m, nmax, tree_dense_cells(std::min(D, c.dense_levels)), 1})));
 
-  // ---- ingest: sources in Morton order (no sort needed for a grid) ----
-  int* tile = ensure<int>(c, B_TILE, ntiles);
-  ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
-  scan_exclusive(tile, tile, ntiles, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ntiles)), misc + M_NSRC, s);
-  uint32_t* skey = ensure<uint32_t>(c, B_SKEY, ngrid);
-  uint32_t* sij = ensure<uint32_t>(c, B_SIJ, ngrid);
-  double* sw = ensure<double>(c, B_SW, ngrid);
-  ingest_grid_emit(f_d, nx, ny, k, h * h, tile, skey, sij, sw, s);
+  uint32_t* skey = ensure<uint32_t>(c, B_SKEY, nmax);
+  uint32_t* sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
+  double* sw = ensure<double>(c, B_SW, nmax);
+  double *pxs = nullptr, *pys = nullptr;
+  if (src.grid) {
+    // ---- ingest: sources in Morton order (no sort needed for a grid) ----
+    int* tile = ensure<int>(c, B_TILE, ntiles);
+    ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
+    scan_exclusive(tile, tile, ntiles, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ntiles)), misc + M_NSRC, s);
+    ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, skey, sij, sw, s);
+  } else if (src.n > 0) {
+    // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
+    int* sperm = (int*)sij;
+    points_keys(psx, psy, pw, src.n, x0, y0, unit, D, skey, sperm, s);
+    radix_sort_pairs(skey, sperm, ensure<uint32_t>(c, B_SKEY2, src.n), ensure<int>(c, B_SPERM2, src.n), src.n, 32,
+                     ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(src.n)), s);
+    pxs = ensure<double>(c, B_PXS, src.n);
+    pys = ensure<double>(c, B_PYS, src.n);
+    points_gather(sperm, misc + M_NSRC, src.n, psx, psy, pw, pxs, pys, sw, s);
+  }
 
   // ---- targets: Morton keys and a stable radix sort ----
   mark(PP_PHASE_SORT);
   uint32_t* tkey = ensure<uint32_t>(c, B_TKEY, m);
   int* tperm = ensure<int>(c, B_TPERM, m);
-  target_keys(tx_d, ty_d, m, x0, y0, h, k, tkey, tperm, misc + M_FLAGS, s);
+  target_keys(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, misc + M_FLAGS, s);
   radix_sort_pairs(tkey, tperm, ensure<uint32_t>(c, B_TKEY2, m), ensure<int>(c, B_TPERM2, m), m, 2 * k,
                    ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(m)), s);
 
@@ -342,14 +416,26 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   mark(PP_PHASE_PACK);
   float4* src4 = ensure<float4>(c, B_SRC4, N);
   double* leaf_w = ensure<double>(c, B_LEAFW, ncells);
-  leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
   float2* rel32 = ensure<float2>(c, B_REL32, m);
   double2* rel64 = ensure<double2>(c, B_REL64, m);
   int* tgtleaf = ensure<int>(c, B_TGTLEAF, m);
-  int* selfi = ensure<int>(c, B_SELFI, m);
-  double* selfd = ensure<double>(c, B_SELFD, m);
-  leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, h, nx, ny, mixed ? 0x1p-40 : 0.0, rel32, rel64,
-                    tgtleaf, selfi, selfd, s);
+  int* selfi = nullptr;
+  double* selfd = nullptr;
+  double* selfw = nullptr;
+  double2* s64 = nullptr;
+  if (src.grid) {
+    leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
+    selfi = ensure<int>(c, B_SELFI, m);
+    selfd = ensure<double>(c, B_SELFD, m);
+    leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, rel32,
+                      rel64, tgtleaf, selfi, selfd, s);
+  } else {
+    s64 = ensure<double2>(c, B_S64, N);
+    selfw = ensure<double>(c, B_SELFW, m);
+    leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, s);
+    leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf, selfw,
+                     s);
+  }
 
   // ---- expansions: upward and downward passes ----
   double* far = nullptr;
@@ -359,7 +445,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
     double2* own = ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
     far = ensure<double>(c, B_FAR, m);
     mark(PP_PHASE_P2M);
-    p2m(tv, sleaves, nsl, src4, sw, p, mp, s);
+    p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
     mark(PP_PHASE_M2M);
     // the recursion from the finest level up, three levels per launch
     for (int top = depth - 1; top >= 0; top -= 3) {
@@ -367,7 +453,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
       m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
     }
     mark(PP_PHASE_M2L);
-    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, h, mp, own, misc + M_FLAGS, s);
+    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
     mark(PP_PHASE_L2L);
     downward(tv, tcells, ntc, p, own, loc, s);
     mark(PP_PHASE_L2P);
@@ -392,6 +478,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   pa.sleaves = sleaves;
   pa.nsleaves = nsl;
   pa.src4 = src4;
+  pa.s64 = s64;
   pa.w64 = sw;
   pa.leaf_w = leaf_w;
   pa.rel32 = rel32;
@@ -408,8 +495,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   // ---- finalize ----
   mark(PP_PHASE_FINALIZE);
   p2p_count_pairs(pa, s);
-  finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, f_d, h, prm.self_mode, misc + M_FLAGS,
-           out_d, s);
+  finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, selfw, f_d, unit, prm.self_mode,
+           misc + M_FLAGS, out_d, s);
   mark(12);
   readback(c, misc, 0, M_PAIRS + 2, s);
   const int flags = c.pinned[M_FLAGS];
@@ -458,23 +545,25 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, int32_t nx, int32_
   return PP_OK;
 }
 
-pp_status guard(pp_ctx* c, bool direct, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
-                int64_t m, const double* tx, const double* ty, const pp_params* prm, double* p_out, void* stream) {
+pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const double* tx, const double* ty,
+                const pp_params* prm, double* p_out, void* stream) {
   if (!c) return PP_ERR_ARG;
   if (c->dead) {
     c->err = "context is unusable after a device error";
     return PP_ERR_DEVICE;
   }
   try {
-    validate(nx, ny, x0, y0, h, f, m, tx, ty, prm, p_out);
+    if (src.grid)
+      validate(src.nx, src.ny, src.x0, src.y0, src.h, src.f, m, tx, ty, prm, p_out);
+    else
+      validate_points(src.n, src.sx, src.sy, src.w, m, tx, ty, prm, p_out);
     if (m == 0) return PP_OK;
-    pp_status st = run_solve(*c, direct, c->exact_lists, nx, ny, x0, y0, h, f, m, tx, ty, *prm, p_out,
-                             (hipStream_t)stream);
+    pp_status st = run_solve(*c, direct, c->exact_lists, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
     if (st == PP_ERR_LIMIT) {
       // a list outgrew its per-cell capacity: make room for next time and redo this solve exactly
       c->cap_m2l *= 2;
       c->cap_p2p *= 2;
-      st = run_solve(*c, direct, true, nx, ny, x0, y0, h, f, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+      st = run_solve(*c, direct, true, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
     }
     c->err.clear();
     return st;
@@ -488,6 +577,28 @@ pp_status guard(pp_ctx* c, bool direct, int32_t nx, int32_t ny, double x0, doubl
     c->last.valid = false;
     return PP_ERR_DEVICE;
   }
+}
+
+Sources grid_sources(int32_t nx, int32_t ny, double x0, double y0, double h, const double* f) {
+  Sources q;
+  q.grid = true;
+  q.nx = nx;
+  q.ny = ny;
+  q.x0 = x0;
+  q.y0 = y0;
+  q.h = h;
+  q.f = f;
+  return q;
+}
+
+Sources point_sources(int64_t n, const double* sx, const double* sy, const double* w) {
+  Sources q;
+  q.grid = false;
+  q.n = n;
+  q.sx = sx;
+  q.sy = sy;
+  q.w = w;
+  return q;
 }
 
 }  // namespace
@@ -536,12 +647,22 @@ void pp_destroy(pp_ctx* c) {
 
 pp_status pp_solve_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                         const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
-  return guard(c, false, nx, ny, x0, y0, h, f, m, tx, ty, params, p_out, stream);
+  return guard(c, false, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_solve_points(pp_ctx* c, int64_t n, const double* sx, const double* sy, const double* w, int64_t m,
+                          const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
+  return guard(c, false, point_sources(n, sx, sy, w), m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_direct_points(pp_ctx* c, int64_t n, const double* sx, const double* sy, const double* w, int64_t m,
+                           const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
+  return guard(c, true, point_sources(n, sx, sy, w), m, tx, ty, params, p_out, stream);
 }
 
 pp_status pp_direct_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                          const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
-  return guard(c, true, nx, ny, x0, y0, h, f, m, tx, ty, params, p_out, stream);
+  return guard(c, true, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
 }
 
 pp_status pp_set_profiling(pp_ctx* c, int32_t on) {
@@ -625,6 +746,9 @@ const char* pp_status_string(pp_status s) {
     case PP_ERR_NOMEM: return "device-memory budget exceeded";
     case PP_ERR_DEVICE: return "device error";
     case PP_ERR_LIMIT: return "internal limit exceeded";
+    case PP_ERR_TIMEOUT: return "timed out";
+    case PP_ERR_CANCELLED: return "cancelled";
+    case PP_ERR_BUSY: return "already started";
     default: return "unknown status";
   }
 }

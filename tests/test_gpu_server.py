@@ -106,3 +106,36 @@ def test_failing_request_reports_its_own_status(pp):
         else:
             srv.wait(t)
     srv.close()
+
+
+def test_work_budget_admission(pp):
+    """With a work bound, the requests running together never exceed it (a lone request always runs)."""
+    reqs = _requests(n=10, seed=12)
+    works = [r["g"].nx * r["g"].ny + r["tx"].size for r in reqs]
+    budget = max(works)
+    srv = pp.Server(0, max_slots=4, work_budget_points=budget)
+    outs = [np.empty(r["tx"].size) for r in reqs]
+    tickets = [srv.submit(r["f"], r["g"].h, r["tx"], r["ty"], o) for r, o in zip(reqs, outs)]
+    infos = [srv.wait(t) for t in tickets]
+    srv.close()
+    for i, a in enumerate(infos):
+        running = [j for j, b in enumerate(infos) if b["start_us"] <= a["start_us"] < b["end_us"]]
+        assert sum(works[j] for j in running) <= budget or len(running) == 1, (i, running)
+
+
+def test_cancel_queued_request(pp):
+    """A request still in the queue can be withdrawn; its output stays untouched."""
+    reqs = _requests(n=6, seed=13)
+    srv = pp.Server(0, max_slots=1)
+    outs = [np.full(r["tx"].size, 7.0) for r in reqs]
+    tickets = [srv.submit(r["f"], r["g"].h, r["tx"], r["ty"], o) for r, o in zip(reqs, outs)]
+    assert srv.cancel(tickets[-1]) is True  # one slot: the last cannot have started yet
+    for t in tickets[:-1]:
+        srv.wait(t)
+    with pytest.raises(pp.PPError) as e:
+        srv.wait(tickets[-1])
+    assert e.value.status == -7
+    assert np.all(outs[-1] == 7.0)
+    with pytest.raises(pp.PPError):  # released by its wait: an unknown ticket now
+        srv.cancel(tickets[-1])
+    srv.close()

@@ -228,6 +228,29 @@ def fish_surface_targets(n_per_side: int, h: float, yc: float = 0.5, amp: float 
     return sx, sy, lx, ly
 
 
+def stretched_axis(n: int, beta: float = 2.0, centre: float = 0.5):
+    """Cell centres and widths of a 1-D grid on [0, 1] refined towards `centre`:
+    edges proportional to sinh(beta (u - centre)) for uniform u, shifted and
+    scaled so that the first edge is 0 and the last is 1."""
+    u = np.linspace(0.0, 1.0, n + 1)
+    e = np.sinh(beta * (u - centre))
+    e = (e - e[0]) / (e[-1] - e[0])
+    return 0.5 * (e[1:] + e[:-1]), np.diff(e)
+
+
+def stretched_sources(n: int, seed, n_vortices: int = 64, beta: float = 2.0, rho: float = 1.0):
+    """Scattered sources with their own cell areas: the cell centres of an n x n
+    tensor-product grid stretched towards (0.5, 0.5), with f the Lamb-Oseen
+    source 2 rho (u_x v_y - u_y v_x) at each centre and w = f dx_i dy_j."""
+    cx, dx = stretched_axis(n, beta)
+    xx, yy = np.meshgrid(cx, cx)
+    ax, ay = np.meshgrid(dx, dx)
+    centres, gamma, rc = lamb_oseen_params(seed, n_vortices)
+    ux, uy, vx, vy = vortex_velocity_gradients(xx.ravel(), yy.ravel(), centres, gamma, rc)
+    f = 2.0 * rho * (ux * vy - uy * vx)
+    return xx.ravel(), yy.ravel(), f * (ax * ay).ravel()
+
+
 def _flat_nodes(g: GridSpec):
     x, y = grid_nodes(g)
     return x.ravel(), y.ravel()
@@ -298,6 +321,16 @@ def _envelope4096():
                 n_grid_targets=0, seed=5,
                 desc="4096x4096 vortex source times a two-band Gaussian envelope (width 0.02), sources with"
                      " envelope < 1e-16 set to zero; 16384 surface + 16384 lifted targets; p=12, theta=0.5")
+
+
+def points_workload(n: int = 256, n_ellipse: int = 2048, seed=6):
+    """Scattered-source case: the stretched-grid sources of `stretched_sources`
+    (n x n), targets = every 7th source position (exact coincidences) plus an
+    ellipse of n_ellipse points; p = 12, theta = 0.5."""
+    sx, sy, w = stretched_sources(n, seed)
+    ex, ey = ellipse_targets(n_ellipse)
+    return dict(name=f"stretched{n}", sx=sx, sy=sy, w=w, tx=np.concatenate([sx[::7], ex]),
+                ty=np.concatenate([sy[::7], ey]), p=12, theta=0.5, seed=seed)
 
 
 WORKLOADS = {
