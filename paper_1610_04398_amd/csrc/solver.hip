@@ -272,6 +272,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // the same FP64 differences the key kernels form for the extreme points
     const double ext = std::max(bx[1] - bx[0], bx[3] - bx[2]);
     unit = 1.0;
+    if (ext > 0.0 && ext < 1e-280) throw PPError{PP_ERR_ARG, "the points span less than 1e-280"};
     if (ext > 0.0) {
       int e = std::ilogb(ext) - D;
       while (std::ldexp(1.0, e + D) <= ext) ++e;
@@ -305,8 +306,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
     int* sperm = (int*)sij;
     points_keys(psx, psy, pw, src.n, x0, y0, unit, D, skey, sperm, s);
+    // sized for this sort and the target sort below, so neither reallocates it
+    int* sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.n, m)));
     radix_sort_pairs(skey, sperm, ensure<uint32_t>(c, B_SKEY2, src.n), ensure<int>(c, B_SPERM2, src.n), src.n, 32,
-                     ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(src.n)), s);
+                     sort_tmp, s);
     pxs = ensure<double>(c, B_PXS, src.n);
     pys = ensure<double>(c, B_PYS, src.n);
     points_gather(sperm, misc + M_NSRC, src.n, psx, psy, pw, pxs, pys, sw, s);
