@@ -92,7 +92,7 @@ def serving_run(pp, G, args, log):
     arrivals -= arrivals[0]
 
     def run(slots):
-        srv = pp.Server(0, max_slots=slots)
+        srv = pp.Server(0, max_slots=slots, work_budget_points=args.serve_work_budget if slots > 1 else 0)
         outs = [torch.empty(r["tx"].numel(), dtype=torch.float64, device="cuda") for r in reqs]
         tickets = [None] * len(reqs)
         start = time.perf_counter()
@@ -114,7 +114,8 @@ def serving_run(pp, G, args, log):
         lat = [i["total_us"] / 1e3 for i in infos]
         same = all(bool(torch.equal(o, a)) for o, a in zip(outs, alone))
         return {"p50_ms": _percentile(lat, 50), "p99_ms": _percentile(lat, 99), "mean_ms": float(np.mean(lat)),
-                "solves_per_s": len(reqs) / (makespan * 1e-6), "slots": slots, "identical_to_alone": same}
+                "solves_per_s": len(reqs) / (makespan * 1e-6), "slots": slots,
+                "work_budget_points": args.serve_work_budget if slots > 1 else 0, "identical_to_alone": same}
 
     log("[bench] serving: one-slot (sequential) path")
     seq = run(1)
@@ -141,6 +142,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-work-budget", type=int, default=0,
+                    help="server admission bound on in-flight grid nodes + targets (0: none)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / sequential solves per second")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the known-size kernel that scales "
