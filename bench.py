@@ -117,10 +117,18 @@ def serving_run(pp, G, args, log):
                 "solves_per_s": len(reqs) / (makespan * 1e-6), "slots": slots,
                 "work_budget_points": args.serve_work_budget if slots > 1 else 0, "identical_to_alone": same}
 
+    def median_run(slots):
+        # the same trace replayed args.serve_reps times; the run with the median p99 is reported
+        runs = sorted((run(slots) for _ in range(args.serve_reps)), key=lambda r: r["p99_ms"])
+        out = dict(runs[len(runs) // 2])
+        out["p99_ms_runs"] = [r["p99_ms"] for r in runs]
+        out["identical_to_alone"] = all(r["identical_to_alone"] for r in runs)
+        return out
+
     log("[bench] serving: one-slot (sequential) path")
-    seq = run(1)
+    seq = median_run(1)
     log(f"[bench] serving: {args.serve_slots}-slot path")
-    srv = run(args.serve_slots)
+    srv = median_run(args.serve_slots)
     sizes = [r["grid"].nx for r in reqs]
     return {"requests": len(reqs), "arrival": f"Poisson, rate {lam:.1f}/s = {args.serve_load} x sequential "
                                                f"throughput ({seq_rate:.1f} solves/s)",
@@ -141,7 +149,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256, help="requests in the serving stream (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-reps", type=int, default=3, help="replays of the arrival trace per path (median p99)")
     ap.add_argument("--serve-work-budget", type=int, default=0,
                     help="server admission bound on in-flight grid nodes + targets (0: none)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / sequential solves per second")

@@ -257,6 +257,32 @@ def test_points_entry_matches_grid_entry():
     assert np.max(np.abs(Pg - Pp)) < 1e-14 * float(np.sum(np.abs(f)) * h * h)
 
 
+def test_points_tiny_brute_force_mpmath():
+    """Scattered sources with their own weights (some zero, some coincident with targets) vs a
+    50-digit evaluation of eq. greenSum with G(0) := 0: pins the points entry on its own."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 60
+    sx = rng.uniform(-1.0, 2.0, n)
+    sy = rng.uniform(0.0, 0.5, n)
+    w = rng.standard_normal(n) * rng.uniform(0.1, 3.0, n)
+    w[::9] = 0.0
+    tx = np.concatenate([sx[:10], rng.uniform(-1.5, 2.5, 20)])
+    ty = np.concatenate([sy[:10], rng.uniform(-0.5, 1.0, 20)])
+    P = direct.direct_points(sx, sy, w, tx, ty)
+    for k in range(tx.size):
+        acc = mpmath.mpf(0)
+        for i in range(n):
+            dx = mpmath.mpf(float(tx[k])) - mpmath.mpf(float(sx[i]))
+            dy = mpmath.mpf(float(ty[k])) - mpmath.mpf(float(sy[i]))
+            if dx == 0 and dy == 0:
+                continue
+            acc += mpmath.mpf(float(w[i])) * mpmath.log(mpmath.sqrt(dx * dx + dy * dy))
+        ref = float(acc / (2 * mpmath.pi))
+        assert abs(P[k] - ref) <= 1e-14 * max(abs(ref), 1e-300) + 1e-16 * float(np.sum(np.abs(w)))
+
+
 def test_thread_count_does_not_change_bits():
     """Static schedule over targets and fixed source order: bitwise identical for 1 and N threads."""
     import subprocess
