@@ -23,6 +23,7 @@
 //     a'_l(parent) += -a_0 d^l / l + sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k(child)
 //   L2P: far(z) = Re sum_l L'_l u^l,  u = (z - z_c) / s.
 #include <algorithm>
+#include <mutex>
 
 #include "blockscan.h"
 #include "internal.h"
@@ -138,36 +139,48 @@ __device__ inline cplx m2m_coeff(int l, int nk, const double2* __restrict__ e, i
   return b;
 }
 
-// M2M for up to three levels per launch (eq. expandedShift applied
+// M2M for up to four levels per launch (eq. expandedShift applied
 // recursively from the finest level up).  One workgroup per cell R at level L
-// computes, bottom up, the expansions of R's grandchildren (level L+2),
-// children (L+1) and R itself from the final expansions one level below the
-// subtree.  The subtree's structure is read level by level with one thread
-// per cell; then every expansion the subtree needs from global memory (the
-// level below it and the leaves inside it) is staged into LDS in one parallel
-// sweep, so the arithmetic never waits on a global load.  Leaves keep their
-// P2M expansions.
+// computes, bottom up, the expansions of R's descendants at levels L+3, L+2,
+// L+1 and of R itself from the final expansions one level below the subtree.
+// The subtree's structure is read level by level with one thread per cell;
+// then every expansion the subtree needs from global memory (the level below
+// it and the leaves inside it) is staged into LDS in one parallel sweep, so
+// the arithmetic never waits on a global load.  Leaves keep their P2M
+// expansions.
 constexpr int kM2MThreads = 256;
-constexpr int kM2MSlots = 85;
-__global__ __launch_bounds__(kM2MThreads) void k_m2m3(TreeView t, int c0, int c1, int levels, int p,
-                                                       double2* __restrict__ mp) {
-  // slots: [0] = R, [1..4] its children, [5..20] grandchildren (4 per child),
-  // [21..84] the level below the subtree (children of the deepest computed slots)
-  __shared__ int cell[kM2MSlots], kid0[kM2MSlots], nkid[kM2MSlots], hsrc[kM2MSlots], quad[kM2MSlots];
-  __shared__ double2 e[kM2MSlots * (kMaxP + 1)];
+constexpr int kM2MLevels = 4;
+constexpr int kM2MSlots = 341;  // 1 + 4 + 16 + 64 + 256
+__host__ __device__ constexpr int m2m_first(int d) { return ((1 << (2 * d)) - 1) / 3; }
+
+// LDS: five int arrays of kM2MSlots (padded to a 16-byte boundary), then the
+// expansions; 121 KB at p = 20, within gfx950's 160 KB per workgroup.
+constexpr int kM2MIntWords = 5 * kM2MSlots + 3;
+size_t m2m_lds_bytes(int p) { return kM2MIntWords * sizeof(int) + (size_t)kM2MSlots * (p + 1) * sizeof(double2); }
+
+__global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1, int levels, int p,
+                                                      double2* __restrict__ mp) {
+  // slots: [0] = R, [1..4] its children, [5..20] grandchildren (4 per parent
+  // slot), ... ; depth d holds slots [m2m_first(d), m2m_first(d + 1)).
+  extern __shared__ int smem[];
+  int* cell = smem;
+  int* kid0 = cell + kM2MSlots;
+  int* nkid = kid0 + kM2MSlots;
+  int* hsrc = nkid + kM2MSlots;
+  int* quad = hsrc + kM2MSlots;
+  double2* e = (double2*)(smem + kM2MIntWords);
   const int R = c0 + blockIdx.x;
   if (R >= c1) return;
   const int P1 = p + 1;
   const int tid = threadIdx.x;
-  const int first[5] = {0, 1, 5, 21, 85};
   for (int d = 0; d <= levels; ++d) {
-    const int lo = first[d], hi = first[d + 1];
+    const int lo = m2m_first(d), hi = m2m_first(d + 1);
     for (int i = lo + tid; i < hi; i += blockDim.x) {
       int c = -1;
       if (d == 0) {
         c = R;
       } else {
-        const int par = (d == 1) ? 0 : first[d - 1] + (i - lo) / 4;
+        const int par = m2m_first(d - 1) + (i - lo) / 4;
         const int q = (i - lo) % 4;
         if (cell[par] >= 0 && hsrc[par] && q < nkid[par] && kid0[par] >= 0) c = kid0[par] + q;
       }
@@ -180,21 +193,22 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m3(TreeView t, int c0, int c1
     __syncthreads();
   }
   // stage: slots of depth `levels`, and leaves above it, hold final expansions
-  const int nstage = first[levels + 1];
+  const int nstage = m2m_first(levels + 1);
+  const int deepest = m2m_first(levels);
   for (int w = tid; w < nstage * P1; w += blockDim.x) {
     const int i = w / P1, l = w % P1;
     const int c = cell[i];
     if (c < 0 || !hsrc[i]) continue;
-    if (i >= first[levels] || kid0[i] < 0) e[i * P1 + l] = mp[(int64_t)c * P1 + l];
+    if (i >= deepest || kid0[i] < 0) e[i * P1 + l] = mp[(int64_t)c * P1 + l];
   }
   __syncthreads();
   for (int d = levels - 1; d >= 0; --d) {
-    const int lo = first[d], hi = first[d + 1];
+    const int lo = m2m_first(d), hi = m2m_first(d + 1);
     for (int w = tid; w < (hi - lo) * P1; w += blockDim.x) {
       const int i = lo + w / P1, l = w % P1;
       const int c = cell[i];
       if (c < 0 || !hsrc[i] || kid0[i] < 0) continue;
-      const int slot0 = first[d + 1] + 4 * (i - lo);
+      const int slot0 = m2m_first(d + 1) + 4 * (i - lo);
       const cplx v = m2m_coeff(l, nkid[i], e, P1, slot0, hsrc, quad);
       e[i * P1 + l] = make_double2(v.x, v.y);
       mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
@@ -376,9 +390,16 @@ void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double
   PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, src4, s64, w64, p, mp);
 }
 
+int m2m_max_levels() { return kM2MLevels; }
+
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s) {
   if (c1 <= c0 || levels < 1) return;
-  k_m2m3<<<c1 - c0, kM2MThreads, 0, s>>>(t, c0, c1, std::min(levels, 3), p, mp);
+  static std::once_flag lds_opt_in;
+  std::call_once(lds_opt_in, [] {
+    (void)hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)m2m_lds_bytes(kMaxP));
+  });
+  k_m2m<<<c1 - c0, kM2MThreads, m2m_lds_bytes(p), s>>>(t, c0, c1, std::min(levels, kM2MLevels), p, mp);
 }
 
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,

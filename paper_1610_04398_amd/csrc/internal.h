@@ -109,24 +109,26 @@ void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, co
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p
 // (indexed by cell id), pass 1 writes the lists at off_m2l / off_p2p (by cell id).
-// Packed per-cell records used by the traversal (ncells int4).
-void cell_records(TreeView t, int4* rec, hipStream_t s);
+// Packed per-cell records used by the traversal (ncells int4); clears the
+// list counts, and for cap_m > 0 writes the one-pass offsets cell * cap.
+void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
+                  hipStream_t s);
 // emit 0: counts only; 1: write at the exact offsets of a count pass;
 // 2: one pass, counts plus lists at cell * cap (kFlagListOverflow if a list
 // is longer than its capacity; its tail is then dropped).
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
                 int* flags, hipStream_t s);
-// off_m[c] = c * cap_m, off_p[c] = c * cap_p (CSR view of the fixed-capacity lists).
-void capacity_offsets(int ncells, int cap_m, int cap_p, int* off_m, int* off_p, hipStream_t s);
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
 // P2M of every source leaf (one wave per leaf).
 // s64 (may be null): FP64 source offsets; without it the FP32 offsets of src4
 // are used (exact for grid nodes).
 void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double2* s64, const double* w64, int p,
          double2* mp, hipStream_t s);
-// M2M for the `levels` (1..3) levels starting at the level whose cells are
-// [c0, c1): one workgroup per cell computes its subtree bottom up.
+// M2M for the `levels` (1..m2m_max_levels()) levels starting at the level
+// whose cells are [c0, c1): one workgroup per cell computes its subtree
+// bottom up.
+int m2m_max_levels();
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, int* flags, hipStream_t s);
@@ -163,8 +165,11 @@ struct P2PArgs {
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };
 void p2p(const P2PArgs& a, int fp64, hipStream_t s);
-// Total (target, source) pairs of the last p2p launch into a.pairs.
-void p2p_count_pairs(const P2PArgs& a, hipStream_t s);
+// Totals for the statistics, one workgroup in a fixed order: the (target,
+// source) pairs of the last p2p launch into a.pairs and, if cnt_m2l is set,
+// the list lengths of the ncells cells into *tot_m2l and *tot_p2p.
+void p2p_totals(const P2PArgs& a, const int* cnt_m2l, const int* cnt_p2p, int ncells, int* tot_m2l, int* tot_p2p,
+                hipStream_t s);
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.

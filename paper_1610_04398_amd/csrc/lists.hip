@@ -32,9 +32,19 @@ __device__ inline int rec_nchild(int4 r) { return (r.w >> 5) & 7; }
 __device__ inline int rec_kidmask(int4 r) { return (r.w >> 8) & 15; }
 __device__ inline bool rec_has_src(int4 r) { return (r.w >> 12) & 1; }
 
-__global__ void k_records(TreeView t, int n, int4* __restrict__ rec) {
+// Also clears the per-cell list counts and, for the one-pass lists
+// (cap_m > 0), writes the fixed-capacity offsets c * cap.
+__global__ void k_records(TreeView t, int n, int4* __restrict__ rec, int* __restrict__ cnt_m2l,
+                          int* __restrict__ cnt_p2p, int* __restrict__ off_m2l, int* __restrict__ off_p2p, int cap_m,
+                          int cap_p) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
+  cnt_m2l[c] = 0;
+  cnt_p2p[c] = 0;
+  if (cap_m > 0) {
+    off_m2l[c] = c * cap_m;
+    off_p2p[c] = c * cap_p;
+  }
   const int k0 = t.child[c], nk = t.nchild[c];
   int mask = 0;
   for (int q = 0; q < nk; ++q) mask |= (t.se[k0 + q] > t.sb[k0 + q]) ? (1 << q) : 0;
@@ -158,9 +168,11 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
 
 }  // namespace
 
-void cell_records(TreeView t, int4* rec, hipStream_t s) {
+void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
+                  hipStream_t s) {
   if (t.ncells <= 0) return;
-  k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(t, t.ncells, rec);
+  k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(t, t.ncells, rec, cnt_m2l, cnt_p2p, off_m2l, off_p2p, cap_m,
+                                                    cap_p);
 }
 
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
@@ -170,20 +182,6 @@ void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int
   k_lists<<<(ntcells + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
       t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
       cap_m, cap_p, flags);
-}
-
-namespace {
-__global__ void k_capacity_offsets(int n, int cap_m, int cap_p, int* __restrict__ off_m, int* __restrict__ off_p) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  off_m[c] = c * cap_m;
-  off_p[c] = c * cap_p;
-}
-}  // namespace
-
-void capacity_offsets(int ncells, int cap_m, int cap_p, int* off_m, int* off_p, hipStream_t s) {
-  if (ncells <= 0) return;
-  k_capacity_offsets<<<(ncells + 255) / 256, 256, 0, s>>>(ncells, cap_m, cap_p, off_m, off_p);
 }
 
 }  // namespace pp

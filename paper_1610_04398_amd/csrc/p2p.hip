@@ -207,19 +207,36 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
   if (bad && lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
 }
 
-// Sum of the per-wave pair counts (one workgroup, fixed order).
-__global__ __launch_bounds__(1024) void k_sum_pairs(const long long* __restrict__ v, int n,
-                                                    unsigned long long* __restrict__ out) {
-  __shared__ long long part[1024];
-  long long acc = 0;
+// Statistics totals in one workgroup (integer sums, so the order does not
+// matter): the per-wave pair counts and, optionally, the per-cell list lengths.
+__global__ __launch_bounds__(1024) void k_totals(const long long* __restrict__ v, int n,
+                                                 unsigned long long* __restrict__ out, const int* __restrict__ cm,
+                                                 const int* __restrict__ cp, int ncells, int* __restrict__ tot_m,
+                                                 int* __restrict__ tot_p) {
+  __shared__ long long part[3][1024];
+  long long acc = 0, am = 0, ap = 0;
   for (int i = threadIdx.x; i < n; i += 1024) acc += v[i];
-  part[threadIdx.x] = acc;
+  if (cm)
+    for (int i = threadIdx.x; i < ncells; i += 1024) {
+      am += cm[i];
+      ap += cp[i];
+    }
+  part[0][threadIdx.x] = acc;
+  part[1][threadIdx.x] = am;
+  part[2][threadIdx.x] = ap;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += part[q][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = (unsigned long long)part[0];
+  if (threadIdx.x == 0) {
+    if (out) *out = (unsigned long long)part[0][0];
+    if (cm) {
+      *tot_m = (int)part[1][0];
+      *tot_p = (int)part[2][0];
+    }
+  }
 }
 }  // namespace
 
@@ -241,10 +258,13 @@ void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
   }
 }
 
-void p2p_count_pairs(const P2PArgs& a, hipStream_t s) {
+void p2p_totals(const P2PArgs& a, const int* cnt_m2l, const int* cnt_p2p, int ncells, int* tot_m2l, int* tot_p2p,
+                hipStream_t s) {
   const int64_t waves = (int64_t)a.ntleaves * a.nparts;
-  if (waves <= 0 || !a.pair_counts || !a.pairs) return;
-  k_sum_pairs<<<1, 1024, 0, s>>>(a.pair_counts, (int)waves, a.pairs);
+  const bool pairs = waves > 0 && a.pair_counts && a.pairs;
+  if (!pairs && !cnt_m2l) return;
+  k_totals<<<1, 1024, 0, s>>>(a.pair_counts, pairs ? (int)waves : 0, pairs ? a.pairs : nullptr, cnt_m2l, cnt_p2p,
+                              ncells, tot_m2l, tot_p2p);
 }
 
 }  // namespace pp

@@ -5,7 +5,8 @@
 // level of the tree can be compacted without a host round trip); grids are then
 // sized for an upper bound and surplus workgroups exit.  Up to kSmallMax
 // elements one workgroup scans everything in a single launch; larger inputs use
-// tile reductions, a one-workgroup scan of the tile sums, and tile scans.
+// tile reductions and then tile scans that each add up the tile sums before
+// their own.
 #include "blockscan.h"
 #include "internal.h"
 
@@ -72,31 +73,26 @@ __global__ __launch_bounds__(kScanBlock) void scan_tile_reduce(const int* __rest
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
-// One workgroup: exclusive scan of the tile sums in place; grand total to *total_out.
-__global__ __launch_bounds__(kScanBlock) void scan_partials(int* __restrict__ partial, int64_t n_host,
-                                                             const int* __restrict__ n_dev,
-                                                             int* __restrict__ total_out) {
-  __shared__ int lds[kScanBlock / kWave + 1];
-  const int64_t n = count_of(n_host, n_dev);
-  const int nb = (int)((n + kScanTile - 1) / kScanTile);
-  int carry = 0;
-  for (int base = 0; base < nb; base += kScanBlock) {
-    const int i = base + threadIdx.x;
-    const int v = i < nb ? partial[i] : 0;
-    int tot;
-    const int ex = block_excl_scan<kScanBlock>(v, lds, &tot);
-    if (i < nb) partial[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
+// Tile scans: each workgroup first sums the tile totals before its own (at
+// most a few thousand ints, read from L2), so no separate pass over the tile
+// sums is needed; workgroup 0 also writes the grand total.
 __global__ __launch_bounds__(kScanBlock) void scan_tiles(const int* __restrict__ in, int64_t n_host,
                                                           const int* __restrict__ n_dev,
-                                                          const int* __restrict__ partial, int* __restrict__ out) {
+                                                          const int* __restrict__ partial, int* __restrict__ out,
+                                                          int* __restrict__ total_out) {
   __shared__ int lds[kScanBlock / kWave + 1];
   const int64_t n = count_of(n_host, n_dev);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n && blockIdx.x > 0) return;
+  const int nb = (int)((n + kScanTile - 1) / kScanTile);
+  // prefix of this tile (and, for workgroup 0, the total of all tiles)
+  const int upto = blockIdx.x == 0 ? nb : (int)blockIdx.x;
+  int acc = 0;
+  for (int i = threadIdx.x; i < upto; i += kScanBlock) acc += partial[i];
+  int sum_upto;
+  block_excl_scan<kScanBlock>(acc, lds, &sum_upto);
+  const int prefix = blockIdx.x == 0 ? 0 : sum_upto;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = sum_upto;
   if (base >= n) return;
   int v[kScanItems];
   int s = 0;
@@ -107,7 +103,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_tiles(const int* __restrict__
     s += v[k];
   }
   int tot;
-  int ex = block_excl_scan<kScanBlock>(s, lds, &tot) + partial[blockIdx.x];
+  int ex = block_excl_scan<kScanBlock>(s, lds, &tot) + prefix;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
@@ -141,8 +137,7 @@ void scan_exclusive_dev(const int* in, int* out, const int* n_dev, int64_t max_n
   }
   const int nb = (int)((max_n + kScanTile - 1) / kScanTile);
   scan_tile_reduce<<<nb, kScanBlock, 0, s>>>(in, max_n, n_dev, temp);
-  scan_partials<<<1, kScanBlock, 0, s>>>(temp, max_n, n_dev, total_dev);
-  scan_tiles<<<nb, kScanBlock, 0, s>>>(in, max_n, n_dev, temp, out);
+  scan_tiles<<<nb, kScanBlock, 0, s>>>(in, max_n, n_dev, temp, out, total_dev);
 }
 
 void scan_exclusive(const int* in, int* out, int64_t n, int* temp, int* total_dev, hipStream_t s) {

@@ -383,11 +383,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   int* p2p_src = nullptr;
   int64_t n_m2l = 0, n_p2pl = 0;
   if (!direct) {
-    fill_i32(cm2l, 0, ncells, s);
-    fill_i32(cp2p, 0, ncells, s);
     int4* rec = ensure<int4>(c, B_REC, ncells);
-    cell_records(tv, rec, s);
     if (exact_lists) {
+      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, s);
       lists_pass(tv, rec, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, 0, 0,
                  misc + M_FLAGS, s);
       int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
@@ -404,14 +402,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     } else {
       m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * c.cap_m2l);
       p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * c.cap_p2p);
-      capacity_offsets(ncells, c.cap_m2l, c.cap_p2p, om2l, op2p, s);
+      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, c.cap_m2l, c.cap_p2p, s);
       lists_pass(tv, rec, tcells, ntc, num, den, 2, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, c.cap_m2l, c.cap_p2p,
                  misc + M_FLAGS, s);
-      // list totals for the statistics, read with the final flags
-      int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
-      int* tmp = ensure<int>(c, B_FOFF, ncells);
-      scan_exclusive(cm2l, tmp, ncells, scan, misc + M_NM2L, s);
-      scan_exclusive(cp2p, tmp, ncells, scan, misc + M_NP2P, s);
     }
   }
 
@@ -450,9 +443,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(PP_PHASE_P2M);
     p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
     mark(PP_PHASE_M2M);
-    // the recursion from the finest level up, three levels per launch
-    for (int top = depth - 1; top >= 0; top -= 3) {
-      const int L = std::max(top - 2, 0);
+    // the recursion from the finest level up, several levels per launch
+    const int ml = m2m_max_levels();
+    for (int top = depth - 1; top >= 0; top -= ml) {
+      const int L = std::max(top - (ml - 1), 0);
       m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
     }
     mark(PP_PHASE_M2L);
@@ -497,7 +491,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   // ---- finalize ----
   mark(PP_PHASE_FINALIZE);
-  p2p_count_pairs(pa, s);
+  // statistics: pair count, and the list totals of the one-pass lists
+  const bool list_totals = !direct && !exact_lists;
+  p2p_totals(pa, list_totals ? cm2l : nullptr, list_totals ? cp2p : nullptr, ncells, misc + M_NM2L, misc + M_NP2P, s);
   finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, selfw, f_d, unit, prm.self_mode,
            misc + M_FLAGS, out_d, s);
   mark(12);
