@@ -25,6 +25,11 @@ applied with the roles of z and z' exchanged:
     L2L: L'_m = sum_{l>=m} L_l C(l, m) d^{l-m},  d = z_child - z_parent
     L2P: P(z) += (1/2pi) Re sum_l L_l (z - z_A)^l
 
+The paper's own tree-code (``treecode_grid``) uses no local expansions: each
+target leaf evaluates the multipole of every accepted group at its targets
+(M2P, eq. pressTruncated) and sums the other leaves directly; acceptance is
+``tree_ref.bh_mac``.
+
 All arrays are complex128; nothing is scaled.
 """
 
@@ -111,6 +116,47 @@ def l2p(L, zc, z):
     return np.real(acc) / TWO_PI
 
 
+def _upward(tree, zs, ws, centre, p: int):
+    """P2M at the source leaves, then M2M from the finest level up (unscaled S, alpha per cell)."""
+    nc = tree.ncells
+    S = np.zeros(nc)
+    alpha = np.zeros((nc, p + 1), dtype=np.complex128)
+    for c in range(nc - 1, -1, -1):
+        if tree.nsrc(c) == 0:
+            continue
+        if tree.leaf[c]:
+            sl = slice(int(tree.sb[c]), int(tree.se[c]))
+            S[c], alpha[c] = p2m(zs[sl], ws[sl], centre(c), p)
+        else:
+            for ch in tree.children(c):
+                if tree.nsrc(ch) == 0:
+                    continue
+                s2, b = m2m(S[ch], alpha[ch], centre(ch), centre(c))
+                S[c] += s2
+                alpha[c] += b
+    return S, alpha
+
+
+def _near(tree, pairs, txs, tys, sxs, sys_, ws, h, self_mode, near):
+    """Direct sum over (target leaf, source leaf) pairs into near[sorted target], without 1/2pi;
+    coincident pairs skipped (or replaced by the cell average)."""
+    lnh = math.log(h)
+    kappa = 1.5 - math.pi / 4.0 + 0.5 * math.log(2.0)
+    for a, b in pairs:
+        tl = range(int(tree.tb[a]), int(tree.te[a]))
+        sl = slice(int(tree.sb[b]), int(tree.se[b]))
+        for t in tl:
+            dx = txs[t] - sxs[sl]
+            dy = tys[t] - sys_[sl]
+            r2 = dx * dx + dy * dy
+            self_ = r2 == 0.0
+            contrib = np.where(self_, 0.0, ws[sl] * 0.5 * np.log(np.where(self_, 1.0, r2)))
+            near[t] += float(np.sum(contrib))
+            if self_mode == 1 and np.any(self_):
+                near[t] += float(np.sum(ws[sl][self_])) * (lnh - kappa)
+    near /= TWO_PI
+
+
 def fmm_grid(f, tx, ty, h, p: int, theta: float, leaf_max: int = 64, x0: float = 0.0, y0: float = 0.0,
              self_mode: int = 0):
     """Slow reference tree-code (P2M, M2M, M2L, L2L, L2P, P2P) on grid sources.
@@ -143,22 +189,7 @@ def fmm_grid(f, tx, ty, h, p: int, theta: float, leaf_max: int = 64, x0: float =
         side = h * 2.0 ** (k - int(tree.level[c]))
         return complex(x0 + (int(tree.ix[c]) + 0.5) * side, y0 + (int(tree.iy[c]) + 0.5) * side)
 
-    S = np.zeros(nc)
-    alpha = np.zeros((nc, p + 1), dtype=np.complex128)
-    # upward pass: P2M at leaves, then M2M from the finest level up
-    for c in range(nc - 1, -1, -1):
-        if tree.nsrc(c) == 0:
-            continue
-        if tree.leaf[c]:
-            sl = slice(int(tree.sb[c]), int(tree.se[c]))
-            S[c], alpha[c] = p2m(zs[sl], ws[sl], centre(c), p)
-        else:
-            for ch in tree.children(c):
-                if tree.nsrc(ch) == 0:
-                    continue
-                s2, b = m2m(S[ch], alpha[ch], centre(ch), centre(c))
-                S[c] += s2
-                alpha[c] += b
+    S, alpha = _upward(tree, zs, ws, centre, p)
     # downward pass
     L = np.zeros((nc, p + 1), dtype=np.complex128)
     for a, b in m2l_pairs:
@@ -174,24 +205,55 @@ def fmm_grid(f, tx, ty, h, p: int, theta: float, leaf_max: int = 64, x0: float =
             continue
         tl = slice(int(tree.tb[c]), int(tree.te[c]))
         far[tl] = l2p(L[c], centre(c), zt[tl])
-    lnh = math.log(h)
-    kappa = 1.5 - math.pi / 4.0 + 0.5 * math.log(2.0)
-    for a, b in p2p_pairs:
-        tl = range(int(tree.tb[a]), int(tree.te[a]))
-        sl = slice(int(tree.sb[b]), int(tree.se[b]))
-        for t in tl:
-            dx = txs[t] - sxs[sl]
-            dy = tys[t] - sys_[sl]
-            r2 = dx * dx + dy * dy
-            self_ = r2 == 0.0
-            contrib = np.where(self_, 0.0, ws[sl] * 0.5 * np.log(np.where(self_, 1.0, r2)))
-            near[t] += float(np.sum(contrib))
-            if self_mode == 1 and np.any(self_):
-                near[t] += float(np.sum(ws[sl][self_])) * (lnh - kappa)
-    near /= TWO_PI
+    _near(tree, p2p_pairs, txs, tys, sxs, sys_, ws, h, self_mode, near)
     out_far = np.empty_like(far)
     out_near = np.empty_like(near)
     out_far[perm] = far
     out_near[perm] = near
     return dict(P=out_far + out_near, far=out_far, near=out_near, S=S, alpha=alpha, L=L, tree=tree,
                 info=info, m2l=m2l_pairs, p2p=p2p_pairs)
+
+
+def treecode_grid(f, tx, ty, h, p: int, theta: float, leaf_max: int = 64, x0: float = 0.0, y0: float = 0.0,
+                  self_mode: int = 0):
+    """Slow reference of the paper's own tree-code on grid sources: P2M and M2M upward, then
+    for every target leaf the multipoles of the accepted cells evaluated at its targets
+    (eq. pressTruncated, M2P) and a direct sum over the other leaves (``tree_ref.bh_lists``).
+    Returns dict(P, far, near, S, alpha, tree, lists) in the caller's target order (1/2pi included).
+    """
+    f = np.asarray(f, dtype=np.float64)
+    ny, nx = f.shape
+    tx = np.asarray(tx, dtype=np.float64)
+    ty = np.asarray(ty, dtype=np.float64)
+    info = tree_ref.grid_tree(f, tx, ty, h, x0, y0, leaf_max)
+    tree = info["tree"]
+    k = info["k"]
+    lists = tree_ref.bh_lists(tree, theta)
+    flat = info["src_flat"]
+    sxs = x0 + (flat % nx + 0.5) * h
+    sys_ = y0 + (flat // nx + 0.5) * h
+    ws = f.ravel()[flat] * h * h
+    perm = info["tgt_perm"]
+    txs, tys = tx[perm], ty[perm]
+    zt = txs + 1j * tys
+
+    def centre(c):
+        side = h * 2.0 ** (k - int(tree.level[c]))
+        return complex(x0 + (int(tree.ix[c]) + 0.5) * side, y0 + (int(tree.iy[c]) + 0.5) * side)
+
+    S, alpha = _upward(tree, sxs + 1j * sys_, ws, centre, p)
+    far = np.zeros(tx.size)
+    near = np.zeros(tx.size)
+    pairs = []
+    for a, (m2p_cells, p2p_cells) in lists.items():
+        tl = slice(int(tree.tb[a]), int(tree.te[a]))
+        for b in m2p_cells:
+            far[tl] += m2p(S[b], alpha[b], centre(b), zt[tl])
+        pairs.extend((a, b) for b in p2p_cells)
+    _near(tree, pairs, txs, tys, sxs, sys_, ws, h, self_mode, near)
+    out_far = np.empty_like(far)
+    out_near = np.empty_like(near)
+    out_far[perm] = far
+    out_near[perm] = near
+    return dict(P=out_far + out_near, far=out_far, near=out_near, S=S, alpha=alpha, tree=tree, info=info,
+                lists=lists)

@@ -34,6 +34,10 @@ readings implemented here are:
   accepted -> M2L pair; else both leaves -> P2P pair; else A is a leaf -> B is
   split; else B is a leaf -> A is split; else both are split.  Only source
   cells with sources and target cells with targets are visited.
+* The paper's own tree-code (a target sees each group either through its
+  expansion or directly): per target leaf, a one-sided traversal of the source
+  tree with the acceptance s_B / d < theta, d the distance from the leaf's
+  square to B's centre (``bh_mac``, ``bh_lists``).
 """
 
 from __future__ import annotations
@@ -256,6 +260,49 @@ def lists_for_cell(tree: Tree, target: int, theta: float):
             stack.extend((aa, bb) for aa in tree.children(a) if aa in on_path
                          for bb in tree.children(b) if tree.nsrc(bb) > 0)
     return sorted(m2l), sorted(p2p)
+
+
+def bh_mac(tree: Tree, a: int, b: int, num: int, den: int) -> bool:
+    """Acceptance of source cell b for every target of leaf a in the paper's tree-code
+    (a group is expanded when it is far enough from the target; read here as s_b / d < theta,
+    s_b the side of b and d the smallest distance from a's square to b's centre).  Exact in
+    integers with positions in units of half a finest cell: s_b^2 den^2 < num^2 d^2."""
+    D = tree.D
+    la, lb = int(tree.level[a]), int(tree.level[b])
+    ax0 = (2 * int(tree.ix[a])) << (D - la)
+    ax1 = (2 * int(tree.ix[a]) + 2) << (D - la)
+    ay0 = (2 * int(tree.iy[a])) << (D - la)
+    ay1 = (2 * int(tree.iy[a]) + 2) << (D - la)
+    cx = (2 * int(tree.ix[b]) + 1) << (D - lb)
+    cy = (2 * int(tree.iy[b]) + 1) << (D - lb)
+    dx = max(0, ax0 - cx, cx - ax1)
+    dy = max(0, ay0 - cy, cy - ay1)
+    sb = 1 << (D - lb + 1)
+    return sb * sb * den * den < num * num * (dx * dx + dy * dy)
+
+
+def bh_lists(tree: Tree, theta: float):
+    """Per target leaf a (leaves holding targets): the source cells whose multipoles are
+    evaluated at a's targets (M2P) and the source leaves summed directly (P2P), from a
+    traversal of the source tree that starts at the root: accepted -> M2P; a leaf -> P2P;
+    otherwise its children with sources are visited.  Returns {a: (m2p, p2p)}, sorted."""
+    num, den = theta_rational(theta)
+    out = {}
+    for a in range(tree.ncells):
+        if not tree.leaf[a] or tree.ntgt(a) == 0:
+            continue
+        m2p, p2p = [], []
+        stack = [0] if tree.nsrc(0) > 0 else []
+        while stack:
+            b = stack.pop()
+            if bh_mac(tree, a, b, num, den):
+                m2p.append(b)
+            elif tree.leaf[b]:
+                p2p.append(b)
+            else:
+                stack.extend(c for c in tree.children(b) if tree.nsrc(c) > 0)
+        out[a] = (sorted(m2p), sorted(p2p))
+    return out
 
 
 def grid_tree(f: np.ndarray, tx, ty, h: float, x0: float = 0.0, y0: float = 0.0, leaf_max: int = 64):

@@ -32,8 +32,9 @@ __device__ inline int rec_nchild(int4 r) { return (r.w >> 5) & 7; }
 __device__ inline int rec_kidmask(int4 r) { return (r.w >> 8) & 15; }
 __device__ inline bool rec_has_src(int4 r) { return (r.w >> 12) & 1; }
 
-// Also clears the per-cell list counts and, for the one-pass lists
-// (cap_m > 0), writes the fixed-capacity offsets c * cap.
+// Packed traversal record of every cell; the same launch clears the per-cell
+// list counts and, for the one-pass lists (cap_m > 0), writes the
+// fixed-capacity offsets c * cap.
 __global__ void k_records(TreeView t, int n, int4* __restrict__ rec, int* __restrict__ cnt_m2l,
                           int* __restrict__ cnt_p2p, int* __restrict__ off_m2l, int* __restrict__ off_p2p, int cap_m,
                           int cap_p) {

@@ -130,3 +130,63 @@ def test_reference_fmm_off_grid_targets_and_cellavg():
         P = direct.direct_grid(f, h, tx, ty, self_mode=mode)
         r = fmm_ref.fmm_grid(f, tx, ty, h, 12, 0.5, leaf_max=16, self_mode=mode)
         assert np.linalg.norm(r["P"] - P) / np.linalg.norm(P) < 1e-9
+
+
+def test_treecode_converges_to_direct():
+    """The paper's tree-code (M2P at the targets, no locals) on random grid sources with off-grid and
+    node targets: error falls geometrically with p and is within the FP64 tolerance at p = 12."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    n = 32
+    h = 1.0 / n
+    f = rng.standard_normal((n, n))
+    g = G.GridSpec(n, n, h)
+    x, y = G.grid_nodes(g)
+    tx = np.concatenate([x.ravel()[::5], rng.uniform(0, 1, 150)])
+    ty = np.concatenate([y.ravel()[::5], rng.uniform(0, 1, 150)])
+    P = direct.direct_grid(f, h, tx, ty)
+    errs = []
+    for p in (4, 8, 12):
+        r = fmm_ref.treecode_grid(f, tx, ty, h, p, 0.5, leaf_max=16)
+        errs.append(np.linalg.norm(r["P"] - P) / np.linalg.norm(P))
+    assert errs[2] < 1e-6
+    assert errs[1] < errs[0] / 10 and errs[2] < errs[1] / 10
+
+
+def test_treecode_far_part_obeys_the_m2p_bound():
+    """For one target leaf, the M2P sum over its accepted cells differs from the direct sum over their
+    sources by at most sum_B A_B / (p+1) c_B^-p / (c_B - 1), c_B = d / r_B (truncation of eq. pressTruncated)."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    n = 32
+    h = 1.0 / n
+    f = rng.standard_normal((n, n))
+    x, y = G.grid_nodes(G.GridSpec(n, n, h))
+    tx, ty = x.ravel()[::7], y.ravel()[::7]
+    p = 6
+    r = fmm_ref.treecode_grid(f, tx, ty, h, p, 0.5, leaf_max=16)
+    t, info = r["tree"], r["info"]
+    k = info["k"]
+    flat = info["src_flat"]
+    sx = (flat % n + 0.5) * h
+    sy = (flat // n + 0.5) * h
+    w = f.ravel()[flat] * h * h
+    perm = info["tgt_perm"]
+    checked = 0
+    for a, (m2p, _) in r["lists"].items():
+        if not m2p:
+            continue
+        tl = perm[int(t.tb[a]):int(t.te[a])]
+        for j in tl:
+            zt = tx[j] + 1j * ty[j]
+            approx = exact = bound = 0.0
+            for b in m2p:
+                side = h * 2.0 ** (k - int(t.level[b]))
+                zc = complex((int(t.ix[b]) + 0.5) * side, (int(t.iy[b]) + 0.5) * side)
+                approx += fmm_ref.m2p(r["S"][b], r["alpha"][b], zc, zt)
+                sl = slice(int(t.sb[b]), int(t.se[b]))
+                exact += np.sum(w[sl] * np.log(np.abs(zt - (sx[sl] + 1j * sy[sl])))) / (2 * math.pi)
+                rad = side / math.sqrt(2)
+                c = abs(zt - zc) / rad
+                bound += np.sum(np.abs(w[sl])) / (p + 1) * c ** (-p) / (c - 1) / (2 * math.pi)
+            assert abs(approx - exact) <= bound * (1 + 1e-9) + 1e-15
+            checked += 1
+    assert checked > 20

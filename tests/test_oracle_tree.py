@@ -159,3 +159,51 @@ def test_uniform_grid_counts():
     m2l, p2p = tree_ref.interaction_lists(t, 0.5)
     # every leaf's P2P neighbourhood is a block of leaves around it; totals from the traversal
     assert len(p2p) == 1156 and len(m2l) == 2040
+
+
+def test_bh_mac_matches_geometry():
+    """The tree-code test s_B / d < theta (d from the leaf's square to B's centre) in exact arithmetic."""
+    from fractions import Fraction
+    f, tx, ty, info = _small_case(seed=6, leaf_max=4)
+    t = info["tree"]
+    rng = np.random.Generator(np.random.PCG64(1))
+    leaves = [a for a in range(t.ncells) if t.leaf[a]]
+    for _ in range(400):
+        a = int(rng.choice(leaves))
+        b = int(rng.integers(0, t.ncells))
+        for theta, (num, den) in ((0.5, (1, 2)), (0.4, (2, 5)), (0.7, (7, 10))):
+            sa = Fraction(1, 2 ** int(t.level[a]))
+            sb = Fraction(1, 2 ** int(t.level[b]))
+            x0, x1 = t.ix[a] * sa, (t.ix[a] + 1) * sa
+            y0, y1 = t.iy[a] * sa, (t.iy[a] + 1) * sa
+            cbx = (t.ix[b] + Fraction(1, 2)) * sb
+            cby = (t.iy[b] + Fraction(1, 2)) * sb
+            dx = max(Fraction(0), x0 - cbx, cbx - x1)
+            dy = max(Fraction(0), y0 - cby, cby - y1)
+            geo = sb ** 2 < Fraction(num, den) ** 2 * (dx * dx + dy * dy)
+            assert geo == tree_ref.bh_mac(t, a, b, num, den)
+
+
+def test_bh_lists_cover_every_pair_once():
+    """Per target leaf, the accepted cells and the direct leaves partition the sources exactly once;
+    accepted cells lie outside the leaf, direct cells are leaves."""
+    for seed, lm, theta in ((1, 8, 0.5), (2, 4, 0.4), (3, 16, 0.6)):
+        f, tx, ty, info = _small_case(seed=seed, leaf_max=lm)
+        t = info["tree"]
+        ns = info["src_keys"].size
+        num, den = tree_ref.theta_rational(theta)
+        lists = tree_ref.bh_lists(t, theta)
+        assert set(lists) == {a for a in range(t.ncells) if t.leaf[a] and t.ntgt(a) > 0}
+        for a, (m2p, p2p) in lists.items():
+            cover = np.zeros(ns, dtype=np.int32)
+            for b in m2p + p2p:
+                cover[t.sb[b]:t.se[b]] += 1
+            assert np.all(cover == 1), a
+            for b in m2p:
+                assert tree_ref.bh_mac(t, a, b, num, den)
+                # B's square and A's square are disjoint (the target never sits inside an accepted group)
+                la, lb = int(t.level[a]), int(t.level[b])
+                lo = min(la, lb)
+                assert not (t.ix[a] >> (la - lo) == t.ix[b] >> (lb - lo)
+                            and t.iy[a] >> (la - lo) == t.iy[b] >> (lb - lo)), (a, b)
+            assert all(t.leaf[b] for b in p2p)
