@@ -144,6 +144,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="vortex512")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--method", default="fmm", choices=["fmm", "treecode"],
+                    help="fmm: M2L/L2L/L2P with the dual-tree acceptance; treecode: the paper's own variant (M2P)")
     ap.add_argument("--direct-steps", type=int, default=3)
     ap.add_argument("--samples", type=int, default=2000, help="targets checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
@@ -193,7 +195,7 @@ def main() -> int:
     tx = torch.as_tensor(w["tx"], device=dev)
     ty = torch.as_tensor(w["ty"], device=dev)
     out = torch.empty(tx.numel(), dtype=torch.float64, device=dev)
-    kw = dict(p=w["p"], theta=w["theta"], leaf_max=64, precision=args.precision)
+    kw = dict(p=w["p"], theta=w["theta"], leaf_max=64, precision=args.precision, method=args.method)
 
     s = pp.Solver(0)
     s.set_profiling(True)
@@ -302,6 +304,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [g.nx, g.ny], "sources_nonzero": N, "targets": M,
                    "p": w["p"], "theta": w["theta"], "leaf_max": 64, "precision": args.precision,
+                   "method": args.method,
                    "seed": w["seed"], "parallelism": "single GPU"},
         "interactions_per_s": N * M / (ms_per_step * 1e-3),
         "direct": None if direct_s is None else {

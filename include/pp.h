@@ -72,8 +72,9 @@ enum {
   PP_ERR_BUSY = -8     /* pp_server_cancel: the request has already started (or finished) */
 };
 
-enum { PP_FP64 = 0, PP_MIXED = 1 };            /* MIXED: P2P and L2P in FP32 (Kahan), expansions FP64 */
+enum { PP_FP64 = 0, PP_MIXED = 1 };            /* MIXED: P2P and L2P/M2P in FP32 (Kahan), expansions FP64 */
 enum { PP_SELF_SKIP = 0, PP_SELF_CELLAVG = 1 };
+enum { PP_METHOD_FMM = 0, PP_METHOD_TREECODE = 1 };
 
 /*
  * Parameters of the tree-code (Appendix A):
@@ -86,6 +87,13 @@ enum { PP_SELF_SKIP = 0, PP_SELF_CELLAVG = 1 };
  *             more than leaf_max targets (1..4096)
  *   precision PP_FP64 or PP_MIXED
  *   self_mode PP_SELF_SKIP or PP_SELF_CELLAVG
+ *   method    PP_METHOD_FMM (default, 0): multipoles shifted into local
+ *             expansions (M2L, L2L, L2P) with the dual-tree acceptance above.
+ *             PP_METHOD_TREECODE: the paper's own tree-code - every target
+ *             leaf evaluates the multipoles of the groups it accepts directly
+ *             at its targets (eq. pressTruncated, M2P; no local expansions),
+ *             with acceptance s_B / d < theta, s_B the side of group B and d
+ *             the distance from the leaf's square to B's centre.
  */
 typedef struct {
   int32_t p;
@@ -93,6 +101,7 @@ typedef struct {
   int32_t leaf_max;
   int32_t precision;
   int32_t self_mode;
+  int32_t method;
 } pp_params;
 
 /* Per-solve statistics of the last successful call on a context. */
@@ -103,7 +112,7 @@ typedef struct {
   int32_t ntgt_leaves;    /* leaves holding targets */
   int64_t nsources;       /* sources with a nonzero weight */
   int64_t ntargets;
-  int64_t n_m2l;          /* M2L (cell, cell) pairs */
+  int64_t n_m2l;          /* M2L (cell, cell) pairs; tree-code: M2P (leaf, cell) pairs */
   int64_t n_p2p_lists;    /* P2P (leaf, leaf) pairs */
   int64_t n_p2p_pairs;    /* P2P (target, source) interactions */
   double ms_total;        /* wall time of the call on the host, ms */
@@ -120,7 +129,7 @@ enum {
   PP_PHASE_PACK = 4,     /* per-leaf source records and target offsets */
   PP_PHASE_P2M = 5,
   PP_PHASE_M2M = 6,      /* bottom-up recursion, four levels per launch */
-  PP_PHASE_M2L = 7,
+  PP_PHASE_M2L = 7,      /* tree-code: M2P */
   PP_PHASE_L2L = 8,      /* final locals: own M2L plus exact shifts of every ancestor's */
   PP_PHASE_L2P = 9,
   PP_PHASE_P2P = 10,
@@ -188,15 +197,15 @@ enum {
   PP_ARR_CELL_CHILD = 11, /* first child or -1 */
   PP_ARR_CELL_NCHILD = 12,
   PP_ARR_CELL_PARENT = 13,
-  PP_ARR_M2L_OFF = 14,    /* per cell: begin of its M2L source list */
+  PP_ARR_M2L_OFF = 14,    /* per cell: begin of its M2L source list (tree-code: M2P list of a target leaf) */
   PP_ARR_M2L_CNT = 15,    /* per cell: length */
   PP_ARR_M2L_SRC = 16,
   PP_ARR_P2P_OFF = 17,
   PP_ARR_P2P_CNT = 18,
   PP_ARR_P2P_SRC = 19,
   PP_ARR_MULTIPOLE = 20,  /* double, per cell (p+1) complex: scaled a'_k = a_k / s^k */
-  PP_ARR_LOCAL = 21,      /* double, per cell (p+1) complex: scaled L'_l = L_l s^l */
-  PP_ARR_FAR = 22,        /* double per sorted target: Re sum_l L'_l u^l (far field times 2pi) */
+  PP_ARR_LOCAL = 21,      /* double, per cell (p+1) complex: scaled L'_l = L_l s^l (not in the tree-code) */
+  PP_ARR_FAR = 22,        /* double per sorted target: the far field times 2pi (L2P, or the M2P sum) */
   PP_ARR_NEAR = 23,       /* double [parts][sorted target]: partial sums over near sources of w ln(r^2/h^2) */
   PP_ARR_LEAF_WNEAR = 24, /* double [parts][cell]: partial sums of w over a target leaf's near sources */
   PP_ARR_TGT_LEAF = 25    /* leaf cell of each sorted target */

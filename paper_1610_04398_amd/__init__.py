@@ -44,12 +44,15 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
 
 _PREC = {"fp64": B.PP_FP64, "mixed": B.PP_MIXED}
 _SELF = {"skip": B.PP_SELF_SKIP, "cellavg": B.PP_SELF_CELLAVG}
+_METHOD = {"fmm": B.PP_METHOD_FMM, "treecode": B.PP_METHOD_TREECODE}
 
 
-def make_params(p: int = 12, theta: float = 0.5, leaf_max: int = 64, precision="mixed", self_mode="skip"):
+def make_params(p: int = 12, theta: float = 0.5, leaf_max: int = 64, precision="mixed", self_mode="skip",
+                method="fmm"):
     prec = _PREC[precision] if isinstance(precision, str) else int(precision)
     selfm = _SELF[self_mode] if isinstance(self_mode, str) else int(self_mode)
-    return B.pp_params(int(p), float(theta), int(leaf_max), prec, selfm)
+    meth = _METHOD[method] if isinstance(method, str) else int(method)
+    return B.pp_params(int(p), float(theta), int(leaf_max), prec, selfm, meth)
 
 
 def _is_torch(x) -> bool:
@@ -116,9 +119,9 @@ class Solver:
         return out
 
     def solve_grid(self, f, h, tx, ty, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
-                   self_mode="skip", out=None, stream=None):
+                   self_mode="skip", out=None, stream=None, method="fmm"):
         """Tree-code pressure at the targets (caller order); see pp_solve_grid in include/pp.h."""
-        prm = make_params(p, theta, leaf_max, precision, self_mode)
+        prm = make_params(p, theta, leaf_max, precision, self_mode, method)
         return self._run(pp_solve_grid, f, h, tx, ty, x0, y0, prm, out, stream)
 
     def direct_grid(self, f, h, tx, ty, x0=0.0, y0=0.0, leaf_max=64, precision="mixed", self_mode="skip",
@@ -159,9 +162,9 @@ class Solver:
         return out
 
     def solve_points(self, sx, sy, w, tx, ty, p=12, theta=0.5, leaf_max=64, precision="mixed", out=None,
-                     stream=None):
+                     stream=None, method="fmm"):
         """Tree-code pressure of scattered weighted sources at the targets; see pp_solve_points."""
-        prm = make_params(p, theta, leaf_max, precision, "skip")
+        prm = make_params(p, theta, leaf_max, precision, "skip", method)
         return self._run_points(pp_solve_points, sx, sy, w, tx, ty, prm, out, stream)
 
     def direct_points(self, sx, sy, w, tx, ty, leaf_max=64, precision="mixed", out=None, stream=None):
@@ -212,7 +215,7 @@ class Server:
         self._keep = {}
 
     def submit(self, f, h, tx, ty, out, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
-               self_mode="skip") -> int:
+               self_mode="skip", method="fmm") -> int:
         fp, fk = _ptr(f, "f")
         xp, xk = _ptr(tx, "tx")
         yp, yk = _ptr(ty, "ty")
@@ -222,7 +225,7 @@ class Server:
         ny, nx = tuple(fk.shape)
         m = int(np.prod(tuple(xk.shape)))
         req = B.pp_request(nx, ny, float(x0), float(y0), float(h), fp, m, xp, yp,
-                           make_params(p, theta, leaf_max, precision, self_mode), op)
+                           make_params(p, theta, leaf_max, precision, self_mode, method), op)
         t = pp_server_submit(self._srv, req)
         self._keep[t] = (fk, xk, yk, ok)
         return t

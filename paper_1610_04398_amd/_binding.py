@@ -24,6 +24,8 @@ PP_FP64 = 0
 PP_MIXED = 1
 PP_SELF_SKIP = 0
 PP_SELF_CELLAVG = 1
+PP_METHOD_FMM = 0
+PP_METHOD_TREECODE = 1
 
 ARRAYS = dict(
     SRC_KEY=0, SRC_INDEX=1, TGT_KEY=2, TGT_PERM=3, CELL_LEVEL=4, CELL_IX=5, CELL_IY=6, CELL_SB=7, CELL_SE=8,
@@ -45,7 +47,7 @@ PP_ERR_BUSY = -8
 
 class pp_params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("theta", ctypes.c_double), ("leaf_max", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("self_mode", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("self_mode", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class pp_stats(ctypes.Structure):

@@ -99,4 +99,20 @@ __host__ __device__ inline bool mac_accept(int D, int la, int ixa, int iya, int 
   return lhs < rhs;
 }
 
+// Acceptance of source cell B for every target of leaf A in the paper's
+// tree-code (a group is used through its expansion when it is far enough from
+// the target): S_B / d < theta with d the distance from A's square to B's
+// centre, exactly in integers (half-finest-cell units): S_B^2 den^2 < num^2 d^2.
+__host__ __device__ inline bool treecode_accept(int D, int la, int ixa, int iya, int lb, int ixb, int iyb, int num,
+                                                int den) {
+  const int64_t ax0 = (int64_t)(2 * ixa) << (D - la), ax1 = (int64_t)(2 * ixa + 2) << (D - la);
+  const int64_t ay0 = (int64_t)(2 * iya) << (D - la), ay1 = (int64_t)(2 * iya + 2) << (D - la);
+  const int64_t cx = (int64_t)(2 * ixb + 1) << (D - lb);
+  const int64_t cy = (int64_t)(2 * iyb + 1) << (D - lb);
+  const int64_t dx = ax0 > cx ? ax0 - cx : (cx > ax1 ? cx - ax1 : 0);
+  const int64_t dy = ay0 > cy ? ay0 - cy : (cy > ay1 ? cy - ay1 : 0);
+  const int64_t s = (int64_t)1 << (D - lb + 1);
+  return s * s * (int64_t)den * (int64_t)den < (int64_t)num * (int64_t)num * (dx * dx + dy * dy);
+}
+
 }  // namespace pp

@@ -367,6 +367,126 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
   far[k] = (double)ax;
 }
 
+// M2P of the paper's tree-code (eq. pressTruncated evaluated at the targets):
+// one wave per target leaf A, lane j on target j of each 64-target chunk, and
+// for every source cell B of A's list
+//   far += a_0 (ln|w| + ln s_B) + Re sum_{k=1..p} a'_k w^-k,   w = (t - z_B) / s_B,
+// by Horner in u = 1/w.  The list entry, B's geometry and its coefficients are
+// wave-uniform (scalar loads).  Offsets from A's corner are in units of h; the
+// corner difference to B's centre is an exact half-integer.
+constexpr double kLn2d = 0.69314718055994530942;
+
+__global__ __launch_bounds__(256) void k_m2p64(TreeView t, const int* __restrict__ tleaves, int n,
+                                               const int* __restrict__ off, const int* __restrict__ cnt,
+                                               const int* __restrict__ src, int p, double lnh,
+                                               const double2* __restrict__ mp, const double2* __restrict__ rel64,
+                                               double* __restrict__ far, int* __restrict__ flags) {
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  if (wid >= n) return;
+  const int lane = threadIdx.x % kWave;
+  const int A = tleaves[wid];
+  const int shA = t.D - t.lvl[A];
+  const int64_t ax2 = (int64_t)(2 * t.ix[A]) << shA, ay2 = (int64_t)(2 * t.iy[A]) << shA;
+  const int e0 = off[A], ne = cnt[A];
+  const int tb = t.tb[A], te = t.te[A];
+  const int P1 = p + 1;
+  bool bad = false;
+  for (int chunk = tb; chunk < te; chunk += kWave) {
+    const int k = chunk + lane;
+    const bool active = k < te;
+    const double2 r = active ? rel64[k] : make_double2(0.0, 0.0);
+    double acc_far = 0.0;
+    for (int e = 0; e < ne; ++e) {
+      const int B = src[e0 + e];
+      if ((unsigned)B >= (unsigned)t.ncells) {
+        bad = true;
+        continue;
+      }
+      const int shB = t.D - t.lvl[B];
+      const double inv_s = ldexp(1.0, -shB);
+      const double dx = 0.5 * (double)(ax2 - ((int64_t)(2 * t.ix[B] + 1) << shB));
+      const double dy = 0.5 * (double)(ay2 - ((int64_t)(2 * t.iy[B] + 1) << shB));
+      const double wx = (r.x + dx) * inv_s, wy = (r.y + dy) * inv_s;
+      const double r2 = wx * wx + wy * wy;
+      const double ir2 = 1.0 / r2;
+      const double ux = wx * ir2, uy = -wy * ir2;
+      const double2* a = mp + (int64_t)B * P1;
+      double hx = 0.0, hy = 0.0;
+      for (int q = p; q >= 1; --q) {
+        const double2 c = a[q];
+        const double nx = hx * ux - hy * uy + c.x;
+        const double ny = hx * uy + hy * ux + c.y;
+        hx = nx;
+        hy = ny;
+      }
+      const double re = hx * ux - hy * uy;
+      acc_far += re + a[0].x * (0.5 * log(r2) + (double)shB * kLn2d + lnh);
+    }
+    if (active) far[k] = acc_far;
+  }
+  if (bad && lane == 0) atomicOr(flags, kFlagBadIndex);
+}
+
+// FP32 evaluation (mixed precision) from FP32 copies of the coefficients; each
+// cell's contribution is added to an FP64 accumulator.
+__global__ __launch_bounds__(256) void k_m2p32(TreeView t, const int* __restrict__ tleaves, int n,
+                                               const int* __restrict__ off, const int* __restrict__ cnt,
+                                               const int* __restrict__ src, int p, double lnh,
+                                               const float2* __restrict__ mp32, const float2* __restrict__ rel32,
+                                               double* __restrict__ far, int* __restrict__ flags) {
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
+  if (wid >= n) return;
+  const int lane = threadIdx.x % kWave;
+  const int A = tleaves[wid];
+  const int shA = t.D - t.lvl[A];
+  const int ax2 = (2 * t.ix[A]) << shA, ay2 = (2 * t.iy[A]) << shA;
+  const int e0 = off[A], ne = cnt[A];
+  const int tb = t.tb[A], te = t.te[A];
+  const int P1 = p + 1;
+  const float lnh2 = (float)lnh;
+  bool bad = false;
+  for (int chunk = tb; chunk < te; chunk += kWave) {
+    const int k = chunk + lane;
+    const bool active = k < te;
+    const float2 r = active ? rel32[k] : make_float2(0.0f, 0.0f);
+    double acc_far = 0.0;
+    for (int e = 0; e < ne; ++e) {
+      const int B = src[e0 + e];
+      if ((unsigned)B >= (unsigned)t.ncells) {
+        bad = true;
+        continue;
+      }
+      const int shB = t.D - t.lvl[B];
+      const float inv_s = ldexpf(1.0f, -shB);
+      const float dx = 0.5f * (float)(ax2 - ((2 * t.ix[B] + 1) << shB));
+      const float dy = 0.5f * (float)(ay2 - ((2 * t.iy[B] + 1) << shB));
+      const float wx = (r.x + dx) * inv_s, wy = (r.y + dy) * inv_s;
+      const float r2 = wx * wx + wy * wy;
+      const float ir2 = 1.0f / r2;
+      const float ux = wx * ir2, uy = -wy * ir2;
+      const float2* a = mp32 + (int64_t)B * P1;
+      float hx = 0.0f, hy = 0.0f;
+      for (int q = p; q >= 1; --q) {
+        const float2 c = a[q];
+        const float nx = hx * ux - hy * uy + c.x;
+        const float ny = hx * uy + hy * ux + c.y;
+        hx = nx;
+        hy = ny;
+      }
+      const float re = hx * ux - hy * uy;
+      const float lg = 0.5f * (float)kLn2d * __builtin_amdgcn_logf(r2) + (float)shB * (float)kLn2d + lnh2;
+      acc_far += (double)(re + a[0].x * lg);
+    }
+    if (active) far[k] = acc_far;
+  }
+  if (bad && lane == 0) atomicOr(flags, kFlagBadIndex);
+}
+
+__global__ void k_to_f32(const double2* __restrict__ a, int64_t n, float2* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
 #define PP_DISPATCH(p, KERNEL, GRID, BLOCK, STREAM, ...)                      \
   do {                                                                        \
     if ((p) <= 4)                                                             \
@@ -434,6 +554,20 @@ void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, con
     k_l2p32<<<g, 256, 0, s>>>(t, m, tleaf, p, loc, rel64, far);
   else
     k_l2p64<<<g, 256, 0, s>>>(t, m, tleaf, p, loc, rel64, far);
+}
+
+void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
+         const double2* mp, float2* mp32, const double2* rel64, const float2* rel32, int fp32, double* far, int* flags,
+         hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned g = (unsigned)((n + 3) / 4);
+  if (fp32) {
+    const int64_t nc = (int64_t)t.ncells * (p + 1);
+    k_to_f32<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(mp, nc, mp32);
+    k_m2p32<<<g, 256, 0, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp32, rel32, far, flags);
+  } else {
+    k_m2p64<<<g, 256, 0, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp, rel64, far, flags);
+  }
 }
 
 }  // namespace pp

@@ -109,6 +109,12 @@ void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, co
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p
 // (indexed by cell id), pass 1 writes the lists at off_m2l / off_p2p (by cell id).
+// Lists of the tree-code variant, per target leaf (indexed by cell id): the
+// source cells whose multipoles are evaluated at the leaf's targets (M2P) and
+// the source leaves summed directly (P2P).  Same emit modes as lists_pass.
+void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
+                         int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
+                         int cap_p, int* flags, hipStream_t s);
 // Packed per-cell records used by the traversal (ncells int4); clears the
 // list counts, and for cap_m > 0 writes the one-pass offsets cell * cap.
 void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
@@ -132,6 +138,12 @@ int m2m_max_levels();
 void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, int* flags, hipStream_t s);
+// M2P of the tree-code variant: far[k] for every target of the n target leaves
+// from the multipoles of their M2P lists (off/cnt by cell id); fp32 != 0
+// evaluates in FP32 from copies of the coefficients written to mp32.
+void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
+         const double2* mp, float2* mp32, const double2* rel64, const float2* rel32, int fp32, double* far, int* flags,
+         hipStream_t s);
 // Final local expansion of every cell with targets from its own M2L local
 // (`own`) and its ancestors' (exact L2L shifts), one launch.
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s);

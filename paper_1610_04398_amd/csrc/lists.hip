@@ -167,6 +167,94 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   }
 }
 
+// Lists of the paper's tree-code: one wave per target leaf A walks the source
+// tree from the root.  A source cell accepted for all of A's targets goes to
+// A's M2P list; a leaf that is not accepted goes to its P2P list; any other
+// cell is replaced by its children with sources.  The frontier lives in LDS
+// and is classified 64 cells at a time; ballots compact the output in a fixed
+// order.  Same emit modes and layouts as k_lists.
+__global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
+    int D, const int4* __restrict__ rec, const int* __restrict__ tleaves, int ntleaves, int num, int den, int emit,
+    int* __restrict__ cnt_m, int* __restrict__ cnt_p, const int* __restrict__ off_m, const int* __restrict__ off_p,
+    int* __restrict__ m_src, int* __restrict__ p_src, int cap_m, int cap_p, int* __restrict__ flags) {
+  __shared__ int front[kListWaves][2][kFrontierCap];
+  const int w = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kListWaves + w);
+  if (wid >= ntleaves) return;
+  const int A = tleaves[wid];
+  const int4 rA = rec[A];
+  const int lA = rec_level(rA);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
+  int* cur = front[w][0];
+  int* nxt = front[w][1];
+  int ncur = 0;
+  if (rec_has_src(rec[0])) {
+    if (lane == 0) cur[0] = 0;
+    ncur = 1;
+  }
+  __syncwarp();
+  int nm = 0, np = 0;
+  const int64_t mbase = emit == 1 ? off_m[A] : (int64_t)A * cap_m;
+  const int64_t pbase = emit == 1 ? off_p[A] : (int64_t)A * cap_p;
+  const int mlim = emit == 2 ? cap_m : INT_MAX;
+  const int plim = emit == 2 ? cap_p : INT_MAX;
+  bool overflow = false;
+  while (ncur > 0) {
+    int nnext = 0;
+    for (int base = 0; base < ncur; base += kWave) {
+      const int i = base + lane;
+      const bool valid = i < ncur;
+      const int B = valid ? cur[i] : 0;
+      bool acc = false, leafB = false;
+      int kid0 = 0, kmask = 0;
+      if (valid) {
+        const int4 rB = rec[B];
+        acc = treecode_accept(D, lA, rA.x, rA.y, rec_level(rB), rB.x, rB.y, num, den);
+        kid0 = rB.z;
+        leafB = kid0 < 0;
+        kmask = rec_kidmask(rB);
+      }
+      const bool em = valid && acc;
+      const bool ep = valid && !acc && leafB;
+      const bool push = valid && !acc && !leafB;
+      const uint64_t bm = __ballot(em);
+      const uint64_t bp = __ballot(ep);
+      if (emit) {
+        const int im = nm + __popcll(bm & lt_mask), ip = np + __popcll(bp & lt_mask);
+        if (em && im < mlim) m_src[mbase + im] = B;
+        if (ep && ip < plim) p_src[pbase + ip] = B;
+      }
+      nm += __popcll(bm);
+      np += __popcll(bp);
+      const int npush = push ? __popc(kmask) : 0;
+      const int incl = wave_incl_scan(npush);
+      const int total = __shfl(incl, kWave - 1, kWave);
+      int pos = nnext + incl - npush;
+      if (nnext + total > kFrontierCap) {
+        overflow = true;
+      } else {
+        if (push)
+          for (int q = 0; q < 4; ++q)
+            if ((kmask >> q) & 1) nxt[pos++] = kid0 + q;
+        nnext += total;
+      }
+    }
+    __syncwarp();
+    if (overflow) break;
+    int* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    ncur = nnext;
+  }
+  if (overflow && lane == 0) atomicOr(flags, kFlagFrontierOverflow);
+  if (emit == 2 && (nm > cap_m || np > cap_p) && lane == 0) atomicOr(flags, kFlagListOverflow);
+  if (emit != 1 && lane == 0) {
+    cnt_m[A] = emit == 2 ? min(nm, cap_m) : nm;
+    cnt_p[A] = emit == 2 ? min(np, cap_p) : np;
+  }
+}
+
 }  // namespace
 
 void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
@@ -183,6 +271,14 @@ void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int
   k_lists<<<(ntcells + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
       t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
       cap_m, cap_p, flags);
+}
+
+void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
+                         int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
+                         int cap_p, int* flags, hipStream_t s) {
+  if (ntleaves <= 0) return;
+  k_lists_treecode<<<(ntleaves + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
+      t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p, m_src, p_src, cap_m, cap_p, flags);
 }
 
 }  // namespace pp

@@ -43,7 +43,7 @@ enum BufId {
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
-  B_S64, B_SELFW,
+  B_S64, B_SELFW, B_MP32,
   B_COUNT
 };
 
@@ -59,13 +59,14 @@ struct Last {
   int ncells = 0, p = 0;
   int64_t n_m2l = 0, n_p2p = 0;
   bool has_expansions = false;
+  bool has_locals = false;
   int nparts = 1;
 };
 
 constexpr int kMiscInts = 128;
 // misc layout: [0] flags, [1] source count, [2] scratch total, [3] level work items,
 // [4..9] cell-list and interaction-list totals, [16..17] near-field pair count (u64),
-// [32..32+D+2] level starts of the tree.
+// [32..32+D+2] level starts of the tree, [96..103] bounding box of scattered input (4 doubles).
 constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7,
               M_NP2P = 8, M_NITEMS = 9, M_PAIRS = 16, M_LS = 32, M_BOX = 96;
 
@@ -76,6 +77,8 @@ struct pp_ctx {
   int p2p_parts = 4;  // near-field list split per target leaf (PP_P2P_PARTS overrides, 1..8)
   int cap_m2l = 128;  // per-cell list capacities of the one-pass lists (doubled on overflow)
   int cap_p2p = 64;
+  int cap_m2p = 512;  // the same for the tree-code variant's per-leaf lists
+  int cap_tp2p = 96;
   bool exact_lists = false;  // PP_EXACT_LISTS=1 forces the two-pass lists
   int dense_levels = 8;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
   bool profiling = false;
@@ -177,6 +180,7 @@ void validate_common(int64_t m, const double* tx, const double* ty, const pp_par
   if (prm->leaf_max < 1 || prm->leaf_max > 4096) throw PPError{PP_ERR_ARG, "leaf_max must lie in [1, 4096]"};
   if (prm->precision != PP_FP64 && prm->precision != PP_MIXED) throw PPError{PP_ERR_ARG, "unknown precision"};
   if (prm->self_mode != PP_SELF_SKIP && prm->self_mode != PP_SELF_CELLAVG) throw PPError{PP_ERR_ARG, "unknown self mode"};
+  if (prm->method != PP_METHOD_FMM && prm->method != PP_METHOD_TREECODE) throw PPError{PP_ERR_ARG, "unknown method"};
 }
 
 void validate(int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m, const double* tx,
@@ -382,12 +386,23 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   int* m2l_src = nullptr;
   int* p2p_src = nullptr;
   int64_t n_m2l = 0, n_p2pl = 0;
+  // the tree-code variant lists per target leaf (M2P cells, P2P leaves); the
+  // multipole method lists per cell with targets (M2L cells, P2P leaves)
+  const bool treecode = prm.method == PP_METHOD_TREECODE;
+  const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
+  const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
+  auto list_pass = [&](const int4* rec, int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp) {
+    if (treecode)
+      lists_treecode_pass(tv, rec, tleaves, ntl, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
+                          s);
+    else
+      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS, s);
+  };
   if (!direct) {
     int4* rec = ensure<int4>(c, B_REC, ncells);
     if (exact_lists) {
       cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, s);
-      lists_pass(tv, rec, tcells, ntc, num, den, 0, cm2l, cp2p, nullptr, nullptr, nullptr, nullptr, 0, 0,
-                 misc + M_FLAGS, s);
+      list_pass(rec, 0, nullptr, nullptr, nullptr, nullptr, 0, 0);
       int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
       scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
       scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
@@ -397,14 +412,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       n_p2pl = c.pinned[M_NP2P];
       m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
       p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
-      lists_pass(tv, rec, tcells, ntc, num, den, 1, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, 0, 0, misc + M_FLAGS,
-                 s);
+      list_pass(rec, 1, om2l, op2p, m2l_src, p2p_src, 0, 0);
     } else {
-      m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * c.cap_m2l);
-      p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * c.cap_p2p);
-      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, c.cap_m2l, c.cap_p2p, s);
-      lists_pass(tv, rec, tcells, ntc, num, den, 2, cm2l, cp2p, om2l, op2p, m2l_src, p2p_src, c.cap_m2l, c.cap_p2p,
-                 misc + M_FLAGS, s);
+      m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
+      p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
+      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, s);
+      list_pass(rec, 2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near);
     }
   }
 
@@ -437,8 +450,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   double* far = nullptr;
   if (!direct) {
     double2* mp = ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
-    double2* loc = ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
-    double2* own = ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
+    double2* loc = treecode ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
+    double2* own = treecode ? nullptr : ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
     far = ensure<double>(c, B_FAR, m);
     mark(PP_PHASE_P2M);
     p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
@@ -450,11 +463,19 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
     }
     mark(PP_PHASE_M2L);
-    m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
-    mark(PP_PHASE_L2L);
-    downward(tv, tcells, ntc, p, own, loc, s);
-    mark(PP_PHASE_L2P);
-    l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+    if (treecode) {
+      // multipoles evaluated at the targets; no local expansions
+      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, mixed ? ensure<float2>(c, B_MP32, (int64_t)ncells * (p + 1)) : nullptr,
+          rel64, rel32, mixed ? 1 : 0, far, misc + M_FLAGS, s);
+      mark(PP_PHASE_L2L);
+      mark(PP_PHASE_L2P);
+    } else {
+      m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
+      mark(PP_PHASE_L2L);
+      downward(tv, tcells, ntc, p, own, loc, s);
+      mark(PP_PHASE_L2P);
+      l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+    }
   } else {
     for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
   }
@@ -537,9 +558,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.last.m = m;
   c.last.ncells = ncells;
   c.last.p = p;
-  c.last.n_m2l = exact_lists ? n_m2l : (int64_t)ncells * c.cap_m2l;
-  c.last.n_p2p = exact_lists ? n_p2pl : (int64_t)ncells * c.cap_p2p;
+  c.last.n_m2l = exact_lists ? n_m2l : (int64_t)ncells * cap_far;
+  c.last.n_p2p = exact_lists ? n_p2pl : (int64_t)ncells * cap_near;
   c.last.has_expansions = !direct;
+  c.last.has_locals = !direct && !treecode;
   c.last.nparts = nparts;
   return PP_OK;
 }
@@ -560,8 +582,13 @@ pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const dou
     pp_status st = run_solve(*c, direct, c->exact_lists, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
     if (st == PP_ERR_LIMIT) {
       // a list outgrew its per-cell capacity: make room for next time and redo this solve exactly
-      c->cap_m2l *= 2;
-      c->cap_p2p *= 2;
+      if (prm->method == PP_METHOD_TREECODE) {
+        c->cap_m2p *= 2;
+        c->cap_tp2p *= 2;
+      } else {
+        c->cap_m2l *= 2;
+        c->cap_p2p *= 2;
+      }
       st = run_solve(*c, direct, true, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
     }
     c->err.clear();
@@ -618,11 +645,16 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
-  if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p" initial capacities
-    int a = 0, b = 0;
-    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a > 0 && b > 0) {
+  if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities
+    int a = 0, b = 0, x = 0, y = 0;
+    const int got = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &x, &y);
+    if (got >= 2 && a > 0 && b > 0) {
       c->cap_m2l = a;
       c->cap_p2p = b;
+    }
+    if (got == 4 && x > 0 && y > 0) {
+      c->cap_m2p = x;
+      c->cap_tp2p = y;
     }
   }
   c->budget = hbm_budget_bytes;
@@ -715,7 +747,7 @@ pp_status pp_debug_copy(const pp_ctx* cc, int32_t what, void* dst, int64_t capac
     case PP_ARR_P2P_CNT: id = L.has_expansions ? B_CP2P : -1; n = L.ncells; break;
     case PP_ARR_P2P_SRC: id = L.has_expansions ? B_P2PSRC : -1; n = L.n_p2p; break;
     case PP_ARR_MULTIPOLE: id = L.has_expansions ? B_MP : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
-    case PP_ARR_LOCAL: id = L.has_expansions ? B_LOC : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
+    case PP_ARR_LOCAL: id = L.has_locals ? B_LOC : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
     case PP_ARR_FAR: id = L.has_expansions ? B_FAR : -1; n = L.m; esz = 8; break;
     case PP_ARR_NEAR: id = B_NEAR; n = L.m * L.nparts; esz = 8; break;
     case PP_ARR_LEAF_WNEAR: id = B_WNEAR; n = (int64_t)L.ncells * L.nparts; esz = 8; break;

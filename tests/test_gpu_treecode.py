@@ -1,0 +1,116 @@
+"""GPU tests of the paper's tree-code variant (method="treecode": per-leaf lists
+with s/d < theta, multipoles evaluated at the targets, no local expansions)
+against the reference tree-code and the FP64 oracle direct sum."""
+
+import numpy as np
+import pytest
+
+from oracle import direct, fmm_ref, tree_ref
+from workloads import generators as G
+
+from gpu_common import rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_04398_amd as pp
+    s = pp.Solver(0)
+    yield s
+    s.close()
+
+
+def _case(seed, n=40, nt=500, zero_frac=0.3):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = rng.standard_normal((n, n))
+    f[rng.uniform(size=f.shape) < zero_frac] = 0.0
+    h = 1.0 / n
+    x, y = G.grid_nodes(G.GridSpec(n, n, h))
+    tx = np.concatenate([x.ravel()[::3], 0.3 + 0.02 * rng.standard_normal(nt // 4), rng.uniform(0, 1, nt)])
+    ty = np.concatenate([y.ravel()[::3], 0.6 + 0.02 * rng.standard_normal(nt // 4), rng.uniform(0, 1, nt)])
+    return f, h, np.clip(tx, 0, 1 - 1e-12), np.clip(ty, 0, 1 - 1e-12)
+
+
+def _gpu_lists(solver, name):
+    off = solver.debug_array(f"{name}_OFF")
+    cnt = solver.debug_array(f"{name}_CNT")
+    src = solver.debug_array(f"{name}_SRC")
+    return off, cnt, src
+
+
+@pytest.mark.parametrize("seed,leaf_max,theta", [(1, 8, 0.5), (2, 16, 0.4), (3, 4, 0.6)])
+def test_treecode_lists_match_reference(solver, seed, leaf_max, theta):
+    f, h, tx, ty = _case(seed)
+    solver.solve_grid(f, h, tx, ty, p=6, theta=theta, leaf_max=leaf_max, precision="fp64", method="treecode")
+    info = tree_ref.grid_tree(f, tx, ty, h, leaf_max=leaf_max)
+    ref = tree_ref.bh_lists(info["tree"], theta)
+    mo, mc, ms = _gpu_lists(solver, "M2L")
+    po, pc, ps = _gpu_lists(solver, "P2P")
+    for a, (m2p, p2p) in ref.items():
+        assert sorted(ms[mo[a]:mo[a] + mc[a]].tolist()) == m2p, a
+        assert sorted(ps[po[a]:po[a] + pc[a]].tolist()) == p2p, a
+
+
+def test_treecode_fp64_matches_reference_treecode(solver):
+    f, h, tx, ty = _case(4, n=32, nt=300)
+    got = solver.solve_grid(f, h, tx, ty, p=10, theta=0.5, leaf_max=16, precision="fp64", method="treecode")
+    r = fmm_ref.treecode_grid(f, tx, ty, h, 10, 0.5, leaf_max=16)
+    assert rel_l2(got, r["P"]) < 1e-12
+    far = solver.debug_array("FAR")
+    perm = solver.debug_array("TGT_PERM")
+    assert rel_l2(far / (2 * np.pi), r["far"][perm]) < 1e-12
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
+@pytest.mark.parametrize("self_mode", ["skip", "cellavg"])
+def test_treecode_vs_direct(solver, precision, tol, self_mode):
+    f, h, tx, ty = _case(5, n=64, nt=800)
+    ref = direct.direct_grid(f, h, tx, ty, self_mode=1 if self_mode == "cellavg" else 0)
+    got = solver.solve_grid(f, h, tx, ty, p=12, theta=0.5, leaf_max=32, precision=precision, self_mode=self_mode,
+                            method="treecode")
+    assert rel_l2(got, ref) < tol
+
+
+def test_treecode_vortex512_sampled(solver):
+    w = G.workload("vortex512")
+    g = w["grid"]
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    P = to_host(solver.solve_grid(f, g.h, tx, ty, p=w["p"], theta=w["theta"], precision="mixed", method="treecode"))
+    rng = np.random.Generator(np.random.PCG64(3))
+    sel = np.concatenate([rng.choice(w["n_grid_targets"], 300, replace=False),
+                          w["n_grid_targets"] + rng.choice(w["tx"].size - w["n_grid_targets"], 100, replace=False)])
+    ref = direct.direct_grid(w["f"], g.h, w["tx"][sel], w["ty"][sel])
+    assert rel_l2(P[sel], ref) < 1e-4
+    st = solver.stats()
+    assert st["n_m2l"] > 0 and st["n_p2p_pairs"] > 0
+
+
+def test_treecode_points(solver):
+    wl = G.points_workload(128)
+    got = solver.solve_points(wl["sx"], wl["sy"], wl["w"], wl["tx"], wl["ty"], p=12, theta=0.5, precision="fp64",
+                              method="treecode")
+    rng = np.random.Generator(np.random.PCG64(8))
+    sel = rng.choice(wl["tx"].size, 400, replace=False)
+    ref = direct.direct_points(wl["sx"], wl["sy"], wl["w"], wl["tx"][sel], wl["ty"][sel])
+    assert rel_l2(got[sel], ref) < 1e-6
+
+
+def test_treecode_list_modes_agree_bitwise(solver, monkeypatch):
+    import paper_1610_04398_amd as pp
+    f, h, tx, ty = _case(11, n=64, nt=900)
+    kw = dict(p=10, theta=0.5, leaf_max=16, precision="mixed", method="treecode")
+    ref = solver.solve_grid(f, h, tx, ty, **kw)
+    for env in ({"PP_EXACT_LISTS": "1"}, {"PP_LIST_CAPS": "128,64,5,3"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        s2 = pp.Solver(0)
+        got = s2.solve_grid(f, h, tx, ty, **kw)
+        again = s2.solve_grid(f, h, tx, ty, **kw)
+        s2.close()
+        for k in env:
+            monkeypatch.delenv(k)
+        assert np.array_equal(got, ref) and np.array_equal(again, ref), env
