@@ -371,120 +371,105 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
 // one wave per target leaf A, lane j on target j of each 64-target chunk, and
 // for every source cell B of A's list
 //   far += a_0 (ln|w| + ln s_B) + Re sum_{k=1..p} a'_k w^-k,   w = (t - z_B) / s_B,
-// by Horner in u = 1/w.  The list entry, B's geometry and its coefficients are
-// wave-uniform (scalar loads).  Offsets from A's corner are in units of h; the
-// corner difference to B's centre is an exact half-integer.
+// by Horner in u = 1/w.  The list is consumed 64 cells at a time: lane i
+// loads cell i's geometry (corner difference to A in units of h, 1/s_B, the
+// ln s_B term) and its coefficients into the wave's LDS slice, so the
+// evaluation loop reads only LDS broadcasts.  T = float for mixed precision
+// (coefficients rounded when staged, each cell's term added to an FP64 sum),
+// double otherwise.
 constexpr double kLn2d = 0.69314718055994530942;
+constexpr int kM2PWaves = 4;
 
-__global__ __launch_bounds__(256) void k_m2p64(TreeView t, const int* __restrict__ tleaves, int n,
-                                               const int* __restrict__ off, const int* __restrict__ cnt,
-                                               const int* __restrict__ src, int p, double lnh,
-                                               const double2* __restrict__ mp, const double2* __restrict__ rel64,
-                                               double* __restrict__ far, int* __restrict__ flags) {
-  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
-  if (wid >= n) return;
+template <class T>
+struct Cx2 {
+  T x, y;
+};
+
+template <class T>
+__global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int* __restrict__ tleaves, int n,
+                                                          const int* __restrict__ off, const int* __restrict__ cnt,
+                                                          const int* __restrict__ src, int p, double lnh,
+                                                          const double2* __restrict__ mp,
+                                                          const double2* __restrict__ rel64,
+                                                          double* __restrict__ far, int* __restrict__ flags) {
+  extern __shared__ double m2p_lds[];
+  const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
+  const int P1 = p + 1;
+  // per wave: kWave cells x (P1 coefficients + 2 geometry slots)
+  Cx2<T>* coef = (Cx2<T>*)m2p_lds + (size_t)w * kWave * (P1 + 2);
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kM2PWaves + w));
+  if (wid >= n) return;
   const int A = tleaves[wid];
   const int shA = t.D - t.lvl[A];
   const int64_t ax2 = (int64_t)(2 * t.ix[A]) << shA, ay2 = (int64_t)(2 * t.iy[A]) << shA;
   const int e0 = off[A], ne = cnt[A];
   const int tb = t.tb[A], te = t.te[A];
-  const int P1 = p + 1;
   bool bad = false;
   for (int chunk = tb; chunk < te; chunk += kWave) {
     const int k = chunk + lane;
     const bool active = k < te;
-    const double2 r = active ? rel64[k] : make_double2(0.0, 0.0);
+    const double2 r64 = active ? rel64[k] : make_double2(0.0, 0.0);
+    const T rx = (T)r64.x, ry = (T)r64.y;
     double acc_far = 0.0;
-    for (int e = 0; e < ne; ++e) {
-      const int B = src[e0 + e];
-      if ((unsigned)B >= (unsigned)t.ncells) {
-        bad = true;
-        continue;
+    for (int base = 0; base < ne; base += kWave) {
+      const int nb = min(kWave, ne - base);
+      // stage: lane i takes list entry base + i
+      if (lane < nb) {
+        int B = src[e0 + base + lane];
+        Cx2<T>* cb = coef + (size_t)lane * (P1 + 2);
+        if ((unsigned)B >= (unsigned)t.ncells) {
+          bad = true;
+          cb[0] = {(T)0, (T)0};
+          cb[1] = {(T)1, (T)0};
+          for (int q = 0; q < P1; ++q) cb[2 + q] = {(T)0, (T)0};
+        } else {
+          const int shB = t.D - t.lvl[B];
+          const double dx = 0.5 * (double)(ax2 - ((int64_t)(2 * t.ix[B] + 1) << shB));
+          const double dy = 0.5 * (double)(ay2 - ((int64_t)(2 * t.iy[B] + 1) << shB));
+          cb[0] = {(T)dx, (T)dy};
+          cb[1] = {(T)ldexp(1.0, -shB), (T)((double)shB * kLn2d + lnh)};
+          const double2* a = mp + (int64_t)B * P1;
+          for (int q = 0; q < P1; ++q) {
+            const double2 v = a[q];
+            cb[2 + q] = {(T)v.x, (T)v.y};
+          }
+        }
       }
-      const int shB = t.D - t.lvl[B];
-      const double inv_s = ldexp(1.0, -shB);
-      const double dx = 0.5 * (double)(ax2 - ((int64_t)(2 * t.ix[B] + 1) << shB));
-      const double dy = 0.5 * (double)(ay2 - ((int64_t)(2 * t.iy[B] + 1) << shB));
-      const double wx = (r.x + dx) * inv_s, wy = (r.y + dy) * inv_s;
-      const double r2 = wx * wx + wy * wy;
-      const double ir2 = 1.0 / r2;
-      const double ux = wx * ir2, uy = -wy * ir2;
-      const double2* a = mp + (int64_t)B * P1;
-      double hx = 0.0, hy = 0.0;
-      for (int q = p; q >= 1; --q) {
-        const double2 c = a[q];
-        const double nx = hx * ux - hy * uy + c.x;
-        const double ny = hx * uy + hy * ux + c.y;
-        hx = nx;
-        hy = ny;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j = 0; j < nb; ++j) {
+        const Cx2<T>* cb = coef + (size_t)j * (P1 + 2);
+        const Cx2<T> g0 = cb[0], g1 = cb[1];
+        const T wx = (rx + g0.x) * g1.x, wy = (ry + g0.y) * g1.x;
+        const T r2 = wx * wx + wy * wy;
+        const T ir2 = (T)1 / r2;
+        const T ux = wx * ir2, uy = -wy * ir2;
+        T hx = (T)0, hy = (T)0;
+        for (int q = p; q >= 1; --q) {
+          const Cx2<T> c = cb[2 + q];
+          const T nx = hx * ux - hy * uy + c.x;
+          const T ny = hx * uy + hy * ux + c.y;
+          hx = nx;
+          hy = ny;
+        }
+        const T re = hx * ux - hy * uy;
+        T lg;
+        if constexpr (sizeof(T) == 4)
+          lg = (T)(0.5 * kLn2d) * __builtin_amdgcn_logf(r2) + g1.y;
+        else
+          lg = (T)0.5 * log(r2) + g1.y;
+        acc_far += (double)(re + cb[2].x * lg);
       }
-      const double re = hx * ux - hy * uy;
-      acc_far += re + a[0].x * (0.5 * log(r2) + (double)shB * kLn2d + lnh);
+      // the slice is rewritten by the next batch only after every lane is done with it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (active) far[k] = acc_far;
   }
   if (bad && lane == 0) atomicOr(flags, kFlagBadIndex);
-}
-
-// FP32 evaluation (mixed precision) from FP32 copies of the coefficients; each
-// cell's contribution is added to an FP64 accumulator.
-__global__ __launch_bounds__(256) void k_m2p32(TreeView t, const int* __restrict__ tleaves, int n,
-                                               const int* __restrict__ off, const int* __restrict__ cnt,
-                                               const int* __restrict__ src, int p, double lnh,
-                                               const float2* __restrict__ mp32, const float2* __restrict__ rel32,
-                                               double* __restrict__ far, int* __restrict__ flags) {
-  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave));
-  if (wid >= n) return;
-  const int lane = threadIdx.x % kWave;
-  const int A = tleaves[wid];
-  const int shA = t.D - t.lvl[A];
-  const int ax2 = (2 * t.ix[A]) << shA, ay2 = (2 * t.iy[A]) << shA;
-  const int e0 = off[A], ne = cnt[A];
-  const int tb = t.tb[A], te = t.te[A];
-  const int P1 = p + 1;
-  const float lnh2 = (float)lnh;
-  bool bad = false;
-  for (int chunk = tb; chunk < te; chunk += kWave) {
-    const int k = chunk + lane;
-    const bool active = k < te;
-    const float2 r = active ? rel32[k] : make_float2(0.0f, 0.0f);
-    double acc_far = 0.0;
-    for (int e = 0; e < ne; ++e) {
-      const int B = src[e0 + e];
-      if ((unsigned)B >= (unsigned)t.ncells) {
-        bad = true;
-        continue;
-      }
-      const int shB = t.D - t.lvl[B];
-      const float inv_s = ldexpf(1.0f, -shB);
-      const float dx = 0.5f * (float)(ax2 - ((2 * t.ix[B] + 1) << shB));
-      const float dy = 0.5f * (float)(ay2 - ((2 * t.iy[B] + 1) << shB));
-      const float wx = (r.x + dx) * inv_s, wy = (r.y + dy) * inv_s;
-      const float r2 = wx * wx + wy * wy;
-      const float ir2 = 1.0f / r2;
-      const float ux = wx * ir2, uy = -wy * ir2;
-      const float2* a = mp32 + (int64_t)B * P1;
-      float hx = 0.0f, hy = 0.0f;
-      for (int q = p; q >= 1; --q) {
-        const float2 c = a[q];
-        const float nx = hx * ux - hy * uy + c.x;
-        const float ny = hx * uy + hy * ux + c.y;
-        hx = nx;
-        hy = ny;
-      }
-      const float re = hx * ux - hy * uy;
-      const float lg = 0.5f * (float)kLn2d * __builtin_amdgcn_logf(r2) + (float)shB * (float)kLn2d + lnh2;
-      acc_far += (double)(re + a[0].x * lg);
-    }
-    if (active) far[k] = acc_far;
-  }
-  if (bad && lane == 0) atomicOr(flags, kFlagBadIndex);
-}
-
-__global__ void k_to_f32(const double2* __restrict__ a, int64_t n, float2* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
 #define PP_DISPATCH(p, KERNEL, GRID, BLOCK, STREAM, ...)                      \
@@ -557,17 +542,25 @@ void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, con
 }
 
 void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
-         const double2* mp, float2* mp32, const double2* rel64, const float2* rel32, int fp32, double* far, int* flags,
-         hipStream_t s) {
+         const double2* mp, const double2* rel64, int fp32, double* far, int* flags, hipStream_t s) {
   if (n <= 0) return;
-  const unsigned g = (unsigned)((n + 3) / 4);
-  if (fp32) {
-    const int64_t nc = (int64_t)t.ncells * (p + 1);
-    k_to_f32<<<(unsigned)((nc + 255) / 256), 256, 0, s>>>(mp, nc, mp32);
-    k_m2p32<<<g, 256, 0, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp32, rel32, far, flags);
-  } else {
-    k_m2p64<<<g, 256, 0, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp, rel64, far, flags);
-  }
+  const unsigned g = (unsigned)((n + kM2PWaves - 1) / kM2PWaves);
+  const size_t per = (size_t)kM2PWaves * kWave * (p + 3);
+  // up to 94 KB of LDS at p = 20 in FP64 (gfx950 allows 160 KB per workgroup)
+  static std::once_flag lds_opt_in;
+  std::call_once(lds_opt_in, [] {
+    const size_t most = (size_t)kM2PWaves * kWave * (kMaxP + 3);
+    (void)hipFuncSetAttribute((const void*)k_m2p<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(most * sizeof(Cx2<float>)));
+    (void)hipFuncSetAttribute((const void*)k_m2p<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(most * sizeof(Cx2<double>)));
+  });
+  if (fp32)
+    k_m2p<float><<<g, kM2PWaves * kWave, per * sizeof(Cx2<float>), s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp,
+                                                                         rel64, far, flags);
+  else
+    k_m2p<double><<<g, kM2PWaves * kWave, per * sizeof(Cx2<double>), s>>>(t, tleaves, n, off, cnt, src, p, log(h),
+                                                                           mp, rel64, far, flags);
 }
 
 }  // namespace pp

@@ -140,10 +140,9 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
          double h, const double2* mp, double2* loc, int* flags, hipStream_t s);
 // M2P of the tree-code variant: far[k] for every target of the n target leaves
 // from the multipoles of their M2P lists (off/cnt by cell id); fp32 != 0
-// evaluates in FP32 from copies of the coefficients written to mp32.
+// evaluates in FP32.
 void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
-         const double2* mp, float2* mp32, const double2* rel64, const float2* rel32, int fp32, double* far, int* flags,
-         hipStream_t s);
+         const double2* mp, const double2* rel64, int fp32, double* far, int* flags, hipStream_t s);
 // Final local expansion of every cell with targets from its own M2L local
 // (`own`) and its ancestors' (exact L2L shifts), one launch.
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s);

@@ -4,10 +4,10 @@
 // is listed for every target leaf.
 //
 // Work item: one wave per (target leaf, part of its source list); lane j owns
-// target j of each 64-target chunk.  Every lane of a wave needs the same source at the same time,
-// so sources are read with wave-uniform addresses (scalar loads, no LDS
-// staging) and each source costs one pass of ~10 VALU instructions over the
-// 64 lanes.
+// target j of each 64-target chunk.  Every lane of a wave needs the same
+// source at the same time, so sources are read with wave-uniform addresses
+// (scalar loads, no LDS staging) and each source costs one pass of ~7 VALU
+// instructions over the 64 lanes.
 //
 // Coordinates are offsets in units of h: sources relative to their own leaf
 // corner (exact half-integers for grid nodes), targets relative to their leaf
@@ -43,24 +43,24 @@ __device__ inline float pair_log2(float tx, float ty, const float4& q, bool guar
 }
 
 // Sources [s0, s1) of one leaf against this lane's target.  Terms are summed
-// four at a time (the first product starts from -comp) and each group is
-// folded into the running sum with Kahan compensation; a ragged tail is
-// folded one term at a time.
+// eight at a time (the first product starts from -comp) and each group is
+// folded into the running sum with Kahan compensation (3 VALU per 8 pairs);
+// a ragged tail is folded one term at a time.
 template <bool GUARD>
 __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s1, float tx, float ty, float& sum,
                                   float& comp) {
+  constexpr int G = 8;
   int s = s0;
-#pragma unroll 2
-  for (; s + 4 <= s1; s += 4) {
-    const float4 q0 = src4[s], q1 = src4[s + 1], q2 = src4[s + 2], q3 = src4[s + 3];
-    const float l0 = pair_log2(tx, ty, q0, GUARD);
-    const float l1 = pair_log2(tx, ty, q1, GUARD);
-    const float l2 = pair_log2(tx, ty, q2, GUARD);
-    const float l3 = pair_log2(tx, ty, q3, GUARD);
-    float y = fmaf(q0.z, l0, -comp);
-    y = fmaf(q1.z, l1, y);
-    y = fmaf(q2.z, l2, y);
-    y = fmaf(q3.z, l3, y);
+  for (; s + G <= s1; s += G) {
+    float4 q[G];
+    float l[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) q[i] = src4[s + i];
+#pragma unroll
+    for (int i = 0; i < G; ++i) l[i] = pair_log2(tx, ty, q[i], GUARD);
+    float y = fmaf(q[0].z, l[0], -comp);
+#pragma unroll
+    for (int i = 1; i < G; ++i) y = fmaf(q[i].z, l[i], y);
     kahan_fold(y, sum, comp);
   }
   for (; s < s1; ++s) {

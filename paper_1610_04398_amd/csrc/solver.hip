@@ -43,7 +43,7 @@ enum BufId {
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
-  B_S64, B_SELFW, B_MP32,
+  B_S64, B_SELFW,
   B_COUNT
 };
 
@@ -465,8 +465,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(PP_PHASE_M2L);
     if (treecode) {
       // multipoles evaluated at the targets; no local expansions
-      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, mixed ? ensure<float2>(c, B_MP32, (int64_t)ncells * (p + 1)) : nullptr,
-          rel64, rel32, mixed ? 1 : 0, far, misc + M_FLAGS, s);
+      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far, misc + M_FLAGS, s);
       mark(PP_PHASE_L2L);
       mark(PP_PHASE_L2P);
     } else {
