@@ -109,34 +109,72 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
       out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
 }
 
-// One M2M output coefficient: a'_l of a parent from its children's scaled
-// coefficients a = e + stride * slot (LDS), q-th child at slot0 + q with
-// centre offset d_q (in parent sides) given by its quadrant.
+// M2M as fixed matrices.  With coefficients scaled by the cell side, the shift
+// of a child's expansion to its parent's centre depends only on the child's
+// quadrant q, through d_q = (+-1/4, +-1/4) (the child centre's offset in parent
+// sides).  From eq. expandedShift with the corrected S term:
+//   a'_l(parent) = sum_q sum_{k=0..l} T_q[l][k] a'_k(child q),
+//   T_q[0][0] = 1,  T_q[l][0] = -d_q^l / l,  T_q[l][k] = C(l-1, k-1) 2^-k d_q^(l-k).
+// The table is built at compile time; every entry but the 1/l ones is exact.
+struct M2MTable {
+  double v[4][kMaxP + 1][kMaxP + 1][2];
+};
+constexpr M2MTable make_m2m_table() {
+  M2MTable t{};
+  for (int q = 0; q < 4; ++q) {
+    const double dx = (q & 1) ? 0.25 : -0.25, dy = (q & 2) ? 0.25 : -0.25;
+    // powers d^n, n = 0..kMaxP
+    double pw[kMaxP + 1][2] = {};
+    pw[0][0] = 1.0;
+    for (int n = 1; n <= kMaxP; ++n) {
+      pw[n][0] = pw[n - 1][0] * dx - pw[n - 1][1] * dy;
+      pw[n][1] = pw[n - 1][0] * dy + pw[n - 1][1] * dx;
+    }
+    t.v[q][0][0][0] = 1.0;
+    for (int l = 1; l <= kMaxP; ++l) {
+      t.v[q][l][0][0] = -pw[l][0] / l;
+      t.v[q][l][0][1] = -pw[l][1] / l;
+      double c = 1.0;  // C(l-1, k-1), k = 1
+      double two = 0.5;  // 2^-k
+      for (int k = 1; k <= l; ++k) {
+        t.v[q][l][k][0] = c * two * pw[l - k][0];
+        t.v[q][l][k][1] = c * two * pw[l - k][1];
+        c = c * (l - k) / k;
+        two *= 0.5;
+      }
+    }
+  }
+  return t;
+}
+__constant__ M2MTable c_m2m = make_m2m_table();
+
+// One M2M output coefficient a'_l of a parent from its children at LDS slots
+// slot0 + q (coefficients e + stride * slot), with the tables tm[q][l][k] in LDS.
 __device__ inline cplx m2m_coeff(int l, int nk, const double2* __restrict__ e, int stride, int slot0,
-                                 const int* __restrict__ hsrc, const int* __restrict__ quad) {
-  cplx b = {0.0, 0.0};
+                                 const int* __restrict__ hsrc, const int* __restrict__ quad,
+                                 const double2* __restrict__ tm, int P1) {
+  double bx0 = 0.0, by0 = 0.0, bx1 = 0.0, by1 = 0.0;
   for (int q = 0; q < nk; ++q) {
     const int slot = slot0 + q;
     if (!hsrc[slot]) continue;
     const double2* a = e + (int64_t)slot * stride;
-    const double a0 = a[0].x;
-    if (l == 0) {
-      b.x += a0;
-      continue;
+    const double2* row = tm + ((int64_t)quad[slot] * P1 + l) * P1;
+    // two accumulators shorten the dependent chain
+    int k = 0;
+    for (; k + 1 <= l; k += 2) {
+      const double2 t0 = row[k], a0 = a[k], t1 = row[k + 1], a1 = a[k + 1];
+      bx0 += t0.x * a0.x - t0.y * a0.y;
+      by0 += t0.x * a0.y + t0.y * a0.x;
+      bx1 += t1.x * a1.x - t1.y * a1.y;
+      by1 += t1.x * a1.y + t1.y * a1.x;
     }
-    const int qd = quad[slot];
-    const cplx d = {(qd & 1) ? 0.25 : -0.25, (qd & 2) ? 0.25 : -0.25};
-    // sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k, then -a_0 d^l / l
-    cplx acc = {0.0, 0.0};
-    cplx dp = {1.0, 0.0};
-    for (int k = l; k >= 1; --k) {
-      const double2 v = a[k];
-      acc = cadd(acc, cscale(cmul({v.x, v.y}, dp), binom(l - 1, k - 1) * ldexp(1.0, -k)));
-      dp = cmul(dp, d);
+    if (k == l) {
+      const double2 t0 = row[k], a0 = a[k];
+      bx0 += t0.x * a0.x - t0.y * a0.y;
+      by0 += t0.x * a0.y + t0.y * a0.x;
     }
-    b = cadd(b, cadd(acc, cscale(dp, -a0 / l)));
   }
-  return b;
+  return {bx0 + bx1, by0 + by1};
 }
 
 // M2M for up to four levels per launch (eq. expandedShift applied
@@ -153,10 +191,13 @@ constexpr int kM2MLevels = 4;
 constexpr int kM2MSlots = 341;  // 1 + 4 + 16 + 64 + 256
 __host__ __device__ constexpr int m2m_first(int d) { return ((1 << (2 * d)) - 1) / 3; }
 
-// LDS: five int arrays of kM2MSlots (padded to a 16-byte boundary), then the
-// expansions; 121 KB at p = 20, within gfx950's 160 KB per workgroup.
+// LDS: five int arrays of kM2MSlots (padded to a 16-byte boundary), the
+// expansions and the four shift tables; 149 KB at p = 20, within gfx950's
+// 160 KB per workgroup.
 constexpr int kM2MIntWords = 5 * kM2MSlots + 3;
-size_t m2m_lds_bytes(int p) { return kM2MIntWords * sizeof(int) + (size_t)kM2MSlots * (p + 1) * sizeof(double2); }
+size_t m2m_lds_bytes(int p) {
+  return kM2MIntWords * sizeof(int) + ((size_t)kM2MSlots * (p + 1) + 4 * (size_t)(p + 1) * (p + 1)) * sizeof(double2);
+}
 
 __global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1, int levels, int p,
                                                       double2* __restrict__ mp) {
@@ -173,6 +214,11 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1,
   if (R >= c1) return;
   const int P1 = p + 1;
   const int tid = threadIdx.x;
+  double2* tm = e + (size_t)kM2MSlots * P1;
+  for (int w = tid; w < 4 * P1 * P1; w += blockDim.x) {
+    const int q = w / (P1 * P1), l = (w / P1) % P1, k = w % P1;
+    tm[w] = make_double2(c_m2m.v[q][l][k][0], c_m2m.v[q][l][k][1]);
+  }
   for (int d = 0; d <= levels; ++d) {
     const int lo = m2m_first(d), hi = m2m_first(d + 1);
     for (int i = lo + tid; i < hi; i += blockDim.x) {
@@ -209,7 +255,7 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1,
       const int c = cell[i];
       if (c < 0 || !hsrc[i] || kid0[i] < 0) continue;
       const int slot0 = m2m_first(d + 1) + 4 * (i - lo);
-      const cplx v = m2m_coeff(l, nkid[i], e, P1, slot0, hsrc, quad);
+      const cplx v = m2m_coeff(l, nkid[i], e, P1, slot0, hsrc, quad, tm, P1);
       e[i * P1 + l] = make_double2(v.x, v.y);
       mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
     }
