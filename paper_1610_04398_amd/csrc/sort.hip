@@ -14,7 +14,7 @@ namespace pp {
 
 namespace {
 constexpr int kRsBlock = 256;
-constexpr int kRsItems = 8;
+constexpr int kRsItems = 4;  // 1024-key tiles: enough workgroups to fill the GPU at ~2.6e5 keys
 constexpr int kRsTile = kRsBlock * kRsItems;
 constexpr int kRsWaves = kRsBlock / kWave;
 constexpr int kRsMaxBits = 9;
