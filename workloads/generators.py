@@ -228,6 +228,36 @@ def fish_surface_targets(n_per_side: int, h: float, yc: float = 0.5, amp: float 
     return sx, sy, lx, ly
 
 
+def polygon_panels(vx, vy):
+    """Surface panels of a closed polygon with counter-clockwise vertices (vx, vy):
+    panel k runs from vertex k to vertex k+1 (cyclically); returns its midpoint
+    (mx, my), its outward unit normal (nx, ny) and its length ds."""
+    vx = np.asarray(vx, dtype=np.float64)
+    vy = np.asarray(vy, dtype=np.float64)
+    ex = np.roll(vx, -1) - vx
+    ey = np.roll(vy, -1) - vy
+    ds = np.hypot(ex, ey)
+    return 0.5 * (vx + np.roll(vx, -1)), 0.5 * (vy + np.roll(vy, -1)), ey / ds, -ex / ds, ds
+
+
+def ellipse_panels(n: int, cx: float = 0.5, cy: float = 0.5, a: float = 0.2, b: float = 0.05):
+    """Panels of the polygon through n points at equal parametric angle on an ellipse."""
+    vx, vy = ellipse_targets(n, cx, cy, a, b)
+    return polygon_panels(vx, vy)
+
+
+def fish_panels(n_per_side: int, h: float, **fish_kw):
+    """Panels of the closed polygon through the fish-surface points of
+    ``fish_surface_targets`` (lower side from head to tail, then the upper side
+    back to the head: counter-clockwise)."""
+    sx, sy, _, _ = fish_surface_targets(n_per_side, h, **fish_kw)
+    upper_x, upper_y = sx[:n_per_side], sy[:n_per_side]
+    lower_x, lower_y = sx[n_per_side:], sy[n_per_side:]
+    vx = np.concatenate([lower_x, upper_x[::-1]])
+    vy = np.concatenate([lower_y, upper_y[::-1]])
+    return polygon_panels(vx, vy)
+
+
 def stretched_axis(n: int, beta: float = 2.0, centre: float = 0.5):
     """Cell centres and widths of a 1-D grid on [0, 1] refined towards `centre`:
     edges proportional to sinh(beta (u - centre)) for uniform u, shifted and
