@@ -169,6 +169,28 @@ pp_status pp_direct_points(pp_ctx* ctx, int64_t n, const double* sx, const doubl
                            const double* tx, const double* ty, const pp_params* params, double* p_out,
                            void* hip_stream);
 
+/*
+ * Pressure forces on body surfaces (Sec. 2.3.1): for every surface panel j
+ * with pressure p[j] (e.g. the output of a solve at the panel points), unit
+ * outward normal (nx[j], ny[j]) and length ds[j], the pointwise force
+ * dF_j = -p_j n_j ds_j (eq. Fpress); for every body s, the panels
+ * [seg_start[s], seg_start[s+1]) of one closed surface, the net force
+ * F = sum_j dF_j (eq. FpressNet), the drag F . U / |U| along the free stream
+ * U = (ux, uy) and the coefficient 2 drag / (rho |U|^2 area) (eq. CdP).
+ * seg_start has nseg + 1 entries, starts at 0, ends at m and does not
+ * decrease (host memory); the sums are compensated and in a fixed order.
+ * dfx/dfy (m doubles, may be NULL) and out (nseg entries) may be host or
+ * device memory.  Errors: PP_ERR_ARG for bad sizes, offsets, |U|, rho or area.
+ */
+typedef struct {
+  double fx, fy;  /* net pressure force */
+  double drag;    /* F . U / |U| */
+  double cd;      /* 2 drag / (rho |U|^2 area) */
+} pp_force;
+pp_status pp_surface_forces(pp_ctx* ctx, int64_t m, const double* p, const double* nx, const double* ny,
+                            const double* ds, int32_t nseg, const int64_t* seg_start, double ux, double uy, double rho,
+                            double area, double* dfx, double* dfy, pp_force* out, void* hip_stream);
+
 pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
 
 /* Enable (on != 0) or disable per-phase GPU timing of later calls.  Timing

@@ -34,6 +34,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_footprint_estimate,
     pp_solve_grid,
     pp_solve_points,
+    pp_surface_forces,
     pp_status_string,
     pp_params,
     PP_FP64,
@@ -171,6 +172,43 @@ class Solver:
         """All-pairs GPU direct sum for scattered sources; see pp_direct_points."""
         prm = make_params(1, 0.5, leaf_max, precision, "skip")
         return self._run_points(pp_direct_points, sx, sy, w, tx, ty, prm, out, stream)
+
+    def surface_forces(self, p, nx, ny, ds, seg_start, u=(1.0, 0.0), rho=1.0, area=1.0, pointwise=False,
+                       stream=None):
+        """Pressure forces on closed surfaces (pp_surface_forces): returns a list of dicts (fx, fy, drag, cd),
+        one per segment, and with pointwise=True also the per-panel (dfx, dfy)."""
+        pp_, pk = _ptr(p, "p")
+        nxp, nxk = _ptr(nx, "nx")
+        nyp, nyk = _ptr(ny, "ny")
+        dsp, dsk = _ptr(ds, "ds")
+        m = int(np.prod(tuple(pk.shape)))
+        seg = np.ascontiguousarray(np.asarray(seg_start, dtype=np.int64))
+        nseg = seg.size - 1
+        out = (B.pp_force * max(nseg, 1))()
+        dfx = dfy = None
+        dxp = dyp = None
+        if pointwise:
+            if _is_torch(p):
+                import torch
+                dfx = torch.empty(m, dtype=torch.float64, device=p.device)
+                dfy = torch.empty(m, dtype=torch.float64, device=p.device)
+            else:
+                dfx = np.empty(m)
+                dfy = np.empty(m)
+            dxp, _ = _ptr(dfx, "dfx")
+            dyp, _ = _ptr(dfy, "dfy")
+        if stream is None:
+            stream = 0
+            if _is_torch(p) and p.is_cuda:
+                import torch
+                stream = torch.cuda.current_stream(p.device).cuda_stream
+        st = pp_surface_forces(self._ctx, m, pp_, nxp, nyp, dsp, nseg, seg.ctypes.data, float(u[0]), float(u[1]),
+                               float(rho), float(area), dxp, dyp, ctypes.addressof(out), stream)
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del pk, nxk, nyk, dsk
+        res = [dict(fx=f.fx, fy=f.fy, drag=f.drag, cd=f.cd) for f in out[:nseg]]
+        return (res, dfx, dfy) if pointwise else res
 
     def set_profiling(self, on: bool = True) -> None:
         st = pp_set_profiling(self._ctx, on)

@@ -37,7 +37,7 @@ UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
 EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
-            "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
+            "pp_surface_forces", "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
             "pp_server_create", "pp_server_submit", "pp_server_wait", "pp_server_cancel", "pp_server_destroy",
             "pp_server_last_error", "pp_footprint_estimate")
 PP_ERR_TIMEOUT = -6
@@ -55,6 +55,10 @@ class pp_stats(ctypes.Structure):
                 ("ntgt_leaves", ctypes.c_int32), ("nsources", ctypes.c_int64), ("ntargets", ctypes.c_int64),
                 ("n_m2l", ctypes.c_int64), ("n_p2p_lists", ctypes.c_int64), ("n_p2p_pairs", ctypes.c_int64),
                 ("ms_total", ctypes.c_double), ("ms_phase", ctypes.c_double * 12)]
+
+
+class pp_force(ctypes.Structure):
+    _fields_ = [("fx", ctypes.c_double), ("fy", ctypes.c_double), ("drag", ctypes.c_double), ("cd", ctypes.c_double)]
 
 
 class pp_server_cfg(ctypes.Structure):
@@ -103,6 +107,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_solve_points.restype = i32
     lib.pp_direct_points.argtypes = points_args
     lib.pp_direct_points.restype = i32
+    lib.pp_surface_forces.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, f64, f64, f64, f64, vp, vp, vp, vp]
+    lib.pp_surface_forces.restype = i32
     lib.pp_get_stats.argtypes = [vp, ctypes.POINTER(pp_stats)]
     lib.pp_get_stats.restype = i32
     lib.pp_set_profiling.argtypes = [vp, i32]
@@ -170,6 +176,12 @@ def pp_solve_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, params: pp
 def pp_direct_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:
     return lib().pp_direct_points(ctx, n, sx_ptr, sy_ptr, w_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params), out_ptr,
                                   stream)
+
+
+def pp_surface_forces(ctx, m, p_ptr, nx_ptr, ny_ptr, ds_ptr, nseg, seg_ptr, ux, uy, rho, area, dfx_ptr, dfy_ptr,
+                      out_ptr, stream) -> int:
+    return lib().pp_surface_forces(ctx, m, p_ptr, nx_ptr, ny_ptr, ds_ptr, nseg, seg_ptr, ux, uy, rho, area, dfx_ptr,
+                                   dfy_ptr, out_ptr, stream)
 
 
 def pp_get_stats(ctx) -> pp_stats:

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "../../include/pp.h"
 
 namespace pp {
 
@@ -191,5 +192,11 @@ void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tle
               const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
               const double* self_w, const double* f, double h, int self_mode, const int* flags, double* out,
               hipStream_t s);
+
+// ---- forces.hip: pressure forces on surfaces -----------------------------------------
+// One workgroup per segment seg[s]..seg[s+1] (device array of nseg + 1); dfx/dfy may be null.
+void surface_forces(const double* p, const double* nx, const double* ny, const double* ds, int nseg,
+                    const int64_t* seg, double ux, double uy, double rho, double area, double* dfx, double* dfy,
+                    pp_force* out, hipStream_t s);
 
 }  // namespace pp

@@ -43,7 +43,7 @@ enum BufId {
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
-  B_S64, B_SELFW,
+  B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
   B_COUNT
 };
 
@@ -693,6 +693,53 @@ pp_status pp_direct_points(pp_ctx* c, int64_t n, const double* sx, const double*
 pp_status pp_direct_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                          const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
   return guard(c, true, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_surface_forces(pp_ctx* c, int64_t m, const double* p, const double* nx, const double* ny,
+                            const double* ds, int32_t nseg, const int64_t* seg_start, double ux, double uy, double rho,
+                            double area, double* dfx, double* dfy, pp_force* out, void* stream) {
+  if (!c) return PP_ERR_ARG;
+  if (c->dead) {
+    c->err = "context is unusable after a device error";
+    return PP_ERR_DEVICE;
+  }
+  try {
+    if (m < 0 || nseg < 1 || !seg_start || !out || (m > 0 && (!p || !nx || !ny || !ds)))
+      throw PPError{PP_ERR_ARG, "bad sizes or null pointers"};
+    if (is_device_ptr(seg_start)) throw PPError{PP_ERR_ARG, "seg_start must be host memory"};
+    if (seg_start[0] != 0 || seg_start[nseg] != m) throw PPError{PP_ERR_ARG, "seg_start must run from 0 to m"};
+    for (int i = 0; i < nseg; ++i)
+      if (seg_start[i + 1] < seg_start[i]) throw PPError{PP_ERR_ARG, "seg_start decreases"};
+    const double speed = std::hypot(ux, uy);
+    if (!(speed > 0.0) || !std::isfinite(speed) || !(rho > 0.0) || !(area > 0.0) || !std::isfinite(rho) ||
+        !std::isfinite(area))
+      throw PPError{PP_ERR_ARG, "|U|, rho and area must be positive and finite"};
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const double* p_d = stage_in(*c, B_FP, p, m, s);
+    const double* nx_d = stage_in(*c, B_FNX, nx, m, s);
+    const double* ny_d = stage_in(*c, B_FNY, ny, m, s);
+    const double* ds_d = stage_in(*c, B_FDS, ds, m, s);
+    int64_t* seg_d = ensure<int64_t>(*c, B_FSEG, nseg + 1);
+    HIPCHK(hipMemcpyAsync(seg_d, seg_start, (size_t)(nseg + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    const bool dfx_dev = dfx && is_device_ptr(dfx), dfy_dev = dfy && is_device_ptr(dfy);
+    const bool out_dev = is_device_ptr(out);
+    double* dfx_d = dfx ? (dfx_dev ? dfx : ensure<double>(*c, B_FDFX, m)) : nullptr;
+    double* dfy_d = dfy ? (dfy_dev ? dfy : ensure<double>(*c, B_FDFY, m)) : nullptr;
+    pp_force* out_d = out_dev ? out : ensure<pp_force>(*c, B_FOUT, nseg);
+    surface_forces(p_d, nx_d, ny_d, ds_d, nseg, seg_d, ux, uy, rho, area, dfx_d, dfy_d, out_d, s);
+    HIPCHK(hipGetLastError());
+    if (dfx && !dfx_dev && m > 0) HIPCHK(hipMemcpyAsync(dfx, dfx_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (dfy && !dfy_dev && m > 0) HIPCHK(hipMemcpyAsync(dfy, dfy_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(out, out_d, (size_t)nseg * sizeof(pp_force), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->err.clear();
+    return PP_OK;
+  } catch (const PPError& e) {
+    c->err = e.msg;
+    if (e.code == PP_ERR_DEVICE) c->dead = true;
+    return e.code;
+  }
 }
 
 pp_status pp_set_profiling(pp_ctx* c, int32_t on) {
