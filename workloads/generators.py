@@ -110,6 +110,50 @@ def vortex_velocity_gradients(x: np.ndarray, y: np.ndarray, centres, gamma, rc):
     return ux, uy, vx, vy
 
 
+def vortex_velocity(x: np.ndarray, y: np.ndarray, centres, gamma, rc):
+    """Sum of Lamb-Oseen velocities (u, v) = K g(r^2) (-Y, X), K = Gamma / 2pi."""
+    u = np.zeros_like(x)
+    v = np.zeros_like(x)
+    for (xc, yc), gm, r in zip(centres, gamma, rc):
+        K = gm / (2.0 * math.pi)
+        X = x - xc
+        Y = y - yc
+        g, _ = _vortex_g(X * X + Y * Y, r * r)
+        u += -K * g * Y
+        v += K * g * X
+    return u, v
+
+
+def vortex_velocity_grid(g: GridSpec, seed, n_vortices: int = 64):
+    """(u, v) of `lamb_oseen_params(seed, n_vortices)` at the nodes of g, shape (ny, nx) each."""
+    centres, gamma, rc = lamb_oseen_params(seed, n_vortices)
+    x, y = grid_nodes(g)
+    u, v = vortex_velocity(x.ravel(), y.ravel(), centres, gamma, rc)
+    return u.reshape(g.ny, g.nx), v.reshape(g.ny, g.nx)
+
+
+def smoothed_heaviside(d: np.ndarray, eps: float) -> np.ndarray:
+    """0 for d <= -eps, 1 for d >= eps, and 1/2 (1 + d/eps + sin(pi d/eps)/pi) in between
+    (a cosine-mollified step of half-width eps)."""
+    d = np.asarray(d, dtype=np.float64)
+    mid = 0.5 * (1.0 + d / eps + np.sin(math.pi * d / eps) / math.pi)
+    return np.where(d <= -eps, 0.0, np.where(d >= eps, 1.0, mid))
+
+
+def ellipse_body(g: GridSpec, cx: float = 0.5, cy: float = 0.5, a: float = 0.2, b: float = 0.05,
+                 omega: float = 1.0, vel=(0.0, 0.0)):
+    """Characteristic function and body velocity of a rigid ellipse on the grid: chi is the
+    smoothed step (half-width 2h) of the scaled inside distance min(a, b) (1 - rho_e), rho_e the
+    ellipse radius function; (us, vs) is a rigid motion with translation vel and rotation omega
+    about the centre."""
+    x, y = grid_nodes(g)
+    re = np.sqrt(((x - cx) / a) ** 2 + ((y - cy) / b) ** 2)
+    chi = smoothed_heaviside(min(a, b) * (1.0 - re), 2.0 * g.h)
+    us = vel[0] - omega * (y - cy)
+    vs = vel[1] + omega * (x - cx)
+    return chi, us, vs
+
+
 def vortex_source(g: GridSpec, seed, n_vortices: int = 64, rho: float = 1.0, mask=None,
                   chunk: int = 1 << 18, workers: int | None = None) -> np.ndarray:
     """f = 2 rho (u_x v_y - u_y v_x) of a seeded Lamb-Oseen superposition.
