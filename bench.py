@@ -157,7 +157,8 @@ def main() -> int:
                     help="server admission bound on in-flight grid nodes + targets (0: none)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / sequential solves per second")
     ap.add_argument("--forces-panels", type=int, default=4096,
-                    help="panels per side of each of two fish bodies for the surface-force step (0: skip)")
+                    help="panels per side of each of two fish bodies for the force steps; 0 skips the source "
+                         "assembly and force timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (the known-size kernel that scales "
                          "the HBM byte counters of a profile) and exit")
@@ -276,27 +277,46 @@ def main() -> int:
                "sample": f"FP64 direct sum over all {N} nonzero sources at {n_sample} of the {M} targets "
                          f"(seeded), {t_cpu:.2f} s; rate scaled to whole solves"}
 
-    # pressure forces on two fish bodies (eq. Fpress, FpressNet, CdP): pressure at the panel midpoints
-    # from a solve with the workload's source, then the per-panel and per-body sums, timed alone
-    forces_rec = None
+    # the steps around the solve, timed alone on the workload's grid: the source from a gridded
+    # Lamb-Oseen velocity (eq. PoissonFinal), and the pressure and viscous forces on two fish bodies
+    # (eq. Fpress / FpressNet / CdP; eq. Fvisc / FviscNet / CdNu, lifted points 2h out)
+    around = None
     if args.forces_panels > 0:
+        reps = 50
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0_ = time.perf_counter()
+            for _ in range(reps):
+                r_ = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0_) / reps * 1e3, r_
+
+        vel = G.vortex_velocity_grid(g, w["seed"] if w["seed"] is not None else 0, 64)
+        ud, vd = (torch.as_tensor(a, device=dev) for a in vel)
+        fa = torch.empty_like(ud)
+        src_ms, _ = timed(lambda: s.pressure_source(ud, vd, g.h, out=fa))
         bodies = [G.fish_panels(args.forces_panels, g.h, yc=0.35), G.fish_panels(args.forces_panels, g.h, yc=0.65,
                                                                                  phase=0.25)]
         mx, my, fnx, fny, fds = [np.concatenate([b[i] for b in bodies]) for i in range(5)]
         seg = [0, bodies[0][0].size, mx.size]
         tpx, tpy, dnx, dny, dds = (torch.as_tensor(a, device=dev) for a in (mx, my, fnx, fny, fds))
-        Pp = s.solve_grid(f, g.h, tpx, tpy, **kw)
-        s.surface_forces(Pp, dnx, dny, dds, seg, u=(1.0, 0.0), rho=1.0, area=0.6)
-        torch.cuda.synchronize()
-        reps = 50
-        tf0 = time.perf_counter()
-        for _ in range(reps):
-            fr = s.surface_forces(Pp, dnx, dny, dds, seg, u=(1.0, 0.0), rho=1.0, area=0.6)
-        forces_ms = (time.perf_counter() - tf0) / reps * 1e3
-        forces_rec = {"panels": int(mx.size), "bodies": 2, "ms_per_call": forces_ms,
-                      "note": "per-panel dF = -P n dS and per-body F, drag, Cd (U = (1, 0), rho = 1, A = 0.6); host "
-                              "wall time per call including the copy of the two results",
-                      "result": fr}
+        lxd, lyd = tpx + 2 * g.h * dnx, tpy + 2 * g.h * dny
+        Pp = s.solve_grid(fa, g.h, tpx, tpy, **kw)
+        fp_ms, fr = timed(lambda: s.surface_forces(Pp, dnx, dny, dds, seg, u=(1.0, 0.0), rho=1.0, area=0.6))
+        fv_ms, fv = timed(lambda: s.viscous_forces(ud, vd, g.h, lxd, lyd, dnx, dny, dds, seg, mu=1e-3,
+                                                   uinf=(1.0, 0.0), rho=1.0, area=0.6))
+        nodes = g.nx * g.ny
+        around = {
+            "source_assembly": {"ms_per_call": src_ms, "grid": [g.nx, g.ny],
+                                "algorithmic_bytes": 24 * nodes,
+                                "GB_per_s": 24 * nodes / (src_ms * 1e-3) / 1e9,
+                                "note": "read u, v and write f (8 B each per node); host wall time per call"},
+            "pressure_forces": {"ms_per_call": fp_ms, "panels": int(mx.size), "bodies": 2, "result": fr},
+            "viscous_forces": {"ms_per_call": fv_ms, "panels": int(mx.size), "mu": 1e-3, "result": fv},
+            "note": "U = (1, 0), rho = 1, A = 0.6; host wall time per call including the copy of the results",
+        }
 
     served = None
     if args.serve_requests > 0:
@@ -339,7 +359,7 @@ def main() -> int:
         "tree": {k: st[k] for k in ("depth", "ncells", "nsrc_leaves", "ntgt_leaves", "n_m2l", "n_p2p_lists",
                                      "n_p2p_pairs")},
         "served": served,
-        "surface_forces": forces_rec,
+        "around_the_solve": around,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -191,6 +191,38 @@ pp_status pp_surface_forces(pp_ctx* ctx, int64_t m, const double* p, const doubl
                             const double* ds, int32_t nseg, const int64_t* seg_start, double ux, double uy, double rho,
                             double area, double* dfx, double* dfy, pp_force* out, void* hip_stream);
 
+/*
+ * Pressure source from a gridded velocity (eq. PoissonFinal): at every node of
+ * the nx x ny grid (spacing h, row-major like f)
+ *   f = -rho (grad u^T : grad u) + rho lambda div(chi (u_s - u))
+ * with grad u^T : grad u = u_x^2 + 2 u_y v_x + v_y^2.  Derivatives: central
+ * differences inside, second-order one-sided differences on the first and last
+ * row/column.  chi, us, vs (the smoothed solid indicator and the solid's
+ * velocity, node fields) may all be NULL, which drops the penalisation term.
+ * f_out (nx*ny) may be host or device memory and can be passed to
+ * pp_solve_grid.  Errors: PP_ERR_ARG for bad sizes or h, or non-finite output.
+ */
+pp_status pp_pressure_source(pp_ctx* ctx, int32_t nx, int32_t ny, double h, const double* u, const double* v,
+                             double rho, double lambda, const double* chi, const double* us, const double* vs,
+                             double* f_out, void* hip_stream);
+
+/*
+ * Viscous forces on body surfaces (Sec. 2.3.2): for every panel j with lifted
+ * point (lx[j], ly[j]) (the surface point moved outward along the normal,
+ * typically by 2h), unit outward normal (nx[j], ny[j]) and length ds[j], the
+ * velocity gradient of the grid node nearest to the lifted point gives
+ * D = (grad u + grad u^T)/2 and the force dF_j = 2 mu D n_j ds_j (eq. Fvisc);
+ * per body (segments as in pp_surface_forces) the net force (eq. FviscNet),
+ * drag and coefficient (eq. CdNu).  The grid is the one of pp_solve_grid
+ * (node (i, j) at x0 + (i + 1/2) h); the nearest node of a point is the
+ * centre of the cell holding it, clamped to the grid.
+ */
+pp_status pp_viscous_forces(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y0, double h, const double* u,
+                            const double* v, int64_t m, const double* lx, const double* ly, const double* pnx,
+                            const double* pny, const double* ds, int32_t nseg, const int64_t* seg_start, double mu,
+                            double ux, double uy, double rho, double area, double* dfx, double* dfy, pp_force* out,
+                            void* hip_stream);
+
 pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
 
 /* Enable (on != 0) or disable per-phase GPU timing of later calls.  Timing

@@ -33,8 +33,10 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_server_wait,
     pp_footprint_estimate,
     pp_solve_grid,
+    pp_pressure_source,
     pp_solve_points,
     pp_surface_forces,
+    pp_viscous_forces,
     pp_status_string,
     pp_params,
     PP_FP64,
@@ -172,6 +174,73 @@ class Solver:
         """All-pairs GPU direct sum for scattered sources; see pp_direct_points."""
         prm = make_params(1, 0.5, leaf_max, precision, "skip")
         return self._run_points(pp_direct_points, sx, sy, w, tx, ty, prm, out, stream)
+
+    def _stream_of(self, x, stream):
+        if stream is not None:
+            return stream
+        if _is_torch(x) and x.is_cuda:
+            import torch
+            return torch.cuda.current_stream(x.device).cuda_stream
+        return 0
+
+    def pressure_source(self, u, v, h, rho=1.0, lam=0.0, chi=None, us=None, vs=None, out=None, stream=None):
+        """f of eq. PoissonFinal on the grid of u, v (shape (ny, nx)); see pp_pressure_source."""
+        up, uk = _ptr(u, "u")
+        vp, vk = _ptr(v, "v")
+        ny, nx = tuple(uk.shape)
+        if tuple(vk.shape) != (ny, nx):
+            raise ValueError("u and v differ in shape")
+        keep = []
+        cp = usp = vsp = None
+        if chi is not None:
+            (cp, ck), (usp, usk), (vsp, vsk) = _ptr(chi, "chi"), _ptr(us, "us"), _ptr(vs, "vs")
+            keep += [ck, usk, vsk]
+        if out is None:
+            if _is_torch(u):
+                import torch
+                out = torch.empty((ny, nx), dtype=torch.float64, device=u.device)
+            else:
+                out = np.empty((ny, nx))
+        op, ok = _ptr(out, "out")
+        st = pp_pressure_source(self._ctx, nx, ny, float(h), up, vp, float(rho), float(lam), cp, usp, vsp, op,
+                                self._stream_of(u, stream))
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del uk, vk, ok, keep
+        return out
+
+    def viscous_forces(self, u, v, h, lx, ly, nx, ny, ds, seg_start, x0=0.0, y0=0.0, mu=1.0, uinf=(1.0, 0.0),
+                       rho=1.0, area=1.0, pointwise=False, stream=None):
+        """Viscous forces on closed surfaces from nearest-node gradients at lifted points; see
+        pp_viscous_forces.  Returns a list of dicts (fx, fy, drag, cd), and (dfx, dfy) with pointwise=True."""
+        up, uk = _ptr(u, "u")
+        vp, vk = _ptr(v, "v")
+        gy, gx = tuple(uk.shape)
+        ptrs = [_ptr(a, nm) for a, nm in ((lx, "lx"), (ly, "ly"), (nx, "nx"), (ny, "ny"), (ds, "ds"))]
+        m = int(np.prod(tuple(ptrs[0][1].shape)))
+        seg = np.ascontiguousarray(np.asarray(seg_start, dtype=np.int64))
+        nseg = seg.size - 1
+        res = (B.pp_force * max(nseg, 1))()
+        dfx = dfy = None
+        dxp = dyp = None
+        if pointwise:
+            if _is_torch(lx):
+                import torch
+                dfx = torch.empty(m, dtype=torch.float64, device=lx.device)
+                dfy = torch.empty(m, dtype=torch.float64, device=lx.device)
+            else:
+                dfx, dfy = np.empty(m), np.empty(m)
+            dxp, _ = _ptr(dfx, "dfx")
+            dyp, _ = _ptr(dfy, "dfy")
+        st = pp_viscous_forces(self._ctx, gx, gy, float(x0), float(y0), float(h), up, vp, m,
+                               *(p for p, _ in ptrs), nseg, seg.ctypes.data, float(mu), float(uinf[0]),
+                               float(uinf[1]), float(rho), float(area), dxp, dyp, ctypes.addressof(res),
+                               self._stream_of(u, stream))
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del uk, vk, ptrs
+        out = [dict(fx=f.fx, fy=f.fy, drag=f.drag, cd=f.cd) for f in res[:nseg]]
+        return (out, dfx, dfy) if pointwise else out
 
     def surface_forces(self, p, nx, ny, ds, seg_start, u=(1.0, 0.0), rho=1.0, area=1.0, pointwise=False,
                        stream=None):

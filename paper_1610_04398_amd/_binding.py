@@ -37,7 +37,7 @@ UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
 EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
-            "pp_surface_forces", "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
+            "pp_surface_forces", "pp_pressure_source", "pp_viscous_forces", "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
             "pp_server_create", "pp_server_submit", "pp_server_wait", "pp_server_cancel", "pp_server_destroy",
             "pp_server_last_error", "pp_footprint_estimate")
 PP_ERR_TIMEOUT = -6
@@ -109,6 +109,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_direct_points.restype = i32
     lib.pp_surface_forces.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp, f64, f64, f64, f64, vp, vp, vp, vp]
     lib.pp_surface_forces.restype = i32
+    lib.pp_pressure_source.argtypes = [vp, i32, i32, f64, vp, vp, f64, f64, vp, vp, vp, vp, vp]
+    lib.pp_pressure_source.restype = i32
+    lib.pp_viscous_forces.argtypes = [vp, i32, i32, f64, f64, f64, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp, f64, f64,
+                                      f64, f64, f64, vp, vp, vp, vp]
+    lib.pp_viscous_forces.restype = i32
     lib.pp_get_stats.argtypes = [vp, ctypes.POINTER(pp_stats)]
     lib.pp_get_stats.restype = i32
     lib.pp_set_profiling.argtypes = [vp, i32]
@@ -182,6 +187,16 @@ def pp_surface_forces(ctx, m, p_ptr, nx_ptr, ny_ptr, ds_ptr, nseg, seg_ptr, ux, 
                       out_ptr, stream) -> int:
     return lib().pp_surface_forces(ctx, m, p_ptr, nx_ptr, ny_ptr, ds_ptr, nseg, seg_ptr, ux, uy, rho, area, dfx_ptr,
                                    dfy_ptr, out_ptr, stream)
+
+
+def pp_pressure_source(ctx, nx, ny, h, u_ptr, v_ptr, rho, lam, chi_ptr, us_ptr, vs_ptr, f_ptr, stream) -> int:
+    return lib().pp_pressure_source(ctx, nx, ny, h, u_ptr, v_ptr, rho, lam, chi_ptr, us_ptr, vs_ptr, f_ptr, stream)
+
+
+def pp_viscous_forces(ctx, nx, ny, x0, y0, h, u_ptr, v_ptr, m, lx_ptr, ly_ptr, nx_ptr, ny_ptr, ds_ptr, nseg, seg_ptr,
+                      mu, ux, uy, rho, area, dfx_ptr, dfy_ptr, out_ptr, stream) -> int:
+    return lib().pp_viscous_forces(ctx, nx, ny, x0, y0, h, u_ptr, v_ptr, m, lx_ptr, ly_ptr, nx_ptr, ny_ptr, ds_ptr,
+                                   nseg, seg_ptr, mu, ux, uy, rho, area, dfx_ptr, dfy_ptr, out_ptr, stream)
 
 
 def pp_get_stats(ctx) -> pp_stats:

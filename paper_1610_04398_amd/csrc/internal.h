@@ -199,4 +199,14 @@ void surface_forces(const double* p, const double* nx, const double* ny, const d
                     const int64_t* seg, double ux, double uy, double rho, double area, double* dfx, double* dfy,
                     pp_force* out, hipStream_t s);
 
+// ---- assembly.hip: source from the gridded velocity, viscous forces -------------------
+// f at every node of the nx x ny grid (eq. PoissonFinal); chi/us/vs null: no penalisation term.
+void pressure_source(const double* u, const double* v, const double* chi, const double* us, const double* vs, int nx,
+                     int ny, double h, double rho, double lam, double* f, int* flags, hipStream_t s);
+// Viscous forces per panel and per segment (eq. Fvisc, FviscNet, CdNu) from nearest-node gradients.
+void viscous_forces(const double* u, const double* v, int nx, int ny, double x0, double y0, double h, const double* lx,
+                    const double* ly, const double* pnx, const double* pny, const double* ds, int nseg,
+                    const int64_t* seg, double mu, double uxi, double uyi, double rho, double area, double* dfx,
+                    double* dfy, pp_force* out, hipStream_t s);
+
 }  // namespace pp

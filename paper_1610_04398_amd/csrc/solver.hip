@@ -44,6 +44,7 @@ enum BufId {
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
   B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
+  B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY,
   B_COUNT
 };
 
@@ -695,51 +696,147 @@ pp_status pp_direct_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0
   return guard(c, true, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
 }
 
-pp_status pp_surface_forces(pp_ctx* c, int64_t m, const double* p, const double* nx, const double* ny,
-                            const double* ds, int32_t nseg, const int64_t* seg_start, double ux, double uy, double rho,
-                            double area, double* dfx, double* dfy, pp_force* out, void* stream) {
+}  // extern "C"
+
+namespace {
+void validate_segments(int64_t m, int32_t nseg, const int64_t* seg_start, double ux, double uy, double rho,
+                       double area) {
+  if (m < 0 || nseg < 1 || !seg_start) throw PPError{PP_ERR_ARG, "bad sizes or null segment offsets"};
+  if (is_device_ptr(seg_start)) throw PPError{PP_ERR_ARG, "seg_start must be host memory"};
+  if (seg_start[0] != 0 || seg_start[nseg] != m) throw PPError{PP_ERR_ARG, "seg_start must run from 0 to m"};
+  for (int i = 0; i < nseg; ++i)
+    if (seg_start[i + 1] < seg_start[i]) throw PPError{PP_ERR_ARG, "seg_start decreases"};
+  const double speed = std::hypot(ux, uy);
+  if (!(speed > 0.0) || !std::isfinite(speed) || !(rho > 0.0) || !(area > 0.0) || !std::isfinite(rho) ||
+      !std::isfinite(area))
+    throw PPError{PP_ERR_ARG, "|U|, rho and area must be positive and finite"};
+}
+
+// Stages the per-panel outputs and the segment table, runs `launch`, copies results to host buffers.
+template <class Launch>
+void run_force_kernel(pp_ctx& c, int64_t m, int32_t nseg, const int64_t* seg_start, double* dfx, double* dfy,
+                      pp_force* out, hipStream_t s, Launch launch) {
+  int64_t* seg_d = ensure<int64_t>(c, B_FSEG, nseg + 1);
+  HIPCHK(hipMemcpyAsync(seg_d, seg_start, (size_t)(nseg + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  const bool dfx_dev = dfx && is_device_ptr(dfx), dfy_dev = dfy && is_device_ptr(dfy);
+  const bool out_dev = is_device_ptr(out);
+  double* dfx_d = dfx ? (dfx_dev ? dfx : ensure<double>(c, B_FDFX, m)) : nullptr;
+  double* dfy_d = dfy ? (dfy_dev ? dfy : ensure<double>(c, B_FDFY, m)) : nullptr;
+  pp_force* out_d = out_dev ? out : ensure<pp_force>(c, B_FOUT, nseg);
+  launch(seg_d, dfx_d, dfy_d, out_d);
+  HIPCHK(hipGetLastError());
+  if (dfx && !dfx_dev && m > 0) HIPCHK(hipMemcpyAsync(dfx, dfx_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (dfy && !dfy_dev && m > 0) HIPCHK(hipMemcpyAsync(dfy, dfy_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (!out_dev) HIPCHK(hipMemcpyAsync(out, out_d, (size_t)nseg * sizeof(pp_force), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+template <class Body>
+pp_status guarded(pp_ctx* c, Body body) {
   if (!c) return PP_ERR_ARG;
   if (c->dead) {
     c->err = "context is unusable after a device error";
     return PP_ERR_DEVICE;
   }
   try {
-    if (m < 0 || nseg < 1 || !seg_start || !out || (m > 0 && (!p || !nx || !ny || !ds)))
-      throw PPError{PP_ERR_ARG, "bad sizes or null pointers"};
-    if (is_device_ptr(seg_start)) throw PPError{PP_ERR_ARG, "seg_start must be host memory"};
-    if (seg_start[0] != 0 || seg_start[nseg] != m) throw PPError{PP_ERR_ARG, "seg_start must run from 0 to m"};
-    for (int i = 0; i < nseg; ++i)
-      if (seg_start[i + 1] < seg_start[i]) throw PPError{PP_ERR_ARG, "seg_start decreases"};
-    const double speed = std::hypot(ux, uy);
-    if (!(speed > 0.0) || !std::isfinite(speed) || !(rho > 0.0) || !(area > 0.0) || !std::isfinite(rho) ||
-        !std::isfinite(area))
-      throw PPError{PP_ERR_ARG, "|U|, rho and area must be positive and finite"};
-    HIPCHK(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
-    const double* p_d = stage_in(*c, B_FP, p, m, s);
-    const double* nx_d = stage_in(*c, B_FNX, nx, m, s);
-    const double* ny_d = stage_in(*c, B_FNY, ny, m, s);
-    const double* ds_d = stage_in(*c, B_FDS, ds, m, s);
-    int64_t* seg_d = ensure<int64_t>(*c, B_FSEG, nseg + 1);
-    HIPCHK(hipMemcpyAsync(seg_d, seg_start, (size_t)(nseg + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    const bool dfx_dev = dfx && is_device_ptr(dfx), dfy_dev = dfy && is_device_ptr(dfy);
-    const bool out_dev = is_device_ptr(out);
-    double* dfx_d = dfx ? (dfx_dev ? dfx : ensure<double>(*c, B_FDFX, m)) : nullptr;
-    double* dfy_d = dfy ? (dfy_dev ? dfy : ensure<double>(*c, B_FDFY, m)) : nullptr;
-    pp_force* out_d = out_dev ? out : ensure<pp_force>(*c, B_FOUT, nseg);
-    surface_forces(p_d, nx_d, ny_d, ds_d, nseg, seg_d, ux, uy, rho, area, dfx_d, dfy_d, out_d, s);
-    HIPCHK(hipGetLastError());
-    if (dfx && !dfx_dev && m > 0) HIPCHK(hipMemcpyAsync(dfx, dfx_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (dfy && !dfy_dev && m > 0) HIPCHK(hipMemcpyAsync(dfy, dfy_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (!out_dev) HIPCHK(hipMemcpyAsync(out, out_d, (size_t)nseg * sizeof(pp_force), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    body();
     c->err.clear();
     return PP_OK;
   } catch (const PPError& e) {
     c->err = e.msg;
     if (e.code == PP_ERR_DEVICE) c->dead = true;
     return e.code;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return PP_ERR_DEVICE;
   }
+}
+}  // namespace
+
+extern "C" {
+
+pp_status pp_pressure_source(pp_ctx* c, int32_t nx, int32_t ny, double h, const double* u, const double* v,
+                             double rho, double lambda, const double* chi, const double* us, const double* vs,
+                             double* f_out, void* stream) {
+  return guarded(c, [&] {
+    if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536 || (int64_t)nx * ny >= ((int64_t)1 << 31))
+      throw PPError{PP_ERR_ARG, "grid size out of range"};
+    if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(rho) || !std::isfinite(lambda))
+      throw PPError{PP_ERR_ARG, "h must be positive, rho and lambda finite"};
+    if (!u || !v || !f_out) throw PPError{PP_ERR_ARG, "null velocity or output"};
+    const bool pen = chi || us || vs;
+    if (pen && !(chi && us && vs)) throw PPError{PP_ERR_ARG, "chi, us and vs must be given together"};
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)nx * ny;
+    int* misc = ensure<int>(*c, B_MISC, kMiscInts);
+    fill_i32(misc, 0, kMiscInts, s);
+    const double* u_d = stage_in(*c, B_AU, u, n, s);
+    const double* v_d = stage_in(*c, B_AV, v, n, s);
+    const double* chi_d = pen ? stage_in(*c, B_ACHI, chi, n, s) : nullptr;
+    const double* us_d = pen ? stage_in(*c, B_AUS, us, n, s) : nullptr;
+    const double* vs_d = pen ? stage_in(*c, B_AVS, vs, n, s) : nullptr;
+    const bool out_dev = is_device_ptr(f_out);
+    double* f_d = out_dev ? f_out : ensure<double>(*c, B_AF, n);
+    pressure_source(u_d, v_d, chi_d, us_d, vs_d, nx, ny, h, rho, lambda, f_d, misc + M_FLAGS, s);
+    HIPCHK(hipGetLastError());
+    readback(*c, misc, 0, 1, s);
+    if (c->pinned[M_FLAGS]) throw PPError{PP_ERR_ARG, "non-finite velocity data (the source is not finite)"};
+    if (!out_dev) {
+      HIPCHK(hipMemcpyAsync(f_out, f_d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+  });
+}
+
+pp_status pp_viscous_forces(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* u,
+                            const double* v, int64_t m, const double* lx, const double* ly, const double* pnx,
+                            const double* pny, const double* ds, int32_t nseg, const int64_t* seg_start, double mu,
+                            double ux, double uy, double rho, double area, double* dfx, double* dfy, pp_force* out,
+                            void* stream) {
+  return guarded(c, [&] {
+    if (nx < 1 || ny < 1 || nx > 65536 || ny > 65536 || (int64_t)nx * ny >= ((int64_t)1 << 31))
+      throw PPError{PP_ERR_ARG, "grid size out of range"};
+    if (!(h > 0.0) || !std::isfinite(h) || !std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(mu))
+      throw PPError{PP_ERR_ARG, "h must be positive, x0, y0 and mu finite"};
+    if (!u || !v || !out || (m > 0 && (!lx || !ly || !pnx || !pny || !ds)))
+      throw PPError{PP_ERR_ARG, "null pointer"};
+    validate_segments(m, nseg, seg_start, ux, uy, rho, area);
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)nx * ny;
+    const double* u_d = stage_in(*c, B_AU, u, n, s);
+    const double* v_d = stage_in(*c, B_AV, v, n, s);
+    const double* lx_d = stage_in(*c, B_VLX, lx, m, s);
+    const double* ly_d = stage_in(*c, B_VLY, ly, m, s);
+    const double* nx_d = stage_in(*c, B_FNX, pnx, m, s);
+    const double* ny_d = stage_in(*c, B_FNY, pny, m, s);
+    const double* ds_d = stage_in(*c, B_FDS, ds, m, s);
+    run_force_kernel(*c, m, nseg, seg_start, dfx, dfy, out, s,
+                     [&](const int64_t* seg_d, double* dfx_d, double* dfy_d, pp_force* out_d) {
+                       viscous_forces(u_d, v_d, nx, ny, x0, y0, h, lx_d, ly_d, nx_d, ny_d, ds_d, nseg, seg_d, mu, ux,
+                                      uy, rho, area, dfx_d, dfy_d, out_d, s);
+                     });
+  });
+}
+
+pp_status pp_surface_forces(pp_ctx* c, int64_t m, const double* p, const double* nx, const double* ny,
+                            const double* ds, int32_t nseg, const int64_t* seg_start, double ux, double uy, double rho,
+                            double area, double* dfx, double* dfy, pp_force* out, void* stream) {
+  return guarded(c, [&] {
+    if (!out || (m > 0 && (!p || !nx || !ny || !ds))) throw PPError{PP_ERR_ARG, "null pointer"};
+    validate_segments(m, nseg, seg_start, ux, uy, rho, area);
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const double* p_d = stage_in(*c, B_FP, p, m, s);
+    const double* nx_d = stage_in(*c, B_FNX, nx, m, s);
+    const double* ny_d = stage_in(*c, B_FNY, ny, m, s);
+    const double* ds_d = stage_in(*c, B_FDS, ds, m, s);
+    run_force_kernel(*c, m, nseg, seg_start, dfx, dfy, out, s,
+                     [&](const int64_t* seg_d, double* dfx_d, double* dfy_d, pp_force* out_d) {
+                       surface_forces(p_d, nx_d, ny_d, ds_d, nseg, seg_d, ux, uy, rho, area, dfx_d, dfy_d, out_d, s);
+                     });
+  });
 }
 
 pp_status pp_set_profiling(pp_ctx* c, int32_t on) {
