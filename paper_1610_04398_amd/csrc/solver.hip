@@ -84,6 +84,19 @@ struct pp_ctx {
   int dense_levels = 8;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
   bool profiling = false;
   hipEvent_t ev[13] = {};
+  // launch replay: each of the two segments of a solve (up to the tree read-back, and
+  // from the lists to the end) is captured into a HIP graph on the second call with
+  // the same inputs and replayed while they stay the same (PP_GRAPHS=0 disables)
+  bool graphs = true;
+  uint64_t gen = 0;  // bumped by every device (re)allocation; part of every graph key
+  // work of calls on the null stream runs on this blocking stream (ordered with the
+  // null stream like the null stream itself), which can be captured
+  hipStream_t own_stream = nullptr;
+  struct Segment {
+    std::vector<uint64_t> key;
+    int seen = 0;
+    hipGraphExec_t exec = nullptr;
+  } seg[2];
   uint64_t budget = 0;
   size_t held = 0;
   DevBuf bufs[B_COUNT];
@@ -117,6 +130,7 @@ T* ensure(pp_ctx& c, int id, int64_t count) {
     throw PPError{PP_ERR_NOMEM, "device-memory budget exceeded (" + std::to_string(others + want) + " > " +
                                     std::to_string(c.budget) + " bytes)"};
   release(c, id);
+  c.gen += 1;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, want);
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
@@ -149,9 +163,80 @@ const T* stage_in(pp_ctx& c, int id, const T* src, int64_t n, hipStream_t s) {
   return d;
 }
 
-void readback(pp_ctx& c, const int* dev, int first, int count, hipStream_t s) {
+void readback_enqueue(pp_ctx& c, const int* dev, int first, int count, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(c.pinned + first, dev + first, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+void readback(pp_ctx& c, const int* dev, int first, int count, hipStream_t s) {
+  readback_enqueue(c, dev, first, count, s);
   HIPCHK(hipStreamSynchronize(s));
+}
+
+void drop_graph(pp_ctx::Segment& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+}
+
+uint64_t bits(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, sizeof(u));
+  return u;
+}
+
+uint64_t bits(const void* p) { return (uint64_t)(uintptr_t)p; }
+
+// Enqueues one segment of a solve on s: `enqueue` only enqueues device work (every
+// buffer it touches was sized before).  Eager the first time a key is seen; on the
+// second call with the same key the work is captured into a graph, which is then
+// launched, and later calls with that key only launch the graph.  Any failure to
+// capture or instantiate falls back to eager launches for the rest of the context.
+template <class F>
+void run_segment(pp_ctx& c, int which, bool allowed, std::vector<uint64_t> key, hipStream_t s, F&& enqueue) {
+  pp_ctx::Segment& g = c.seg[which];
+  if (!allowed || !c.graphs || s == nullptr) {
+    enqueue();
+    return;
+  }
+  key.push_back(c.gen);
+  if (g.key != key) {
+    drop_graph(g);
+    g.key = key;
+    g.seen = 0;
+  }
+  if (g.exec) {
+    HIPCHK(hipGraphLaunch(g.exec, s));
+    return;
+  }
+  if (g.seen++ == 0) {
+    enqueue();
+    return;
+  }
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    c.graphs = false;
+    enqueue();
+    return;
+  }
+  bool ok = true;
+  try {
+    enqueue();
+  } catch (const PPError&) {
+    ok = false;
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &graph);
+  if (!ok || e != hipSuccess || !graph || c.gen != key.back() ||
+      hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    // nothing captured ran: disable replay and do the work eagerly
+    (void)hipGetLastError();
+    if (graph) (void)hipGraphDestroy(graph);
+    drop_graph(g);
+    c.graphs = false;
+    enqueue();
+    return;
+  }
+  (void)hipGraphDestroy(graph);
+  HIPCHK(hipGraphLaunch(g.exec, s));
 }
 
 int root_exponent(int nx, int ny) {
@@ -218,6 +303,9 @@ void validate_points(int64_t n, const double* sx, const double* sy, const double
 
 // One solve.  Two host round trips: after the tree (its level starts and the
 // cell-list counts size the later launches) and at the end (flags, statistics).
+// The launches between them form two segments, each of which is replayed from a
+// captured HIP graph when a call repeats the previous one's shape, device
+// pointers and (for the second) tree; every buffer is sized before a segment.
 // `exact_lists` selects the two-pass interaction lists (count, scan, emit);
 // otherwise the lists are written in one pass into a fixed capacity per cell,
 // and a list that does not fit makes the solve report kFlagListOverflow (the
@@ -226,6 +314,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                     const double* ty, const pp_params& prm, double* p_out, hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
   HIPCHK(hipSetDevice(c.device));
+  if (s == nullptr) {
+    if (!c.own_stream) HIPCHK(hipStreamCreate(&c.own_stream));  // blocking, default priority
+    s = c.own_stream;
+  }
   c.last.valid = false;
   const int32_t nx = src.grid ? src.nx : 0, ny = src.grid ? src.ny : 0;
   const int64_t ngrid = src.grid ? (int64_t)nx * ny : 0;
@@ -239,7 +331,6 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto mark = [&](int i) {
     if (c.profiling) HIPCHK(hipEventRecord(c.ev[i], s));
   };
-  mark(PP_PHASE_INGEST);
   const double* f_d = src.grid ? stage_in(c, B_F, src.f, ngrid, s) : nullptr;
   const double* tx_d = stage_in(c, B_TX, tx, m, s);
   const double* ty_d = stage_in(c, B_TY, ty, m, s);
@@ -248,7 +339,6 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   int* misc = ensure<int>(c, B_MISC, kMiscInts);
   unsigned long long* pairs = (unsigned long long*)(misc + M_PAIRS);  // 8-byte aligned slot
-  fill_i32(misc, 0, kMiscInts, s);
 
   // root square: anchor (x0, y0), finest cell side `unit`, finest level D
   int D = 0;
@@ -260,6 +350,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     y0 = src.y0;
     unit = src.h;
   } else {
+    fill_i32(misc, 0, kMiscInts, s);
     psx = stage_in(c, B_PSX, src.sx, src.n, s);
     psy = stage_in(c, B_PSY, src.sy, src.n, s);
     pw = stage_in(c, B_PW, src.w, src.n, s);
@@ -301,35 +392,19 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   uint32_t* sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
   double* sw = ensure<double>(c, B_SW, nmax);
   double *pxs = nullptr, *pys = nullptr;
-  if (src.grid) {
-    // ---- ingest: sources in Morton order (no sort needed for a grid) ----
-    int* tile = ensure<int>(c, B_TILE, ntiles);
-    ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
-    scan_exclusive(tile, tile, ntiles, ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ntiles)), misc + M_NSRC, s);
-    ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, skey, sij, sw, s);
-  } else if (src.n > 0) {
-    // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
-    int* sperm = (int*)sij;
-    points_keys(psx, psy, pw, src.n, x0, y0, unit, D, skey, sperm, s);
-    // sized for this sort and the target sort below, so neither reallocates it
-    int* sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.n, m)));
-    radix_sort_pairs(skey, sperm, ensure<uint32_t>(c, B_SKEY2, src.n), ensure<int>(c, B_SPERM2, src.n), src.n, 32,
-                     sort_tmp, s);
+  // every buffer of the first segment, sized before anything is enqueued
+  int* tile = src.grid ? ensure<int>(c, B_TILE, ntiles) : nullptr;
+  int* sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.grid ? 0 : src.n, m)));
+  uint32_t* skey2 = src.grid ? nullptr : ensure<uint32_t>(c, B_SKEY2, src.n);
+  int* sperm2 = src.grid ? nullptr : ensure<int>(c, B_SPERM2, src.n);
+  if (!src.grid) {
     pxs = ensure<double>(c, B_PXS, src.n);
     pys = ensure<double>(c, B_PYS, src.n);
-    points_gather(sperm, misc + M_NSRC, src.n, psx, psy, pw, pxs, pys, sw, s);
   }
-
-  // ---- targets: Morton keys and a stable radix sort ----
-  mark(PP_PHASE_SORT);
   uint32_t* tkey = ensure<uint32_t>(c, B_TKEY, m);
   int* tperm = ensure<int>(c, B_TPERM, m);
-  target_keys(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, misc + M_FLAGS, s);
-  radix_sort_pairs(tkey, tperm, ensure<uint32_t>(c, B_TKEY2, m), ensure<int>(c, B_TPERM2, m), m, 2 * k,
-                   ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(m)), s);
-
-  // ---- tree, top down: one launch group per level, no host round trip ----
-  mark(PP_PHASE_TREE);
+  uint32_t* tkey2 = ensure<uint32_t>(c, B_TKEY2, m);
+  int* tperm2 = ensure<int>(c, B_TPERM2, m);
   TreeArrays ta{ensure<int>(c, B_LVL, cap),   ensure<int>(c, B_IX, cap),     ensure<int>(c, B_IY, cap),
                 ensure<int>(c, B_SB, cap),    ensure<int>(c, B_SE, cap),     ensure<int>(c, B_TB, cap),
                 ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
@@ -337,34 +412,65 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   int* ls_d = misc + M_LS;
   // levels 0..Ld from the dense prefix table, the rest one level at a time
   const int Ld = std::min(D, c.dense_levels);
-  {
-    const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
-    const int64_t F = tree_dense_cells(Ld);
-    tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, tkey, (int)m, ensure<int>(c, B_DSS, np),
-                   ensure<int>(c, B_DTS, np), ensure<int>(c, B_DFLAG, F), ensure<int>(c, B_DOFF, F),
-                   ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(F)), misc + M_TOT, misc + M_FLAGS, s);
-  }
-  {
-    const int64_t wmax = std::min<int64_t>(cap, per_level);
-    int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
-    int* sp = ensure<int>(c, B_SPLIT, 6 * wmax);
-    int* ex = ensure<int>(c, B_CNT, 4 * wmax);
-    int* off = ensure<int>(c, B_OFF, 4 * wmax);
-    int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(4 * wmax));
+  const int64_t dense_np = ((int64_t)1 << (2 * Ld)) + 1;
+  const int64_t dense_F = tree_dense_cells(Ld);
+  int* dss = ensure<int>(c, B_DSS, dense_np);
+  int* dts = ensure<int>(c, B_DTS, dense_np);
+  int* dflag = ensure<int>(c, B_DFLAG, dense_F);
+  int* doff = ensure<int>(c, B_DOFF, dense_F);
+  const int64_t wmax = std::min<int64_t>(cap, per_level);
+  int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
+  int* sp = ensure<int>(c, B_SPLIT, 6 * wmax);
+  int* ex = ensure<int>(c, B_CNT, 4 * wmax);
+  int* off = ensure<int>(c, B_OFF, 4 * wmax);
+  int* scan = ensure<int>(c, B_SCAN, 1);  // sized above for every scan of the solve
+  int* sleaves = ensure<int>(c, B_SLEAF, cap);
+  int* tleaves = ensure<int>(c, B_TLEAF, cap);
+  int* tcells = ensure<int>(c, B_TCELL, cap);
+  int* flag3 = ensure<int>(c, B_FLAG, 3 * cap);
+  int* off3 = ensure<int>(c, B_FOFF, 3 * cap);
+
+  // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
+  // (graph replay only for device-resident grid input: host input is staged by copies)
+  const bool replayable = src.grid && !exact_lists && !direct && f_d == src.f && tx_d == tx && ty_d == ty &&
+                          out_on_device;
+  const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
+                                      (uint64_t)lm, (uint64_t)c.dense_levels, (uint64_t)c.profiling, bits(f_d),
+                                      bits(tx_d), bits(ty_d)};
+  run_segment(c, 0, replayable, key1, s, [&] {
+    mark(PP_PHASE_INGEST);
+    if (src.grid) fill_i32(misc, 0, kMiscInts, s);  // scattered input: cleared before its bounding box
+    if (src.grid) {
+      // ---- ingest: sources in Morton order (no sort needed for a grid) ----
+      ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
+      scan_exclusive(tile, tile, ntiles, scan, misc + M_NSRC, s);
+      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, skey, sij, sw, s);
+    } else if (src.n > 0) {
+      // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
+      int* sperm = (int*)sij;
+      points_keys(psx, psy, pw, src.n, x0, y0, unit, D, skey, sperm, s);
+      radix_sort_pairs(skey, sperm, skey2, sperm2, src.n, 32, sort_tmp, s);
+      points_gather(sperm, misc + M_NSRC, src.n, psx, psy, pw, pxs, pys, sw, s);
+    }
+    // ---- targets: Morton keys and a stable radix sort ----
+    mark(PP_PHASE_SORT);
+    target_keys(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, misc + M_FLAGS, s);
+    radix_sort_pairs(tkey, tperm, tkey2, tperm2, m, 2 * k, sort_tmp, s);
+    // ---- tree: dense top levels, then one launch group per level, no host round trip ----
+    mark(PP_PHASE_TREE);
+    tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, tkey, (int)m, dss, dts, dflag, doff, scan,
+                   misc + M_TOT, misc + M_FLAGS, s);
     for (int l = Ld; l < D; ++l) {
       const int64_t lmax = std::min<int64_t>(wmax, (int64_t)1 << std::min(2 * l, 40));
       tree_level(ta, ls_d, l, D, lm, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4, misc + M_TOT,
                  misc + M_FLAGS, s);
     }
-  }
-  // cell lists over the whole tree (its size is the last level start, on the device)
-  int* sleaves = ensure<int>(c, B_SLEAF, cap);
-  int* tleaves = ensure<int>(c, B_TLEAF, cap);
-  int* tcells = ensure<int>(c, B_TCELL, cap);
-  classify_cells(ta, ls_d + D + 1, (int)cap, ensure<int>(c, B_FLAG, 3 * cap), ensure<int>(c, B_FOFF, 3 * cap),
-                 ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(3 * cap)), misc + M_TOT, misc + M_N4, sleaves,
-                 tleaves, tcells, misc + M_NSL, s);
-  readback(c, misc, 0, M_LS + D + 2, s);
+    // cell lists over the whole tree (its size is the last level start, on the device)
+    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, off3, scan, misc + M_TOT, misc + M_N4, sleaves, tleaves, tcells,
+                   misc + M_NSL, s);
+    readback_enqueue(c, misc, 0, M_LS + D + 2, s);
+  });
+  HIPCHK(hipStreamSynchronize(s));
   check_flags(c.pinned[M_FLAGS]);
   const int64_t N = c.pinned[M_NSRC];
   const int* ls_h = c.pinned + M_LS;
@@ -378,8 +484,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
-  // ---- interaction lists ----
-  mark(PP_PHASE_LISTS);
+  // ---- every buffer of the second segment, sized before anything is enqueued ----
   int* cm2l = ensure<int>(c, B_CM2L, ncells);
   int* om2l = ensure<int>(c, B_OM2L, ncells);
   int* cp2p = ensure<int>(c, B_CP2P, ncells);
@@ -392,107 +497,34 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const bool treecode = prm.method == PP_METHOD_TREECODE;
   const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
   const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
-  auto list_pass = [&](const int4* rec, int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp) {
-    if (treecode)
-      lists_treecode_pass(tv, rec, tleaves, ntl, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
-                          s);
-    else
-      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS, s);
-  };
-  if (!direct) {
-    int4* rec = ensure<int4>(c, B_REC, ncells);
-    if (exact_lists) {
-      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, s);
-      list_pass(rec, 0, nullptr, nullptr, nullptr, nullptr, 0, 0);
-      int* scan = ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(ncells));
-      scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
-      scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
-      readback(c, misc, 0, 16, s);
-      check_flags(c.pinned[M_FLAGS]);
-      n_m2l = c.pinned[M_NM2L];
-      n_p2pl = c.pinned[M_NP2P];
-      m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
-      p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
-      list_pass(rec, 1, om2l, op2p, m2l_src, p2p_src, 0, 0);
-    } else {
-      m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
-      p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
-      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, s);
-      list_pass(rec, 2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near);
-    }
+  int4* rec = direct ? nullptr : ensure<int4>(c, B_REC, ncells);
+  if (!direct && !exact_lists) {
+    m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
+    p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
   }
-
-  // ---- per-leaf packing ----
-  mark(PP_PHASE_PACK);
   float4* src4 = ensure<float4>(c, B_SRC4, N);
   double* leaf_w = ensure<double>(c, B_LEAFW, ncells);
   float2* rel32 = ensure<float2>(c, B_REL32, m);
   double2* rel64 = ensure<double2>(c, B_REL64, m);
   int* tgtleaf = ensure<int>(c, B_TGTLEAF, m);
-  int* selfi = nullptr;
-  double* selfd = nullptr;
-  double* selfw = nullptr;
-  double2* s64 = nullptr;
-  if (src.grid) {
-    leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
-    selfi = ensure<int>(c, B_SELFI, m);
-    selfd = ensure<double>(c, B_SELFD, m);
-    leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, rel32,
-                      rel64, tgtleaf, selfi, selfd, s);
-  } else {
-    s64 = ensure<double2>(c, B_S64, N);
-    selfw = ensure<double>(c, B_SELFW, m);
-    leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, s);
-    leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf, selfw,
-                     s);
-  }
-
-  // ---- expansions: upward and downward passes ----
-  double* far = nullptr;
-  if (!direct) {
-    double2* mp = ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
-    double2* loc = treecode ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
-    double2* own = treecode ? nullptr : ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
-    far = ensure<double>(c, B_FAR, m);
-    mark(PP_PHASE_P2M);
-    p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
-    mark(PP_PHASE_M2M);
-    // the recursion from the finest level up, several levels per launch
-    const int ml = m2m_max_levels();
-    for (int top = depth - 1; top >= 0; top -= ml) {
-      const int L = std::max(top - (ml - 1), 0);
-      m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
-    }
-    mark(PP_PHASE_M2L);
-    if (treecode) {
-      // multipoles evaluated at the targets; no local expansions
-      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far, misc + M_FLAGS, s);
-      mark(PP_PHASE_L2L);
-      mark(PP_PHASE_L2P);
-    } else {
-      m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
-      mark(PP_PHASE_L2L);
-      downward(tv, tcells, ntc, p, own, loc, s);
-      mark(PP_PHASE_L2P);
-      l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
-    }
-  } else {
-    for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
-  }
-
-  // ---- near field ----
+  int* selfi = src.grid ? ensure<int>(c, B_SELFI, m) : nullptr;
+  double* selfd = src.grid ? ensure<double>(c, B_SELFD, m) : nullptr;
+  double* selfw = src.grid ? nullptr : ensure<double>(c, B_SELFW, m);
+  double2* s64 = src.grid ? nullptr : ensure<double2>(c, B_S64, N);
+  double2* mp = direct ? nullptr : ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
+  double2* loc = (direct || treecode) ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
+  double2* own = (direct || treecode) ? nullptr : ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
+  double* far = direct ? nullptr : ensure<double>(c, B_FAR, m);
   const int nparts = c.p2p_parts;
   double* near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
   double* wnear = ensure<double>(c, B_WNEAR, (int64_t)nparts * ncells);
   long long* pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
-  mark(PP_PHASE_P2P);
   P2PArgs pa{};
   pa.t = tv;
   pa.tleaves = tleaves;
   pa.ntleaves = ntl;
   pa.list_off = direct ? nullptr : op2p;
   pa.list_cnt = direct ? nullptr : cp2p;
-  pa.list_src = direct ? nullptr : p2p_src;
   pa.sleaves = sleaves;
   pa.nsleaves = nsl;
   pa.src4 = src4;
@@ -508,17 +540,101 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   pa.pairs = pairs;
   pa.near_sum = near;
   pa.leaf_wnear = wnear;
-  p2p(pa, mixed ? 0 : 1, s);
-
-  // ---- finalize ----
-  mark(PP_PHASE_FINALIZE);
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
-  p2p_totals(pa, list_totals ? cm2l : nullptr, list_totals ? cp2p : nullptr, ncells, misc + M_NM2L, misc + M_NP2P, s);
-  finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, selfw, f_d, unit, prm.self_mode,
-           misc + M_FLAGS, out_d, s);
-  mark(12);
-  readback(c, misc, 0, M_PAIRS + 2, s);
+
+  auto list_pass = [&](int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp) {
+    if (treecode)
+      lists_treecode_pass(tv, rec, tleaves, ntl, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
+                          s);
+    else
+      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS, s);
+  };
+  std::vector<uint64_t> key2 = key1;
+  for (uint64_t v : {(uint64_t)N, (uint64_t)ncells, (uint64_t)nsl, (uint64_t)ntl, (uint64_t)ntc, (uint64_t)depth,
+                     (uint64_t)p, (uint64_t)num, (uint64_t)den, (uint64_t)prm.precision, (uint64_t)prm.self_mode,
+                     (uint64_t)prm.method, (uint64_t)cap_far, (uint64_t)cap_near, (uint64_t)nparts, bits(out_d)})
+    key2.push_back(v);
+  for (int v : lstart) key2.push_back((uint64_t)v);
+
+  // ---- segment 2: lists, expansions, near field, finalize; ends with the read-back ----
+  run_segment(c, 1, replayable, key2, s, [&] {
+    // ---- interaction lists ----
+    mark(PP_PHASE_LISTS);
+    if (!direct) {
+      if (exact_lists) {
+        cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, s);
+        list_pass(0, nullptr, nullptr, nullptr, nullptr, 0, 0);
+        scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
+        scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
+        readback(c, misc, 0, 16, s);
+        check_flags(c.pinned[M_FLAGS]);
+        n_m2l = c.pinned[M_NM2L];
+        n_p2pl = c.pinned[M_NP2P];
+        m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
+        p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
+        list_pass(1, om2l, op2p, m2l_src, p2p_src, 0, 0);
+      } else {
+        cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, s);
+        list_pass(2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near);
+      }
+    }
+    pa.list_src = direct ? nullptr : p2p_src;
+
+    // ---- per-leaf packing ----
+    mark(PP_PHASE_PACK);
+    if (src.grid) {
+      leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
+      leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, rel32,
+                        rel64, tgtleaf, selfi, selfd, s);
+    } else {
+      leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, s);
+      leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf,
+                       selfw, s);
+    }
+
+    // ---- expansions: upward and downward passes ----
+    if (!direct) {
+      mark(PP_PHASE_P2M);
+      p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
+      mark(PP_PHASE_M2M);
+      // the recursion from the finest level up, several levels per launch
+      const int ml = m2m_max_levels();
+      for (int top = depth - 1; top >= 0; top -= ml) {
+        const int L = std::max(top - (ml - 1), 0);
+        m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
+      }
+      mark(PP_PHASE_M2L);
+      if (treecode) {
+        // multipoles evaluated at the targets; no local expansions
+        m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far, misc + M_FLAGS, s);
+        mark(PP_PHASE_L2L);
+        mark(PP_PHASE_L2P);
+      } else {
+        m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
+        mark(PP_PHASE_L2L);
+        downward(tv, tcells, ntc, p, own, loc, s);
+        mark(PP_PHASE_L2P);
+        l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+      }
+    } else {
+      for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
+    }
+
+    // ---- near field ----
+    mark(PP_PHASE_P2P);
+    p2p(pa, mixed ? 0 : 1, s);
+
+    // ---- finalize ----
+    mark(PP_PHASE_FINALIZE);
+    p2p_totals(pa, list_totals ? cm2l : nullptr, list_totals ? cp2p : nullptr, ncells, misc + M_NM2L, misc + M_NP2P,
+               s);
+    finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, selfw, f_d, unit, prm.self_mode,
+             misc + M_FLAGS, out_d, s);
+    mark(12);
+    readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
+  });
+  HIPCHK(hipStreamSynchronize(s));
   const int flags = c.pinned[M_FLAGS];
   if (flags & kFlagListOverflow) return PP_ERR_LIMIT;  // nothing written; repeat with exact lists
   check_flags(flags);
@@ -645,6 +761,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
+  if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities
     int a = 0, b = 0, x = 0, y = 0;
     const int got = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &x, &y);
@@ -669,6 +786,8 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
 void pp_destroy(pp_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  for (auto& g : c->seg) drop_graph(g);
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   for (int i = 0; i < B_COUNT; ++i) release(*c, i);
   for (int i = 0; i < 13; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);

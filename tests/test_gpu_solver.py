@@ -315,3 +315,41 @@ def test_list_modes_agree_bitwise(solver, monkeypatch):
         for k in env:
             monkeypatch.delenv(k)
         assert np.array_equal(got, ref) and np.array_equal(again, ref), env
+
+
+def test_graph_replay_matches_eager(monkeypatch):
+    """Repeated solves on device inputs replay captured graphs (same shape and pointers; the second segment
+    also needs the same tree).  Every call, with eager device work and synchronisations in between and with
+    the source changed in place (same and different zero pattern), equals a context without replay bit for
+    bit."""
+    import torch
+    import paper_1610_04398_amd as pp
+    n = 128
+    g = G.GridSpec(n, n, 1.0 / n)
+    base = G.vortex_source(g, 21, 16)
+    rng = np.random.Generator(np.random.PCG64(22))
+    tx = rng.uniform(0, 1, 3000)
+    ty = rng.uniform(0, 1, 3000)
+    fd, txd, tyd = to_dev(base, tx, ty)
+    out = torch.empty(tx.size, dtype=torch.float64, device="cuda")
+    monkeypatch.setenv("PP_GRAPHS", "0")
+    eager = pp.Solver(0)
+    monkeypatch.delenv("PP_GRAPHS")
+    fast = pp.Solver(0)
+    kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed")
+    try:
+        for it in range(7):
+            if it == 3:
+                fd.mul_(1.5)                      # same zero pattern: same tree
+            if it == 5:
+                fd[: n // 2].zero_()              # different sources: a different tree
+            scratch = torch.randn(1 << 16, device="cuda").sum()  # eager device work between replays
+            torch.cuda.synchronize()
+            got = to_host(fast.solve_grid(fd, g.h, txd, tyd, out=out, **kw)).copy()
+            ref = to_host(eager.solve_grid(fd, g.h, txd, tyd, **kw))
+            assert np.array_equal(got, ref), it
+            assert fast.stats()["n_p2p_pairs"] == eager.stats()["n_p2p_pairs"]
+            del scratch
+    finally:
+        fast.close()
+        eager.close()
