@@ -279,8 +279,9 @@ class Solver:
         res = [dict(fx=f.fx, fy=f.fy, drag=f.drag, cd=f.cd) for f in out[:nseg]]
         return (res, dfx, dfy) if pointwise else res
 
-    def set_profiling(self, on: bool = True) -> None:
-        st = pp_set_profiling(self._ctx, on)
+    def set_profiling(self, on=True) -> None:
+        """True/1: events between all phases; 2: events around the near-field launch only; False/0: off."""
+        st = pp_set_profiling(self._ctx, int(on))
         if st != B.PP_OK:
             raise PPError(st, pp_last_error(self._ctx))
 

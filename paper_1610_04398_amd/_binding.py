@@ -207,8 +207,8 @@ def pp_get_stats(ctx) -> pp_stats:
     return s
 
 
-def pp_set_profiling(ctx, on: bool) -> int:
-    return lib().pp_set_profiling(ctx, 1 if on else 0)
+def pp_set_profiling(ctx, on: int) -> int:
+    return lib().pp_set_profiling(ctx, int(on))
 
 
 def pp_debug_copy(ctx, what: int, dst_ptr, capacity: int) -> tuple[int, int]:

@@ -82,7 +82,7 @@ struct pp_ctx {
   int cap_tp2p = 96;
   bool exact_lists = false;  // PP_EXACT_LISTS=1 forces the two-pass lists
   int dense_levels = 8;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
-  bool profiling = false;
+  int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
   // from the lists to the end) is captured into a HIP graph on the second call with
@@ -328,8 +328,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const bool mixed = prm.precision == PP_MIXED;
   const int lm = prm.leaf_max;
 
+  // profiling 1: events between all phases (no graph replay); 2: events around the
+  // near-field launch only, which then runs outside the replayed segments
   auto mark = [&](int i) {
-    if (c.profiling) HIPCHK(hipEventRecord(c.ev[i], s));
+    if (c.profiling == 1) HIPCHK(hipEventRecord(c.ev[i], s));
   };
   const double* f_d = src.grid ? stage_in(c, B_F, src.f, ngrid, s) : nullptr;
   const double* tx_d = stage_in(c, B_TX, tx, m, s);
@@ -433,7 +435,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
   // (graph replay only for device-resident grid input: host input is staged by copies)
   const bool replayable = src.grid && !exact_lists && !direct && f_d == src.f && tx_d == tx && ty_d == ty &&
-                          out_on_device;
+                          out_on_device && c.profiling != 1;
   const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
                                       (uint64_t)lm, (uint64_t)c.dense_levels, (uint64_t)c.profiling, bits(f_d),
                                       bits(tx_d), bits(ty_d)};
@@ -540,6 +542,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   pa.pairs = pairs;
   pa.near_sum = near;
   pa.leaf_wnear = wnear;
+  pa.list_src = direct ? nullptr : p2p_src;  // set again below once exact lists are allocated
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
 
@@ -558,7 +561,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   for (int v : lstart) key2.push_back((uint64_t)v);
 
   // ---- segment 2: lists, expansions, near field, finalize; ends with the read-back ----
-  run_segment(c, 1, replayable, key2, s, [&] {
+  auto seg2_expansions = [&] {
     // ---- interaction lists ----
     mark(PP_PHASE_LISTS);
     if (!direct) {
@@ -621,10 +624,14 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
     }
 
+  };
+  auto seg2_near = [&] {
     // ---- near field ----
     mark(PP_PHASE_P2P);
     p2p(pa, mixed ? 0 : 1, s);
 
+  };
+  auto seg2_finalize = [&] {
     // ---- finalize ----
     mark(PP_PHASE_FINALIZE);
     p2p_totals(pa, list_totals ? cm2l : nullptr, list_totals ? cp2p : nullptr, ncells, misc + M_NM2L, misc + M_NP2P,
@@ -633,19 +640,39 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
              misc + M_FLAGS, out_d, s);
     mark(12);
     readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
-  });
+  };
+  if (c.profiling == 2) {
+    // the near field between two replayed segments, bracketed by events on this stream
+    std::vector<uint64_t> ka = key2, kb = key2;
+    ka.push_back(1);
+    kb.push_back(2);
+    run_segment(c, 1, replayable, ka, s, seg2_expansions);
+    HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], s));
+    p2p(pa, mixed ? 0 : 1, s);
+    HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], s));
+    run_segment(c, 2, replayable, kb, s, seg2_finalize);
+  } else {
+    run_segment(c, 1, replayable, key2, s, [&] {
+      seg2_expansions();
+      seg2_near();
+      seg2_finalize();
+    });
+  }
   HIPCHK(hipStreamSynchronize(s));
   const int flags = c.pinned[M_FLAGS];
   if (flags & kFlagListOverflow) return PP_ERR_LIMIT;  // nothing written; repeat with exact lists
   check_flags(flags);
-  if (c.profiling) {
+  for (int i = 0; i < 12; ++i) c.stats.ms_phase[i] = 0.0;
+  if (c.profiling == 1) {
     for (int i = 0; i < 12; ++i) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, c.ev[i], c.ev[i + 1]));
       c.stats.ms_phase[i] = ms;
     }
-  } else {
-    for (int i = 0; i < 12; ++i) c.stats.ms_phase[i] = 0.0;
+  } else if (c.profiling == 2) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c.ev[PP_PHASE_P2P], c.ev[PP_PHASE_FINALIZE]));
+    c.stats.ms_phase[PP_PHASE_P2P] = ms;
   }
   if (!out_on_device && m > 0) {
     HIPCHK(hipMemcpyAsync(p_out, out_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -959,14 +986,14 @@ pp_status pp_surface_forces(pp_ctx* c, int64_t m, const double* p, const double*
 }
 
 pp_status pp_set_profiling(pp_ctx* c, int32_t on) {
-  if (!c) return PP_ERR_ARG;
+  if (!c || on < 0 || on > 2) return PP_ERR_ARG;
   if (on && !c->profiling) {
     if (hipSetDevice(c->device) != hipSuccess) return PP_ERR_DEVICE;
     for (int i = 0; i < 13; ++i) {
       if (!c->ev[i] && hipEventCreate(&c->ev[i]) != hipSuccess) return PP_ERR_DEVICE;
     }
   }
-  c->profiling = on != 0;
+  c->profiling = on;
   return PP_OK;
 }
 

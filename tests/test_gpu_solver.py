@@ -338,17 +338,21 @@ def test_graph_replay_matches_eager(monkeypatch):
     fast = pp.Solver(0)
     kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed")
     try:
-        for it in range(7):
+        for it in range(10):
             if it == 3:
                 fd.mul_(1.5)                      # same zero pattern: same tree
             if it == 5:
                 fd[: n // 2].zero_()              # different sources: a different tree
+            if it == 7:
+                fast.set_profiling(2)             # near field timed between replayed segments
             scratch = torch.randn(1 << 16, device="cuda").sum()  # eager device work between replays
             torch.cuda.synchronize()
             got = to_host(fast.solve_grid(fd, g.h, txd, tyd, out=out, **kw)).copy()
             ref = to_host(eager.solve_grid(fd, g.h, txd, tyd, **kw))
             assert np.array_equal(got, ref), it
             assert fast.stats()["n_p2p_pairs"] == eager.stats()["n_p2p_pairs"]
+            if it >= 7:
+                assert fast.stats()["ms_phase"]["p2p"] > 0.0
             del scratch
     finally:
         fast.close()
