@@ -96,7 +96,11 @@ struct pp_ctx {
     std::vector<uint64_t> key;
     int seen = 0;
     hipGraphExec_t exec = nullptr;
-  } seg[2];
+  };
+  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, up to the near
+  // field); 2: after the near field (timing mode 2)
+  static constexpr int kSegments = 3;
+  Segment seg[kSegments];
   uint64_t budget = 0;
   size_t held = 0;
   DevBuf bufs[B_COUNT];
@@ -192,6 +196,7 @@ uint64_t bits(const void* p) { return (uint64_t)(uintptr_t)p; }
 // capture or instantiate falls back to eager launches for the rest of the context.
 template <class F>
 void run_segment(pp_ctx& c, int which, bool allowed, std::vector<uint64_t> key, hipStream_t s, F&& enqueue) {
+  if (which < 0 || which >= pp_ctx::kSegments) throw PPError{PP_ERR_LIMIT, "bad graph segment"};
   pp_ctx::Segment& g = c.seg[which];
   if (!allowed || !c.graphs || s == nullptr) {
     enqueue();
