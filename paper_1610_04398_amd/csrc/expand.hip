@@ -199,8 +199,15 @@ size_t m2m_lds_bytes(int p) {
   return kM2MIntWords * sizeof(int) + ((size_t)kM2MSlots * (p + 1) + 4 * (size_t)(p + 1) * (p + 1)) * sizeof(double2);
 }
 
-__global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1, int levels, int p,
-                                                      double2* __restrict__ mp) {
+// dense_flag/dense_off: the existence flags and cell numbers of the dense prefix
+// table the tree build used for its top levels (index ((4^L - 1) / 3) + prefix at
+// level L).  When the launch's levels all lie in that table (dense != 0), every
+// slot finds its cell there directly (slot offsets within a depth are Morton
+// offsets within R's subtree), instead of walking down the child links one
+// level at a time.
+__global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1, int L, int levels, int p,
+                                                      double2* __restrict__ mp, const int* __restrict__ dense_flag,
+                                                      const int* __restrict__ dense_off, int dense) {
   // slots: [0] = R, [1..4] its children, [5..20] grandchildren (4 per parent
   // slot), ... ; depth d holds slots [m2m_first(d), m2m_first(d + 1)).
   extern __shared__ int smem[];
@@ -219,24 +226,44 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1,
     const int q = w / (P1 * P1), l = (w / P1) % P1, k = w % P1;
     tm[w] = make_double2(c_m2m.v[q][l][k][0], c_m2m.v[q][l][k][1]);
   }
-  for (int d = 0; d <= levels; ++d) {
-    const int lo = m2m_first(d), hi = m2m_first(d + 1);
-    for (int i = lo + tid; i < hi; i += blockDim.x) {
-      int c = -1;
-      if (d == 0) {
-        c = R;
-      } else {
-        const int par = m2m_first(d - 1) + (i - lo) / 4;
-        const int q = (i - lo) % 4;
-        if (cell[par] >= 0 && hsrc[par] && q < nkid[par] && kid0[par] >= 0) c = kid0[par] + q;
+  if (dense) {
+    const int64_t PR = (int64_t)morton((uint32_t)t.ix[R], (uint32_t)t.iy[R]);
+    for (int i = tid; i < m2m_first(levels + 1); i += blockDim.x) {
+      int d = 0;
+      while (m2m_first(d + 1) <= i) ++d;
+      const int j = i - m2m_first(d);
+      int c = R;
+      if (d > 0) {
+        const int64_t idx = ((((int64_t)1 << (2 * (L + d))) - 1) / 3) + (PR << (2 * d)) + j;
+        c = dense_flag[idx] ? dense_off[idx] : -1;
       }
       cell[i] = c;
       kid0[i] = c >= 0 ? t.child[c] : -1;
-      nkid[i] = c >= 0 ? t.nchild[c] : 0;
+      nkid[i] = 4;  // children sit at their quadrant's slot; missing ones have no sources
       hsrc[i] = c >= 0 ? (t.se[c] > t.sb[c]) : 0;
-      quad[i] = c >= 0 ? ((t.ix[c] & 1) | ((t.iy[c] & 1) << 1)) : 0;
+      quad[i] = d > 0 ? (j & 3) : 0;
     }
     __syncthreads();
+  } else {
+    for (int d = 0; d <= levels; ++d) {
+      const int lo = m2m_first(d), hi = m2m_first(d + 1);
+      for (int i = lo + tid; i < hi; i += blockDim.x) {
+        int c = -1;
+        if (d == 0) {
+          c = R;
+        } else {
+          const int par = m2m_first(d - 1) + (i - lo) / 4;
+          const int q = (i - lo) % 4;
+          if (cell[par] >= 0 && hsrc[par] && q < nkid[par] && kid0[par] >= 0) c = kid0[par] + q;
+        }
+        cell[i] = c;
+        kid0[i] = c >= 0 ? t.child[c] : -1;
+        nkid[i] = c >= 0 ? t.nchild[c] : 0;
+        hsrc[i] = c >= 0 ? (t.se[c] > t.sb[c]) : 0;
+        quad[i] = c >= 0 ? ((t.ix[c] & 1) | ((t.iy[c] & 1) << 1)) : 0;
+      }
+      __syncthreads();
+    }
   }
   // stage: slots of depth `levels`, and leaves above it, hold final expansions
   const int nstage = m2m_first(levels + 1);
@@ -543,14 +570,17 @@ void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double
 
 int m2m_max_levels() { return kM2MLevels; }
 
-void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s) {
+void m2m_levels(TreeView t, int c0, int c1, int L, int levels, int p, double2* mp, const int* dense_flag,
+                const int* dense_off, int dense_levels, hipStream_t s) {
   if (c1 <= c0 || levels < 1) return;
+  levels = std::min(levels, kM2MLevels);
+  const int dense = (dense_flag && dense_off && L + levels <= dense_levels) ? 1 : 0;
   static std::once_flag lds_opt_in;
   std::call_once(lds_opt_in, [] {
     (void)hipFuncSetAttribute((const void*)k_m2m, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)m2m_lds_bytes(kMaxP));
   });
-  k_m2m<<<c1 - c0, kM2MThreads, m2m_lds_bytes(p), s>>>(t, c0, c1, std::min(levels, kM2MLevels), p, mp);
+  k_m2m<<<c1 - c0, kM2MThreads, m2m_lds_bytes(p), s>>>(t, c0, c1, L, levels, p, mp, dense_flag, dense_off, dense);
 }
 
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,

@@ -135,8 +135,12 @@ void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double
 // M2M for the `levels` (1..m2m_max_levels()) levels starting at the level
 // whose cells are [c0, c1): one workgroup per cell computes its subtree
 // bottom up.
+// L is the level of [c0, c1); dense_flag/dense_off/dense_levels describe the dense
+// prefix table of the tree build (its top dense_levels levels), used to find the
+// subtree cells directly when the launch lies inside it (may be null).
 int m2m_max_levels();
-void m2m_levels(TreeView t, int c0, int c1, int levels, int p, double2* mp, hipStream_t s);
+void m2m_levels(TreeView t, int c0, int c1, int L, int levels, int p, double2* mp, const int* dense_flag,
+                const int* dense_off, int dense_levels, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, int* flags, hipStream_t s);
 // M2P of the tree-code variant: far[k] for every target of the n target leaves
@@ -177,7 +181,7 @@ struct P2PArgs {
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };
 void p2p(const P2PArgs& a, int fp64, hipStream_t s);
-// Totals for the statistics, one workgroup in a fixed order: the (target,
+// Totals for the statistics, added atomically to zeroed slots: the (target,
 // source) pairs of the last p2p launch into a.pairs and, if cnt_m2l is set,
 // the list lengths of the ncells cells into *tot_m2l and *tot_p2p.
 void p2p_totals(const P2PArgs& a, const int* cnt_m2l, const int* cnt_p2p, int ncells, int* tot_m2l, int* tot_p2p,

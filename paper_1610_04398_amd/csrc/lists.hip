@@ -23,7 +23,11 @@ namespace pp {
 
 namespace {
 constexpr int kListWaves = 4;
-constexpr int kFrontierCap = 2048;
+// Frontier capacity per wave (two buffers).  The frontier of a target cell holds the
+// non-accepted source cells near its path, ~4 (2/theta + 1)^2 at most in a uniform
+// tree (about 100 at theta = 0.5): 1024 entries keep LDS at 32 KB per workgroup (five
+// workgroups per CU) for theta >= 0.3; smaller theta uses 2048.  Overflow is flagged.
+__host__ __device__ constexpr int frontier_cap_for(bool small_theta) { return small_theta ? 2048 : 1024; }
 
 // Packed per-cell record for the traversal: {ix, iy, first child, meta} with
 // meta = level | nchild << 5 | (children-with-sources mask) << 8 | has_src << 12.
@@ -53,6 +57,7 @@ __global__ void k_records(TreeView t, int n, int4* __restrict__ rec, int* __rest
   rec[c] = make_int4(t.ix[c], t.iy[c], k0, meta);
 }
 
+template <int kFrontierCap>
 __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4* __restrict__ rec,
                                                                const int* __restrict__ parent,
                                                                const int* __restrict__ tcells, int ntcells, int num,
@@ -173,6 +178,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
 // cell is replaced by its children with sources.  The frontier lives in LDS
 // and is classified 64 cells at a time; ballots compact the output in a fixed
 // order.  Same emit modes and layouts as k_lists.
+template <int kFrontierCap>
 __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
     int D, const int4* __restrict__ rec, const int* __restrict__ tleaves, int ntleaves, int num, int den, int emit,
     int* __restrict__ cnt_m, int* __restrict__ cnt_p, const int* __restrict__ off_m, const int* __restrict__ off_p,
@@ -268,17 +274,28 @@ void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
                 int* flags, hipStream_t s) {
   if (ntcells <= 0) return;
-  k_lists<<<(ntcells + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
-      t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
-      cap_m, cap_p, flags);
+  const unsigned g = (unsigned)((ntcells + kListWaves - 1) / kListWaves);
+  if (num * 10 < 3 * den)  // theta < 0.3
+    k_lists<frontier_cap_for(true)><<<g, kListWaves * kWave, 0, s>>>(
+        t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
+        cap_m, cap_p, flags);
+  else
+    k_lists<frontier_cap_for(false)><<<g, kListWaves * kWave, 0, s>>>(
+        t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
+        cap_m, cap_p, flags);
 }
 
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
                          int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
                          int cap_p, int* flags, hipStream_t s) {
   if (ntleaves <= 0) return;
-  k_lists_treecode<<<(ntleaves + kListWaves - 1) / kListWaves, kListWaves * kWave, 0, s>>>(
-      t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p, m_src, p_src, cap_m, cap_p, flags);
+  const unsigned g = (unsigned)((ntleaves + kListWaves - 1) / kListWaves);
+  if (num * 10 < 3 * den)
+    k_lists_treecode<frontier_cap_for(true)><<<g, kListWaves * kWave, 0, s>>>(
+        t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p, m_src, p_src, cap_m, cap_p, flags);
+  else
+    k_lists_treecode<frontier_cap_for(false)><<<g, kListWaves * kWave, 0, s>>>(
+        t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p, m_src, p_src, cap_m, cap_p, flags);
 }
 
 }  // namespace pp

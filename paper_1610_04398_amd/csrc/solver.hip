@@ -610,7 +610,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       const int ml = m2m_max_levels();
       for (int top = depth - 1; top >= 0; top -= ml) {
         const int L = std::max(top - (ml - 1), 0);
-        m2m_levels(tv, lstart[L], lstart[L + 1], top - L + 1, p, mp, s);
+        m2m_levels(tv, lstart[L], lstart[L + 1], L, top - L + 1, p, mp, dflag, doff, Ld, s);
       }
       mark(PP_PHASE_M2L);
       if (treecode) {
