@@ -13,17 +13,53 @@
 // Scattered sources that coincide exactly with a target were skipped by the
 // near-field kernel the same way; their share w ln u of the near weight term
 // is removed here (G(0) := 0).
+#include <algorithm>
+
 #include "internal.h"
 
 namespace pp {
 
 namespace {
-__global__ void k_finalize(int64_t m, int ncells, int nparts, const int* __restrict__ perm, const int* __restrict__ tleaf,
-                           const double* __restrict__ far, const double* __restrict__ near_sum,
-                           const double* __restrict__ leaf_wnear, const int* __restrict__ self_idx,
-                           const double* __restrict__ self_logd, const double* __restrict__ self_w,
-                           const double* __restrict__ f, double h, double lnh,
-                           int self_mode, const int* __restrict__ flags, double* __restrict__ out) {
+constexpr int kFinBlock = 256;
+constexpr int kTotItems = 16;  // statistics items per thread in the blocks that sum them
+
+// The first workgroups also sum the statistics (per-wave pair counts, per-cell
+// list lengths) into zeroed slots with integer atomics, so they need no launch of
+// their own.
+__global__ __launch_bounds__(kFinBlock) void k_finalize(
+    int64_t m, int ncells, int nparts, const int* __restrict__ perm, const int* __restrict__ tleaf,
+    const double* __restrict__ far, const double* __restrict__ near_sum, const double* __restrict__ leaf_wnear,
+    const int* __restrict__ self_idx, const double* __restrict__ self_logd, const double* __restrict__ self_w,
+    const double* __restrict__ f, double h, double lnh, int self_mode, const int* __restrict__ flags,
+    double* __restrict__ out, FinalizeTotals tot) {
+  const int64_t tot_n = std::max<int64_t>(tot.pairs ? tot.nwaves : 0, tot.cnt_m ? tot.ncells : 0);
+  const int64_t tot_base = (int64_t)blockIdx.x * kFinBlock * kTotItems;
+  if (tot_base < tot_n) {  // uniform per workgroup
+    __shared__ long long part[3][kFinBlock];
+    long long acc = 0, am = 0, ap = 0;
+    for (int q = 0; q < kTotItems; ++q) {
+      const int64_t i = tot_base + (int64_t)q * kFinBlock + threadIdx.x;
+      if (tot.pairs && i < tot.nwaves) acc += tot.pair_counts[i];
+      if (tot.cnt_m && i < tot.ncells) {
+        am += tot.cnt_m[i];
+        ap += tot.cnt_p[i];
+      }
+    }
+    part[0][threadIdx.x] = acc;
+    part[1][threadIdx.x] = am;
+    part[2][threadIdx.x] = ap;
+    __syncthreads();
+    for (int w = kFinBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w)
+        for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += part[q][threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (tot.pairs && part[0][0]) atomicAdd(tot.pairs, (unsigned long long)part[0][0]);
+      if (tot.cnt_m && part[1][0]) atomicAdd(tot.tot_m, (int)part[1][0]);
+      if (tot.cnt_m && part[2][0]) atomicAdd(tot.tot_p, (int)part[2][0]);
+    }
+  }
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   if (*flags != 0) return;
@@ -52,11 +88,14 @@ __global__ void k_finalize(int64_t m, int ncells, int nparts, const int* __restr
 void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
               const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
               const double* self_w, const double* f, double h, int self_mode, const int* flags, double* out,
-              hipStream_t s) {
-  if (m <= 0) return;
-  k_finalize<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, ncells, nparts, perm, tleaf, far, near_sum, leaf_wnear,
-                                                         self_idx, self_logd, self_w, f, h, log(h), self_mode, flags,
-                                                         out);
+              const FinalizeTotals& tot, hipStream_t s) {
+  const int64_t tot_n = std::max<int64_t>(tot.pairs ? tot.nwaves : 0, tot.cnt_m ? tot.ncells : 0);
+  const int64_t blocks = std::max((m + kFinBlock - 1) / kFinBlock,
+                                  (tot_n + (int64_t)kFinBlock * kTotItems - 1) / ((int64_t)kFinBlock * kTotItems));
+  if (blocks <= 0) return;
+  k_finalize<<<(unsigned)blocks, kFinBlock, 0, s>>>(m, ncells, nparts, perm, tleaf, far, near_sum, leaf_wnear,
+                                                    self_idx, self_logd, self_w, f, h, log(h), self_mode, flags, out,
+                                                    tot);
 }
 
 }  // namespace pp

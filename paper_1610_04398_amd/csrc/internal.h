@@ -181,21 +181,29 @@ struct P2PArgs {
   double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
 };
 void p2p(const P2PArgs& a, int fp64, hipStream_t s);
-// Totals for the statistics, added atomically to zeroed slots: the (target,
-// source) pairs of the last p2p launch into a.pairs and, if cnt_m2l is set,
-// the list lengths of the ncells cells into *tot_m2l and *tot_p2p.
-void p2p_totals(const P2PArgs& a, const int* cnt_m2l, const int* cnt_p2p, int ncells, int* tot_m2l, int* tot_p2p,
-                hipStream_t s);
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.
 // near_sum and leaf_wnear hold nparts partial sums (strides m and ncells).
+// Statistics summed by the finalize launch into zeroed slots: the per-wave pair
+// counts (pair_counts[0..nwaves) into *pairs, if pairs is set) and the per-cell list
+// lengths (cnt_m/cnt_p[0..ncells) into *tot_m/*tot_p, if cnt_m is set).
+struct FinalizeTotals {
+  const long long* pair_counts = nullptr;
+  int64_t nwaves = 0;
+  unsigned long long* pairs = nullptr;
+  const int* cnt_m = nullptr;
+  const int* cnt_p = nullptr;
+  int64_t ncells = 0;
+  int* tot_m = nullptr;
+  int* tot_p = nullptr;
+};
 // self_idx/self_logd: grid-node coincidence (may be null); self_w: per target
 // the weight of exactly coincident scattered sources (may be null).
 void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
               const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
               const double* self_w, const double* f, double h, int self_mode, const int* flags, double* out,
-              hipStream_t s);
+              const FinalizeTotals& tot, hipStream_t s);
 
 // ---- forces.hip: pressure forces on surfaces -----------------------------------------
 // One workgroup per segment seg[s]..seg[s+1] (device array of nseg + 1); dfx/dfy may be null.

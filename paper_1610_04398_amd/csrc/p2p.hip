@@ -209,41 +209,6 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
   if (bad && lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
 }
 
-// Statistics totals: the per-wave pair counts and, optionally, the per-cell list
-// lengths.  Each workgroup sums a slice and adds it atomically (integers, so the
-// order does not matter); the targets start at zero.
-constexpr int kTotBlock = 256;
-constexpr int kTotItems = 16;
-__global__ __launch_bounds__(kTotBlock) void k_totals(const long long* __restrict__ v, int n,
-                                                      unsigned long long* __restrict__ out,
-                                                      const int* __restrict__ cm, const int* __restrict__ cp,
-                                                      int ncells, int* __restrict__ tot_m, int* __restrict__ tot_p) {
-  __shared__ long long part[3][kTotBlock];
-  const int64_t base = (int64_t)blockIdx.x * kTotBlock * kTotItems;
-  long long acc = 0, am = 0, ap = 0;
-  for (int q = 0; q < kTotItems; ++q) {
-    const int64_t i = base + (int64_t)q * kTotBlock + threadIdx.x;
-    if (out && i < n) acc += v[i];
-    if (cm && i < ncells) {
-      am += cm[i];
-      ap += cp[i];
-    }
-  }
-  part[0][threadIdx.x] = acc;
-  part[1][threadIdx.x] = am;
-  part[2][threadIdx.x] = ap;
-  __syncthreads();
-  for (int w = kTotBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int q = 0; q < 3; ++q) part[q][threadIdx.x] += part[q][threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (out && part[0][0]) atomicAdd(out, (unsigned long long)part[0][0]);
-    if (cm && part[1][0]) atomicAdd(tot_m, (int)part[1][0]);
-    if (cm && part[2][0]) atomicAdd(tot_p, (int)part[2][0]);
-  }
-}
 }  // namespace
 
 void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
@@ -262,17 +227,6 @@ void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
     else
       k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4);
   }
-}
-
-void p2p_totals(const P2PArgs& a, const int* cnt_m2l, const int* cnt_p2p, int ncells, int* tot_m2l, int* tot_p2p,
-                hipStream_t s) {
-  const int64_t waves = (int64_t)a.ntleaves * a.nparts;
-  const bool pairs = waves > 0 && a.pair_counts && a.pairs;
-  if (!pairs && !cnt_m2l) return;
-  const int64_t n = std::max<int64_t>(pairs ? waves : 0, cnt_m2l ? ncells : 0);
-  const int64_t per = (int64_t)kTotBlock * kTotItems;
-  k_totals<<<(unsigned)std::max<int64_t>(1, (n + per - 1) / per), kTotBlock, 0, s>>>(
-      a.pair_counts, pairs ? (int)waves : 0, pairs ? a.pairs : nullptr, cnt_m2l, cnt_p2p, ncells, tot_m2l, tot_p2p);
 }
 
 }  // namespace pp

@@ -639,10 +639,17 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto seg2_finalize = [&] {
     // ---- finalize ----
     mark(PP_PHASE_FINALIZE);
-    p2p_totals(pa, list_totals ? cm2l : nullptr, list_totals ? cp2p : nullptr, ncells, misc + M_NM2L, misc + M_NP2P,
-               s);
+    FinalizeTotals tot;
+    tot.pair_counts = pcount;
+    tot.nwaves = (int64_t)ntl * nparts;
+    tot.pairs = pairs;
+    tot.cnt_m = list_totals ? cm2l : nullptr;
+    tot.cnt_p = list_totals ? cp2p : nullptr;
+    tot.ncells = ncells;
+    tot.tot_m = misc + M_NM2L;
+    tot.tot_p = misc + M_NP2P;
     finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, selfw, f_d, unit, prm.self_mode,
-             misc + M_FLAGS, out_d, s);
+             misc + M_FLAGS, out_d, tot, s);
     mark(12);
     readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
   };

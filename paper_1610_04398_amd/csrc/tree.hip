@@ -19,17 +19,6 @@ namespace pp {
 
 namespace {
 
-__device__ inline int lower_bound_u32(const uint32_t* __restrict__ a, int lo, int hi, uint64_t key) {
-  while (lo < hi) {
-    const int mid = lo + ((hi - lo) >> 1);
-    if ((uint64_t)a[mid] < key)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
 // lower_bound of key in a[lo, hi) by one wave: 64 probes per step shrink the
 // range 64-fold, so a range of 2^18 keys takes three dependent loads instead
 // of eighteen.  All lanes return the same index.
@@ -158,6 +147,39 @@ __device__ inline int dense_level_of(int64_t idx) {
   return L;
 }
 
+// lower_bound of key in a[0, n) starting from a guess g: gallop away from g until
+// the answer is bracketed, then bisect the bracket.  For keys spread evenly over
+// the key range a guess proportional to the key needs only a few probes.
+__device__ inline int lower_bound_from(const uint32_t* __restrict__ a, int n, uint64_t key, int64_t guess) {
+  const int64_t g = guess < 0 ? 0 : (guess > n ? n : guess);
+  int64_t lo, hi;
+  if (g < n && (uint64_t)a[g] < key) {
+    lo = g + 1;
+    int64_t step = 1;
+    while (lo + step - 1 < n && (uint64_t)a[lo + step - 1] < key) {
+      lo += step;
+      step *= 2;
+    }
+    hi = min((int64_t)n, lo + step - 1);
+  } else {
+    hi = g;
+    int64_t step = 1;
+    while (hi - step >= 0 && (uint64_t)a[hi - step] >= key) {
+      hi -= step;
+      step *= 2;
+    }
+    lo = max((int64_t)0, hi - step + 1);
+  }
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if ((uint64_t)a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (int)lo;
+}
+
 __global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __restrict__ nsrc_dev,
                                const uint32_t* __restrict__ tkey, int ntgt, int D, int Ld, int* __restrict__ ss,
                                int* __restrict__ ts) {
@@ -165,8 +187,9 @@ __global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __r
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (P > np) return;
   const uint64_t key = (uint64_t)P << (2 * (D - Ld));
-  ss[P] = lower_bound_u32(skey, 0, *nsrc_dev, key);
-  ts[P] = lower_bound_u32(tkey, 0, ntgt, key);
+  const int ns = *nsrc_dev;
+  ss[P] = lower_bound_from(skey, ns, key, (P * (int64_t)ns) / np);
+  ts[P] = lower_bound_from(tkey, ntgt, key, (P * (int64_t)ntgt) / np);
 }
 
 __global__ void k_dense_flags(const int* __restrict__ ss, const int* __restrict__ ts, int D, int Ld, int leaf_max,
