@@ -83,7 +83,8 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
 // possible aliasing the compiler keeps their wave-uniform loads on the scalar
 // path although the kernel stores partial sums between chunks.
 template <bool DIRECT>
-__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p32(P2PArgs a, const float4* __restrict__ src4) {
+__global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_p2p32(
+    P2PArgs a, const float4* __restrict__ src4) {
   // wave-uniform work index (keeps all per-item data in scalar registers)
   const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
                                                     threadIdx.x / kWave);

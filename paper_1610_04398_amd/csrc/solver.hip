@@ -81,7 +81,7 @@ struct pp_ctx {
   int cap_m2p = 512;  // the same for the tree-code variant's per-leaf lists
   int cap_tp2p = 96;
   bool exact_lists = false;  // PP_EXACT_LISTS=1 forces the two-pass lists
-  int dense_levels = 8;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
+  int dense_levels = 9;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
