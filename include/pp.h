@@ -226,12 +226,16 @@ pp_status pp_viscous_forces(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, doub
 pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
 
 /* GPU timing of later calls: 0 off; 1 HIP events between all phases
- * (ms_phase[]; launches are then not replayed from graphs); 2 HIP events
- * around the near-field launch only (ms_phase[PP_PHASE_P2P]; the launches
- * before and after it are still replayed).  Events are recorded on the call's
- * stream and add no synchronisation beyond the call's own.  Repeated calls with
- * device-resident grid input of unchanged shape and pointers replay the
- * launches of their two segments from captured HIP graphs. */
+ * (ms_phase[]; every phase then runs on the call's stream, one after the
+ * other, and launches are not replayed from graphs); 2 HIP events around the
+ * near-field launch only (ms_phase[PP_PHASE_P2P]; the launches before and
+ * after it are still replayed).  Events add no synchronisation beyond the
+ * call's own.  Outside mode 1 the near field runs on a second stream owned by
+ * the context, concurrently with the expansions on the call's stream, which
+ * waits for it before the finalize step; the mode-2 events are recorded on
+ * that second stream.  Repeated calls with device-resident grid input of
+ * unchanged shape and pointers replay the launches of their two segments from
+ * captured HIP graphs. */
 pp_status pp_set_profiling(pp_ctx* ctx, int32_t on);
 
 /*

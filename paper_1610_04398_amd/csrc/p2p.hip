@@ -44,31 +44,41 @@ __device__ inline float pair_log2(float tx, float ty, const float4& q, bool guar
   return __builtin_amdgcn_logf(r2);  // v_log_f32: log2
 }
 
-// Sources [s0, s1) of one leaf against this lane's target.  Terms are summed
-// eight at a time (the first product starts from -comp) and each group is
-// folded into the running sum with Kahan compensation (3 VALU per 8 pairs);
-// a ragged tail is folded one term at a time.
+// G consecutive sources from s: their terms are summed in order (the first
+// product starts from -comp) and the group is folded into the running sum with
+// Kahan compensation.
+template <int G, bool GUARD>
+__device__ inline void p2p32_group(const float4* __restrict__ src4, int s, float tx, float ty, float& sum,
+                                   float& comp) {
+  float4 q[G];
+  float l[G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) q[i] = src4[s + i];
+#pragma unroll
+  for (int i = 0; i < G; ++i) l[i] = pair_log2(tx, ty, q[i], GUARD);
+  float y = fmaf(q[0].z, l[0], -comp);
+#pragma unroll
+  for (int i = 1; i < G; ++i) y = fmaf(q[i].z, l[i], y);
+  kahan_fold(y, sum, comp);
+}
+
+// Sources [s0, s1) of one leaf against this lane's target: groups of eight
+// (3 VALU of compensation per 8 pairs), then the ragged tail as at most one
+// group each of four, two and one.
 template <bool GUARD>
 __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s1, float tx, float ty, float& sum,
                                   float& comp) {
-  constexpr int G = 8;
   int s = s0;
-  for (; s + G <= s1; s += G) {
-    float4 q[G];
-    float l[G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) q[i] = src4[s + i];
-#pragma unroll
-    for (int i = 0; i < G; ++i) l[i] = pair_log2(tx, ty, q[i], GUARD);
-    float y = fmaf(q[0].z, l[0], -comp);
-#pragma unroll
-    for (int i = 1; i < G; ++i) y = fmaf(q[i].z, l[i], y);
-    kahan_fold(y, sum, comp);
+  for (; s + 8 <= s1; s += 8) p2p32_group<8, GUARD>(src4, s, tx, ty, sum, comp);
+  if (s + 4 <= s1) {
+    p2p32_group<4, GUARD>(src4, s, tx, ty, sum, comp);
+    s += 4;
   }
-  for (; s < s1; ++s) {
-    const float4 q = src4[s];
-    kahan_fold(fmaf(q.z, pair_log2(tx, ty, q, GUARD), -comp), sum, comp);
+  if (s + 2 <= s1) {
+    p2p32_group<2, GUARD>(src4, s, tx, ty, sum, comp);
+    s += 2;
   }
+  if (s < s1) p2p32_group<1, GUARD>(src4, s, tx, ty, sum, comp);
 }
 
 // Work: wave w (workgroups spread over the XCDs in contiguous runs, so an

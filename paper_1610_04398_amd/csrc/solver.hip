@@ -92,14 +92,20 @@ struct pp_ctx {
   // work of calls on the null stream runs on this blocking stream (ordered with the
   // null stream like the null stream itself), which can be captured
   hipStream_t own_stream = nullptr;
+  // the near field runs on this second stream (default priority, non-blocking)
+  // while the expansions run on the caller's stream; fork and join are events
+  // (PP_NEAR_STREAM=0 keeps it on the caller's stream after the expansions)
+  bool near_stream = true;
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   struct Segment {
     std::vector<uint64_t> key;
     int seen = 0;
     hipGraphExec_t exec = nullptr;
   };
-  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, up to the near
-  // field); 2: after the near field (timing mode 2)
-  static constexpr int kSegments = 3;
+  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, the lists and
+  // packing); in timing mode 2 also 2: the expansions, 3: the finalize step
+  static constexpr int kSegments = 4;
   Segment seg[kSegments];
   uint64_t budget = 0;
   size_t held = 0;
@@ -566,7 +572,29 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   for (int v : lstart) key2.push_back((uint64_t)v);
 
   // ---- segment 2: lists, expansions, near field, finalize; ends with the read-back ----
-  auto seg2_expansions = [&] {
+  // The near field depends only on the lists and the packed leaves, the expansions
+  // only on the lists: after the packing the near field forks onto the side stream
+  // and runs beside the upward and downward passes (each fills the other's idle
+  // compute units), and the finalize step waits for both.  Timing mode 1 keeps
+  // every phase on one stream so that its per-phase events mean something.
+  hipStream_t ss = s;
+  if (c.profiling != 1 && c.near_stream) {
+    if (!c.side_stream) HIPCHK(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
+    if (!c.ev_fork) HIPCHK(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    if (!c.ev_join) HIPCHK(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    ss = c.side_stream;
+  }
+  auto fork_near = [&] {
+    if (ss == s) return;
+    HIPCHK(hipEventRecord(c.ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(ss, c.ev_fork, 0));
+  };
+  auto join_near = [&] {
+    if (ss == s) return;
+    HIPCHK(hipEventRecord(c.ev_join, ss));
+    HIPCHK(hipStreamWaitEvent(s, c.ev_join, 0));
+  };
+  auto seg2_lists = [&] {
     // ---- interaction lists ----
     mark(PP_PHASE_LISTS);
     if (!direct) {
@@ -600,7 +628,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf,
                        selfw, s);
     }
-
+  };
+  auto seg2_far = [&] {
     // ---- expansions: upward and downward passes ----
     if (!direct) {
       mark(PP_PHASE_P2M);
@@ -628,13 +657,6 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     } else {
       for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
     }
-
-  };
-  auto seg2_near = [&] {
-    // ---- near field ----
-    mark(PP_PHASE_P2P);
-    p2p(pa, mixed ? 0 : 1, s);
-
   };
   auto seg2_finalize = [&] {
     // ---- finalize ----
@@ -654,19 +676,33 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
   };
   if (c.profiling == 2) {
-    // the near field between two replayed segments, bracketed by events on this stream
-    std::vector<uint64_t> ka = key2, kb = key2;
+    // the same schedule with the near field launched outside the replayed segments,
+    // bracketed by events on its own stream
+    std::vector<uint64_t> ka = key2, kb = key2, kc = key2;
     ka.push_back(1);
     kb.push_back(2);
-    run_segment(c, 1, replayable, ka, s, seg2_expansions);
-    HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], s));
-    p2p(pa, mixed ? 0 : 1, s);
-    HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], s));
-    run_segment(c, 2, replayable, kb, s, seg2_finalize);
+    kc.push_back(3);
+    run_segment(c, 1, replayable, ka, s, seg2_lists);
+    fork_near();
+    HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
+    p2p(pa, mixed ? 0 : 1, ss);
+    HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
+    run_segment(c, 2, replayable, kb, s, seg2_far);
+    join_near();
+    run_segment(c, 3, replayable, kc, s, seg2_finalize);
   } else {
     run_segment(c, 1, replayable, key2, s, [&] {
-      seg2_expansions();
-      seg2_near();
+      seg2_lists();
+      if (ss == s) {
+        seg2_far();
+        mark(PP_PHASE_P2P);
+        p2p(pa, mixed ? 0 : 1, s);
+      } else {
+        fork_near();
+        p2p(pa, mixed ? 0 : 1, ss);
+        seg2_far();
+        join_near();
+      }
       seg2_finalize();
     });
   }
@@ -801,6 +837,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities
     int a = 0, b = 0, x = 0, y = 0;
     const int got = std::sscanf(e, "%d,%d,%d,%d", &a, &b, &x, &y);
@@ -827,6 +864,9 @@ void pp_destroy(pp_ctx* c) {
   (void)hipSetDevice(c->device);
   for (auto& g : c->seg) drop_graph(g);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (int i = 0; i < B_COUNT; ++i) release(*c, i);
   for (int i = 0; i < 13; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -889,6 +929,12 @@ void run_force_kernel(pp_ctx& c, int64_t m, int32_t nseg, const int64_t* seg_sta
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// A call that failed after forking the near field must not return while that
+// launch may still use the context's buffers.
+void drain_side(pp_ctx* c) {
+  if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
+}
+
 template <class Body>
 pp_status guarded(pp_ctx* c, Body body) {
   if (!c) return PP_ERR_ARG;
@@ -903,9 +949,11 @@ pp_status guarded(pp_ctx* c, Body body) {
   } catch (const PPError& e) {
     c->err = e.msg;
     if (e.code == PP_ERR_DEVICE) c->dead = true;
+    drain_side(c);
     return e.code;
   } catch (const std::exception& e) {
     c->err = e.what();
+    drain_side(c);
     return PP_ERR_DEVICE;
   }
 }
