@@ -8,10 +8,12 @@ plus 2,048 points on an ellipse, expansion order p = 12, acceptance theta =
 expansions).  One step = one complete solve (ingest, target sort, tree,
 interaction lists, P2M, M2M, M2L, L2L, L2P, P2P, finalize) with the inputs
 already resident in device memory.  Repeated solves replay their launches from
-captured HIP graphs (the library does this when shape and pointers repeat);
-HIP events around every near-field launch in the timed region give the
-kernel's duration for the roofline, and a further untimed pass with events
-between all phases gives the phase breakdown.
+captured HIP graphs (the library does this when shape and pointers repeat),
+and the near field runs on a second stream beside the upward and downward
+passes.  HIP events around every near-field launch in the timed region (on
+that stream) give the kernel's duration for the roofline; a further pass with
+events between all phases, each phase alone on one stream, gives the phase
+breakdown, and a last pass without any events gives the untimed rate.
 
 Prints one JSON line: solves/s, effective interactions/s against the GPU
 all-pairs direct sum, accuracy against the FP64 CPU oracle on sampled targets,
@@ -206,7 +208,7 @@ def main() -> int:
 
     s = pp.Solver(0)
     # timed region: launches replayed from captured graphs, HIP events around every near-field
-    # launch (on the solve's stream) for the roofline
+    # launch (on the stream it runs on) for the roofline
     s.set_profiling(2)
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -246,6 +248,16 @@ def main() -> int:
     ms_eager = 1e3 * (time.perf_counter() - tp0) / nph
     phases = dict(zip(pp._binding.PHASES, (phase_sum / nph).tolist()))
     s.set_profiling(0)
+
+    # the same solves with no timing events at all (one replayed graph per segment)
+    for _ in range(3):
+        s.solve_grid(f, g.h, tx, ty, out=out, **kw)
+    torch.cuda.synchronize()
+    tu0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.solve_grid(f, g.h, tx, ty, out=out, **kw)
+    torch.cuda.synchronize()
+    untimed_value = args.steps / (time.perf_counter() - tu0)
 
     direct_s = None
     if args.direct_steps > 0:
@@ -374,8 +386,12 @@ def main() -> int:
             "speedup_tree_vs_direct": direct_s / (ms_per_step * 1e-3)},
         "accuracy_vs_oracle": acc,
         "phases_ms": phases,
-        "phases_note": f"per-phase HIP-event times from {nph} further solves launched without graph replay "
-                       f"({ms_eager:.3f} ms per solve); the timed solves replay their launches from graphs",
+        "phases_note": f"per-phase HIP-event times from {nph} further solves launched without graph replay, "
+                       f"every phase on one stream ({ms_eager:.3f} ms per solve); the timed solves replay their "
+                       "launches from graphs and run the near field on a second stream beside the expansions",
+        "untimed_solves_per_s": untimed_value,
+        "untimed_note": "the same solves without the near-field timing events: each segment one replayed graph, "
+                        "the lists also overlapping the upward pass",
         "tree": {k: st[k] for k in ("depth", "ncells", "nsrc_leaves", "ntgt_leaves", "n_m2l", "n_p2p_lists",
                                      "n_p2p_pairs")},
         "served": served,

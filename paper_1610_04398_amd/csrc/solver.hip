@@ -97,14 +97,15 @@ struct pp_ctx {
   // (PP_NEAR_STREAM=0 keeps it on the caller's stream after the expansions)
   bool near_stream = true;
   hipStream_t side_stream = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_lists = nullptr, ev_join = nullptr;
   struct Segment {
     std::vector<uint64_t> key;
     int seen = 0;
     hipGraphExec_t exec = nullptr;
   };
-  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, the lists and
-  // packing); in timing mode 2 also 2: the expansions, 3: the finalize step
+  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, the work
+  // before the near field); in timing mode 2 also 2: the expansions after it,
+  // 3: the finalize step
   static constexpr int kSegments = 4;
   Segment seg[kSegments];
   uint64_t budget = 0;
@@ -557,12 +558,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
 
-  auto list_pass = [&](int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp) {
+  auto list_pass = [&](int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp, hipStream_t q) {
     if (treecode)
       lists_treecode_pass(tv, rec, tleaves, ntl, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
-                          s);
+                          q);
     else
-      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS, s);
+      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS, q);
   };
   std::vector<uint64_t> key2 = key1;
   for (uint64_t v : {(uint64_t)N, (uint64_t)ncells, (uint64_t)nsl, (uint64_t)ntl, (uint64_t)ntc, (uint64_t)depth,
@@ -572,94 +573,100 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   for (int v : lstart) key2.push_back((uint64_t)v);
 
   // ---- segment 2: lists, expansions, near field, finalize; ends with the read-back ----
-  // The near field depends only on the lists and the packed leaves, the expansions
-  // only on the lists: after the packing the near field forks onto the side stream
-  // and runs beside the upward and downward passes (each fills the other's idle
-  // compute units), and the finalize step waits for both.  Timing mode 1 keeps
-  // every phase on one stream so that its per-phase events mean something.
+  // Dependencies: the upward pass needs only the packed source leaves; the lists
+  // need only the tree; the near field needs the lists and both packings; the
+  // M2L (or M2P) needs the lists and the upward pass.  So after the source
+  // packing the work forks: the side stream builds the lists, prepares the
+  // targets and runs the near field, while the caller's stream runs the upward
+  // pass, waits for the lists, runs the M2L and downward passes, and finally
+  // waits for the near field before the finalize step.  Each stream's work fills
+  // compute units the other leaves idle.  Timing mode 1 keeps every phase on one
+  // stream, in phase order, so that its per-phase events mean something.
   hipStream_t ss = s;
   if (c.profiling != 1 && c.near_stream) {
     if (!c.side_stream) HIPCHK(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
-    if (!c.ev_fork) HIPCHK(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
-    if (!c.ev_join) HIPCHK(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    for (hipEvent_t* e : {&c.ev_fork, &c.ev_lists, &c.ev_join})
+      if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
     ss = c.side_stream;
   }
-  auto fork_near = [&] {
+  // `from` signals `to` through event e (no-op without the side stream)
+  auto signal = [&](hipEvent_t e, hipStream_t from, hipStream_t to) {
     if (ss == s) return;
-    HIPCHK(hipEventRecord(c.ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(ss, c.ev_fork, 0));
+    HIPCHK(hipEventRecord(e, from));
+    HIPCHK(hipStreamWaitEvent(to, e, 0));
   };
-  auto join_near = [&] {
-    if (ss == s) return;
-    HIPCHK(hipEventRecord(c.ev_join, ss));
-    HIPCHK(hipStreamWaitEvent(s, c.ev_join, 0));
-  };
-  auto seg2_lists = [&] {
-    // ---- interaction lists ----
-    mark(PP_PHASE_LISTS);
-    if (!direct) {
-      if (exact_lists) {
-        cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, s);
-        list_pass(0, nullptr, nullptr, nullptr, nullptr, 0, 0);
-        scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, s);
-        scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, s);
-        readback(c, misc, 0, 16, s);
-        check_flags(c.pinned[M_FLAGS]);
-        n_m2l = c.pinned[M_NM2L];
-        n_p2pl = c.pinned[M_NP2P];
-        m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
-        p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
-        list_pass(1, om2l, op2p, m2l_src, p2p_src, 0, 0);
-      } else {
-        cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, s);
-        list_pass(2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near);
-      }
+  // the two-pass lists read a total back to the host, so they run first, on s
+  const bool lists_early = exact_lists && !direct;
+  auto do_lists = [&](hipStream_t q) {
+    if (direct) return;
+    if (exact_lists) {
+      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, q);
+      list_pass(0, nullptr, nullptr, nullptr, nullptr, 0, 0, q);
+      scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, q);
+      scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, q);
+      readback(c, misc, 0, 16, q);
+      check_flags(c.pinned[M_FLAGS]);
+      n_m2l = c.pinned[M_NM2L];
+      n_p2pl = c.pinned[M_NP2P];
+      m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
+      p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
+      list_pass(1, om2l, op2p, m2l_src, p2p_src, 0, 0, q);
+    } else {
+      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, q);
+      list_pass(2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near, q);
     }
-    pa.list_src = direct ? nullptr : p2p_src;
-
-    // ---- per-leaf packing ----
-    mark(PP_PHASE_PACK);
-    if (src.grid) {
+    pa.list_src = p2p_src;
+  };
+  auto do_pack_sources = [&] {
+    if (src.grid)
       leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
-      leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, rel32,
-                        rel64, tgtleaf, selfi, selfd, s);
-    } else {
+    else
       leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, s);
+  };
+  auto do_prep_targets = [&](hipStream_t q) {
+    if (src.grid)
+      leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, rel32,
+                        rel64, tgtleaf, selfi, selfd, q);
+    else
       leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf,
-                       selfw, s);
-    }
+                       selfw, q);
   };
-  auto seg2_far = [&] {
-    // ---- expansions: upward and downward passes ----
-    if (!direct) {
-      mark(PP_PHASE_P2M);
-      p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
+  auto do_upward = [&] {
+    mark(PP_PHASE_P2M);
+    if (direct) {
       mark(PP_PHASE_M2M);
-      // the recursion from the finest level up, several levels per launch
-      const int ml = m2m_max_levels();
-      for (int top = depth - 1; top >= 0; top -= ml) {
-        const int L = std::max(top - (ml - 1), 0);
-        m2m_levels(tv, lstart[L], lstart[L + 1], L, top - L + 1, p, mp, dflag, doff, Ld, s);
-      }
-      mark(PP_PHASE_M2L);
-      if (treecode) {
-        // multipoles evaluated at the targets; no local expansions
-        m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far, misc + M_FLAGS, s);
-        mark(PP_PHASE_L2L);
-        mark(PP_PHASE_L2P);
-      } else {
-        m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
-        mark(PP_PHASE_L2L);
-        downward(tv, tcells, ntc, p, own, loc, s);
-        mark(PP_PHASE_L2P);
-        l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
-      }
-    } else {
-      for (int ph = PP_PHASE_P2M; ph <= PP_PHASE_L2P; ++ph) mark(ph);
+      return;
+    }
+    p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
+    mark(PP_PHASE_M2M);
+    // the recursion from the finest level up, several levels per launch
+    const int ml = m2m_max_levels();
+    for (int top = depth - 1; top >= 0; top -= ml) {
+      const int L = std::max(top - (ml - 1), 0);
+      m2m_levels(tv, lstart[L], lstart[L + 1], L, top - L + 1, p, mp, dflag, doff, Ld, s);
     }
   };
-  auto seg2_finalize = [&] {
-    // ---- finalize ----
+  auto do_downward = [&] {
+    if (direct) {
+      for (int ph = PP_PHASE_M2L; ph <= PP_PHASE_L2P; ++ph) mark(ph);
+      return;
+    }
+    mark(PP_PHASE_M2L);
+    if (treecode) {
+      // multipoles evaluated at the targets; no local expansions
+      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far, misc + M_FLAGS, s);
+      mark(PP_PHASE_L2L);
+      mark(PP_PHASE_L2P);
+    } else {
+      m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
+      mark(PP_PHASE_L2L);
+      downward(tv, tcells, ntc, p, own, loc, s);
+      mark(PP_PHASE_L2P);
+      l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+    }
+  };
+  auto do_near = [&](hipStream_t q) { p2p(pa, mixed ? 0 : 1, q); };
+  auto do_finalize = [&] {
     mark(PP_PHASE_FINALIZE);
     FinalizeTotals tot;
     tot.pair_counts = pcount;
@@ -675,35 +682,66 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(12);
     readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
   };
+  // side-stream part before the near field
+  auto side_lists = [&] {
+    if (!lists_early) do_lists(ss);
+    do_prep_targets(ss);
+  };
+
   if (c.profiling == 2) {
-    // the same schedule with the near field launched outside the replayed segments,
-    // bracketed by events on its own stream
-    std::vector<uint64_t> ka = key2, kb = key2, kc = key2;
-    ka.push_back(1);
-    kb.push_back(2);
-    kc.push_back(3);
-    run_segment(c, 1, replayable, ka, s, seg2_lists);
-    fork_near();
+    // The near field launched outside the replayed segments, bracketed by events
+    // on its own stream: the work it depends on (packing, lists) is replayed
+    // first, then it runs beside the replayed upward and downward passes.  (The
+    // lists then no longer overlap the upward pass; otherwise the schedule is
+    // that of an untimed call.)
+    auto key = [&](uint64_t i) {
+      std::vector<uint64_t> k = key2;
+      k.push_back(i);
+      return k;
+    };
+    if (lists_early) do_lists(s);
+    run_segment(c, 1, replayable, key(1), s, [&] {
+      do_pack_sources();
+      if (!lists_early) do_lists(s);
+      do_prep_targets(s);
+    });
+    signal(c.ev_fork, s, ss);
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
-    p2p(pa, mixed ? 0 : 1, ss);
+    do_near(ss);
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
-    run_segment(c, 2, replayable, kb, s, seg2_far);
-    join_near();
-    run_segment(c, 3, replayable, kc, s, seg2_finalize);
-  } else {
+    run_segment(c, 2, replayable, key(2), s, [&] {
+      do_upward();
+      do_downward();
+    });
+    signal(c.ev_join, ss, s);
+    run_segment(c, 3, replayable, key(3), s, do_finalize);
+  } else if (ss == s) {
+    // one stream, phases in order (timing mode 1, or the side stream disabled)
     run_segment(c, 1, replayable, key2, s, [&] {
-      seg2_lists();
-      if (ss == s) {
-        seg2_far();
-        mark(PP_PHASE_P2P);
-        p2p(pa, mixed ? 0 : 1, s);
-      } else {
-        fork_near();
-        p2p(pa, mixed ? 0 : 1, ss);
-        seg2_far();
-        join_near();
-      }
-      seg2_finalize();
+      mark(PP_PHASE_LISTS);
+      do_lists(s);
+      mark(PP_PHASE_PACK);
+      do_pack_sources();
+      do_prep_targets(s);
+      do_upward();
+      do_downward();
+      mark(PP_PHASE_P2P);
+      do_near(s);
+      do_finalize();
+    });
+  } else {
+    if (lists_early) do_lists(s);
+    run_segment(c, 1, replayable, key2, s, [&] {
+      do_pack_sources();
+      signal(c.ev_fork, s, ss);
+      side_lists();
+      HIPCHK(hipEventRecord(c.ev_lists, ss));
+      do_near(ss);
+      do_upward();
+      HIPCHK(hipStreamWaitEvent(s, c.ev_lists, 0));
+      do_downward();
+      signal(c.ev_join, ss, s);
+      do_finalize();
     });
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -865,8 +903,8 @@ void pp_destroy(pp_ctx* c) {
   for (auto& g : c->seg) drop_graph(g);
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
-  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  for (hipEvent_t e : {c->ev_fork, c->ev_lists, c->ev_join})
+    if (e) (void)hipEventDestroy(e);
   for (int i = 0; i < B_COUNT; ++i) release(*c, i);
   for (int i = 0; i < 13; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);

@@ -317,11 +317,12 @@ def test_list_modes_agree_bitwise(solver, monkeypatch):
         assert np.array_equal(got, ref) and np.array_equal(again, ref), env
 
 
-def test_graph_replay_matches_eager(monkeypatch):
+@pytest.mark.parametrize("near_stream", ["1", "0"])
+def test_graph_replay_matches_eager(monkeypatch, near_stream):
     """Repeated solves on device inputs replay captured graphs (same shape and pointers; the second segment
     also needs the same tree).  Every call, with eager device work and synchronisations in between and with
     the source changed in place (same and different zero pattern), equals a context without replay bit for
-    bit."""
+    bit; with the near field on its own stream (forked and joined inside the graphs) and without."""
     import torch
     import paper_1610_04398_amd as pp
     n = 128
@@ -335,7 +336,9 @@ def test_graph_replay_matches_eager(monkeypatch):
     monkeypatch.setenv("PP_GRAPHS", "0")
     eager = pp.Solver(0)
     monkeypatch.delenv("PP_GRAPHS")
+    monkeypatch.setenv("PP_NEAR_STREAM", near_stream)
     fast = pp.Solver(0)
+    monkeypatch.delenv("PP_NEAR_STREAM")
     kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed")
     try:
         for it in range(10):
