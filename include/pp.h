@@ -268,8 +268,8 @@ enum {
   PP_ARR_MULTIPOLE = 20,  /* double, per cell (p+1) complex: scaled a'_k = a_k / s^k */
   PP_ARR_LOCAL = 21,      /* double, per cell (p+1) complex: scaled L'_l = L_l s^l (not in the tree-code) */
   PP_ARR_FAR = 22,        /* double per sorted target: the far field times 2pi (L2P, or the M2P sum) */
-  PP_ARR_NEAR = 23,       /* double [parts][sorted target]: partial sums over near sources of w ln(r^2/h^2) */
-  PP_ARR_LEAF_WNEAR = 24, /* double [parts][cell]: partial sums of w over a target leaf's near sources */
+  PP_ARR_NEAR = 23,       /* double [parts][sorted target]: partial sums over near sources of w ln r */
+  PP_ARR_LEAF_WNEAR = 24, /* not stored (the near weights are folded into PP_ARR_NEAR): PP_ERR_ARG */
   PP_ARR_TGT_LEAF = 25    /* leaf cell of each sorted target */
 };
 pp_status pp_debug_copy(const pp_ctx* ctx, int32_t what, void* dst, int64_t capacity, int64_t* length);

@@ -99,13 +99,15 @@ void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, con
                       const int* perm, double x0, double y0, double u, const double* xs, const double* ys,
                       const double* ws, float2* rel32, double2* rel64, int* tleaf, double* self_w, hipStream_t s);
 // Per target leaf: offsets relative to the leaf corner (FP32 and FP64, in units
-// of h), owning leaf, and the coincident-node information for the self rule.
+// of h), owning leaf, and for the self rule the weight f h^2 of the node the
+// target coincides with (0 for none) and the log of its distance (-inf: exact).
 // A target at squared distance d2 from its nearest node with d2 == 0 or
 // d2 < snap_frac2 h^2 is snapped onto the node (its exact term is restored by
 // the finalize step); FP32 near fields use snap_frac2 = 2^-40, FP64 ones 0.
 void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
                        const int* perm, double x0, double y0, double h, int nx, int ny, double snap_frac2,
-                       float2* rel32, double2* rel64, int* tleaf, int* self_idx, double* self_logd, hipStream_t s);
+                       const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w, double* self_logd,
+                       hipStream_t s);
 
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p
@@ -177,14 +179,14 @@ struct P2PArgs {
   long long* pair_counts;     // per wave: (target, source) pairs evaluated (may be null)
   int* flags;                 // error flags (kFlagBadIndex for a list entry outside the tree)
   unsigned long long* pairs;  // if set with pair_counts, receives their sum
-  double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r^2 / h^2)
-  double* leaf_wnear;   // [nparts][ncells]: per target leaf, sum of the near sources' weights
+  double lnh;           // ln of the grid spacing (the unit of the offsets)
+  double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r) over the part's near sources
 };
 void p2p(const P2PArgs& a, int fp64, hipStream_t s);
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.
-// near_sum and leaf_wnear hold nparts partial sums (strides m and ncells).
+// near_sum holds nparts partial sums (stride m).
 // Statistics summed by the finalize launch into zeroed slots: the per-wave pair
 // counts (pair_counts[0..nwaves) into *pairs, if pairs is set) and the per-cell list
 // lengths (cnt_m/cnt_p[0..ncells) into *tot_m/*tot_p, if cnt_m is set).
@@ -198,11 +200,11 @@ struct FinalizeTotals {
   int* tot_m = nullptr;
   int* tot_p = nullptr;
 };
-// self_idx/self_logd: grid-node coincidence (may be null); self_w: per target
-// the weight of exactly coincident scattered sources (may be null).
-void finalize(int64_t m, int ncells, int nparts, const int* perm, const int* tleaf, const double* far,
-              const double* near_sum, const double* leaf_wnear, const int* self_idx, const double* self_logd,
-              const double* self_w, const double* f, double h, int self_mode, const int* flags, double* out,
+// self_w (may be null): per target the weight of the source it coincides with
+// (grid node or scattered sources), 0 for none; self_logd (may be null: exact
+// coincidence throughout) the log of the distance to that node, -inf if exact.
+void finalize(int64_t m, int nparts, const int* perm, const double* far, const double* near_sum,
+              const double* self_w, const double* self_logd, double h, int self_mode, const int* flags, double* out,
               const FinalizeTotals& tot, hipStream_t s);
 
 // ---- forces.hip: pressure forces on surfaces -----------------------------------------

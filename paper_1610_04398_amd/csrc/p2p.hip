@@ -13,8 +13,9 @@
 // corner (exact half-integers for grid nodes), targets relative to their leaf
 // corner, shifted per source leaf by the integer corner difference.  This keeps
 // FP32 positions accurate to ~1e-6 h however large the grid.  The kernel sums
-// w log2(r^2 / h^2); the finalize step adds ln(h) times the near weight and the
-// factor ln 2 / 2.
+// w log2(r^2 / h^2); per target and list part it then stores, in FP64, half
+// that sum times ln 2 plus ln(h) times the part's near weight W = sum w, which
+// is the part's share of sum w ln r.
 //
 // Mixed precision: FP32 with Kahan-compensated accumulation in a fixed order.
 // The pair of a target with a coincident node only occurs inside its own leaf;
@@ -86,9 +87,9 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
 // tleaves[w / nparts] and the list part
 // w % nparts (entries [part * nb / nparts, (part + 1) * nb / nparts)), looping
 // over the leaf's targets 64 at a time.  Partial sums go to
-// near_sum[part * m + k] and leaf_wnear[part * ncells + A] and are added in a
-// fixed order by the finalize step; pair_counts[w] receives the number of
-// (target, source) pairs the wave evaluated.
+// near_sum[part * m + k] and are added in a fixed order by the finalize step;
+// pair_counts[w] receives the number of (target, source) pairs the wave
+// evaluated.
 // The source records come in as a separate __restrict__ argument: with no
 // possible aliasing the compiler keeps their wave-uniform loads on the scalar
 // path although the kernel stores partial sums between chunks.
@@ -136,8 +137,7 @@ __global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_e
       else
         p2p32_leaf<false>(src4, s0, s1, tx, ty, sum, comp);
     }
-    if (active) a.near_sum[(int64_t)part * a.m + k] = ((double)sum - (double)comp) * kLn2;
-    if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
+    if (active) a.near_sum[(int64_t)part * a.m + k] = 0.5 * (((double)sum - (double)comp) * kLn2) + a.lnh * wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
   }
   if (lane == 0 && a.pair_counts) a.pair_counts[wid] = pairs;
@@ -212,8 +212,7 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
       else
         p2p64_leaf<false>(src4, s64, w64, s0, s1, tx, ty, sum);
     }
-    if (active) a.near_sum[(int64_t)part * a.m + k] = sum;
-    if (lane == 0 && chunk == tb) a.leaf_wnear[(int64_t)part * t.ncells + A] = wn;
+    if (active) a.near_sum[(int64_t)part * a.m + k] = 0.5 * sum + a.lnh * wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
   }
   if (lane == 0 && a.pair_counts) a.pair_counts[wid] = pairs;

@@ -41,7 +41,7 @@ enum BufId {
   B_F, B_TX, B_TY, B_OUT, B_MISC, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
   B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
-  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFI, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_WNEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
+  B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
   B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
   B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY,
@@ -521,9 +521,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   float2* rel32 = ensure<float2>(c, B_REL32, m);
   double2* rel64 = ensure<double2>(c, B_REL64, m);
   int* tgtleaf = ensure<int>(c, B_TGTLEAF, m);
-  int* selfi = src.grid ? ensure<int>(c, B_SELFI, m) : nullptr;
   double* selfd = src.grid ? ensure<double>(c, B_SELFD, m) : nullptr;
-  double* selfw = src.grid ? nullptr : ensure<double>(c, B_SELFW, m);
+  double* selfw = ensure<double>(c, B_SELFW, m);
   double2* s64 = src.grid ? nullptr : ensure<double2>(c, B_S64, N);
   double2* mp = direct ? nullptr : ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
   double2* loc = (direct || treecode) ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
@@ -531,7 +530,6 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   double* far = direct ? nullptr : ensure<double>(c, B_FAR, m);
   const int nparts = c.p2p_parts;
   double* near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
-  double* wnear = ensure<double>(c, B_WNEAR, (int64_t)nparts * ncells);
   long long* pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
   P2PArgs pa{};
   pa.t = tv;
@@ -553,7 +551,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   pa.flags = misc + M_FLAGS;
   pa.pairs = pairs;
   pa.near_sum = near;
-  pa.leaf_wnear = wnear;
+  pa.lnh = std::log(unit);
   pa.list_src = direct ? nullptr : p2p_src;  // set again below once exact lists are allocated
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
@@ -625,8 +623,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   };
   auto do_prep_targets = [&](hipStream_t q) {
     if (src.grid)
-      leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, rel32,
-                        rel64, tgtleaf, selfi, selfd, q);
+      leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d,
+                        rel32, rel64, tgtleaf, selfw, selfd, q);
     else
       leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf,
                        selfw, q);
@@ -677,8 +675,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     tot.ncells = ncells;
     tot.tot_m = misc + M_NM2L;
     tot.tot_p = misc + M_NP2P;
-    finalize(m, ncells, nparts, tperm, tgtleaf, far, near, wnear, selfi, selfd, selfw, f_d, unit, prm.self_mode,
-             misc + M_FLAGS, out_d, tot, s);
+    finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, s);
     mark(12);
     readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
   };
@@ -1137,7 +1134,6 @@ pp_status pp_debug_copy(const pp_ctx* cc, int32_t what, void* dst, int64_t capac
     case PP_ARR_LOCAL: id = L.has_locals ? B_LOC : -1; n = (int64_t)L.ncells * (L.p + 1) * 2; esz = 8; break;
     case PP_ARR_FAR: id = L.has_expansions ? B_FAR : -1; n = L.m; esz = 8; break;
     case PP_ARR_NEAR: id = B_NEAR; n = L.m * L.nparts; esz = 8; break;
-    case PP_ARR_LEAF_WNEAR: id = B_WNEAR; n = (int64_t)L.ncells * L.nparts; esz = 8; break;
     case PP_ARR_TGT_LEAF: id = B_TGTLEAF; n = L.m; break;
     default: c->err = "unknown array id"; return PP_ERR_ARG;
   }

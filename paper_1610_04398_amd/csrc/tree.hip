@@ -319,9 +319,9 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
                                                        const double* __restrict__ tx, const double* __restrict__ ty,
                                                        const int* __restrict__ perm, double x0, double y0, double h,
                                                        int nx, int ny, double snap_frac2,
-                                                       float2* __restrict__ rel32, double2* __restrict__ rel64,
-                                                       int* __restrict__ tleaf, int* __restrict__ self_idx,
-                                                       double* __restrict__ self_logd) {
+                                                       const double* __restrict__ f, float2* __restrict__ rel32,
+                                                       double2* __restrict__ rel64, int* __restrict__ tleaf,
+                                                       double* __restrict__ self_w, double* __restrict__ self_logd) {
 #pragma clang fp contract(off)
   const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (wid >= n) return;
@@ -341,14 +341,13 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
     const double fx = floor(ux), fy = floor(uy);
     const bool inside = fx >= 0.0 && fy >= 0.0 && fx < 65536.0 && fy < 65536.0;
     const int i = inside ? (int)fx : -1, j = inside ? (int)fy : -1;
-    int sidx = -1;
-    double lg = 0.0;
+    double sw = 0.0, lg = 0.0;
     if (i >= 0 && j >= 0 && i < nx && j < ny) {
       const double dx = x - node_coord(x0, i, h);
       const double dy = y - node_coord(y0, j, h);
       const double d2 = dx * dx + dy * dy;
       if (d2 == 0.0 || d2 < snap2) {
-        sidx = j * nx + i;
+        sw = f[(int64_t)j * nx + i] * (h * h);
         lg = (d2 == 0.0) ? -INFINITY : 0.5 * log(d2);
         rx = ((double)i + 0.5) - cx;
         ry = ((double)j + 0.5) - cy;
@@ -357,7 +356,7 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
     rel64[k] = make_double2(rx, ry);
     rel32[k] = make_float2((float)rx, (float)ry);
     tleaf[k] = c;
-    self_idx[k] = sidx;
+    self_w[k] = sw;
     self_logd[k] = lg;
   }
 }
@@ -413,10 +412,11 @@ void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, co
 
 void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
                        const int* perm, double x0, double y0, double h, int nx, int ny, double snap_frac2,
-                       float2* rel32, double2* rel64, int* tleaf, int* self_idx, double* self_logd, hipStream_t s) {
+                       const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
+                       double* self_logd, hipStream_t s) {
   if (ntleaves <= 0) return;
   k_prep_targets<<<(ntleaves + 3) / 4, 256, 0, s>>>(t, tleaves, ntleaves, D, tx, ty, perm, x0, y0, h, nx, ny,
-                                                     snap_frac2, rel32, rel64, tleaf, self_idx, self_logd);
+                                                     snap_frac2, f, rel32, rel64, tleaf, self_w, self_logd);
 }
 
 }  // namespace pp
