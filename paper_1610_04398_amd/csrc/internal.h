@@ -19,6 +19,11 @@ void scan_exclusive(const int* in, int* out, int64_t n, int* temp, int* total_de
 void scan_exclusive_dev(const int* in, int* out, const int* n_dev, int64_t max_n, int* temp, int* total_dev,
                         hipStream_t s);
 void fill_i32(int* p, int v, int64_t n, hipStream_t s);
+// Copies src[0..count) (count <= 256) into host-visible coherent memory `mail`,
+// then increments the device counter *ctr and stores its new value into
+// mail[seq_slot] after a system-scope fence: the host spins on that slot
+// instead of synchronising the stream.
+void publish(const int* src, int count, int* ctr, int* mail, int seq_slot, hipStream_t s);
 
 // ---- ingest.hip: sources in Morton order, target keys ------------------------------
 // Morton tiles of 1024 indices cover [0, 4^k).

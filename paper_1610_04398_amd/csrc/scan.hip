@@ -116,7 +116,30 @@ __global__ void k_fill_i32(int* __restrict__ p, int v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+
+constexpr int kPublishBlock = 256;
+
+// One workgroup: lane i copies src[i] to the host mailbox, then (after a
+// system-scope fence and a barrier) lane 0 advances the device counter and
+// stores its new value into mail[seq_slot] with release semantics.
+__global__ __launch_bounds__(kPublishBlock) void k_publish(const int* __restrict__ src, int count,
+                                                           int* __restrict__ ctr, int* mail, int seq_slot) {
+  const int i = threadIdx.x;
+  if (i < count) mail[i] = src[i];
+  __threadfence_system();
+  __syncthreads();
+  if (i == 0) {
+    const int v = *ctr + 1;
+    *ctr = v;
+    __hip_atomic_store(mail + seq_slot, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
 }  // namespace
+
+void publish(const int* src, int count, int* ctr, int* mail, int seq_slot, hipStream_t s) {
+  if (count < 0 || count > kPublishBlock) count = kPublishBlock;
+  k_publish<<<1, kPublishBlock, 0, s>>>(src, count, ctr, mail, seq_slot);
+}
 
 void fill_i32(int* p, int v, int64_t n, hipStream_t s) {
   if (n <= 0) return;

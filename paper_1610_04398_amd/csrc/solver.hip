@@ -65,6 +65,8 @@ struct Last {
 };
 
 constexpr int kMiscInts = 128;
+constexpr int kMailExtra = 32;
+constexpr int kSeqSlot = kMiscInts;
 // misc layout: [0] flags, [1] source count, [2] scratch total, [3] level work items,
 // [4..9] cell-list and interaction-list totals, [16..17] near-field pair count (u64),
 // [32..32+D+2] level starts of the tree, [96..103] bounding box of scattered input (4 doubles).
@@ -111,7 +113,11 @@ struct pp_ctx {
   uint64_t budget = 0;
   size_t held = 0;
   DevBuf bufs[B_COUNT];
-  int* pinned = nullptr;  // kMiscInts ints of pinned host memory for read-backs
+  // kMiscInts + kMailExtra ints of coherent pinned host memory for read-backs;
+  // slot kSeqSlot receives the sequence number of the last published read-back
+  int* pinned = nullptr;
+  int* pub_ctr = nullptr;  // device counter of published read-backs
+  hipStream_t cur_stream = nullptr;  // the running call's stream (drained after a failure)
   std::string err;
   bool dead = false;
   Last last;
@@ -176,6 +182,39 @@ const T* stage_in(pp_ctx& c, int id, const T* src, int64_t n, hipStream_t s) {
 
 void readback_enqueue(pp_ctx& c, const int* dev, int first, int count, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(c.pinned + first, dev + first, (size_t)count * sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+// Read-back of misc[0..count) at the end of a segment: a kernel writes the
+// values into the coherent pinned buffer and then a sequence number, and the
+// host spins on that number (a few microseconds sooner than a stream
+// synchronisation).  published_seq() before the segment is enqueued gives the
+// number to wait for (one more); every earlier read-back has been waited for.
+int published_seq(const pp_ctx& c) { return __atomic_load_n(c.pinned + kSeqSlot, __ATOMIC_ACQUIRE); }
+
+void publish_enqueue(pp_ctx& c, const int* misc, int count, hipStream_t s) {
+  publish(misc, count, c.pub_ctr, c.pinned, kSeqSlot, s);
+}
+
+// Spins until read-back `expect` has arrived.  After 2 ms it also asks the
+// stream every 0.2 ms: an error is reported, and a stream that finished without
+// the number arriving is a device error, so the wait always ends when the
+// stream does.
+void wait_published(pp_ctx& c, hipStream_t s, int expect) {
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto next = t0 + std::chrono::milliseconds(2);
+  for (uint64_t n = 1;; ++n) {
+    if (published_seq(c) == expect) return;
+    if ((n & 255) == 0 && clk::now() >= next) {
+      next = clk::now() + std::chrono::microseconds(200);
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipErrorNotReady) continue;
+      HIPCHK(e);
+      if (published_seq(c) == expect) return;
+      throw PPError{PP_ERR_DEVICE, "a read-back did not arrive"};
+    }
+    __builtin_ia32_pause();
+  }
 }
 
 void readback(pp_ctx& c, const int* dev, int first, int count, hipStream_t s) {
@@ -330,6 +369,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     if (!c.own_stream) HIPCHK(hipStreamCreate(&c.own_stream));  // blocking, default priority
     s = c.own_stream;
   }
+  c.cur_stream = s;
   c.last.valid = false;
   const int32_t nx = src.grid ? src.nx : 0, ny = src.grid ? src.ny : 0;
   const int64_t ngrid = src.grid ? (int64_t)nx * ny : 0;
@@ -451,6 +491,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
                                       (uint64_t)lm, (uint64_t)c.dense_levels, (uint64_t)c.profiling, bits(f_d),
                                       bits(tx_d), bits(ty_d)};
+  const int seq1 = published_seq(c) + 1;
   run_segment(c, 0, replayable, key1, s, [&] {
     mark(PP_PHASE_INGEST);
     if (src.grid) fill_i32(misc, 0, kMiscInts, s);  // scattered input: cleared before its bounding box
@@ -482,9 +523,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // cell lists over the whole tree (its size is the last level start, on the device)
     classify_cells(ta, ls_d + D + 1, (int)cap, flag3, off3, scan, misc + M_TOT, misc + M_N4, sleaves, tleaves, tcells,
                    misc + M_NSL, s);
-    readback_enqueue(c, misc, 0, M_LS + D + 2, s);
+    publish_enqueue(c, misc, M_LS + D + 2, s);
   });
-  HIPCHK(hipStreamSynchronize(s));
+  wait_published(c, s, seq1);
   check_flags(c.pinned[M_FLAGS]);
   const int64_t N = c.pinned[M_NSRC];
   const int* ls_h = c.pinned + M_LS;
@@ -677,7 +718,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     tot.tot_p = misc + M_NP2P;
     finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, s);
     mark(12);
-    readback_enqueue(c, misc, 0, M_PAIRS + 2, s);
+    publish_enqueue(c, misc, M_PAIRS + 2, s);
   };
   // side-stream part before the near field
   auto side_lists = [&] {
@@ -685,6 +726,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     do_prep_targets(ss);
   };
 
+  const int seq2 = published_seq(c) + 1;
   if (c.profiling == 2) {
     // The near field launched outside the replayed segments, bracketed by events
     // on its own stream: the work it depends on (packing, lists) is replayed
@@ -741,12 +783,16 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       do_finalize();
     });
   }
-  HIPCHK(hipStreamSynchronize(s));
+  wait_published(c, s, seq2);
   const int flags = c.pinned[M_FLAGS];
-  if (flags & kFlagListOverflow) return PP_ERR_LIMIT;  // nothing written; repeat with exact lists
+  if (flags & kFlagListOverflow) {  // nothing written; repeat with exact lists
+    c.cur_stream = nullptr;
+    return PP_ERR_LIMIT;
+  }
   check_flags(flags);
   for (int i = 0; i < 12; ++i) c.stats.ms_phase[i] = 0.0;
   if (c.profiling == 1) {
+    HIPCHK(hipEventSynchronize(c.ev[12]));
     for (int i = 0; i < 12; ++i) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, c.ev[i], c.ev[i + 1]));
@@ -754,6 +800,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     }
   } else if (c.profiling == 2) {
     float ms = 0.f;
+    HIPCHK(hipEventSynchronize(c.ev[PP_PHASE_FINALIZE]));
     HIPCHK(hipEventElapsedTime(&ms, c.ev[PP_PHASE_P2P], c.ev[PP_PHASE_FINALIZE]));
     c.stats.ms_phase[PP_PHASE_P2P] = ms;
   }
@@ -789,6 +836,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.last.has_expansions = !direct;
   c.last.has_locals = !direct && !treecode;
   c.last.nparts = nparts;
+  c.cur_stream = nullptr;
   return PP_OK;
 }
 
@@ -886,7 +934,17 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
     }
   }
   c->budget = hbm_budget_bytes;
-  if (hipHostMalloc((void**)&c->pinned, kMiscInts * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->pinned, (kMiscInts + kMailExtra) * sizeof(int), hipHostMallocCoherent) !=
+      hipSuccess) {
+    delete c;
+    return PP_ERR_DEVICE;
+  }
+  std::memset(c->pinned, 0, (kMiscInts + kMailExtra) * sizeof(int));
+  const int zeros[64] = {};
+  if (hipMalloc((void**)&c->pub_ctr, sizeof(zeros)) != hipSuccess ||
+      hipMemcpy(c->pub_ctr, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess) {
+    if (c->pub_ctr) (void)hipFree(c->pub_ctr);
+    (void)hipHostFree(c->pinned);
     delete c;
     return PP_ERR_DEVICE;
   }
@@ -906,6 +964,7 @@ void pp_destroy(pp_ctx* c) {
   for (int i = 0; i < 13; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pub_ctr) (void)hipFree(c->pub_ctr);
   delete c;
 }
 
@@ -968,6 +1027,8 @@ void run_force_kernel(pp_ctx& c, int64_t m, int32_t nseg, const int64_t* seg_sta
 // launch may still use the context's buffers.
 void drain_side(pp_ctx* c) {
   if (c->side_stream) (void)hipStreamSynchronize(c->side_stream);
+  if (c->cur_stream) (void)hipStreamSynchronize(c->cur_stream);
+  c->cur_stream = nullptr;
 }
 
 template <class Body>
