@@ -24,6 +24,9 @@ void fill_i32(int* p, int v, int64_t n, hipStream_t s);
 // mail[seq_slot] after a system-scope fence: the host spins on that slot
 // instead of synchronising the stream.
 void publish(const int* src, int count, int* ctr, int* mail, int seq_slot, hipStream_t s);
+// Whether the context runs the near field on a second stream beside the
+// expansions (on by default; the server turns it off when it runs several slots).
+void ctx_set_near_stream(pp_ctx* c, bool on);
 
 // ---- ingest.hip: sources in Morton order, target keys ------------------------------
 // Morton tiles of 1024 indices cover [0, 4^k).

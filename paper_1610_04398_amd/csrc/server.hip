@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/pp.h"
+#include "internal.h"
 
 namespace {
 
@@ -151,6 +152,7 @@ void worker_loop(pp_server* s, int slot) {
       pp_destroy(ctx);
       ctx = nullptr;
       if (pp_create(s->cfg.device, 0, &ctx) != PP_OK) return;
+      if (s->cfg.max_slots > 1) pp::ctx_set_near_stream(ctx, false);
       s->ctxs[slot] = ctx;
     }
   }
@@ -179,6 +181,10 @@ pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out) {
       delete s;
       return PP_ERR_DEVICE;
     }
+    // with several slots the concurrency comes from the requests: each slot keeps
+    // its whole solve on its own stream (a second stream per slot only adds
+    // contention for the hardware queues)
+    if (cfg->max_slots > 1) pp::ctx_set_near_stream(c, false);
     s->ctxs.push_back(c);
     s->streams.push_back(st);
   }

@@ -195,18 +195,19 @@ void publish_enqueue(pp_ctx& c, const int* misc, int count, hipStream_t s) {
   publish(misc, count, c.pub_ctr, c.pinned, kSeqSlot, s);
 }
 
-// Spins until read-back `expect` has arrived.  After 2 ms it also asks the
-// stream every 0.2 ms: an error is reported, and a stream that finished without
-// the number arriving is a device error, so the wait always ends when the
-// stream does.
+// Spins until read-back `expect` has arrived.  After 20 ms it also asks the
+// stream every 2 ms (rarely: a query takes the runtime's locks, which other
+// threads launching work need): an error is reported, and a stream that
+// finished without the number arriving is a device error, so the wait always
+// ends when the stream does.
 void wait_published(pp_ctx& c, hipStream_t s, int expect) {
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
-  auto next = t0 + std::chrono::milliseconds(2);
+  auto next = t0 + std::chrono::milliseconds(20);
   for (uint64_t n = 1;; ++n) {
     if (published_seq(c) == expect) return;
     if ((n & 255) == 0 && clk::now() >= next) {
-      next = clk::now() + std::chrono::microseconds(200);
+      next = clk::now() + std::chrono::milliseconds(2);
       const hipError_t e = hipStreamQuery(s);
       if (e == hipErrorNotReady) continue;
       HIPCHK(e);
@@ -1022,6 +1023,14 @@ void run_force_kernel(pp_ctx& c, int64_t m, int32_t nseg, const int64_t* seg_sta
   if (!out_dev) HIPCHK(hipMemcpyAsync(out, out_d, (size_t)nseg * sizeof(pp_force), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
 }
+
+}  // namespace
+
+void pp::ctx_set_near_stream(pp_ctx* c, bool on) {
+  if (c) c->near_stream = on;
+}
+
+namespace {
 
 // A call that failed after forking the near field must not return while that
 // launch may still use the context's buffers.
