@@ -745,14 +745,17 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       if (!lists_early) do_lists(s);
       do_prep_targets(s);
     });
-    signal(c.ev_fork, s, ss);
-    HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
-    do_near(ss);
-    HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
+    // the expansions are enqueued before the near field so that their first
+    // launches find the compute units free
+    if (ss != s) HIPCHK(hipEventRecord(c.ev_fork, s));
     run_segment(c, 2, replayable, key(2), s, [&] {
       do_upward();
       do_downward();
     });
+    if (ss != s) HIPCHK(hipStreamWaitEvent(ss, c.ev_fork, 0));
+    HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
+    do_near(ss);
+    HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
     signal(c.ev_join, ss, s);
     run_segment(c, 3, replayable, key(3), s, do_finalize);
   } else if (ss == s) {
