@@ -186,7 +186,11 @@ __device__ inline cplx m2m_coeff(int l, int nk, const double2* __restrict__ e, i
 // it and the leaves inside it) is staged into LDS in one parallel sweep, so
 // the arithmetic never waits on a global load.  Leaves keep their P2M
 // expansions.
-constexpr int kM2MThreads = 1024;  // one workgroup per CU fits the LDS at p <= 12: its waves hide the latency
+// 512 threads: a workgroup of 8 waves finds room on a compute unit as soon as
+// two near-field workgroups (4 waves each) leave it, when the near field runs
+// beside the upward pass on another stream; 1024-thread workgroups waited far
+// longer for a whole free half of a compute unit.
+constexpr int kM2MThreads = 512;
 constexpr int kM2MLevels = 4;
 constexpr int kM2MSlots = 341;  // 1 + 4 + 16 + 64 + 256
 __host__ __device__ constexpr int m2m_first(int d) { return ((1 << (2 * d)) - 1) / 3; }
