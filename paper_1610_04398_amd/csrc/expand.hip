@@ -56,11 +56,16 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
 
 // P2M: 16 lanes per source leaf (four leaves per wave); lanes stride over the
 // leaf's sources and a fixed-order butterfly over the 16 lanes sums the
-// per-lane powers.
+// per-lane powers.  The source offsets from the leaf corner (units of the
+// finest cell) are formed here from the ordered sources, as the packing step
+// forms them for the near field, so P2M does not wait for that step: grid
+// nodes from their packed index (exact half-integers), scattered sources from
+// their FP64 coordinates.
 constexpr int kP2MLanes = 16;
 template <int PM>
 __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
-                                             const float4* __restrict__ src4, const double2* __restrict__ s64,
+                                             const uint32_t* __restrict__ ij, const double* __restrict__ xs,
+                                             const double* __restrict__ ys, double x0, double y0, double u,
                                              const double* __restrict__ w64, int p, double2* __restrict__ mp) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int li = (int)(gtid / kP2MLanes);
@@ -69,20 +74,21 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
   const int c = sleaves[li];
   const double side = cell_side(t.D, t.lvl[c]);
   const double inv = 1.0 / side;
+  const int sh = t.D - t.lvl[c];
+  const int cxi = t.ix[c] << sh, cyi = t.iy[c] << sh;
   cplx acc[PM + 1];
 #pragma unroll
   for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
   const int sb = t.sb[c], se = t.se[c];
   for (int s = sb + sub; s < se; s += kP2MLanes) {
     double ox, oy;
-    if (s64) {
-      const double2 o = s64[s];
-      ox = o.x;
-      oy = o.y;
+    if (ij) {
+      const uint32_t v = ij[s];
+      ox = (double)((int)(v & 0xFFFFu) - cxi) + 0.5;
+      oy = (double)((int)(v >> 16) - cyi) + 0.5;
     } else {
-      const float4 q = src4[s];
-      ox = (double)q.x;
-      oy = (double)q.y;
+      ox = (xs[s] - x0) / u - (double)cxi;
+      oy = (ys[s] - y0) / u - (double)cyi;
     }
     const double w = w64[s];
     const cplx z = {ox * inv - 0.5, oy * inv - 0.5};
@@ -565,11 +571,11 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
 
 }  // namespace
 
-void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double2* s64, const double* w64, int p,
-         double2* mp, hipStream_t s) {
+void p2m(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys, double x0,
+         double y0, double u, const double* w64, int p, double2* mp, hipStream_t s) {
   if (n <= 0) return;
   const unsigned g = (unsigned)(((int64_t)n * kP2MLanes + 255) / 256);
-  PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, src4, s64, w64, p, mp);
+  PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
 }
 
 int m2m_max_levels() { return kM2MLevels; }

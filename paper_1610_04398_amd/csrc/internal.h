@@ -137,11 +137,12 @@ void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
                 int* flags, hipStream_t s);
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
-// P2M of every source leaf (one wave per leaf).
-// s64 (may be null): FP64 source offsets; without it the FP32 offsets of src4
-// are used (exact for grid nodes).
-void p2m(TreeView t, const int* sleaves, int n, const float4* src4, const double2* s64, const double* w64, int p,
-         double2* mp, hipStream_t s);
+// P2M of every source leaf (16 lanes per leaf), from the ordered sources: grid
+// nodes by their packed index ij (i | j << 16), or (ij null) scattered sources
+// by their coordinates xs, ys in a root square anchored at (x0, y0) with
+// finest cell side u.
+void p2m(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys, double x0,
+         double y0, double u, const double* w64, int p, double2* mp, hipStream_t s);
 // M2M for the `levels` (1..m2m_max_levels()) levels starting at the level
 // whose cells are [c0, c1): one workgroup per cell computes its subtree
 // bottom up.

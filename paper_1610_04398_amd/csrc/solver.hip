@@ -105,10 +105,10 @@ struct pp_ctx {
     int seen = 0;
     hipGraphExec_t exec = nullptr;
   };
-  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, the work
-  // before the near field); in timing mode 2 also 2: the expansions after it,
-  // 3: the finalize step
-  static constexpr int kSegments = 4;
+  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, packing,
+  // lists and target preparation on the side stream); in timing mode 2 also
+  // 2: the upward pass, 3: M2L and the downward pass, 4: the finalize step
+  static constexpr int kSegments = 5;
   Segment seg[kSegments];
   uint64_t budget = 0;
   size_t held = 0;
@@ -657,11 +657,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     }
     pa.list_src = p2p_src;
   };
-  auto do_pack_sources = [&] {
+  auto do_pack_sources = [&](hipStream_t q) {
     if (src.grid)
-      leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, s);
+      leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, q);
     else
-      leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, s);
+      leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, q);
   };
   auto do_prep_targets = [&](hipStream_t q) {
     if (src.grid)
@@ -677,7 +677,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       mark(PP_PHASE_M2M);
       return;
     }
-    p2m(tv, sleaves, nsl, src4, s64, sw, p, mp, s);
+    p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, s);
     mark(PP_PHASE_M2M);
     // the recursion from the finest level up, several levels per launch
     const int ml = m2m_max_levels();
@@ -729,42 +729,38 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   const int seq2 = published_seq(c) + 1;
   if (c.profiling == 2) {
-    // The near field launched outside the replayed segments, bracketed by events
-    // on its own stream: the work it depends on (packing, lists) is replayed
-    // first, then it runs beside the replayed upward and downward passes.  (The
-    // lists then no longer overlap the upward pass; otherwise the schedule is
-    // that of an untimed call.)
+    // The schedule of an untimed call with the near field launched outside the
+    // replayed segments, bracketed by events on its own stream.  Segment 1 is
+    // complete (the host has seen its read-back), so the side stream starts
+    // without waiting on s: its replayed packing, lists and target preparation,
+    // then the near field.  The upward pass runs meanwhile on s, which then
+    // waits for the lists (M2L, L2L, L2P) and for the near field (finalize).
     auto key = [&](uint64_t i) {
       std::vector<uint64_t> k = key2;
       k.push_back(i);
       return k;
     };
     if (lists_early) do_lists(s);
-    run_segment(c, 1, replayable, key(1), s, [&] {
-      do_pack_sources();
-      if (!lists_early) do_lists(s);
-      do_prep_targets(s);
+    run_segment(c, 1, replayable, key(1), ss, [&] {
+      do_pack_sources(ss);
+      side_lists();
     });
-    // the expansions are enqueued before the near field so that their first
-    // launches find the compute units free
-    if (ss != s) HIPCHK(hipEventRecord(c.ev_fork, s));
-    run_segment(c, 2, replayable, key(2), s, [&] {
-      do_upward();
-      do_downward();
-    });
-    if (ss != s) HIPCHK(hipStreamWaitEvent(ss, c.ev_fork, 0));
+    if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
     do_near(ss);
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
+    run_segment(c, 2, replayable, key(2), s, do_upward);
+    if (ss != s) HIPCHK(hipStreamWaitEvent(s, c.ev_lists, 0));
+    run_segment(c, 3, replayable, key(3), s, do_downward);
     signal(c.ev_join, ss, s);
-    run_segment(c, 3, replayable, key(3), s, do_finalize);
+    run_segment(c, 4, replayable, key(4), s, do_finalize);
   } else if (ss == s) {
     // one stream, phases in order (timing mode 1, or the side stream disabled)
     run_segment(c, 1, replayable, key2, s, [&] {
       mark(PP_PHASE_LISTS);
       do_lists(s);
       mark(PP_PHASE_PACK);
-      do_pack_sources();
+      do_pack_sources(s);
       do_prep_targets(s);
       do_upward();
       do_downward();
@@ -775,7 +771,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   } else {
     if (lists_early) do_lists(s);
     run_segment(c, 1, replayable, key2, s, [&] {
-      do_pack_sources();
+      do_pack_sources(s);
       signal(c.ev_fork, s, ss);
       side_lists();
       HIPCHK(hipEventRecord(c.ev_lists, ss));
