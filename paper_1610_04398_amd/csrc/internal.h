@@ -94,15 +94,16 @@ void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, in
                     int* total_slot, int* n3_slot, int* sleaves, int* tleaves, int* tcells, int* counts,
                     hipStream_t s);
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
-// cell units, and the FP64 leaf weight.
+// cell units, as three planes (x at s32[s], y at s32[stride + s], w at
+// s32[2 stride + s]), and the FP64 leaf weight.
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
-                       float4* src4, double* leaf_w, hipStream_t s);
+                       float* s32, int64_t stride, double* leaf_w, hipStream_t s);
 // Scattered-source counterparts: FP32 records and FP64 offsets (units of u)
 // per source leaf; per target leaf the offsets, owning leaf, and the weight of
 // the sources that coincide exactly with the target.
 void leaf_pack_points(TreeArrays t, const int* sleaves, int nsleaves, int D, const double* xs, const double* ys,
-                      const double* ws, double x0, double y0, double u, float4* src4, double2* s64, double* leaf_w,
-                      hipStream_t s);
+                      const double* ws, double x0, double y0, double u, float* s32, int64_t stride, double2* s64,
+                      double* leaf_w, hipStream_t s);
 void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
                       const int* perm, double x0, double y0, double u, const double* xs, const double* ys,
                       const double* ws, float2* rel32, double2* rel64, int* tleaf, double* self_w, hipStream_t s);
@@ -177,8 +178,12 @@ struct P2PArgs {
   const int* list_src;  // source leaf ids
   const int* sleaves;   // all source leaves (direct mode)
   int nsleaves;
-  const float4* src4;
-  const double2* s64;   // FP64 source offsets for the FP64 kernel (null: those of src4, exact for grid nodes)
+  // FP32 source records as three planes of the sorted sources: offsets from the
+  // leaf corner (x, y, units of the finest cell) and weights
+  const float* sx;
+  const float* sy;
+  const float* sw;
+  const double2* s64;   // FP64 source offsets for the FP64 kernel (null: those of sx, sy, exact for grid nodes)
   const double* w64;
   const double* leaf_w;
   const float2* rel32;

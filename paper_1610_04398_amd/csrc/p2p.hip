@@ -37,29 +37,38 @@ __device__ inline void kahan_fold(float y, float& sum, float& comp) {
   sum = tt;
 }
 
-__device__ inline float pair_log2(float tx, float ty, const float4& q, bool guard) {
-  const float dx = tx - q.x;
-  const float dy = ty - q.y;
+__device__ inline float pair_log2(float tx, float ty, float qx, float qy, bool guard) {
+  const float dx = tx - qx;
+  const float dy = ty - qy;
   float r2 = fmaf(dy, dy, dx * dx);
   if (guard) r2 = (r2 == 0.0f) ? 1.0f : r2;
   return __builtin_amdgcn_logf(r2);  // v_log_f32: log2
 }
 
+// Source planes (offsets x, y and weights w of the sorted sources).
+struct Planes {
+  const float* __restrict__ x;
+  const float* __restrict__ y;
+  const float* __restrict__ w;
+};
+
 // G consecutive sources from s: their terms are summed in order (the first
 // product starts from -comp) and the group is folded into the running sum with
 // Kahan compensation.
 template <int G, bool GUARD>
-__device__ inline void p2p32_group(const float4* __restrict__ src4, int s, float tx, float ty, float& sum,
-                                   float& comp) {
-  float4 q[G];
-  float l[G];
+__device__ inline void p2p32_group(const Planes& q, int s, float tx, float ty, float& sum, float& comp) {
+  float qx[G], qy[G], qw[G], l[G];
 #pragma unroll
-  for (int i = 0; i < G; ++i) q[i] = src4[s + i];
+  for (int i = 0; i < G; ++i) {
+    qx[i] = q.x[s + i];
+    qy[i] = q.y[s + i];
+    qw[i] = q.w[s + i];
+  }
 #pragma unroll
-  for (int i = 0; i < G; ++i) l[i] = pair_log2(tx, ty, q[i], GUARD);
-  float y = fmaf(q[0].z, l[0], -comp);
+  for (int i = 0; i < G; ++i) l[i] = pair_log2(tx, ty, qx[i], qy[i], GUARD);
+  float y = fmaf(qw[0], l[0], -comp);
 #pragma unroll
-  for (int i = 1; i < G; ++i) y = fmaf(q[i].z, l[i], y);
+  for (int i = 1; i < G; ++i) y = fmaf(qw[i], l[i], y);
   kahan_fold(y, sum, comp);
 }
 
@@ -67,19 +76,18 @@ __device__ inline void p2p32_group(const float4* __restrict__ src4, int s, float
 // (3 VALU of compensation per 8 pairs), then the ragged tail as at most one
 // group each of four, two and one.
 template <bool GUARD>
-__device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s1, float tx, float ty, float& sum,
-                                  float& comp) {
+__device__ inline void p2p32_leaf(const Planes& q, int s0, int s1, float tx, float ty, float& sum, float& comp) {
   int s = s0;
-  for (; s + 8 <= s1; s += 8) p2p32_group<8, GUARD>(src4, s, tx, ty, sum, comp);
+  for (; s + 8 <= s1; s += 8) p2p32_group<8, GUARD>(q, s, tx, ty, sum, comp);
   if (s + 4 <= s1) {
-    p2p32_group<4, GUARD>(src4, s, tx, ty, sum, comp);
+    p2p32_group<4, GUARD>(q, s, tx, ty, sum, comp);
     s += 4;
   }
   if (s + 2 <= s1) {
-    p2p32_group<2, GUARD>(src4, s, tx, ty, sum, comp);
+    p2p32_group<2, GUARD>(q, s, tx, ty, sum, comp);
     s += 2;
   }
-  if (s < s1) p2p32_group<1, GUARD>(src4, s, tx, ty, sum, comp);
+  if (s < s1) p2p32_group<1, GUARD>(q, s, tx, ty, sum, comp);
 }
 
 // Work: wave w (workgroups spread over the XCDs in contiguous runs, so an
@@ -90,12 +98,13 @@ __device__ inline void p2p32_leaf(const float4* __restrict__ src4, int s0, int s
 // near_sum[part * m + k] and are added in a fixed order by the finalize step;
 // pair_counts[w] receives the number of (target, source) pairs the wave
 // evaluated.
-// The source records come in as a separate __restrict__ argument: with no
+// The source planes come in as separate __restrict__ arguments: with no
 // possible aliasing the compiler keeps their wave-uniform loads on the scalar
 // path although the kernel stores partial sums between chunks.
 template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_p2p32(
-    P2PArgs a, const float4* __restrict__ src4) {
+    P2PArgs a, const float* __restrict__ sx, const float* __restrict__ sy, const float* __restrict__ sw) {
+  const Planes q{sx, sy, sw};
   // wave-uniform work index (keeps all per-item data in scalar registers)
   const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
                                                     threadIdx.x / kWave);
@@ -133,9 +142,9 @@ __global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_e
       nsrc += s1 - s0;
       wn += a.leaf_w[B];
       if (B == A)
-        p2p32_leaf<true>(src4, s0, s1, tx, ty, sum, comp);
+        p2p32_leaf<true>(q, s0, s1, tx, ty, sum, comp);
       else
-        p2p32_leaf<false>(src4, s0, s1, tx, ty, sum, comp);
+        p2p32_leaf<false>(q, s0, s1, tx, ty, sum, comp);
     }
     if (active) a.near_sum[(int64_t)part * a.m + k] = 0.5 * (((double)sum - (double)comp) * kLn2) + a.lnh * wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
@@ -145,23 +154,23 @@ __global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_e
 }
 
 template <bool GUARD>
-__device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double2* __restrict__ s64,
-                                  const double* __restrict__ w64, int s0, int s1, double tx, double ty, double& sum) {
+__device__ inline void p2p64_leaf(const float* __restrict__ sx, const float* __restrict__ sy,
+                                  const double2* __restrict__ s64, const double* __restrict__ w64, int s0, int s1,
+                                  double tx, double ty, double& sum) {
 #pragma unroll 2
   for (int s = s0; s < s1; ++s) {
-    double sx, sy;
+    double ox, oy;
     if (s64) {
       const double2 o = s64[s];
-      sx = o.x;
-      sy = o.y;
+      ox = o.x;
+      oy = o.y;
     } else {
-      const float4 q = src4[s];
-      sx = (double)q.x;
-      sy = (double)q.y;
+      ox = (double)sx[s];
+      oy = (double)sy[s];
     }
     const double w = w64[s];
-    const double dx = tx - sx;
-    const double dy = ty - sy;
+    const double dx = tx - ox;
+    const double dy = ty - oy;
     const double r2 = fma(dy, dy, dx * dx);
     if (GUARD && r2 == 0.0) continue;
     sum = fma(w, log(r2), sum);
@@ -169,7 +178,8 @@ __device__ inline void p2p64_leaf(const float4* __restrict__ src4, const double2
 }
 
 template <bool DIRECT>
-__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const float4* __restrict__ src4,
+__global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const float* __restrict__ sx,
+                                                             const float* __restrict__ sy,
                                                              const double2* __restrict__ s64,
                                                              const double* __restrict__ w64) {
   const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
@@ -208,9 +218,9 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
       nsrc += s1 - s0;
       wn += a.leaf_w[B];
       if (B == A)
-        p2p64_leaf<true>(src4, s64, w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<true>(sx, sy, s64, w64, s0, s1, tx, ty, sum);
       else
-        p2p64_leaf<false>(src4, s64, w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<false>(sx, sy, s64, w64, s0, s1, tx, ty, sum);
     }
     if (active) a.near_sum[(int64_t)part * a.m + k] = 0.5 * sum + a.lnh * wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
@@ -228,14 +238,14 @@ void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
   const bool direct = a.list_cnt == nullptr;
   if (fp64) {
     if (direct)
-      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.s64, a.w64);
+      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.s64, a.w64);
     else
-      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4, a.s64, a.w64);
+      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.s64, a.w64);
   } else {
     if (direct)
-      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4);
+      k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.sw);
     else
-      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.src4);
+      k_p2p32<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.sw);
   }
 }
 

@@ -151,7 +151,8 @@ __global__ void k_gather_points(const int* __restrict__ perm, const int* __restr
 __global__ __launch_bounds__(256) void k_pack_points(TreeArrays t, const int* __restrict__ sleaves, int n, int D,
                                                       const double* __restrict__ xs, const double* __restrict__ ys,
                                                       const double* __restrict__ ws, double x0, double y0, double u,
-                                                      float4* __restrict__ src4, double2* __restrict__ s64,
+                                                      float* __restrict__ s32, int64_t stride,
+                                                      double2* __restrict__ s64,
                                                       double* __restrict__ leaf_w) {
   const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (wid >= n) return;
@@ -165,7 +166,9 @@ __global__ __launch_bounds__(256) void k_pack_points(TreeArrays t, const int* __
     const double rx = (xs[s] - x0) / u - cx;
     const double ry = (ys[s] - y0) / u - cy;
     const double w = ws[s];
-    src4[s] = make_float4((float)rx, (float)ry, (float)w, 0.0f);
+    s32[s] = (float)rx;
+    s32[stride + s] = (float)ry;
+    s32[2 * stride + s] = (float)w;
     s64[s] = make_double2(rx, ry);
     acc += w;
   }
@@ -234,10 +237,12 @@ void points_gather(const int* perm, const int* nsrc_dev, int64_t nmax, const dou
 }
 
 void leaf_pack_points(TreeArrays t, const int* sleaves, int nsleaves, int D, const double* xs, const double* ys,
-                      const double* ws, double x0, double y0, double u, float4* src4, double2* s64, double* leaf_w,
+                      const double* ws, double x0, double y0, double u, float* s32, int64_t stride, double2* s64,
+                      double* leaf_w,
                       hipStream_t s) {
   if (nsleaves <= 0) return;
-  k_pack_points<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, xs, ys, ws, x0, y0, u, src4, s64, leaf_w);
+  k_pack_points<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, xs, ys, ws, x0, y0, u, s32, stride, s64,
+                                                   leaf_w);
 }
 
 void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,

@@ -558,7 +558,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
     p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
   }
-  float4* src4 = ensure<float4>(c, B_SRC4, N);
+  float* s32 = ensure<float>(c, B_SRC4, 3 * std::max<int64_t>(N, 1));  // x, y, w planes of stride N
   double* leaf_w = ensure<double>(c, B_LEAFW, ncells);
   float2* rel32 = ensure<float2>(c, B_REL32, m);
   double2* rel64 = ensure<double2>(c, B_REL64, m);
@@ -581,7 +581,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   pa.list_cnt = direct ? nullptr : cp2p;
   pa.sleaves = sleaves;
   pa.nsleaves = nsl;
-  pa.src4 = src4;
+  pa.sx = s32;
+  pa.sy = s32 + std::max<int64_t>(N, 1);
+  pa.sw = s32 + 2 * std::max<int64_t>(N, 1);
   pa.s64 = s64;
   pa.w64 = sw;
   pa.leaf_w = leaf_w;
@@ -659,9 +661,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   };
   auto do_pack_sources = [&](hipStream_t q) {
     if (src.grid)
-      leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, src4, leaf_w, q);
+      leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, q);
     else
-      leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, src4, s64, leaf_w, q);
+      leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, s32, std::max<int64_t>(N, 1), s64, leaf_w,
+                       q);
   };
   auto do_prep_targets = [&](hipStream_t q) {
     if (src.grid)

@@ -286,7 +286,8 @@ __global__ void k_classify_scatter(const int* __restrict__ n_dev, const int* __r
 // units of h, w) per source; leaf weight sum in FP64 in a fixed order.
 __global__ __launch_bounds__(256) void k_pack_sources(TreeArrays t, const int* __restrict__ sleaves, int n, int D,
                                                        const uint32_t* __restrict__ ij, const double* __restrict__ w64,
-                                                       float4* __restrict__ src4, double* __restrict__ leaf_w) {
+                                                       float* __restrict__ s32, int64_t stride,
+                                                       double* __restrict__ leaf_w) {
   const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (wid >= n) return;
   const int lane = threadIdx.x % kWave;
@@ -299,7 +300,9 @@ __global__ __launch_bounds__(256) void k_pack_sources(TreeArrays t, const int* _
     const uint32_t v = ij[s];
     const int i = (int)(v & 0xFFFFu), j = (int)(v >> 16);
     const double w = w64[s];
-    src4[s] = make_float4((float)(i - cx) + 0.5f, (float)(j - cy) + 0.5f, (float)w, 0.0f);
+    s32[s] = (float)(i - cx) + 0.5f;
+    s32[stride + s] = (float)(j - cy) + 0.5f;
+    s32[2 * stride + s] = (float)w;
     acc += w;
   }
 #pragma unroll
@@ -405,9 +408,9 @@ void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, in
 }
 
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
-                       float4* src4, double* leaf_w, hipStream_t s) {
+                       float* s32, int64_t stride, double* leaf_w, hipStream_t s) {
   if (nsleaves <= 0) return;
-  k_pack_sources<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, ij, w64, src4, leaf_w);
+  k_pack_sources<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, ij, w64, s32, stride, leaf_w);
 }
 
 void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
