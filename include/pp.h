@@ -228,8 +228,9 @@ pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
 /* GPU timing of later calls: 0 off; 1 HIP events between all phases
  * (ms_phase[]; every phase then runs on the call's stream, one after the
  * other, and launches are not replayed from graphs); 2 HIP events around the
- * near-field launch only (ms_phase[PP_PHASE_P2P]; the launches before and
- * after it are still replayed).  Events add no synchronisation beyond the
+ * near-field launch only (ms_phase[PP_PHASE_P2P]; the first segment of the
+ * solve is still replayed, the launches of the second are issued one by one).
+ * Events add no synchronisation beyond the
  * call's own.  Outside mode 1 the near field runs on a second stream owned by
  * the context, concurrently with the expansions on the call's stream, which
  * waits for it before the finalize step; the mode-2 events are recorded on

@@ -105,10 +105,8 @@ struct pp_ctx {
     int seen = 0;
     hipGraphExec_t exec = nullptr;
   };
-  // 0: up to the tree read-back; 1: the rest (or, in timing mode 2, packing,
-  // lists and target preparation on the side stream); in timing mode 2 also
-  // 2: the upward pass, 3: M2L and the downward pass, 4: the finalize step
-  static constexpr int kSegments = 5;
+  // 0: up to the tree read-back; 1: the rest (not replayed in timing mode 2)
+  static constexpr int kSegments = 2;
   Segment seg[kSegments];
   uint64_t budget = 0;
   size_t held = 0;
@@ -732,31 +730,27 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   const int seq2 = published_seq(c) + 1;
   if (c.profiling == 2) {
-    // The schedule of an untimed call with the near field launched outside the
-    // replayed segments, bracketed by events on its own stream.  Segment 1 is
+    // The schedule of an untimed call with the near field bracketed by events
+    // on its own stream, every launch of this segment issued directly (a
+    // captured graph drops event records, and replaying the pieces around the
+    // near field as four small graphs was measured slower than issuing their
+    // launches: each graph launch delays its first kernel).  Segment 1 is
     // complete (the host has seen its read-back), so the side stream starts
-    // without waiting on s: its replayed packing, lists and target preparation,
-    // then the near field.  The upward pass runs meanwhile on s, which then
-    // waits for the lists (M2L, L2L, L2P) and for the near field (finalize).
-    auto key = [&](uint64_t i) {
-      std::vector<uint64_t> k = key2;
-      k.push_back(i);
-      return k;
-    };
+    // without waiting on s: packing, lists and target preparation, then the
+    // near field.  The upward pass runs meanwhile on s, which then waits for
+    // the lists (M2L, L2L, L2P) and for the near field (finalize).
     if (lists_early) do_lists(s);
-    run_segment(c, 1, replayable, key(1), ss, [&] {
-      do_pack_sources(ss);
-      side_lists();
-    });
+    do_pack_sources(ss);
+    side_lists();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
     do_near(ss);
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
-    run_segment(c, 2, replayable, key(2), s, do_upward);
+    do_upward();
     if (ss != s) HIPCHK(hipStreamWaitEvent(s, c.ev_lists, 0));
-    run_segment(c, 3, replayable, key(3), s, do_downward);
+    do_downward();
     signal(c.ev_join, ss, s);
-    run_segment(c, 4, replayable, key(4), s, do_finalize);
+    do_finalize();
   } else if (ss == s) {
     // one stream, phases in order (timing mode 1, or the side stream disabled)
     run_segment(c, 1, replayable, key2, s, [&] {
