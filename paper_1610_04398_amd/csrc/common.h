@@ -55,6 +55,26 @@ __host__ __device__ inline uint32_t compact_bits(uint32_t v) {
 }
 __host__ __device__ inline uint32_t morton(uint32_t ix, uint32_t iy) { return spread_bits(ix) | (spread_bits(iy) << 1); }
 
+// Finest-cell Morton key of a target: floor((t - x0) / h) per axis with the
+// same FP64 operations (subtract, then divide; no contraction) as the
+// reference tree, in a root of 2^k cells per side.  *err: 1 for a non-finite
+// coordinate, 2 for a target outside the root (the key is then 0).
+__device__ inline uint32_t target_key(double x, double y, double x0, double y0, double h, int k, int* err) {
+#pragma clang fp contract(off)
+  if (!isfinite(x) || !isfinite(y)) {
+    *err = 1;
+    return 0;
+  }
+  const double ux = floor((x - x0) / h);
+  const double uy = floor((y - y0) / h);
+  const double lim = (double)(1u << k);
+  if (!(ux >= 0.0 && ux < lim && uy >= 0.0 && uy < lim)) {
+    *err = 2;
+    return 0;
+  }
+  return morton((uint32_t)ux, (uint32_t)uy);
+}
+
 // Device view of the quadtree: structure-of-arrays over all cells, numbered
 // level by level (root = 0), children of a cell contiguous and in quadrant
 // order q = qx + 2 qy.

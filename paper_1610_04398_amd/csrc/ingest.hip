@@ -46,11 +46,26 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __rest
   if (threadIdx.x == 0) tile_cnt[blockIdx.x] = total;
 }
 
+// tile_sum: tile_off holds the per-tile counts instead of their exclusive
+// scan; each workgroup then adds up the counts before its own tile (few
+// tiles: at most kIngFusedTiles), and the last one stores the total.
 __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restrict__ f, int nx, int ny, int k,
                                                             double h2, const int* __restrict__ tile_off,
+                                                            int tile_sum, int* __restrict__ total_out,
                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ ij,
                                                             double* __restrict__ w64) {
   __shared__ int lds[kIngBlock / kWave + 1];
+  int before = 0;
+  if (tile_sum) {
+    int acc = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kIngBlock) acc += tile_off[t];
+    int all;
+    block_excl_scan<kIngBlock>(acc, lds, &all);
+    before = all;
+    __syncthreads();
+  } else {
+    before = tile_off[blockIdx.x];
+  }
   const uint64_t mend = (uint64_t)1 << (2 * k);
   const uint64_t base = (uint64_t)blockIdx.x * kIngTile + (uint64_t)threadIdx.x * kIngItems;
   double v[kIngItems];
@@ -61,7 +76,8 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
     c += ok[q] ? 1 : 0;
   }
   int total;
-  int pos = block_excl_scan<kIngBlock>(c, lds, &total) + tile_off[blockIdx.x];
+  int pos = block_excl_scan<kIngBlock>(c, lds, &total) + before;
+  if (tile_sum && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = before + total;
   for (int q = 0; q < kIngItems; ++q) {
     if (!ok[q]) continue;
     const uint64_t m = base + q;
@@ -74,27 +90,14 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
   }
 }
 
-// Finest-cell index of a target: floor((t - x0) / h), the same FP64 operations
-// (subtract, then divide; no contraction) as the reference tree.
 __global__ void k_target_keys(const double* __restrict__ tx, const double* __restrict__ ty, int64_t m, double x0,
                               double y0, double h, int k, uint32_t* __restrict__ key, int* __restrict__ idx,
                               int* __restrict__ flags) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m) return;
-  const double x = tx[t], y = ty[t];
-  uint32_t kk = 0;
-  if (!isfinite(x) || !isfinite(y)) {
-    atomicOr(flags, kFlagNonFiniteTarget);
-  } else {
-    const double ux = floor((x - x0) / h);
-    const double uy = floor((y - y0) / h);
-    const double lim = (double)(1u << k);
-    if (!(ux >= 0.0 && ux < lim && uy >= 0.0 && uy < lim)) {
-      atomicOr(flags, kFlagTargetOutside);
-    } else {
-      kk = morton((uint32_t)ux, (uint32_t)uy);
-    }
-  }
+  int err = 0;
+  const uint32_t kk = target_key(tx[t], ty[t], x0, y0, h, k, &err);
+  if (err) atomicOr(flags, err == 1 ? kFlagNonFiniteTarget : kFlagTargetOutside);
   key[t] = kk;
   idx[t] = (int)t;
 }
@@ -109,9 +112,10 @@ void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, in
   k_ingest_count<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, tile_cnt, flags);
 }
 
-void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, uint32_t* key,
-                      uint32_t* ij, double* w64, hipStream_t s) {
-  k_ingest_emit<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_off, key, ij, w64);
+void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, int tile_sum,
+                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, hipStream_t s) {
+  k_ingest_emit<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_off, tile_sum, total_out,
+                                                                     key, ij, w64);
 }
 
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k, uint32_t* key,

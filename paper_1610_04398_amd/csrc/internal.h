@@ -32,8 +32,11 @@ void ctx_set_near_stream(pp_ctx* c, bool on);
 // Morton tiles of 1024 indices cover [0, 4^k).
 int64_t ingest_num_tiles(int k);
 void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s);
-void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, uint32_t* key,
-                      uint32_t* ij, double* w64, hipStream_t s);
+// tile_sum != 0: tile_off holds the per-tile counts (not their scan) and
+// *total_out receives the source count; only for at most kIngFusedTiles tiles.
+constexpr int64_t kIngFusedTiles = 1024;
+void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, int tile_sum,
+                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, hipStream_t s);
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
                  uint32_t* key, int* idx, int* flags, hipStream_t s);
 
@@ -57,6 +60,11 @@ size_t radix_temp_ints(int64_t n);
 // Sorts the low `bits` bits of keys; results end in (keys, vals).  tmp arrays of n.
 void radix_sort_pairs(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int64_t n, int bits,
                       int* temp, hipStream_t s);
+// Target keys (as target_keys) sorted with their indices (as radix_sort_pairs
+// over 2k bits); the first pass computes the keys while it counts digits.
+void target_keys_sorted(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
+                        uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int* temp, int* flags,
+                        hipStream_t s);
 
 // ---- tree.hip: top-down construction, per-leaf packing ------------------------------
 struct TreeArrays {

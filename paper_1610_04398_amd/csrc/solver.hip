@@ -497,8 +497,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     if (src.grid) {
       // ---- ingest: sources in Morton order (no sort needed for a grid) ----
       ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
-      scan_exclusive(tile, tile, ntiles, scan, misc + M_NSRC, s);
-      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, skey, sij, sw, s);
+      if (ntiles <= kIngFusedTiles) {  // the emitting workgroups add up the tile counts themselves
+        ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 1, misc + M_NSRC, skey, sij, sw, s);
+      } else {
+        scan_exclusive(tile, tile, ntiles, scan, misc + M_NSRC, s);
+        ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 0, nullptr, skey, sij, sw, s);
+      }
     } else if (src.n > 0) {
       // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
       int* sperm = (int*)sij;
@@ -508,8 +512,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     }
     // ---- targets: Morton keys and a stable radix sort ----
     mark(PP_PHASE_SORT);
-    target_keys(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, misc + M_FLAGS, s);
-    radix_sort_pairs(tkey, tperm, tkey2, tperm2, m, 2 * k, sort_tmp, s);
+    target_keys_sorted(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, tkey2, tperm2, sort_tmp, misc + M_FLAGS, s);
     // ---- tree: dense top levels, then one launch group per level, no host round trip ----
     mark(PP_PHASE_TREE);
     tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, tkey, (int)m, dss, dts, dflag, doff, scan,

@@ -35,6 +35,37 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_hist(const uint32_t* __restr
   for (int b = threadIdx.x; b < BINS; b += kRsBlock) hist[b * nblocks + blockIdx.x] = h[b];
 }
 
+// The first pass's histogram fused with the computation of the target keys
+// (finest-cell Morton keys, see target_key): each workgroup computes and stores
+// the keys and indices of its tile and counts their lowest digit.
+template <int BITS>
+__global__ __launch_bounds__(kRsBlock) void k_keys_hist(const double* __restrict__ tx, const double* __restrict__ ty,
+                                                        int n, double x0, double y0, double h, int k, int nblocks,
+                                                        uint32_t* __restrict__ keys, int* __restrict__ vals,
+                                                        int* __restrict__ hist, int* __restrict__ flags) {
+  constexpr int BINS = 1 << BITS;
+  __shared__ int hs[BINS];
+  for (int b = threadIdx.x; b < BINS; b += kRsBlock) hs[b] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kRsTile;
+  int errs = 0;
+  for (int q = 0; q < kRsItems; ++q) {
+    const int i = base + q * kRsBlock + threadIdx.x;
+    if (i < n) {
+      int err = 0;
+      const uint32_t key = target_key(tx[i], ty[i], x0, y0, h, k, &err);
+      errs |= err;
+      keys[i] = key;
+      vals[i] = i;
+      atomicAdd(&hs[key & (BINS - 1)], 1);
+    }
+  }
+  if (errs & 1) atomicOr(flags, kFlagNonFiniteTarget);
+  if (errs & 2) atomicOr(flags, kFlagTargetOutside);
+  __syncthreads();
+  for (int b = threadIdx.x; b < BINS; b += kRsBlock) hist[b * nblocks + blockIdx.x] = hs[b];
+}
+
 template <int BITS>
 __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                              const int* __restrict__ vin, int n, int shift, int nblocks,
@@ -106,12 +137,60 @@ __global__ void k_copy_pairs(const uint32_t* __restrict__ ks, const int* __restr
   }
 }
 
+// The target coordinates when the first pass also computes the keys.
+struct KeySource {
+  const double* tx = nullptr;
+  const double* ty = nullptr;
+  double x0 = 0.0, y0 = 0.0, h = 1.0;
+  int k = 0;
+  int* flags = nullptr;
+};
+
 template <int BITS>
-void radix_pass(const uint32_t* ka, const int* va, uint32_t* kb, int* vb, int n, int shift, int nb, int* table,
-                int* scan_tmp, hipStream_t s) {
-  k_radix_hist<BITS><<<nb, kRsBlock, 0, s>>>(ka, n, shift, nb, table);
+void radix_pass(uint32_t* ka, int* va, uint32_t* kb, int* vb, int n, int shift, int nb, int* table, int* scan_tmp,
+                const KeySource* ks, hipStream_t s) {
+  if (ks)
+    k_keys_hist<BITS><<<nb, kRsBlock, 0, s>>>(ks->tx, ks->ty, n, ks->x0, ks->y0, ks->h, ks->k, nb, ka, va, table,
+                                              ks->flags);
+  else
+    k_radix_hist<BITS><<<nb, kRsBlock, 0, s>>>(ka, n, shift, nb, table);
   scan_exclusive(table, table, (int64_t)(1 << BITS) * nb, scan_tmp, nullptr, s);
   k_radix_scatter<BITS><<<nb, kRsBlock, 0, s>>>(ka, va, n, shift, nb, table, kb, vb);
+}
+
+void sort_impl(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int64_t n, int bits, int* temp,
+               const KeySource* ks, hipStream_t s) {
+  const int nb = (int)((n + kRsTile - 1) / kRsTile);
+  int* table = temp;
+  int* scan_tmp = temp + (1 << kRsMaxBits) * (int64_t)nb;
+  uint32_t* ka = keys;
+  int* va = vals;
+  uint32_t* kb = keys_tmp;
+  int* vb = vals_tmp;
+  const int passes = (bits + kRsMaxBits - 1) / kRsMaxBits;
+  const int width = (bits + passes - 1) / passes;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = width * ps;
+    const KeySource* kp = ps == 0 ? ks : nullptr;
+    switch (width) {
+      case 1: radix_pass<1>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 2: radix_pass<2>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 3: radix_pass<3>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 4: radix_pass<4>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 5: radix_pass<5>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 6: radix_pass<6>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 7: radix_pass<7>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      case 8: radix_pass<8>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+      default: radix_pass<9>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, kp, s); break;
+    }
+    uint32_t* tk = ka;
+    ka = kb;
+    kb = tk;
+    int* tv = va;
+    va = vb;
+    vb = tv;
+  }
+  if (ka != keys) k_copy_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ka, va, (int)n, keys, vals);
 }
 }  // namespace
 
@@ -125,36 +204,26 @@ size_t radix_temp_ints(int64_t n) {
 void radix_sort_pairs(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int64_t n, int bits, int* temp,
                       hipStream_t s) {
   if (n <= 1 || bits <= 0) return;
-  const int nb = (int)((n + kRsTile - 1) / kRsTile);
-  int* table = temp;
-  int* scan_tmp = temp + (1 << kRsMaxBits) * (int64_t)nb;
-  uint32_t* ka = keys;
-  int* va = vals;
-  uint32_t* kb = keys_tmp;
-  int* vb = vals_tmp;
-  const int passes = (bits + kRsMaxBits - 1) / kRsMaxBits;
-  const int width = (bits + passes - 1) / passes;
-  for (int ps = 0; ps < passes; ++ps) {
-    const int shift = width * ps;
-    switch (width) {
-      case 1: radix_pass<1>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 2: radix_pass<2>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 3: radix_pass<3>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 4: radix_pass<4>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 5: radix_pass<5>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 6: radix_pass<6>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 7: radix_pass<7>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      case 8: radix_pass<8>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-      default: radix_pass<9>(ka, va, kb, vb, (int)n, shift, nb, table, scan_tmp, s); break;
-    }
-    uint32_t* tk = ka;
-    ka = kb;
-    kb = tk;
-    int* tv = va;
-    va = vb;
-    vb = tv;
+  sort_impl(keys, vals, keys_tmp, vals_tmp, n, bits, temp, nullptr, s);
+}
+
+void target_keys_sorted(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
+                        uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int* temp, int* flags,
+                        hipStream_t s) {
+  if (m <= 0) return;
+  if (m == 1 || k <= 0) {
+    target_keys(tx, ty, m, x0, y0, h, k, keys, vals, flags, s);
+    return;
   }
-  if (ka != keys) k_copy_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ka, va, (int)n, keys, vals);
+  KeySource ks;
+  ks.tx = tx;
+  ks.ty = ty;
+  ks.x0 = x0;
+  ks.y0 = y0;
+  ks.h = h;
+  ks.k = k;
+  ks.flags = flags;
+  sort_impl(keys, vals, keys_tmp, vals_tmp, m, 2 * k, temp, &ks, s);
 }
 
 }  // namespace pp
