@@ -527,7 +527,11 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
         const Cx2<T> g0 = cb[0], g1 = cb[1];
         const T wx = (rx + g0.x) * g1.x, wy = (ry + g0.y) * g1.x;
         const T r2 = wx * wx + wy * wy;
-        const T ir2 = (T)1 / r2;
+        T ir2;
+        if constexpr (sizeof(T) == 4)
+          ir2 = __builtin_amdgcn_rcpf(r2);  // v_rcp_f32 (1 ulp): the mixed-precision path rounds to FP32 anyway
+        else
+          ir2 = (T)1 / r2;
         const T ux = wx * ir2, uy = -wy * ir2;
         T hx = (T)0, hy = (T)0;
         for (int q = p; q >= 1; --q) {
