@@ -98,9 +98,10 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
 // Compacted cell lists: source leaves, target leaves, cells with targets, for
 // the *ncells_dev cells of the tree (cap = allocated cells; flag3/off3 scratch
 // of 3 * cap); counts[0..2] receive their lengths.
-void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, int* off3, int* scan_tmp,
-                    int* total_slot, int* n3_slot, int* sleaves, int* tleaves, int* tcells, int* counts,
-                    hipStream_t s);
+// part: classify_part_ints(cap) ints of scratch.  counts[0..2]: the three list lengths.
+int64_t classify_part_ints(int64_t cap);
+void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
+                    int* tcells, int* counts, hipStream_t s);
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
 // cell units, as three planes (x at s32[s], y at s32[stride + s], w at
 // s32[2 stride + s]), and the FP64 leaf weight.

@@ -40,7 +40,7 @@ struct PPError {
 enum BufId {
   B_F, B_TX, B_TY, B_OUT, B_MISC, B_TILE, B_SCAN, B_SKEY, B_SIJ, B_SW, B_SRC4, B_TKEY, B_TPERM, B_TKEY2,
   B_TPERM2, B_SORT, B_LVL, B_IX, B_IY, B_SB, B_SE, B_TB, B_TE, B_CHILD, B_NCHILD, B_PARENT, B_CNT, B_OFF, B_CR,
-  B_FLAG, B_FOFF, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
+  B_FLAG, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
   B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
@@ -480,8 +480,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   int* sleaves = ensure<int>(c, B_SLEAF, cap);
   int* tleaves = ensure<int>(c, B_TLEAF, cap);
   int* tcells = ensure<int>(c, B_TCELL, cap);
-  int* flag3 = ensure<int>(c, B_FLAG, 3 * cap);
-  int* off3 = ensure<int>(c, B_FOFF, 3 * cap);
+  int* flag3 = ensure<int>(c, B_FLAG, classify_part_ints(cap));  // per-tile counts of the classification
 
   // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
   // (graph replay only for device-resident grid input: host input is staged by copies)
@@ -523,8 +522,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                  misc + M_FLAGS, s);
     }
     // cell lists over the whole tree (its size is the last level start, on the device)
-    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, off3, scan, misc + M_TOT, misc + M_N4, sleaves, tleaves, tcells,
-                   misc + M_NSL, s);
+    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, sleaves, tleaves, tcells, misc + M_NSL, s);
     publish_enqueue(c, misc, M_LS + D + 2, s);
   });
   wait_published(c, s, seq1);

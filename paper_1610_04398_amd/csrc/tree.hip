@@ -252,34 +252,98 @@ __global__ void k_dense_write(TreeArrays t, const int* __restrict__ flag, const 
 // flag[kind * n + c] for kind 0 = leaf with sources, 1 = leaf with targets,
 // 2 = any cell with targets; the cell count n is read on the device (the
 // tree's last level start) and 3n is left in *n3 for the scan.
-__global__ void k_classify(TreeArrays t, const int* __restrict__ n_dev, int* __restrict__ flag, int* __restrict__ n3) {
-  const int n = *n_dev;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) *n3 = 3 * n;
-  if (c >= n) return;
+// Cell classification: source leaves, target leaves and cells with targets,
+// each compacted in cell order.  Two launches over tiles of kClsTile cells:
+// the first counts the three kinds per tile, the second adds up the counts of
+// the tiles before its own (few: the tree's cells / kClsTile) and compacts its
+// tile with block scans.  The cell count is read from the device.
+constexpr int kClsBlock = 256;
+constexpr int kClsItems = 1;
+constexpr int kClsTile = kClsBlock * kClsItems;
+
+__device__ inline int cls_bits(const TreeArrays& t, int c) {
   const bool leaf = t.child[c] < 0;
   const bool hs = t.se[c] > t.sb[c];
   const bool ht = t.te[c] > t.tb[c];
-  flag[c] = (leaf && hs) ? 1 : 0;
-  flag[n + c] = (leaf && ht) ? 1 : 0;
-  flag[2 * n + c] = ht ? 1 : 0;
+  return (leaf && hs ? 1 : 0) | (leaf && ht ? 2 : 0) | (ht ? 4 : 0);
 }
 
-__global__ void k_classify_scatter(const int* __restrict__ n_dev, const int* __restrict__ flag,
-                                   const int* __restrict__ off, const int* __restrict__ total,
-                                   int* __restrict__ out0, int* __restrict__ out1, int* __restrict__ out2,
-                                   int* __restrict__ counts) {
+__global__ __launch_bounds__(kClsBlock) void k_classify_count(TreeArrays t, const int* __restrict__ n_dev,
+                                                               int* __restrict__ part) {
+  __shared__ int lds[kClsBlock / kWave + 1];
   const int n = *n_dev;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c == 0) {
-    counts[0] = n > 0 ? off[n] - off[0] : 0;
-    counts[1] = n > 0 ? off[2 * n] - off[n] : 0;
-    counts[2] = n > 0 ? *total - off[2 * n] : 0;
+  const int64_t base = (int64_t)blockIdx.x * kClsTile;
+  if (base >= n) return;  // uniform per workgroup
+  int c0 = 0, c1 = 0, c2 = 0;
+  for (int q = 0; q < kClsItems; ++q) {
+    const int64_t c = base + (int64_t)threadIdx.x * kClsItems + q;
+    if (c < n) {
+      const int b = cls_bits(t, (int)c);
+      c0 += b & 1;
+      c1 += (b >> 1) & 1;
+      c2 += (b >> 2) & 1;
+    }
   }
-  if (c >= n) return;
-  if (flag[c]) out0[off[c] - off[0]] = c;
-  if (flag[n + c]) out1[off[n + c] - off[n]] = c;
-  if (flag[2 * n + c]) out2[off[2 * n + c] - off[2 * n]] = c;
+  int tot0, tot1, tot2;
+  block_excl_scan<kClsBlock>(c0, lds, &tot0);
+  block_excl_scan<kClsBlock>(c1, lds, &tot1);
+  block_excl_scan<kClsBlock>(c2, lds, &tot2);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = tot0;
+    part[3 * blockIdx.x + 1] = tot1;
+    part[3 * blockIdx.x + 2] = tot2;
+  }
+}
+
+__global__ __launch_bounds__(kClsBlock) void k_classify_emit(TreeArrays t, const int* __restrict__ n_dev,
+                                                              const int* __restrict__ part, int* __restrict__ out0,
+                                                              int* __restrict__ out1, int* __restrict__ out2,
+                                                              int* __restrict__ counts) {
+  __shared__ int lds[kClsBlock / kWave + 1];
+  const int n = *n_dev;
+  const int ntiles = (int)(((int64_t)n + kClsTile - 1) / kClsTile);
+  const int64_t base = (int64_t)blockIdx.x * kClsTile;
+  if (blockIdx.x > 0 && base >= n) return;  // uniform per workgroup
+  // offsets of this tile (and, in workgroup 0, the totals of all tiles)
+  const int upto = blockIdx.x == 0 ? ntiles : (int)blockIdx.x;
+  int p0 = 0, p1 = 0, p2 = 0;
+  for (int i = threadIdx.x; i < upto; i += kClsBlock) {
+    p0 += part[3 * i];
+    p1 += part[3 * i + 1];
+    p2 += part[3 * i + 2];
+  }
+  int s0, s1, s2;
+  block_excl_scan<kClsBlock>(p0, lds, &s0);
+  block_excl_scan<kClsBlock>(p1, lds, &s1);
+  block_excl_scan<kClsBlock>(p2, lds, &s2);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      counts[0] = s0;
+      counts[1] = s1;
+      counts[2] = s2;
+    }
+    s0 = s1 = s2 = 0;
+  }
+  if (base >= n) return;
+  int bits[kClsItems];
+  int c0 = 0, c1 = 0, c2 = 0;
+  for (int q = 0; q < kClsItems; ++q) {
+    const int64_t c = base + (int64_t)threadIdx.x * kClsItems + q;
+    bits[q] = c < n ? cls_bits(t, (int)c) : 0;
+    c0 += bits[q] & 1;
+    c1 += (bits[q] >> 1) & 1;
+    c2 += (bits[q] >> 2) & 1;
+  }
+  int tot;
+  int o0 = block_excl_scan<kClsBlock>(c0, lds, &tot) + s0;
+  int o1 = block_excl_scan<kClsBlock>(c1, lds, &tot) + s1;
+  int o2 = block_excl_scan<kClsBlock>(c2, lds, &tot) + s2;
+  for (int q = 0; q < kClsItems; ++q) {
+    const int c = (int)(base + (int64_t)threadIdx.x * kClsItems + q);
+    if (bits[q] & 1) out0[o0++] = c;
+    if (bits[q] & 2) out1[o1++] = c;
+    if (bits[q] & 4) out2[o2++] = c;
+  }
 }
 
 // One wave per source leaf: FP32 record (x, y relative to the leaf corner in
@@ -397,14 +461,14 @@ void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap,
   k_dense_write<<<g, 256, 0, s>>>(t, flag, off, total_slot, ss, ts, Ld, cap, ls, flags);
 }
 
-void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* flag3, int* off3, int* scan_tmp,
-                    int* total_slot, int* n3_slot, int* sleaves, int* tleaves, int* tcells, int* counts,
-                    hipStream_t s) {
+int64_t classify_part_ints(int64_t cap) { return 3 * ((cap + kClsTile - 1) / kClsTile) + 3; }
+
+void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
+                    int* tcells, int* counts, hipStream_t s) {
   if (cap <= 0) return;
-  const unsigned g = (unsigned)((cap + 255) / 256);
-  k_classify<<<g, 256, 0, s>>>(t, ncells_dev, flag3, n3_slot);
-  scan_exclusive_dev(flag3, off3, n3_slot, 3 * (int64_t)cap, scan_tmp, total_slot, s);
-  k_classify_scatter<<<g, 256, 0, s>>>(ncells_dev, flag3, off3, total_slot, sleaves, tleaves, tcells, counts);
+  const unsigned g = (unsigned)(((int64_t)cap + kClsTile - 1) / kClsTile);
+  k_classify_count<<<g, kClsBlock, 0, s>>>(t, ncells_dev, part);
+  k_classify_emit<<<g, kClsBlock, 0, s>>>(t, ncells_dev, part, sleaves, tleaves, tcells, counts);
 }
 
 void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
