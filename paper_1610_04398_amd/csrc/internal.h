@@ -85,6 +85,8 @@ struct TreeArrays {
 // tree_level to continue from.  Gives the same cells and numbering as
 // building the levels one at a time from the root.
 int64_t tree_dense_cells(int Ld);
+// ints of scan_tmp that tree_dense_top needs (per-workgroup counts of the flags)
+int64_t tree_dense_part_ints(int Ld);
 void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
                     const int* nsrc_dev, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag, int* off,
                     int* scan_tmp, int* total_slot, int* flags, hipStream_t s);

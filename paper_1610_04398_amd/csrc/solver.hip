@@ -438,8 +438,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const int64_t per_level = 4 * (nmax / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
   const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
   if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
-  ensure<int>(c, B_SCAN, (int64_t)scan_temp_ints(std::max<int64_t>(
-                            {ntiles, 4 * per_level, 3 * cap, m, nmax, tree_dense_cells(std::min(D, c.dense_levels)), 1})));
+  ensure<int>(c, B_SCAN, std::max<int64_t>((int64_t)scan_temp_ints(std::max<int64_t>({ntiles, 4 * per_level, cap, m, nmax, 1})),
+                                            tree_dense_part_ints(std::min(D, c.dense_levels))));
 
   uint32_t* skey = ensure<uint32_t>(c, B_SKEY, nmax);
   uint32_t* sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index

@@ -192,23 +192,59 @@ __global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __r
   ts[P] = lower_bound_from(tkey, ntgt, key, (P * (int64_t)ntgt) / np);
 }
 
-__global__ void k_dense_flags(const int* __restrict__ ss, const int* __restrict__ ts, int D, int Ld, int leaf_max,
-                              int* __restrict__ flag) {
+// Existence flag of every prefix-table cell, and per workgroup (kDenseBlock
+// consecutive cells) the number of cells that exist, for k_dense_offsets.
+constexpr int kDenseBlock = 256;
+__global__ __launch_bounds__(kDenseBlock) void k_dense_flags(const int* __restrict__ ss, const int* __restrict__ ts,
+                                                              int D, int Ld, int leaf_max, int* __restrict__ flag,
+                                                              int* __restrict__ part) {
+  __shared__ int lds[kDenseBlock / kWave + 1];
   const int64_t F = dense_level_offset(Ld + 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= F) return;
-  const int L = dense_level_of(idx);
-  if (L == 0) {
-    flag[idx] = 1;
-    return;
+  int f = 0;
+  if (idx < F) {
+    const int L = dense_level_of(idx);
+    if (L == 0) {
+      f = 1;
+    } else {
+      const int64_t P = idx - dense_level_offset(L);
+      const int sh = 2 * (Ld - L), shp = sh + 2;
+      const int64_t Q = P >> 2;
+      const int ns = ss[(P + 1) << sh] - ss[P << sh], nt = ts[(P + 1) << sh] - ts[P << sh];
+      const int nps = ss[(Q + 1) << shp] - ss[Q << shp], npt = ts[(Q + 1) << shp] - ts[Q << shp];
+      const bool split = L - 1 < D && (nps > leaf_max || npt > leaf_max);
+      f = (split && (ns > 0 || nt > 0)) ? 1 : 0;
+    }
+    flag[idx] = f;
   }
-  const int64_t P = idx - dense_level_offset(L);
-  const int sh = 2 * (Ld - L), shp = sh + 2;
-  const int64_t Q = P >> 2;
-  const int ns = ss[(P + 1) << sh] - ss[P << sh], nt = ts[(P + 1) << sh] - ts[P << sh];
-  const int nps = ss[(Q + 1) << shp] - ss[Q << shp], npt = ts[(Q + 1) << shp] - ts[Q << shp];
-  const bool split = L - 1 < D && (nps > leaf_max || npt > leaf_max);
-  flag[idx] = (split && (ns > 0 || nt > 0)) ? 1 : 0;
+  int total;
+  block_excl_scan<kDenseBlock>(f, lds, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+// Exclusive scan of the flags (the cell numbers): each workgroup adds up the
+// counts of the workgroups before it, then scans its own cells; workgroup 0
+// also stores the total.
+__global__ __launch_bounds__(kDenseBlock) void k_dense_offsets(const int* __restrict__ flag,
+                                                                const int* __restrict__ part, int Ld,
+                                                                int* __restrict__ off, int* __restrict__ total_out) {
+  __shared__ int lds[kDenseBlock / kWave + 1];
+  const int64_t F = dense_level_offset(Ld + 1);
+  const int nb = (int)((F + kDenseBlock - 1) / kDenseBlock);
+  const int upto = blockIdx.x == 0 ? nb : (int)blockIdx.x;
+  int acc = 0;
+  for (int i = threadIdx.x; i < upto; i += kDenseBlock) acc += part[i];
+  int before;
+  block_excl_scan<kDenseBlock>(acc, lds, &before);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *total_out = before;
+    before = 0;
+  }
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = idx < F ? flag[idx] : 0;
+  int tot;
+  const int ex = block_excl_scan<kDenseBlock>(f, lds, &tot) + before;
+  if (idx < F) off[idx] = ex;
 }
 
 __global__ void k_dense_write(TreeArrays t, const int* __restrict__ flag, const int* __restrict__ off,
@@ -447,6 +483,8 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
   k_level_link<<<g, 256, 0, s>>>(t, ls, level, cr, exists, off, total_slot, cap, flags);
 }
 
+int64_t tree_dense_part_ints(int Ld) { return (tree_dense_cells(Ld) + kDenseBlock - 1) / kDenseBlock + 1; }
+
 int64_t tree_dense_cells(int Ld) { return ((((int64_t)1) << (2 * (Ld + 1))) - 1) / 3; }
 
 void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
@@ -455,9 +493,9 @@ void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap,
   const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
   k_dense_starts<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(skey, nsrc_dev, tkey, ntgt, D, Ld, ss, ts);
   const int64_t F = tree_dense_cells(Ld);
-  const unsigned g = (unsigned)((F + 255) / 256);
-  k_dense_flags<<<g, 256, 0, s>>>(ss, ts, D, Ld, leaf_max, flag);
-  scan_exclusive(flag, off, F, scan_tmp, total_slot, s);
+  const unsigned g = (unsigned)((F + kDenseBlock - 1) / kDenseBlock);
+  k_dense_flags<<<g, kDenseBlock, 0, s>>>(ss, ts, D, Ld, leaf_max, flag, scan_tmp);
+  k_dense_offsets<<<g, kDenseBlock, 0, s>>>(flag, scan_tmp, Ld, off, total_slot);
   k_dense_write<<<g, 256, 0, s>>>(t, flag, off, total_slot, ss, ts, Ld, cap, ls, flags);
 }
 
