@@ -81,8 +81,8 @@ extern "C" uint64_t pp_footprint_estimate(int32_t nx, int32_t ny, int64_t m, int
   const uint64_t g = (uint64_t)nx * (uint64_t)ny;
   int k = 0;
   while ((1 << k) < std::max(nx, ny)) ++k;
-  // per grid node: f staging, key, packed index, weight, 16-byte record, ingest tiles
-  const uint64_t src = g * (8 + 4 + 4 + 8 + 16 + 1);
+  // per grid node: f staging, key, packed index, weight, three FP32 record planes, ingest tiles
+  const uint64_t src = g * (8 + 4 + 4 + 8 + 12 + 1);
   // per target: coordinates, keys/permutations (x2), offsets, leaf, self data, far, near parts, output
   const uint64_t tgt = (uint64_t)m * (16 + 16 + 8 + 16 + 4 + 4 + 8 + 8 + 8 * 8 + 8);
   // cells: bounded by the tree capacity; arrays, records, expansions, lists
