@@ -159,7 +159,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-reps", type=int, default=3, help="replays of the arrival trace per path (median p99)")
-    ap.add_argument("--serve-work-budget", type=int, default=0,
+    ap.add_argument("--serve-work-budget", type=int, default=1300000,
                     help="server admission bound on in-flight grid nodes + targets (0: none)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / sequential solves per second")
     ap.add_argument("--forces-panels", type=int, default=4096,

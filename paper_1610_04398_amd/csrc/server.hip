@@ -122,6 +122,9 @@ void worker_loop(pp_server* s, int slot) {
       s->inflight_work += job->work;
       job->slot = slot;
       job->t_start = clk::now();
+      // a request that starts alone on the GPU runs its near field on the
+      // context's second stream; beside other requests it keeps one stream
+      if (s->cfg.max_slots > 1) pp::ctx_set_near_stream(ctx, s->inflight == 1);
     }
     const pp_request& r = job->req;
     const double* f = job->f_copy.empty() ? r.f : job->f_copy.data();
