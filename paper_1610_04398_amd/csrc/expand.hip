@@ -48,6 +48,8 @@ __constant__ BinomTable c_binom = make_binom();
 __device__ inline double binom(int n, int k) { return c_binom.v[n][k]; }
 
 __device__ inline double cell_side(int D, int l) { return (double)(1 << (D - l)); }
+// 1 / cell_side, exact (a power of two): x * inv_cell_side equals x / cell_side.
+__device__ inline double inv_cell_side(int D, int l) { return ldexp(1.0, l - D); }
 
 // Offset of child quadrant from its parent's centre, in parent sides.
 __device__ inline cplx quadrant_offset(int ix, int iy) {
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
     cplx tl = tt;
 #pragma unroll
     for (int l = 1; l <= PM; ++l) {
-      cplx s = {-a0 / l, 0.0};
+      cplx s = {-a0 * (1.0 / l), 0.0};  // 1 / l is a compile-time constant of the unrolled loop
 #pragma unroll
       for (int k = 1; k <= PM; ++k) s = cadd(s, cscale(bk[k], binom(l + k - 1, k - 1)));
       L[l] = cadd(L[l], cmul(tl, s));
@@ -397,8 +399,8 @@ __global__ void k_downward(TreeView t, const int* __restrict__ tcells, int n, in
   int X = t.parent[c];
   while (X >= 0) {
     const int lX = t.lvl[X];
-    const double sX = cell_side(D, lX);
-    const cplx d = {(cx - (t.ix[X] + 0.5) * sX) / sX, (cy - (t.iy[X] + 0.5) * sX) / sX};
+    const double sX = cell_side(D, lX), iX = inv_cell_side(D, lX);
+    const cplx d = {(cx - (t.ix[X] + 0.5) * sX) * iX, (cy - (t.iy[X] + 0.5) * sX) * iX};
     const double2* L = own + (int64_t)X * P1;
     cplx s = {0.0, 0.0};
     cplx dp = {1.0, 0.0};
@@ -418,9 +420,9 @@ __global__ void k_l2p64(TreeView t, int64_t m, const int* __restrict__ tleaf, in
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const int c = tleaf[k];
-  const double side = cell_side(t.D, t.lvl[c]);
+  const double side = cell_side(t.D, t.lvl[c]), inv = inv_cell_side(t.D, t.lvl[c]);
   const double2 r = rel64[k];
-  const cplx u = {(r.x - 0.5 * side) / side, (r.y - 0.5 * side) / side};
+  const cplx u = {(r.x - 0.5 * side) * inv, (r.y - 0.5 * side) * inv};
   const double2* L = loc + (int64_t)c * (p + 1);
   cplx acc = {0.0, 0.0};
   for (int l = p; l >= 0; --l) {
@@ -435,9 +437,9 @@ __global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, in
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const int c = tleaf[k];
-  const double side = cell_side(t.D, t.lvl[c]);
+  const double side = cell_side(t.D, t.lvl[c]), inv = inv_cell_side(t.D, t.lvl[c]);
   const double2 r = rel64[k];
-  const float ux = (float)((r.x - 0.5 * side) / side), uy = (float)((r.y - 0.5 * side) / side);
+  const float ux = (float)((r.x - 0.5 * side) * inv), uy = (float)((r.y - 0.5 * side) * inv);
   const double2* L = loc + (int64_t)c * (p + 1);
   float ax = 0.f, ay = 0.f;
   for (int l = p; l >= 0; --l) {
