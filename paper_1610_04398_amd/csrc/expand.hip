@@ -382,25 +382,45 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
 // recursion "local(child) = own M2L + L2L(local(parent))" equals the sum, over
 // the cell and each of its ancestors X, of X's own M2L local shifted from X's
 // centre to the cell:  L'_m = sum_X 2^{-m (l_c - l_X)} sum_{k>=m} C(k, m) d_X^{k-m} L'_k(X),
-// d_X = (z_c - z_X) / s_X.  One thread per (cell with targets, coefficient m).
-__global__ void k_downward(TreeView t, const int* __restrict__ tcells, int n, int p,
-                           const double2* __restrict__ own, double2* __restrict__ loc) {
+// d_X = (z_c - z_X) / s_X.  Eight lanes per (cell with targets, coefficient m):
+// lane j takes the ancestors at levels j and j + 8 (the cell itself at its own
+// level), and a fixed butterfly over the eight lanes adds the terms.  An
+// ancestor at a level of the dense prefix table is found there directly from
+// the cell's coordinates; deeper ones by following parent links.
+constexpr int kDownLanes = 8;
+__global__ void k_downward(TreeView t, const int* __restrict__ tcells, int n, int p, const double2* __restrict__ own,
+                           double2* __restrict__ loc, const int* __restrict__ dense_off, int dense_levels) {
   const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int P1 = p + 1;
-  const int i = (int)(w / P1);
-  const int m = (int)(w % P1);
-  if (i >= n) return;
-  const int c = tcells[i];
+  const int lane = (int)(w % kDownLanes);
+  const int64_t item = w / kDownLanes;
+  const int i = (int)(item / P1);
+  const int m = (int)(item % P1);
+  const bool live = i < n;  // all lanes of an item agree; the butterfly needs every lane
+  const int c = live ? tcells[i] : 0;
   const int D = t.D;
-  const int lc = t.lvl[c];
+  const int lc = live ? t.lvl[c] : 0;
+  const int icx = live ? t.ix[c] : 0, icy = live ? t.iy[c] : 0;
   const double sc = cell_side(D, lc);
-  const double cx = (t.ix[c] + 0.5) * sc, cy = (t.iy[c] + 0.5) * sc;
-  cplx acc = {own[(int64_t)c * P1 + m].x, own[(int64_t)c * P1 + m].y};
-  int X = t.parent[c];
-  while (X >= 0) {
-    const int lX = t.lvl[X];
-    const double sX = cell_side(D, lX), iX = inv_cell_side(D, lX);
-    const cplx d = {(cx - (t.ix[X] + 0.5) * sX) * iX, (cy - (t.iy[X] + 0.5) * sX) * iX};
+  const double cx = (icx + 0.5) * sc, cy = (icy + 0.5) * sc;
+  cplx acc = {0.0, 0.0};
+  for (int j = lane; live && j <= lc; j += kDownLanes) {
+    if (j == lc) {
+      const double2 v = own[(int64_t)c * P1 + m];
+      acc = cadd(acc, {v.x, v.y});
+      continue;
+    }
+    const int sh = lc - j;
+    const int ax = icx >> sh, ay = icy >> sh;  // the ancestor's coordinates at level j
+    int X;
+    if (j <= dense_levels) {
+      X = dense_off[((((int64_t)1 << (2 * j)) - 1) / 3) + (int64_t)morton((uint32_t)ax, (uint32_t)ay)];
+    } else {
+      X = c;
+      for (int l = lc; l > j; --l) X = t.parent[X];
+    }
+    const double sX = cell_side(D, j), iX = inv_cell_side(D, j);
+    const cplx d = {(cx - (ax + 0.5) * sX) * iX, (cy - (ay + 0.5) * sX) * iX};
     const double2* L = own + (int64_t)X * P1;
     cplx s = {0.0, 0.0};
     cplx dp = {1.0, 0.0};
@@ -409,10 +429,14 @@ __global__ void k_downward(TreeView t, const int* __restrict__ tcells, int n, in
       s = cadd(s, cscale(cmul({v.x, v.y}, dp), binom(k, m)));
       dp = cmul(dp, d);
     }
-    acc = cadd(acc, cscale(s, ldexp(1.0, -m * (lc - lX))));
-    X = t.parent[X];
+    acc = cadd(acc, cscale(s, ldexp(1.0, -m * (lc - j))));
   }
-  loc[(int64_t)c * P1 + m] = make_double2(acc.x, acc.y);
+#pragma unroll
+  for (int o = kDownLanes / 2; o > 0; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o, kDownLanes);
+    acc.y += __shfl_xor(acc.y, o, kDownLanes);
+  }
+  if (live && lane == 0) loc[(int64_t)c * P1 + m] = make_double2(acc.x, acc.y);
 }
 
 __global__ void k_l2p64(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
@@ -617,10 +641,11 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
     k_m2l<20, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
 }
 
-void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s) {
-  const int64_t w = (int64_t)n * (p + 1);
+void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, const int* dense_off,
+              int dense_levels, hipStream_t s) {
+  const int64_t w = (int64_t)n * (p + 1) * kDownLanes;
   if (w <= 0) return;
-  k_downward<<<(unsigned)((w + 255) / 256), 256, 0, s>>>(t, tcells, n, p, own, loc);
+  k_downward<<<(unsigned)((w + 255) / 256), 256, 0, s>>>(t, tcells, n, p, own, loc, dense_off, dense_levels);
 }
 
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,

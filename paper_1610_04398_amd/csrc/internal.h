@@ -173,7 +173,10 @@ void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, 
          const double2* mp, const double2* rel64, int fp32, double* far, int* flags, hipStream_t s);
 // Final local expansion of every cell with targets from its own M2L local
 // (`own`) and its ancestors' (exact L2L shifts), one launch.
-void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, hipStream_t s);
+// dense_off/dense_levels: the cell numbers of the tree build's dense prefix
+// table (levels 0..dense_levels), where ancestors are looked up directly.
+void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, const int* dense_off,
+              int dense_levels, hipStream_t s);
 // far[k] = Re sum_l c'_l u^l for every sorted target k (u: offset from its
 // leaf centre over the leaf side); fp32 != 0 evaluates in FP32.
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,

@@ -702,7 +702,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     } else {
       m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
       mark(PP_PHASE_L2L);
-      downward(tv, tcells, ntc, p, own, loc, s);
+      downward(tv, tcells, ntc, p, own, loc, doff, Ld, s);
       mark(PP_PHASE_L2P);
       l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
     }
