@@ -208,9 +208,13 @@ struct P2PArgs {
   int* flags;                 // error flags (kFlagBadIndex for a list entry outside the tree)
   unsigned long long* pairs;  // if set with pair_counts, receives their sum
   double lnh;           // ln of the grid spacing (the unit of the offsets)
+  const double* log_tab;  // FP64 kernel: kLogTable values of ln n (log_table)
   double* near_sum;     // [nparts][m]: per sorted target, sum w ln(r) over the part's near sources
 };
 void p2p(const P2PArgs& a, int fp64, hipStream_t s);
+// ln n for n in [1, kLogTable) (tab[0] = 0), for the FP64 near field.
+constexpr int kLogTable = 4096;
+void log_table(double* tab, hipStream_t s);
 
 // ---- finalize.hip ----------------------------------------------------------------------
 // P at every target, scattered to the caller's order; writes nothing if *flags != 0.

@@ -153,10 +153,15 @@ __global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_e
   if (bad && lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
 }
 
+// FP64 near field.  Grid-node targets and grid sources sit at exact
+// half-integer offsets, so r^2 is an exact integer there; below kLogTable it
+// is looked up in a table of ln n computed on the device with the same log
+// (bitwise the same term), any other r^2 calls log.
 template <bool GUARD>
 __device__ inline void p2p64_leaf(const float* __restrict__ sx, const float* __restrict__ sy,
-                                  const double2* __restrict__ s64, const double* __restrict__ w64, int s0, int s1,
-                                  double tx, double ty, double& sum) {
+                                  const double2* __restrict__ s64, const double* __restrict__ w64,
+                                  const double* __restrict__ log_tab, int s0, int s1, double tx, double ty,
+                                  double& sum) {
 #pragma unroll 2
   for (int s = s0; s < s1; ++s) {
     double ox, oy;
@@ -173,15 +178,26 @@ __device__ inline void p2p64_leaf(const float* __restrict__ sx, const float* __r
     const double dy = ty - oy;
     const double r2 = fma(dy, dy, dx * dx);
     if (GUARD && r2 == 0.0) continue;
-    sum = fma(w, log(r2), sum);
+    double lg;
+    if (r2 < (double)kLogTable && r2 == floor(r2))
+      lg = log_tab[(int)r2];
+    else
+      lg = log(r2);
+    sum = fma(w, lg, sum);
   }
+}
+
+__global__ void k_log_table(double* __restrict__ tab) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < kLogTable) tab[n] = n > 0 ? log((double)n) : 0.0;
 }
 
 template <bool DIRECT>
 __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const float* __restrict__ sx,
                                                              const float* __restrict__ sy,
                                                              const double2* __restrict__ s64,
-                                                             const double* __restrict__ w64) {
+                                                             const double* __restrict__ w64,
+                                                             const double* __restrict__ log_tab) {
   const int wid = __builtin_amdgcn_readfirstlane(xcd_contiguous(blockIdx.x, gridDim.x) * kP2PWaves +
                                                     threadIdx.x / kWave);
   if (wid >= a.ntleaves * a.nparts) return;
@@ -218,9 +234,9 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
       nsrc += s1 - s0;
       wn += a.leaf_w[B];
       if (B == A)
-        p2p64_leaf<true>(sx, sy, s64, w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<true>(sx, sy, s64, w64, log_tab, s0, s1, tx, ty, sum);
       else
-        p2p64_leaf<false>(sx, sy, s64, w64, s0, s1, tx, ty, sum);
+        p2p64_leaf<false>(sx, sy, s64, w64, log_tab, s0, s1, tx, ty, sum);
     }
     if (active) a.near_sum[(int64_t)part * a.m + k] = 0.5 * sum + a.lnh * wn;
     pairs += (int64_t)min(kWave, te - chunk) * nsrc;
@@ -231,6 +247,8 @@ __global__ __launch_bounds__(kP2PWaves* kWave) void k_p2p64(P2PArgs a, const flo
 
 }  // namespace
 
+void log_table(double* tab, hipStream_t s) { k_log_table<<<(kLogTable + 255) / 256, 256, 0, s>>>(tab); }
+
 void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
   const int64_t waves = (int64_t)a.ntleaves * a.nparts;
   if (waves <= 0) return;
@@ -238,9 +256,9 @@ void p2p(const P2PArgs& a, int fp64, hipStream_t s) {
   const bool direct = a.list_cnt == nullptr;
   if (fp64) {
     if (direct)
-      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.s64, a.w64);
+      k_p2p64<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.s64, a.w64, a.log_tab);
     else
-      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.s64, a.w64);
+      k_p2p64<false><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.s64, a.w64, a.log_tab);
   } else {
     if (direct)
       k_p2p32<true><<<g, kP2PWaves * kWave, 0, s>>>(a, a.sx, a.sy, a.sw);

@@ -114,7 +114,8 @@ struct pp_ctx {
   // kMiscInts + kMailExtra ints of coherent pinned host memory for read-backs;
   // slot kSeqSlot receives the sequence number of the last published read-back
   int* pinned = nullptr;
-  int* pub_ctr = nullptr;  // device counter of published read-backs
+  int* pub_ctr = nullptr;
+  double* log_tab = nullptr;  // ln n table of the FP64 near field, filled at its first use  // device counter of published read-backs
   hipStream_t cur_stream = nullptr;  // the running call's stream (drained after a failure)
   std::string err;
   bool dead = false;
@@ -595,6 +596,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   pa.pairs = pairs;
   pa.near_sum = near;
   pa.lnh = std::log(unit);
+  if (!mixed && !c.log_tab) {  // filled once, outside any captured segment
+    HIPCHK(hipMalloc((void**)&c.log_tab, kLogTable * sizeof(double)));
+    log_table(c.log_tab, s);
+    HIPCHK(hipStreamSynchronize(s));  // the near field may run on the side stream without waiting on s
+  }
+  pa.log_tab = c.log_tab;
   pa.list_src = direct ? nullptr : p2p_src;  // set again below once exact lists are allocated
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
@@ -942,6 +949,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (hipMalloc((void**)&c->pub_ctr, sizeof(zeros)) != hipSuccess ||
       hipMemcpy(c->pub_ctr, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess) {
     if (c->pub_ctr) (void)hipFree(c->pub_ctr);
+  if (c->log_tab) (void)hipFree(c->log_tab);
     (void)hipHostFree(c->pinned);
     delete c;
     return PP_ERR_DEVICE;
@@ -963,6 +971,7 @@ void pp_destroy(pp_ctx* c) {
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->pub_ctr) (void)hipFree(c->pub_ctr);
+  if (c->log_tab) (void)hipFree(c->log_tab);
   delete c;
 }
 
