@@ -172,8 +172,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (the multi-GPU sharding "
-                                   "of the solve is a design note, not an implementation)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 (sharding the solve over "
+                                   "several GPUs is described, not implemented)"}))
         return 2
 
     import numpy as np
