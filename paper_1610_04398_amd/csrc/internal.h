@@ -137,7 +137,7 @@ void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, co
 // the source leaves summed directly (P2P).  Same emit modes as lists_pass.
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
                          int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
-                         int cap_p, int* flags, hipStream_t s);
+                         int cap_p, int* flags, int tier_boost, hipStream_t s);
 // Packed per-cell records used by the traversal (ncells int4); clears the
 // list counts, and for cap_m > 0 writes the one-pass offsets cell * cap.
 void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
@@ -147,7 +147,10 @@ void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2
 // is longer than its capacity; its tail is then dropped).
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
-                int* flags, hipStream_t s);
+                int* flags, int tier_boost, hipStream_t s);
+// The traversal frontier has three capacity tiers chosen from theta; tier_boost
+// raises it after an overflow.  True when no higher tier is left.
+bool frontier_at_top(int num, int den, int tier_boost);
 // ---- expand.hip: multipole and local passes (FP64) ---------------------------------
 // P2M of every source leaf (16 lanes per leaf), from the ordered sources: grid
 // nodes by their packed index ij (i | j << 16), or (ij null) scattered sources

@@ -1,7 +1,7 @@
 // Interaction lists of the dual-tree traversal.
 //
 // The paper sums group contributions, treating a group through its expansion
-// "at sufficiently large distances" and the rest directly (Appendix A, the
+// once it is far enough away and the rest directly (Appendix A, the
 // superposition equation after Fig. multipole).  The traversal read here pairs
 // a target cell A with a source cell B starting from the roots: accepted by
 // the exact integer test -> M2L; both leaves -> P2P; A leaf -> split B; B leaf
@@ -12,8 +12,13 @@
 // ancestor path.  The pairs (X, B) with X the current path cell form a
 // frontier of source cells kept in LDS; the 64 lanes classify 64 candidates at
 // a time and compact what they emit with ballots, so each cell's lists come out
-// in a fixed order without atomics.  A count pass sizes the lists, an emit pass
+// in a fixed order without atomics.  Down to A the frontier advances one level
+// at a time; at A itself it becomes a stack popped 64 cells at a time, so that a
+// target leaf much larger than the source cells beside it (whose breadth-first
+// frontier would hold every source cell of a level near it) needs only about
+// 3 x 64 entries per level below A.  A count pass sizes the lists, an emit pass
 // writes them.
+#include <algorithm>
 #include <climits>
 
 #include "blockscan.h"
@@ -23,11 +28,19 @@ namespace pp {
 
 namespace {
 constexpr int kListWaves = 4;
-// Frontier capacity per wave (two buffers).  The frontier of a target cell holds the
-// non-accepted source cells near its path, ~4 (2/theta + 1)^2 at most in a uniform
-// tree (about 100 at theta = 0.5): 1024 entries keep LDS at 32 KB per workgroup (five
-// workgroups per CU) for theta >= 0.3; smaller theta uses 2048.  Overflow is flagged.
-__host__ __device__ constexpr int frontier_cap_for(bool small_theta) { return small_theta ? 2048 : 1024; }
+// Frontier capacity per wave (two level buffers, or one stack of twice the
+// size at the target cell), in three tiers.  The frontier of a target cell holds
+// the non-accepted source cells near its path, ~4 (2/theta + 1)^2 in a uniform
+// tree (about 100 at theta = 0.5).  Tier 0 (256 entries, 8 KB of LDS per
+// workgroup, so LDS no longer limits the waves per CU) serves theta >= 0.5;
+// tier 1 (1024) theta >= 0.3; tier 2 (2048) smaller theta.  Overflow is flagged
+// and the solve repeats at the next tier.
+constexpr int kFrontierTiers[3] = {256, 1024, 2048};
+int frontier_tier_for(int num, int den) {
+  if (2 * num >= den) return 0;       // theta >= 0.5
+  if (num * 10 >= 3 * den) return 1;  // theta >= 0.3
+  return 2;
+}
 
 // Packed per-cell record for the traversal: {ix, iy, first child, meta} with
 // meta = level | nchild << 5 | (children-with-sources mask) << 8 | has_src << 12.
@@ -57,6 +70,62 @@ __global__ void k_records(TreeView t, int n, int4* __restrict__ rec, int* __rest
   rec[c] = make_int4(t.ix[c], t.iy[c], k0, meta);
 }
 
+// The traversal at the target cell A itself, from the source cells left on the
+// stack st[0, top): accepted -> A's far list (M2L, or M2P for the tree-code);
+// not accepted and a leaf -> A's near list when A is a leaf; not accepted and
+// not a leaf -> its children with sources pushed when A is a leaf (for a
+// non-leaf A the rest belongs to A's children).  Pops the top 64 entries at a
+// time.  Returns true when the stack would exceed `cap` (the lists are then
+// incomplete).
+template <bool kTreecode>
+__device__ bool lists_at_target(int* st, int top, int cap, int D, int4 rA, bool leafA, int num, int den,
+                                const int4* __restrict__ rec, int emit, int* __restrict__ m_src, int64_t mbase,
+                                int mlim, int* __restrict__ p_src, int64_t pbase, int plim, int& nm, int& np,
+                                int lane, uint64_t lt_mask) {
+  const int lA = rec_level(rA);
+  while (top > 0) {
+    const int n = min(kWave, top);
+    const bool valid = lane < n;
+    const int B = valid ? st[top - n + lane] : 0;
+    top -= n;
+    __syncwarp();  // the popped slots take this round's pushes
+    bool acc = false, leafB = false;
+    int kid0 = 0, kmask = 0;
+    if (valid) {
+      const int4 rB = rec[B];
+      acc = kTreecode ? treecode_accept(D, lA, rA.x, rA.y, rec_level(rB), rB.x, rB.y, num, den)
+                      : mac_accept(D, lA, rA.x, rA.y, rec_level(rB), rB.x, rB.y, num, den);
+      kid0 = rB.z;
+      leafB = kid0 < 0;
+      kmask = rec_kidmask(rB);
+    }
+    const bool em = valid && acc;
+    const bool ep = valid && !acc && leafB && leafA;
+    const bool push = valid && !acc && !leafB && leafA;
+    const uint64_t bm = __ballot(em);
+    const uint64_t bp = __ballot(ep);
+    if (emit) {
+      const int im = nm + __popcll(bm & lt_mask), ip = np + __popcll(bp & lt_mask);
+      if (em && im < mlim) m_src[mbase + im] = B;
+      if (ep && ip < plim) p_src[pbase + ip] = B;
+    }
+    nm += __popcll(bm);
+    np += __popcll(bp);
+    const int npush = push ? __popc(kmask) : 0;
+    const int incl = wave_incl_scan(npush);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    if (top + total > cap) return true;
+    if (push) {
+      int pos = top + incl - npush;
+      for (int q = 0; q < 4; ++q)
+        if ((kmask >> q) & 1) st[pos++] = kid0 + q;
+    }
+    top += total;
+    __syncwarp();
+  }
+  return false;
+}
+
 template <int kFrontierCap>
 __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4* __restrict__ rec,
                                                                const int* __restrict__ parent,
@@ -67,7 +136,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
                                                                const int* __restrict__ off_p2p,
                                                                int* __restrict__ m2l_src, int* __restrict__ p2p_src,
                                                                int cap_m, int cap_p, int* __restrict__ flags) {
-  __shared__ int front[kListWaves][2][kFrontierCap];
+  __shared__ int front[kListWaves][2 * kFrontierCap];
   __shared__ int path[kListWaves][kMaxDepth + 1];
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -85,64 +154,50 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   }
   const bool leafA = rA.z < 0;
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
-  int* cur = front[w][0];
-  int* nxt = front[w][1];
+  int* const buf = front[w];
+  int* cur = buf;
+  int* nxt = buf + kFrontierCap;
   int ncur = 0;
   if (rec_has_src(rec[0])) {
     if (lane == 0) cur[0] = 0;
     ncur = 1;
   }
   __syncwarp();
-  int xl = 0;  // index on the path of the current target cell X
-  int nm = 0, np = 0;
   // emit 1: exact offsets from a count pass; emit 2: fixed capacity per cell
   const int64_t mbase = emit == 1 ? off_m2l[A] : (int64_t)A * cap_m;
   const int64_t pbase = emit == 1 ? off_p2p[A] : (int64_t)A * cap_p;
   const int mlim = emit == 2 ? cap_m : INT_MAX;
   const int plim = emit == 2 ? cap_p : INT_MAX;
   bool overflow = false;
-  while (ncur > 0) {
-    const int X = path[w][xl];
-    const bool atA = (X == A);
-    const int4 rX = (X == A) ? rA : rec[X];
-    const bool leafX = rX.z < 0;
-    const int lX = rec_level(rX);
+  // Down the path: X (level xl) is a proper ancestor of A, so not a leaf, and a
+  // pair accepted here belongs to X's lists.  A source leaf that is not
+  // accepted stays for the next level, any other source cell is replaced by its
+  // children with sources.
+  for (int xl = 0; xl < lA && ncur > 0; ++xl) {
+    const int4 rX = rec[path[w][xl]];
     int nnext = 0;
     for (int base = 0; base < ncur; base += kWave) {
       const int i = base + lane;
       const bool valid = i < ncur;
       const int B = valid ? cur[i] : 0;
-      bool acc = false, leafB = false;
+      bool keep = false, leafB = false;
       int kid0 = 0, kmask = 0;
       if (valid) {
         const int4 rB = rec[B];
-        acc = mac_accept(D, lX, rX.x, rX.y, rec_level(rB), rB.x, rB.y, num, den);
+        keep = !mac_accept(D, xl, rX.x, rX.y, rec_level(rB), rB.x, rB.y, num, den);
         kid0 = rB.z;
         leafB = kid0 < 0;
         kmask = rec_kidmask(rB);
       }
-      const bool em2l = valid && acc && atA;
-      const bool ep2p = valid && !acc && leafX && leafB && atA;
-      const bool push_self = valid && !acc && !leafX && leafB && !atA;
-      const bool push_kids = valid && !acc && !leafB && (leafX ? atA : !atA);
-      const uint64_t bm = __ballot(em2l);
-      const uint64_t bp = __ballot(ep2p);
-      if (emit) {
-        const int im = nm + __popcll(bm & lt_mask), ip = np + __popcll(bp & lt_mask);
-        if (em2l && im < mlim) m2l_src[mbase + im] = B;
-        if (ep2p && ip < plim) p2p_src[pbase + ip] = B;
-      }
-      nm += __popcll(bm);
-      np += __popcll(bp);
-      const int npush = push_self ? 1 : (push_kids ? __popc(kmask) : 0);
+      const int npush = keep ? (leafB ? 1 : __popc(kmask)) : 0;
       const int incl = wave_incl_scan(npush);
       const int total = __shfl(incl, kWave - 1, kWave);
       int pos = nnext + incl - npush;
       if (nnext + total > kFrontierCap) {
         overflow = true;
       } else {
-        if (push_self) nxt[pos] = B;
-        if (push_kids) {
+        if (keep && leafB) nxt[pos] = B;
+        if (keep && !leafB) {
           for (int q = 0; q < 4; ++q)
             if ((kmask >> q) & 1) nxt[pos++] = kid0 + q;
         }
@@ -155,11 +210,15 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
     cur = nxt;
     nxt = tmp;
     ncur = nnext;
-    if (!atA) {
-      ++xl;
-    } else if (!leafA) {
-      break;
+  }
+  int nm = 0, np = 0;
+  if (!overflow && ncur > 0) {
+    if (cur != buf) {  // the stack starts at the bottom of the buffer (no overlap: ncur <= kFrontierCap)
+      for (int i = lane; i < ncur; i += kWave) buf[i] = cur[i];
+      __syncwarp();
     }
+    overflow = lists_at_target<false>(buf, ncur, 2 * kFrontierCap, D, rA, leafA, num, den, rec, emit, m2l_src,
+                                      mbase, mlim, p2p_src, pbase, plim, nm, np, lane, lt_mask);
   }
   if (overflow && lane == 0) atomicOr(flags, kFlagFrontierOverflow);
   if (emit == 2 && (nm > cap_m || np > cap_p) && lane == 0) atomicOr(flags, kFlagListOverflow);
@@ -175,29 +234,27 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
 // Lists of the paper's tree-code: one wave per target leaf A walks the source
 // tree from the root.  A source cell accepted for all of A's targets goes to
 // A's M2P list; a leaf that is not accepted goes to its P2P list; any other
-// cell is replaced by its children with sources.  The frontier lives in LDS
-// and is classified 64 cells at a time; ballots compact the output in a fixed
-// order.  Same emit modes and layouts as k_lists.
+// cell is replaced by its children with sources.  The cells still to visit
+// form a stack in LDS, popped and classified 64 at a time; ballots compact the
+// output in a fixed order.  Same emit modes and layouts as k_lists.
 template <int kFrontierCap>
 __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
     int D, const int4* __restrict__ rec, const int* __restrict__ tleaves, int ntleaves, int num, int den, int emit,
     int* __restrict__ cnt_m, int* __restrict__ cnt_p, const int* __restrict__ off_m, const int* __restrict__ off_p,
     int* __restrict__ m_src, int* __restrict__ p_src, int cap_m, int cap_p, int* __restrict__ flags) {
-  __shared__ int front[kListWaves][2][kFrontierCap];
+  __shared__ int front[kListWaves][2 * kFrontierCap];
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kListWaves + w);
   if (wid >= ntleaves) return;
   const int A = tleaves[wid];
   const int4 rA = rec[A];
-  const int lA = rec_level(rA);
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
-  int* cur = front[w][0];
-  int* nxt = front[w][1];
-  int ncur = 0;
+  int* const buf = front[w];
+  int top = 0;
   if (rec_has_src(rec[0])) {
-    if (lane == 0) cur[0] = 0;
-    ncur = 1;
+    if (lane == 0) buf[0] = 0;
+    top = 1;
   }
   __syncwarp();
   int nm = 0, np = 0;
@@ -205,54 +262,8 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
   const int64_t pbase = emit == 1 ? off_p[A] : (int64_t)A * cap_p;
   const int mlim = emit == 2 ? cap_m : INT_MAX;
   const int plim = emit == 2 ? cap_p : INT_MAX;
-  bool overflow = false;
-  while (ncur > 0) {
-    int nnext = 0;
-    for (int base = 0; base < ncur; base += kWave) {
-      const int i = base + lane;
-      const bool valid = i < ncur;
-      const int B = valid ? cur[i] : 0;
-      bool acc = false, leafB = false;
-      int kid0 = 0, kmask = 0;
-      if (valid) {
-        const int4 rB = rec[B];
-        acc = treecode_accept(D, lA, rA.x, rA.y, rec_level(rB), rB.x, rB.y, num, den);
-        kid0 = rB.z;
-        leafB = kid0 < 0;
-        kmask = rec_kidmask(rB);
-      }
-      const bool em = valid && acc;
-      const bool ep = valid && !acc && leafB;
-      const bool push = valid && !acc && !leafB;
-      const uint64_t bm = __ballot(em);
-      const uint64_t bp = __ballot(ep);
-      if (emit) {
-        const int im = nm + __popcll(bm & lt_mask), ip = np + __popcll(bp & lt_mask);
-        if (em && im < mlim) m_src[mbase + im] = B;
-        if (ep && ip < plim) p_src[pbase + ip] = B;
-      }
-      nm += __popcll(bm);
-      np += __popcll(bp);
-      const int npush = push ? __popc(kmask) : 0;
-      const int incl = wave_incl_scan(npush);
-      const int total = __shfl(incl, kWave - 1, kWave);
-      int pos = nnext + incl - npush;
-      if (nnext + total > kFrontierCap) {
-        overflow = true;
-      } else {
-        if (push)
-          for (int q = 0; q < 4; ++q)
-            if ((kmask >> q) & 1) nxt[pos++] = kid0 + q;
-        nnext += total;
-      }
-    }
-    __syncwarp();
-    if (overflow) break;
-    int* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
-    ncur = nnext;
-  }
+  const bool overflow = lists_at_target<true>(buf, top, 2 * kFrontierCap, D, rA, true, num, den, rec, emit, m_src,
+                                              mbase, mlim, p_src, pbase, plim, nm, np, lane, lt_mask);
   if (overflow && lane == 0) atomicOr(flags, kFlagFrontierOverflow);
   if (emit == 2 && (nm > cap_m || np > cap_p) && lane == 0) atomicOr(flags, kFlagListOverflow);
   if (emit != 1 && lane == 0) {
@@ -270,32 +281,36 @@ void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2
                                                     cap_p);
 }
 
+#define PP_LIST_TIER(tier, KERNEL, G, S, ...)                                  \
+  do {                                                                         \
+    if ((tier) <= 0)                                                           \
+      KERNEL<kFrontierTiers[0]><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__); \
+    else if ((tier) == 1)                                                      \
+      KERNEL<kFrontierTiers[1]><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__); \
+    else                                                                       \
+      KERNEL<kFrontierTiers[2]><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__); \
+  } while (0)
+
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
-                int* flags, hipStream_t s) {
+                int* flags, int tier_boost, hipStream_t s) {
   if (ntcells <= 0) return;
   const unsigned g = (unsigned)((ntcells + kListWaves - 1) / kListWaves);
-  if (num * 10 < 3 * den)  // theta < 0.3
-    k_lists<frontier_cap_for(true)><<<g, kListWaves * kWave, 0, s>>>(
-        t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
-        cap_m, cap_p, flags);
-  else
-    k_lists<frontier_cap_for(false)><<<g, kListWaves * kWave, 0, s>>>(
-        t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l, off_p2p, m2l_src, p2p_src,
-        cap_m, cap_p, flags);
+  const int tier = std::min(2, frontier_tier_for(num, den) + tier_boost);
+  PP_LIST_TIER(tier, k_lists, g, s, t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l,
+               off_p2p, m2l_src, p2p_src, cap_m, cap_p, flags);
 }
 
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
                          int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
-                         int cap_p, int* flags, hipStream_t s) {
+                         int cap_p, int* flags, int tier_boost, hipStream_t s) {
   if (ntleaves <= 0) return;
   const unsigned g = (unsigned)((ntleaves + kListWaves - 1) / kListWaves);
-  if (num * 10 < 3 * den)
-    k_lists_treecode<frontier_cap_for(true)><<<g, kListWaves * kWave, 0, s>>>(
-        t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p, m_src, p_src, cap_m, cap_p, flags);
-  else
-    k_lists_treecode<frontier_cap_for(false)><<<g, kListWaves * kWave, 0, s>>>(
-        t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p, m_src, p_src, cap_m, cap_p, flags);
+  const int tier = std::min(2, frontier_tier_for(num, den) + tier_boost);
+  PP_LIST_TIER(tier, k_lists_treecode, g, s, t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p,
+               m_src, p_src, cap_m, cap_p, flags);
 }
+
+bool frontier_at_top(int num, int den, int tier_boost) { return frontier_tier_for(num, den) + tier_boost >= 2; }
 
 }  // namespace pp

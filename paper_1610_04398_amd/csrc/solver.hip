@@ -30,6 +30,9 @@ struct PPError {
   pp_status code;
   std::string msg;
 };
+// Thrown once the traversal frontier overflowed below its largest tier: the tier
+// has been raised and the solve is repeated (nothing was written to the output).
+struct FrontierRetry {};
 
 #define HIPCHK(x)                                                                             \
   do {                                                                                        \
@@ -114,8 +117,9 @@ struct pp_ctx {
   // kMiscInts + kMailExtra ints of coherent pinned host memory for read-backs;
   // slot kSeqSlot receives the sequence number of the last published read-back
   int* pinned = nullptr;
-  int* pub_ctr = nullptr;
-  double* log_tab = nullptr;  // ln n table of the FP64 near field, filled at its first use  // device counter of published read-backs
+  int* pub_ctr = nullptr;      // device counter of published read-backs
+  double* log_tab = nullptr;  // ln n table of the FP64 near field, filled at its first use
+  int frontier_boost = 0;     // traversal frontier tiers above theta's own (raised after an overflow)
   hipStream_t cur_stream = nullptr;  // the running call's stream (drained after a failure)
   std::string err;
   bool dead = false;
@@ -606,17 +610,26 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
 
+  // a frontier that overflowed below the top tier: raise the tier for this and later solves
+  auto frontier_retry = [&](int flags) {
+    if (!(flags & kFlagFrontierOverflow) || frontier_at_top(num, den, c.frontier_boost)) return;
+    ++c.frontier_boost;
+    c.cur_stream = nullptr;
+    throw FrontierRetry{};
+  };
   auto list_pass = [&](int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp, hipStream_t q) {
     if (treecode)
       lists_treecode_pass(tv, rec, tleaves, ntl, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
-                          q);
+                          c.frontier_boost, q);
     else
-      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS, q);
+      lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
+                 c.frontier_boost, q);
   };
   std::vector<uint64_t> key2 = key1;
   for (uint64_t v : {(uint64_t)N, (uint64_t)ncells, (uint64_t)nsl, (uint64_t)ntl, (uint64_t)ntc, (uint64_t)depth,
                      (uint64_t)p, (uint64_t)num, (uint64_t)den, (uint64_t)prm.precision, (uint64_t)prm.self_mode,
-                     (uint64_t)prm.method, (uint64_t)cap_far, (uint64_t)cap_near, (uint64_t)nparts, bits(out_d)})
+                     (uint64_t)prm.method, (uint64_t)cap_far, (uint64_t)cap_near, (uint64_t)nparts, bits(out_d),
+                     (uint64_t)c.frontier_boost})
     key2.push_back(v);
   for (int v : lstart) key2.push_back((uint64_t)v);
 
@@ -653,6 +666,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, q);
       scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, q);
       readback(c, misc, 0, 16, q);
+      frontier_retry(c.pinned[M_FLAGS]);
       check_flags(c.pinned[M_FLAGS]);
       n_m2l = c.pinned[M_NM2L];
       n_p2pl = c.pinned[M_NP2P];
@@ -790,6 +804,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   }
   wait_published(c, s, seq2);
   const int flags = c.pinned[M_FLAGS];
+  frontier_retry(flags);
   if (flags & kFlagListOverflow) {  // nothing written; repeat with exact lists
     c.cur_stream = nullptr;
     return PP_ERR_LIMIT;
@@ -858,9 +873,18 @@ pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const dou
     else
       validate_points(src.n, src.sx, src.sy, src.w, m, tx, ty, prm, p_out);
     if (m == 0) return PP_OK;
-    pp_status st = run_solve(*c, direct, c->exact_lists, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
-    if (st == PP_ERR_LIMIT) {
-      // a list outgrew its per-cell capacity: make room for next time and redo this solve exactly
+    // A solve is repeated (at most a few times) when the traversal frontier
+    // overflowed below its top tier, or when a one-pass list outgrew its per-cell
+    // capacity (then exactly, with room made for next time).
+    bool exact = c->exact_lists;
+    pp_status st = PP_OK;
+    for (;;) {
+      try {
+        st = run_solve(*c, direct, exact, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+      } catch (const FrontierRetry&) {
+        continue;
+      }
+      if (st != PP_ERR_LIMIT || exact) break;
       if (prm->method == PP_METHOD_TREECODE) {
         c->cap_m2p *= 2;
         c->cap_tp2p *= 2;
@@ -868,7 +892,7 @@ pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const dou
         c->cap_m2l *= 2;
         c->cap_p2p *= 2;
       }
-      st = run_solve(*c, direct, true, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+      exact = true;
     }
     c->err.clear();
     return st;

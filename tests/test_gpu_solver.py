@@ -317,6 +317,35 @@ def test_list_modes_agree_bitwise(solver, monkeypatch):
         assert np.array_equal(got, ref) and np.array_equal(again, ref), env
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 1e-5)])
+def test_large_target_leaf_beside_fine_sources(precision, tol):
+    """Targets only in the empty half of a half-filled source grid (leaf_max 1) sit in a target leaf a
+    quarter of the domain wide beside source leaves of the finest level.  Almost no source cell is
+    accepted for it, so its near list holds nearly every source leaf, and the traversal below it needs a
+    longer stack than the smallest frontier tier holds: the first solve repeats at the next tier, a second
+    call starts there, and both match the oracle's FMM and each other bit for bit."""
+    import paper_1610_04398_amd as pp
+    n = 128
+    rng = np.random.Generator(np.random.PCG64(31))
+    f = rng.standard_normal((n, n))
+    f[:, n // 2:] = 0.0
+    h = 1.0 / n
+    tx = np.array([0.75, 0.8, 0.9])
+    ty = np.array([0.5, 0.6, 0.7])
+    ref = fmm_ref.fmm_grid(f, tx, ty, h, 10, 0.5, leaf_max=1)["P"]
+    exact = direct.direct_grid(f, h, tx, ty)
+    s = pp.Solver(0)
+    try:
+        kw = dict(p=10, theta=0.5, leaf_max=1, precision=precision)
+        first = s.solve_grid(f, h, tx, ty, **kw)
+        second = s.solve_grid(f, h, tx, ty, **kw)
+    finally:
+        s.close()
+    assert np.array_equal(first, second)
+    assert rel_max(first, ref) < tol, rel_max(first, ref)
+    assert rel_max(first, exact) < 1e-6
+
+
 @pytest.mark.parametrize("near_stream", ["1", "0"])
 def test_graph_replay_matches_eager(monkeypatch, near_stream):
     """Repeated solves on device inputs replay captured graphs (same shape and pointers; the second segment
