@@ -113,3 +113,13 @@ def test_points_degenerate(solver):
     with pytest.raises(pp.PPError) as e:
         solver.solve_points(bad, sy, w, tx, ty)
     assert e.value.status == -1
+
+
+def test_points_multi_tile_sort(solver):
+    """Point sources over many sort tiles (32-bit keys, four passes, ragged tail): the tree solve stays
+    within the mixed tolerance of the direct sum and counts every nonzero source."""
+    sx, sy, w, tx, ty = _clustered(9, n=2 * 4096 + 77, m=2000)
+    ref = direct.direct_points(sx, sy, w, tx, ty)
+    got = solver.solve_points(sx, sy, w, tx, ty, p=12, theta=0.5, leaf_max=32, precision="mixed")
+    assert rel_l2(got, ref) < 1e-4
+    assert solver.stats()["nsources"] == int(np.count_nonzero(w))

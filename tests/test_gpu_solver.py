@@ -102,6 +102,24 @@ def test_tree_bit_exact_adaptive(solver, seed, leaf_max, theta):
     _compare_tree(solver, info, theta, f.shape[1])
 
 
+def test_target_sort_multi_tile(solver):
+    """The target sort over many tiles with a ragged tail, a third of the targets repeated (equal keys,
+    whose input order the stable sort keeps) and the rest spread: keys and permutation equal the
+    oracle's stable sort."""
+    n = 128
+    h = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(41))
+    f = rng.standard_normal((n, n))
+    m = 3 * 4096 + 1234
+    rep = rng.uniform(0.0, 1.0, (40, 2))[rng.integers(0, 40, m // 3)]
+    tx = np.concatenate([rep[:, 0], rng.uniform(0.0, 1.0, m - m // 3)])
+    ty = np.concatenate([rep[:, 1], rng.uniform(0.0, 1.0, m - m // 3)])
+    solver.solve_grid(f, h, tx, ty, p=6, theta=0.5, leaf_max=64, precision="mixed")
+    keys, perm = tree_ref.target_keys_sorted(tx, ty, 0.0, 0.0, h, tree_ref.root_exponent(n, n))
+    np.testing.assert_array_equal(solver.debug_array("TGT_KEY").astype(np.uint64), keys)
+    np.testing.assert_array_equal(solver.debug_array("TGT_PERM"), perm)
+
+
 @pytest.mark.parametrize("dense_levels", ["0", "3"])
 def test_tree_bit_exact_levelwise(monkeypatch, dense_levels):
     """The level-by-level construction (from the root, or below a shallow dense top) gives the same tree."""
