@@ -104,30 +104,29 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
 int64_t classify_part_ints(int64_t cap);
 void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
                     int* tcells, int* counts, hipStream_t s);
+// One launch for two independent per-leaf passes.
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
 // cell units, as three planes (x at s32[s], y at s32[stride + s], w at
 // s32[2 stride + s]), and the FP64 leaf weight.
-void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
-                       float* s32, int64_t stride, double* leaf_w, hipStream_t s);
-// Scattered-source counterparts: FP32 records and FP64 offsets (units of u)
-// per source leaf; per target leaf the offsets, owning leaf, and the weight of
-// the sources that coincide exactly with the target.
-void leaf_pack_points(TreeArrays t, const int* sleaves, int nsleaves, int D, const double* xs, const double* ys,
-                      const double* ws, double x0, double y0, double u, float* s32, int64_t stride, double2* s64,
-                      double* leaf_w, hipStream_t s);
-void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
-                      const int* perm, double x0, double y0, double u, const double* xs, const double* ys,
-                      const double* ws, float2* rel32, double2* rel64, int* tleaf, double* self_w, hipStream_t s);
 // Per target leaf: offsets relative to the leaf corner (FP32 and FP64, in units
 // of h), owning leaf, and for the self rule the weight f h^2 of the node the
-// target coincides with (0 for none) and the log of its distance (-inf: exact).
+// target coincides with (0 if none) and ln of its distance to it (-inf on it).
 // A target at squared distance d2 from its nearest node with d2 == 0 or
 // d2 < snap_frac2 h^2 is snapped onto the node (its exact term is restored by
 // the finalize step); FP32 near fields use snap_frac2 = 2^-40, FP64 ones 0.
-void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
-                       const int* perm, double x0, double y0, double h, int nx, int ny, double snap_frac2,
-                       const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w, double* self_logd,
-                       hipStream_t s);
+void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const uint32_t* ij, const double* w64,
+                    float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
+                    const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
+                    double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
+                    double* self_logd, hipStream_t s);
+// Scattered-source counterpart, in one launch: FP32 records and FP64 offsets
+// (units of u) per source leaf; per target leaf the offsets, owning leaf, and
+// the weight of the sources that coincide exactly with the target.
+void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, const double* xs, const double* ys,
+                           const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
+                           double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
+                           const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
+                           double* self_w, hipStream_t s);
 
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p

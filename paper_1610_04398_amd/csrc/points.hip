@@ -148,15 +148,11 @@ __global__ void k_gather_points(const int* __restrict__ perm, const int* __restr
 
 // One wave per source leaf: offsets from the leaf corner in units of u, FP32
 // (with the weight) and FP64, and the FP64 leaf weight in a fixed order.
-__global__ __launch_bounds__(256) void k_pack_points(TreeArrays t, const int* __restrict__ sleaves, int n, int D,
-                                                      const double* __restrict__ xs, const double* __restrict__ ys,
-                                                      const double* __restrict__ ws, double x0, double y0, double u,
-                                                      float* __restrict__ s32, int64_t stride,
-                                                      double2* __restrict__ s64,
-                                                      double* __restrict__ leaf_w) {
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (wid >= n) return;
-  const int lane = threadIdx.x % kWave;
+__device__ inline void pack_point_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
+                                       const double* __restrict__ xs, const double* __restrict__ ys,
+                                       const double* __restrict__ ws, double x0, double y0, double u,
+                                       float* __restrict__ s32, int64_t stride, double2* __restrict__ s64,
+                                       double* __restrict__ leaf_w) {
   const int c = sleaves[wid];
   const int sh = D - t.lvl[c];
   const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
@@ -182,16 +178,13 @@ __global__ __launch_bounds__(256) void k_pack_points(TreeArrays t, const int* __
 // the owning leaf, and the summed weight of the sources that coincide exactly
 // with the target (they are skipped by the near-field kernel, and the finalize
 // step removes their share of the near weight).
-__global__ __launch_bounds__(256) void k_prep_points(TreeArrays t, const int* __restrict__ tleaves, int n, int D,
-                                                      const double* __restrict__ tx, const double* __restrict__ ty,
-                                                      const int* __restrict__ perm, double x0, double y0, double u,
-                                                      const double* __restrict__ xs, const double* __restrict__ ys,
-                                                      const double* __restrict__ ws, float2* __restrict__ rel32,
-                                                      double2* __restrict__ rel64, int* __restrict__ tleaf,
-                                                      double* __restrict__ self_w) {
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (wid >= n) return;
-  const int lane = threadIdx.x % kWave;
+__device__ inline void prep_point_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ tleaves, int D,
+                                       const double* __restrict__ tx, const double* __restrict__ ty,
+                                       const int* __restrict__ perm, double x0, double y0, double u,
+                                       const double* __restrict__ xs, const double* __restrict__ ys,
+                                       const double* __restrict__ ws, float2* __restrict__ rel32,
+                                       double2* __restrict__ rel64, int* __restrict__ tleaf,
+                                       double* __restrict__ self_w) {
   const int c = tleaves[wid];
   const int sh = D - t.lvl[c];
   const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
@@ -208,6 +201,37 @@ __global__ __launch_bounds__(256) void k_prep_points(TreeArrays t, const int* __
     rel32[k] = make_float2((float)rx, (float)ry);
     tleaf[k] = c;
     self_w[k] = sw;
+  }
+}
+
+// Both per-leaf passes in one launch (they are independent): the first
+// workgroups pack the source leaves, the rest prepare the target leaves.
+struct PointFrame {
+  double x0, y0, u;
+  const double* xs;
+  const double* ys;
+  const double* ws;
+};
+__global__ __launch_bounds__(256) void k_pack_prep_points(TreeArrays t, int D, PointFrame fr,
+                                                           const int* __restrict__ sleaves, int ns,
+                                                           float* __restrict__ s32, int64_t stride,
+                                                           double2* __restrict__ s64, double* __restrict__ leaf_w,
+                                                           int pack_blocks, const int* __restrict__ tleaves, int nt,
+                                                           const double* __restrict__ tx,
+                                                           const double* __restrict__ ty,
+                                                           const int* __restrict__ perm, float2* __restrict__ rel32,
+                                                           double2* __restrict__ rel64, int* __restrict__ tleaf,
+                                                           double* __restrict__ self_w) {
+  const int lane = threadIdx.x % kWave;
+  if ((int)blockIdx.x < pack_blocks) {
+    const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (wid < ns)
+      pack_point_leaf(wid, lane, t, sleaves, D, fr.xs, fr.ys, fr.ws, fr.x0, fr.y0, fr.u, s32, stride, s64, leaf_w);
+  } else {
+    const int wid = (blockIdx.x - pack_blocks) * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (wid < nt)
+      prep_point_leaf(wid, lane, t, tleaves, D, tx, ty, perm, fr.x0, fr.y0, fr.u, fr.xs, fr.ys, fr.ws, rel32, rel64,
+                      tleaf, self_w);
   }
 }
 }  // namespace
@@ -236,21 +260,17 @@ void points_gather(const int* perm, const int* nsrc_dev, int64_t nmax, const dou
   k_gather_points<<<(unsigned)((nmax + 255) / 256), 256, 0, s>>>(perm, nsrc_dev, sx, sy, w, xs, ys, ws);
 }
 
-void leaf_pack_points(TreeArrays t, const int* sleaves, int nsleaves, int D, const double* xs, const double* ys,
-                      const double* ws, double x0, double y0, double u, float* s32, int64_t stride, double2* s64,
-                      double* leaf_w,
-                      hipStream_t s) {
-  if (nsleaves <= 0) return;
-  k_pack_points<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, xs, ys, ws, x0, y0, u, s32, stride, s64,
-                                                   leaf_w);
-}
-
-void leaf_prep_points(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
-                      const int* perm, double x0, double y0, double u, const double* xs, const double* ys,
-                      const double* ws, float2* rel32, double2* rel64, int* tleaf, double* self_w, hipStream_t s) {
-  if (ntleaves <= 0) return;
-  k_prep_points<<<(ntleaves + 3) / 4, 256, 0, s>>>(t, tleaves, ntleaves, D, tx, ty, perm, x0, y0, u, xs, ys, ws,
-                                                    rel32, rel64, tleaf, self_w);
+void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, const double* xs, const double* ys,
+                           const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
+                           double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
+                           const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
+                           double* self_w, hipStream_t s) {
+  const int gp = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
+  const int gt = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
+  if (gp + gt <= 0) return;
+  const PointFrame fr{x0, y0, u, xs, ys, ws};
+  k_pack_prep_points<<<gp + gt, 256, 0, s>>>(t, D, fr, sleaves, nsleaves, s32, stride, s64, leaf_w, gp, tleaves,
+                                             ntleaves, tx, ty, perm, rel32, rel64, tleaf, self_w);
 }
 
 }  // namespace pp

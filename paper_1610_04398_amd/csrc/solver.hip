@@ -634,15 +634,16 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   for (int v : lstart) key2.push_back((uint64_t)v);
 
   // ---- segment 2: lists, expansions, near field, finalize; ends with the read-back ----
-  // Dependencies: the upward pass needs only the packed source leaves; the lists
-  // need only the tree; the near field needs the lists and both packings; the
-  // M2L (or M2P) needs the lists and the upward pass.  So after the source
-  // packing the work forks: the side stream builds the lists, prepares the
-  // targets and runs the near field, while the caller's stream runs the upward
-  // pass, waits for the lists, runs the M2L and downward passes, and finally
-  // waits for the near field before the finalize step.  Each stream's work fills
-  // compute units the other leaves idle.  Timing mode 1 keeps every phase on one
-  // stream, in phase order, so that its per-phase events mean something.
+  // Dependencies: the upward pass and the lists need only segment 1 (P2M forms
+  // its source offsets itself); the near field needs the lists and both
+  // packings; the M2L (or M2P) needs the lists and the upward pass.  So the
+  // work forks: the side stream builds the lists, prepares the targets and
+  // runs the near field, while the caller's stream runs the upward pass, waits
+  // for the lists, runs the M2L and downward passes, and finally waits for the
+  // near field before the finalize step.
+  // Each stream's work fills compute units the other leaves idle.  Timing mode
+  // 1 keeps every phase on one stream, in phase order, so that its per-phase
+  // events mean something.
   hipStream_t ss = s;
   if (c.profiling != 1 && c.near_stream) {
     if (!c.side_stream) HIPCHK(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
@@ -679,35 +680,32 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     }
     pa.list_src = p2p_src;
   };
-  auto do_pack_sources = [&](hipStream_t q) {
+  // source packing and target preparation, one launch
+  auto do_pack_prep = [&](hipStream_t q) {
     if (src.grid)
-      leaf_pack_sources(ta, sleaves, nsl, D, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, q);
+      leaf_pack_prep(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d, ty_d,
+                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd, q);
     else
-      leaf_pack_points(ta, sleaves, nsl, D, pxs, pys, sw, x0, y0, unit, s32, std::max<int64_t>(N, 1), s64, leaf_w,
-                       q);
+      leaf_pack_prep_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
+                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw, q);
   };
-  auto do_prep_targets = [&](hipStream_t q) {
-    if (src.grid)
-      leaf_prep_targets(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d,
-                        rel32, rel64, tgtleaf, selfw, selfd, q);
-    else
-      leaf_prep_points(ta, tleaves, ntl, D, tx_d, ty_d, tperm, x0, y0, unit, pxs, pys, sw, rel32, rel64, tgtleaf,
-                       selfw, q);
-  };
-  auto do_upward = [&] {
+  auto do_p2m = [&] {
     mark(PP_PHASE_P2M);
-    if (direct) {
-      mark(PP_PHASE_M2M);
-      return;
-    }
-    p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, s);
+    if (!direct) p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, s);
+  };
+  auto do_m2m = [&] {
     mark(PP_PHASE_M2M);
+    if (direct) return;
     // the recursion from the finest level up, several levels per launch
     const int ml = m2m_max_levels();
     for (int top = depth - 1; top >= 0; top -= ml) {
       const int L = std::max(top - (ml - 1), 0);
       m2m_levels(tv, lstart[L], lstart[L + 1], L, top - L + 1, p, mp, dflag, doff, Ld, s);
     }
+  };
+  auto do_upward = [&] {
+    do_p2m();
+    do_m2m();
   };
   auto do_downward = [&] {
     if (direct) {
@@ -744,10 +742,17 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(12);
     publish_enqueue(c, misc, M_PAIRS + 2, s);
   };
-  // side-stream part before the near field
-  auto side_lists = [&] {
+  // The two streams' launches before the near field, interleaved for the
+  // directly issued schedule: the host issues launches one at a time, so each
+  // stream gets its first kernel at once rather than after all of the other
+  // stream's launches, and the upward pass runs beside the list building
+  // (kernels that leave most of the GPU idle) rather than beside the near
+  // field, which fills it.
+  auto fork_work = [&] {
+    do_pack_prep(ss);
+    do_p2m();
     if (!lists_early) do_lists(ss);
-    do_prep_targets(ss);
+    do_m2m();
   };
 
   const int seq2 = published_seq(c) + 1;
@@ -759,16 +764,15 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // launches: each graph launch delays its first kernel).  Segment 1 is
     // complete (the host has seen its read-back), so the side stream starts
     // without waiting on s: packing, lists and target preparation, then the
-    // near field.  The upward pass runs meanwhile on s, which then waits for
-    // the lists (M2L, L2L, L2P) and for the near field (finalize).
+    // near field.  The upward pass runs meanwhile on s (its launches issued
+    // between the side stream's), which then waits for the lists (M2L, L2L,
+    // L2P) and for the near field (finalize).
     if (lists_early) do_lists(s);
-    do_pack_sources(ss);
-    side_lists();
+    fork_work();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
     do_near(ss);
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
-    do_upward();
     if (ss != s) HIPCHK(hipStreamWaitEvent(s, c.ev_lists, 0));
     do_downward();
     signal(c.ev_join, ss, s);
@@ -779,8 +783,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       mark(PP_PHASE_LISTS);
       do_lists(s);
       mark(PP_PHASE_PACK);
-      do_pack_sources(s);
-      do_prep_targets(s);
+      do_pack_prep(s);
       do_upward();
       do_downward();
       mark(PP_PHASE_P2P);
@@ -788,11 +791,14 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       do_finalize();
     });
   } else {
+    // Captured in phase order: the graph runs the side branch's kernels before
+    // the upward pass whatever the order of capture, and a fork at the start of
+    // the segment (two root nodes) was measured to delay the first kernels.
     if (lists_early) do_lists(s);
     run_segment(c, 1, replayable, key2, s, [&] {
-      do_pack_sources(s);
+      do_pack_prep(s);
       signal(c.ev_fork, s, ss);
-      side_lists();
+      if (!lists_early) do_lists(ss);
       HIPCHK(hipEventRecord(c.ev_lists, ss));
       do_near(ss);
       do_upward();

@@ -384,13 +384,10 @@ __global__ __launch_bounds__(kClsBlock) void k_classify_emit(TreeArrays t, const
 
 // One wave per source leaf: FP32 record (x, y relative to the leaf corner in
 // units of h, w) per source; leaf weight sum in FP64 in a fixed order.
-__global__ __launch_bounds__(256) void k_pack_sources(TreeArrays t, const int* __restrict__ sleaves, int n, int D,
-                                                       const uint32_t* __restrict__ ij, const double* __restrict__ w64,
-                                                       float* __restrict__ s32, int64_t stride,
-                                                       double* __restrict__ leaf_w) {
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (wid >= n) return;
-  const int lane = threadIdx.x % kWave;
+// One wave packs source leaf sleaves[wid].
+__device__ inline void pack_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
+                                 const uint32_t* __restrict__ ij, const double* __restrict__ w64,
+                                 float* __restrict__ s32, int64_t stride, double* __restrict__ leaf_w) {
   const int c = sleaves[wid];
   const int sh = D - t.lvl[c];
   const int cx = t.ix[c] << sh, cy = t.iy[c] << sh;
@@ -418,17 +415,14 @@ __device__ inline double node_coord(double x0, int i, double h) {
   return x0 + a;
 }
 
-__global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* __restrict__ tleaves, int n, int D,
-                                                       const double* __restrict__ tx, const double* __restrict__ ty,
-                                                       const int* __restrict__ perm, double x0, double y0, double h,
-                                                       int nx, int ny, double snap_frac2,
-                                                       const double* __restrict__ f, float2* __restrict__ rel32,
-                                                       double2* __restrict__ rel64, int* __restrict__ tleaf,
-                                                       double* __restrict__ self_w, double* __restrict__ self_logd) {
+// One wave prepares the targets of target leaf tleaves[wid].
+__device__ inline void prep_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ tleaves, int D,
+                                 const double* __restrict__ tx, const double* __restrict__ ty,
+                                 const int* __restrict__ perm, double x0, double y0, double h, int nx, int ny,
+                                 double snap_frac2, const double* __restrict__ f, float2* __restrict__ rel32,
+                                 double2* __restrict__ rel64, int* __restrict__ tleaf, double* __restrict__ self_w,
+                                 double* __restrict__ self_logd) {
 #pragma clang fp contract(off)
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (wid >= n) return;
-  const int lane = threadIdx.x % kWave;
   const int c = tleaves[wid];
   const int sh = D - t.lvl[c];
   const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
@@ -461,6 +455,47 @@ __global__ __launch_bounds__(256) void k_prep_targets(TreeArrays t, const int* _
     tleaf[k] = c;
     self_w[k] = sw;
     self_logd[k] = lg;
+  }
+}
+
+// Both per-leaf passes in one launch (they are independent): the first
+// workgroups pack the source leaves, the rest prepare the target leaves.
+struct PackArgs {
+  const int* sleaves;
+  int ns;
+  const uint32_t* ij;
+  const double* w64;
+  float* s32;
+  int64_t stride;
+  double* leaf_w;
+};
+struct PrepArgs {
+  const int* tleaves;
+  int nt;
+  const double* tx;
+  const double* ty;
+  const int* perm;
+  double x0, y0, h;
+  int nx, ny;
+  double snap_frac2;
+  const double* f;
+  float2* rel32;
+  double2* rel64;
+  int* tleaf;
+  double* self_w;
+  double* self_logd;
+};
+
+__global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs a, int pack_blocks, PrepArgs b) {
+  const int lane = threadIdx.x % kWave;
+  if ((int)blockIdx.x < pack_blocks) {
+    const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (wid < a.ns) pack_leaf(wid, lane, t, a.sleaves, D, a.ij, a.w64, a.s32, a.stride, a.leaf_w);
+  } else {
+    const int wid = (blockIdx.x - pack_blocks) * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (wid < b.nt)
+      prep_leaf(wid, lane, t, b.tleaves, D, b.tx, b.ty, b.perm, b.x0, b.y0, b.h, b.nx, b.ny, b.snap_frac2, b.f,
+                b.rel32, b.rel64, b.tleaf, b.self_w, b.self_logd);
   }
 }
 
@@ -509,19 +544,18 @@ void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int
   k_classify_emit<<<g, kClsBlock, 0, s>>>(t, ncells_dev, part, sleaves, tleaves, tcells, counts);
 }
 
-void leaf_pack_sources(TreeArrays t, const int* sleaves, int nsleaves, int D, const uint32_t* ij, const double* w64,
-                       float* s32, int64_t stride, double* leaf_w, hipStream_t s) {
-  if (nsleaves <= 0) return;
-  k_pack_sources<<<(nsleaves + 3) / 4, 256, 0, s>>>(t, sleaves, nsleaves, D, ij, w64, s32, stride, leaf_w);
-}
-
-void leaf_prep_targets(TreeArrays t, const int* tleaves, int ntleaves, int D, const double* tx, const double* ty,
-                       const int* perm, double x0, double y0, double h, int nx, int ny, double snap_frac2,
-                       const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                       double* self_logd, hipStream_t s) {
-  if (ntleaves <= 0) return;
-  k_prep_targets<<<(ntleaves + 3) / 4, 256, 0, s>>>(t, tleaves, ntleaves, D, tx, ty, perm, x0, y0, h, nx, ny,
-                                                     snap_frac2, f, rel32, rel64, tleaf, self_w, self_logd);
+void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const uint32_t* ij, const double* w64,
+                    float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
+                    const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
+                    double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
+                    double* self_logd, hipStream_t s) {
+  const int gp = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
+  const int gt = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
+  if (gp + gt <= 0) return;
+  const PackArgs a{sleaves, nsleaves, ij, w64, s32, stride, leaf_w};
+  const PrepArgs b{tleaves, ntleaves, tx, ty, perm, x0, y0, h, nx, ny, snap_frac2, f, rel32, rel64, tleaf, self_w,
+                   self_logd};
+  k_pack_prep<<<gp + gt, 256, 0, s>>>(t, D, a, gp, b);
 }
 
 }  // namespace pp
