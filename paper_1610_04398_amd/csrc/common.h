@@ -36,6 +36,33 @@ __host__ __device__ inline cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + 
 __host__ __device__ inline cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __host__ __device__ inline cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
 
+// L2P at one target: Re sum_l L'_l u^l by Horner with u = (t - z_c) / s_c, from
+// the target's offset r to its leaf's corner (units of h) and the leaf at level
+// lvl of a root with 2^D cells per side.  FP32 arithmetic for the mixed path
+// (coefficients rounded as read), FP64 otherwise.
+__device__ inline double l2p_eval(const double2* __restrict__ L, int p, double2 r, int D, int lvl, bool fp32) {
+  const double side = (double)(1 << (D - lvl)), inv = ldexp(1.0, lvl - D);
+  if (fp32) {
+    const float ux = (float)((r.x - 0.5 * side) * inv), uy = (float)((r.y - 0.5 * side) * inv);
+    float ax = 0.f, ay = 0.f;
+    for (int l = p; l >= 0; --l) {
+      const double2 v = L[l];
+      const float nx = ax * ux - ay * uy + (float)v.x;
+      const float ny = ax * uy + ay * ux + (float)v.y;
+      ax = nx;
+      ay = ny;
+    }
+    return (double)ax;
+  }
+  const cplx u = {(r.x - 0.5 * side) * inv, (r.y - 0.5 * side) * inv};
+  cplx acc = {0.0, 0.0};
+  for (int l = p; l >= 0; --l) {
+    const double2 v = L[l];
+    acc = cadd(cmul(acc, u), {v.x, v.y});
+  }
+  return acc.x;
+}
+
 // Morton bit spreading: bit b of v goes to bit 2b.
 __host__ __device__ inline uint32_t spread_bits(uint32_t v) {
   v &= 0xFFFFu;

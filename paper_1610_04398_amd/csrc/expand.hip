@@ -382,98 +382,102 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
 // recursion "local(child) = own M2L + L2L(local(parent))" equals the sum, over
 // the cell and each of its ancestors X, of X's own M2L local shifted from X's
 // centre to the cell:  L'_m = sum_X 2^{-m (l_c - l_X)} sum_{k>=m} C(k, m) d_X^{k-m} L'_k(X),
-// d_X = (z_c - z_X) / s_X.  Eight lanes per (cell with targets, coefficient m):
-// lane j takes the ancestors at levels j and j + 8 (the cell itself at its own
-// level), and a fixed butterfly over the eight lanes adds the terms.  An
-// ancestor at a level of the dense prefix table is found there directly from
-// the cell's coordinates; deeper ones by following parent links.
-constexpr int kDownLanes = 8;
-__global__ void k_downward(TreeView t, const int* __restrict__ tcells, int n, int p, const double2* __restrict__ own,
-                           double2* __restrict__ loc, const int* __restrict__ dense_off, int dense_levels) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// d_X = (z_c - z_X) / s_X.  Sixteen lanes per cell with targets (four cells per
+// wave): lane j takes the ancestor at level j (and j + 16), loads its p + 1 own
+// coefficients once, shifts them to the cell in place by synthetic division (a
+// Taylor shift by d_X: p (p + 1) / 2 complex multiply-adds) and scales
+// coefficient m by 2^{-m (l_c - l_X)}; the cell itself (j = l_c) contributes its
+// own local unshifted.  The lanes' terms are then added through LDS, lane m of
+// the cell summing coefficient m over the levels in ascending order (a fixed
+// order, so the result is reproducible).  An ancestor at a level of the dense
+// prefix table is found there directly from the cell's coordinates; deeper ones
+// by following parent links.
+constexpr int kDownLanes = 16;
+template <int PM>
+__global__ __launch_bounds__(kWave) void k_downward(TreeView t, const int* __restrict__ tcells, int n, int p,
+                                                    const double2* __restrict__ own, double2* __restrict__ loc,
+                                                    const int* __restrict__ dense_off, int dense_levels) {
+  __shared__ double2 red[kWave][PM + 1];
+  const int lane = threadIdx.x;
+  const int sub = lane % kDownLanes;
+  const int grp = lane / kDownLanes;
+  const int i = blockIdx.x * (kWave / kDownLanes) + grp;
+  const bool live = i < n;
   const int P1 = p + 1;
-  const int lane = (int)(w % kDownLanes);
-  const int64_t item = w / kDownLanes;
-  const int i = (int)(item / P1);
-  const int m = (int)(item % P1);
-  const bool live = i < n;  // all lanes of an item agree; the butterfly needs every lane
-  const int c = live ? tcells[i] : 0;
   const int D = t.D;
-  const int lc = live ? t.lvl[c] : 0;
+  const int c = live ? tcells[i] : 0;
+  const int lc = live ? t.lvl[c] : -1;
   const int icx = live ? t.ix[c] : 0, icy = live ? t.iy[c] : 0;
-  const double sc = cell_side(D, lc);
+  const double sc = cell_side(D, live ? lc : 0);
   const double cx = (icx + 0.5) * sc, cy = (icy + 0.5) * sc;
-  cplx acc = {0.0, 0.0};
-  for (int j = lane; live && j <= lc; j += kDownLanes) {
-    if (j == lc) {
-      const double2 v = own[(int64_t)c * P1 + m];
-      acc = cadd(acc, {v.x, v.y});
+  cplx acc[PM + 1];
+#pragma unroll
+  for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
+  for (int a = sub; a <= lc; a += kDownLanes) {
+    if (a == lc) {
+#pragma unroll
+      for (int k = 0; k <= PM; ++k)
+        if (k <= p) {
+          const double2 v = own[(int64_t)c * P1 + k];
+          acc[k] = cadd(acc[k], {v.x, v.y});
+        }
       continue;
     }
-    const int sh = lc - j;
-    const int ax = icx >> sh, ay = icy >> sh;  // the ancestor's coordinates at level j
+    const int sh = lc - a;
+    const int ax = icx >> sh, ay = icy >> sh;  // the ancestor's coordinates at level a
     int X;
-    if (j <= dense_levels) {
-      X = dense_off[((((int64_t)1 << (2 * j)) - 1) / 3) + (int64_t)morton((uint32_t)ax, (uint32_t)ay)];
+    if (a <= dense_levels) {
+      X = dense_off[((((int64_t)1 << (2 * a)) - 1) / 3) + (int64_t)morton((uint32_t)ax, (uint32_t)ay)];
     } else {
       X = c;
-      for (int l = lc; l > j; --l) X = t.parent[X];
+      for (int l = lc; l > a; --l) X = t.parent[X];
     }
-    const double sX = cell_side(D, j), iX = inv_cell_side(D, j);
+    const double sX = cell_side(D, a), iX = inv_cell_side(D, a);
     const cplx d = {(cx - (ax + 0.5) * sX) * iX, (cy - (ay + 0.5) * sX) * iX};
-    const double2* L = own + (int64_t)X * P1;
-    cplx s = {0.0, 0.0};
-    cplx dp = {1.0, 0.0};
-    for (int k = m; k <= p; ++k) {
-      const double2 v = L[k];
-      s = cadd(s, cscale(cmul({v.x, v.y}, dp), binom(k, m)));
-      dp = cmul(dp, d);
+    cplx L[PM + 1];
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) {
+      if (k <= p) {
+        const double2 v = own[(int64_t)X * P1 + k];
+        L[k] = {v.x, v.y};
+      } else {
+        L[k] = {0.0, 0.0};
+      }
     }
-    acc = cadd(acc, cscale(s, ldexp(1.0, -m * (lc - j))));
+    // Taylor shift by d: afterwards L[m] = sum_{k>=m} C(k, m) d^{k-m} L[k]
+#pragma unroll
+    for (int r = 0; r < PM; ++r)
+#pragma unroll
+      for (int k = PM - 1; k >= r; --k)
+        if (k < p) L[k] = cadd(L[k], cmul(d, L[k + 1]));
+    const double f = ldexp(1.0, -sh);  // s_c / s_X
+    double g = 1.0;
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) {
+      acc[k] = cadd(acc[k], cscale(L[k], g));
+      g *= f;  // exact: a power of two
+    }
   }
 #pragma unroll
-  for (int o = kDownLanes / 2; o > 0; o >>= 1) {
-    acc.x += __shfl_xor(acc.x, o, kDownLanes);
-    acc.y += __shfl_xor(acc.y, o, kDownLanes);
+  for (int k = 0; k <= PM; ++k) red[lane][k] = make_double2(acc[k].x, acc[k].y);
+  __syncthreads();
+  if (!live) return;
+  for (int m = sub; m <= p; m += kDownLanes) {
+    cplx s = {0.0, 0.0};
+    for (int q = 0; q < kDownLanes; ++q) {
+      const double2 v = red[grp * kDownLanes + q][m];
+      s = cadd(s, {v.x, v.y});
+    }
+    loc[(int64_t)c * P1 + m] = make_double2(s.x, s.y);
   }
-  if (live && lane == 0) loc[(int64_t)c * P1 + m] = make_double2(acc.x, acc.y);
 }
 
-__global__ void k_l2p64(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
-                        const double2* __restrict__ rel64, double* __restrict__ far) {
+__global__ void k_l2p(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
+                      const double2* __restrict__ rel64, int fp32, double* __restrict__ far) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const int c = tleaf[k];
-  const double side = cell_side(t.D, t.lvl[c]), inv = inv_cell_side(t.D, t.lvl[c]);
-  const double2 r = rel64[k];
-  const cplx u = {(r.x - 0.5 * side) * inv, (r.y - 0.5 * side) * inv};
-  const double2* L = loc + (int64_t)c * (p + 1);
-  cplx acc = {0.0, 0.0};
-  for (int l = p; l >= 0; --l) {
-    const double2 v = L[l];
-    acc = cadd(cmul(acc, u), {v.x, v.y});
-  }
-  far[k] = acc.x;
-}
-
-__global__ void k_l2p32(TreeView t, int64_t m, const int* __restrict__ tleaf, int p, const double2* __restrict__ loc,
-                        const double2* __restrict__ rel64, double* __restrict__ far) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m) return;
-  const int c = tleaf[k];
-  const double side = cell_side(t.D, t.lvl[c]), inv = inv_cell_side(t.D, t.lvl[c]);
-  const double2 r = rel64[k];
-  const float ux = (float)((r.x - 0.5 * side) * inv), uy = (float)((r.y - 0.5 * side) * inv);
-  const double2* L = loc + (int64_t)c * (p + 1);
-  float ax = 0.f, ay = 0.f;
-  for (int l = p; l >= 0; --l) {
-    const double2 v = L[l];
-    const float nx = ax * ux - ay * uy + (float)v.x;
-    const float ny = ax * uy + ay * ux + (float)v.y;
-    ax = nx;
-    ay = ny;
-  }
-  far[k] = (double)ax;
+  far[k] = l2p_eval(loc + (int64_t)c * (p + 1), p, rel64[k], t.D, t.lvl[c], fp32 != 0);
 }
 
 // M2P of the paper's tree-code (eq. pressTruncated evaluated at the targets):
@@ -643,19 +647,15 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
 
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, const int* dense_off,
               int dense_levels, hipStream_t s) {
-  const int64_t w = (int64_t)n * (p + 1) * kDownLanes;
-  if (w <= 0) return;
-  k_downward<<<(unsigned)((w + 255) / 256), 256, 0, s>>>(t, tcells, n, p, own, loc, dense_off, dense_levels);
+  if (n <= 0) return;
+  const unsigned g = (unsigned)((n + kWave / kDownLanes - 1) / (kWave / kDownLanes));
+  PP_DISPATCH(p, k_downward, g, kWave, s, t, tcells, n, p, own, loc, dense_off, dense_levels);
 }
 
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,
          double* far, hipStream_t s) {
   if (m <= 0) return;
-  const unsigned g = (unsigned)((m + 255) / 256);
-  if (fp32)
-    k_l2p32<<<g, 256, 0, s>>>(t, m, tleaf, p, loc, rel64, far);
-  else
-    k_l2p64<<<g, 256, 0, s>>>(t, m, tleaf, p, loc, rel64, far);
+  k_l2p<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(t, m, tleaf, p, loc, rel64, fp32, far);
 }
 
 void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,

@@ -1,6 +1,7 @@
 // Final assembly of P at each target (Appendix A, superposition of the group
-// contributions): far field from the local expansion plus the near field, with
-// the 1/(2 pi) of eq. green2D, scattered back to the caller's target order.
+// contributions): far field from the local expansion (read, or evaluated here
+// by L2P) plus the near field, with the 1/(2 pi) of eq. green2D, scattered back
+// to the caller's target order.
 //
 // The near-field kernel leaves, per target and list part, sum w ln r over the
 // part's near sources (its own leaf included).  A target that coincides with a
@@ -34,12 +35,12 @@ __device__ inline long long wave_sum(long long v) {
 // counter) into zeroed slots, so they need no launch of their own and add
 // little to the launch's critical path.
 __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, const int* __restrict__ perm,
-                                                         const double* __restrict__ far,
+                                                         double* __restrict__ far,
                                                          const double* __restrict__ near_sum,
                                                          const double* __restrict__ self_w,
                                                          const double* __restrict__ self_logd, double lnh,
                                                          int self_mode, const int* __restrict__ flags,
-                                                         double* __restrict__ out, FinalizeTotals tot) {
+                                                         double* __restrict__ out, FinalizeTotals tot, FarEval fe) {
   const int64_t tot_n = std::max<int64_t>(tot.pairs ? tot.nwaves : 0, tot.cnt_m ? tot.ncells : 0);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int64_t)blockIdx.x * kFinBlock < tot_n) {  // uniform per workgroup
@@ -74,7 +75,15 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, c
   if (*flags != 0) return;
   double ns = near_sum[k];
   for (int q = 1; q < nparts; ++q) ns += near_sum[(int64_t)q * m + k];
-  double v = (far ? far[k] : 0.0) + ns;
+  double fv;
+  if (fe.loc) {
+    const int c = fe.tleaf[k];
+    fv = l2p_eval(fe.loc + (int64_t)c * (fe.p + 1), fe.p, fe.rel64[k], fe.D, fe.lvl[c], fe.fp32 != 0);
+    if (far) far[k] = fv;  // kept for the far-field array read-back
+  } else {
+    fv = far ? far[k] : 0.0;
+  }
+  double v = fv + ns;
   if (self_w) {
     const double w = self_w[k];
     const double lg = self_logd ? self_logd[k] : -INFINITY;
@@ -88,14 +97,14 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, c
 }
 }  // namespace
 
-void finalize(int64_t m, int nparts, const int* perm, const double* far, const double* near_sum,
+void finalize(int64_t m, int nparts, const int* perm, double* far, const double* near_sum,
               const double* self_w, const double* self_logd, double h, int self_mode, const int* flags, double* out,
-              const FinalizeTotals& tot, hipStream_t s) {
+              const FinalizeTotals& tot, const FarEval& fe, hipStream_t s) {
   const int64_t tot_n = std::max<int64_t>(tot.pairs ? tot.nwaves : 0, tot.cnt_m ? tot.ncells : 0);
   const int64_t blocks = (std::max(m, tot_n) + kFinBlock - 1) / kFinBlock;
   if (blocks <= 0) return;
   k_finalize<<<(unsigned)blocks, kFinBlock, 0, s>>>(m, nparts, perm, far, near_sum, self_w, self_logd, log(h),
-                                                    self_mode, flags, out, tot);
+                                                    self_mode, flags, out, tot, fe);
 }
 
 }  // namespace pp

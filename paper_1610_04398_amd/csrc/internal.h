@@ -234,12 +234,21 @@ struct FinalizeTotals {
   int* tot_m = nullptr;
   int* tot_p = nullptr;
 };
+// The far field evaluated inside the finalize launch (L2P, as l2p) when loc is
+// set; it is then written to far (if not null) rather than read from it.
+struct FarEval {
+  const double2* loc = nullptr;
+  const double2* rel64 = nullptr;
+  const int* tleaf = nullptr;
+  const int* lvl = nullptr;
+  int D = 0, p = 0, fp32 = 0;
+};
 // self_w (may be null): per target the weight of the source it coincides with
 // (grid node or scattered sources), 0 for none; self_logd (may be null: exact
 // coincidence throughout) the log of the distance to that node, -inf if exact.
-void finalize(int64_t m, int nparts, const int* perm, const double* far, const double* near_sum,
+void finalize(int64_t m, int nparts, const int* perm, double* far, const double* near_sum,
               const double* self_w, const double* self_logd, double h, int self_mode, const int* flags, double* out,
-              const FinalizeTotals& tot, hipStream_t s);
+              const FinalizeTotals& tot, const FarEval& fe, hipStream_t s);
 
 // ---- forces.hip: pressure forces on surfaces -----------------------------------------
 // One workgroup per segment seg[s]..seg[s+1] (device array of nseg + 1); dfx/dfy may be null.

@@ -707,6 +707,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     do_p2m();
     do_m2m();
   };
+  // L2P runs inside the finalize launch (one launch fewer after the near
+  // field), except in timing mode 1, which times it as a phase of its own
+  const bool fuse_l2p = !direct && !treecode && c.profiling != 1;
   auto do_downward = [&] {
     if (direct) {
       for (int ph = PP_PHASE_M2L; ph <= PP_PHASE_L2P; ++ph) mark(ph);
@@ -723,7 +726,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       mark(PP_PHASE_L2L);
       downward(tv, tcells, ntc, p, own, loc, doff, Ld, s);
       mark(PP_PHASE_L2P);
-      l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
+      if (!fuse_l2p) l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
     }
   };
   auto do_near = [&](hipStream_t q) { p2p(pa, mixed ? 0 : 1, q); };
@@ -738,7 +741,17 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     tot.ncells = ncells;
     tot.tot_m = misc + M_NM2L;
     tot.tot_p = misc + M_NP2P;
-    finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, s);
+    FarEval fe;
+    if (fuse_l2p) {
+      fe.loc = loc;
+      fe.rel64 = rel64;
+      fe.tleaf = tgtleaf;
+      fe.lvl = tv.lvl;
+      fe.D = D;
+      fe.p = p;
+      fe.fp32 = mixed ? 1 : 0;
+    }
+    finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, fe, s);
     mark(12);
     publish_enqueue(c, misc, M_PAIRS + 2, s);
   };
