@@ -487,9 +487,11 @@ __global__ void k_l2p(TreeView t, int64_t m, const int* __restrict__ tleaf, int 
 // by Horner in u = 1/w.  The list is consumed 64 cells at a time: lane i
 // loads cell i's geometry (corner difference to A in units of h, 1/s_B, the
 // ln s_B term) and its coefficients into the wave's LDS slice, so the
-// evaluation loop reads only LDS broadcasts.  T = float for mixed precision
-// (coefficients rounded when staged, each cell's term added to an FP64 sum),
-// double otherwise.
+// evaluation loop reads only LDS broadcasts.  The slice holds PM + 1
+// coefficients per cell, zero above p (Horner over zeros leaves the sum
+// unchanged), so the loop is fully unrolled and its reads are issued ahead of
+// the arithmetic.  T = float for mixed precision (coefficients rounded when
+// staged, each cell's term added to an FP64 sum), double otherwise.
 constexpr double kLn2d = 0.69314718055994530942;
 constexpr int kM2PWaves = 4;
 
@@ -498,7 +500,7 @@ struct Cx2 {
   T x, y;
 };
 
-template <class T>
+template <class T, int PM>
 __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int* __restrict__ tleaves, int n,
                                                           const int* __restrict__ off, const int* __restrict__ cnt,
                                                           const int* __restrict__ src, int p, double lnh,
@@ -509,8 +511,8 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const int P1 = p + 1;
-  // per wave: kWave cells x (P1 coefficients + 2 geometry slots)
-  Cx2<T>* coef = (Cx2<T>*)m2p_lds + (size_t)w * kWave * (P1 + 2);
+  constexpr int kSlot = PM + 3;  // per cell: 2 geometry slots and PM + 1 coefficients
+  Cx2<T>* coef = (Cx2<T>*)m2p_lds + (size_t)w * kWave * kSlot;
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kM2PWaves + w));
   if (wid >= n) return;
   const int A = tleaves[wid];
@@ -530,7 +532,8 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
       // stage: lane i takes list entry base + i
       if (lane < nb) {
         int B = src[e0 + base + lane];
-        Cx2<T>* cb = coef + (size_t)lane * (P1 + 2);
+        Cx2<T>* cb = coef + (size_t)lane * kSlot;
+        for (int q = P1; q <= PM; ++q) cb[2 + q] = {(T)0, (T)0};
         if ((unsigned)B >= (unsigned)t.ncells) {
           bad = true;
           cb[0] = {(T)0, (T)0};
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (int j = 0; j < nb; ++j) {
-        const Cx2<T>* cb = coef + (size_t)j * (P1 + 2);
+        const Cx2<T>* cb = coef + (size_t)j * kSlot;
         const Cx2<T> g0 = cb[0], g1 = cb[1];
         const T wx = (rx + g0.x) * g1.x, wy = (ry + g0.y) * g1.x;
         const T r2 = wx * wx + wy * wy;
@@ -564,7 +567,8 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
           ir2 = (T)1 / r2;
         const T ux = wx * ir2, uy = -wy * ir2;
         T hx = (T)0, hy = (T)0;
-        for (int q = p; q >= 1; --q) {
+#pragma unroll
+        for (int q = PM; q >= 1; --q) {
           const Cx2<T> c = cb[2 + q];
           const T nx = hx * ux - hy * uy + c.x;
           const T ny = hx * uy + hy * ux + c.y;
@@ -658,26 +662,41 @@ void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, con
   k_l2p<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(t, m, tleaf, p, loc, rel64, fp32, far);
 }
 
+template <class T, int PM>
+void m2p_launch(unsigned g, TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
+                int p, double h, const double2* mp, const double2* rel64, double* far, int* flags, hipStream_t s) {
+  // up to 94 KB of LDS at PM = 20 in FP64 (gfx950 allows 160 KB per workgroup)
+  const size_t bytes = (size_t)kM2PWaves * kWave * (PM + 3) * sizeof(Cx2<T>);
+  static std::once_flag lds_opt_in;
+  std::call_once(lds_opt_in, [bytes] {
+    (void)hipFuncSetAttribute((const void*)k_m2p<T, PM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  });
+  k_m2p<T, PM><<<g, kM2PWaves * kWave, bytes, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp, rel64, far, flags);
+}
+
+template <class T>
+void m2p_dispatch(unsigned g, TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
+                  int p, double h, const double2* mp, const double2* rel64, double* far, int* flags, hipStream_t s) {
+  if (p <= 4)
+    m2p_launch<T, 4>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+  else if (p <= 8)
+    m2p_launch<T, 8>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+  else if (p <= 12)
+    m2p_launch<T, 12>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+  else if (p <= 16)
+    m2p_launch<T, 16>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+  else
+    m2p_launch<T, 20>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+}
+
 void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
          const double2* mp, const double2* rel64, int fp32, double* far, int* flags, hipStream_t s) {
   if (n <= 0) return;
   const unsigned g = (unsigned)((n + kM2PWaves - 1) / kM2PWaves);
-  const size_t per = (size_t)kM2PWaves * kWave * (p + 3);
-  // up to 94 KB of LDS at p = 20 in FP64 (gfx950 allows 160 KB per workgroup)
-  static std::once_flag lds_opt_in;
-  std::call_once(lds_opt_in, [] {
-    const size_t most = (size_t)kM2PWaves * kWave * (kMaxP + 3);
-    (void)hipFuncSetAttribute((const void*)k_m2p<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(most * sizeof(Cx2<float>)));
-    (void)hipFuncSetAttribute((const void*)k_m2p<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(most * sizeof(Cx2<double>)));
-  });
   if (fp32)
-    k_m2p<float><<<g, kM2PWaves * kWave, per * sizeof(Cx2<float>), s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp,
-                                                                         rel64, far, flags);
+    m2p_dispatch<float>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
   else
-    k_m2p<double><<<g, kM2PWaves * kWave, per * sizeof(Cx2<double>), s>>>(t, tleaves, n, off, cnt, src, p, log(h),
-                                                                           mp, rel64, far, flags);
+    m2p_dispatch<double>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
 }
 
 }  // namespace pp
