@@ -505,8 +505,9 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
                                                           const int* __restrict__ off, const int* __restrict__ cnt,
                                                           const int* __restrict__ src, int p, double lnh,
                                                           const double2* __restrict__ mp,
-                                                          const double2* __restrict__ rel64,
-                                                          double* __restrict__ far, int* __restrict__ flags) {
+                                                          const double2* __restrict__ rel64, int nparts,
+                                                          int64_t m, double* __restrict__ far,
+                                                          int* __restrict__ flags) {
   extern __shared__ double m2p_lds[];
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -514,11 +515,17 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
   constexpr int kSlot = PM + 3;  // per cell: 2 geometry slots and PM + 1 coefficients
   Cx2<T>* coef = (Cx2<T>*)m2p_lds + (size_t)w * kWave * kSlot;
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * kM2PWaves + w));
-  if (wid >= n) return;
-  const int A = tleaves[wid];
+  if (wid >= n * nparts) return;
+  // wave (leaf, part): the part's share of the leaf's list, its partial far
+  // field stored at far[part * m + k] (the finalize step adds the parts)
+  const int part = wid % nparts;
+  const int A = tleaves[wid / nparts];
   const int shA = t.D - t.lvl[A];
   const int64_t ax2 = (int64_t)(2 * t.ix[A]) << shA, ay2 = (int64_t)(2 * t.iy[A]) << shA;
-  const int e0 = off[A], ne = cnt[A];
+  const int nall = cnt[A];
+  const int e0 = off[A] + (int)((int64_t)nall * part / nparts);
+  const int ne = (int)((int64_t)nall * (part + 1) / nparts) - (int)((int64_t)nall * part / nparts);
+  double* far_part = far + (int64_t)part * m;
   const int tb = t.tb[A], te = t.te[A];
   bool bad = false;
   for (int chunk = tb; chunk < te; chunk += kWave) {
@@ -588,7 +595,7 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (active) far[k] = acc_far;
+    if (active) far_part[k] = acc_far;
   }
   if (bad && lane == 0) atomicOr(flags, kFlagBadIndex);
 }
@@ -664,39 +671,43 @@ void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, con
 
 template <class T, int PM>
 void m2p_launch(unsigned g, TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
-                int p, double h, const double2* mp, const double2* rel64, double* far, int* flags, hipStream_t s) {
+                int p, double h, const double2* mp, const double2* rel64, int nparts, int64_t m, double* far,
+                int* flags, hipStream_t s) {
   // up to 94 KB of LDS at PM = 20 in FP64 (gfx950 allows 160 KB per workgroup)
   const size_t bytes = (size_t)kM2PWaves * kWave * (PM + 3) * sizeof(Cx2<T>);
   static std::once_flag lds_opt_in;
   std::call_once(lds_opt_in, [bytes] {
     (void)hipFuncSetAttribute((const void*)k_m2p<T, PM>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   });
-  k_m2p<T, PM><<<g, kM2PWaves * kWave, bytes, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp, rel64, far, flags);
+  k_m2p<T, PM><<<g, kM2PWaves * kWave, bytes, s>>>(t, tleaves, n, off, cnt, src, p, log(h), mp, rel64, nparts, m,
+                                                   far, flags);
 }
 
 template <class T>
 void m2p_dispatch(unsigned g, TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src,
-                  int p, double h, const double2* mp, const double2* rel64, double* far, int* flags, hipStream_t s) {
+                  int p, double h, const double2* mp, const double2* rel64, int nparts, int64_t m, double* far,
+                  int* flags, hipStream_t s) {
   if (p <= 4)
-    m2p_launch<T, 4>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_launch<T, 4>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
   else if (p <= 8)
-    m2p_launch<T, 8>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_launch<T, 8>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
   else if (p <= 12)
-    m2p_launch<T, 12>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_launch<T, 12>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
   else if (p <= 16)
-    m2p_launch<T, 16>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_launch<T, 16>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
   else
-    m2p_launch<T, 20>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_launch<T, 20>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
 }
 
 void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
-         const double2* mp, const double2* rel64, int fp32, double* far, int* flags, hipStream_t s) {
+         const double2* mp, const double2* rel64, int fp32, int nparts, int64_t m, double* far, int* flags,
+         hipStream_t s) {
   if (n <= 0) return;
-  const unsigned g = (unsigned)((n + kM2PWaves - 1) / kM2PWaves);
+  const unsigned g = (unsigned)(((int64_t)n * nparts + kM2PWaves - 1) / kM2PWaves);
   if (fp32)
-    m2p_dispatch<float>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_dispatch<float>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
   else
-    m2p_dispatch<double>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, far, flags, s);
+    m2p_dispatch<double>(g, t, tleaves, n, off, cnt, src, p, h, mp, rel64, nparts, m, far, flags, s);
 }
 
 }  // namespace pp

@@ -82,6 +82,10 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, c
     if (far) far[k] = fv;  // kept for the far-field array read-back
   } else {
     fv = far ? far[k] : 0.0;
+    if (far && fe.far_parts > 1) {
+      for (int q = 1; q < fe.far_parts; ++q) fv += far[(int64_t)q * m + k];
+      far[k] = fv;  // the total, for the far-field array read-back
+    }
   }
   double v = fv + ns;
   if (self_w) {

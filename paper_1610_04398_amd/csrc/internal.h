@@ -168,11 +168,16 @@ void m2m_levels(TreeView t, int c0, int c1, int L, int levels, int p, double2* m
                 const int* dense_off, int dense_levels, hipStream_t s);
 void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2l_cnt, const int* m2l_src, int p,
          double h, const double2* mp, double2* loc, int* flags, hipStream_t s);
-// M2P of the tree-code variant: far[k] for every target of the n target leaves
-// from the multipoles of their M2P lists (off/cnt by cell id); fp32 != 0
-// evaluates in FP32.
+// List parts per target leaf in the tree-code's M2P (more, shorter waves than
+// one per leaf: the leaves with the longest lists no longer set the time).
+constexpr int kM2PParts = 4;
+// M2P of the tree-code variant: the far field of every target of the n target
+// leaves from the multipoles of their M2P lists (off/cnt by cell id), each list
+// split into nparts parts whose partial sums go to far[part * m + k] (m
+// targets); fp32 != 0 evaluates in FP32.
 void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, const int* src, int p, double h,
-         const double2* mp, const double2* rel64, int fp32, double* far, int* flags, hipStream_t s);
+         const double2* mp, const double2* rel64, int fp32, int nparts, int64_t m, double* far, int* flags,
+         hipStream_t s);
 // Final local expansion of every cell with targets from its own M2L local
 // (`own`) and its ancestors' (exact L2L shifts), one launch.
 // dense_off/dense_levels: the cell numbers of the tree build's dense prefix
@@ -236,12 +241,15 @@ struct FinalizeTotals {
 };
 // The far field evaluated inside the finalize launch (L2P, as l2p) when loc is
 // set; it is then written to far (if not null) rather than read from it.
+// Otherwise far holds far_parts partial sums per target (far[q * m + k]),
+// added here and the total written back to far[k].
 struct FarEval {
   const double2* loc = nullptr;
   const double2* rel64 = nullptr;
   const int* tleaf = nullptr;
   const int* lvl = nullptr;
   int D = 0, p = 0, fp32 = 0;
+  int far_parts = 1;
 };
 // self_w (may be null): per target the weight of the source it coincides with
 // (grid node or scattered sources), 0 for none; self_logd (may be null: exact

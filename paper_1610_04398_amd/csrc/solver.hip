@@ -573,7 +573,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   double2* mp = direct ? nullptr : ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
   double2* loc = (direct || treecode) ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
   double2* own = (direct || treecode) ? nullptr : ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
-  double* far = direct ? nullptr : ensure<double>(c, B_FAR, m);
+  // the tree-code's M2P leaves its list parts' partial sums side by side
+  const int far_parts = treecode ? kM2PParts : 1;
+  double* far = direct ? nullptr : ensure<double>(c, B_FAR, m * far_parts);
   const int nparts = c.p2p_parts;
   double* near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
   long long* pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
@@ -718,7 +720,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(PP_PHASE_M2L);
     if (treecode) {
       // multipoles evaluated at the targets; no local expansions
-      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far, misc + M_FLAGS, s);
+      m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far_parts, m, far,
+          misc + M_FLAGS, s);
       mark(PP_PHASE_L2L);
       mark(PP_PHASE_L2P);
     } else {
@@ -742,6 +745,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     tot.tot_m = misc + M_NM2L;
     tot.tot_p = misc + M_NP2P;
     FarEval fe;
+    fe.far_parts = far_parts;
     if (fuse_l2p) {
       fe.loc = loc;
       fe.rel64 = rel64;
