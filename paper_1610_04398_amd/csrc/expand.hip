@@ -303,19 +303,24 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1,
 }
 
 // G lanes per target cell: lane j of the group takes list entries j, j+G, ...
-// and accumulates their local contributions in registers; a butterfly over the
-// group (fixed order, so the result is reproducible) sums them.
+// and accumulates their local contributions in registers.  The group then
+// sums them through LDS: every lane stores its 2 (p + 1) partial values, and
+// lane q of the group adds value q over the G lanes in lane order (a fixed
+// order, so the result is reproducible).
+constexpr int kM2LBlock = 128;
 template <int PM, int G>
-__global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__ tcells, int n,
+__global__ __launch_bounds__(kM2LBlock) void k_m2l(TreeView t, const int* __restrict__ tcells, int n,
                                              const int* __restrict__ off, const int* __restrict__ cnt,
                                              const int* __restrict__ src, int p, double lnh,
                                              const double2* __restrict__ mp, double2* __restrict__ loc,
                                              int* __restrict__ flags) {
+  static_assert(2 * (PM + 1) <= 2 * G, "two partial values per coefficient and at most two per lane");
+  __shared__ double red[kM2LBlock][2 * (PM + 1)];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int gi = (int)(gtid / G);
   const int sub = (int)(gtid % G);
-  if (gi >= n) return;
-  const int A = tcells[gi];
+  const bool live = gi < n;  // whole groups agree; every lane reaches the barrier
+  const int A = live ? tcells[gi] : 0;
   const int D = t.D;
   const int lA = t.lvl[A];
   const double sA = cell_side(D, lA);
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
   cplx L[PM + 1];
 #pragma unroll
   for (int k = 0; k <= PM; ++k) L[k] = {0.0, 0.0};
-  const int e0 = off[A], ne = cnt[A];
+  const int e0 = live ? off[A] : 0, ne = live ? cnt[A] : 0;
   for (int e = sub; e < ne; e += G) {
     const int B = src[e0 + e];
     if ((unsigned)B >= (unsigned)t.ncells) {
@@ -334,7 +339,8 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
     const double sB = cell_side(D, lB);
     const cplx z0 = {(t.ix[B] + 0.5) * sB - cax, (t.iy[B] + 0.5) * sB - cay};
     const double r2 = z0.x * z0.x + z0.y * z0.y;
-    const cplx inv = {z0.x / r2, -z0.y / r2};  // 1 / z0
+    const double ir2 = 1.0 / r2;
+    const cplx inv = {z0.x * ir2, -z0.y * ir2};  // 1 / z0
     const cplx tt = cscale(inv, sA);
     const cplx mr = cscale(inv, -sB);           // -s_B / z0
     const double2* a = mp + (int64_t)B * (p + 1);
@@ -366,16 +372,18 @@ __global__ __launch_bounds__(256) void k_m2l(TreeView t, const int* __restrict__
   }
 #pragma unroll
   for (int k = 0; k <= PM; ++k) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-      L[k].x += __shfl_xor(L[k].x, o, G);
-      L[k].y += __shfl_xor(L[k].y, o, G);
-    }
+    red[threadIdx.x][2 * k] = L[k].x;
+    red[threadIdx.x][2 * k + 1] = L[k].y;
   }
-  double2* out = loc + (int64_t)A * (p + 1);
-#pragma unroll
-  for (int k = 0; k <= PM; ++k)
-    if (k <= p && (k % G) == sub) out[k] = make_double2(L[k].x, L[k].y);
+  __syncthreads();
+  if (!live) return;
+  const int g0 = (int)(threadIdx.x - sub);  // the group's first lane in the block
+  double* out = (double*)(loc + (int64_t)A * (p + 1));
+  for (int q = sub; q < 2 * (p + 1); q += G) {
+    double v = 0.0;
+    for (int j = 0; j < G; ++j) v += red[g0 + j][q];
+    out[q] = v;
+  }
 }
 
 // Downward pass in one launch.  L2L is exact for a degree-p polynomial, so the
@@ -642,18 +650,18 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
          double h, const double2* mp, double2* loc, int* flags, hipStream_t s) {
   if (n <= 0) return;
   constexpr int G = 32;
-  const unsigned g = (unsigned)(((int64_t)n * G + 255) / 256);
+  const unsigned g = (unsigned)(((int64_t)n * G + kM2LBlock - 1) / kM2LBlock);
   const double lnh = log(h);
   if (p <= 4)
-    k_m2l<4, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
+    k_m2l<4, G><<<g, kM2LBlock, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else if (p <= 8)
-    k_m2l<8, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
+    k_m2l<8, G><<<g, kM2LBlock, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else if (p <= 12)
-    k_m2l<12, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
+    k_m2l<12, G><<<g, kM2LBlock, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else if (p <= 16)
-    k_m2l<16, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
+    k_m2l<16, G><<<g, kM2LBlock, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
   else
-    k_m2l<20, G><<<g, 256, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
+    k_m2l<20, G><<<g, kM2LBlock, 0, s>>>(t, tcells, n, m2l_off, m2l_cnt, m2l_src, p, lnh, mp, loc, flags);
 }
 
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, const int* dense_off,
