@@ -131,6 +131,33 @@ struct TreeView {
   const int* parent;   // -1 for the root
 };
 
+// Per-cell setup of the interaction lists: the cell's packed traversal record
+// {ix, iy, first child, meta} with meta = level | nchild << 5 |
+// (children-with-sources mask) << 8 | has_src << 12, its list counts cleared,
+// and for the one-pass lists (cap_m > 0) the fixed-capacity offsets c * cap.
+struct RecordArgs {
+  TreeView t;
+  int4* rec;
+  int* cnt_m;
+  int* cnt_p;
+  int* off_m;
+  int* off_p;
+  int cap_m, cap_p;
+};
+__device__ inline void cell_setup(const RecordArgs& a, int c) {
+  a.cnt_m[c] = 0;
+  a.cnt_p[c] = 0;
+  if (a.cap_m > 0) {
+    a.off_m[c] = c * a.cap_m;
+    a.off_p[c] = c * a.cap_p;
+  }
+  const int k0 = a.t.child[c], nk = a.t.nchild[c];
+  int mask = 0;
+  for (int q = 0; q < nk; ++q) mask |= (a.t.se[k0 + q] > a.t.sb[k0 + q]) ? (1 << q) : 0;
+  const int meta = a.t.lvl[c] | (nk << 5) | (mask << 8) | ((a.t.se[c] > a.t.sb[c]) ? (1 << 12) : 0);
+  a.rec[c] = make_int4(a.t.ix[c], a.t.iy[c], k0, meta);
+}
+
 // Exact acceptance test (r_A + r_B) < theta d with theta = num/den, all in
 // units of half a finest cell: (S_A + S_B)^2 den^2 < 2 num^2 d^2.
 __host__ __device__ inline bool mac_accept(int D, int la, int ixa, int iya, int lb, int ixb, int iyb, int num,

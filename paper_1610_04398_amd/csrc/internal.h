@@ -104,7 +104,8 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
 int64_t classify_part_ints(int64_t cap);
 void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
                     int* tcells, int* counts, hipStream_t s);
-// One launch for two independent per-leaf passes.
+// One launch for two independent per-leaf passes, and (rec not null) the
+// per-cell list setup of cell_records for all rec->t.ncells cells.
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
 // cell units, as three planes (x at s32[s], y at s32[stride + s], w at
 // s32[2 stride + s]), and the FP64 leaf weight.
@@ -118,7 +119,7 @@ void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const
                     float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                     const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                     double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                    double* self_logd, hipStream_t s);
+                    double* self_logd, const RecordArgs* rec, hipStream_t s);
 // Scattered-source counterpart, in one launch: FP32 records and FP64 offsets
 // (units of u) per source leaf; per target leaf the offsets, owning leaf, and
 // the weight of the sources that coincide exactly with the target.
@@ -126,7 +127,7 @@ void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, 
                            const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
                            double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                            const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
-                           double* self_w, hipStream_t s);
+                           double* self_w, const RecordArgs* rec, hipStream_t s);
 
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p

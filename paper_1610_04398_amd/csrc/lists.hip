@@ -49,25 +49,11 @@ __device__ inline int rec_nchild(int4 r) { return (r.w >> 5) & 7; }
 __device__ inline int rec_kidmask(int4 r) { return (r.w >> 8) & 15; }
 __device__ inline bool rec_has_src(int4 r) { return (r.w >> 12) & 1; }
 
-// Packed traversal record of every cell; the same launch clears the per-cell
-// list counts and, for the one-pass lists (cap_m > 0), writes the
-// fixed-capacity offsets c * cap.
-__global__ void k_records(TreeView t, int n, int4* __restrict__ rec, int* __restrict__ cnt_m2l,
-                          int* __restrict__ cnt_p2p, int* __restrict__ off_m2l, int* __restrict__ off_p2p, int cap_m,
-                          int cap_p) {
+// Packed traversal record of every cell (cell_setup); the same launch clears
+// the per-cell list counts and, for the one-pass lists, writes the offsets.
+__global__ void k_records(RecordArgs a, int n) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  cnt_m2l[c] = 0;
-  cnt_p2p[c] = 0;
-  if (cap_m > 0) {
-    off_m2l[c] = c * cap_m;
-    off_p2p[c] = c * cap_p;
-  }
-  const int k0 = t.child[c], nk = t.nchild[c];
-  int mask = 0;
-  for (int q = 0; q < nk; ++q) mask |= (t.se[k0 + q] > t.sb[k0 + q]) ? (1 << q) : 0;
-  const int meta = t.lvl[c] | (nk << 5) | (mask << 8) | ((t.se[c] > t.sb[c]) ? (1 << 12) : 0);
-  rec[c] = make_int4(t.ix[c], t.iy[c], k0, meta);
+  if (c < n) cell_setup(a, c);
 }
 
 // The traversal at the target cell A itself, from the source cells left on the
@@ -277,8 +263,8 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
 void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
                   hipStream_t s) {
   if (t.ncells <= 0) return;
-  k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(t, t.ncells, rec, cnt_m2l, cnt_p2p, off_m2l, off_p2p, cap_m,
-                                                    cap_p);
+  const RecordArgs a{t, rec, cnt_m2l, cnt_p2p, off_m2l, off_p2p, cap_m, cap_p};
+  k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(a, t.ncells);
 }
 
 #define PP_LIST_TIER(tier, KERNEL, G, S, ...)                                  \

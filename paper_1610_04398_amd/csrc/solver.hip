@@ -661,6 +661,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   };
   // the two-pass lists read a total back to the host, so they run first, on s
   const bool lists_early = exact_lists && !direct;
+  // The one-pass lists' per-cell setup (traversal records, cleared counts,
+  // offsets) joins the packing launch where that launch comes before the
+  // lists: the timed schedule, and the graph with the side stream.
+  const bool records_in_pack = !direct && !exact_lists && (c.profiling == 2 || ss != s);
+  const RecordArgs rec_args{tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near};
   auto do_lists = [&](hipStream_t q) {
     if (direct) return;
     if (exact_lists) {
@@ -677,7 +682,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
       list_pass(1, om2l, op2p, m2l_src, p2p_src, 0, 0, q);
     } else {
-      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, q);
+      if (!records_in_pack) cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, q);
       list_pass(2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near, q);
     }
     pa.list_src = p2p_src;
@@ -686,10 +691,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto do_pack_prep = [&](hipStream_t q) {
     if (src.grid)
       leaf_pack_prep(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d, ty_d,
-                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd, q);
+                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd,
+                     records_in_pack ? &rec_args : nullptr, q);
     else
       leaf_pack_prep_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
-                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw, q);
+                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw,
+                            records_in_pack ? &rec_args : nullptr, q);
   };
   auto do_p2m = [&] {
     mark(PP_PHASE_P2M);
