@@ -50,15 +50,16 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str):
+def traffic_from_profile(workload: str, parts: int):
     """HBM bytes per near-field launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source with the same number of list parts per target
+    leaf (each part writes its own partial sums); else None."""
     path = os.path.join(ROOT, "profiles", f"p2p_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash() or rec.get("p2p_parts") != parts:
         return None
     return rec.get("bytes_per_launch")
 
@@ -231,6 +232,8 @@ def main() -> int:
     M = int(st["ntargets"])
     pairs = int(st["n_p2p_pairs"])
     P = out.cpu().numpy()
+    # list parts of the near field in this run: its partial sums are [parts][targets]
+    p2p_parts = int(s.debug_array("NEAR").size // max(M, 1))
 
     # phase breakdown: the same solve with events between all phases (launched eagerly)
     s.set_profiling(1)
@@ -356,8 +359,8 @@ def main() -> int:
     achieved = OPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None
     roofline = {"bound": "alu", "kernel": "k_p2p32 (near field)", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
-                "traffic": traffic_from_profile(args.workload), "ops_per_pair": OPS_PER_PAIR,
-                "pairs_per_launch": pairs, "avg_launch_ms": p2p_ms,
+                "traffic": traffic_from_profile(args.workload, p2p_parts), "ops_per_pair": OPS_PER_PAIR,
+                "pairs_per_launch": pairs, "avg_launch_ms": p2p_ms, "p2p_list_parts": p2p_parts,
                 "note": "6 algorithmic FP32 VALU lane-ops per near-field pair (sub, sub, mul, fma, log2, fma); "
                         "peak = 256 CU x 64 lanes x 2.4 GHz without packed FP32"}
     if args.precision == "fp64":

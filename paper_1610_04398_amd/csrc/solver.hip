@@ -80,7 +80,7 @@ constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5
 
 struct pp_ctx {
   int device = 0;
-  int p2p_parts = 4;  // near-field list split per target leaf (PP_P2P_PARTS overrides, 1..8)
+  int p2p_parts = 5;  // near-field list split per target leaf (PP_P2P_PARTS overrides, 1..8)
   int cap_m2l = 128;  // per-cell list capacities of the one-pass lists (doubled on overflow)
   int cap_p2p = 64;
   int cap_m2p = 512;  // the same for the tree-code variant's per-leaf lists
