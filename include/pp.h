@@ -66,7 +66,7 @@ enum {
   PP_ERR_DOMAIN = -2,  /* a target lies outside the root square */
   PP_ERR_NOMEM = -3,   /* the solve would exceed the context's device-memory budget */
   PP_ERR_DEVICE = -4,  /* a HIP call failed; the context is unusable */
-  PP_ERR_LIMIT = -5,   /* the tree exceeded an internal limit (e.g. traversal frontier) */
+  PP_ERR_LIMIT = -5,   /* the tree exceeded an internal limit (the largest traversal frontier, cell capacity) */
   PP_ERR_TIMEOUT = -6, /* pp_server_wait: the request did not finish in time (ticket stays valid) */
   PP_ERR_CANCELLED = -7, /* pp_server_wait: the request was cancelled before it started */
   PP_ERR_BUSY = -8     /* pp_server_cancel: the request has already started (or finished) */
@@ -143,7 +143,11 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out);
 void pp_destroy(pp_ctx* ctx);
 
 /* Tree-code solve (P2M, M2M, M2L, L2L, L2P, P2P) of eq. greenSum for grid
- * sources f at the m targets (tx, ty).  Writes P to p_out[0..m). */
+ * sources f at the m targets (tx, ty).  Writes P to p_out[0..m).  A traversal
+ * frontier or interaction list that outgrows its working capacity makes the
+ * call raise that capacity for the context and repeat the solve by itself;
+ * PP_ERR_LIMIT only if the largest frontier capacity (2048 source cells per
+ * level on the way down, a stack of 4096 at the target cell) is exceeded. */
 pp_status pp_solve_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f,
                         int64_t m, const double* tx, const double* ty, const pp_params* params, double* p_out,
                         void* hip_stream);
