@@ -66,6 +66,7 @@ void target_keys_sorted(const double* tx, const double* ty, int64_t m, double x0
                         uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int* temp, int* flags,
                         hipStream_t s);
 
+struct LeafPass;  // leafpass.h: per-leaf passes that ride on the list launch (lp may be null)
 // ---- tree.hip: top-down construction, per-leaf packing ------------------------------
 struct TreeArrays {
   int* lvl;
@@ -101,9 +102,11 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
 // the *ncells_dev cells of the tree (cap = allocated cells; flag3/off3 scratch
 // of 3 * cap); counts[0..2] receive their lengths.
 // part: classify_part_ints(cap) ints of scratch.  counts[0..2]: the three list lengths.
+// rec (may be null): the same launch also sets up every cell for the lists
+// (cell_setup; rec->t's arrays are the tree's, its ncells unused).
 int64_t classify_part_ints(int64_t cap);
 void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
-                    int* tcells, int* counts, hipStream_t s);
+                    int* tcells, int* counts, const RecordArgs* rec, hipStream_t s);
 // One launch for two independent per-leaf passes, and (rec not null) the
 // per-cell list setup of cell_records for all rec->t.ncells cells.
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
@@ -137,7 +140,7 @@ void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, 
 // the source leaves summed directly (P2P).  Same emit modes as lists_pass.
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
                          int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
-                         int cap_p, int* flags, int tier_boost, hipStream_t s);
+                         int cap_p, int* flags, int tier_boost, const struct LeafPass* lp, hipStream_t s);
 // Packed per-cell records used by the traversal (ncells int4); clears the
 // list counts, and for cap_m > 0 writes the one-pass offsets cell * cap.
 void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
@@ -147,7 +150,7 @@ void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2
 // is longer than its capacity; its tail is then dropped).
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
-                int* flags, int tier_boost, hipStream_t s);
+                int* flags, int tier_boost, const struct LeafPass* lp, hipStream_t s);
 // The traversal frontier has three capacity tiers chosen from theta; tier_boost
 // raises it after an overflow.  True when no higher tier is left.
 bool frontier_at_top(int num, int den, int tier_boost);

@@ -23,6 +23,7 @@
 
 #include "blockscan.h"
 #include "internal.h"
+#include "leafpass.h"
 
 namespace pp {
 
@@ -112,7 +113,7 @@ __device__ bool lists_at_target(int* st, int top, int cap, int D, int4 rA, bool 
   return false;
 }
 
-template <int kFrontierCap>
+template <int kFrontierCap, bool kLeafPass>
 __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4* __restrict__ rec,
                                                                const int* __restrict__ parent,
                                                                const int* __restrict__ tcells, int ntcells, int num,
@@ -121,9 +122,17 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
                                                                const int* __restrict__ off_m2l,
                                                                const int* __restrict__ off_p2p,
                                                                int* __restrict__ m2l_src, int* __restrict__ p2p_src,
-                                                               int cap_m, int cap_p, int* __restrict__ flags) {
+                                                               int cap_m, int cap_p, int* __restrict__ flags,
+                                                               LeafPass lp) {
   __shared__ int front[kListWaves][2 * kFrontierCap];
   __shared__ int path[kListWaves][kMaxDepth + 1];
+  if constexpr (kLeafPass) {  // the per-leaf passes riding on this launch
+    const int list_blocks = (ntcells + kListWaves - 1) / kListWaves;
+    if ((int)blockIdx.x >= list_blocks) {
+      run_leaf_pass(lp, (int)blockIdx.x - list_blocks);
+      return;
+    }
+  }
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kListWaves + w);
@@ -223,12 +232,19 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
 // cell is replaced by its children with sources.  The cells still to visit
 // form a stack in LDS, popped and classified 64 at a time; ballots compact the
 // output in a fixed order.  Same emit modes and layouts as k_lists.
-template <int kFrontierCap>
+template <int kFrontierCap, bool kLeafPass>
 __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
     int D, const int4* __restrict__ rec, const int* __restrict__ tleaves, int ntleaves, int num, int den, int emit,
     int* __restrict__ cnt_m, int* __restrict__ cnt_p, const int* __restrict__ off_m, const int* __restrict__ off_p,
-    int* __restrict__ m_src, int* __restrict__ p_src, int cap_m, int cap_p, int* __restrict__ flags) {
+    int* __restrict__ m_src, int* __restrict__ p_src, int cap_m, int cap_p, int* __restrict__ flags, LeafPass lp) {
   __shared__ int front[kListWaves][2 * kFrontierCap];
+  if constexpr (kLeafPass) {  // the per-leaf passes riding on this launch
+    const int list_blocks = (ntleaves + kListWaves - 1) / kListWaves;
+    if ((int)blockIdx.x >= list_blocks) {
+      run_leaf_pass(lp, (int)blockIdx.x - list_blocks);
+      return;
+    }
+  }
   const int w = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kListWaves + w);
@@ -267,34 +283,44 @@ void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2
   k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(a, t.ncells);
 }
 
-#define PP_LIST_TIER(tier, KERNEL, G, S, ...)                                  \
-  do {                                                                         \
-    if ((tier) <= 0)                                                           \
-      KERNEL<kFrontierTiers[0]><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__); \
-    else if ((tier) == 1)                                                      \
-      KERNEL<kFrontierTiers[1]><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__); \
-    else                                                                       \
-      KERNEL<kFrontierTiers[2]><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__); \
+#define PP_LIST_TIER(tier, LP, KERNEL, G, S, ...)                                      \
+  do {                                                                                 \
+    if ((tier) <= 0 && (LP))                                                           \
+      KERNEL<kFrontierTiers[0], true><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__);   \
+    else if ((tier) <= 0)                                                              \
+      KERNEL<kFrontierTiers[0], false><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__);  \
+    else if ((tier) == 1 && (LP))                                                      \
+      KERNEL<kFrontierTiers[1], true><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__);   \
+    else if ((tier) == 1)                                                              \
+      KERNEL<kFrontierTiers[1], false><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__);  \
+    else if (LP)                                                                       \
+      KERNEL<kFrontierTiers[2], true><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__);   \
+    else                                                                               \
+      KERNEL<kFrontierTiers[2], false><<<G, kListWaves * kWave, 0, S>>>(__VA_ARGS__);  \
   } while (0)
 
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
-                int* flags, int tier_boost, hipStream_t s) {
-  if (ntcells <= 0) return;
-  const unsigned g = (unsigned)((ntcells + kListWaves - 1) / kListWaves);
+                int* flags, int tier_boost, const LeafPass* lp, hipStream_t s) {
+  const int nlist = std::max(ntcells, 0);
+  const int extra = lp ? lp->pack_blocks + lp->prep_blocks : 0;
+  const unsigned g = (unsigned)((nlist + kListWaves - 1) / kListWaves + extra);
+  if (g == 0) return;
   const int tier = std::min(2, frontier_tier_for(num, den) + tier_boost);
-  PP_LIST_TIER(tier, k_lists, g, s, t.D, rec, t.parent, tcells, ntcells, num, den, emit, cnt_m2l, cnt_p2p, off_m2l,
-               off_p2p, m2l_src, p2p_src, cap_m, cap_p, flags);
+  PP_LIST_TIER(tier, lp != nullptr, k_lists, g, s, t.D, rec, t.parent, tcells, nlist, num, den, emit, cnt_m2l, cnt_p2p, off_m2l,
+               off_p2p, m2l_src, p2p_src, cap_m, cap_p, flags, lp ? *lp : LeafPass{});
 }
 
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
                          int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
-                         int cap_p, int* flags, int tier_boost, hipStream_t s) {
-  if (ntleaves <= 0) return;
-  const unsigned g = (unsigned)((ntleaves + kListWaves - 1) / kListWaves);
+                         int cap_p, int* flags, int tier_boost, const LeafPass* lp, hipStream_t s) {
+  const int nlist = std::max(ntleaves, 0);
+  const int extra = lp ? lp->pack_blocks + lp->prep_blocks : 0;
+  const unsigned g = (unsigned)((nlist + kListWaves - 1) / kListWaves + extra);
+  if (g == 0) return;
   const int tier = std::min(2, frontier_tier_for(num, den) + tier_boost);
-  PP_LIST_TIER(tier, k_lists_treecode, g, s, t.D, rec, tleaves, ntleaves, num, den, emit, cnt_m, cnt_p, off_m, off_p,
-               m_src, p_src, cap_m, cap_p, flags);
+  PP_LIST_TIER(tier, lp != nullptr, k_lists_treecode, g, s, t.D, rec, tleaves, nlist, num, den, emit, cnt_m, cnt_p, off_m, off_p,
+               m_src, p_src, cap_m, cap_p, flags, lp ? *lp : LeafPass{});
 }
 
 bool frontier_at_top(int num, int den, int tier_boost) { return frontier_tier_for(num, den) + tier_boost >= 2; }

@@ -13,6 +13,7 @@
 
 #include "blockscan.h"
 #include "internal.h"
+#include "leafpass.h"
 
 namespace pp {
 
@@ -146,73 +147,6 @@ __global__ void k_gather_points(const int* __restrict__ perm, const int* __restr
   ws[i] = w[o];
 }
 
-// One wave per source leaf: offsets from the leaf corner in units of u, FP32
-// (with the weight) and FP64, and the FP64 leaf weight in a fixed order.
-__device__ inline void pack_point_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
-                                       const double* __restrict__ xs, const double* __restrict__ ys,
-                                       const double* __restrict__ ws, double x0, double y0, double u,
-                                       float* __restrict__ s32, int64_t stride, double2* __restrict__ s64,
-                                       double* __restrict__ leaf_w) {
-  const int c = sleaves[wid];
-  const int sh = D - t.lvl[c];
-  const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
-  const int sb = t.sb[c], se = t.se[c];
-  double acc = 0.0;
-  for (int s = sb + lane; s < se; s += kWave) {
-    const double rx = (xs[s] - x0) / u - cx;
-    const double ry = (ys[s] - y0) / u - cy;
-    const double w = ws[s];
-    s32[s] = (float)rx;
-    s32[stride + s] = (float)ry;
-    s32[2 * stride + s] = (float)w;
-    s64[s] = make_double2(rx, ry);
-    acc += w;
-  }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  if (lane == 0) leaf_w[c] = acc;
-}
-
-// One wave per target leaf: offsets from the leaf corner (the same FP64
-// operations as for the sources, so coincident points get identical offsets),
-// the owning leaf, and the summed weight of the sources that coincide exactly
-// with the target (they are skipped by the near-field kernel, and the finalize
-// step removes their share of the near weight).
-__device__ inline void prep_point_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ tleaves, int D,
-                                       const double* __restrict__ tx, const double* __restrict__ ty,
-                                       const int* __restrict__ perm, double x0, double y0, double u,
-                                       const double* __restrict__ xs, const double* __restrict__ ys,
-                                       const double* __restrict__ ws, float2* __restrict__ rel32,
-                                       double2* __restrict__ rel64, int* __restrict__ tleaf,
-                                       double* __restrict__ self_w) {
-  const int c = tleaves[wid];
-  const int sh = D - t.lvl[c];
-  const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
-  const int tb = t.tb[c], te = t.te[c], sb = t.sb[c], se = t.se[c];
-  for (int k = tb + lane; k < te; k += kWave) {
-    const int o = perm[k];
-    const double x = tx[o], y = ty[o];
-    const double rx = (x - x0) / u - cx;
-    const double ry = (y - y0) / u - cy;
-    double sw = 0.0;
-    for (int s = sb; s < se; ++s)
-      if (xs[s] == x && ys[s] == y) sw += ws[s];
-    rel64[k] = make_double2(rx, ry);
-    rel32[k] = make_float2((float)rx, (float)ry);
-    tleaf[k] = c;
-    self_w[k] = sw;
-  }
-}
-
-// Both per-leaf passes in one launch (they are independent): the first
-// workgroups pack the source leaves, the next prepare the target leaves, and
-// the last (if any) set up every cell for the interaction lists.
-struct PointFrame {
-  double x0, y0, u;
-  const double* xs;
-  const double* ys;
-  const double* ws;
-};
 __global__ __launch_bounds__(256) void k_pack_prep_points(TreeArrays t, int D, PointFrame fr,
                                                            const int* __restrict__ sleaves, int ns,
                                                            float* __restrict__ s32, int64_t stride,
@@ -263,6 +197,22 @@ void points_gather(const int* perm, const int* nsrc_dev, int64_t nmax, const dou
                    const double* w, double* xs, double* ys, double* ws, hipStream_t s) {
   if (nmax <= 0) return;
   k_gather_points<<<(unsigned)((nmax + 255) / 256), 256, 0, s>>>(perm, nsrc_dev, sx, sy, w, xs, ys, ws);
+}
+
+LeafPass leaf_pass_points(TreeArrays t, int D, double x0, double y0, double u, const double* xs, const double* ys,
+                          const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
+                          double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
+                          const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
+                          double* self_w) {
+  LeafPass lp;
+  lp.kind = 2;
+  lp.pack_blocks = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
+  lp.prep_blocks = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
+  lp.t = t;
+  lp.D = D;
+  lp.pa = PointArgs{PointFrame{x0, y0, u, xs, ys, ws}, sleaves, nsleaves, s32, stride, s64, leaf_w, tleaves, ntleaves,
+                    tx, ty, perm, rel32, rel64, tleaf, self_w};
+  return lp;
 }
 
 void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, const double* xs, const double* ys,

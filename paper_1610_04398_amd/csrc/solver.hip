@@ -21,6 +21,7 @@
 
 #include "../../include/pp.h"
 #include "internal.h"
+#include "leafpass.h"
 
 using namespace pp;
 
@@ -467,6 +468,16 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                 ensure<int>(c, B_SB, cap),    ensure<int>(c, B_SE, cap),     ensure<int>(c, B_TB, cap),
                 ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
                 ensure<int>(c, B_PARENT, cap)};
+  // the lists' per-cell setup (records, counts, one-pass offsets) is written by
+  // the first segment's cell classification, so its buffers hold `cap` cells
+  const bool treecode = prm.method == PP_METHOD_TREECODE;
+  const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
+  const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
+  int4* rec = direct ? nullptr : ensure<int4>(c, B_REC, cap);
+  int* cm2l = ensure<int>(c, B_CM2L, cap);
+  int* om2l = ensure<int>(c, B_OM2L, cap);
+  int* cp2p = ensure<int>(c, B_CP2P, cap);
+  int* op2p = ensure<int>(c, B_OP2P, cap);
   int* ls_d = misc + M_LS;
   // levels 0..Ld from the dense prefix table, the rest one level at a time
   const int Ld = std::min(D, c.dense_levels);
@@ -493,7 +504,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                           out_on_device && c.profiling != 1;
   const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
                                       (uint64_t)lm, (uint64_t)c.dense_levels, (uint64_t)c.profiling, bits(f_d),
-                                      bits(tx_d), bits(ty_d)};
+                                      bits(tx_d), bits(ty_d), (uint64_t)direct, (uint64_t)cap_far,
+                                      (uint64_t)cap_near};
   const int seq1 = published_seq(c) + 1;
   run_segment(c, 0, replayable, key1, s, [&] {
     mark(PP_PHASE_INGEST);
@@ -527,7 +539,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                  misc + M_FLAGS, s);
     }
     // cell lists over the whole tree (its size is the last level start, on the device)
-    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, sleaves, tleaves, tcells, misc + M_NSL, s);
+    const TreeView tv0{D, 0, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
+    const RecordArgs rec0{tv0, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near};
+    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, sleaves, tleaves, tcells, misc + M_NSL,
+                   direct ? nullptr : &rec0, s);
     publish_enqueue(c, misc, M_LS + D + 2, s);
   });
   wait_published(c, s, seq1);
@@ -545,19 +560,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
   // ---- every buffer of the second segment, sized before anything is enqueued ----
-  int* cm2l = ensure<int>(c, B_CM2L, ncells);
-  int* om2l = ensure<int>(c, B_OM2L, ncells);
-  int* cp2p = ensure<int>(c, B_CP2P, ncells);
-  int* op2p = ensure<int>(c, B_OP2P, ncells);
   int* m2l_src = nullptr;
   int* p2p_src = nullptr;
   int64_t n_m2l = 0, n_p2pl = 0;
   // the tree-code variant lists per target leaf (M2P cells, P2P leaves); the
   // multipole method lists per cell with targets (M2L cells, P2P leaves)
-  const bool treecode = prm.method == PP_METHOD_TREECODE;
-  const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
-  const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
-  int4* rec = direct ? nullptr : ensure<int4>(c, B_REC, ncells);
   if (!direct && !exact_lists) {
     m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
     p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
@@ -619,13 +626,14 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     c.cur_stream = nullptr;
     throw FrontierRetry{};
   };
-  auto list_pass = [&](int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp, hipStream_t q) {
+  auto list_pass = [&](int emit, const int* om, const int* op, int* ms, int* ps, int cm, int cp,
+                       const LeafPass* lp, hipStream_t q) {
     if (treecode)
       lists_treecode_pass(tv, rec, tleaves, ntl, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
-                          c.frontier_boost, q);
+                          c.frontier_boost, lp, q);
     else
       lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
-                 c.frontier_boost, q);
+                 c.frontier_boost, lp, q);
   };
   std::vector<uint64_t> key2 = key1;
   for (uint64_t v : {(uint64_t)N, (uint64_t)ncells, (uint64_t)nsl, (uint64_t)ntl, (uint64_t)ntc, (uint64_t)depth,
@@ -661,16 +669,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   };
   // the two-pass lists read a total back to the host, so they run first, on s
   const bool lists_early = exact_lists && !direct;
-  // The one-pass lists' per-cell setup (traversal records, cleared counts,
-  // offsets) joins the packing launch where that launch comes before the
-  // lists: the timed schedule, and the graph with the side stream.
-  const bool records_in_pack = !direct && !exact_lists && (c.profiling == 2 || ss != s);
-  const RecordArgs rec_args{tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near};
-  auto do_lists = [&](hipStream_t q) {
+
+  // lp (one-pass lists only): the per-leaf packing rides on the list launch
+  auto do_lists = [&](hipStream_t q, const LeafPass* lp) {
     if (direct) return;
     if (exact_lists) {
-      cell_records(tv, rec, cm2l, cp2p, om2l, op2p, 0, 0, q);
-      list_pass(0, nullptr, nullptr, nullptr, nullptr, 0, 0, q);
+      list_pass(0, nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, q);  // records, cleared counts: segment 1
       scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, q);
       scan_exclusive(cp2p, op2p, ncells, scan, misc + M_NP2P, q);
       readback(c, misc, 0, 16, q);
@@ -680,10 +684,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       n_p2pl = c.pinned[M_NP2P];
       m2l_src = ensure<int>(c, B_M2LSRC, n_m2l);
       p2p_src = ensure<int>(c, B_P2PSRC, n_p2pl);
-      list_pass(1, om2l, op2p, m2l_src, p2p_src, 0, 0, q);
+      list_pass(1, om2l, op2p, m2l_src, p2p_src, 0, 0, nullptr, q);
     } else {
-      if (!records_in_pack) cell_records(tv, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near, q);
-      list_pass(2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near, q);
+      list_pass(2, om2l, op2p, m2l_src, p2p_src, cap_far, cap_near, lp, q);  // records, offsets: segment 1
     }
     pa.list_src = p2p_src;
   };
@@ -692,12 +695,23 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     if (src.grid)
       leaf_pack_prep(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d, ty_d,
                      tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd,
-                     records_in_pack ? &rec_args : nullptr, q);
+                     nullptr, q);
     else
       leaf_pack_prep_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
-                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw,
-                            records_in_pack ? &rec_args : nullptr, q);
+                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw, nullptr, q);
   };
+  // The one-pass lists (records and offsets written by segment 1) carry the
+  // per-leaf packing in extra workgroups of their launch, so the two overlap,
+  // in the directly issued schedule.  (In the graph, lists and packing before
+  // the fork made the replay 10% slower: there the packing stays its own
+  // launch before the fork, and the lists run on the side stream.)
+  const bool fused = !direct && !exact_lists && c.profiling == 2;
+  const LeafPass lpass =
+      src.grid ? leaf_pass_grid(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d,
+                                ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf,
+                                selfw, selfd)
+               : leaf_pass_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
+                                  leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw);
   auto do_p2m = [&] {
     mark(PP_PHASE_P2M);
     if (!direct) p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, s);
@@ -773,9 +787,15 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // (kernels that leave most of the GPU idle) rather than beside the near
   // field, which fills it.
   auto fork_work = [&] {
+    if (fused) {
+      do_lists(ss, &lpass);
+      do_p2m();
+      do_m2m();
+      return;
+    }
     do_pack_prep(ss);
     do_p2m();
-    if (!lists_early) do_lists(ss);
+    if (!lists_early) do_lists(ss, nullptr);
     do_m2m();
   };
 
@@ -791,7 +811,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // near field.  The upward pass runs meanwhile on s (its launches issued
     // between the side stream's), which then waits for the lists (M2L, L2L,
     // L2P) and for the near field (finalize).
-    if (lists_early) do_lists(s);
+    if (lists_early) do_lists(s, nullptr);
     fork_work();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
     HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
@@ -805,7 +825,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // one stream, phases in order (timing mode 1, or the side stream disabled)
     run_segment(c, 1, replayable, key2, s, [&] {
       mark(PP_PHASE_LISTS);
-      do_lists(s);
+      do_lists(s, nullptr);
       mark(PP_PHASE_PACK);
       do_pack_prep(s);
       do_upward();
@@ -818,11 +838,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // Captured in phase order: the graph runs the side branch's kernels before
     // the upward pass whatever the order of capture, and a fork at the start of
     // the segment (two root nodes) was measured to delay the first kernels.
-    if (lists_early) do_lists(s);
+    if (lists_early) do_lists(s, nullptr);
     run_segment(c, 1, replayable, key2, s, [&] {
       do_pack_prep(s);
       signal(c.ev_fork, s, ss);
-      if (!lists_early) do_lists(ss);
+      if (!lists_early) do_lists(ss, nullptr);
       HIPCHK(hipEventRecord(c.ev_lists, ss));
       do_near(ss);
       do_upward();

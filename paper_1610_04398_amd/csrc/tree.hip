@@ -14,6 +14,7 @@
 
 #include "blockscan.h"
 #include "internal.h"
+#include "leafpass.h"
 
 namespace pp {
 
@@ -305,7 +306,7 @@ __device__ inline int cls_bits(const TreeArrays& t, int c) {
 }
 
 __global__ __launch_bounds__(kClsBlock) void k_classify_count(TreeArrays t, const int* __restrict__ n_dev,
-                                                               int* __restrict__ part) {
+                                                               int* __restrict__ part, RecordArgs rec) {
   __shared__ int lds[kClsBlock / kWave + 1];
   const int n = *n_dev;
   const int64_t base = (int64_t)blockIdx.x * kClsTile;
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(kClsBlock) void k_classify_count(TreeArrays t, cons
   for (int q = 0; q < kClsItems; ++q) {
     const int64_t c = base + (int64_t)threadIdx.x * kClsItems + q;
     if (c < n) {
+      if (rec.rec) cell_setup(rec, (int)c);
       const int b = cls_bits(t, (int)c);
       c0 += b & 1;
       c1 += (b >> 1) & 1;
@@ -384,109 +386,6 @@ __global__ __launch_bounds__(kClsBlock) void k_classify_emit(TreeArrays t, const
 
 // One wave per source leaf: FP32 record (x, y relative to the leaf corner in
 // units of h, w) per source; leaf weight sum in FP64 in a fixed order.
-// One wave packs source leaf sleaves[wid].
-__device__ inline void pack_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
-                                 const uint32_t* __restrict__ ij, const double* __restrict__ w64,
-                                 float* __restrict__ s32, int64_t stride, double* __restrict__ leaf_w) {
-  const int c = sleaves[wid];
-  const int sh = D - t.lvl[c];
-  const int cx = t.ix[c] << sh, cy = t.iy[c] << sh;
-  const int sb = t.sb[c], se = t.se[c];
-  double acc = 0.0;
-  for (int s = sb + lane; s < se; s += kWave) {
-    const uint32_t v = ij[s];
-    const int i = (int)(v & 0xFFFFu), j = (int)(v >> 16);
-    const double w = w64[s];
-    s32[s] = (float)(i - cx) + 0.5f;
-    s32[stride + s] = (float)(j - cy) + 0.5f;
-    s32[2 * stride + s] = (float)w;
-    acc += w;
-  }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-  if (lane == 0) leaf_w[c] = acc;
-}
-
-// x0 + (i + 1/2) h without contraction: the node coordinate exactly as the
-// oracle forms it, so that coincidence is the same FP64 equality on both sides.
-__device__ inline double node_coord(double x0, int i, double h) {
-#pragma clang fp contract(off)
-  const double a = ((double)i + 0.5) * h;
-  return x0 + a;
-}
-
-// One wave prepares the targets of target leaf tleaves[wid].
-__device__ inline void prep_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ tleaves, int D,
-                                 const double* __restrict__ tx, const double* __restrict__ ty,
-                                 const int* __restrict__ perm, double x0, double y0, double h, int nx, int ny,
-                                 double snap_frac2, const double* __restrict__ f, float2* __restrict__ rel32,
-                                 double2* __restrict__ rel64, int* __restrict__ tleaf, double* __restrict__ self_w,
-                                 double* __restrict__ self_logd) {
-#pragma clang fp contract(off)
-  const int c = tleaves[wid];
-  const int sh = D - t.lvl[c];
-  const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
-  const int tb = t.tb[c], te = t.te[c];
-  // squared distance below which a target is snapped onto its nearest node
-  const double snap2 = h * h * snap_frac2;
-  for (int k = tb + lane; k < te; k += kWave) {
-    const int o = perm[k];
-    const double x = tx[o], y = ty[o];
-    const double ux = (x - x0) / h;
-    const double uy = (y - y0) / h;
-    double rx = ux - cx, ry = uy - cy;
-    const double fx = floor(ux), fy = floor(uy);
-    const bool inside = fx >= 0.0 && fy >= 0.0 && fx < 65536.0 && fy < 65536.0;
-    const int i = inside ? (int)fx : -1, j = inside ? (int)fy : -1;
-    double sw = 0.0, lg = 0.0;
-    if (i >= 0 && j >= 0 && i < nx && j < ny) {
-      const double dx = x - node_coord(x0, i, h);
-      const double dy = y - node_coord(y0, j, h);
-      const double d2 = dx * dx + dy * dy;
-      if (d2 == 0.0 || d2 < snap2) {
-        sw = f[(int64_t)j * nx + i] * (h * h);
-        lg = (d2 == 0.0) ? -INFINITY : 0.5 * log(d2);
-        rx = ((double)i + 0.5) - cx;
-        ry = ((double)j + 0.5) - cy;
-      }
-    }
-    rel64[k] = make_double2(rx, ry);
-    rel32[k] = make_float2((float)rx, (float)ry);
-    tleaf[k] = c;
-    self_w[k] = sw;
-    self_logd[k] = lg;
-  }
-}
-
-// Both per-leaf passes in one launch (they are independent): the first
-// workgroups pack the source leaves, the next prepare the target leaves, and
-// the last (if any) set up every cell for the interaction lists.
-struct PackArgs {
-  const int* sleaves;
-  int ns;
-  const uint32_t* ij;
-  const double* w64;
-  float* s32;
-  int64_t stride;
-  double* leaf_w;
-};
-struct PrepArgs {
-  const int* tleaves;
-  int nt;
-  const double* tx;
-  const double* ty;
-  const int* perm;
-  double x0, y0, h;
-  int nx, ny;
-  double snap_frac2;
-  const double* f;
-  float2* rel32;
-  double2* rel64;
-  int* tleaf;
-  double* self_w;
-  double* self_logd;
-};
-
 __global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs a, int pack_blocks, PrepArgs b,
                                                     int prep_blocks, RecordArgs r, int nrec) {
   const int lane = threadIdx.x % kWave;
@@ -542,11 +441,28 @@ void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap,
 int64_t classify_part_ints(int64_t cap) { return 3 * ((cap + kClsTile - 1) / kClsTile) + 3; }
 
 void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
-                    int* tcells, int* counts, hipStream_t s) {
+                    int* tcells, int* counts, const RecordArgs* rec, hipStream_t s) {
   if (cap <= 0) return;
   const unsigned g = (unsigned)(((int64_t)cap + kClsTile - 1) / kClsTile);
-  k_classify_count<<<g, kClsBlock, 0, s>>>(t, ncells_dev, part);
+  k_classify_count<<<g, kClsBlock, 0, s>>>(t, ncells_dev, part, rec ? *rec : RecordArgs{});
   k_classify_emit<<<g, kClsBlock, 0, s>>>(t, ncells_dev, part, sleaves, tleaves, tcells, counts);
+}
+
+LeafPass leaf_pass_grid(TreeArrays t, int D, const int* sleaves, int nsleaves, const uint32_t* ij, const double* w64,
+                        float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
+                        const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
+                        double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
+                        double* self_logd) {
+  LeafPass lp;
+  lp.kind = 1;
+  lp.pack_blocks = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
+  lp.prep_blocks = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
+  lp.t = t;
+  lp.D = D;
+  lp.ga = PackArgs{sleaves, nsleaves, ij, w64, s32, stride, leaf_w};
+  lp.gb = PrepArgs{tleaves, ntleaves, tx, ty, perm, x0, y0, h, nx, ny, snap_frac2, f, rel32, rel64, tleaf, self_w,
+                   self_logd};
+  return lp;
 }
 
 void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const uint32_t* ij, const double* w64,
