@@ -50,16 +50,18 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, parts: int):
+def traffic_from_profile(workload: str, parts: int, precision: str, method: str):
     """HBM bytes per near-field launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source with the same number of list parts per target
-    leaf (each part writes its own partial sums); else None."""
+    leaf (each part writes its own partial sums), precision and method; else None."""
     path = os.path.join(ROOT, "profiles", f"p2p_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_sha256_16") != kernel_source_hash() or rec.get("p2p_parts") != parts:
+        return None
+    if rec.get("precision") != precision or rec.get("method") != method:
         return None
     return rec.get("bytes_per_launch")
 
@@ -359,7 +361,8 @@ def main() -> int:
     achieved = OPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None
     roofline = {"bound": "alu", "kernel": "k_p2p32 (near field)", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
-                "traffic": traffic_from_profile(args.workload, p2p_parts), "ops_per_pair": OPS_PER_PAIR,
+                "traffic": traffic_from_profile(args.workload, p2p_parts, args.precision, args.method),
+                "ops_per_pair": OPS_PER_PAIR,
                 "pairs_per_launch": pairs, "avg_launch_ms": p2p_ms, "p2p_list_parts": p2p_parts,
                 "note": "6 algorithmic FP32 VALU lane-ops per near-field pair (sub, sub, mul, fma, log2, fma); "
                         "peak = 256 CU x 64 lanes x 2.4 GHz without packed FP32"}
