@@ -107,8 +107,7 @@ void tree_level(TreeArrays t, int* ls, int level, int D, int leaf_max, int64_t m
 int64_t classify_part_ints(int64_t cap);
 void classify_cells(TreeArrays t, const int* ncells_dev, int cap, int* part, int* sleaves, int* tleaves,
                     int* tcells, int* counts, const RecordArgs* rec, hipStream_t s);
-// One launch for two independent per-leaf passes, and (rec not null) the
-// per-cell list setup of cell_records for all rec->t.ncells cells.
+// One launch for two independent per-leaf passes.
 // Per source leaf: FP32 source records relative to the leaf corner, in finest
 // cell units, as three planes (x at s32[s], y at s32[stride + s], w at
 // s32[2 stride + s]), and the FP64 leaf weight.
@@ -122,7 +121,7 @@ void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const
                     float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                     const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                     double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                    double* self_logd, const RecordArgs* rec, hipStream_t s);
+                    double* self_logd, hipStream_t s);
 // Scattered-source counterpart, in one launch: FP32 records and FP64 offsets
 // (units of u) per source leaf; per target leaf the offsets, owning leaf, and
 // the weight of the sources that coincide exactly with the target.
@@ -130,7 +129,7 @@ void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, 
                            const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
                            double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                            const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
-                           double* self_w, const RecordArgs* rec, hipStream_t s);
+                           double* self_w, hipStream_t s);
 
 // ---- lists.hip: dual-tree interaction lists ------------------------------------
 // One wave per target cell in `tcells`; pass 0 counts into cnt_m2l / cnt_p2p
@@ -141,10 +140,6 @@ void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, 
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,
                          int* cnt_m, int* cnt_p, const int* off_m, const int* off_p, int* m_src, int* p_src, int cap_m,
                          int cap_p, int* flags, int tier_boost, const struct LeafPass* lp, hipStream_t s);
-// Packed per-cell records used by the traversal (ncells int4); clears the
-// list counts, and for cap_m > 0 writes the one-pass offsets cell * cap.
-void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
-                  hipStream_t s);
 // emit 0: counts only; 1: write at the exact offsets of a count pass;
 // 2: one pass, counts plus lists at cell * cap (kFlagListOverflow if a list
 // is longer than its capacity; its tail is then dropped).

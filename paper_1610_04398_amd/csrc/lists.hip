@@ -50,13 +50,6 @@ __device__ inline int rec_nchild(int4 r) { return (r.w >> 5) & 7; }
 __device__ inline int rec_kidmask(int4 r) { return (r.w >> 8) & 15; }
 __device__ inline bool rec_has_src(int4 r) { return (r.w >> 12) & 1; }
 
-// Packed traversal record of every cell (cell_setup); the same launch clears
-// the per-cell list counts and, for the one-pass lists, writes the offsets.
-__global__ void k_records(RecordArgs a, int n) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) cell_setup(a, c);
-}
-
 // The traversal at the target cell A itself, from the source cells left on the
 // stack st[0, top): accepted -> A's far list (M2L, or M2P for the tree-code);
 // not accepted and a leaf -> A's near list when A is a leaf; not accepted and
@@ -275,13 +268,6 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
 }
 
 }  // namespace
-
-void cell_records(TreeView t, int4* rec, int* cnt_m2l, int* cnt_p2p, int* off_m2l, int* off_p2p, int cap_m, int cap_p,
-                  hipStream_t s) {
-  if (t.ncells <= 0) return;
-  const RecordArgs a{t, rec, cnt_m2l, cnt_p2p, off_m2l, off_p2p, cap_m, cap_p};
-  k_records<<<(t.ncells + 255) / 256, 256, 0, s>>>(a, t.ncells);
-}
 
 #define PP_LIST_TIER(tier, LP, KERNEL, G, S, ...)                                      \
   do {                                                                                 \

@@ -147,6 +147,8 @@ __global__ void k_gather_points(const int* __restrict__ perm, const int* __restr
   ws[i] = w[o];
 }
 
+// Both per-leaf passes in one launch: the first workgroups pack the source
+// leaves, the rest prepare the target leaves.
 __global__ __launch_bounds__(256) void k_pack_prep_points(TreeArrays t, int D, PointFrame fr,
                                                            const int* __restrict__ sleaves, int ns,
                                                            float* __restrict__ s32, int64_t stride,
@@ -156,13 +158,9 @@ __global__ __launch_bounds__(256) void k_pack_prep_points(TreeArrays t, int D, P
                                                            const double* __restrict__ ty,
                                                            const int* __restrict__ perm, float2* __restrict__ rel32,
                                                            double2* __restrict__ rel64, int* __restrict__ tleaf,
-                                                           double* __restrict__ self_w, int prep_blocks,
-                                                           RecordArgs r, int nrec) {
+                                                           double* __restrict__ self_w) {
   const int lane = threadIdx.x % kWave;
-  if ((int)blockIdx.x >= pack_blocks + prep_blocks) {  // the cells' list setup, one cell per thread
-    const int c = (blockIdx.x - pack_blocks - prep_blocks) * blockDim.x + threadIdx.x;
-    if (c < nrec) cell_setup(r, c);
-  } else if ((int)blockIdx.x < pack_blocks) {
+  if ((int)blockIdx.x < pack_blocks) {
     const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (wid < ns)
       pack_point_leaf(wid, lane, t, sleaves, D, fr.xs, fr.ys, fr.ws, fr.x0, fr.y0, fr.u, s32, stride, s64, leaf_w);
@@ -219,16 +217,13 @@ void leaf_pack_prep_points(TreeArrays t, int D, double x0, double y0, double u, 
                            const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
                            double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                            const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
-                           double* self_w, const RecordArgs* rec, hipStream_t s) {
+                           double* self_w, hipStream_t s) {
   const int gp = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
   const int gt = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
-  const int nrec = rec ? rec->t.ncells : 0;
-  const int gr = (nrec + 255) / 256;
-  if (gp + gt + gr <= 0) return;
+  if (gp + gt <= 0) return;
   const PointFrame fr{x0, y0, u, xs, ys, ws};
-  k_pack_prep_points<<<gp + gt + gr, 256, 0, s>>>(t, D, fr, sleaves, nsleaves, s32, stride, s64, leaf_w, gp, tleaves,
-                                                  ntleaves, tx, ty, perm, rel32, rel64, tleaf, self_w, gt,
-                                                  rec ? *rec : RecordArgs{}, nrec);
+  k_pack_prep_points<<<gp + gt, 256, 0, s>>>(t, D, fr, sleaves, nsleaves, s32, stride, s64, leaf_w, gp, tleaves,
+                                             ntleaves, tx, ty, perm, rel32, rel64, tleaf, self_w);
 }
 
 }  // namespace pp

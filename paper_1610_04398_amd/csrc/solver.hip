@@ -694,11 +694,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto do_pack_prep = [&](hipStream_t q) {
     if (src.grid)
       leaf_pack_prep(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d, ty_d,
-                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd,
-                     nullptr, q);
+                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd, q);
     else
       leaf_pack_prep_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
-                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw, nullptr, q);
+                            leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw, q);
   };
   // The one-pass lists (records and offsets written by segment 1) carry the
   // per-leaf packing in extra workgroups of their launch, so the two overlap,

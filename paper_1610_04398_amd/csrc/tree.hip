@@ -386,13 +386,11 @@ __global__ __launch_bounds__(kClsBlock) void k_classify_emit(TreeArrays t, const
 
 // One wave per source leaf: FP32 record (x, y relative to the leaf corner in
 // units of h, w) per source; leaf weight sum in FP64 in a fixed order.
-__global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs a, int pack_blocks, PrepArgs b,
-                                                    int prep_blocks, RecordArgs r, int nrec) {
+// Both per-leaf passes in one launch: the first workgroups pack the source
+// leaves, the rest prepare the target leaves.
+__global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs a, int pack_blocks, PrepArgs b) {
   const int lane = threadIdx.x % kWave;
-  if ((int)blockIdx.x >= pack_blocks + prep_blocks) {  // the cells' list setup, one cell per thread
-    const int c = (blockIdx.x - pack_blocks - prep_blocks) * blockDim.x + threadIdx.x;
-    if (c < nrec) cell_setup(r, c);
-  } else if ((int)blockIdx.x < pack_blocks) {
+  if ((int)blockIdx.x < pack_blocks) {
     const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (wid < a.ns) pack_leaf(wid, lane, t, a.sleaves, D, a.ij, a.w64, a.s32, a.stride, a.leaf_w);
   } else {
@@ -469,16 +467,14 @@ void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const
                     float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                     const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                     double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                    double* self_logd, const RecordArgs* rec, hipStream_t s) {
+                    double* self_logd, hipStream_t s) {
   const int gp = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
   const int gt = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
-  const int nrec = rec ? rec->t.ncells : 0;
-  const int gr = (nrec + 255) / 256;
-  if (gp + gt + gr <= 0) return;
+  if (gp + gt <= 0) return;
   const PackArgs a{sleaves, nsleaves, ij, w64, s32, stride, leaf_w};
   const PrepArgs b{tleaves, ntleaves, tx, ty, perm, x0, y0, h, nx, ny, snap_frac2, f, rel32, rel64, tleaf, self_w,
                    self_logd};
-  k_pack_prep<<<gp + gt + gr, 256, 0, s>>>(t, D, a, gp, b, gt, rec ? *rec : RecordArgs{}, nrec);
+  k_pack_prep<<<gp + gt, 256, 0, s>>>(t, D, a, gp, b);
 }
 
 }  // namespace pp
