@@ -806,10 +806,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // near field as four small graphs was measured slower than issuing their
     // launches: each graph launch delays its first kernel).  Segment 1 is
     // complete (the host has seen its read-back), so the side stream starts
-    // without waiting on s: packing, lists and target preparation, then the
-    // near field.  The upward pass runs meanwhile on s (its launches issued
-    // between the side stream's), which then waits for the lists (M2L, L2L,
-    // L2P) and for the near field (finalize).
+    // without waiting on s: the lists with the packing and target preparation
+    // riding on their launch, then the near field.  The upward pass runs
+    // meanwhile on s (its launches issued after the side stream's first),
+    // which then waits for the lists (M2L, L2L) and for the near field
+    // (finalize, with L2P).
     if (lists_early) do_lists(s, nullptr);
     fork_work();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
