@@ -114,3 +114,21 @@ def test_treecode_list_modes_agree_bitwise(solver, monkeypatch):
         for k in env:
             monkeypatch.delenv(k)
         assert np.array_equal(got, ref) and np.array_equal(again, ref), env
+
+
+def test_treecode_timed_schedule_matches():
+    """The timed schedule (near field between HIP events; the per-leaf packing rides on the tree-code's
+    list launch) gives the same bits as the untimed one for grid sources."""
+    import paper_1610_04398_amd as pp
+    f, h, tx, ty = _case(17, n=96, nt=1500)
+    kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed", method="treecode")
+    s = pp.Solver(0)
+    try:
+        base = s.solve_grid(f, h, tx, ty, **kw)
+        s.set_profiling(2)
+        timed = s.solve_grid(f, h, tx, ty, **kw)
+        again = s.solve_grid(f, h, tx, ty, **kw)
+    finally:
+        s.close()
+    assert np.array_equal(base, timed) and np.array_equal(base, again)
+    assert rel_l2(base, direct.direct_grid(f, h, tx, ty)) < 1e-4
