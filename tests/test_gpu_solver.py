@@ -335,14 +335,17 @@ def test_list_modes_agree_bitwise(solver, monkeypatch):
         assert np.array_equal(got, ref) and np.array_equal(again, ref), env
 
 
+@pytest.mark.parametrize("exact_lists", ["0", "1"])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 1e-5)])
-def test_large_target_leaf_beside_fine_sources(precision, tol):
+def test_large_target_leaf_beside_fine_sources(monkeypatch, precision, tol, exact_lists):
     """Targets only in the empty half of a half-filled source grid (leaf_max 1) sit in a target leaf a
     quarter of the domain wide beside source leaves of the finest level.  Almost no source cell is
     accepted for it, so its near list holds nearly every source leaf, and the traversal below it needs a
     longer stack than the smallest frontier tier holds: the first solve repeats at the next tier, a second
-    call starts there, and both match the oracle's FMM and each other bit for bit."""
+    call starts there, and both match the oracle's FMM and each other bit for bit.  Run with the one-pass
+    lists and with the two-pass lists (count, then emit), whose count pass meets the overflow."""
     import paper_1610_04398_amd as pp
+    monkeypatch.setenv("PP_EXACT_LISTS", exact_lists)
     n = 128
     rng = np.random.Generator(np.random.PCG64(31))
     f = rng.standard_normal((n, n))
