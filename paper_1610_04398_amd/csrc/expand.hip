@@ -156,31 +156,24 @@ constexpr M2MTable make_m2m_table() {
 }
 __constant__ M2MTable c_m2m = make_m2m_table();
 
-// One M2M output coefficient a'_l of a parent from its children at LDS slots
-// slot0 + q (coefficients e + stride * slot), with the tables tm[q][l][k] in LDS.
-__device__ inline cplx m2m_coeff(int l, int nk, const double2* __restrict__ e, int stride, int slot0,
-                                 const int* __restrict__ hsrc, const int* __restrict__ quad,
-                                 const double2* __restrict__ tm, int P1) {
+// One child's share of the M2M output coefficient a'_l of its parent: the sum
+// over k <= l of row[k] a[k], with a the child's coefficients and row the
+// table tm[quadrant][l] (both in LDS).
+__device__ inline cplx m2m_child(int l, const double2* __restrict__ a, const double2* __restrict__ row) {
   double bx0 = 0.0, by0 = 0.0, bx1 = 0.0, by1 = 0.0;
-  for (int q = 0; q < nk; ++q) {
-    const int slot = slot0 + q;
-    if (!hsrc[slot]) continue;
-    const double2* a = e + (int64_t)slot * stride;
-    const double2* row = tm + ((int64_t)quad[slot] * P1 + l) * P1;
-    // two accumulators shorten the dependent chain
-    int k = 0;
-    for (; k + 1 <= l; k += 2) {
-      const double2 t0 = row[k], a0 = a[k], t1 = row[k + 1], a1 = a[k + 1];
-      bx0 += t0.x * a0.x - t0.y * a0.y;
-      by0 += t0.x * a0.y + t0.y * a0.x;
-      bx1 += t1.x * a1.x - t1.y * a1.y;
-      by1 += t1.x * a1.y + t1.y * a1.x;
-    }
-    if (k == l) {
-      const double2 t0 = row[k], a0 = a[k];
-      bx0 += t0.x * a0.x - t0.y * a0.y;
-      by0 += t0.x * a0.y + t0.y * a0.x;
-    }
+  // two accumulators shorten the dependent chain
+  int k = 0;
+  for (; k + 1 <= l; k += 2) {
+    const double2 t0 = row[k], a0 = a[k], t1 = row[k + 1], a1 = a[k + 1];
+    bx0 += t0.x * a0.x - t0.y * a0.y;
+    by0 += t0.x * a0.y + t0.y * a0.x;
+    bx1 += t1.x * a1.x - t1.y * a1.y;
+    by1 += t1.x * a1.y + t1.y * a1.x;
+  }
+  if (k == l) {
+    const double2 t0 = row[k], a0 = a[k];
+    bx0 += t0.x * a0.x - t0.y * a0.y;
+    by0 += t0.x * a0.y + t0.y * a0.x;
   }
   return {bx0 + bx1, by0 + by1};
 }
@@ -287,16 +280,29 @@ __global__ __launch_bounds__(kM2MThreads) void k_m2m(TreeView t, int c0, int c1,
     if (i >= deepest || kid0[i] < 0) e[i * P1 + l] = mp[(int64_t)c * P1 + l];
   }
   __syncthreads();
+  // Each (parent, coefficient) item takes four adjacent lanes, one per child
+  // slot; the four partial sums meet through two cross-lane adds, in the same
+  // order on every lane.  The trip count is the same for every lane, so whole
+  // wavefronts reach the exchanges.
   for (int d = levels - 1; d >= 0; --d) {
     const int lo = m2m_first(d), hi = m2m_first(d + 1);
-    for (int w = tid; w < (hi - lo) * P1; w += blockDim.x) {
-      const int i = lo + w / P1, l = w % P1;
-      const int c = cell[i];
-      if (c < 0 || !hsrc[i] || kid0[i] < 0) continue;
-      const int slot0 = m2m_first(d + 1) + 4 * (i - lo);
-      const cplx v = m2m_coeff(l, nkid[i], e, P1, slot0, hsrc, quad, tm, P1);
-      e[i * P1 + l] = make_double2(v.x, v.y);
-      mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
+    const int items = 4 * (hi - lo) * P1;
+    for (int base = 0; base < items; base += blockDim.x) {
+      const int w = base + tid, q = w & 3, item = w >> 2;
+      const int i = lo + item / P1, l = item % P1;
+      const int c = w < items ? cell[i] : -1;
+      const bool live = c >= 0 && hsrc[i] && kid0[i] >= 0;
+      const int slot = m2m_first(d + 1) + 4 * (i - lo) + q;
+      cplx v = {0.0, 0.0};
+      if (live && q < nkid[i] && hsrc[slot]) v = m2m_child(l, e + (int64_t)slot * P1, tm + ((int64_t)quad[slot] * P1 + l) * P1);
+      v.x += __shfl_xor(v.x, 1);
+      v.y += __shfl_xor(v.y, 1);
+      v.x += __shfl_xor(v.x, 2);
+      v.y += __shfl_xor(v.y, 2);
+      if (live && q == 0) {
+        e[i * P1 + l] = make_double2(v.x, v.y);
+        mp[(int64_t)c * P1 + l] = make_double2(v.x, v.y);
+      }
     }
     __syncthreads();
   }
