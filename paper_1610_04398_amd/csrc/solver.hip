@@ -87,6 +87,9 @@ struct pp_ctx {
   int cap_m2p = 512;  // the same for the tree-code variant's per-leaf lists
   int cap_tp2p = 96;
   bool exact_lists = false;  // PP_EXACT_LISTS=1 forces the two-pass lists
+  // untimed calls issue the second segment directly, as the timed ones do,
+  // instead of replaying it from a graph (PP_DIRECT_ISSUE=0 replays it)
+  int direct_issue = 1;
   int dense_levels = 9;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only
   hipEvent_t ev[13] = {};
@@ -704,7 +707,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // in the directly issued schedule.  (In the graph, lists and packing before
   // the fork made the replay 10% slower: there the packing stays its own
   // launch before the fork, and the lists run on the side stream.)
-  const bool fused = !direct && !exact_lists && c.profiling == 2;
+  // The second segment issued directly: timed calls, and by default untimed
+  // ones too (the replayed graph runs the side branch's kernels first, which
+  // made the multipole solve 2-4 % and the tree-code 15 % slower).
+  const bool issue2 = c.profiling == 2 || (c.profiling == 0 && c.direct_issue && ss != s);
+  const bool fused = !direct && !exact_lists && issue2;
   const LeafPass lpass =
       src.grid ? leaf_pass_grid(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d,
                                 ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf,
@@ -799,9 +806,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   };
 
   const int seq2 = published_seq(c) + 1;
-  if (c.profiling == 2) {
-    // The schedule of an untimed call with the near field bracketed by events
-    // on its own stream, every launch of this segment issued directly (a
+  if (issue2) {
+    // The schedule of a call with the near field on its own stream (bracketed
+    // by events in timing mode 2), every launch of this segment issued directly (a
     // captured graph drops event records, and replaying the pieces around the
     // near field as four small graphs was measured slower than issuing their
     // launches: each graph launch delays its first kernel).  Segment 1 is
@@ -814,9 +821,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     if (lists_early) do_lists(s, nullptr);
     fork_work();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
-    HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
+    if (c.profiling == 2) HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
     do_near(ss);
-    HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
+    if (c.profiling == 2) HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
     if (ss != s) HIPCHK(hipStreamWaitEvent(s, c.ev_lists, 0));
     do_downward();
     signal(c.ev_join, ss, s);
@@ -997,6 +1004,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   c->device = device;
   if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PP_DIRECT_ISSUE")) c->direct_issue = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;

@@ -367,12 +367,13 @@ def test_large_target_leaf_beside_fine_sources(monkeypatch, precision, tol, exac
     assert rel_max(first, exact) < 1e-6
 
 
-@pytest.mark.parametrize("near_stream", ["1", "0"])
-def test_graph_replay_matches_eager(monkeypatch, near_stream):
+@pytest.mark.parametrize("near_stream,direct_issue", [("1", "1"), ("1", "0"), ("0", "1")])
+def test_graph_replay_matches_eager(monkeypatch, near_stream, direct_issue):
     """Repeated solves on device inputs replay captured graphs (same shape and pointers; the second segment
     also needs the same tree).  Every call, with eager device work and synchronisations in between and with
     the source changed in place (same and different zero pattern), equals a context without replay bit for
-    bit; with the near field on its own stream (forked and joined inside the graphs) and without."""
+    bit; with the near field on its own stream (the second segment issued directly, or forked and joined
+    inside its graph) and without."""
     import torch
     import paper_1610_04398_amd as pp
     n = 128
@@ -387,8 +388,10 @@ def test_graph_replay_matches_eager(monkeypatch, near_stream):
     eager = pp.Solver(0)
     monkeypatch.delenv("PP_GRAPHS")
     monkeypatch.setenv("PP_NEAR_STREAM", near_stream)
+    monkeypatch.setenv("PP_DIRECT_ISSUE", direct_issue)
     fast = pp.Solver(0)
     monkeypatch.delenv("PP_NEAR_STREAM")
+    monkeypatch.delenv("PP_DIRECT_ISSUE")
     kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed")
     try:
         for it in range(10):

@@ -116,12 +116,13 @@ def test_treecode_list_modes_agree_bitwise(solver, monkeypatch):
         assert np.array_equal(got, ref) and np.array_equal(again, ref), env
 
 
-def test_treecode_timed_schedule_matches():
+def test_treecode_timed_schedule_matches(monkeypatch):
     """The timed schedule (near field between HIP events; the per-leaf packing rides on the tree-code's
     list launch) gives the same bits as the untimed one for grid sources."""
     import paper_1610_04398_amd as pp
     f, h, tx, ty = _case(17, n=96, nt=1500)
     kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed", method="treecode")
+    monkeypatch.setenv("PP_DIRECT_ISSUE", "0")  # untimed calls replay the second segment from a graph
     s = pp.Solver(0)
     try:
         base = s.solve_grid(f, h, tx, ty, **kw)
