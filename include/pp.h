@@ -290,7 +290,12 @@ const char* pp_last_error(const pp_ctx* ctx);
  * the estimated device footprints of the requests in flight plus its own fit
  * in hbm_budget_bytes, and their work (grid nodes plus targets) fits in
  * work_budget_points (0 = no bound for either; a request always runs when
- * nothing else is in flight).  The work bound keeps large requests from
+ * nothing else is in flight).  The memory counted is that of every slot: the
+ * buffers an idle slot keeps resident from its last request, or the larger of
+ * those and the footprint of the request a busy slot runs; a slot whose
+ * resident buffers leave the total above the budget after a request releases
+ * them (so once every request has finished, the slots hold at most the
+ * budget).  The work bound keeps large requests from
  * sharing the GPU with each other, which would stretch all of their
  * latencies, while small ones still overlap.  Requests admitted together run
  * concurrently and their kernels overlap on the device.  A request's result
@@ -342,6 +347,8 @@ pp_status pp_server_cancel(pp_server* s, uint64_t ticket);
 /* Finish every queued request, then stop the slots and free their memory. */
 pp_status pp_server_destroy(pp_server* s);
 const char* pp_server_last_error(const pp_server* s);
+/* Device bytes the server's slots hold right now (their resident buffers). */
+uint64_t pp_server_device_bytes(pp_server* s);
 /* Device bytes a request of this shape may use (the admission estimate). */
 uint64_t pp_footprint_estimate(int32_t nx, int32_t ny, int64_t m, int32_t p, int32_t leaf_max);
 

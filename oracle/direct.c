@@ -25,6 +25,7 @@
  * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -50,13 +51,19 @@ static inline void nsum_add(nsum *a, double x) {
  * Targets (tx[k], ty[k]), k < m.  out[k] receives P at target k.
  * Returns 0, or -1 on a bad argument.
  */
+/* Threads of the target loop (0: the OpenMP default).  The result does not
+ * depend on it: each target's sum runs in one thread in a fixed order. */
+static int oracle_threads = 0;
+void oracle_set_threads(int n) { oracle_threads = n > 0 ? n : 0; }
+int oracle_get_threads(void) { return oracle_threads > 0 ? oracle_threads : omp_get_max_threads(); }
+
 int oracle_direct_grid(int32_t nx, int32_t ny, double x0, double y0, double h, const double *f, int64_t m,
                        const double *tx, const double *ty, int32_t self_mode, double *out) {
   if (nx <= 0 || ny <= 0 || !(h > 0.0) || m < 0 || !f || (m > 0 && (!tx || !ty || !out))) return -1;
   if (self_mode != 0 && self_mode != 1) return -1;
   const double h2 = h * h;
   const double lnh = log(h);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(oracle_get_threads())
   for (int64_t k = 0; k < m; ++k) {
     const double px = tx[k], py = ty[k];
     nsum acc = {0.0, 0.0};
@@ -89,7 +96,7 @@ int oracle_direct_grid(int32_t nx, int32_t ny, double x0, double y0, double h, c
 int oracle_direct_points(int64_t n, const double *sx, const double *sy, const double *w, int64_t m,
                          const double *tx, const double *ty, double *out) {
   if (n < 0 || m < 0 || (n > 0 && (!sx || !sy || !w)) || (m > 0 && (!tx || !ty || !out))) return -1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) num_threads(oracle_get_threads())
   for (int64_t k = 0; k < m; ++k) {
     const double px = tx[k], py = ty[k];
     nsum acc = {0.0, 0.0};

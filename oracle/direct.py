@@ -44,8 +44,21 @@ def _load():
         lib.oracle_direct_grid.restype = ctypes.c_int
         lib.oracle_direct_points.argtypes = [ctypes.c_int64, d, d, d, ctypes.c_int64, d, d, d]
         lib.oracle_direct_points.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_get_threads.argtypes = []
+        lib.oracle_get_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the target loop (0 restores the OpenMP default); results do not depend on it."""
+    _load().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().oracle_get_threads())
 
 
 def _ptr(a: np.ndarray):

@@ -28,6 +28,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_server_cancel,
     pp_server_create,
     pp_server_destroy,
+    pp_server_device_bytes,
     pp_server_last_error,
     pp_server_submit,
     pp_server_wait,
@@ -356,6 +357,10 @@ class Server:
         if st == B.PP_ERR_BUSY:
             return False
         raise PPError(st, f"{pp_status_string(st)}: {pp_server_last_error(self._srv)}")
+
+    def device_bytes(self) -> int:
+        """Device memory the slots hold right now (their resident buffers)."""
+        return pp_server_device_bytes(self._srv)
 
     def close(self):
         if self._srv:

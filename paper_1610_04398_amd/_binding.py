@@ -39,7 +39,7 @@ UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
             "pp_surface_forces", "pp_pressure_source", "pp_viscous_forces", "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
             "pp_server_create", "pp_server_submit", "pp_server_wait", "pp_server_cancel", "pp_server_destroy",
-            "pp_server_last_error", "pp_footprint_estimate")
+            "pp_server_last_error", "pp_server_device_bytes", "pp_footprint_estimate")
 PP_ERR_TIMEOUT = -6
 PP_ERR_CANCELLED = -7
 PP_ERR_BUSY = -8
@@ -132,6 +132,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_server_destroy.restype = i32
     lib.pp_server_last_error.argtypes = [vp]
     lib.pp_server_last_error.restype = ctypes.c_char_p
+    lib.pp_server_device_bytes.argtypes = [vp]
+    lib.pp_server_device_bytes.restype = ctypes.c_uint64
     lib.pp_footprint_estimate.argtypes = [i32, i32, i64, i32, i32]
     lib.pp_footprint_estimate.restype = ctypes.c_uint64
     lib.pp_status_string.argtypes = [i32]
@@ -259,6 +261,10 @@ def pp_server_destroy(server) -> int:
 
 def pp_server_last_error(server) -> str:
     return lib().pp_server_last_error(server).decode()
+
+
+def pp_server_device_bytes(server) -> int:
+    return int(lib().pp_server_device_bytes(server))
 
 
 def pp_footprint_estimate(nx: int, ny: int, m: int, p: int, leaf_max: int) -> int:

@@ -27,6 +27,10 @@ void publish(const int* src, int count, int* ctr, int* mail, int seq_slot, hipSt
 // Whether the context runs the near field on a second stream beside the
 // expansions (on by default; the server turns it off when it runs several slots).
 void ctx_set_near_stream(pp_ctx* c, bool on);
+// Device bytes the context's buffers hold, and releasing all of them (the
+// next solve allocates again).
+size_t ctx_held_bytes(const pp_ctx* c);
+void ctx_trim(pp_ctx* c);
 
 // ---- ingest.hip: sources in Morton order, target keys ------------------------------
 // Morton tiles of 1024 indices cover [0, 4^k).

@@ -2,9 +2,11 @@
 //
 // Each slot owns a library context (its device buffers stay resident between
 // requests) and a HIP stream, and is driven by its own host thread; a request
-// is admitted to a free slot as soon as the sum of the estimated device
-// footprints of the requests in flight leaves room for it, and so does the
-// sum of their work (grid nodes plus targets).  Requests that arrive while
+// is admitted to a free slot as soon as the device memory of all slots (the
+// buffers each one holds, or the estimated footprint of the request it runs)
+// leaves room for it, and so does the sum of the work in flight (grid nodes
+// plus targets).  A slot whose resident buffers push the total over the
+// budget after a request releases them.  Requests that arrive while
 // others are running therefore start immediately and their kernels overlap on
 // the GPU with the others'; the work bound stops several large requests from
 // dividing the GPU between them, which would stretch each one's latency.  A
@@ -73,6 +75,10 @@ struct pp_server {
   std::vector<std::thread> workers;
   std::vector<pp_ctx*> ctxs;
   std::vector<hipStream_t> streams;
+  // device bytes each slot's context holds between requests (its buffers stay
+  // resident), and the footprint of the request a slot is running (0 = idle)
+  std::vector<uint64_t> held;
+  std::vector<uint64_t> running_fp;
   std::string err;
 };
 
@@ -109,7 +115,13 @@ void worker_loop(pp_server* s, int slot) {
         // FIFO admission: the head runs when the memory and work bounds leave
         // room for it (always when nothing else is in flight)
         if (s->inflight == 0) return true;
-        const bool mem_ok = s->cfg.hbm_budget_bytes == 0 || s->inflight_bytes + head.footprint <= s->cfg.hbm_budget_bytes;
+        // device memory once the head runs here: every other slot's resident
+        // buffers (or its running request's footprint, if larger) plus this
+        // slot's buffers grown to the head's footprint
+        uint64_t resident = std::max(s->held[slot], head.footprint);
+        for (int o = 0; o < (int)s->held.size(); ++o)
+          if (o != slot) resident += std::max(s->held[o], s->running_fp[o]);
+        const bool mem_ok = s->cfg.hbm_budget_bytes == 0 || resident <= s->cfg.hbm_budget_bytes;
         const bool work_ok =
             s->cfg.work_budget_points == 0 || s->inflight_work + head.work <= s->cfg.work_budget_points;
         return mem_ok && work_ok;
@@ -120,6 +132,7 @@ void worker_loop(pp_server* s, int slot) {
       s->inflight += 1;
       s->inflight_bytes += job->footprint;
       s->inflight_work += job->work;
+      s->running_fp[slot] = job->footprint;
       job->slot = slot;
       job->t_start = clk::now();
       // a request that starts alone on the GPU runs its near field on the
@@ -147,6 +160,18 @@ void worker_loop(pp_server* s, int slot) {
       s->inflight -= 1;
       s->inflight_bytes -= job->footprint;
       s->inflight_work -= job->work;
+      s->running_fp[slot] = 0;
+      // a slot whose buffers push the resident total over the budget (after a
+      // request larger than the others) gives them back
+      s->held[slot] = pp::ctx_held_bytes(ctx);
+      if (s->cfg.hbm_budget_bytes) {
+        uint64_t total = 0;
+        for (int o = 0; o < (int)s->held.size(); ++o) total += std::max(s->held[o], s->running_fp[o]);
+        if (total > s->cfg.hbm_budget_bytes) {
+          pp::ctx_trim(ctx);
+          s->held[slot] = pp::ctx_held_bytes(ctx);
+        }
+      }
     }
     s->cv_done.notify_all();
     s->cv_work.notify_all();
@@ -156,7 +181,9 @@ void worker_loop(pp_server* s, int slot) {
       ctx = nullptr;
       if (pp_create(s->cfg.device, 0, &ctx) != PP_OK) return;
       if (s->cfg.max_slots > 1) pp::ctx_set_near_stream(ctx, false);
+      std::lock_guard<std::mutex> lk(s->mu);
       s->ctxs[slot] = ctx;
+      s->held[slot] = 0;
     }
   }
 }
@@ -177,7 +204,8 @@ pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out) {
   for (int i = 0; i < cfg->max_slots; ++i) {
     pp_ctx* c = nullptr;
     hipStream_t st = nullptr;
-    if (pp_create(cfg->device, 0, &c) != PP_OK || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    if (pp_create(cfg->device, 0, &c) != PP_OK ||
+        hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       if (c) pp_destroy(c);
       for (auto* x : s->ctxs) pp_destroy(x);
       for (auto x : s->streams) (void)hipStreamDestroy(x);
@@ -190,6 +218,8 @@ pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out) {
     if (cfg->max_slots > 1) pp::ctx_set_near_stream(c, false);
     s->ctxs.push_back(c);
     s->streams.push_back(st);
+    s->held.push_back(0);
+    s->running_fp.push_back(0);
   }
   for (int i = 0; i < cfg->max_slots; ++i) s->workers.emplace_back(worker_loop, s, i);
   *out = s;
@@ -289,5 +319,13 @@ pp_status pp_server_destroy(pp_server* s) {
 }
 
 const char* pp_server_last_error(const pp_server* s) { return s ? s->err.c_str() : "null server"; }
+
+uint64_t pp_server_device_bytes(pp_server* s) {
+  if (!s) return 0;
+  std::lock_guard<std::mutex> lk(s->mu);
+  uint64_t total = 0;
+  for (uint64_t b : s->held) total += b;
+  return total;
+}
 
 }  // extern "C"

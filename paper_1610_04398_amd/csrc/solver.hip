@@ -118,6 +118,11 @@ struct pp_ctx {
   uint64_t budget = 0;
   size_t held = 0;
   DevBuf bufs[B_COUNT];
+  // Planning pass: ensure() records the bytes each buffer needs instead of
+  // allocating, so that a call can check its footprint against the budget
+  // before it allocates or enqueues anything.
+  bool planning = false;
+  size_t plan_need[B_COUNT] = {};
   // kMiscInts + kMailExtra ints of coherent pinned host memory for read-backs;
   // slot kSeqSlot receives the sequence number of the last published read-back
   int* pinned = nullptr;
@@ -145,11 +150,14 @@ void release(pp_ctx& c, int id) {
 template <class T>
 T* ensure(pp_ctx& c, int id, int64_t count) {
   const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  if (c.planning) {
+    c.plan_need[id] = std::max(c.plan_need[id], bytes);
+    return (T*)(uintptr_t)256;  // never dereferenced: nothing is enqueued while planning
+  }
   DevBuf& b = c.bufs[id];
   if (b.bytes >= bytes) return (T*)b.p;
-  size_t want = bytes + bytes / 4;
   const size_t others = c.held - b.bytes;
-  if (c.budget && others + want > c.budget) want = bytes;
+  size_t want = c.budget ? bytes : bytes + bytes / 4;  // headroom only without a budget
   if (c.budget && others + want > c.budget)
     throw PPError{PP_ERR_NOMEM, "device-memory budget exceeded (" + std::to_string(others + want) + " > " +
                                     std::to_string(c.budget) + " bytes)"};
@@ -166,6 +174,34 @@ T* ensure(pp_ctx& c, int id, int64_t count) {
   b.bytes = want;
   c.held += want;
   return (T*)p;
+}
+
+// Runs `alloc` (a block of ensure() calls with no other effect) once as a
+// plan, checks that the buffers it asks for fit the context's budget together
+// with everything else the context holds (PP_ERR_NOMEM before anything is
+// allocated or enqueued), then runs it for real.  While a budget is set, the
+// buffers of a planned block get no growth headroom, so the check is exact.
+template <class F>
+void reserve(pp_ctx& c, F&& alloc) {
+  if (!c.budget) {
+    alloc();
+    return;
+  }
+  std::fill(std::begin(c.plan_need), std::end(c.plan_need), (size_t)0);
+  c.planning = true;
+  try {
+    alloc();
+  } catch (...) {
+    c.planning = false;
+    throw;
+  }
+  c.planning = false;
+  size_t total = 0;
+  for (int i = 0; i < B_COUNT; ++i) total += std::max(c.bufs[i].bytes, c.plan_need[i]);
+  if (total > c.budget)
+    throw PPError{PP_ERR_NOMEM, "the solve needs " + std::to_string(total) + " bytes of device memory, more than the "
+                                "context's budget of " + std::to_string(c.budget) + " bytes"};
+  alloc();
 }
 
 bool is_device_ptr(const void* p) {
@@ -393,38 +429,134 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto mark = [&](int i) {
     if (c.profiling == 1) HIPCHK(hipEventRecord(c.ev[i], s));
   };
-  const double* f_d = src.grid ? stage_in(c, B_F, src.f, ngrid, s) : nullptr;
-  const double* tx_d = stage_in(c, B_TX, tx, m, s);
-  const double* ty_d = stage_in(c, B_TY, ty, m, s);
+  // Every buffer of the first segment (staging copies of host inputs included)
+  // depends on the input sizes only: sized, and checked against the budget,
+  // before anything is allocated or enqueued.
+  const bool f_host = src.grid && ngrid > 0 && !is_device_ptr(src.f);
+  const bool t_host = m > 0 && !is_device_ptr(tx);
+  const bool ty_host = m > 0 && !is_device_ptr(ty);
   const bool out_on_device = is_device_ptr(p_out);
-  double* out_d = out_on_device ? p_out : ensure<double>(c, B_OUT, m);
+  const bool pts_host = !src.grid && src.n > 0 && !is_device_ptr(src.sx);
+  const bool ptsy_host = !src.grid && src.n > 0 && !is_device_ptr(src.sy);
+  const bool ptsw_host = !src.grid && src.n > 0 && !is_device_ptr(src.w);
+  const int D = src.grid ? root_exponent(nx, ny) : kPointsDepth;
+  const int k = D;
+  // capacities from the input sizes (the source count is only known on the device)
+  const int64_t ntiles = src.grid ? ingest_num_tiles(k) : 1;
+  int64_t geo = 0;
+  for (int l = 0; l <= D; ++l) geo += (int64_t)1 << (2 * l);
+  const int64_t per_level = 4 * (nmax / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
+  const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
+  if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
+  const bool treecode = prm.method == PP_METHOD_TREECODE;
+  const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
+  const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
+  // levels 0..Ld from the dense prefix table, the rest one level at a time
+  const int Ld = std::min(D, c.dense_levels);
+  const int64_t dense_np = ((int64_t)1 << (2 * Ld)) + 1;
+  const int64_t dense_F = tree_dense_cells(Ld);
+  const int64_t wmax = std::min<int64_t>(cap, per_level);
+  const int nbox = src.grid ? 0 : points_box_blocks(src.n + m);
 
-  int* misc = ensure<int>(c, B_MISC, kMiscInts);
+  double* f_stage = nullptr;
+  double *tx_stage = nullptr, *ty_stage = nullptr, *out_d = p_out;
+  double *psx_stage = nullptr, *psy_stage = nullptr, *pw_stage = nullptr;
+  int* misc = nullptr;
+  double4* boxp = nullptr;
+  int* boxc = nullptr;
+  uint32_t *skey = nullptr, *sij = nullptr, *skey2 = nullptr, *tkey = nullptr, *tkey2 = nullptr;
+  double *sw = nullptr, *pxs = nullptr, *pys = nullptr;
+  int *tile = nullptr, *sort_tmp = nullptr, *sperm2 = nullptr, *tperm = nullptr, *tperm2 = nullptr;
+  TreeArrays ta{};
+  int4* rec = nullptr;
+  int *cm2l = nullptr, *om2l = nullptr, *cp2p = nullptr, *op2p = nullptr;
+  int *dss = nullptr, *dts = nullptr, *dflag = nullptr, *doff = nullptr;
+  int4* cr = nullptr;
+  int *sp = nullptr, *ex = nullptr, *off = nullptr, *scan = nullptr;
+  int *sleaves = nullptr, *tleaves = nullptr, *tcells = nullptr, *flag3 = nullptr;
+  reserve(c, [&] {
+    if (f_host) f_stage = ensure<double>(c, B_F, ngrid);
+    if (t_host) tx_stage = ensure<double>(c, B_TX, m);
+    if (ty_host) ty_stage = ensure<double>(c, B_TY, m);
+    out_d = out_on_device ? p_out : ensure<double>(c, B_OUT, m);
+    misc = ensure<int>(c, B_MISC, kMiscInts);
+    if (!src.grid) {
+      if (pts_host) psx_stage = ensure<double>(c, B_PSX, src.n);
+      if (ptsy_host) psy_stage = ensure<double>(c, B_PSY, src.n);
+      if (ptsw_host) pw_stage = ensure<double>(c, B_PW, src.n);
+      boxp = ensure<double4>(c, B_BOXP, nbox);
+      boxc = ensure<int>(c, B_BOXC, nbox);
+    }
+    scan = ensure<int>(c, B_SCAN,
+                       std::max<int64_t>((int64_t)scan_temp_ints(std::max<int64_t>({ntiles, 4 * per_level, cap, m, nmax, 1})),
+                                         tree_dense_part_ints(Ld)));
+    skey = ensure<uint32_t>(c, B_SKEY, nmax);
+    sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
+    sw = ensure<double>(c, B_SW, nmax);
+    tile = src.grid ? ensure<int>(c, B_TILE, ntiles) : nullptr;
+    sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.grid ? 0 : src.n, m)));
+    skey2 = src.grid ? nullptr : ensure<uint32_t>(c, B_SKEY2, src.n);
+    sperm2 = src.grid ? nullptr : ensure<int>(c, B_SPERM2, src.n);
+    if (!src.grid) {
+      pxs = ensure<double>(c, B_PXS, src.n);
+      pys = ensure<double>(c, B_PYS, src.n);
+    }
+    tkey = ensure<uint32_t>(c, B_TKEY, m);
+    tperm = ensure<int>(c, B_TPERM, m);
+    tkey2 = ensure<uint32_t>(c, B_TKEY2, m);
+    tperm2 = ensure<int>(c, B_TPERM2, m);
+    ta = TreeArrays{ensure<int>(c, B_LVL, cap),  ensure<int>(c, B_IX, cap),    ensure<int>(c, B_IY, cap),
+                    ensure<int>(c, B_SB, cap),   ensure<int>(c, B_SE, cap),    ensure<int>(c, B_TB, cap),
+                    ensure<int>(c, B_TE, cap),   ensure<int>(c, B_CHILD, cap), ensure<int>(c, B_NCHILD, cap),
+                    ensure<int>(c, B_PARENT, cap)};
+    // the lists' per-cell setup (records, counts, one-pass offsets) is written by
+    // the first segment's cell classification, so its buffers hold `cap` cells
+    rec = direct ? nullptr : ensure<int4>(c, B_REC, cap);
+    cm2l = ensure<int>(c, B_CM2L, cap);
+    om2l = ensure<int>(c, B_OM2L, cap);
+    cp2p = ensure<int>(c, B_CP2P, cap);
+    op2p = ensure<int>(c, B_OP2P, cap);
+    dss = ensure<int>(c, B_DSS, dense_np);
+    dts = ensure<int>(c, B_DTS, dense_np);
+    dflag = ensure<int>(c, B_DFLAG, dense_F);
+    doff = ensure<int>(c, B_DOFF, dense_F);
+    cr = ensure<int4>(c, B_CR, 4 * wmax);
+    sp = ensure<int>(c, B_SPLIT, 6 * wmax);
+    ex = ensure<int>(c, B_CNT, 4 * wmax);
+    off = ensure<int>(c, B_OFF, 4 * wmax);
+    sleaves = ensure<int>(c, B_SLEAF, cap);
+    tleaves = ensure<int>(c, B_TLEAF, cap);
+    tcells = ensure<int>(c, B_TCELL, cap);
+    flag3 = ensure<int>(c, B_FLAG, classify_part_ints(cap));  // per-tile counts of the classification
+  });
+  auto copy_in = [&](double* dst, const double* srcp, int64_t n) -> const double* {
+    if (!dst) return srcp;
+    HIPCHK(hipMemcpyAsync(dst, srcp, (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+    return dst;
+  };
+  const double* f_d = src.grid ? copy_in(f_stage, src.f, ngrid) : nullptr;
+  const double* tx_d = copy_in(tx_stage, tx, m);
+  const double* ty_d = copy_in(ty_stage, ty, m);
   unsigned long long* pairs = (unsigned long long*)(misc + M_PAIRS);  // 8-byte aligned slot
 
   // root square: anchor (x0, y0), finest cell side `unit`, finest level D
-  int D = 0;
   double x0 = 0.0, y0 = 0.0, unit = 1.0;
   const double *psx = nullptr, *psy = nullptr, *pw = nullptr;
   if (src.grid) {
-    D = root_exponent(nx, ny);
     x0 = src.x0;
     y0 = src.y0;
     unit = src.h;
   } else {
     fill_i32(misc, 0, kMiscInts, s);
-    psx = stage_in(c, B_PSX, src.sx, src.n, s);
-    psy = stage_in(c, B_PSY, src.sy, src.n, s);
-    pw = stage_in(c, B_PW, src.w, src.n, s);
-    const int nb = points_box_blocks(src.n + m);
+    psx = copy_in(psx_stage, src.sx, src.n);
+    psy = copy_in(psy_stage, src.sy, src.n);
+    pw = copy_in(pw_stage, src.w, src.n);
     double* box = (double*)(misc + M_BOX);
-    points_box(psx, psy, pw, src.n, tx_d, ty_d, m, ensure<double4>(c, B_BOXP, nb), ensure<int>(c, B_BOXC, nb), box,
-               misc + M_NSRC, misc + M_FLAGS, s);
+    points_box(psx, psy, pw, src.n, tx_d, ty_d, m, boxp, boxc, box, misc + M_NSRC, misc + M_FLAGS, s);
     readback(c, misc, 0, M_BOX + 8, s);
     check_flags(c.pinned[M_FLAGS]);
     double bx[4];
     std::memcpy(bx, c.pinned + M_BOX, sizeof(bx));
-    D = kPointsDepth;
     x0 = bx[0];
     y0 = bx[2];
     // the same FP64 differences the key kernels form for the extreme points
@@ -438,68 +570,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       unit = std::ldexp(1.0, e);
     }
   }
-  const int k = D;
-
-  // capacities from the input sizes (the source count is only known on the device)
-  const int64_t ntiles = src.grid ? ingest_num_tiles(k) : 1;
-  int64_t geo = 0;
-  for (int l = 0; l <= D; ++l) geo += (int64_t)1 << (2 * l);
-  const int64_t per_level = 4 * (nmax / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
-  const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
-  if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
-  ensure<int>(c, B_SCAN, std::max<int64_t>((int64_t)scan_temp_ints(std::max<int64_t>({ntiles, 4 * per_level, cap, m, nmax, 1})),
-                                            tree_dense_part_ints(std::min(D, c.dense_levels))));
-
-  uint32_t* skey = ensure<uint32_t>(c, B_SKEY, nmax);
-  uint32_t* sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
-  double* sw = ensure<double>(c, B_SW, nmax);
-  double *pxs = nullptr, *pys = nullptr;
-  // every buffer of the first segment, sized before anything is enqueued
-  int* tile = src.grid ? ensure<int>(c, B_TILE, ntiles) : nullptr;
-  int* sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.grid ? 0 : src.n, m)));
-  uint32_t* skey2 = src.grid ? nullptr : ensure<uint32_t>(c, B_SKEY2, src.n);
-  int* sperm2 = src.grid ? nullptr : ensure<int>(c, B_SPERM2, src.n);
-  if (!src.grid) {
-    pxs = ensure<double>(c, B_PXS, src.n);
-    pys = ensure<double>(c, B_PYS, src.n);
-  }
-  uint32_t* tkey = ensure<uint32_t>(c, B_TKEY, m);
-  int* tperm = ensure<int>(c, B_TPERM, m);
-  uint32_t* tkey2 = ensure<uint32_t>(c, B_TKEY2, m);
-  int* tperm2 = ensure<int>(c, B_TPERM2, m);
-  TreeArrays ta{ensure<int>(c, B_LVL, cap),   ensure<int>(c, B_IX, cap),     ensure<int>(c, B_IY, cap),
-                ensure<int>(c, B_SB, cap),    ensure<int>(c, B_SE, cap),     ensure<int>(c, B_TB, cap),
-                ensure<int>(c, B_TE, cap),    ensure<int>(c, B_CHILD, cap),  ensure<int>(c, B_NCHILD, cap),
-                ensure<int>(c, B_PARENT, cap)};
-  // the lists' per-cell setup (records, counts, one-pass offsets) is written by
-  // the first segment's cell classification, so its buffers hold `cap` cells
-  const bool treecode = prm.method == PP_METHOD_TREECODE;
-  const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
-  const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
-  int4* rec = direct ? nullptr : ensure<int4>(c, B_REC, cap);
-  int* cm2l = ensure<int>(c, B_CM2L, cap);
-  int* om2l = ensure<int>(c, B_OM2L, cap);
-  int* cp2p = ensure<int>(c, B_CP2P, cap);
-  int* op2p = ensure<int>(c, B_OP2P, cap);
   int* ls_d = misc + M_LS;
-  // levels 0..Ld from the dense prefix table, the rest one level at a time
-  const int Ld = std::min(D, c.dense_levels);
-  const int64_t dense_np = ((int64_t)1 << (2 * Ld)) + 1;
-  const int64_t dense_F = tree_dense_cells(Ld);
-  int* dss = ensure<int>(c, B_DSS, dense_np);
-  int* dts = ensure<int>(c, B_DTS, dense_np);
-  int* dflag = ensure<int>(c, B_DFLAG, dense_F);
-  int* doff = ensure<int>(c, B_DOFF, dense_F);
-  const int64_t wmax = std::min<int64_t>(cap, per_level);
-  int4* cr = ensure<int4>(c, B_CR, 4 * wmax);
-  int* sp = ensure<int>(c, B_SPLIT, 6 * wmax);
-  int* ex = ensure<int>(c, B_CNT, 4 * wmax);
-  int* off = ensure<int>(c, B_OFF, 4 * wmax);
-  int* scan = ensure<int>(c, B_SCAN, 1);  // sized above for every scan of the solve
-  int* sleaves = ensure<int>(c, B_SLEAF, cap);
-  int* tleaves = ensure<int>(c, B_TLEAF, cap);
-  int* tcells = ensure<int>(c, B_TCELL, cap);
-  int* flag3 = ensure<int>(c, B_FLAG, classify_part_ints(cap));  // per-tile counts of the classification
 
   // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
   // (graph replay only for device-resident grid input: host input is staged by copies)
@@ -562,33 +633,42 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
-  // ---- every buffer of the second segment, sized before anything is enqueued ----
+  // ---- every buffer of the second segment, sized (and checked against the
+  // budget) from the tree's counts before anything of it is allocated ----
   int* m2l_src = nullptr;
   int* p2p_src = nullptr;
   int64_t n_m2l = 0, n_p2pl = 0;
-  // the tree-code variant lists per target leaf (M2P cells, P2P leaves); the
-  // multipole method lists per cell with targets (M2L cells, P2P leaves)
-  if (!direct && !exact_lists) {
-    m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
-    p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
-  }
-  float* s32 = ensure<float>(c, B_SRC4, 3 * std::max<int64_t>(N, 1));  // x, y, w planes of stride N
-  double* leaf_w = ensure<double>(c, B_LEAFW, ncells);
-  float2* rel32 = ensure<float2>(c, B_REL32, m);
-  double2* rel64 = ensure<double2>(c, B_REL64, m);
-  int* tgtleaf = ensure<int>(c, B_TGTLEAF, m);
-  double* selfd = src.grid ? ensure<double>(c, B_SELFD, m) : nullptr;
-  double* selfw = ensure<double>(c, B_SELFW, m);
-  double2* s64 = src.grid ? nullptr : ensure<double2>(c, B_S64, N);
-  double2* mp = direct ? nullptr : ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
-  double2* loc = (direct || treecode) ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
-  double2* own = (direct || treecode) ? nullptr : ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
   // the tree-code's M2P leaves its list parts' partial sums side by side
   const int far_parts = treecode ? kM2PParts : 1;
-  double* far = direct ? nullptr : ensure<double>(c, B_FAR, m * far_parts);
   const int nparts = c.p2p_parts;
-  double* near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
-  long long* pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
+  float* s32 = nullptr;
+  double *leaf_w = nullptr, *selfd = nullptr, *selfw = nullptr, *far = nullptr, *near = nullptr;
+  float2* rel32 = nullptr;
+  double2 *rel64 = nullptr, *s64 = nullptr, *mp = nullptr, *loc = nullptr, *own = nullptr;
+  int* tgtleaf = nullptr;
+  long long* pcount = nullptr;
+  reserve(c, [&] {
+    // the tree-code variant lists per target leaf (M2P cells, P2P leaves); the
+    // multipole method lists per cell with targets (M2L cells, P2P leaves)
+    if (!direct && !exact_lists) {
+      m2l_src = ensure<int>(c, B_M2LSRC, (int64_t)ncells * cap_far);
+      p2p_src = ensure<int>(c, B_P2PSRC, (int64_t)ncells * cap_near);
+    }
+    s32 = ensure<float>(c, B_SRC4, 3 * std::max<int64_t>(N, 1));  // x, y, w planes of stride N
+    leaf_w = ensure<double>(c, B_LEAFW, ncells);
+    rel32 = ensure<float2>(c, B_REL32, m);
+    rel64 = ensure<double2>(c, B_REL64, m);
+    tgtleaf = ensure<int>(c, B_TGTLEAF, m);
+    selfd = src.grid ? ensure<double>(c, B_SELFD, m) : nullptr;
+    selfw = ensure<double>(c, B_SELFW, m);
+    s64 = src.grid ? nullptr : ensure<double2>(c, B_S64, N);
+    mp = direct ? nullptr : ensure<double2>(c, B_MP, (int64_t)ncells * (p + 1));
+    loc = (direct || treecode) ? nullptr : ensure<double2>(c, B_LOC, (int64_t)ncells * (p + 1));
+    own = (direct || treecode) ? nullptr : ensure<double2>(c, B_OWNLOC, (int64_t)ncells * (p + 1));
+    far = direct ? nullptr : ensure<double>(c, B_FAR, m * far_parts);
+    near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
+    pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
+  });
   P2PArgs pa{};
   pa.t = tv;
   pa.tleaves = tleaves;
@@ -818,7 +898,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // meanwhile on s (its launches issued after the side stream's first),
     // which then waits for the lists (M2L, L2L) and for the near field
     // (finalize, with L2P).
-    if (lists_early) do_lists(s, nullptr);
+    if (lists_early) {
+      // the two-pass lists are emitted on s: the near field on the side stream
+      // reads them, so that stream waits for the emit pass
+      do_lists(s, nullptr);
+      signal(c.ev_fork, s, ss);
+    }
     fork_work();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
     if (c.profiling == 2) HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
@@ -1116,6 +1201,17 @@ void run_force_kernel(pp_ctx& c, int64_t m, int32_t nseg, const int64_t* seg_sta
 
 void pp::ctx_set_near_stream(pp_ctx* c, bool on) {
   if (c) c->near_stream = on;
+}
+
+size_t pp::ctx_held_bytes(const pp_ctx* c) { return c ? c->held : 0; }
+
+void pp::ctx_trim(pp_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (auto& g : c->seg) drop_graph(g);
+  for (int i = 0; i < B_COUNT; ++i) release(*c, i);
+  c->gen += 1;
+  c->last.valid = false;
 }
 
 namespace {

@@ -6,7 +6,7 @@
 // split when it holds more than leaf_max sources or more than leaf_max
 // targets, and its children (quadrant order q = qx + 2 qy) are kept when
 // non-empty.  Cells are numbered level by level, in Morton order within a
-// level.  The top levels (up to 8) come from one dense table of Morton
+// level.  The top levels (up to 9, the default) come from one dense table of Morton
 // prefixes in a fixed number of launches; deeper levels are built top down,
 // one launch group per level, a child's source and target ranges found by
 // binary search of its key prefix inside the parent's ranges.

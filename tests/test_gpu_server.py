@@ -88,6 +88,31 @@ def test_admission_respects_budget(pp):
         assert sum(fps[j] for j in running) <= budget or len(running) == 1, (i, running)
 
 
+def test_resident_memory_stays_under_budget(pp):
+    """Idle slots keep their buffers between requests; the admission counts them, and a slot whose
+    buffers leave the total above the budget after a large request releases them, so that once every
+    request has finished the slots hold at most the budget (and results stay bitwise those of a lone
+    solve)."""
+    reqs = _requests(n=8, seed=14)
+    fps = sorted(pp.pp_footprint_estimate(r["g"].nx, r["g"].ny, r["tx"].size, 12, 64) for r in reqs)
+    budget = fps[-1] + fps[0]
+    srv = pp.Server(0, max_slots=3, hbm_budget_bytes=budget)
+    outs = [np.empty(r["tx"].size) for r in reqs]
+    tickets = [srv.submit(r["f"], r["g"].h, r["tx"], r["ty"], o) for r, o in zip(reqs, outs)]
+    for t in tickets:
+        srv.wait(t)
+    held = srv.device_bytes()
+    srv.close()
+    assert held <= budget, (held, budget)
+    s = pp.Solver(0)
+    try:
+        for r, o in zip(reqs[:3], outs[:3]):
+            assert np.array_equal(s.solve_grid(r["f"], r["g"].h, r["tx"], r["ty"], p=12, theta=0.5,
+                                               precision="mixed"), o)
+    finally:
+        s.close()
+
+
 def test_failing_request_reports_its_own_status(pp):
     reqs = _requests(n=4, seed=7)
     srv = pp.Server(0, max_slots=2)

@@ -191,20 +191,77 @@ def test_host_and_device_pointers_agree_and_deterministic(solver):
     assert np.array_equal(P1, P2) and np.array_equal(P2, P3)
 
 
-def test_vortex512_sampled(solver):
-    """The 512^2 vortex workload at full size; targets sampled for the oracle."""
+# Observed on MI355X (all 264,192 targets of vortex512, against the oracle):
+# mixed rel-L2 ~6e-8, rel-max ~1.5e-7; FP64 rel-L2 ~1e-10.  The bounds below
+# sit about ten times above what the kernels reach, and far below the
+# tolerances of the accuracy contract (rel-L2 1e-4 mixed, 1e-6 FP64), so a
+# handful of wrong targets or a lost compensation fails them.
+C2_BOUNDS = {"fp64": {"rel_l2": 1e-6, "rel_l2_tight": 2e-9, "rel_max": 1e-8},
+             "mixed": {"rel_l2": 1e-4, "rel_l2_tight": 6e-7, "rel_max": 2e-6}}
+
+
+def _group_errors(P, ref, n_grid):
+    out = {}
+    for name, sl in (("grid", slice(0, n_grid)), ("surface", slice(n_grid, None))):
+        out[name] = {"rel_l2": rel_l2(P[sl], ref[sl]), "rel_max": rel_max(P[sl], ref[sl])}
+    return out
+
+
+def test_vortex512_full(solver):
+    """The 512^2 vortex workload at full size against the oracle at every one of its 264,192 targets
+    (262,144 grid nodes, 2,048 ellipse points), FP64 and mixed: rel-L2 separately over grid and surface
+    targets, and the largest error of any single target relative to max |P|."""
+    from oracle_cache import full_direct
     w = G.workload("vortex512")
     g = w["grid"]
-    rng = np.random.Generator(np.random.PCG64(12))
-    sel = np.concatenate([rng.choice(w["n_grid_targets"], 1500, replace=False),
-                          w["n_grid_targets"] + rng.choice(2048, 500, replace=False)])
-    ref = direct.direct_grid(w["f"], g.h, w["tx"][sel], w["ty"][sel])
+    ref = full_direct("vortex512")
     f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
-    for prec, tol in (("fp64", 1e-6), ("mixed", 1e-4)):
+    for prec in ("fp64", "mixed"):
         P = to_host(solver.solve_grid(f, g.h, tx, ty, p=12, theta=0.5, precision=prec))
-        e_grid = rel_l2(P[sel[:1500]], ref[:1500])
-        e_surf = rel_l2(P[sel[1500:]], ref[1500:])
-        assert e_grid < tol and e_surf < tol, (prec, e_grid, e_surf)
+        errs = _group_errors(P, ref, w["n_grid_targets"])
+        print(f"vortex512 {prec}: {errs}")
+        b = C2_BOUNDS[prec]
+        for grp, e in errs.items():
+            assert e["rel_l2"] < b["rel_l2"] and e["rel_l2"] < b["rel_l2_tight"], (prec, grp, e)
+            assert e["rel_max"] < b["rel_max"], (prec, grp, e)
+
+
+def test_vortex512_tree_bit_exact(solver):
+    """Morton keys, the target permutation, every cell array and both interaction lists of the full
+    vortex512 tree (5,733 cells) equal the reference quadtree's bit for bit."""
+    w = G.workload("vortex512")
+    g = w["grid"]
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    solver.solve_grid(f, g.h, tx, ty, p=12, theta=0.5, precision="mixed")
+    info = tree_ref.grid_tree(w["f"], w["tx"], w["ty"], g.h, leaf_max=64)
+    _compare_tree(solver, info, 0.5, g.nx)
+
+
+def test_vortex512_kahan_near_field(solver):
+    """Compensated FP32 near field (pin 11 of the accuracy contract): on the vortex512 lists, the
+    library's mixed-precision near sums of 40 sampled target leaves (2,400+ targets, ~1,500 sources each)
+    lie within 1e-6 (rel-L2) of the FP64 near sums over the same source sets, and are several times
+    closer to them than a plain FP32 running sum of the same FP32 terms in the same part split."""
+    from near_emulation import near_lists, near_sums
+    w = G.workload("vortex512")
+    g = w["grid"]
+    f, tx, ty = to_dev(w["f"], w["tx"], w["ty"])
+    solver.solve_grid(f, g.h, tx, ty, p=12, theta=0.5, precision="mixed")
+    near = solver.debug_array("NEAR")
+    m = w["tx"].size
+    parts = near.size // m
+    gpu = near.reshape(parts, m).sum(axis=0)
+    info = tree_ref.grid_tree(w["f"], w["tx"], w["ty"], g.h, leaf_max=64)
+    lists = near_lists(info["tree"], 0.5)
+    rng = np.random.Generator(np.random.PCG64(5))
+    leaves = sorted(lists)
+    pick = [leaves[i] for i in sorted(rng.choice(len(leaves), 40, replace=False))]
+    ref, naive, idx = near_sums(w["f"], g.h, w["tx"], w["ty"], info, lists, pick, nparts=parts)
+    e_gpu = rel_l2(gpu[idx], ref)
+    e_naive = rel_l2(naive, ref)
+    print(f"near field: compensated {e_gpu:.3e}, plain FP32 {e_naive:.3e} ({idx.size} targets)")
+    assert e_gpu < 1e-6, e_gpu
+    assert e_gpu * 5 < e_naive, (e_gpu, e_naive)
 
 
 def test_error_paths_leave_output_untouched(solver):
@@ -229,6 +286,27 @@ def test_error_paths_leave_output_untouched(solver):
         solver.solve_grid(f, -h, tx, ty, out=out)
     assert e.value.status == -1
     assert np.all(out == 7.0)
+
+
+def test_budget_exceeded_before_any_work():
+    """A context whose device-memory budget is too small for a solve returns PP_ERR_NOMEM before it
+    allocates or launches anything: the output is untouched, the context holds no new memory, and it
+    still solves a problem that fits the budget."""
+    import paper_1610_04398_amd as pp
+    budget = 4 << 20
+    s = pp.Solver(0, hbm_budget_bytes=budget)
+    try:
+        f, h, tx, ty = _case_random(8, n=128, nt=2000)
+        out = np.full(tx.size, 7.0)
+        with pytest.raises(pp.PPError) as e:
+            s.solve_grid(f, h, tx, ty, out=out)
+        assert e.value.status == -3 and np.all(out == 7.0)
+        assert "budget" in str(e.value)
+        small, hs, sx, sy = _case_random(9, n=16, nt=50)
+        got = s.solve_grid(small, hs, sx, sy, precision="fp64")
+        assert rel_l2(got, direct.direct_grid(small, hs, sx, sy)) < 1e-6
+    finally:
+        s.close()
 
 
 def test_degenerate_inputs(solver):
@@ -276,6 +354,8 @@ def test_degenerate_inputs(solver):
 
 
 def _sampled_check(solver, name, n_samples=600, seed=21):
+    """rel-L2 and largest single-target error (relative to max |P| of the sample) of FP64 and mixed solves
+    on seeded sampled targets, against the oracle evaluated at those targets one by one."""
     w = G.workload(name)
     g = w["grid"]
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -285,14 +365,28 @@ def _sampled_check(solver, name, n_samples=600, seed=21):
     errs = {}
     for prec in ("fp64", "mixed"):
         P = to_host(solver.solve_grid(f, g.h, tx, ty, p=w["p"], theta=w["theta"], precision=prec))
-        errs[prec] = rel_l2(P[sel], ref)
+        errs[prec] = {"rel_l2": rel_l2(P[sel], ref), "rel_max": rel_max(P[sel], ref)}
+    print(f"{name}: {errs}")
     return w, errs
+
+
+# Observed on MI355X at the sampled targets: band2048 (p = 16, theta = 0.4) mixed rel-L2 ~1e-7,
+# FP64 ~1e-12; envelope4096 (p = 12) mixed ~1e-7, FP64 ~1e-10.  Bounds about ten times above.
+SAMPLED_BOUNDS = {"band2048": {"fp64": (1e-9, 1e-8), "mixed": (1e-6, 3e-6)},
+                  "envelope4096": {"fp64": (1e-8, 1e-7), "mixed": (1e-6, 3e-6)}}
+
+
+def _check_bounds(name, errs):
+    for prec, (b_l2, b_max) in SAMPLED_BOUNDS[name].items():
+        tol = 1e-6 if prec == "fp64" else 1e-4
+        e = errs[prec]
+        assert e["rel_l2"] < tol and e["rel_l2"] < b_l2 and e["rel_max"] < b_max, (name, prec, e)
 
 
 def test_band2048_sampled(solver):
     """2048^2 band-masked vortex source, 16,384 surface/lifted targets, p=16, theta=0.4."""
     w, errs = _sampled_check(solver, "band2048")
-    assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-4, errs
+    _check_bounds("band2048", errs)
     # the tree of this adaptive case against the reference: arrays in full, lists on sampled cells
     info = tree_ref.grid_tree(w["f"], w["tx"], w["ty"], w["grid"].h, leaf_max=64)
     t = info["tree"]
@@ -311,11 +405,32 @@ def test_band2048_sampled(solver):
 
 
 def test_envelope4096_sampled(solver):
-    """4096^2 two-band envelope source (6.16M nonzero), 32,768 surface/lifted targets, p=12, theta=0.5."""
+    """4096^2 two-band envelope source (6.16M nonzero), 32,768 surface/lifted targets, p=12, theta=0.5.
+    Accuracy on sampled targets; the tree (depth 12, ~130k cells) against the reference quadtree: keys,
+    permutation and every cell array in full, the interaction lists on sampled target cells."""
     w, errs = _sampled_check(solver, "envelope4096", n_samples=400)
-    assert errs["fp64"] < 1e-6 and errs["mixed"] < 1e-4, errs
+    _check_bounds("envelope4096", errs)
     st = solver.stats()
     assert st["nsources"] == int(np.count_nonzero(w["f"]))
+    info = tree_ref.grid_tree(w["f"], w["tx"], w["ty"], w["grid"].h, leaf_max=64)
+    t = info["tree"]
+    np.testing.assert_array_equal(solver.debug_array("SRC_KEY").astype(np.uint64), info["src_keys"])
+    ij = solver.debug_array("SRC_INDEX").astype(np.int64)
+    assert np.array_equal((ij >> 16) * w["grid"].nx + (ij & 0xFFFF), info["src_flat"])
+    np.testing.assert_array_equal(solver.debug_array("TGT_KEY").astype(np.uint64), info["tgt_keys"])
+    np.testing.assert_array_equal(solver.debug_array("TGT_PERM"), info["tgt_perm"])
+    for name, ref in (("CELL_LEVEL", t.level), ("CELL_IX", t.ix), ("CELL_IY", t.iy), ("CELL_SB", t.sb),
+                      ("CELL_SE", t.se), ("CELL_TB", t.tb), ("CELL_TE", t.te), ("CELL_CHILD", t.child_begin),
+                      ("CELL_NCHILD", t.nchild), ("CELL_PARENT", t.parent)):
+        np.testing.assert_array_equal(solver.debug_array(name), ref, err_msg=name)
+    rng = np.random.Generator(np.random.PCG64(7))
+    tc = np.flatnonzero(t.te > t.tb)
+    off = {k: solver.debug_array(k) for k in ("M2L_OFF", "M2L_CNT", "M2L_SRC", "P2P_OFF", "P2P_CNT", "P2P_SRC")}
+    for a in rng.choice(tc, min(200, tc.size), replace=False):
+        lm, lp = tree_ref.lists_for_cell(t, int(a), w["theta"])
+        got_m = sorted(off["M2L_SRC"][off["M2L_OFF"][a]:off["M2L_OFF"][a] + off["M2L_CNT"][a]].tolist())
+        got_p = sorted(off["P2P_SRC"][off["P2P_OFF"][a]:off["P2P_OFF"][a] + off["P2P_CNT"][a]].tolist())
+        assert got_m == lm and got_p == lp, a
 
 
 def test_list_modes_agree_bitwise(solver, monkeypatch):
@@ -367,13 +482,17 @@ def test_large_target_leaf_beside_fine_sources(monkeypatch, precision, tol, exac
     assert rel_max(first, exact) < 1e-6
 
 
-@pytest.mark.parametrize("near_stream,direct_issue", [("1", "1"), ("1", "0"), ("0", "1")])
-def test_graph_replay_matches_eager(monkeypatch, near_stream, direct_issue):
+@pytest.mark.parametrize("near_stream,direct_issue,lists", [("1", "1", "onepass"), ("1", "0", "onepass"),
+                                                             ("0", "1", "onepass"), ("1", "1", "exact"),
+                                                             ("1", "1", "overflow")])
+def test_graph_replay_matches_eager(monkeypatch, near_stream, direct_issue, lists):
     """Repeated solves on device inputs replay captured graphs (same shape and pointers; the second segment
     also needs the same tree).  Every call, with eager device work and synchronisations in between and with
-    the source changed in place (same and different zero pattern), equals a context without replay bit for
-    bit; with the near field on its own stream (the second segment issued directly, or forked and joined
-    inside its graph) and without."""
+    the source changed in place (same and different zero pattern), equals a context without replay and with
+    every phase on one stream, bit for bit; with the near field on its own stream (the second segment issued
+    directly, or forked and joined inside its graph) and without.  The two-pass lists (forced, or the retry
+    after a one-pass list outgrew a tiny capacity) are emitted on the caller's stream before the near field
+    starts on the side stream, which must wait for them."""
     import torch
     import paper_1610_04398_amd as pp
     n = 128
@@ -385,13 +504,18 @@ def test_graph_replay_matches_eager(monkeypatch, near_stream, direct_issue):
     fd, txd, tyd = to_dev(base, tx, ty)
     out = torch.empty(tx.size, dtype=torch.float64, device="cuda")
     monkeypatch.setenv("PP_GRAPHS", "0")
+    monkeypatch.setenv("PP_NEAR_STREAM", "0")
     eager = pp.Solver(0)
     monkeypatch.delenv("PP_GRAPHS")
     monkeypatch.setenv("PP_NEAR_STREAM", near_stream)
     monkeypatch.setenv("PP_DIRECT_ISSUE", direct_issue)
+    if lists == "exact":
+        monkeypatch.setenv("PP_EXACT_LISTS", "1")
+    elif lists == "overflow":
+        monkeypatch.setenv("PP_LIST_CAPS", "3,2")
     fast = pp.Solver(0)
-    monkeypatch.delenv("PP_NEAR_STREAM")
-    monkeypatch.delenv("PP_DIRECT_ISSUE")
+    for k in ("PP_NEAR_STREAM", "PP_DIRECT_ISSUE", "PP_EXACT_LISTS", "PP_LIST_CAPS"):
+        monkeypatch.delenv(k, raising=False)
     kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed")
     try:
         for it in range(10):
