@@ -1,24 +1,29 @@
 #!/usr/bin/env python3
 """Benchmark of the pressure-Poisson tree-code on one MI355X.
 
-Workload (default ``vortex512``): a 512 x 512 grid of sources f = 2(u_x v_y -
-u_y v_x) from 64 seeded Lamb-Oseen vortices, targets = the 262,144 grid nodes
-plus 2,048 points on an ellipse, expansion order p = 12, acceptance theta =
-0.5, mixed precision (FP32 + Kahan near field and local evaluation, FP64
-expansions).  One step = one complete solve (ingest, target sort, tree,
-interaction lists, P2M, M2M, M2L, L2L, L2P, P2P, finalize) with the inputs
-already resident in device memory.  Repeated solves replay their launches from
-captured HIP graphs (the library does this when shape and pointers repeat),
-and the near field runs on a second stream beside the upward and downward
-passes.  HIP events around every near-field launch in the timed region (on
-that stream) give the kernel's duration for the roofline; a further pass with
-events between all phases, each phase alone on one stream, gives the phase
-breakdown, and a last pass without any events gives the untimed rate.
+Workload (default ``envelope4096``, the largest single-GPU configuration): a
+4096 x 4096 grid (h = 1/4096) of sources f = 2(u_x v_y - u_y v_x) from 64
+seeded Lamb-Oseen vortices, times a two-band Gaussian envelope (width 0.02)
+around two deforming fish midlines; nodes where the envelope is below 1e-16
+are zero and culled, leaving 6.16M sources.  Targets: 16,384 points on the two
+fish surfaces plus 16,384 lifted 2h along the normals.  p = 12, theta = 0.5,
+mixed precision (FP32 + Kahan near field and local evaluation, FP64
+expansions).
+
+One step = one complete cold solve (ingest, target sort, tree, interaction
+lists, P2M, M2M, M2L, L2L, L2P, P2P, finalize) with the inputs already resident
+in device memory.  Also measured: the resident solve (the tree, lists and
+target sort of the first solve kept, a new source with the same nonzero nodes
+and new targets in the same cells: weights, expansions, near field and
+finalize only), the per-phase breakdown with each phase's roofline fraction,
+the 512^2 vortex workload (all grid nodes plus an ellipse as targets), and the
+serving stream of uneven requests against the one-at-a-time path.
 
 Prints one JSON line: solves/s, effective interactions/s against the GPU
 all-pairs direct sum, accuracy against the FP64 CPU oracle on sampled targets,
-the roofline of the dominant kernel (the near field) and the CPU oracle timed
-on a bounded sample on the host cores.
+the roofline of the dominant kernel (HIP events around its launch in the timed
+solves) and of every phase, and the CPU oracle timed on a bounded sample on the
+host cores.
 """
 
 from __future__ import annotations
@@ -26,6 +31,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -33,11 +39,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs, 64 FP32 lanes per CU per clock without packed instructions, 2.4 GHz
+# MI355X published peaks: HBM3E 8 TB/s; FP64 vector 78.6 TFLOP/s; FP32 lanes without packed instructions
+# 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-ops/s (the near field's bound: one VALU issue per lane-op)
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Algorithmic FP32 lane operations of one near-field pair: dx, dy, dx^2, +dy^2 (fma), log2, and
-# the weighted accumulation w*log2 (fma).  Compensation and loop overhead are not counted, so they
-# lower the fraction.
+# the weighted accumulation w*log2 (fma).  Compensation and loop overhead are not counted.
 OPS_PER_PAIR = 6
 
 
@@ -45,25 +53,95 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_1610_04398_amd", "csrc", "p2p.hip"), "rb") as fh:
+def kernel_source_hash(name: str) -> str:
+    with open(os.path.join(ROOT, "paper_1610_04398_amd", "csrc", name), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_from_profile(workload: str, parts: int, precision: str, method: str):
-    """HBM bytes per near-field launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source with the same number of list parts per target
-    leaf (each part writes its own partial sums), precision and method; else None."""
-    path = os.path.join(ROOT, "profiles", f"p2p_{workload}_traffic.json")
+def traffic_from_profile(workload: str, phase: str, **match):
+    """HBM bytes per launch of a phase's kernel from the committed rocprofv3 counter summary
+    (profiles/<phase>_<workload>_traffic.json), if it was taken on the current kernel source and
+    the same settings; else None."""
+    path = os.path.join(ROOT, "profiles", f"{phase}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash() or rec.get("p2p_parts") != parts:
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash(rec.get("kernel_source", "p2p.hip")):
         return None
-    if rec.get("precision") != precision or rec.get("method") != method:
-        return None
+    for k, v in match.items():
+        if rec.get(k) != v:
+            return None
     return rec.get("bytes_per_launch")
+
+
+def phase_work(st: dict, w: dict, parts: int) -> dict:
+    """Algorithmic work of each phase of one solve: (bound, amount, unit).  Bytes are what the phase
+    must move at least (its inputs read once, its outputs written once); flops count an FMA as 2 and
+    a complex multiply-add as 8; the near field counts 6 FP32 lane-ops per pair."""
+    N, M = int(st["nsources"]), int(st["ntargets"])
+    C, Ls = int(st["ncells"]), int(st["nsrc_leaves"])
+    X, Y, Q = int(st["n_m2l"]), int(st["n_p2p_lists"]), int(st["n_p2p_pairs"])
+    G = w["grid"].nx * w["grid"].ny
+    p = int(w["p"])
+    D = max(1, math.ceil(math.log2(max(w["grid"].nx, w["grid"].ny))))
+    passes = math.ceil(2 * D / 8)
+    cp = 16 * (p + 1)  # bytes of one expansion
+    return {
+        # read f once, write key, node index and weight of every kept source
+        "ingest": ("hbm", 8 * G + 16 * N, "B"),
+        # target keys from the coordinates, then (key, index) read and written per radix pass
+        "sort": ("hbm", 24 * M + passes * 16 * M, "B"),
+        # sorted keys read once, cell arrays and list records written once
+        "tree": ("hbm", 4 * (N + M) + 72 * C, "B"),
+        # list entries written once, cell records read once
+        "lists": ("hbm", 4 * (X + Y) + 32 * C, "B"),
+        # source records (index, weight in; x, y, w FP32 out), target offsets and self data
+        "pack": ("hbm", 24 * N + 64 * M, "B"),
+        "p2m": ("fp64", (8 * p + 5) * N, "flop"),
+        "m2m": ("fp64", 8 * (p + 1) ** 2 * max(C - 1, 0), "flop"),
+        "m2l": ("fp64", 8 * (p + 1) ** 2 * X, "flop"),
+        "l2l": ("fp64", 4 * (p + 1) * (p + 2) * C, "flop"),
+        "l2p": ("alu", 8 * (p + 1) * M, "op"),
+        "p2p": ("alu", OPS_PER_PAIR * Q, "op"),
+        "finalize": ("hbm", (8 * parts + 44) * M + cp * min(C, M), "B"),
+    }
+
+
+def roofline_of(work, ms):
+    bound, amount, unit = work
+    t = ms * 1e-3
+    if bound == "hbm":
+        ideal = amount / (HBM_PEAK_GBS * 1e9)
+        achieved, peak, u = amount / t / 1e9 if t > 0 else None, HBM_PEAK_GBS, "GB/s"
+    elif bound == "fp64":
+        ideal = amount / (FP64_PEAK_TFLOPS * 1e12)
+        achieved, peak, u = amount / t / 1e12 if t > 0 else None, FP64_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        ideal = amount / (VALU_PEAK_TOPS * 1e12)
+        achieved, peak, u = amount / t / 1e12 if t > 0 else None, VALU_PEAK_TOPS, "T lane-op/s"
+    return {"bound": bound, "work": amount, "work_unit": unit, "ms": ms, "achieved": achieved, "peak": peak,
+            "unit": u, "frac": (achieved / peak) if achieved else None, "ideal_ms": ideal * 1e3}
+
+
+def host_cpu_info() -> dict:
+    """CPU model, sockets and logical CPUs of the host (from /proc/cpuinfo), and the CPUs this process may use."""
+    model, sockets, logical = None, set(), 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name" and model is None:
+                    model = v.strip()
+                elif k == "physical id":
+                    sockets.add(v.strip())
+    except OSError:
+        pass
+    return {"model": model, "sockets": len(sockets) or None, "logical_cpus": logical or None,
+            "usable_cpus": len(os.sched_getaffinity(0))}
 
 
 def _percentile(v, q):
@@ -146,19 +224,62 @@ def serving_run(pp, G, args, log):
             "p99_speedup": seq["p99_ms"] / srv["p99_ms"] if srv["p99_ms"] > 0 else None}
 
 
+def accuracy(P, w, n_samples, seed, oracle_direct):
+    """rel-L2 and largest error (relative to max |P|) on seeded sampled grid and surface targets."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    M = P.size
+    ng = int(w["n_grid_targets"])
+    ns = M - ng
+    k_grid = min(n_samples * 3 // 4, ng) if ns > 0 else min(n_samples, ng)
+    k_surf = min(n_samples - k_grid, ns)
+    sel_g = rng.choice(ng, k_grid, replace=False) if k_grid else np.zeros(0, int)
+    sel_s = ng + rng.choice(ns, k_surf, replace=False) if k_surf else np.zeros(0, int)
+    acc = {}
+    for name, sel in (("grid", sel_g), ("surface", sel_s)):
+        if sel.size == 0:
+            continue
+        ref = oracle_direct.direct_grid(w["f"], w["grid"].h, w["tx"][sel], w["ty"][sel])
+        acc[name] = {"rel_l2": float(np.linalg.norm(P[sel] - ref) / np.linalg.norm(ref)),
+                     "rel_max": float(np.max(np.abs(P[sel] - ref)) / np.max(np.abs(ref))),
+                     "targets": int(sel.size)}
+    return acc
+
+
+def timed_solves(s, f, g, tx, ty, out, kw, steps, phase):
+    """steps solves with HIP events around `phase`'s launches (on its stream); (solves/s, mean ms of
+    the phase).  The solves run in the schedule of an untimed call."""
+    import torch
+    s.set_profiling(phase=phase)
+    ph_sum = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.solve_grid(f, g.h, tx, ty, out=out, **kw)
+        ph_sum += s.stats()["ms_phase"][phase]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.set_profiling(0)
+    return steps / el, el / steps * 1e3, ph_sum / steps
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="vortex512")
+    ap.add_argument("--workload", default="envelope4096")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--method", default="fmm", choices=["fmm", "treecode"],
                     help="fmm: M2L/L2L/L2P with the dual-tree acceptance; treecode: the paper's own variant (M2P)")
-    ap.add_argument("--direct-steps", type=int, default=3)
+    ap.add_argument("--roofline-phase", default=None,
+                    help="phase whose launches are bracketed by HIP events in the timed solves (default: the "
+                         "phase with the largest time in the per-phase breakdown)")
+    ap.add_argument("--direct-steps", type=int, default=2)
     ap.add_argument("--samples", type=int, default=2000, help="targets checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--also", default="vortex512", help="second workload timed beside the main one ('' skips)")
     ap.add_argument("--serve-requests", type=int, default=256, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-reps", type=int, default=3, help="replays of the arrival trace per path (median p99)")
@@ -210,49 +331,35 @@ def main() -> int:
     kw = dict(p=w["p"], theta=w["theta"], leaf_max=64, precision=args.precision, method=args.method)
 
     s = pp.Solver(0)
-    # timed region: launches replayed from captured graphs, HIP events around every near-field
-    # launch (on the stream it runs on) for the roofline
-    s.set_profiling(2)
     log(f"[bench] warmup {args.warmup}")
     for _ in range(args.warmup):
         s.solve_grid(f, g.h, tx, ty, out=out, **kw)
     torch.cuda.synchronize()
-    p2p_sum = 0.0
-    log(f"[bench] timing {args.steps} solves")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.solve_grid(f, g.h, tx, ty, out=out, **kw)
-        p2p_sum += s.stats()["ms_phase"]["p2p"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
-    p2p_ms_timed = p2p_sum / args.steps
-    st = s.stats()
-    N = int(st["nsources"])
-    M = int(st["ntargets"])
-    pairs = int(st["n_p2p_pairs"])
-    P = out.cpu().numpy()
-    # list parts of the near field in this run: its partial sums are [parts][targets]
-    p2p_parts = int(s.debug_array("NEAR").size // max(M, 1))
 
-    # phase breakdown: the same solve with events between all phases (launched eagerly)
+    # phase breakdown: every phase alone on one stream, events between the phases (eager launches)
     s.set_profiling(1)
-    nph = max(5, args.steps // 2)
+    nph = max(5, args.steps // 4)
     log(f"[bench] phase breakdown over {nph} solves")
     s.solve_grid(f, g.h, tx, ty, out=out, **kw)
     phase_sum = None
-    tp0 = time.perf_counter()
     for _ in range(nph):
         s.solve_grid(f, g.h, tx, ty, out=out, **kw)
-        stp = s.stats()
-        ph = np.array([stp["ms_phase"][k] for k in pp._binding.PHASES])
+        ph = np.array([s.stats()["ms_phase"][k] for k in pp._binding.PHASES])
         phase_sum = ph if phase_sum is None else phase_sum + ph
     torch.cuda.synchronize()
-    ms_eager = 1e3 * (time.perf_counter() - tp0) / nph
     phases = dict(zip(pp._binding.PHASES, (phase_sum / nph).tolist()))
     s.set_profiling(0)
+    rphase = args.roofline_phase or max(phases, key=phases.get)
+
+    # timed region: the default schedule (first segment replayed from its graph unless the bracketed
+    # phase is in it, second segment issued directly, near field on the side stream), HIP events
+    # around the launches of the dominant phase
+    log(f"[bench] timing {args.steps} solves (events around {rphase})")
+    value, ms_per_step, rphase_ms = timed_solves(s, f, g, tx, ty, out, kw, args.steps, rphase)
+    st = s.stats()
+    N, M = int(st["nsources"]), int(st["ntargets"])
+    P = out.cpu().numpy()
+    p2p_parts = int(s.debug_array("NEAR").size // max(M, 1))
 
     # the same solves with no timing events at all
     for _ in range(3):
@@ -263,6 +370,34 @@ def main() -> int:
         s.solve_grid(f, g.h, tx, ty, out=out, **kw)
     torch.cuda.synchronize()
     untimed_value = args.steps / (time.perf_counter() - tu0)
+
+    # resident solves: the tree of the last solve kept; the source alternates between two fields with
+    # the same nonzero nodes (f and 1.5 f + a seeded perturbation on them), the targets between their
+    # positions and positions moved inside their finest cells
+    log(f"[bench] resident solves x{args.steps}")
+    rng = np.random.Generator(np.random.PCG64(77))
+    f_alt = torch.as_tensor(np.where(w["f"] != 0.0, 1.5 * w["f"] + 0.1 * np.abs(w["f"]).max()
+                                     * rng.standard_normal(w["f"].shape), 0.0), device=dev)
+    cx, cy = np.floor(w["tx"] / g.h), np.floor(w["ty"] / g.h)
+    mx = np.clip((cx + rng.uniform(0.1, 0.9, cx.size)) * g.h, cx * g.h, (cx + 1) * g.h)
+    my = np.clip((cy + rng.uniform(0.1, 0.9, cy.size)) * g.h, cy * g.h, (cy + 1) * g.h)
+    keep = (np.floor(mx / g.h) == cx) & (np.floor(my / g.h) == cy)
+    tx_alt = torch.as_tensor(np.where(keep, mx, w["tx"]), device=dev)
+    ty_alt = torch.as_tensor(np.where(keep, my, w["ty"]), device=dev)
+    inputs = [(f, tx, ty), (f_alt, tx_alt, ty_alt)]
+    s.solve_grid(f, g.h, tx, ty, out=out, **kw)
+    for i in range(3):
+        s.solve_grid_resident(*inputs[i % 2], out=out)
+    torch.cuda.synchronize()
+    tr0 = time.perf_counter()
+    for i in range(args.steps):
+        s.solve_grid_resident(*inputs[i % 2], out=out)
+    torch.cuda.synchronize()
+    resident_value = args.steps / (time.perf_counter() - tr0)
+    s.solve_grid_resident(f_alt, tx_alt, ty_alt, out=out)
+    P_res = out.cpu().numpy()
+    fresh = s.solve_grid(f_alt, g.h, tx_alt, ty_alt, **kw).cpu().numpy()
+    resident_same = bool(np.array_equal(P_res, fresh))
 
     direct_s = None
     if args.direct_steps > 0:
@@ -275,29 +410,48 @@ def main() -> int:
         torch.cuda.synchronize()
         direct_s = (time.perf_counter() - td0) / args.direct_steps
 
-    # accuracy on sampled targets against the FP64 oracle
     from oracle import direct as oracle_direct
-    rng = np.random.Generator(np.random.PCG64(2024))
-    ng = int(w["n_grid_targets"])
-    ns = M - ng
-    k_grid = min(args.samples * 3 // 4, ng) if ns > 0 else min(args.samples, ng)
-    k_surf = min(args.samples - k_grid, ns)
-    sel_g = rng.choice(ng, k_grid, replace=False) if k_grid else np.zeros(0, int)
-    sel_s = ng + rng.choice(ns, k_surf, replace=False) if k_surf else np.zeros(0, int)
-    log(f"[bench] oracle on {k_grid + k_surf} sampled targets")
-    acc = {}
-    for name, sel in (("grid", sel_g), ("surface", sel_s)):
-        if sel.size == 0:
-            continue
-        ref = oracle_direct.direct_grid(w["f"], g.h, w["tx"][sel], w["ty"][sel])
-        acc[name] = {"rel_l2": float(np.linalg.norm(P[sel] - ref) / np.linalg.norm(ref)),
-                     "rel_max": float(np.max(np.abs(P[sel] - ref)) / np.max(np.abs(ref))),
-                     "targets": int(sel.size)}
+    log(f"[bench] oracle on {args.samples} sampled targets")
+    acc = accuracy(P, w, args.samples, 2024, oracle_direct)
 
-    # CPU oracle baseline on a bounded sample of the same workload
+    # per-phase roofline: each phase's algorithmic work over its time alone (mode 1 above), and the
+    # whole solve's fraction sum_phases max(bytes/BW, work/peak) / measured time
+    works = phase_work(st, w, p2p_parts)
+    per_phase = {k: roofline_of(works[k], phases[k]) for k in pp._binding.PHASES}
+    ideal_ms = sum(v["ideal_ms"] for v in per_phase.values())
+    overall = {"ideal_ms": ideal_ms, "measured_ms": ms_per_step, "frac": ideal_ms / ms_per_step,
+               "note": "sum over phases of max(algorithmic bytes / 8 TB/s, algorithmic work / peak), over the "
+                       "timed solve's time"}
+
+    # the headline kernel: HIP events around its launches in the timed solves
+    rw = roofline_of(works[rphase], rphase_ms)
+    traffic = None
+    if rphase == "p2p":
+        traffic = traffic_from_profile(args.workload, "p2p", kernel_source="p2p.hip", p2p_parts=p2p_parts,
+                                       precision=args.precision, method=args.method)
+    elif rphase in ("p2m",):
+        traffic = traffic_from_profile(args.workload, rphase, kernel_source="expand.hip",
+                                       precision=args.precision, method=args.method)
+    elif rphase in ("ingest",):
+        traffic = traffic_from_profile(args.workload, rphase, kernel_source="ingest.hip")
+    # FP64 work on this path runs on the vector ALUs (no matrix cores): bound "alu" against the FP64 peak
+    roofline = {"bound": "hbm" if rw["bound"] == "hbm" else "alu",
+                "kernel": rphase, "achieved": rw["achieved"], "peak": rw["peak"],
+                "unit": {"hbm": "GB/s", "fp64": "TFLOP/s", "alu": "TFLOP/s"}[rw["bound"]],
+                "frac": rw["frac"], "traffic": traffic, "work_per_launch": rw["work"],
+                "work_unit": rw["work_unit"], "avg_launch_ms": rphase_ms, "p2p_list_parts": p2p_parts,
+                "note": {"hbm": "algorithmic bytes per solve of the phase over its HIP-event time in the timed solves; "
+                                "peak = MI355X HBM3E 8 TB/s",
+                         "fp64": "FP64 flops (FMA = 2) per solve of the phase over its HIP-event time; peak = "
+                                 "MI355X FP64 vector 78.6 TFLOP/s",
+                         "alu": "FP32 lane-ops per solve of the phase over its HIP-event time; peak = 256 CU x 64 "
+                                "lanes x 2.4 GHz without packed FP32"}[rw["bound"]]}
+
+    # CPU oracle baseline on a bounded sample of the same workload (all host threads), and one thread
     cpu = None
     if not args.no_cpu_baseline:
-        probe = 64
+        info = host_cpu_info()
+        probe = 32
         tp0 = time.perf_counter()
         oracle_direct.direct_grid(w["f"], g.h, w["tx"][:probe], w["ty"][:probe])
         t_probe = time.perf_counter() - tp0
@@ -307,17 +461,61 @@ def main() -> int:
         tc0 = time.perf_counter()
         oracle_direct.direct_grid(w["f"], g.h, w["tx"][idx], w["ty"][idx])
         t_cpu = time.perf_counter() - tc0
-        cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
-        cpu = {"value": (n_sample / M) / t_cpu, "unit": "solves/s", "cores": cores, "kind": "oracle",
+        threads = oracle_direct.get_threads()
+        oracle_direct.set_threads(1)
+        n1 = max(8, int(n_sample * 3.0 / max(t_cpu * threads, 1e-9)))
+        n1 = min(n1, 4096)
+        log(f"[bench] CPU oracle, one thread, on {n1} targets")
+        t10 = time.perf_counter()
+        oracle_direct.direct_grid(w["f"], g.h, w["tx"][idx[:n1]], w["ty"][idx[:n1]])
+        t1 = time.perf_counter() - t10
+        oracle_direct.set_threads(0)
+        cpu = {"value": (n_sample / M) / t_cpu, "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": f"FP64 direct sum over all {N} nonzero sources at {n_sample} of the {M} targets "
-                         f"(seeded), {t_cpu:.2f} s; rate scaled to whole solves"}
+                         f"(seeded), {t_cpu:.2f} s on {threads} threads; rate scaled to whole solves",
+               "single_thread": {"value": (n1 / M) / t1, "unit": "solves/s", "targets": n1, "seconds": t1},
+               "host": info}
+
+    # the second workload (vortex512: all 262,144 grid nodes and an ellipse as targets)
+    also = None
+    if args.also:
+        log(f"[bench] second workload {args.also}")
+        w2 = G.workload(args.also)
+        g2 = w2["grid"]
+        f2, tx2, ty2 = (torch.as_tensor(w2[k], device=dev) for k in ("f", "tx", "ty"))
+        out2 = torch.empty(tx2.numel(), dtype=torch.float64, device=dev)
+        kw2 = dict(p=w2["p"], theta=w2["theta"], leaf_max=64, precision=args.precision, method=args.method)
+        for _ in range(args.warmup):
+            s.solve_grid(f2, g2.h, tx2, ty2, out=out2, **kw2)
+        v2, ms2, p2p2 = timed_solves(s, f2, g2, tx2, ty2, out2, kw2, args.steps, "p2p")
+        st2 = s.stats()
+        P2 = out2.cpu().numpy()
+        acc2 = accuracy(P2, w2, args.samples, 2024, oracle_direct)
+        s.solve_grid(f2, g2.h, tx2, ty2, out=out2, **kw2)
+        for _ in range(3):
+            s.solve_grid_resident(f2, tx2, ty2, out=out2)
+        torch.cuda.synchronize()
+        tr0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.solve_grid_resident(f2, tx2, ty2, out=out2)
+        torch.cuda.synchronize()
+        res2 = args.steps / (time.perf_counter() - tr0)
+        pr2 = roofline_of(("alu", OPS_PER_PAIR * int(st2["n_p2p_pairs"]), "op"), p2p2)
+        also = {"workload": args.also, "solves_per_s": v2, "ms_per_solve": ms2, "resident_solves_per_s": res2,
+                "sources_nonzero": int(st2["nsources"]), "targets": int(st2["ntargets"]),
+                "interactions_per_s": int(st2["nsources"]) * int(st2["ntargets"]) / (ms2 * 1e-3),
+                "accuracy_vs_oracle": acc2,
+                "p2p_roofline": {"achieved": pr2["achieved"], "peak": pr2["peak"], "unit": "T lane-op/s",
+                                 "frac": pr2["frac"], "avg_launch_ms": p2p2},
+                "tree": {k: st2[k] for k in ("depth", "ncells", "nsrc_leaves", "ntgt_leaves", "n_m2l",
+                                              "n_p2p_lists", "n_p2p_pairs")}}
 
     # the steps around the solve, timed alone on the workload's grid: the source from a gridded
     # Lamb-Oseen velocity (eq. PoissonFinal), and the pressure and viscous forces on two fish bodies
     # (eq. Fpress / FpressNet / CdP; eq. Fvisc / FviscNet / CdNu, lifted points 2h out)
     around = None
     if args.forces_panels > 0:
-        reps = 50
+        reps = 20
 
         def timed(fn):
             fn()
@@ -330,15 +528,16 @@ def main() -> int:
 
         vel = G.vortex_velocity_grid(g, w["seed"] if w["seed"] is not None else 0, 64)
         ud, vd = (torch.as_tensor(a, device=dev) for a in vel)
+        del vel
         fa = torch.empty_like(ud)
         src_ms, _ = timed(lambda: s.pressure_source(ud, vd, g.h, out=fa))
         bodies = [G.fish_panels(args.forces_panels, g.h, yc=0.35), G.fish_panels(args.forces_panels, g.h, yc=0.65,
                                                                                  phase=0.25)]
-        mx, my, fnx, fny, fds = [np.concatenate([b[i] for b in bodies]) for i in range(5)]
-        seg = [0, bodies[0][0].size, mx.size]
-        tpx, tpy, dnx, dny, dds = (torch.as_tensor(a, device=dev) for a in (mx, my, fnx, fny, fds))
+        mx_, my_, fnx, fny, fds = [np.concatenate([b[i] for b in bodies]) for i in range(5)]
+        seg = [0, bodies[0][0].size, mx_.size]
+        tpx, tpy, dnx, dny, dds = (torch.as_tensor(a, device=dev) for a in (mx_, my_, fnx, fny, fds))
         lxd, lyd = tpx + 2 * g.h * dnx, tpy + 2 * g.h * dny
-        Pp = s.solve_grid(fa, g.h, tpx, tpy, **kw)
+        Pp = s.solve_grid(f, g.h, tpx, tpy, **kw)
         fp_ms, fr = timed(lambda: s.surface_forces(Pp, dnx, dny, dds, seg, u=(1.0, 0.0), rho=1.0, area=0.6))
         fv_ms, fv = timed(lambda: s.viscous_forces(ud, vd, g.h, lxd, lyd, dnx, dny, dds, seg, mu=1e-3,
                                                    uinf=(1.0, 0.0), rho=1.0, area=0.6))
@@ -348,26 +547,15 @@ def main() -> int:
                                 "algorithmic_bytes": 24 * nodes,
                                 "GB_per_s": 24 * nodes / (src_ms * 1e-3) / 1e9,
                                 "note": "read u, v and write f (8 B each per node); host wall time per call"},
-            "pressure_forces": {"ms_per_call": fp_ms, "panels": int(mx.size), "bodies": 2, "result": fr},
-            "viscous_forces": {"ms_per_call": fv_ms, "panels": int(mx.size), "mu": 1e-3, "result": fv},
+            "pressure_forces": {"ms_per_call": fp_ms, "panels": int(mx_.size), "bodies": 2, "result": fr},
+            "viscous_forces": {"ms_per_call": fv_ms, "panels": int(mx_.size), "mu": 1e-3, "result": fv},
             "note": "U = (1, 0), rho = 1, A = 0.6; host wall time per call including the copy of the results",
         }
+        del ud, vd, fa
 
     served = None
     if args.serve_requests > 0:
         served = serving_run(pp, G, args, log)
-
-    p2p_ms = p2p_ms_timed
-    achieved = OPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None
-    roofline = {"bound": "alu", "kernel": "k_p2p32 (near field)", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": (achieved / VALU_PEAK_TOPS) if achieved else None,
-                "traffic": traffic_from_profile(args.workload, p2p_parts, args.precision, args.method),
-                "ops_per_pair": OPS_PER_PAIR,
-                "pairs_per_launch": pairs, "avg_launch_ms": p2p_ms, "p2p_list_parts": p2p_parts,
-                "note": "6 algorithmic FP32 VALU lane-ops per near-field pair (sub, sub, mul, fma, log2, fma); "
-                        "peak = 256 CU x 64 lanes x 2.4 GHz without packed FP32"}
-    if args.precision == "fp64":
-        roofline["kernel"] = "k_p2p64 (near field)"
 
     rec = {
         "metric": "pressure solves/s & interactions/s vs direct at rel-L2 1e-4; served p50/p99 ms",
@@ -384,22 +572,27 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [g.nx, g.ny], "sources_nonzero": N, "targets": M,
                    "p": w["p"], "theta": w["theta"], "leaf_max": 64, "precision": args.precision,
-                   "method": args.method,
-                   "seed": w["seed"], "parallelism": "single GPU"},
+                   "method": args.method, "seed": w["seed"], "parallelism": "single GPU",
+                   "step": "one cold solve (tree rebuilt), inputs resident in HBM"},
         "interactions_per_s": N * M / (ms_per_step * 1e-3),
         "direct": None if direct_s is None else {
             "ms_per_solve": direct_s * 1e3, "interactions_per_s": N * M / direct_s,
             "speedup_tree_vs_direct": direct_s / (ms_per_step * 1e-3)},
         "accuracy_vs_oracle": acc,
-        "phases_ms": phases,
-        "phases_note": f"per-phase HIP-event times from {nph} further solves launched without graph replay, "
-                       f"every phase on one stream ({ms_eager:.3f} ms per solve); the timed solves replay the "
-                       "first segment from a graph and run the near field on a second stream beside the expansions",
         "untimed_solves_per_s": untimed_value,
-        "untimed_note": "the same solves without the near-field timing events: the first segment one replayed "
-                        "graph, the second issued directly in the same order as the timed solves",
+        "untimed_note": "the same cold solves without any timing events",
+        "resident": {"solves_per_s": resident_value, "ms_per_solve": 1e3 / resident_value,
+                     "bitwise_equal_to_cold_solve": resident_same,
+                     "note": "pp_solve_grid_resident: tree, lists and target sort kept; each call a new source "
+                             "with the same nonzero nodes and targets moved inside their finest cells"},
+        "phases_ms": phases,
+        "phases_note": f"per-phase HIP-event times from {nph} solves with every phase alone on one stream "
+                       "(eager launches); the timed solves overlap the near field with the expansions",
+        "phase_roofline": per_phase,
+        "overall_roofline": overall,
         "tree": {k: st[k] for k in ("depth", "ncells", "nsrc_leaves", "ntgt_leaves", "n_m2l", "n_p2p_lists",
                                      "n_p2p_pairs")},
+        "also": also,
         "served": served,
         "around_the_solve": around,
         "roofline": roofline,

@@ -152,6 +152,26 @@ pp_status pp_solve_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y
                         int64_t m, const double* tx, const double* ty, const pp_params* params, double* p_out,
                         void* hip_stream);
 
+/* Resident solve: the pressure is recomputed every time step on the same
+ * grid (Sec. 2.2: the source f changes with the flow, the grid does not), so
+ * the quadtree, its interaction lists and the target sort of the last
+ * successful pp_solve_grid on this context are kept and reused.  f (nx*ny,
+ * the grid of that call) brings new values; tx, ty (m points, the count of
+ * that call) may move as long as each target stays in the finest cell (side
+ * h) it was sorted into.  Only the weights, the expansions, the near field
+ * and the finalize step run: no ingest, sort, tree build or list build.  f
+ * may be zero where it was nonzero (the node keeps its place with weight 0),
+ * but must be zero wherever it was zero: both this and the targets' cells are
+ * checked on the device, and a mismatch returns PP_ERR_ARG with p_out
+ * untouched (the retained tree stays usable).  Parameters, precision and
+ * method are those of the retained call.  PP_ERR_ARG also when the last call
+ * on the context was not a successful pp_solve_grid (pp_solve_points,
+ * pp_direct_*, a failure, and a context without a solve keep no tree).  The
+ * result is bitwise that of pp_solve_grid on the same inputs whenever f has
+ * the same nonzero nodes. */
+pp_status pp_solve_grid_resident(pp_ctx* ctx, const double* f, const double* tx, const double* ty, double* p_out,
+                                 void* hip_stream);
+
 /* All-pairs direct sum of eq. greenSum on the GPU (no expansions): the
  * baseline the tree-code is measured against.  Uses params->precision,
  * params->self_mode and params->leaf_max (tiling); p and theta are ignored. */
@@ -231,9 +251,12 @@ pp_status pp_get_stats(const pp_ctx* ctx, pp_stats* out);
 
 /* GPU timing of later calls: 0 off; 1 HIP events between all phases
  * (ms_phase[]; every phase then runs on the call's stream, one after the
- * other, and launches are not replayed from graphs); 2 HIP events around the
- * near-field launch only (ms_phase[PP_PHASE_P2P]; the first segment of the
- * solve is still replayed, the launches of the second are issued one by one).
+ * other, and launches are not replayed from graphs); 16 + phase (PP_PHASE_*)
+ * HIP events around that phase's launches only, on the stream they run on,
+ * in the schedule of an untimed call (ms_phase[phase]; the launches of the
+ * second segment are issued one by one, and the first segment is replayed
+ * from its graph unless the timed phase is in it: ingest, sort or tree);
+ * 2 is 16 + PP_PHASE_P2P, the near-field launch.
  * Events add no synchronisation beyond the
  * call's own.  Outside mode 1 the near field runs on a second stream owned by
  * the context, concurrently with the expansions on the call's stream, which

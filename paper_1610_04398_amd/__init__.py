@@ -34,6 +34,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_server_wait,
     pp_footprint_estimate,
     pp_solve_grid,
+    pp_solve_grid_resident,
     pp_pressure_source,
     pp_solve_points,
     pp_surface_forces,
@@ -118,7 +119,9 @@ class Solver:
                 stream = torch.cuda.current_stream(tx.device).cuda_stream
         st = fn(self._ctx, nx, ny, float(x0), float(y0), float(h), fp, m, xp, yp, params, op, stream)
         if st != B.PP_OK:
+            self._resident_shape = None
             raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        self._resident_shape = (ny, nx, m) if fn is pp_solve_grid else None
         del fk, xk, yk, ok
         return out
 
@@ -127,6 +130,38 @@ class Solver:
         """Tree-code pressure at the targets (caller order); see pp_solve_grid in include/pp.h."""
         prm = make_params(p, theta, leaf_max, precision, self_mode, method)
         return self._run(pp_solve_grid, f, h, tx, ty, x0, y0, prm, out, stream)
+
+    def solve_grid_resident(self, f, tx, ty, out=None, stream=None):
+        """Pressure with the tree of the last solve_grid kept (new f with no new nonzero node, targets in
+        the same finest cells); see pp_solve_grid_resident in include/pp.h."""
+        torch_mode = _is_torch(tx)
+        fp, fk = _ptr(f, "f")
+        xp, xk = _ptr(tx, "tx")
+        yp, yk = _ptr(ty, "ty")
+        m = int(np.prod(tuple(xk.shape)))
+        if int(np.prod(tuple(yk.shape))) != m:
+            raise ValueError("tx and ty differ in length")
+        if out is None:
+            if torch_mode:
+                import torch
+                out = torch.empty(m, dtype=torch.float64, device=tx.device)
+            else:
+                out = np.empty(m, dtype=np.float64)
+        op, ok = _ptr(out, "out")
+        shape = getattr(self, "_resident_shape", None)
+        if shape is not None and (tuple(fk.shape) != shape[:2] or m != shape[2] or
+                                  int(np.prod(tuple(ok.shape))) != m):
+            raise ValueError(f"f must have shape {shape[:2]} and there must be {shape[2]} targets and outputs")
+        if stream is None:
+            stream = 0
+            if torch_mode and tx.is_cuda:
+                import torch
+                stream = torch.cuda.current_stream(tx.device).cuda_stream
+        st = pp_solve_grid_resident(self._ctx, fp, xp, yp, op, stream)
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del fk, xk, yk, ok
+        return out
 
     def direct_grid(self, f, h, tx, ty, x0=0.0, y0=0.0, leaf_max=64, precision="mixed", self_mode="skip",
                     out=None, stream=None):
@@ -159,6 +194,7 @@ class Solver:
             if torch_mode and tx.is_cuda:
                 import torch
                 stream = torch.cuda.current_stream(tx.device).cuda_stream
+        self._resident_shape = None
         st = fn(self._ctx, n, sxp, syp, wp, m, xp, yp, params, op, stream)
         if st != B.PP_OK:
             raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
@@ -280,9 +316,11 @@ class Solver:
         res = [dict(fx=f.fx, fy=f.fy, drag=f.drag, cd=f.cd) for f in out[:nseg]]
         return (res, dfx, dfy) if pointwise else res
 
-    def set_profiling(self, on=True) -> None:
-        """True/1: events between all phases; 2: events around the near-field launch only; False/0: off."""
-        st = pp_set_profiling(self._ctx, int(on))
+    def set_profiling(self, on=True, phase=None) -> None:
+        """True/1: events between all phases; 2: events around the near-field launch only; False/0: off;
+        phase="p2m" (a name of PHASES): events around that phase's launches only."""
+        mode = int(on) if phase is None else 16 + B.PHASES.index(phase)
+        st = pp_set_profiling(self._ctx, mode)
         if st != B.PP_OK:
             raise PPError(st, pp_last_error(self._ctx))
 

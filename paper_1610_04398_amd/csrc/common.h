@@ -26,6 +26,7 @@ enum : int {
   kFlagCellOverflow = 16,
   kFlagListOverflow = 32,
   kFlagBadIndex = 64,  // a list entry outside the tree (an internal error); the entry is skipped
+  kFlagStale = 128,    // resident solve: the retained tree does not fit the new sources or targets
 };
 
 struct cplx {

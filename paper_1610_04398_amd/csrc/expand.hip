@@ -56,14 +56,32 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
   return {(ix & 1) ? 0.25 : -0.25, (iy & 1) ? 0.25 : -0.25};
 }
 
-// P2M: 16 lanes per source leaf (four leaves per wave); lanes stride over the
-// leaf's sources and a fixed-order butterfly over the 16 lanes sums the
-// per-lane powers.  The source offsets from the leaf corner (units of the
-// finest cell) are formed here from the ordered sources, as the packing step
-// forms them for the near field, so P2M does not wait for that step: grid
-// nodes from their packed index (exact half-integers), scattered sources from
-// their FP64 coordinates.
+// P2M: 16 lanes per source leaf (four leaves per wave, one DPP row each);
+// lanes stride over the leaf's sources and the per-lane powers are summed
+// across the row by four rotate-and-add steps (row_ror 8, 4, 2, 1: plain VALU
+// moves, no LDS round trips), after which every lane of the row holds the
+// same sums.  The source offsets from the leaf corner (units of the finest
+// cell) are formed here from the ordered sources, as the packing step forms
+// them for the near field, so P2M does not wait for that step: grid nodes
+// from their packed index (exact half-integers), scattered sources from their
+// FP64 coordinates.
 constexpr int kP2MLanes = 16;
+
+// v plus the value of the lane N places further along its row of 16 lanes
+template <int N>
+__device__ inline double row_ror_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x120 + N, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
+}
+
+__device__ inline double row_sum16(double v) {
+  v = row_ror_add<8>(v);
+  v = row_ror_add<4>(v);
+  v = row_ror_add<2>(v);
+  return row_ror_add<1>(v);
+}
+
 template <int PM>
 __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
                                              const uint32_t* __restrict__ ij, const double* __restrict__ xs,
@@ -72,8 +90,9 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int li = (int)(gtid / kP2MLanes);
   const int sub = (int)(gtid % kP2MLanes);
-  if (li >= n) return;
-  const int c = sleaves[li];
+  // every lane of a row takes part in the row sums: lanes past the last leaf
+  // work on a copy of it and store nothing
+  const int c = sleaves[li < n ? li : n - 1];
   const double side = cell_side(t.D, t.lvl[c]);
   const double inv = 1.0 / side;
   const int sh = t.D - t.lvl[c];
@@ -104,12 +123,10 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
   }
 #pragma unroll
   for (int k = 0; k <= PM; ++k) {
-#pragma unroll
-    for (int o = kP2MLanes / 2; o > 0; o >>= 1) {
-      acc[k].x += __shfl_xor(acc[k].x, o, kP2MLanes);
-      acc[k].y += __shfl_xor(acc[k].y, o, kP2MLanes);
-    }
+    acc[k].x = row_sum16(acc[k].x);
+    acc[k].y = row_sum16(acc[k].y);
   }
+  if (li >= n) return;
   double2* out = mp + (int64_t)c * (p + 1);
 #pragma unroll
   for (int k = 0; k <= PM; ++k)

@@ -5,6 +5,8 @@
 // cells in increasing order and keeping nodes with f != 0 yields the sources
 // already in key order.  Each workgroup owns a tile of 1024 consecutive Morton
 // indices (a 32 x 32 block of the grid), so its reads of f stay within 32 rows.
+#include <algorithm>
+
 #include "blockscan.h"
 #include "internal.h"
 
@@ -49,11 +51,16 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __rest
 // tile_sum: tile_off holds the per-tile counts instead of their exclusive
 // scan; each workgroup then adds up the counts before its own tile (few
 // tiles: at most kIngFusedTiles), and the last one stores the total.
+// starts (may be null): for every Morton prefix of 2 * sh bits (the cells of
+// the tree's dense table), the position of its first source, i.e. the number
+// of sources with a smaller key: written by the item whose index begins the
+// prefix, before it emits.
 __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restrict__ f, int nx, int ny, int k,
                                                             double h2, const int* __restrict__ tile_off,
                                                             int tile_sum, int* __restrict__ total_out,
                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ ij,
-                                                            double* __restrict__ w64) {
+                                                            double* __restrict__ w64, int* __restrict__ starts,
+                                                            int sh) {
   __shared__ int lds[kIngBlock / kWave + 1];
   int before = 0;
   if (tile_sum) {
@@ -78,7 +85,92 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
   int total;
   int pos = block_excl_scan<kIngBlock>(c, lds, &total) + before;
   if (tile_sum && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = before + total;
+  const uint64_t pmask = ((uint64_t)1 << (2 * sh)) - 1;
   for (int q = 0; q < kIngItems; ++q) {
+    if (starts && base + q < mend && ((base + q) & pmask) == 0) starts[(base + q) >> (2 * sh)] = pos;
+    if (!ok[q]) continue;
+    const uint64_t m = base + q;
+    const uint32_t i = compact_bits((uint32_t)m);
+    const uint32_t j = compact_bits((uint32_t)(m >> 1));
+    key[pos] = (uint32_t)m;
+    ij[pos] = i | (j << 16);
+    w64[pos] = v[q] * h2;
+    ++pos;
+  }
+}
+
+// Single pass (count, prefix, emit) over the tiles with a decoupled look-back:
+// a workgroup takes the next tile number from a ticket counter (so every
+// smaller tile belongs to a workgroup that is already running), counts its
+// tile's nonzero nodes, publishes that count, then walks back over the
+// earlier tiles' published words, adding counts until it meets a published
+// prefix (count of everything before that tile plus its own), publishes its
+// own prefix and emits.  Status word of a tile: 0 not yet, 1 << 62 | count
+// (its own count), 2 << 62 | prefix (the inclusive prefix); the array and the
+// ticket start at zero.  A wait that does not end within kSpinLimit polls
+// raises kFlagBadIndex and the tile goes on with what it has (the solve is
+// then reported as failed), so the kernel always finishes.
+constexpr unsigned long long kStAgg = 1ull << 62, kStPre = 2ull << 62, kStVal = (1ull << 62) - 1;
+constexpr int kSpinLimit = 1 << 24;
+
+__global__ __launch_bounds__(kIngBlock) void k_ingest_fused(const double* __restrict__ f, int nx, int ny, int k,
+                                                             double h2, unsigned long long* __restrict__ status,
+                                                             int* __restrict__ ticket, int* __restrict__ total_out,
+                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ ij,
+                                                             double* __restrict__ w64, int* __restrict__ starts,
+                                                             int sh, int* __restrict__ flags) {
+  __shared__ int lds[kIngBlock / kWave + 1];
+  __shared__ int tile_s, before_s;
+  if (threadIdx.x == 0) tile_s = atomicAdd(ticket, 1);
+  __syncthreads();
+  const int tile = tile_s;
+  const uint64_t mend = (uint64_t)1 << (2 * k);
+  const uint64_t base = (uint64_t)tile * kIngTile + (uint64_t)threadIdx.x * kIngItems;
+  double v[kIngItems];
+  bool ok[kIngItems];
+  int c = 0, bad = 0;
+#pragma unroll
+  for (int q = 0; q < kIngItems; ++q) {
+    ok[q] = node_value(f, nx, ny, base + q, mend, &v[q], &bad);
+    c += ok[q] ? 1 : 0;
+  }
+  if (bad) atomicOr(flags, kFlagNonFiniteSource);
+  int total;
+  int pos = block_excl_scan<kIngBlock>(c, lds, &total);
+  if (threadIdx.x == 0) {
+    long long before = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&status[0], kStPre | (unsigned long long)total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&status[tile], kStAgg | (unsigned long long)total, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      int j = tile - 1, spins = 0;
+      for (;;) {
+        const unsigned long long st = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if ((st & ~kStVal) == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(flags, kFlagBadIndex);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        before += (long long)(st & kStVal);
+        if ((st & ~kStVal) == kStPre || j == 0) break;
+        --j;
+      }
+      __hip_atomic_store(&status[tile], kStPre | (unsigned long long)(before + total), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    before_s = (int)before;
+    if (tile == (int)gridDim.x - 1) *total_out = (int)(before + total);
+  }
+  __syncthreads();
+  pos += before_s;
+  const uint64_t pmask = ((uint64_t)1 << (2 * sh)) - 1;
+#pragma unroll
+  for (int q = 0; q < kIngItems; ++q) {
+    if (starts && base + q < mend && ((base + q) & pmask) == 0) starts[(base + q) >> (2 * sh)] = pos;
     if (!ok[q]) continue;
     const uint64_t m = base + q;
     const uint32_t i = compact_bits((uint32_t)m);
@@ -101,7 +193,84 @@ __global__ void k_target_keys(const double* __restrict__ tx, const double* __res
   key[t] = kk;
   idx[t] = (int)t;
 }
+// ---- resident solves: new weights on a retained tree, and the checks that
+// the tree still fits the input ----
+
+constexpr int kResBlock = 256;
+
+__device__ inline int block_sum_int(int v, int* lds) {
+  int total;
+  block_excl_scan<kResBlock>(v, lds, &total);
+  return total;
+}
+
+// w = f h^2 of every retained source (its packed node index), the number of
+// retained sources with f != 0, and the number of nonzero nodes of the whole
+// grid: the retained tree fits the new f exactly when the two counts agree
+// (no node outside it has become nonzero).
+__global__ __launch_bounds__(kResBlock) void k_resident_weights(const double* __restrict__ f, int nx, int64_t ngrid,
+                                                                 double h2, const uint32_t* __restrict__ ij,
+                                                                 int64_t n, double* __restrict__ w64,
+                                                                 int* __restrict__ cnt_kept,
+                                                                 int* __restrict__ cnt_all, int* __restrict__ flags) {
+  __shared__ int lds[kResBlock / kWave + 1];
+  const int64_t stride = (int64_t)gridDim.x * kResBlock;
+  int kept = 0, all = 0, bad = 0;
+  for (int64_t q = (int64_t)blockIdx.x * kResBlock + threadIdx.x; q < n; q += stride) {
+    const uint32_t c = ij[q];
+    const double v = f[(int64_t)(c >> 16) * nx + (c & 0xFFFFu)];
+    w64[q] = v * h2;
+    kept += v != 0.0;
+  }
+  for (int64_t q = (int64_t)blockIdx.x * kResBlock + threadIdx.x; q < ngrid; q += stride) {
+    const double v = f[q];
+    bad |= !isfinite(v);
+    all += v != 0.0;
+  }
+  if (bad) atomicOr(flags, kFlagNonFiniteSource);
+  kept = block_sum_int(kept, lds);
+  __syncthreads();
+  all = block_sum_int(all, lds);
+  if (threadIdx.x == 0) {
+    if (kept) atomicAdd(cnt_kept, kept);
+    if (all) atomicAdd(cnt_all, all);
+  }
+}
+
+// Every target must still lie in the finest cell it was sorted into.
+__global__ void k_resident_targets(const double* __restrict__ tx, const double* __restrict__ ty, int64_t m,
+                                   const int* __restrict__ perm, const uint32_t* __restrict__ key, double x0,
+                                   double y0, double h, int k, int* __restrict__ flags) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= m) return;
+  const int t = perm[q];
+  int err = 0;
+  const uint32_t kk = target_key(tx[t], ty[t], x0, y0, h, k, &err);
+  if (err) atomicOr(flags, err == 1 ? kFlagNonFiniteTarget : kFlagTargetOutside);
+  else if (kk != key[q]) atomicOr(flags, kFlagStale);
+}
+
+__global__ void k_resident_verdict(const int* __restrict__ cnt_kept, const int* __restrict__ cnt_all,
+                                   int* __restrict__ flags) {
+  if (threadIdx.x == 0 && *cnt_kept != *cnt_all) atomicOr(flags, kFlagStale);
+}
 }  // namespace
+
+void resident_weights(const double* f, int nx, int ny, double h2, const uint32_t* ij, int64_t n, double* w64,
+                      int* cnt_kept, int* cnt_all, int* flags, hipStream_t s) {
+  const int64_t ngrid = (int64_t)nx * ny;
+  const int64_t work = std::max<int64_t>(ngrid, 1);
+  const unsigned blocks = (unsigned)std::min<int64_t>((work + kResBlock - 1) / kResBlock, 4096);
+  k_resident_weights<<<blocks, kResBlock, 0, s>>>(f, nx, ngrid, h2, ij, n, w64, cnt_kept, cnt_all, flags);
+  k_resident_verdict<<<1, kWave, 0, s>>>(cnt_kept, cnt_all, flags);
+}
+
+void resident_targets(const double* tx, const double* ty, int64_t m, const int* perm, const uint32_t* key, double x0,
+                      double y0, double h, int k, int* flags, hipStream_t s) {
+  if (m <= 0) return;
+  const int b = 256;
+  k_resident_targets<<<(unsigned)((m + b - 1) / b), b, 0, s>>>(tx, ty, m, perm, key, x0, y0, h, k, flags);
+}
 
 int64_t ingest_num_tiles(int k) {
   const int64_t cells = (int64_t)1 << (2 * k);
@@ -113,9 +282,16 @@ void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, in
 }
 
 void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, int tile_sum,
-                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, hipStream_t s) {
+                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s) {
   k_ingest_emit<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_off, tile_sum, total_out,
-                                                                     key, ij, w64);
+                                                                     key, ij, w64, starts, sh);
+}
+
+void ingest_grid_fused(const double* f, int nx, int ny, int k, double h2, unsigned long long* status, int* ticket,
+                       int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, int* flags,
+                       hipStream_t s) {
+  k_ingest_fused<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, status, ticket, total_out,
+                                                                      key, ij, w64, starts, sh, flags);
 }
 
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k, uint32_t* key,

@@ -35,12 +35,28 @@ void ctx_trim(pp_ctx* c);
 // ---- ingest.hip: sources in Morton order, target keys ------------------------------
 // Morton tiles of 1024 indices cover [0, 4^k).
 int64_t ingest_num_tiles(int k);
+// Resident solves (a retained tree, new f): w = f h^2 for the n retained
+// sources (packed node indices ij); the counts of retained nonzero sources and
+// of nonzero grid nodes go to *cnt_kept and *cnt_all (zeroed by the caller),
+// and kFlagStale is raised when they differ.
+void resident_weights(const double* f, int nx, int ny, double h2, const uint32_t* ij, int64_t n, double* w64,
+                      int* cnt_kept, int* cnt_all, int* flags, hipStream_t s);
+// kFlagStale unless every target (caller index perm[q]) still has the sorted key key[q].
+void resident_targets(const double* tx, const double* ty, int64_t m, const int* perm, const uint32_t* key, double x0,
+                      double y0, double h, int k, int* flags, hipStream_t s);
 void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s);
 // tile_sum != 0: tile_off holds the per-tile counts (not their scan) and
 // *total_out receives the source count; only for at most kIngFusedTiles tiles.
 constexpr int64_t kIngFusedTiles = 1024;
+// The same in one pass (a decoupled look-back over the tiles, in the order of a
+// ticket counter): status (ingest_num_tiles(k) words) and *ticket must be zero.
+void ingest_grid_fused(const double* f, int nx, int ny, int k, double h2, unsigned long long* status, int* ticket,
+                       int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, int* flags,
+                       hipStream_t s);
+// starts (may be null): the source range start of every Morton prefix of
+// 2 * sh bits (cells of the dense table sh levels above the finest).
 void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, int tile_sum,
-                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, hipStream_t s);
+                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s);
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
                  uint32_t* key, int* idx, int* flags, hipStream_t s);
 
@@ -86,15 +102,18 @@ struct TreeArrays {
 };
 // Levels 0..Ld of the tree in one pass over a dense table of Morton prefixes
 // (4^Ld + 1 range starts per key array, tree_dense_cells(Ld) flags); writes
-// ls[0..Ld+1] on the device, and level Ld's cells are left as leaves for
-// tree_level to continue from.  Gives the same cells and numbering as
-// building the levels one at a time from the root.
+// ls[0..D+1] on the device (the levels below Ld empty), and level Ld's cells
+// are left as leaves for tree_level to continue from, which is needed only
+// when *deep becomes nonzero (a cell of level Ld holds more than leaf_max
+// sources or targets).  Gives the same cells and numbering as building the
+// levels one at a time from the root.  src_done: ss[0..4^Ld) was written by
+// the grid ingest.
 int64_t tree_dense_cells(int Ld);
 // ints of scan_tmp that tree_dense_top needs (per-workgroup counts of the flags)
 int64_t tree_dense_part_ints(int Ld);
 void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
-                    const int* nsrc_dev, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag, int* off,
-                    int* scan_tmp, int* total_slot, int* flags, hipStream_t s);
+                    const int* nsrc_dev, int src_done, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag,
+                    int* off, int* scan_tmp, int* total_slot, int* deep, int* flags, hipStream_t s);
 // One level of the top-down construction, with no host round trip: the level's
 // cells are [ls[level], ls[level+1]) read on the device; its children are
 // appended and ls[level+2] is written.  max_cells bounds the level's size (grid

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -47,7 +48,7 @@ enum BufId {
   B_FLAG, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
-  B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
+  B_S64, B_SELFW, B_TSTAT, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
   B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY,
   B_COUNT
 };
@@ -68,14 +69,32 @@ struct Last {
   int nparts = 1;
 };
 
+// The tree of the last successful grid solve, kept for resident solves
+// (new f on the same grid, targets in the same finest cells): everything the
+// second segment is sized from.  Its device arrays are the context's buffers.
+struct Resident {
+  bool valid = false;
+  int32_t nx = 0, ny = 0;
+  double x0 = 0.0, y0 = 0.0, h = 0.0;
+  int64_t m = 0;
+  pp_params prm{};
+  bool exact_lists = false;
+  int cap_far = 0, cap_near = 0, frontier_boost = 0;
+  int64_t N = 0, n_m2l = 0, n_p2pl = 0;
+  std::vector<int> lstart;
+  int nsl = 0, ntl = 0, ntc = 0;
+};
+
 constexpr int kMiscInts = 128;
 constexpr int kMailExtra = 32;
 constexpr int kSeqSlot = kMiscInts;
 // misc layout: [0] flags, [1] source count, [2] scratch total, [3] level work items,
-// [4..9] cell-list and interaction-list totals, [16..17] near-field pair count (u64),
+// [4..8] cell-list and interaction-list totals, [10..11] resident-solve counts, [12] levels below the dense
+// table needed, [13] ticket counter of the single-pass ingest, [16..17] near-field pair count (u64),
 // [32..32+D+2] level starts of the tree, [96..103] bounding box of scattered input (4 doubles).
 constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7,
-              M_NP2P = 8, M_NITEMS = 9, M_PAIRS = 16, M_LS = 32, M_BOX = 96;
+              M_NP2P = 8, M_RKEPT = 10, M_RALL = 11, M_DEEP = 12, M_TICKET = 13, M_PAIRS = 16, M_LS = 32,
+              M_BOX = 96;
 
 }  // namespace
 
@@ -91,7 +110,8 @@ struct pp_ctx {
   // instead of replaying it from a graph (PP_DIRECT_ISSUE=0 replays it)
   int direct_issue = 1;
   int dense_levels = 9;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
-  int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only
+  bool ingest_fused = true;  // grid ingest in one pass with a look-back (PP_INGEST_FUSED=0: count, scan, emit)
+  int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only, 16 + phase that phase's launches
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
   // from the lists to the end) is captured into a HIP graph on the second call with
@@ -133,6 +153,7 @@ struct pp_ctx {
   std::string err;
   bool dead = false;
   Last last;
+  Resident res;
   pp_stats stats{};
 };
 
@@ -347,6 +368,9 @@ void check_flags(int flags) {
   if (flags & kFlagFrontierOverflow) throw PPError{PP_ERR_LIMIT, "traversal frontier exceeded its capacity"};
   if (flags & kFlagCellOverflow) throw PPError{PP_ERR_LIMIT, "cell capacity exceeded"};
   if (flags & kFlagBadIndex) throw PPError{PP_ERR_LIMIT, "internal index check failed"};
+  if (flags & kFlagStale)
+    throw PPError{PP_ERR_ARG, "the retained tree does not fit: f is nonzero at a node that was zero when the tree "
+                              "was built, or a target left its finest cell"};
   if (flags) throw PPError{PP_ERR_DEVICE, "unknown kernel flag"};
 }
 
@@ -406,7 +430,7 @@ void validate_points(int64_t n, const double* sx, const double* sy, const double
 // and a list that does not fit makes the solve report kFlagListOverflow (the
 // caller then repeats it with exact lists).
 pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src, int64_t m, const double* tx,
-                    const double* ty, const pp_params& prm, double* p_out, hipStream_t s) {
+                    const double* ty, const pp_params& prm, double* p_out, hipStream_t s, bool resident = false) {
   const auto t_start = std::chrono::steady_clock::now();
   HIPCHK(hipSetDevice(c.device));
   if (s == nullptr) {
@@ -415,6 +439,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   }
   c.cur_stream = s;
   c.last.valid = false;
+  // a resident solve reuses the retained tree (its sizes and list layout);
+  // any other solve rebuilds the buffers the tree lives in
+  const Resident R = c.res;
+  if (resident) exact_lists = R.exact_lists;
+  else c.res.valid = false;
   const int32_t nx = src.grid ? src.nx : 0, ny = src.grid ? src.ny : 0;
   const int64_t ngrid = src.grid ? (int64_t)nx * ny : 0;
   const int64_t nmax = src.grid ? ngrid : src.n;  // sources before culling zeros
@@ -428,6 +457,15 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // near-field launch only, which then runs outside the replayed segments
   auto mark = [&](int i) {
     if (c.profiling == 1) HIPCHK(hipEventRecord(c.ev[i], s));
+  };
+  // profiling 2 / 16 + phase: events around one phase's launches, on the
+  // stream they run on, in the schedule of an untimed call
+  const int timed_phase = c.profiling == 2 ? PP_PHASE_P2P : c.profiling >= 16 ? c.profiling - 16 : -1;
+  auto tbegin = [&](int ph, hipStream_t q) {
+    if (ph == timed_phase) HIPCHK(hipEventRecord(c.ev[0], q));
+  };
+  auto tend = [&](int ph, hipStream_t q) {
+    if (ph == timed_phase) HIPCHK(hipEventRecord(c.ev[1], q));
   };
   // Every buffer of the first segment (staging copies of host inputs included)
   // depends on the input sizes only: sized, and checked against the budget,
@@ -449,8 +487,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const int64_t cap = std::min<int64_t>(geo, 1 + (int64_t)std::max(D, 1) * per_level) + 1;
   if (cap >= ((int64_t)1 << 31) / 4) throw PPError{PP_ERR_LIMIT, "tree capacity exceeds the index range"};
   const bool treecode = prm.method == PP_METHOD_TREECODE;
-  const int cap_far = treecode ? c.cap_m2p : c.cap_m2l;
-  const int cap_near = treecode ? c.cap_tp2p : c.cap_p2p;
+  const int cap_far = resident ? R.cap_far : treecode ? c.cap_m2p : c.cap_m2l;
+  const int cap_near = resident ? R.cap_near : treecode ? c.cap_tp2p : c.cap_p2p;
   // levels 0..Ld from the dense prefix table, the rest one level at a time
   const int Ld = std::min(D, c.dense_levels);
   const int64_t dense_np = ((int64_t)1 << (2 * Ld)) + 1;
@@ -466,6 +504,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   int* boxc = nullptr;
   uint32_t *skey = nullptr, *sij = nullptr, *skey2 = nullptr, *tkey = nullptr, *tkey2 = nullptr;
   double *sw = nullptr, *pxs = nullptr, *pys = nullptr;
+  unsigned long long* tstat = nullptr;
   int *tile = nullptr, *sort_tmp = nullptr, *sperm2 = nullptr, *tperm = nullptr, *tperm2 = nullptr;
   TreeArrays ta{};
   int4* rec = nullptr;
@@ -494,6 +533,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
     sw = ensure<double>(c, B_SW, nmax);
     tile = src.grid ? ensure<int>(c, B_TILE, ntiles) : nullptr;
+    tstat = src.grid && c.ingest_fused ? ensure<unsigned long long>(c, B_TSTAT, ntiles) : nullptr;
     sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.grid ? 0 : src.n, m)));
     skey2 = src.grid ? nullptr : ensure<uint32_t>(c, B_SKEY2, src.n);
     sperm2 = src.grid ? nullptr : ensure<int>(c, B_SPERM2, src.n);
@@ -574,24 +614,60 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
   // (graph replay only for device-resident grid input: host input is staged by copies)
-  const bool replayable = src.grid && !exact_lists && !direct && f_d == src.f && tx_d == tx && ty_d == ty &&
-                          out_on_device && c.profiling != 1;
+  const bool replayable = src.grid && !exact_lists && !direct && !resident && f_d == src.f && tx_d == tx &&
+                          ty_d == ty && out_on_device && c.profiling != 1 &&
+                          !(timed_phase >= PP_PHASE_INGEST && timed_phase <= PP_PHASE_TREE);
   const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
                                       (uint64_t)lm, (uint64_t)c.dense_levels, (uint64_t)c.profiling, bits(f_d),
                                       bits(tx_d), bits(ty_d), (uint64_t)direct, (uint64_t)cap_far,
                                       (uint64_t)cap_near};
+  // the levels below the dense table, one launch group per level (on the device sizes)
+  auto build_levels_below = [&] {
+    for (int l = Ld; l < D; ++l) {
+      const int64_t lmax = std::min<int64_t>(wmax, (int64_t)1 << std::min(2 * l, 40));
+      tree_level(ta, ls_d, l, D, lm, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4, misc + M_TOT,
+                 misc + M_FLAGS, s);
+    }
+  };
+  // cell lists over the whole tree (its size is the last level start, on the device)
+  auto classify = [&] {
+    const TreeView tv0{D, 0, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
+    const RecordArgs rec0{tv0, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near};
+    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, sleaves, tleaves, tcells, misc + M_NSL,
+                   direct ? nullptr : &rec0, s);
+  };
   const int seq1 = published_seq(c) + 1;
-  run_segment(c, 0, replayable, key1, s, [&] {
+  if (resident) {
+    // the retained tree: new weights for its sources, and the checks that it
+    // still fits (no new nonzero node, every target in its finest cell)
+    mark(PP_PHASE_INGEST);
+    fill_i32(misc, 0, kMiscInts, s);
+    tbegin(PP_PHASE_INGEST, s);
+    resident_weights(f_d, nx, ny, unit * unit, sij, R.N, sw, misc + M_RKEPT, misc + M_RALL, misc + M_FLAGS, s);
+    tend(PP_PHASE_INGEST, s);
+    mark(PP_PHASE_SORT);
+    tbegin(PP_PHASE_SORT, s);
+    resident_targets(tx_d, ty_d, m, tperm, tkey, x0, y0, unit, k, misc + M_FLAGS, s);
+    tend(PP_PHASE_SORT, s);
+    mark(PP_PHASE_TREE);
+  } else run_segment(c, 0, replayable, key1, s, [&] {
     mark(PP_PHASE_INGEST);
     if (src.grid) fill_i32(misc, 0, kMiscInts, s);  // scattered input: cleared before its bounding box
+    tbegin(PP_PHASE_INGEST, s);
     if (src.grid) {
       // ---- ingest: sources in Morton order (no sort needed for a grid) ----
-      ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
-      if (ntiles <= kIngFusedTiles) {  // the emitting workgroups add up the tile counts themselves
-        ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 1, misc + M_NSRC, skey, sij, sw, s);
-      } else {
-        scan_exclusive(tile, tile, ntiles, scan, misc + M_NSRC, s);
-        ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 0, nullptr, skey, sij, sw, s);
+      if (tstat) {  // one pass over f
+        fill_i32((int*)tstat, 0, 2 * ntiles, s);
+        ingest_grid_fused(f_d, nx, ny, k, unit * unit, tstat, misc + M_TICKET, misc + M_NSRC, skey, sij, sw, dss,
+                          D - Ld, misc + M_FLAGS, s);
+      } else {  // count per tile, then emit
+        ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
+        if (ntiles <= kIngFusedTiles) {  // the emitting workgroups add up the tile counts themselves
+          ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 1, misc + M_NSRC, skey, sij, sw, dss, D - Ld, s);
+        } else {
+          scan_exclusive(tile, tile, ntiles, scan, misc + M_NSRC, s);
+          ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 0, nullptr, skey, sij, sw, dss, D - Ld, s);
+        }
       }
     } else if (src.n > 0) {
       // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
@@ -600,37 +676,54 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       radix_sort_pairs(skey, sperm, skey2, sperm2, src.n, 32, sort_tmp, s);
       points_gather(sperm, misc + M_NSRC, src.n, psx, psy, pw, pxs, pys, sw, s);
     }
+    tend(PP_PHASE_INGEST, s);
     // ---- targets: Morton keys and a stable radix sort ----
     mark(PP_PHASE_SORT);
+    tbegin(PP_PHASE_SORT, s);
     target_keys_sorted(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, tkey2, tperm2, sort_tmp, misc + M_FLAGS, s);
-    // ---- tree: dense top levels, then one launch group per level, no host round trip ----
+    tend(PP_PHASE_SORT, s);
+    // ---- tree: dense top levels, then (scattered sources) one launch group per level ----
     mark(PP_PHASE_TREE);
-    tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, tkey, (int)m, dss, dts, dflag, doff, scan,
-                   misc + M_TOT, misc + M_FLAGS, s);
-    for (int l = Ld; l < D; ++l) {
-      const int64_t lmax = std::min<int64_t>(wmax, (int64_t)1 << std::min(2 * l, 40));
-      tree_level(ta, ls_d, l, D, lm, lmax, (int)cap, skey, tkey, sp, cr, ex, off, scan, misc + M_N4, misc + M_TOT,
-                 misc + M_FLAGS, s);
-    }
-    // cell lists over the whole tree (its size is the last level start, on the device)
-    const TreeView tv0{D, 0, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
-    const RecordArgs rec0{tv0, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near};
-    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, sleaves, tleaves, tcells, misc + M_NSL,
-                   direct ? nullptr : &rec0, s);
+    tbegin(PP_PHASE_TREE, s);
+    tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, src.grid ? 1 : 0, tkey, (int)m, dss, dts,
+                   dflag, doff, scan, misc + M_TOT, misc + M_DEEP, misc + M_FLAGS, s);
+    // Grid sources: a cell of the dense table's last level holds at most
+    // 4^(D - Ld) nodes, so it is split only by its targets, which is rare:
+    // the levels below are built after the read-back, only if one is.
+    if (!src.grid) build_levels_below();
+    classify();
+    tend(PP_PHASE_TREE, s);
     publish_enqueue(c, misc, M_LS + D + 2, s);
   });
-  wait_published(c, s, seq1);
-  check_flags(c.pinned[M_FLAGS]);
-  const int64_t N = c.pinned[M_NSRC];
-  const int* ls_h = c.pinned + M_LS;
-  std::vector<int> lstart = {ls_h[0], ls_h[1]};  // level l holds cells [lstart[l], lstart[l+1])
-  for (int l = 1; l <= D; ++l) {
-    if (ls_h[l + 1] == ls_h[l]) break;
-    lstart.push_back(ls_h[l + 1]);
+  if (!resident) {
+    wait_published(c, s, seq1);
+    check_flags(c.pinned[M_FLAGS]);
+    if (src.grid && c.pinned[M_DEEP]) {
+      // a cell of the dense table's last level has more than leaf_max targets
+      const int seq_deep = published_seq(c) + 1;
+      build_levels_below();
+      classify();
+      publish_enqueue(c, misc, M_LS + D + 2, s);
+      wait_published(c, s, seq_deep);
+      check_flags(c.pinned[M_FLAGS]);
+    }
+  }
+  const int64_t N = resident ? R.N : c.pinned[M_NSRC];
+  std::vector<int> lstart;  // level l holds cells [lstart[l], lstart[l+1])
+  if (resident) {
+    lstart = R.lstart;
+  } else {
+    const int* ls_h = c.pinned + M_LS;
+    lstart = {ls_h[0], ls_h[1]};
+    for (int l = 1; l <= D; ++l) {
+      if (ls_h[l + 1] == ls_h[l]) break;
+      lstart.push_back(ls_h[l + 1]);
+    }
   }
   const int ncells = lstart.back();
   const int depth = (int)lstart.size() - 2;
-  const int nsl = c.pinned[M_NSL], ntl = c.pinned[M_NTL], ntc = c.pinned[M_NTC];
+  const int nsl = resident ? R.nsl : c.pinned[M_NSL], ntl = resident ? R.ntl : c.pinned[M_NTL],
+            ntc = resident ? R.ntc : c.pinned[M_NTC];
   const TreeView tv{D, ncells, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
 
   // ---- every buffer of the second segment, sized (and checked against the
@@ -669,6 +762,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
     pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
   });
+  if (resident && exact_lists) {  // the retained two-pass lists
+    m2l_src = (int*)c.bufs[B_M2LSRC].p;
+    p2p_src = (int*)c.bufs[B_P2PSRC].p;
+    n_m2l = R.n_m2l;
+    n_p2pl = R.n_p2pl;
+  }
   P2PArgs pa{};
   pa.t = tv;
   pa.tleaves = tleaves;
@@ -751,11 +850,15 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     HIPCHK(hipStreamWaitEvent(to, e, 0));
   };
   // the two-pass lists read a total back to the host, so they run first, on s
-  const bool lists_early = exact_lists && !direct;
+  const bool lists_early = exact_lists && !direct && !resident;
 
   // lp (one-pass lists only): the per-leaf packing rides on the list launch
   auto do_lists = [&](hipStream_t q, const LeafPass* lp) {
     if (direct) return;
+    if (resident) {  // retained
+      pa.list_src = p2p_src;
+      return;
+    }
     if (exact_lists) {
       list_pass(0, nullptr, nullptr, nullptr, nullptr, 0, 0, nullptr, q);  // records, cleared counts: segment 1
       scan_exclusive(cm2l, om2l, ncells, scan, misc + M_NM2L, q);
@@ -790,8 +893,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // The second segment issued directly: timed calls, and by default untimed
   // ones too (the replayed graph runs the side branch's kernels first, which
   // made the multipole solve 2-4 % and the tree-code 15 % slower).
-  const bool issue2 = c.profiling == 2 || (c.profiling == 0 && c.direct_issue && ss != s);
-  const bool fused = !direct && !exact_lists && issue2;
+  const bool issue2 = timed_phase >= 0 || (c.profiling == 0 && (c.direct_issue || resident) && ss != s);
+  const bool fused = !direct && !exact_lists && issue2 && !resident;
   const LeafPass lpass =
       src.grid ? leaf_pass_grid(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d,
                                 ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf,
@@ -800,17 +903,21 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                                   leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw);
   auto do_p2m = [&] {
     mark(PP_PHASE_P2M);
+    tbegin(PP_PHASE_P2M, s);
     if (!direct) p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, s);
+    tend(PP_PHASE_P2M, s);
   };
   auto do_m2m = [&] {
     mark(PP_PHASE_M2M);
     if (direct) return;
+    tbegin(PP_PHASE_M2M, s);
     // the recursion from the finest level up, several levels per launch
     const int ml = m2m_max_levels();
     for (int top = depth - 1; top >= 0; top -= ml) {
       const int L = std::max(top - (ml - 1), 0);
       m2m_levels(tv, lstart[L], lstart[L + 1], L, top - L + 1, p, mp, dflag, doff, Ld, s);
     }
+    tend(PP_PHASE_M2M, s);
   };
   auto do_upward = [&] {
     do_p2m();
@@ -825,16 +932,21 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       return;
     }
     mark(PP_PHASE_M2L);
+    tbegin(PP_PHASE_M2L, s);
     if (treecode) {
       // multipoles evaluated at the targets; no local expansions
       m2p(tv, tleaves, ntl, om2l, cm2l, m2l_src, p, unit, mp, rel64, mixed ? 1 : 0, far_parts, m, far,
           misc + M_FLAGS, s);
+      tend(PP_PHASE_M2L, s);
       mark(PP_PHASE_L2L);
       mark(PP_PHASE_L2P);
     } else {
       m2l(tv, tcells, ntc, om2l, cm2l, m2l_src, p, unit, mp, own, misc + M_FLAGS, s);
+      tend(PP_PHASE_M2L, s);
       mark(PP_PHASE_L2L);
+      tbegin(PP_PHASE_L2L, s);
       downward(tv, tcells, ntc, p, own, loc, doff, Ld, s);
+      tend(PP_PHASE_L2L, s);
       mark(PP_PHASE_L2P);
       if (!fuse_l2p) l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
     }
@@ -862,7 +974,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       fe.p = p;
       fe.fp32 = mixed ? 1 : 0;
     }
+    tbegin(PP_PHASE_FINALIZE, s);
     finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, fe, s);
+    tend(PP_PHASE_FINALIZE, s);
     mark(12);
     publish_enqueue(c, misc, M_PAIRS + 2, s);
   };
@@ -874,14 +988,21 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // field, which fills it.
   auto fork_work = [&] {
     if (fused) {
+      // one launch: the lists, with the packing in extra workgroups
+      tbegin(PP_PHASE_LISTS, ss);
       do_lists(ss, &lpass);
+      tend(PP_PHASE_LISTS, ss);
       do_p2m();
       do_m2m();
       return;
     }
+    tbegin(PP_PHASE_PACK, ss);
     do_pack_prep(ss);
+    tend(PP_PHASE_PACK, ss);
     do_p2m();
+    tbegin(PP_PHASE_LISTS, ss);
     if (!lists_early) do_lists(ss, nullptr);
+    tend(PP_PHASE_LISTS, ss);
     do_m2m();
   };
 
@@ -904,11 +1025,14 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       do_lists(s, nullptr);
       signal(c.ev_fork, s, ss);
     }
+    // a resident solve wrote its new weights on s without a host round trip:
+    // the packing on the side stream reads them
+    if (resident) signal(c.ev_fork, s, ss);
     fork_work();
     if (ss != s) HIPCHK(hipEventRecord(c.ev_lists, ss));
-    if (c.profiling == 2) HIPCHK(hipEventRecord(c.ev[PP_PHASE_P2P], ss));
+    tbegin(PP_PHASE_P2P, ss);
     do_near(ss);
-    if (c.profiling == 2) HIPCHK(hipEventRecord(c.ev[PP_PHASE_FINALIZE], ss));
+    tend(PP_PHASE_P2P, ss);
     if (ss != s) HIPCHK(hipStreamWaitEvent(s, c.ev_lists, 0));
     do_downward();
     signal(c.ev_join, ss, s);
@@ -960,11 +1084,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       HIPCHK(hipEventElapsedTime(&ms, c.ev[i], c.ev[i + 1]));
       c.stats.ms_phase[i] = ms;
     }
-  } else if (c.profiling == 2) {
+  } else if (timed_phase >= 0) {
     float ms = 0.f;
-    HIPCHK(hipEventSynchronize(c.ev[PP_PHASE_FINALIZE]));
-    HIPCHK(hipEventElapsedTime(&ms, c.ev[PP_PHASE_P2P], c.ev[PP_PHASE_FINALIZE]));
-    c.stats.ms_phase[PP_PHASE_P2P] = ms;
+    HIPCHK(hipEventSynchronize(c.ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms, c.ev[0], c.ev[1]));
+    c.stats.ms_phase[timed_phase] = ms;
   }
   if (!out_on_device && m > 0) {
     HIPCHK(hipMemcpyAsync(p_out, out_d, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -988,6 +1112,28 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.stats.n_p2p_pairs = (int64_t)npairs;
   c.stats.ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  if (src.grid && !direct && !resident) {
+    Resident& r = c.res;
+    r.valid = true;
+    r.nx = nx;
+    r.ny = ny;
+    r.x0 = x0;
+    r.y0 = y0;
+    r.h = unit;
+    r.m = m;
+    r.prm = prm;
+    r.exact_lists = exact_lists;
+    r.cap_far = cap_far;
+    r.cap_near = cap_near;
+    r.frontier_boost = c.frontier_boost;
+    r.N = N;
+    r.n_m2l = n_m2l;
+    r.n_p2pl = n_p2pl;
+    r.lstart = lstart;
+    r.nsl = nsl;
+    r.ntl = ntl;
+    r.ntc = ntc;
+  }
   c.last.valid = true;
   c.last.n_src = N;
   c.last.m = m;
@@ -1003,7 +1149,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 }
 
 pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const double* tx, const double* ty,
-                const pp_params* prm, double* p_out, void* stream) {
+                const pp_params* prm, double* p_out, void* stream, bool resident = false) {
   if (!c) return PP_ERR_ARG;
   if (c->dead) {
     c->err = "context is unusable after a device error";
@@ -1014,6 +1160,15 @@ pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const dou
       validate(src.nx, src.ny, src.x0, src.y0, src.h, src.f, m, tx, ty, prm, p_out);
     else
       validate_points(src.n, src.sx, src.sy, src.w, m, tx, ty, prm, p_out);
+    if (resident) {
+      // the retained tree is used once as it is: no list rebuild, no retry
+      const pp_status st = m == 0 ? PP_OK
+                                  : run_solve(*c, false, c->res.exact_lists, src, m, tx, ty, *prm, p_out,
+                                              (hipStream_t)stream, true);
+      if (st != PP_OK) throw PPError{st, "resident solve failed"};
+      c->err.clear();
+      return st;
+    }
     if (m == 0) return PP_OK;
     // A solve is repeated (at most a few times) when the traversal frontier
     // overflowed below its top tier, or when a one-pass list outgrew its per-cell
@@ -1091,6 +1246,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DIRECT_ISSUE")) c->direct_issue = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
+  if (const char* e = std::getenv("PP_INGEST_FUSED")) c->ingest_fused = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities
@@ -1116,7 +1272,6 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (hipMalloc((void**)&c->pub_ctr, sizeof(zeros)) != hipSuccess ||
       hipMemcpy(c->pub_ctr, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess) {
     if (c->pub_ctr) (void)hipFree(c->pub_ctr);
-  if (c->log_tab) (void)hipFree(c->log_tab);
     (void)hipHostFree(c->pinned);
     delete c;
     return PP_ERR_DEVICE;
@@ -1145,6 +1300,17 @@ void pp_destroy(pp_ctx* c) {
 pp_status pp_solve_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                         const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
   return guard(c, false, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_solve_grid_resident(pp_ctx* c, const double* f, const double* tx, const double* ty, double* p_out,
+                                 void* stream) {
+  if (!c) return PP_ERR_ARG;
+  if (!c->res.valid) {
+    c->err = "no retained tree: the last call on this context was not a successful pp_solve_grid";
+    return PP_ERR_ARG;
+  }
+  const Resident R = c->res;
+  return guard(c, false, grid_sources(R.nx, R.ny, R.x0, R.y0, R.h, f), R.m, tx, ty, &R.prm, p_out, stream, true);
 }
 
 pp_status pp_solve_points(pp_ctx* c, int64_t n, const double* sx, const double* sy, const double* w, int64_t m,
@@ -1212,6 +1378,7 @@ void pp::ctx_trim(pp_ctx* c) {
   for (int i = 0; i < B_COUNT; ++i) release(*c, i);
   c->gen += 1;
   c->last.valid = false;
+  c->res.valid = false;
 }
 
 namespace {
@@ -1335,7 +1502,7 @@ pp_status pp_surface_forces(pp_ctx* c, int64_t m, const double* p, const double*
 }
 
 pp_status pp_set_profiling(pp_ctx* c, int32_t on) {
-  if (!c || on < 0 || on > 2) return PP_ERR_ARG;
+  if (!c || on < 0 || (on > 2 && on < 16) || on >= 16 + 12) return PP_ERR_ARG;
   if (on && !c->profiling) {
     if (hipSetDevice(c->device) != hipSuccess) return PP_ERR_DEVICE;
     for (int i = 0; i < 13; ++i) {

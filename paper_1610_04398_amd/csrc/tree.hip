@@ -181,15 +181,17 @@ __device__ inline int lower_bound_from(const uint32_t* __restrict__ a, int n, ui
   return (int)lo;
 }
 
+// src_done: the source starts ss[0..np) were written by the ingest (grid
+// sources, whose ingest visits every Morton index in order); only ss[np].
 __global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __restrict__ nsrc_dev,
-                               const uint32_t* __restrict__ tkey, int ntgt, int D, int Ld, int* __restrict__ ss,
-                               int* __restrict__ ts) {
+                               const uint32_t* __restrict__ tkey, int ntgt, int D, int Ld, int src_done,
+                               int* __restrict__ ss, int* __restrict__ ts) {
   const int64_t np = (int64_t)1 << (2 * Ld);
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (P > np) return;
   const uint64_t key = (uint64_t)P << (2 * (D - Ld));
   const int ns = *nsrc_dev;
-  ss[P] = lower_bound_from(skey, ns, key, (P * (int64_t)ns) / np);
+  if (!src_done || P == np) ss[P] = P == np ? ns : lower_bound_from(skey, ns, key, (P * (int64_t)ns) / np);
   ts[P] = lower_bound_from(tkey, ntgt, key, (P * (int64_t)ntgt) / np);
 }
 
@@ -248,17 +250,20 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_offsets(const int* __rest
   if (idx < F) off[idx] = ex;
 }
 
+// The levels below Ld are left empty (ls[Ld+2..D+1] = ls[Ld+1]); *deep
+// becomes nonzero when a cell of level Ld is split after all (more than
+// leaf_max sources or targets, Ld < D), so the levels below have to be built.
 __global__ void k_dense_write(TreeArrays t, const int* __restrict__ flag, const int* __restrict__ off,
                               const int* __restrict__ total_dev, const int* __restrict__ ss,
-                              const int* __restrict__ ts, int Ld, int cap, int* __restrict__ ls,
-                              int* __restrict__ flags) {
+                              const int* __restrict__ ts, int D, int Ld, int leaf_max, int cap,
+                              int* __restrict__ ls, int* __restrict__ deep, int* __restrict__ flags) {
   const int64_t F = dense_level_offset(Ld + 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int total = *total_dev;
   if (idx == 0) {
     // level starts; clamped to the capacity so later launches stay in bounds
     for (int L = 0; L <= Ld; ++L) ls[L] = min(off[dense_level_offset(L)], cap);
-    ls[Ld + 1] = min(total, cap);
+    for (int L = Ld + 1; L <= D + 1; ++L) ls[L] = min(total, cap);
     if (total > cap) atomicOr(flags, kFlagCellOverflow);
   }
   if (idx >= F || !flag[idx]) return;
@@ -284,6 +289,7 @@ __global__ void k_dense_write(TreeArrays t, const int* __restrict__ flag, const 
   }
   t.child[id] = first;
   t.nchild[id] = n;
+  if (L == Ld && Ld < D && (t.se[id] - t.sb[id] > leaf_max || t.te[id] - t.tb[id] > leaf_max)) atomicOr(deep, 1);
 }
 
 // flag[kind * n + c] for kind 0 = leaf with sources, 1 = leaf with targets,
@@ -425,15 +431,15 @@ int64_t tree_dense_part_ints(int Ld) { return (tree_dense_cells(Ld) + kDenseBloc
 int64_t tree_dense_cells(int Ld) { return ((((int64_t)1) << (2 * (Ld + 1))) - 1) / 3; }
 
 void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
-                    const int* nsrc_dev, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag, int* off,
-                    int* scan_tmp, int* total_slot, int* flags, hipStream_t s) {
+                    const int* nsrc_dev, int src_done, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag,
+                    int* off, int* scan_tmp, int* total_slot, int* deep, int* flags, hipStream_t s) {
   const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
-  k_dense_starts<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(skey, nsrc_dev, tkey, ntgt, D, Ld, ss, ts);
+  k_dense_starts<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(skey, nsrc_dev, tkey, ntgt, D, Ld, src_done, ss, ts);
   const int64_t F = tree_dense_cells(Ld);
   const unsigned g = (unsigned)((F + kDenseBlock - 1) / kDenseBlock);
   k_dense_flags<<<g, kDenseBlock, 0, s>>>(ss, ts, D, Ld, leaf_max, flag, scan_tmp);
   k_dense_offsets<<<g, kDenseBlock, 0, s>>>(flag, scan_tmp, Ld, off, total_slot);
-  k_dense_write<<<g, 256, 0, s>>>(t, flag, off, total_slot, ss, ts, Ld, cap, ls, flags);
+  k_dense_write<<<g, 256, 0, s>>>(t, flag, off, total_slot, ss, ts, D, Ld, leaf_max, cap, ls, deep, flags);
 }
 
 int64_t classify_part_ints(int64_t cap) { return 3 * ((cap + kClsTile - 1) / kClsTile) + 3; }
