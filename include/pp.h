@@ -152,6 +152,25 @@ pp_status pp_solve_grid(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y
                         int64_t m, const double* tx, const double* ty, const pp_params* params, double* p_out,
                         void* hip_stream);
 
+/* For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid allocation): the same
+ * solve as pp_solve_grid, with every intermediate array taken from a fixed
+ * workspace of 256 MiB that the library holds on each GPU it runs on (a
+ * static device array, alive until the process ends), so the call itself
+ * allocates nothing.  f, tx, ty and p_out must be device memory (else
+ * PP_ERR_ARG; there are no staging copies).  A solve whose arrays do not fit
+ * in the workspace returns PP_ERR_NOMEM before anything is enqueued (the 512^2
+ * vortex workload with 264,192 targets needs about 80 MiB; grids up to 1024^2
+ * with a few thousand targets fit).  All calls on one GPU share the
+ * workspace, which keeps the last call's contents: calls that overlap on one
+ * GPU (from several threads or contexts) race and must be serialised by the
+ * caller.  The call runs on hip_stream alone (no second stream, no graph
+ * replay), returns after completion like pp_solve_grid, gives bitwise the
+ * same result, and keeps no tree for pp_solve_grid_resident. */
+pp_status pp_solve_grid_noalloc(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, double y0, double h,
+                                const double* f, int64_t m, const double* tx, const double* ty,
+                                const pp_params* params, double* p_out, void* hip_stream);
+
 /* Resident solve: the pressure is recomputed every time step on the same
  * grid (Sec. 2.2: the source f changes with the flow, the grid does not), so
  * the quadtree, its interaction lists and the target sort of the last

@@ -34,6 +34,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_server_wait,
     pp_footprint_estimate,
     pp_solve_grid,
+    pp_solve_grid_noalloc,
     pp_solve_grid_resident,
     pp_pressure_source,
     pp_solve_points,
@@ -130,6 +131,13 @@ class Solver:
         """Tree-code pressure at the targets (caller order); see pp_solve_grid in include/pp.h."""
         prm = make_params(p, theta, leaf_max, precision, self_mode, method)
         return self._run(pp_solve_grid, f, h, tx, ty, x0, y0, prm, out, stream)
+
+    def solve_grid_noalloc(self, f, h, tx, ty, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
+                           self_mode="skip", out=None, stream=None, method="fmm"):
+        """pp_solve_grid with every intermediate array in the library's fixed workspace (device inputs and
+        output only); see pp_solve_grid_noalloc in include/pp.h."""
+        prm = make_params(p, theta, leaf_max, precision, self_mode, method)
+        return self._run(pp_solve_grid_noalloc, f, h, tx, ty, x0, y0, prm, out, stream)
 
     def solve_grid_resident(self, f, tx, ty, out=None, stream=None):
         """Pressure with the tree of the last solve_grid kept (new f with no new nonzero node, targets in

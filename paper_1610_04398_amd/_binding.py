@@ -36,7 +36,7 @@ DOUBLE_ARRAYS = {"MULTIPOLE", "LOCAL", "FAR", "NEAR", "LEAF_WNEAR"}
 UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
-EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_solve_grid_resident", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
+EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_solve_grid_noalloc", "pp_solve_grid_resident", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
             "pp_surface_forces", "pp_pressure_source", "pp_viscous_forces", "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
             "pp_server_create", "pp_server_submit", "pp_server_wait", "pp_server_cancel", "pp_server_destroy",
             "pp_server_last_error", "pp_server_device_bytes", "pp_footprint_estimate")
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     solve_args = [vp, i32, i32, f64, f64, f64, vp, i64, vp, vp, ctypes.POINTER(pp_params), vp, vp]
     lib.pp_solve_grid.argtypes = solve_args
     lib.pp_solve_grid.restype = i32
+    lib.pp_solve_grid_noalloc.argtypes = solve_args
+    lib.pp_solve_grid_noalloc.restype = i32
     lib.pp_solve_grid_resident.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.pp_solve_grid_resident.restype = i32
     lib.pp_direct_grid.argtypes = solve_args
@@ -170,6 +172,12 @@ def pp_destroy(ctx: int) -> None:
 def pp_solve_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:
     return lib().pp_solve_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params), out_ptr,
                                stream)
+
+
+def pp_solve_grid_noalloc(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr,
+                          stream) -> int:
+    return lib().pp_solve_grid_noalloc(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, ctypes.byref(params),
+                                       out_ptr, stream)
 
 
 def pp_solve_grid_resident(ctx, f_ptr, tx_ptr, ty_ptr, out_ptr, stream) -> int:

@@ -26,6 +26,13 @@
 
 using namespace pp;
 
+// Device memory of the allocation-free solve (pp_solve_grid_noalloc): one
+// array per GPU, alive while the library is loaded.  Host code never uses its
+// name as an address: the device address comes from hipGetSymbolAddress, once
+// per device (scratch_address below).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 struct PPError {
@@ -49,7 +56,7 @@ enum BufId {
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
   B_S64, B_SELFW, B_TSTAT, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
-  B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY,
+  B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY, B_LOGT,
   B_COUNT
 };
 
@@ -57,6 +64,25 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
+
+// The address of `scratch` on each device, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+void* scratch_address(int device) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
 
 // Metadata of the last successful solve (for pp_debug_copy).
 struct Last {
@@ -67,6 +93,7 @@ struct Last {
   bool has_expansions = false;
   bool has_locals = false;
   int nparts = 1;
+  bool arena = false;  // its arrays are pieces of the workspace (pp_solve_grid_noalloc)
 };
 
 // The tree of the last successful grid solve, kept for resident solves
@@ -143,6 +170,14 @@ struct pp_ctx {
   // before it allocates or enqueues anything.
   bool planning = false;
   size_t plan_need[B_COUNT] = {};
+  // Workspace mode (pp_solve_grid_noalloc): ensure() hands out 256-byte
+  // aligned pieces of the device's scratch array instead of allocating; the
+  // pieces of one call are laid out from its start, in the order asked for.
+  bool arena = false;
+  char* arena_base = nullptr;
+  size_t arena_used = 0;
+  DevBuf abufs[B_COUNT];
+  void* scratch_ptr = nullptr;  // this device's scratch array (looked up at creation)
   // kMiscInts + kMailExtra ints of coherent pinned host memory for read-backs;
   // slot kSeqSlot receives the sequence number of the last published read-back
   int* pinned = nullptr;
@@ -175,6 +210,18 @@ T* ensure(pp_ctx& c, int id, int64_t count) {
     c.plan_need[id] = std::max(c.plan_need[id], bytes);
     return (T*)(uintptr_t)256;  // never dereferenced: nothing is enqueued while planning
   }
+  if (c.arena) {
+    DevBuf& a = c.abufs[id];
+    if (a.bytes >= bytes) return (T*)a.p;
+    const size_t start = (c.arena_used + 255) & ~(size_t)255;
+    if (start + bytes > kScratchBytes)
+      throw PPError{PP_ERR_NOMEM, "the solve needs more than the " + std::to_string(kScratchBytes >> 20) +
+                                      " MiB of the allocation-free workspace"};
+    a.p = c.arena_base + start;
+    a.bytes = bytes;
+    c.arena_used = start + bytes;
+    return (T*)a.p;
+  }
   DevBuf& b = c.bufs[id];
   if (b.bytes >= bytes) return (T*)b.p;
   const size_t others = c.held - b.bytes;
@@ -204,6 +251,27 @@ T* ensure(pp_ctx& c, int id, int64_t count) {
 // buffers of a planned block get no growth headroom, so the check is exact.
 template <class F>
 void reserve(pp_ctx& c, F&& alloc) {
+  if (c.arena) {
+    // workspace mode: the pieces this block asks for must fit after those
+    // already handed out in this call
+    std::fill(std::begin(c.plan_need), std::end(c.plan_need), (size_t)0);
+    c.planning = true;
+    try {
+      alloc();
+    } catch (...) {
+      c.planning = false;
+      throw;
+    }
+    c.planning = false;
+    size_t total = c.arena_used;
+    for (int i = 0; i < B_COUNT; ++i)
+      if (c.plan_need[i] > c.abufs[i].bytes) total = ((total + 255) & ~(size_t)255) + c.plan_need[i];
+    if (total > kScratchBytes)
+      throw PPError{PP_ERR_NOMEM, "the solve needs " + std::to_string(total) + " bytes of workspace, more than the " +
+                                      std::to_string(kScratchBytes >> 20) + " MiB of the allocation-free entry point"};
+    alloc();
+    return;
+  }
   if (!c.budget) {
     alloc();
     return;
@@ -444,6 +512,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const Resident R = c.res;
   if (resident) exact_lists = R.exact_lists;
   else c.res.valid = false;
+  if (c.arena) {  // every piece of the workspace is handed out anew
+    c.arena_used = 0;
+    for (auto& a : c.abufs) a = DevBuf{};
+  }
   const int32_t nx = src.grid ? src.nx : 0, ny = src.grid ? src.ny : 0;
   const int64_t ngrid = src.grid ? (int64_t)nx * ny : 0;
   const int64_t nmax = src.grid ? ngrid : src.n;  // sources before culling zeros
@@ -614,7 +686,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
   // (graph replay only for device-resident grid input: host input is staged by copies)
-  const bool replayable = src.grid && !exact_lists && !direct && !resident && f_d == src.f && tx_d == tx &&
+  const bool replayable = src.grid && !exact_lists && !direct && !resident && !c.arena && f_d == src.f && tx_d == tx &&
                           ty_d == ty && out_on_device && c.profiling != 1 &&
                           !(timed_phase >= PP_PHASE_INGEST && timed_phase <= PP_PHASE_TREE);
   const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
@@ -791,12 +863,18 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   pa.pairs = pairs;
   pa.near_sum = near;
   pa.lnh = std::log(unit);
-  if (!mixed && !c.log_tab) {  // filled once, outside any captured segment
-    HIPCHK(hipMalloc((void**)&c.log_tab, kLogTable * sizeof(double)));
-    log_table(c.log_tab, s);
-    HIPCHK(hipStreamSynchronize(s));  // the near field may run on the side stream without waiting on s
+  if (!mixed && c.arena) {  // a piece of the workspace, filled on every call (one stream)
+    double* lt = ensure<double>(c, B_LOGT, kLogTable);
+    log_table(lt, s);
+    pa.log_tab = lt;
+  } else {
+    if (!mixed && !c.log_tab) {  // filled once, outside any captured segment
+      HIPCHK(hipMalloc((void**)&c.log_tab, kLogTable * sizeof(double)));
+      log_table(c.log_tab, s);
+      HIPCHK(hipStreamSynchronize(s));  // the near field may run on the side stream without waiting on s
+    }
+    pa.log_tab = c.log_tab;
   }
-  pa.log_tab = c.log_tab;
   pa.list_src = direct ? nullptr : p2p_src;  // set again below once exact lists are allocated
   // statistics: pair count, and the list totals of the one-pass lists
   const bool list_totals = !direct && !exact_lists;
@@ -837,7 +915,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // 1 keeps every phase on one stream, in phase order, so that its per-phase
   // events mean something.
   hipStream_t ss = s;
-  if (c.profiling != 1 && c.near_stream) {
+  // (the allocation-free solve keeps one stream: no stream or event is created for it)
+  if (c.profiling != 1 && c.near_stream && !c.arena) {
     if (!c.side_stream) HIPCHK(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
     for (hipEvent_t* e : {&c.ev_fork, &c.ev_lists, &c.ev_join})
       if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
@@ -1112,7 +1191,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.stats.n_p2p_pairs = (int64_t)npairs;
   c.stats.ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-  if (src.grid && !direct && !resident) {
+  if (src.grid && !direct && !resident && !c.arena) {
     Resident& r = c.res;
     r.valid = true;
     r.nx = nx;
@@ -1144,6 +1223,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.last.has_expansions = !direct;
   c.last.has_locals = !direct && !treecode;
   c.last.nparts = nparts;
+  c.last.arena = c.arena;
   c.cur_stream = nullptr;
   return PP_OK;
 }
@@ -1268,10 +1348,19 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
     return PP_ERR_DEVICE;
   }
   std::memset(c->pinned, 0, (kMiscInts + kMailExtra) * sizeof(int));
+  // set-up of the allocation-free entry point: this device's workspace address,
+  // and the stream that calls on the null stream use (created here, not there)
+  c->scratch_ptr = scratch_address(device);
+  if (!c->scratch_ptr || hipStreamCreate(&c->own_stream) != hipSuccess) {
+    (void)hipHostFree(c->pinned);
+    delete c;
+    return PP_ERR_DEVICE;
+  }
   const int zeros[64] = {};
   if (hipMalloc((void**)&c->pub_ctr, sizeof(zeros)) != hipSuccess ||
       hipMemcpy(c->pub_ctr, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess) {
     if (c->pub_ctr) (void)hipFree(c->pub_ctr);
+    (void)hipStreamDestroy(c->own_stream);
     (void)hipHostFree(c->pinned);
     delete c;
     return PP_ERR_DEVICE;
@@ -1300,6 +1389,22 @@ void pp_destroy(pp_ctx* c) {
 pp_status pp_solve_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                         const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
   return guard(c, false, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_solve_grid_noalloc(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h,
+                                const double* f, int64_t m, const double* tx, const double* ty,
+                                const pp_params* params, double* p_out, void* stream) {
+  if (!c) return PP_ERR_ARG;
+  if ((f && !is_device_ptr(f)) || (m > 0 && ((tx && !is_device_ptr(tx)) || (ty && !is_device_ptr(ty)) ||
+                                              (p_out && !is_device_ptr(p_out))))) {
+    c->err = "the allocation-free solve takes device memory only (no staging copies)";
+    return PP_ERR_ARG;
+  }
+  c->arena = true;
+  c->arena_base = (char*)c->scratch_ptr;
+  const pp_status st = guard(c, false, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
+  c->arena = false;
+  return st;
 }
 
 pp_status pp_solve_grid_resident(pp_ctx* c, const double* f, const double* tx, const double* ty, double* p_out,
@@ -1566,7 +1671,7 @@ pp_status pp_debug_copy(const pp_ctx* cc, int32_t what, void* dst, int64_t capac
   const int64_t cnt = std::min(n, std::max<int64_t>(capacity, 0));
   if (cnt <= 0) return PP_OK;
   if (hipSetDevice(c->device) != hipSuccess ||
-      hipMemcpy(dst, c->bufs[id].p, (size_t)cnt * esz, hipMemcpyDeviceToHost) != hipSuccess) {
+      hipMemcpy(dst, (L.arena ? c->abufs : c->bufs)[id].p, (size_t)cnt * esz, hipMemcpyDeviceToHost) != hipSuccess) {
     c->err = "copy failed";
     return PP_ERR_DEVICE;
   }
