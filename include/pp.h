@@ -128,7 +128,7 @@ enum {
   PP_PHASE_LISTS = 3,    /* cell lists, interaction lists, near-field work items */
   PP_PHASE_PACK = 4,     /* per-leaf source records and target offsets */
   PP_PHASE_P2M = 5,
-  PP_PHASE_M2M = 6,      /* bottom-up recursion, four levels per launch */
+  PP_PHASE_M2M = 6,      /* bottom-up recursion, three levels per launch */
   PP_PHASE_M2L = 7,      /* tree-code: M2P */
   PP_PHASE_L2L = 8,      /* final locals: own M2L plus exact shifts of every ancestor's */
   PP_PHASE_L2P = 9,

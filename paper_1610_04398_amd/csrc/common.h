@@ -37,23 +37,67 @@ __host__ __device__ inline cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + 
 __host__ __device__ inline cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __host__ __device__ inline cplx cscale(cplx a, double s) { return {a.x * s, a.y * s}; }
 
-// L2P at one target: Re sum_l L'_l u^l by Horner with u = (t - z_c) / s_c, from
-// the target's offset r to its leaf's corner (units of h) and the leaf at level
-// lvl of a root with 2^D cells per side.  FP32 arithmetic for the mixed path
-// (coefficients rounded as read), FP64 otherwise.
+// Error-free transformations in FP32: a + b = s + e exactly (Knuth's TwoSum),
+// and a b = p + e exactly (with a fused multiply-add).  Contraction is off in
+// both (and wherever their results are combined): a product fused into a
+// later sum would no longer be the value whose error was captured.
+__device__ inline float two_sum(float a, float b, float& e) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+__device__ inline float two_prod(float a, float b, float& e) {
+#pragma clang fp contract(off)
+  const float q = a * b;
+  e = fmaf(a, b, -q);
+  return q;
+}
+
+// L2P at one target: Re sum_l L'_l u^l with u = (t - z_c) / s_c, from the
+// target's offset r to its leaf's corner (units of h) and the leaf at level
+// lvl of a root with 2^D cells per side.
+// FP64: Horner.  FP32 (mixed path): compensated Horner (Graillat, Langlois and
+// Louvet's scheme, in complex arithmetic): every step's rounding errors, exact
+// through the transformations above, are collected in a second Horner
+// recurrence that runs beside the first and is added at the end; u and each
+// coefficient are carried as an FP32 pair (high part + rounding remainder),
+// whose low parts enter that error recurrence.  The result is as accurate as
+// an evaluation in twice FP32's precision.
 __device__ inline double l2p_eval(const double2* __restrict__ L, int p, double2 r, int D, int lvl, bool fp32) {
   const double side = (double)(1 << (D - lvl)), inv = ldexp(1.0, lvl - D);
   if (fp32) {
-    const float ux = (float)((r.x - 0.5 * side) * inv), uy = (float)((r.y - 0.5 * side) * inv);
-    float ax = 0.f, ay = 0.f;
+#pragma clang fp contract(off)
+    const double uxd = (r.x - 0.5 * side) * inv, uyd = (r.y - 0.5 * side) * inv;
+    const float ux = (float)uxd, uy = (float)uyd;
+    const float uxl = (float)(uxd - (double)ux), uyl = (float)(uyd - (double)uy);
+    float ax = 0.f, ay = 0.f;  // the running value
+    float ex = 0.f, ey = 0.f;  // the running error
     for (int l = p; l >= 0; --l) {
       const double2 v = L[l];
-      const float nx = ax * ux - ay * uy + (float)v.x;
-      const float ny = ax * uy + ay * ux + (float)v.y;
+      const float cx = (float)v.x, cy = (float)v.y;
+      const float cxl = (float)(v.x - (double)cx), cyl = (float)(v.y - (double)cy);
+      // a * u, exactly as rounded parts plus errors
+      float e1, e2, e3, e4, e5, e6, e7, e8;
+      const float p1 = two_prod(ax, ux, e1), p2 = two_prod(ay, uy, e2);
+      const float p3 = two_prod(ax, uy, e3), p4 = two_prod(ay, ux, e4);
+      const float pr = two_sum(p1, -p2, e5), pi = two_sum(p3, p4, e6);
+      // + the coefficient
+      const float nx = two_sum(pr, cx, e7), ny = two_sum(pi, cy, e8);
+      // this step's error: the transformations' parts, the low parts of the
+      // coefficient, and a times the low part of u
+      const float lx = ((e1 - e2) + e5 + e7) + (cxl + (ax * uxl - ay * uyl));
+      const float ly = ((e3 + e4) + e6 + e8) + (cyl + (ax * uyl + ay * uxl));
+      // the error recurrence: e = e u + this step's error
+      const float tx = ex * ux - ey * uy + lx;
+      const float ty = ex * uy + ey * ux + ly;
+      ex = tx;
+      ey = ty;
       ax = nx;
       ay = ny;
     }
-    return (double)ax;
+    return (double)ax + (double)ex;
   }
   const cplx u = {(r.x - 0.5 * side) * inv, (r.y - 0.5 * side) * inv};
   cplx acc = {0.0, 0.0};

@@ -101,24 +101,35 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
 #pragma unroll
   for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
   const int sb = t.sb[c], se = t.se[c];
-  for (int s = sb + sub; s < se; s += kP2MLanes) {
-    double ox, oy;
-    if (ij) {
-      const uint32_t v = ij[s];
-      ox = (double)((int)(v & 0xFFFFu) - cxi) + 0.5;
-      oy = (double)((int)(v >> 16) - cyi) + 0.5;
-    } else {
-      ox = (xs[s] - x0) / u - (double)cxi;
-      oy = (ys[s] - y0) / u - (double)cyi;
-    }
-    const double w = w64[s];
-    const cplx z = {ox * inv - 0.5, oy * inv - 0.5};
-    acc[0].x += w;
-    cplx zk = {w * z.x, w * z.y};
+  // four sources per lane per step, their loads issued together (a missing
+  // source gets weight 0 at the leaf corner and adds nothing)
+  constexpr int kR = 4;
+  for (int s = sb + sub; s < se; s += kR * kP2MLanes) {
+    double ox[kR], oy[kR], w[kR];
 #pragma unroll
-    for (int k = 1; k <= PM; ++k) {
-      acc[k] = cadd(acc[k], zk);
-      zk = cmul(zk, z);
+    for (int r = 0; r < kR; ++r) {
+      const int sr = s + r * kP2MLanes;
+      const bool ok = sr < se;
+      if (ij) {
+        const uint32_t v = ok ? ij[sr] : (uint32_t)cxi | ((uint32_t)cyi << 16);
+        ox[r] = (double)((int)(v & 0xFFFFu) - cxi) + 0.5;
+        oy[r] = (double)((int)(v >> 16) - cyi) + 0.5;
+      } else {
+        ox[r] = ok ? (xs[sr] - x0) / u - (double)cxi : 0.0;
+        oy[r] = ok ? (ys[sr] - y0) / u - (double)cyi : 0.0;
+      }
+      w[r] = ok ? w64[sr] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const cplx z = {ox[r] * inv - 0.5, oy[r] * inv - 0.5};
+      acc[0].x += w[r];
+      cplx zk = {w[r] * z.x, w[r] * z.y};
+#pragma unroll
+      for (int k = 1; k <= PM; ++k) {
+        acc[k] = cadd(acc[k], zk);
+        zk = cmul(zk, z);
+      }
     }
   }
 #pragma unroll
@@ -195,10 +206,10 @@ __device__ inline cplx m2m_child(int l, const double2* __restrict__ a, const dou
   return {bx0 + bx1, by0 + by1};
 }
 
-// M2M for up to four levels per launch (eq. expandedShift applied
+// M2M for up to three levels per launch (eq. expandedShift applied
 // recursively from the finest level up).  One workgroup per cell R at level L
-// computes, bottom up, the expansions of R's descendants at levels L+3, L+2,
-// L+1 and of R itself from the final expansions one level below the subtree.
+// computes, bottom up, the expansions of R's descendants at levels L+2, L+1
+// and of R itself from the final expansions one level below the subtree.
 // The subtree's structure is read level by level with one thread per cell;
 // then every expansion the subtree needs from global memory (the level below
 // it and the leaves inside it) is staged into LDS in one parallel sweep, so
@@ -209,13 +220,13 @@ __device__ inline cplx m2m_child(int l, const double2* __restrict__ a, const dou
 // beside the upward pass on another stream; 1024-thread workgroups waited far
 // longer for a whole free half of a compute unit.
 constexpr int kM2MThreads = 512;
-constexpr int kM2MLevels = 4;
-constexpr int kM2MSlots = 341;  // 1 + 4 + 16 + 64 + 256
+constexpr int kM2MLevels = 3;
+constexpr int kM2MSlots = 85;  // 1 + 4 + 16 + 64
 __host__ __device__ constexpr int m2m_first(int d) { return ((1 << (2 * d)) - 1) / 3; }
 
 // LDS: five int arrays of kM2MSlots (padded to a 16-byte boundary), the
-// expansions and the four shift tables; 149 KB at p = 20, within gfx950's
-// 160 KB per workgroup.
+// expansions and the four shift tables: 30 KB at p = 12 (four workgroups of
+// 512 threads fill a compute unit), 58 KB at p = 20.
 constexpr int kM2MIntWords = 5 * kM2MSlots + 3;
 size_t m2m_lds_bytes(int p) {
   return kM2MIntWords * sizeof(int) + ((size_t)kM2MSlots * (p + 1) + 4 * (size_t)(p + 1) * (p + 1)) * sizeof(double2);

@@ -102,16 +102,33 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
 // Single pass (count, prefix, emit) over the tiles with a decoupled look-back:
 // a workgroup takes the next tile number from a ticket counter (so every
 // smaller tile belongs to a workgroup that is already running), counts its
-// tile's nonzero nodes, publishes that count, then walks back over the
-// earlier tiles' published words, adding counts until it meets a published
-// prefix (count of everything before that tile plus its own), publishes its
-// own prefix and emits.  Status word of a tile: 0 not yet, 1 << 62 | count
-// (its own count), 2 << 62 | prefix (the inclusive prefix); the array and the
-// ticket start at zero.  A wait that does not end within kSpinLimit polls
-// raises kFlagBadIndex and the tile goes on with what it has (the solve is
-// then reported as failed), so the kernel always finishes.
+// tile's nonzero nodes and publishes that count.  Its first wave then reads
+// the published words of the 64 tiles before it at once: when the nearest
+// one that carries a prefix (the count of everything before that tile plus
+// its own) is found and every tile after it has published its count, the
+// counts and that prefix are added (a wave sum) and the walk ends; a window
+// with no prefix is added whole and the walk moves 64 tiles back.  The tile
+// then publishes its own prefix and emits.  Status word of a tile: 0 not yet,
+// 1 << 62 | count, 2 << 62 | prefix; the array and the ticket start at zero.
+// The words carry their own values and nothing else is read through them, so
+// relaxed device-scope atomics suffice (acquire loads would invalidate the
+// compute unit's caches on every poll).
+// A window that is not complete after kSpinLimit reads raises kFlagBadIndex
+// and the tile goes on with what it has (the solve is then reported as
+// failed), so the kernel always finishes.
 constexpr unsigned long long kStAgg = 1ull << 62, kStPre = 2ull << 62, kStVal = (1ull << 62) - 1;
-constexpr int kSpinLimit = 1 << 24;
+constexpr int kSpinLimit = 1 << 20;
+
+__device__ inline long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Tiles of kFusedItems nodes per thread (4,096 nodes): a quarter as many tiles
+// as the two-pass ingest, so the look-back walks a quarter as far.
+constexpr int kFusedItems = 16;
+constexpr int kFusedTile = kIngBlock * kFusedItems;
 
 __global__ __launch_bounds__(kIngBlock) void k_ingest_fused(const double* __restrict__ f, int nx, int ny, int k,
                                                              double h2, unsigned long long* __restrict__ status,
@@ -125,51 +142,61 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_fused(const double* __rest
   __syncthreads();
   const int tile = tile_s;
   const uint64_t mend = (uint64_t)1 << (2 * k);
-  const uint64_t base = (uint64_t)tile * kIngTile + (uint64_t)threadIdx.x * kIngItems;
-  double v[kIngItems];
-  bool ok[kIngItems];
+  const uint64_t base = (uint64_t)tile * kFusedTile + (uint64_t)threadIdx.x * kFusedItems;
+  double v[kFusedItems];
+  bool ok[kFusedItems];
   int c = 0, bad = 0;
 #pragma unroll
-  for (int q = 0; q < kIngItems; ++q) {
+  for (int q = 0; q < kFusedItems; ++q) {
     ok[q] = node_value(f, nx, ny, base + q, mend, &v[q], &bad);
     c += ok[q] ? 1 : 0;
   }
   if (bad) atomicOr(flags, kFlagNonFiniteSource);
   int total;
   int pos = block_excl_scan<kIngBlock>(c, lds, &total);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < kWave) {  // the first wave publishes and looks back
+    const int lane = threadIdx.x;
     long long before = 0;
-    if (tile == 0) {
-      __hip_atomic_store(&status[0], kStPre | (unsigned long long)total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&status[tile], kStAgg | (unsigned long long)total, __ATOMIC_RELEASE,
+    if (lane == 0)
+      __hip_atomic_store(&status[tile], (tile == 0 ? kStPre : kStAgg) | (unsigned long long)total, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
-      int j = tile - 1, spins = 0;
+    if (tile > 0) {
+      int top = tile - 1, reads = 0;
       for (;;) {
-        const unsigned long long st = __hip_atomic_load(&status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if ((st & ~kStVal) == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(flags, kFlagBadIndex);
+        const int j = top - lane;
+        const unsigned long long st =
+            j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kStPre;
+        const unsigned long long kind = st & ~kStVal;
+        const unsigned long long pre = __ballot(kind == kStPre);
+        const unsigned long long wait = __ballot(kind == 0);
+        const int first = pre ? __builtin_ctzll(pre) : kWave;  // nearest tile with a prefix
+        const unsigned long long upto = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1);
+        if (wait & upto) {  // a tile at or after the prefix has not published yet
+          if (++reads > kSpinLimit) {
+            if (lane == 0) atomicOr(flags, kFlagBadIndex);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        before += (long long)(st & kStVal);
-        if ((st & ~kStVal) == kStPre || j == 0) break;
-        --j;
+        before += wave_sum_ll(lane <= first ? (long long)(st & kStVal) : 0);
+        if (first < kWave) break;
+        top -= kWave;
       }
-      __hip_atomic_store(&status[tile], kStPre | (unsigned long long)(before + total), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0)
+        __hip_atomic_store(&status[tile], kStPre | (unsigned long long)(before + total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    before_s = (int)before;
-    if (tile == (int)gridDim.x - 1) *total_out = (int)(before + total);
+    if (lane == 0) {
+      before_s = (int)before;
+      if (tile == (int)gridDim.x - 1) *total_out = (int)(before + total);
+    }
   }
   __syncthreads();
   pos += before_s;
   const uint64_t pmask = ((uint64_t)1 << (2 * sh)) - 1;
 #pragma unroll
-  for (int q = 0; q < kIngItems; ++q) {
+  for (int q = 0; q < kFusedItems; ++q) {
     if (starts && base + q < mend && ((base + q) & pmask) == 0) starts[(base + q) >> (2 * sh)] = pos;
     if (!ok[q]) continue;
     const uint64_t m = base + q;
@@ -287,11 +314,16 @@ void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const i
                                                                      key, ij, w64, starts, sh);
 }
 
+int64_t ingest_fused_tiles(int k) {
+  const int64_t cells = (int64_t)1 << (2 * k);
+  return (cells + kFusedTile - 1) / kFusedTile;
+}
+
 void ingest_grid_fused(const double* f, int nx, int ny, int k, double h2, unsigned long long* status, int* ticket,
                        int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, int* flags,
                        hipStream_t s) {
-  k_ingest_fused<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, status, ticket, total_out,
-                                                                      key, ij, w64, starts, sh, flags);
+  k_ingest_fused<<<(unsigned)ingest_fused_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, status, ticket, total_out,
+                                                                        key, ij, w64, starts, sh, flags);
 }
 
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k, uint32_t* key,

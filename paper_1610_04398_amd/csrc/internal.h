@@ -49,7 +49,8 @@ void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, in
 // *total_out receives the source count; only for at most kIngFusedTiles tiles.
 constexpr int64_t kIngFusedTiles = 1024;
 // The same in one pass (a decoupled look-back over the tiles, in the order of a
-// ticket counter): status (ingest_num_tiles(k) words) and *ticket must be zero.
+// ticket counter): status (ingest_fused_tiles(k) words) and *ticket must be zero.
+int64_t ingest_fused_tiles(int k);
 void ingest_grid_fused(const double* f, int nx, int ny, int k, double h2, unsigned long long* status, int* ticket,
                        int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, int* flags,
                        hipStream_t s);

@@ -90,6 +90,72 @@ __device__ inline void p2p32_leaf(const Planes& q, int s0, int s1, float tx, flo
   if (s < s1) p2p32_group<1, GUARD>(q, s, tx, ty, sum, comp);
 }
 
+// Sparse target leaves (at most kSparseTargets targets, e.g. surface points
+// crossing a leaf): one lane per (target, source slot), Q source slots per
+// target (Q = 4, 8 or 16 for up to 16, 8 or 4 targets), so that Q times
+// more lanes do useful work than with one lane per target.  (Two slots for
+// up to 32 targets were measured slower than one lane per target.)  Lane (t, q) takes the
+// sources q, q + Q, q + 2Q, ... of every source leaf of its list part, sums
+// their terms four at a time in FP32 and folds each group into a Kahan-
+// compensated running sum; the Q slots' compensated totals are then added in
+// FP64 in a fixed order (a butterfly over the Q lanes).
+constexpr int kSparseTargets = 16;
+
+template <bool GUARD>
+__device__ inline void p2p32_strided(const Planes& q, int s, int s1, int stride, float tx, float ty, float& sum,
+                                     float& comp) {
+  for (; s < s1; s += 4 * stride) {
+    float y = -comp;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int sj = s + j * stride;
+      if (sj < s1) y = fmaf(q.w[sj], pair_log2(tx, ty, q.x[sj], q.y[sj], GUARD), y);
+    }
+    kahan_fold(y, sum, comp);
+  }
+}
+
+template <bool DIRECT>
+__device__ inline void p2p32_sparse(const P2PArgs& a, const Planes& q, int A, int part, int e0, int e1, const int* lst,
+                                    int wid) {
+  const TreeView& t = a.t;
+  const int lane = threadIdx.x % kWave;
+  const int tb = t.tb[A], nt = t.te[A] - tb;
+  const int Q = nt <= 4 ? 16 : nt <= 8 ? 8 : 4;
+  const int ti = lane / Q, qi = lane % Q;
+  const bool active = ti < nt;
+  const int k = tb + (active ? ti : 0);
+  const int shA = t.D - t.lvl[A];
+  const int cax = t.ix[A] << shA, cay = t.iy[A] << shA;
+  const float2 r = a.rel32[k];
+  float sum = 0.0f, comp = 0.0f;
+  double wn = 0.0;
+  int64_t nsrc = 0;
+  bool bad = false;
+  for (int e = e0; e < e1; ++e) {
+    const int B = lst[e];
+    if ((unsigned)B >= (unsigned)t.ncells) {
+      bad = true;
+      continue;
+    }
+    const int shB = t.D - t.lvl[B];
+    const float tx = r.x + (float)(cax - (t.ix[B] << shB));
+    const float ty = r.y + (float)(cay - (t.iy[B] << shB));
+    const int s0 = t.sb[B], s1 = t.se[B];
+    nsrc += s1 - s0;
+    wn += a.leaf_w[B];
+    if (B == A)
+      p2p32_strided<true>(q, s0 + qi, s1, Q, tx, ty, sum, comp);
+    else
+      p2p32_strided<false>(q, s0 + qi, s1, Q, tx, ty, sum, comp);
+  }
+  double v = (double)sum - (double)comp;
+  for (int o = 1; o < Q; o <<= 1) v += __shfl_xor(v, o, kWave);
+  if (active && qi == 0) a.near_sum[(int64_t)part * a.m + k] = 0.5 * (v * kLn2) + a.lnh * wn;
+  if (lane == 0 && a.pair_counts) a.pair_counts[wid] = (int64_t)nt * nsrc;
+  if (bad && lane == 0 && a.flags) atomicOr(a.flags, kFlagBadIndex);
+}
+
 // Work: wave w (workgroups spread over the XCDs in contiguous runs, so an
 // XCD's L2 holds the sources of a compact region) handles target leaf
 // tleaves[w / nparts] and the list part
@@ -120,6 +186,10 @@ __global__ __launch_bounds__(kP2PWaves* kWave) __attribute__((amdgpu_waves_per_e
   const int e0 = (int)((int64_t)part * nb / a.nparts);
   const int e1 = (int)((int64_t)(part + 1) * nb / a.nparts);
   const int tb = t.tb[A], te = t.te[A];
+  if (te - tb <= kSparseTargets) {  // wave-uniform
+    p2p32_sparse<DIRECT>(a, q, A, part, e0, e1, lst, wid);
+    return;
+  }
   int64_t pairs = 0;
   bool bad = false;
   for (int chunk = tb; chunk < te; chunk += kWave) {

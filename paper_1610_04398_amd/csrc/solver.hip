@@ -137,7 +137,9 @@ struct pp_ctx {
   // instead of replaying it from a graph (PP_DIRECT_ISSUE=0 replays it)
   int direct_issue = 1;
   int dense_levels = 9;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
-  bool ingest_fused = true;  // grid ingest in one pass with a look-back (PP_INGEST_FUSED=0: count, scan, emit)
+  // grid ingest in one pass with a decoupled look-back (PP_INGEST_FUSED=1) instead of count, scan and emit:
+  // correct, but measured 2.2x slower at 4096^2 (polling device-coherent words across the XCDs)
+  bool ingest_fused = false;
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only, 16 + phase that phase's launches
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
@@ -605,7 +607,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
     sw = ensure<double>(c, B_SW, nmax);
     tile = src.grid ? ensure<int>(c, B_TILE, ntiles) : nullptr;
-    tstat = src.grid && c.ingest_fused ? ensure<unsigned long long>(c, B_TSTAT, ntiles) : nullptr;
+    tstat = src.grid && c.ingest_fused ? ensure<unsigned long long>(c, B_TSTAT, ingest_fused_tiles(k)) : nullptr;
     sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.grid ? 0 : src.n, m)));
     skey2 = src.grid ? nullptr : ensure<uint32_t>(c, B_SKEY2, src.n);
     sperm2 = src.grid ? nullptr : ensure<int>(c, B_SPERM2, src.n);
@@ -729,7 +731,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     if (src.grid) {
       // ---- ingest: sources in Morton order (no sort needed for a grid) ----
       if (tstat) {  // one pass over f
-        fill_i32((int*)tstat, 0, 2 * ntiles, s);
+        fill_i32((int*)tstat, 0, 2 * ingest_fused_tiles(k), s);
         ingest_grid_fused(f_d, nx, ny, k, unit * unit, tstat, misc + M_TICKET, misc + M_NSRC, skey, sij, sw, dss,
                           D - Ld, misc + M_FLAGS, s);
       } else {  // count per tile, then emit

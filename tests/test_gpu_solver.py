@@ -121,7 +121,7 @@ def test_target_sort_multi_tile(solver):
 
 
 @pytest.mark.parametrize("n", [40, 1024])
-def test_ingest_single_pass_matches_two_pass(monkeypatch, n):
+def test_ingest_single_pass_matches_two_pass(solver, monkeypatch, n):
     """The single-pass grid ingest (tiles taken in ticket order, each adding up the counts before it with a
     look-back) gives the sources of the reference ordering bit for bit, and the same solve as the count /
     scan / emit ingest, on a one-tile grid and on a 1024^2 grid of 1,024 tiles with sparse patches."""
@@ -199,6 +199,52 @@ def test_fmm_per_pass_against_reference(solver):
             ref_l = r["L"][c] * s**kk
             scale = np.abs(ref_l).max() + 1e-300
             assert np.max(np.abs(locc[c] - ref_l)) < 1e-10 * scale, c
+
+
+def test_mixed_l2p_is_compensated(solver):
+    """The mixed path's FP32 L2P is a compensated Horner evaluation (u and the coefficients carried as FP32
+    pairs).  Both precisions build the same FP64 local expansions, so the mixed far field must equal the
+    FP64 path's to far better than FP32 rounding (< 1e-11), while a plain FP32 Horner evaluation of the
+    reference FMM's locals misses the reference far field by ~4e-8; and both far fields match the reference
+    FMM's (FP64 locals of a different summation order) to its own agreement, < 1e-8."""
+    f, h, tx, ty = _case_random(4, n=32, nt=300)
+    p = 10
+    perm = None
+    fars = {}
+    for prec in ("fp64", "mixed"):
+        solver.solve_grid(f, h, tx, ty, p=p, theta=0.5, leaf_max=16, precision=prec)
+        perm = solver.debug_array("TGT_PERM")
+        far = np.empty(tx.size)
+        far[perm] = solver.debug_array("FAR") / (2 * math.pi)
+        fars[prec] = far
+    r = fmm_ref.fmm_grid(f, tx, ty, h, p, 0.5, leaf_max=16)
+    t = r["tree"]
+    k = r["info"]["k"]
+    ref = r["far"]
+    # plain FP32 Horner of the reference locals (scaled by the cell side) at the same points
+    rperm = r["info"]["tgt_perm"]
+    naive = np.empty(tx.size)
+    for c in range(t.ncells):
+        if not t.leaf[c] or t.ntgt(c) == 0:
+            continue
+        side = h * 2.0 ** (k - t.level[c])
+        zc = complex((t.ix[c] + 0.5) * side, (t.iy[c] + 0.5) * side)
+        for q in range(int(t.tb[c]), int(t.te[c])):
+            u = (complex(tx[rperm[q]], ty[rperm[q]]) - zc) / side
+            ux, uy = np.float32(u.real), np.float32(u.imag)
+            ax, ay = np.float32(0), np.float32(0)
+            for l in range(p, -1, -1):
+                cl = r["L"][c][l] * side**l
+                ax, ay = (np.float32(ax * ux - ay * uy + np.float32(cl.real)),
+                          np.float32(ax * uy + ay * ux + np.float32(cl.imag)))
+            naive[rperm[q]] = float(ax) / (2 * math.pi)
+    e_comp = rel_l2(fars["mixed"], fars["fp64"])
+    e_naive = rel_l2(naive, ref)
+    e_ref = {prec: rel_l2(v, ref) for prec, v in fars.items()}
+    print(f"far field: compensated FP32 vs FP64 {e_comp:.3e}, plain FP32 {e_naive:.3e}, vs reference {e_ref}")
+    assert e_comp < 1e-11, e_comp
+    assert e_comp * 1000 < e_naive, (e_comp, e_naive)
+    assert max(e_ref.values()) < 1e-8, e_ref
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("mixed", 1e-4)])
@@ -291,6 +337,37 @@ def test_vortex512_kahan_near_field(solver):
     print(f"near field: compensated {e_gpu:.3e}, plain FP32 {e_naive:.3e} ({idx.size} targets)")
     assert e_gpu < 1e-6, e_gpu
     assert e_gpu * 5 < e_naive, (e_gpu, e_naive)
+
+
+def test_kahan_near_field_sparse_target_leaves(solver):
+    """The same pin for leaves that hold at most 16 targets (surface points over a grid source), where one
+    lane per (target, source slot) sums strided sources: within 1e-6 of the FP64 near sums of the reference
+    lists, and several times closer to them than a plain FP32 running sum."""
+    from near_emulation import near_lists, near_sums
+    n = 512
+    g = G.GridSpec(n, n, 1.0 / n)
+    f = G.vortex_source(g, 2)
+    ex, ey = G.ellipse_targets(2048)
+    sx, sy, lx, ly = G.fish_surface_targets(1024, g.h)
+    tx, ty = np.concatenate([ex, sx, lx]), np.concatenate([ey, sy, ly])
+    fd, txd, tyd = to_dev(f, tx, ty)
+    solver.solve_grid(fd, g.h, txd, tyd, p=12, theta=0.5, precision="mixed")
+    near = solver.debug_array("NEAR")
+    parts = near.size // tx.size
+    gpu = near.reshape(parts, tx.size).sum(axis=0)
+    info = tree_ref.grid_tree(f, tx, ty, g.h, leaf_max=64)
+    t = info["tree"]
+    lists = near_lists(t, 0.5)
+    sparse = [a for a in sorted(lists) if 0 < t.te[a] - t.tb[a] <= 16]
+    assert len(sparse) >= 60
+    rng = np.random.Generator(np.random.PCG64(6))
+    pick = [sparse[i] for i in sorted(rng.choice(len(sparse), 60, replace=False))]
+    ref, naive, idx = near_sums(f, g.h, tx, ty, info, lists, pick, nparts=parts)
+    e_gpu = rel_l2(gpu[idx], ref)
+    e_naive = rel_l2(naive, ref)
+    print(f"sparse leaves near field: compensated {e_gpu:.3e}, plain FP32 {e_naive:.3e} ({idx.size} targets)")
+    assert e_gpu < 1e-6, e_gpu
+    assert e_gpu * 3 < e_naive, (e_gpu, e_naive)
 
 
 def test_error_paths_leave_output_untouched(solver):
