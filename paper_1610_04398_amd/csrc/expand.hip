@@ -23,6 +23,7 @@
 //     a'_l(parent) += -a_0 d^l / l + sum_{k=1..l} C(l-1, k-1) 2^-k d^(l-k) a'_k(child)
 //   L2P: far(z) = Re sum_l L'_l u^l,  u = (z - z_c) / s.
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 
 #include "blockscan.h"
@@ -56,42 +57,43 @@ __device__ inline cplx quadrant_offset(int ix, int iy) {
   return {(ix & 1) ? 0.25 : -0.25, (iy & 1) ? 0.25 : -0.25};
 }
 
-// P2M: 16 lanes per source leaf (four leaves per wave, one DPP row each);
-// lanes stride over the leaf's sources and the per-lane powers are summed
-// across the row by four rotate-and-add steps (row_ror 8, 4, 2, 1: plain VALU
-// moves, no LDS round trips), after which every lane of the row holds the
-// same sums.  The source offsets from the leaf corner (units of the finest
-// cell) are formed here from the ordered sources, as the packing step forms
-// them for the near field, so P2M does not wait for that step: grid nodes
-// from their packed index (exact half-integers), scattered sources from their
-// FP64 coordinates.
-constexpr int kP2MLanes = 16;
-
-// v plus the value of the lane N places further along its row of 16 lanes
-template <int N>
-__device__ inline double row_ror_add(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x120 + N, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x120 + N, 0xF, 0xF, false);
+// P2M: LANES lanes per source leaf (8 by default: eight leaves per wave);
+// lanes stride over the leaf's sources, four sources per lane per step with
+// their loads issued together, and the per-lane powers are summed across the
+// lane group by DPP moves (plain VALU, no LDS round trips): within quads
+// (lane xor 1, xor 2), then half rows (mirror: lane i with 7 - i), then rows
+// (rotate by 8).  After each step the lanes of a group hold bitwise equal
+// sums (the partner's value is added in the same order).  The source offsets
+// from the leaf corner (units of the finest cell) are formed here from the
+// ordered sources, as the packing step forms them for the near field, so P2M
+// does not wait for that step: grid nodes from their packed index (exact
+// half-integers), scattered sources from their FP64 coordinates.
+template <int CTRL>
+__device__ inline double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
   return v + __hiloint2double(hi, lo);
 }
 
-__device__ inline double row_sum16(double v) {
-  v = row_ror_add<8>(v);
-  v = row_ror_add<4>(v);
-  v = row_ror_add<2>(v);
-  return row_ror_add<1>(v);
+template <int LANES>
+__device__ inline double group_sum(double v) {
+  v = dpp_add<0xB1>(v);                     // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4E>(v);                     // quad_perm [2, 3, 0, 1]
+  if (LANES >= 8) v = dpp_add<0x141>(v);    // row_half_mirror
+  if (LANES >= 16) v = dpp_add<0x128>(v);   // row_ror:8
+  return v;
 }
 
-template <int PM>
+template <int PM, int LANES>
 __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
                                              const uint32_t* __restrict__ ij, const double* __restrict__ xs,
                                              const double* __restrict__ ys, double x0, double y0, double u,
                                              const double* __restrict__ w64, int p, double2* __restrict__ mp) {
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int li = (int)(gtid / kP2MLanes);
-  const int sub = (int)(gtid % kP2MLanes);
-  // every lane of a row takes part in the row sums: lanes past the last leaf
-  // work on a copy of it and store nothing
+  const int li = (int)(gtid / LANES);
+  const int sub = (int)(gtid % LANES);
+  // every lane of a group takes part in the group sums: lanes past the last
+  // leaf work on a copy of it and store nothing
   const int c = sleaves[li < n ? li : n - 1];
   const double side = cell_side(t.D, t.lvl[c]);
   const double inv = 1.0 / side;
@@ -101,14 +103,14 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
 #pragma unroll
   for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
   const int sb = t.sb[c], se = t.se[c];
-  // four sources per lane per step, their loads issued together (a missing
-  // source gets weight 0 at the leaf corner and adds nothing)
+  // four sources per lane per step (a missing source gets weight 0 at the
+  // leaf corner and adds nothing)
   constexpr int kR = 4;
-  for (int s = sb + sub; s < se; s += kR * kP2MLanes) {
+  for (int s = sb + sub; s < se; s += kR * LANES) {
     double ox[kR], oy[kR], w[kR];
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
-      const int sr = s + r * kP2MLanes;
+      const int sr = s + r * LANES;
       const bool ok = sr < se;
       if (ij) {
         const uint32_t v = ok ? ij[sr] : (uint32_t)cxi | ((uint32_t)cyi << 16);
@@ -134,14 +136,14 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
   }
 #pragma unroll
   for (int k = 0; k <= PM; ++k) {
-    acc[k].x = row_sum16(acc[k].x);
-    acc[k].y = row_sum16(acc[k].y);
+    acc[k].x = group_sum<LANES>(acc[k].x);
+    acc[k].y = group_sum<LANES>(acc[k].y);
   }
   if (li >= n) return;
   double2* out = mp + (int64_t)c * (p + 1);
 #pragma unroll
   for (int k = 0; k <= PM; ++k)
-    if (k <= p && (k % kP2MLanes) == sub)
+    if (k <= p && (k % LANES) == sub)
       out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
 }
 
@@ -658,11 +660,37 @@ __global__ __launch_bounds__(kM2PWaves* kWave) void k_m2p(TreeView t, const int*
 
 }  // namespace
 
+template <int LANES>
+void p2m_lanes(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys,
+               double x0, double y0, double u, const double* w64, int p, double2* mp, hipStream_t s) {
+  const unsigned g = (unsigned)(((int64_t)n * LANES + 255) / 256);
+  if (p <= 4)
+    k_p2m<4, LANES><<<g, 256, 0, s>>>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
+  else if (p <= 8)
+    k_p2m<8, LANES><<<g, 256, 0, s>>>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
+  else if (p <= 12)
+    k_p2m<12, LANES><<<g, 256, 0, s>>>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
+  else if (p <= 16)
+    k_p2m<16, LANES><<<g, 256, 0, s>>>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
+  else
+    k_p2m<kMaxP, LANES><<<g, 256, 0, s>>>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
+}
+
 void p2m(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys, double x0,
          double y0, double u, const double* w64, int p, double2* mp, hipStream_t s) {
   if (n <= 0) return;
-  const unsigned g = (unsigned)(((int64_t)n * kP2MLanes + 255) / 256);
-  PP_DISPATCH(p, k_p2m, g, 256, s, t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp);
+  // lanes per leaf: PP_P2M_LANES = 4, 8 (default) or 16
+  static const int lanes = [] {
+    const char* e = std::getenv("PP_P2M_LANES");
+    const int v = e ? std::atoi(e) : 8;
+    return (v == 4 || v == 16) ? v : 8;
+  }();
+  if (lanes == 4)
+    p2m_lanes<4>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp, s);
+  else if (lanes == 16)
+    p2m_lanes<16>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp, s);
+  else
+    p2m_lanes<8>(t, sleaves, n, ij, xs, ys, x0, y0, u, w64, p, mp, s);
 }
 
 int m2m_max_levels() { return kM2MLevels; }

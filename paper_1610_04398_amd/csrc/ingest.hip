@@ -3,8 +3,10 @@
 //
 // Grid sources need no sort: enumerating Morton indices m of the root's finest
 // cells in increasing order and keeping nodes with f != 0 yields the sources
-// already in key order.  Each workgroup owns a tile of 1024 consecutive Morton
-// indices (a 32 x 32 block of the grid), so its reads of f stay within 32 rows.
+// already in key order.  Two passes over f: nonzero counts per Morton tile,
+// then the emission of each tile at its offset.  A resident solve (the tree of
+// the last solve on the same grid kept) runs the emitting pass alone, with the
+// retained tile counts, and checks that the nonzero nodes are still the same.
 #include <algorithm>
 
 #include "blockscan.h"
@@ -14,199 +16,256 @@ namespace pp {
 
 namespace {
 constexpr int kIngBlock = 256;
-constexpr int kIngItems = 4;
-constexpr int kIngTile = kIngBlock * kIngItems;
+// A tile: 2^11 consecutive Morton indices, i.e. a block of 64 columns by 32
+// rows (x takes the even key bits).  Its rows are read whole (each lane two
+// neighbouring nodes, 32 lanes a 512-byte row), so the loads stay coalesced
+// although the output is in Morton order.
+constexpr int kTileBits = 11;
+constexpr int kIngTile = 1 << kTileBits;
+constexpr int kTileW = 64, kTileH = 32;
+constexpr int kPairLanes = kTileW / 2;                // lanes per tile row
+constexpr int kRowsPerPass = kIngBlock / kPairLanes;  // 8
+constexpr int kPasses = kTileH / kRowsPerPass;        // 4 row passes per tile
+constexpr int kItems = kIngTile / kIngBlock;          // 8 consecutive indices per thread
+// Tiles are counted in groups (one counting workgroup each); at most this many
+// groups, so that an emitting workgroup adds up few group totals.
+constexpr int64_t kMaxGroups = 1024;
+constexpr int kGroupReads = (int)(kMaxGroups / kIngBlock);  // group totals read per lane
 
-__device__ inline bool node_value(const double* __restrict__ f, int nx, int ny, uint64_t m, uint64_t mend,
-                                  double* v, int* bad) {
-  if (m >= mend) return false;
-  const uint32_t i = compact_bits((uint32_t)m);
-  const uint32_t j = compact_bits((uint32_t)(m >> 1));
-  if (i >= (uint32_t)nx || j >= (uint32_t)ny) return false;
-  const double x = f[(int64_t)j * nx + i];
-  if (!isfinite(x)) {
-    *bad = 1;
-    return false;
+// Two horizontally neighbouring nodes (i, j) and (i + 1, j); zero outside the
+// grid.  VEC: f is 16-byte aligned and nx even, so a pair is one 16-byte load
+// and lies wholly inside or outside the grid.
+template <bool VEC>
+__device__ inline void load_pair(const double* __restrict__ f, int nx, int ny, int i, int j, double* a,
+                                 double* b) {
+  *a = 0.0;
+  *b = 0.0;
+  if (i >= nx || j >= ny) return;
+  const double* p = f + (int64_t)j * nx + i;
+  if (VEC) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    *a = v.x;
+    *b = v.y;
+  } else {
+    *a = p[0];
+    if (i + 1 < nx) *b = p[1];
   }
-  *v = x;
-  return x != 0.0;
 }
 
-__global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __restrict__ f, int nx, int ny, int k,
-                                                             int* __restrict__ tile_cnt, int* __restrict__ flags) {
+// Local Morton index of column x, row y inside a tile.
+__device__ inline uint32_t tile_index(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
+
+// Tile counts.  Workgroup g counts the nonzero nodes of tiles [g G, g G + G)
+// two tiles at a time (eight row loads in flight per lane), then stores, per
+// tile, the count of the tiles before it in the group (tile_pre) and the group
+// total (grp[g]).  Non-finite values raise kFlagNonFiniteSource.
+template <bool VEC>
+__global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __restrict__ f, int nx, int ny, int G,
+                                                             int* __restrict__ tile_pre, int* __restrict__ grp,
+                                                             int* __restrict__ flags) {
+  extern __shared__ int cnt[];  // G counts
   __shared__ int lds[kIngBlock / kWave + 1];
-  const uint64_t mend = (uint64_t)1 << (2 * k);
-  const uint64_t base = (uint64_t)blockIdx.x * kIngTile + (uint64_t)threadIdx.x * kIngItems;
-  int c = 0, bad = 0;
-  for (int q = 0; q < kIngItems; ++q) {
-    double v;
-    c += node_value(f, nx, ny, base + q, mend, &v, &bad) ? 1 : 0;
+  const int g = blockIdx.x;
+  for (int q = threadIdx.x; q < G; q += kIngBlock) cnt[q] = 0;
+  __syncthreads();
+  const int c = threadIdx.x % kPairLanes, r = threadIdx.x / kPairLanes;
+  int bad = 0;
+  for (int q = 0; q < G; q += 2) {
+    int n[2] = {0, 0};
+    double a[2][kPasses], b[2][kPasses];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const uint32_t m0 = (uint32_t)(((int64_t)g * G + q + u) << kTileBits);
+      const int i0 = (int)compact_bits(m0), j0 = (int)compact_bits(m0 >> 1);
+      const bool live = q + u < G;
+#pragma unroll
+      for (int s = 0; s < kPasses; ++s) {
+        a[u][s] = b[u][s] = 0.0;
+        if (live) load_pair<VEC>(f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[u][s], &b[u][s]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int s = 0; s < kPasses; ++s) {
+        bad |= !isfinite(a[u][s]) || !isfinite(b[u][s]);
+        n[u] += (a[u][s] != 0.0) + (b[u][s] != 0.0);
+      }
+      n[u] = wave_sum(n[u]);
+    }
+    if (lane_id() == 0) {
+      if (n[0]) atomicAdd(&cnt[q], n[0]);
+      if (n[1] && q + 1 < G) atomicAdd(&cnt[q + 1], n[1]);
+    }
   }
   if (bad) atomicOr(flags, kFlagNonFiniteSource);
+  __syncthreads();
+  // exclusive scan of the G counts (G / 256 per thread, in order)
+  const int per = (G + kIngBlock - 1) / kIngBlock;
+  const int q0 = threadIdx.x * per;
+  int mine = 0;
+  for (int q = q0; q < q0 + per && q < G; ++q) mine += cnt[q];
   int total;
-  block_excl_scan<kIngBlock>(c, lds, &total);
-  if (threadIdx.x == 0) tile_cnt[blockIdx.x] = total;
+  int run = block_excl_scan<kIngBlock>(mine, lds, &total);
+  for (int q = q0; q < q0 + per && q < G; ++q) {
+    tile_pre[(int64_t)g * G + q] = run;
+    run += cnt[q];
+  }
+  if (threadIdx.x == 0) grp[g] = total;
 }
 
-// tile_sum: tile_off holds the per-tile counts instead of their exclusive
-// scan; each workgroup then adds up the counts before its own tile (few
-// tiles: at most kIngFusedTiles), and the last one stores the total.
+// Emission of tile blockIdx.x: its offset is the sum of the group totals
+// before its group plus its prefix inside the group (both from the counting
+// pass).  The tile's rows are staged in LDS in Morton order; each thread then
+// takes 8 consecutive indices, the workgroup scans the nonzero counts, the
+// kept nodes are compacted in LDS (weight and local index) and written out
+// with consecutive lanes on consecutive sources.
 // starts (may be null): for every Morton prefix of 2 * sh bits (the cells of
 // the tree's dense table), the position of its first source, i.e. the number
-// of sources with a smaller key: written by the item whose index begins the
-// prefix, before it emits.
+// of sources with a smaller key.
+template <bool VEC>
 __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restrict__ f, int nx, int ny, int k,
-                                                            double h2, const int* __restrict__ tile_off,
-                                                            int tile_sum, int* __restrict__ total_out,
-                                                            uint32_t* __restrict__ key, uint32_t* __restrict__ ij,
-                                                            double* __restrict__ w64, int* __restrict__ starts,
-                                                            int sh) {
+                                                            double h2, const int* __restrict__ tile_pre,
+                                                            const int* __restrict__ grp, int G,
+                                                            int* __restrict__ total_out, uint32_t* __restrict__ key,
+                                                            uint32_t* __restrict__ ij, double* __restrict__ w64,
+                                                            int* __restrict__ starts, int sh) {
+  __shared__ double wv[kIngTile];     // node values in Morton order, then the kept weights
+  __shared__ uint16_t lix[kIngTile];  // local Morton index of each kept node
   __shared__ int lds[kIngBlock / kWave + 1];
-  int before = 0;
-  if (tile_sum) {
-    int acc = 0;
-    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kIngBlock) acc += tile_off[t];
-    int all;
-    block_excl_scan<kIngBlock>(acc, lds, &all);
-    before = all;
-    __syncthreads();
-  } else {
-    before = tile_off[blockIdx.x];
-  }
-  const uint64_t mend = (uint64_t)1 << (2 * k);
-  const uint64_t base = (uint64_t)blockIdx.x * kIngTile + (uint64_t)threadIdx.x * kIngItems;
-  double v[kIngItems];
-  bool ok[kIngItems];
-  int c = 0, bad = 0;
-  for (int q = 0; q < kIngItems; ++q) {
-    ok[q] = node_value(f, nx, ny, base + q, mend, &v[q], &bad);
-    c += ok[q] ? 1 : 0;
-  }
-  int total;
-  int pos = block_excl_scan<kIngBlock>(c, lds, &total) + before;
-  if (tile_sum && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total_out = before + total;
-  const uint64_t pmask = ((uint64_t)1 << (2 * sh)) - 1;
-  for (int q = 0; q < kIngItems; ++q) {
-    if (starts && base + q < mend && ((base + q) & pmask) == 0) starts[(base + q) >> (2 * sh)] = pos;
-    if (!ok[q]) continue;
-    const uint64_t m = base + q;
-    const uint32_t i = compact_bits((uint32_t)m);
-    const uint32_t j = compact_bits((uint32_t)(m >> 1));
-    key[pos] = (uint32_t)m;
-    ij[pos] = i | (j << 16);
-    w64[pos] = v[q] * h2;
-    ++pos;
-  }
-}
-
-// Single pass (count, prefix, emit) over the tiles with a decoupled look-back:
-// a workgroup takes the next tile number from a ticket counter (so every
-// smaller tile belongs to a workgroup that is already running), counts its
-// tile's nonzero nodes and publishes that count.  Its first wave then reads
-// the published words of the 64 tiles before it at once: when the nearest
-// one that carries a prefix (the count of everything before that tile plus
-// its own) is found and every tile after it has published its count, the
-// counts and that prefix are added (a wave sum) and the walk ends; a window
-// with no prefix is added whole and the walk moves 64 tiles back.  The tile
-// then publishes its own prefix and emits.  Status word of a tile: 0 not yet,
-// 1 << 62 | count, 2 << 62 | prefix; the array and the ticket start at zero.
-// The words carry their own values and nothing else is read through them, so
-// relaxed device-scope atomics suffice (acquire loads would invalidate the
-// compute unit's caches on every poll).
-// A window that is not complete after kSpinLimit reads raises kFlagBadIndex
-// and the tile goes on with what it has (the solve is then reported as
-// failed), so the kernel always finishes.
-constexpr unsigned long long kStAgg = 1ull << 62, kStPre = 2ull << 62, kStVal = (1ull << 62) - 1;
-constexpr int kSpinLimit = 1 << 20;
-
-__device__ inline long long wave_sum_ll(long long v) {
+  const int64_t t = blockIdx.x;
+  const uint32_t m0 = (uint32_t)(t << kTileBits);
+  const int i0 = (int)compact_bits(m0), j0 = (int)compact_bits(m0 >> 1);
+  const int c = threadIdx.x % kPairLanes, r = threadIdx.x / kPairLanes;
+  // offset of the tile: the group totals before its group (read first, so
+  // that adding them up need not wait for the rows) and its prefix in the group
+  const int g = (int)(t / G);
+  int gv[kGroupReads];
 #pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-
-// Tiles of kFusedItems nodes per thread (4,096 nodes): a quarter as many tiles
-// as the two-pass ingest, so the look-back walks a quarter as far.
-constexpr int kFusedItems = 16;
-constexpr int kFusedTile = kIngBlock * kFusedItems;
-
-__global__ __launch_bounds__(kIngBlock) void k_ingest_fused(const double* __restrict__ f, int nx, int ny, int k,
-                                                             double h2, unsigned long long* __restrict__ status,
-                                                             int* __restrict__ ticket, int* __restrict__ total_out,
-                                                             uint32_t* __restrict__ key, uint32_t* __restrict__ ij,
-                                                             double* __restrict__ w64, int* __restrict__ starts,
-                                                             int sh, int* __restrict__ flags) {
-  __shared__ int lds[kIngBlock / kWave + 1];
-  __shared__ int tile_s, before_s;
-  if (threadIdx.x == 0) tile_s = atomicAdd(ticket, 1);
+  for (int u = 0; u < kGroupReads; ++u) {
+    const int q = threadIdx.x + u * kIngBlock;
+    gv[u] = q < g ? grp[q] : 0;
+  }
+  const int inner = tile_pre[t];
+  double a[kPasses], b[kPasses];
+#pragma unroll
+  for (int s = 0; s < kPasses; ++s) load_pair<VEC>(f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
+  int acc = 0;
+#pragma unroll
+  for (int u = 0; u < kGroupReads; ++u) acc += gv[u];
+  int before;
+  block_excl_scan<kIngBlock>(acc, lds, &before);
+  before += inner;
+#pragma unroll
+  for (int s = 0; s < kPasses; ++s) {
+    const uint32_t li = tile_index(2 * c, r + s * kRowsPerPass);  // even: the pair is adjacent
+    *reinterpret_cast<double2*>(&wv[li]) = make_double2(a[s], b[s]);
+  }
   __syncthreads();
-  const int tile = tile_s;
-  const uint64_t mend = (uint64_t)1 << (2 * k);
-  const uint64_t base = (uint64_t)tile * kFusedTile + (uint64_t)threadIdx.x * kFusedItems;
-  double v[kFusedItems];
-  bool ok[kFusedItems];
-  int c = 0, bad = 0;
+  const int l0 = threadIdx.x * kItems;
+  double v[kItems];
 #pragma unroll
-  for (int q = 0; q < kFusedItems; ++q) {
-    ok[q] = node_value(f, nx, ny, base + q, mend, &v[q], &bad);
-    c += ok[q] ? 1 : 0;
+  for (int q = 0; q < kItems; q += 2) {
+    const double2 p = *reinterpret_cast<const double2*>(&wv[l0 + q]);
+    v[q] = p.x;
+    v[q + 1] = p.y;
+  }
+  int cn = 0;
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) cn += v[q] != 0.0;
+  int total;
+  int pos = block_excl_scan<kIngBlock>(cn, lds, &total);  // ends with a barrier: wv is free
+  const uint64_t mend = (uint64_t)1 << (2 * k);
+  const uint32_t pmask = (uint32_t)(((uint64_t)1 << (2 * sh)) - 1);
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const uint32_t m = m0 | (uint32_t)(l0 + q);
+    if (starts && (uint64_t)m < mend && (m & pmask) == 0) starts[m >> (2 * sh)] = before + pos;
+    if (v[q] != 0.0) {
+      wv[pos] = v[q] * h2;
+      lix[pos] = (uint16_t)(l0 + q);
+      ++pos;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < total; q += kIngBlock) {
+    const int64_t o = (int64_t)before + q;
+    const uint32_t li = lix[q];
+    key[o] = m0 | li;
+    ij[o] = (uint32_t)(i0 + (int)compact_bits(li)) | ((uint32_t)(j0 + (int)compact_bits(li >> 1)) << 16);
+    w64[o] = wv[q];
+  }
+  if (t == (int64_t)gridDim.x - 1 && threadIdx.x == 0) *total_out = before + total;
+}
+
+// Resident weights: tile blockIdx.x of the new f is staged in LDS in Morton
+// order as above; its retained sources (the key range the counting pass of the
+// retained tree gave the tile) take w = f h^2 from it and mark their nodes in
+// a bitmap, and a nonzero node left unmarked (a node outside the retained
+// tree) raises kFlagStale.  Nodes that became zero keep their place with w = 0.
+template <bool VEC>
+__global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __restrict__ f, int nx, int ny,
+                                                                 double h2, const int* __restrict__ tile_pre,
+                                                                 const int* __restrict__ grp, int G,
+                                                                 const uint32_t* __restrict__ key, int64_t n,
+                                                                 double* __restrict__ w64, int* __restrict__ flags) {
+  __shared__ double wv[kIngTile];
+  __shared__ uint32_t kept[kIngTile / 32];
+  __shared__ int lds[kIngBlock / kWave + 1];
+  const int64_t t = blockIdx.x;
+  const uint32_t m0 = (uint32_t)(t << kTileBits);
+  const int i0 = (int)compact_bits(m0), j0 = (int)compact_bits(m0 >> 1);
+  const int c = threadIdx.x % kPairLanes, r = threadIdx.x / kPairLanes;
+  const int g = (int)(t / G);
+  int gv[kGroupReads];
+#pragma unroll
+  for (int u = 0; u < kGroupReads; ++u) {
+    const int q = threadIdx.x + u * kIngBlock;
+    gv[u] = q < g ? grp[q] : 0;
+  }
+  const int inner = tile_pre[t];
+  const int next = (t + 1) % G == 0 ? grp[g] : tile_pre[t + 1];
+  double a[kPasses], b[kPasses];
+#pragma unroll
+  for (int s = 0; s < kPasses; ++s) load_pair<VEC>(f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
+  if (threadIdx.x < kIngTile / 32) kept[threadIdx.x] = 0;
+  int acc = 0;
+#pragma unroll
+  for (int u = 0; u < kGroupReads; ++u) acc += gv[u];
+  int before;
+  block_excl_scan<kIngBlock>(acc, lds, &before);  // (its barriers also order the bitmap's clearing)
+  const int cnt = next - inner;
+  before += inner;
+  int bad = 0;
+#pragma unroll
+  for (int s = 0; s < kPasses; ++s) {
+    bad |= !isfinite(a[s]) || !isfinite(b[s]);
+    const uint32_t li = tile_index(2 * c, r + s * kRowsPerPass);
+    *reinterpret_cast<double2*>(&wv[li]) = make_double2(a[s], b[s]);
   }
   if (bad) atomicOr(flags, kFlagNonFiniteSource);
-  int total;
-  int pos = block_excl_scan<kIngBlock>(c, lds, &total);
-  if (threadIdx.x < kWave) {  // the first wave publishes and looks back
-    const int lane = threadIdx.x;
-    long long before = 0;
-    if (lane == 0)
-      __hip_atomic_store(&status[tile], (tile == 0 ? kStPre : kStAgg) | (unsigned long long)total, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    if (tile > 0) {
-      int top = tile - 1, reads = 0;
-      for (;;) {
-        const int j = top - lane;
-        const unsigned long long st =
-            j >= 0 ? __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : kStPre;
-        const unsigned long long kind = st & ~kStVal;
-        const unsigned long long pre = __ballot(kind == kStPre);
-        const unsigned long long wait = __ballot(kind == 0);
-        const int first = pre ? __builtin_ctzll(pre) : kWave;  // nearest tile with a prefix
-        const unsigned long long upto = first >= kWave - 1 ? ~0ull : ((2ull << first) - 1);
-        if (wait & upto) {  // a tile at or after the prefix has not published yet
-          if (++reads > kSpinLimit) {
-            if (lane == 0) atomicOr(flags, kFlagBadIndex);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        before += wave_sum_ll(lane <= first ? (long long)(st & kStVal) : 0);
-        if (first < kWave) break;
-        top -= kWave;
-      }
-      if (lane == 0)
-        __hip_atomic_store(&status[tile], kStPre | (unsigned long long)(before + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  int stale = 0;
+  for (int q = threadIdx.x; q < cnt; q += kIngBlock) {
+    const int64_t o = (int64_t)before + q;
+    if (o >= n) {
+      stale = 1;
+      break;
     }
-    if (lane == 0) {
-      before_s = (int)before;
-      if (tile == (int)gridDim.x - 1) *total_out = (int)(before + total);
+    const uint32_t li = key[o] - m0;
+    if (li >= (uint32_t)kIngTile) {
+      stale = 1;
+      continue;
     }
+    w64[o] = wv[li] * h2;
+    atomicOr(&kept[li >> 5], 1u << (li & 31));
   }
   __syncthreads();
-  pos += before_s;
-  const uint64_t pmask = ((uint64_t)1 << (2 * sh)) - 1;
+  const int l0 = threadIdx.x * kItems;
+  const uint32_t mask = (kept[l0 >> 5] >> (l0 & 31)) & 0xFFu;
 #pragma unroll
-  for (int q = 0; q < kFusedItems; ++q) {
-    if (starts && base + q < mend && ((base + q) & pmask) == 0) starts[(base + q) >> (2 * sh)] = pos;
-    if (!ok[q]) continue;
-    const uint64_t m = base + q;
-    const uint32_t i = compact_bits((uint32_t)m);
-    const uint32_t j = compact_bits((uint32_t)(m >> 1));
-    key[pos] = (uint32_t)m;
-    ij[pos] = i | (j << 16);
-    w64[pos] = v[q] * h2;
-    ++pos;
-  }
+  for (int q = 0; q < kItems; ++q) stale |= wv[l0 + q] != 0.0 && !((mask >> q) & 1u);
+  if (stale) atomicOr(flags, kFlagStale);
 }
 
 __global__ void k_target_keys(const double* __restrict__ tx, const double* __restrict__ ty, int64_t m, double x0,
@@ -220,49 +279,9 @@ __global__ void k_target_keys(const double* __restrict__ tx, const double* __res
   key[t] = kk;
   idx[t] = (int)t;
 }
-// ---- resident solves: new weights on a retained tree, and the checks that
-// the tree still fits the input ----
 
-constexpr int kResBlock = 256;
-
-__device__ inline int block_sum_int(int v, int* lds) {
-  int total;
-  block_excl_scan<kResBlock>(v, lds, &total);
-  return total;
-}
-
-// w = f h^2 of every retained source (its packed node index), the number of
-// retained sources with f != 0, and the number of nonzero nodes of the whole
-// grid: the retained tree fits the new f exactly when the two counts agree
-// (no node outside it has become nonzero).
-__global__ __launch_bounds__(kResBlock) void k_resident_weights(const double* __restrict__ f, int nx, int64_t ngrid,
-                                                                 double h2, const uint32_t* __restrict__ ij,
-                                                                 int64_t n, double* __restrict__ w64,
-                                                                 int* __restrict__ cnt_kept,
-                                                                 int* __restrict__ cnt_all, int* __restrict__ flags) {
-  __shared__ int lds[kResBlock / kWave + 1];
-  const int64_t stride = (int64_t)gridDim.x * kResBlock;
-  int kept = 0, all = 0, bad = 0;
-  for (int64_t q = (int64_t)blockIdx.x * kResBlock + threadIdx.x; q < n; q += stride) {
-    const uint32_t c = ij[q];
-    const double v = f[(int64_t)(c >> 16) * nx + (c & 0xFFFFu)];
-    w64[q] = v * h2;
-    kept += v != 0.0;
-  }
-  for (int64_t q = (int64_t)blockIdx.x * kResBlock + threadIdx.x; q < ngrid; q += stride) {
-    const double v = f[q];
-    bad |= !isfinite(v);
-    all += v != 0.0;
-  }
-  if (bad) atomicOr(flags, kFlagNonFiniteSource);
-  kept = block_sum_int(kept, lds);
-  __syncthreads();
-  all = block_sum_int(all, lds);
-  if (threadIdx.x == 0) {
-    if (kept) atomicAdd(cnt_kept, kept);
-    if (all) atomicAdd(cnt_all, all);
-  }
-}
+// ---- resident solves: the check that the sorted targets still fit the
+// retained tree (its new weights come from the emitting pass above) ----
 
 // Every target must still lie in the finest cell it was sorted into.
 __global__ void k_resident_targets(const double* __restrict__ tx, const double* __restrict__ ty, int64_t m,
@@ -277,20 +296,7 @@ __global__ void k_resident_targets(const double* __restrict__ tx, const double* 
   else if (kk != key[q]) atomicOr(flags, kFlagStale);
 }
 
-__global__ void k_resident_verdict(const int* __restrict__ cnt_kept, const int* __restrict__ cnt_all,
-                                   int* __restrict__ flags) {
-  if (threadIdx.x == 0 && *cnt_kept != *cnt_all) atomicOr(flags, kFlagStale);
-}
 }  // namespace
-
-void resident_weights(const double* f, int nx, int ny, double h2, const uint32_t* ij, int64_t n, double* w64,
-                      int* cnt_kept, int* cnt_all, int* flags, hipStream_t s) {
-  const int64_t ngrid = (int64_t)nx * ny;
-  const int64_t work = std::max<int64_t>(ngrid, 1);
-  const unsigned blocks = (unsigned)std::min<int64_t>((work + kResBlock - 1) / kResBlock, 4096);
-  k_resident_weights<<<blocks, kResBlock, 0, s>>>(f, nx, ngrid, h2, ij, n, w64, cnt_kept, cnt_all, flags);
-  k_resident_verdict<<<1, kWave, 0, s>>>(cnt_kept, cnt_all, flags);
-}
 
 void resident_targets(const double* tx, const double* ty, int64_t m, const int* perm, const uint32_t* key, double x0,
                       double y0, double h, int k, int* flags, hipStream_t s) {
@@ -304,26 +310,49 @@ int64_t ingest_num_tiles(int k) {
   return (cells + kIngTile - 1) / kIngTile;
 }
 
+namespace {
+int group_tiles(int k) { return (int)std::max<int64_t>(1, ingest_num_tiles(k) / kMaxGroups); }
+bool vec_ok(const double* f, int nx) { return (nx % 2) == 0 && ((uintptr_t)f % 16) == 0; }
+}  // namespace
+
+int64_t ingest_count_ints(int k) {
+  const int64_t nt = ingest_num_tiles(k);
+  return nt + nt / group_tiles(k);
+}
+
 void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s) {
-  k_ingest_count<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, tile_cnt, flags);
+  const int G = group_tiles(k);
+  const int64_t nt = ingest_num_tiles(k);
+  const unsigned ng = (unsigned)(nt / G);
+  const size_t lds = (size_t)G * sizeof(int);
+  if (vec_ok(f, nx))
+    k_ingest_count<true><<<ng, kIngBlock, lds, s>>>(f, nx, ny, G, tile_cnt, tile_cnt + nt, flags);
+  else
+    k_ingest_count<false><<<ng, kIngBlock, lds, s>>>(f, nx, ny, G, tile_cnt, tile_cnt + nt, flags);
 }
 
-void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, int tile_sum,
-                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s) {
-  k_ingest_emit<<<(unsigned)ingest_num_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_off, tile_sum, total_out,
-                                                                     key, ij, w64, starts, sh);
+void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, int* total_out,
+                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s) {
+  const int G = group_tiles(k);
+  const int64_t nt = ingest_num_tiles(k);
+  if (vec_ok(f, nx))
+    k_ingest_emit<true><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_cnt, tile_cnt + nt, G, total_out,
+                                                            key, ij, w64, starts, sh);
+  else
+    k_ingest_emit<false><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_cnt, tile_cnt + nt, G, total_out,
+                                                             key, ij, w64, starts, sh);
 }
 
-int64_t ingest_fused_tiles(int k) {
-  const int64_t cells = (int64_t)1 << (2 * k);
-  return (cells + kFusedTile - 1) / kFusedTile;
-}
-
-void ingest_grid_fused(const double* f, int nx, int ny, int k, double h2, unsigned long long* status, int* ticket,
-                       int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, int* flags,
-                       hipStream_t s) {
-  k_ingest_fused<<<(unsigned)ingest_fused_tiles(k), kIngBlock, 0, s>>>(f, nx, ny, k, h2, status, ticket, total_out,
-                                                                        key, ij, w64, starts, sh, flags);
+void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* key,
+                      int64_t n, double* w64, int* flags, hipStream_t s) {
+  const int G = group_tiles(k);
+  const int64_t nt = ingest_num_tiles(k);
+  if (vec_ok(f, nx))
+    k_resident_weights<true><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, h2, tile_cnt, tile_cnt + nt, G, key, n,
+                                                                 w64, flags);
+  else
+    k_resident_weights<false><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, h2, tile_cnt, tile_cnt + nt, G, key, n,
+                                                                  w64, flags);
 }
 
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k, uint32_t* key,

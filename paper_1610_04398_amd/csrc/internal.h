@@ -33,31 +33,28 @@ size_t ctx_held_bytes(const pp_ctx* c);
 void ctx_trim(pp_ctx* c);
 
 // ---- ingest.hip: sources in Morton order, target keys ------------------------------
-// Morton tiles of 1024 indices cover [0, 4^k).
+// Morton tiles of 2048 indices (64 x 32 nodes) cover [0, 4^k).
 int64_t ingest_num_tiles(int k);
-// Resident solves (a retained tree, new f): w = f h^2 for the n retained
-// sources (packed node indices ij); the counts of retained nonzero sources and
-// of nonzero grid nodes go to *cnt_kept and *cnt_all (zeroed by the caller),
-// and kFlagStale is raised when they differ.
-void resident_weights(const double* f, int nx, int ny, double h2, const uint32_t* ij, int64_t n, double* w64,
-                      int* cnt_kept, int* cnt_all, int* flags, hipStream_t s);
+// Ints of the tile-count buffer: per tile the nonzero count of the tiles before
+// it in its group, then one total per group.
+int64_t ingest_count_ints(int k);
+// First pass: tile counts (tile_cnt: ingest_count_ints(k) ints; no clearing needed).
+void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s);
+// Second pass: the sources in Morton order (key, packed node index ij,
+// w = f h^2) and *total_out = their count.  starts (may be null): the source
+// range start of every Morton prefix of 2 * sh bits (cells of the dense table
+// sh levels above the finest).
+void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, int* total_out,
+                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s);
+// Resident solves (the tree of the last solve kept, new f on the same grid):
+// w = f h^2 of the n retained sources (keys key, tile counts tile_cnt of the
+// retained solve), in one pass over f; kFlagStale when a node outside them is
+// nonzero (retained nodes may have become zero).
+void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* key,
+                      int64_t n, double* w64, int* flags, hipStream_t s);
 // kFlagStale unless every target (caller index perm[q]) still has the sorted key key[q].
 void resident_targets(const double* tx, const double* ty, int64_t m, const int* perm, const uint32_t* key, double x0,
                       double y0, double h, int k, int* flags, hipStream_t s);
-void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s);
-// tile_sum != 0: tile_off holds the per-tile counts (not their scan) and
-// *total_out receives the source count; only for at most kIngFusedTiles tiles.
-constexpr int64_t kIngFusedTiles = 1024;
-// The same in one pass (a decoupled look-back over the tiles, in the order of a
-// ticket counter): status (ingest_fused_tiles(k) words) and *ticket must be zero.
-int64_t ingest_fused_tiles(int k);
-void ingest_grid_fused(const double* f, int nx, int ny, int k, double h2, unsigned long long* status, int* ticket,
-                       int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, int* flags,
-                       hipStream_t s);
-// starts (may be null): the source range start of every Morton prefix of
-// 2 * sh bits (cells of the dense table sh levels above the finest).
-void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_off, int tile_sum,
-                      int* total_out, uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s);
 void target_keys(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
                  uint32_t* key, int* idx, int* flags, hipStream_t s);
 

@@ -55,7 +55,7 @@ enum BufId {
   B_FLAG, B_SLEAF, B_TLEAF, B_TCELL, B_M2MC, B_L2LC, B_CM2L, B_OM2L, B_CP2P, B_OP2P, B_M2LSRC, B_P2PSRC,
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
-  B_S64, B_SELFW, B_TSTAT, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
+  B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
   B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY, B_LOGT,
   B_COUNT
 };
@@ -116,11 +116,11 @@ constexpr int kMiscInts = 128;
 constexpr int kMailExtra = 32;
 constexpr int kSeqSlot = kMiscInts;
 // misc layout: [0] flags, [1] source count, [2] scratch total, [3] level work items,
-// [4..8] cell-list and interaction-list totals, [10..11] resident-solve counts, [12] levels below the dense
-// table needed, [13] ticket counter of the single-pass ingest, [16..17] near-field pair count (u64),
+// [4..8] cell-list and interaction-list totals, [12] levels below the dense
+// table needed, [16..17] near-field pair count (u64),
 // [32..32+D+2] level starts of the tree, [96..103] bounding box of scattered input (4 doubles).
 constexpr int M_FLAGS = 0, M_NSRC = 1, M_TOT = 2, M_N4 = 3, M_NSL = 4, M_NTL = 5, M_NTC = 6, M_NM2L = 7,
-              M_NP2P = 8, M_RKEPT = 10, M_RALL = 11, M_DEEP = 12, M_TICKET = 13, M_PAIRS = 16, M_LS = 32,
+              M_NP2P = 8, M_DEEP = 12, M_PAIRS = 16, M_LS = 32,
               M_BOX = 96;
 
 }  // namespace
@@ -137,9 +137,6 @@ struct pp_ctx {
   // instead of replaying it from a graph (PP_DIRECT_ISSUE=0 replays it)
   int direct_issue = 1;
   int dense_levels = 9;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
-  // grid ingest in one pass with a decoupled look-back (PP_INGEST_FUSED=1) instead of count, scan and emit:
-  // correct, but measured 2.2x slower at 4096^2 (polling device-coherent words across the XCDs)
-  bool ingest_fused = false;
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only, 16 + phase that phase's launches
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
@@ -554,7 +551,6 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const int D = src.grid ? root_exponent(nx, ny) : kPointsDepth;
   const int k = D;
   // capacities from the input sizes (the source count is only known on the device)
-  const int64_t ntiles = src.grid ? ingest_num_tiles(k) : 1;
   int64_t geo = 0;
   for (int l = 0; l <= D; ++l) geo += (int64_t)1 << (2 * l);
   const int64_t per_level = 4 * (nmax / (lm + 1) + m / (lm + 1) + 1);  // children of split cells
@@ -578,7 +574,6 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   int* boxc = nullptr;
   uint32_t *skey = nullptr, *sij = nullptr, *skey2 = nullptr, *tkey = nullptr, *tkey2 = nullptr;
   double *sw = nullptr, *pxs = nullptr, *pys = nullptr;
-  unsigned long long* tstat = nullptr;
   int *tile = nullptr, *sort_tmp = nullptr, *sperm2 = nullptr, *tperm = nullptr, *tperm2 = nullptr;
   TreeArrays ta{};
   int4* rec = nullptr;
@@ -601,13 +596,12 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       boxc = ensure<int>(c, B_BOXC, nbox);
     }
     scan = ensure<int>(c, B_SCAN,
-                       std::max<int64_t>((int64_t)scan_temp_ints(std::max<int64_t>({ntiles, 4 * per_level, cap, m, nmax, 1})),
+                       std::max<int64_t>((int64_t)scan_temp_ints(std::max<int64_t>({4 * per_level, cap, m, nmax, 1})),
                                          tree_dense_part_ints(Ld)));
     skey = ensure<uint32_t>(c, B_SKEY, nmax);
     sij = ensure<uint32_t>(c, B_SIJ, nmax);  // grid: packed (i, j); points: input index
     sw = ensure<double>(c, B_SW, nmax);
-    tile = src.grid ? ensure<int>(c, B_TILE, ntiles) : nullptr;
-    tstat = src.grid && c.ingest_fused ? ensure<unsigned long long>(c, B_TSTAT, ingest_fused_tiles(k)) : nullptr;
+    tile = src.grid ? ensure<int>(c, B_TILE, ingest_count_ints(k)) : nullptr;
     sort_tmp = ensure<int>(c, B_SORT, (int64_t)radix_temp_ints(std::max<int64_t>(src.grid ? 0 : src.n, m)));
     skey2 = src.grid ? nullptr : ensure<uint32_t>(c, B_SKEY2, src.n);
     sperm2 = src.grid ? nullptr : ensure<int>(c, B_SPERM2, src.n);
@@ -717,7 +711,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(PP_PHASE_INGEST);
     fill_i32(misc, 0, kMiscInts, s);
     tbegin(PP_PHASE_INGEST, s);
-    resident_weights(f_d, nx, ny, unit * unit, sij, R.N, sw, misc + M_RKEPT, misc + M_RALL, misc + M_FLAGS, s);
+    resident_weights(f_d, nx, ny, k, unit * unit, tile, skey, R.N, sw, misc + M_FLAGS, s);
     tend(PP_PHASE_INGEST, s);
     mark(PP_PHASE_SORT);
     tbegin(PP_PHASE_SORT, s);
@@ -730,19 +724,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     tbegin(PP_PHASE_INGEST, s);
     if (src.grid) {
       // ---- ingest: sources in Morton order (no sort needed for a grid) ----
-      if (tstat) {  // one pass over f
-        fill_i32((int*)tstat, 0, 2 * ingest_fused_tiles(k), s);
-        ingest_grid_fused(f_d, nx, ny, k, unit * unit, tstat, misc + M_TICKET, misc + M_NSRC, skey, sij, sw, dss,
-                          D - Ld, misc + M_FLAGS, s);
-      } else {  // count per tile, then emit
-        ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
-        if (ntiles <= kIngFusedTiles) {  // the emitting workgroups add up the tile counts themselves
-          ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 1, misc + M_NSRC, skey, sij, sw, dss, D - Ld, s);
-        } else {
-          scan_exclusive(tile, tile, ntiles, scan, misc + M_NSRC, s);
-          ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, 0, nullptr, skey, sij, sw, dss, D - Ld, s);
-        }
-      }
+      ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
+      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, misc + M_NSRC, skey, sij, sw, dss, D - Ld, s);
     } else if (src.n > 0) {
       // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
       int* sperm = (int*)sij;
@@ -1328,7 +1311,6 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DIRECT_ISSUE")) c->direct_issue = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
-  if (const char* e = std::getenv("PP_INGEST_FUSED")) c->ingest_fused = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities

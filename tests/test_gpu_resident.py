@@ -131,3 +131,37 @@ def test_resident_refuses_a_tree_that_does_not_fit(pp):
         assert e.value.status == -1
     finally:
         s.close()
+
+
+def test_resident_multi_group_grid(pp):
+    """A 1100^2 grid (2,048 Morton tiles, counted in groups of two): with the same nonzero nodes the resident
+    solve is bitwise the fresh one; with nodes zeroed it agrees with the fresh solve to the accuracy contract;
+    a node that becomes nonzero in a late tile (inside a zero patch) is refused."""
+    n = 1100
+    h = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(2024))
+    f = rng.standard_normal((n, n))
+    f[rng.uniform(size=f.shape) < 0.5] = 0.0
+    f[900:1000, 900:1000] = 0.0
+    tx, ty = rng.uniform(0, 1, 2000), rng.uniform(0, 1, 2000)
+    s, ref = pp.Solver(0), pp.Solver(0)
+    try:
+        kw = dict(p=10, theta=0.5, precision="mixed")
+        txd, tyd = to_dev(tx, ty)
+        s.solve_grid(to_dev(f)[0], h, txd, tyd, **kw)
+        f2d = to_dev(1.7 * f)[0]
+        got = to_host(s.solve_grid_resident(f2d, txd, tyd))
+        assert np.array_equal(got, to_host(ref.solve_grid(f2d, h, txd, tyd, **kw)))
+        f3 = 1.7 * f
+        f3[rng.uniform(size=f.shape) < 0.2] = 0.0
+        f3d = to_dev(f3)[0]
+        got = to_host(s.solve_grid_resident(f3d, txd, tyd))
+        assert rel_l2(got, to_host(ref.solve_grid(f3d, h, txd, tyd, **kw))) < 1e-6
+        f4 = f.copy()
+        f4[950, 950] = 1.0
+        with pytest.raises(pp.PPError) as e:
+            s.solve_grid_resident(to_dev(f4)[0], txd, tyd)
+        assert e.value.status == -1
+    finally:
+        s.close()
+        ref.close()

@@ -120,33 +120,29 @@ def test_target_sort_multi_tile(solver):
     np.testing.assert_array_equal(solver.debug_array("TGT_PERM"), perm)
 
 
-@pytest.mark.parametrize("n", [40, 1024])
-def test_ingest_single_pass_matches_two_pass(solver, monkeypatch, n):
-    """The single-pass grid ingest (tiles taken in ticket order, each adding up the counts before it with a
-    look-back) gives the sources of the reference ordering bit for bit, and the same solve as the count /
-    scan / emit ingest, on a one-tile grid and on a 1024^2 grid of 1,024 tiles with sparse patches."""
-    import paper_1610_04398_amd as pp
-    rng = np.random.Generator(np.random.PCG64(77 + n))
-    f = rng.standard_normal((n, n))
+@pytest.mark.parametrize("ny,nx,offset", [(40, 40, 0), (700, 1101, 0), (1030, 1030, 1), (2050, 2050, 0)])
+def test_ingest_sources_bit_exact(solver, ny, nx, offset):
+    """The grid ingest (nonzero counts per Morton tile of 64 x 32 nodes in groups of tiles, then emission of
+    each tile at its offset) gives the oracle's sources bit for bit: one tile; an odd row length (node pairs
+    loaded one by one) over 2,048 tiles in groups of two; f 8 bytes off 16-byte alignment; 8,192 tiles in
+    groups of eight.  Zero patches leave whole tiles and groups empty."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(77 + nx + ny))
+    f = rng.standard_normal((ny, nx))
     f[rng.uniform(size=f.shape) < 0.6] = 0.0
-    f[: n // 3, : n // 2] = 0.0  # empty tiles
-    h = 1.0 / n
-    tx, ty = rng.uniform(0, 1, 500), rng.uniform(0, 1, 500)
-    outs, keys = [], []
-    for fused in ("1", "0"):
-        monkeypatch.setenv("PP_INGEST_FUSED", fused)
-        s = pp.Solver(0)
-        try:
-            outs.append(s.solve_grid(f, h, tx, ty, p=8, theta=0.5, precision="mixed"))
-            keys.append((s.debug_array("SRC_KEY").astype(np.uint64), s.debug_array("SRC_INDEX").astype(np.int64)))
-        finally:
-            s.close()
-    monkeypatch.delenv("PP_INGEST_FUSED")
+    f[: ny // 3, : nx // 2] = 0.0
+    h = 1.0 / max(nx, ny)
+    tx, ty = rng.uniform(0, nx * h, 300), rng.uniform(0, ny * h, 300)
+    base = torch.zeros(nx * ny + offset, dtype=torch.float64, device="cuda")
+    fd = base[offset:].view(ny, nx)
+    fd.copy_(torch.from_numpy(f))
+    assert (fd.data_ptr() % 16 == 0) == (offset == 0)
+    solver.solve_grid(fd, h, *to_dev(tx, ty), p=6, theta=0.5, precision="mixed")
     ref_keys, ref_flat = tree_ref.source_keys_grid(f)
-    for k, ij in keys:
-        np.testing.assert_array_equal(k, ref_keys)
-        assert np.array_equal((ij >> 16) * n + (ij & 0xFFFF), ref_flat)
-    assert np.array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(solver.debug_array("SRC_KEY").astype(np.uint64), ref_keys)
+    ij = solver.debug_array("SRC_INDEX").astype(np.int64)
+    assert np.array_equal((ij >> 16) * nx + (ij & 0xFFFF), ref_flat)
+    assert solver.stats()["nsources"] == ref_keys.size
 
 
 @pytest.mark.parametrize("dense_levels", ["0", "3"])
