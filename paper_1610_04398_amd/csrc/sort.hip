@@ -4,7 +4,9 @@
 // order, so the permutation is unique.
 //
 // Per digit pass: per-tile digit histograms -> one device-wide exclusive scan
-// of the digit-major histogram table -> stable scatter.  Within a tile the
+// of the digit-major histogram table -> stable scatter (for at most 64 tiles
+// the scatter's workgroups form their offsets from the table themselves, and
+// the scan launch is skipped).  Within a tile the
 // scatter ranks keys round by round (256 keys per round, in thread order),
 // matching equal digits across a wave with one ballot per digit bit.
 #include "blockscan.h"
@@ -66,20 +68,62 @@ __global__ __launch_bounds__(kRsBlock) void k_keys_hist(const double* __restrict
   for (int b = threadIdx.x; b < BINS; b += kRsBlock) hist[b * nblocks + blockIdx.x] = hs[b];
 }
 
-template <int BITS>
+// FOLD: `off` holds the raw per-tile digit counts (digit-major) instead of
+// their exclusive scan, and each workgroup forms its own offsets from them:
+// the totals of all smaller digits plus the counts of its digit in the tiles
+// before it.  For few tiles (at most kRsFoldTiles) this replaces the scan
+// launch between the histogram and the scatter.
+constexpr int kRsFoldTiles = 64;
+
+template <int BITS, bool FOLD>
 __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                              const int* __restrict__ vin, int n, int shift, int nblocks,
                                                              const int* __restrict__ off, uint32_t* __restrict__ kout,
                                                              int* __restrict__ vout) {
   constexpr int BINS = 1 << BITS;
+  constexpr int PER = (BINS + kRsBlock - 1) / kRsBlock;  // digits per thread
   __shared__ int goff[BINS];
   __shared__ int run[BINS];
   __shared__ int wcnt[kRsWaves][BINS];
+  __shared__ int lds[kRsWaves + 1];
   const int t = threadIdx.x;
   const int lane = t % kWave;
   const int w = t / kWave;
+  if (FOLD) {
+    // thread t owns digits [t PER, t PER + PER)
+    int tot[PER], pre[PER], sum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = t * PER + q;
+      tot[q] = pre[q] = 0;
+      if (b < BINS) {
+        // 16 loads in flight at a time (clamped indices, no branch around them)
+        for (int b0 = 0; b0 < nblocks; b0 += 16) {
+          int c[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) c[u] = off[b * nblocks + min(b0 + u, nblocks - 1)];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int blk = b0 + u;
+            tot[q] += blk < nblocks ? c[u] : 0;
+            pre[q] += blk < (int)blockIdx.x ? c[u] : 0;
+          }
+        }
+      }
+      sum += tot[q];
+    }
+    int all;
+    int base = block_excl_scan<kRsBlock>(sum, lds, &all);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int b = t * PER + q;
+      if (b < BINS) goff[b] = base + pre[q];
+      base += tot[q];
+    }
+  } else {
+    for (int b = t; b < BINS; b += kRsBlock) goff[b] = off[b * nblocks + blockIdx.x];
+  }
   for (int b = t; b < BINS; b += kRsBlock) {
-    goff[b] = off[b * nblocks + blockIdx.x];
     run[b] = 0;
     for (int ww = 0; ww < kRsWaves; ++ww) wcnt[ww][b] = 0;
   }
@@ -154,8 +198,12 @@ void radix_pass(uint32_t* ka, int* va, uint32_t* kb, int* vb, int n, int shift, 
                                               ks->flags);
   else
     k_radix_hist<BITS><<<nb, kRsBlock, 0, s>>>(ka, n, shift, nb, table);
-  scan_exclusive(table, table, (int64_t)(1 << BITS) * nb, scan_tmp, nullptr, s);
-  k_radix_scatter<BITS><<<nb, kRsBlock, 0, s>>>(ka, va, n, shift, nb, table, kb, vb);
+  if (nb <= kRsFoldTiles) {
+    k_radix_scatter<BITS, true><<<nb, kRsBlock, 0, s>>>(ka, va, n, shift, nb, table, kb, vb);
+  } else {
+    scan_exclusive(table, table, (int64_t)(1 << BITS) * nb, scan_tmp, nullptr, s);
+    k_radix_scatter<BITS, false><<<nb, kRsBlock, 0, s>>>(ka, va, n, shift, nb, table, kb, vb);
+  }
 }
 
 void sort_impl(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int64_t n, int bits, int* temp,
@@ -163,12 +211,15 @@ void sort_impl(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int
   const int nb = (int)((n + kRsTile - 1) / kRsTile);
   int* table = temp;
   int* scan_tmp = temp + (1 << kRsMaxBits) * (int64_t)nb;
-  uint32_t* ka = keys;
-  int* va = vals;
-  uint32_t* kb = keys_tmp;
-  int* vb = vals_tmp;
   const int passes = (bits + kRsMaxBits - 1) / kRsMaxBits;
   const int width = (bits + passes - 1) / passes;
+  // keys computed by the first pass start in the buffer from which an odd
+  // number of passes ends in the result buffers (no final copy)
+  const bool start_tmp = ks && (passes & 1);
+  uint32_t* ka = start_tmp ? keys_tmp : keys;
+  int* va = start_tmp ? vals_tmp : vals;
+  uint32_t* kb = start_tmp ? keys : keys_tmp;
+  int* vb = start_tmp ? vals : vals_tmp;
   for (int ps = 0; ps < passes; ++ps) {
     const int shift = width * ps;
     const KeySource* kp = ps == 0 ? ks : nullptr;

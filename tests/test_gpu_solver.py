@@ -120,6 +120,29 @@ def test_target_sort_multi_tile(solver):
     np.testing.assert_array_equal(solver.debug_array("TGT_PERM"), perm)
 
 
+@pytest.mark.parametrize("ny,nx,m", [(2100, 2100, 32768), (3, 9000, 20000), (5, 5, 2), (128, 128, 70001)])
+def test_target_sort_widths(ny, nx, m):
+    """The target sort at several key widths: three passes of 8 bits at a 4096 root (32 tiles, offsets
+    summed inside the scatter), four of 7 bits at 16384, one of 6 bits at 8, two of 7 bits over 69 tiles
+    (offsets from a separate scan).  Keys and permutation equal the oracle's stable sort; a third of the
+    targets share one of 40 positions (equal keys)."""
+    import paper_1610_04398_amd as pp
+    s = pp.Solver(0)
+    try:
+        rng = np.random.Generator(np.random.PCG64(nx + m))
+        f = rng.standard_normal((ny, nx))
+        h = 1.0 / max(nx, ny)
+        rep = rng.uniform(0.0, 1.0, (40, 2))[rng.integers(0, 40, m // 3)]
+        tx = np.concatenate([rep[:, 0], rng.uniform(0.0, 1.0, m - m // 3)]) * nx * h
+        ty = np.concatenate([rep[:, 1], rng.uniform(0.0, 1.0, m - m // 3)]) * ny * h
+        s.solve_grid(f, h, tx, ty, p=4, theta=0.5, leaf_max=64, precision="mixed")
+        keys, perm = tree_ref.target_keys_sorted(tx, ty, 0.0, 0.0, h, tree_ref.root_exponent(nx, ny))
+        np.testing.assert_array_equal(s.debug_array("TGT_KEY").astype(np.uint64), keys)
+        np.testing.assert_array_equal(s.debug_array("TGT_PERM"), perm)
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("ny,nx,offset", [(40, 40, 0), (700, 1101, 0), (1030, 1030, 1), (2050, 2050, 0)])
 def test_ingest_sources_bit_exact(solver, ny, nx, offset):
     """The grid ingest (nonzero counts per Morton tile of 64 x 32 nodes in groups of tiles, then emission of
@@ -373,6 +396,9 @@ def test_error_paths_leave_output_untouched(solver):
     with pytest.raises(pp.PPError) as e:
         solver.solve_grid(f, h, np.concatenate([tx[:-1], [2.0]]), ty, out=out)
     assert e.value.status == -2 and np.all(out == 7.0)
+    with pytest.raises(pp.PPError) as e:  # a non-finite target coordinate
+        solver.solve_grid(f, h, tx, np.concatenate([ty[:-1], [np.nan]]), out=out)
+    assert e.value.status == -1 and np.all(out == 7.0)
     bad = f.copy()
     bad[3, 4] = np.nan
     with pytest.raises(pp.PPError) as e:
