@@ -9,11 +9,10 @@
 
 namespace pp {
 
-// One wave packs source leaf sleaves[wid].
-__device__ inline void pack_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
-                                 const uint32_t* __restrict__ ij, const double* __restrict__ w64,
-                                 float* __restrict__ s32, int64_t stride, double* __restrict__ leaf_w) {
-  const int c = sleaves[wid];
+// One wave packs source leaf c.
+__device__ inline void pack_leaf_cell(int c, int lane, const TreeArrays& t, int D, const uint32_t* __restrict__ ij,
+                                      const double* __restrict__ w64, float* __restrict__ s32, int64_t stride,
+                                      double* __restrict__ leaf_w) {
   const int sh = D - t.lvl[c];
   const int cx = t.ix[c] << sh, cy = t.iy[c] << sh;
   const int sb = t.sb[c], se = t.se[c];
@@ -30,6 +29,13 @@ __device__ inline void pack_leaf(int wid, int lane, const TreeArrays& t, const i
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (lane == 0) leaf_w[c] = acc;
+}
+
+// One wave packs source leaf sleaves[wid].
+__device__ inline void pack_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
+                                 const uint32_t* __restrict__ ij, const double* __restrict__ w64,
+                                 float* __restrict__ s32, int64_t stride, double* __restrict__ leaf_w) {
+  pack_leaf_cell(sleaves[wid], lane, t, D, ij, w64, s32, stride, leaf_w);
 }
 
 // x0 + (i + 1/2) h without contraction: the node coordinate exactly as the
@@ -85,12 +91,10 @@ __device__ inline void prep_leaf(int wid, int lane, const TreeArrays& t, const i
 
 // One wave per source leaf: offsets from the leaf corner in units of u, FP32
 // (with the weight) and FP64, and the FP64 leaf weight in a fixed order.
-__device__ inline void pack_point_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
-                                       const double* __restrict__ xs, const double* __restrict__ ys,
-                                       const double* __restrict__ ws, double x0, double y0, double u,
-                                       float* __restrict__ s32, int64_t stride, double2* __restrict__ s64,
-                                       double* __restrict__ leaf_w) {
-  const int c = sleaves[wid];
+__device__ inline void pack_point_cell(int c, int lane, const TreeArrays& t, int D, const double* __restrict__ xs,
+                                       const double* __restrict__ ys, const double* __restrict__ ws, double x0,
+                                       double y0, double u, float* __restrict__ s32, int64_t stride,
+                                       double2* __restrict__ s64, double* __restrict__ leaf_w) {
   const int sh = D - t.lvl[c];
   const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
   const int sb = t.sb[c], se = t.se[c];
@@ -108,6 +112,13 @@ __device__ inline void pack_point_leaf(int wid, int lane, const TreeArrays& t, c
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
   if (lane == 0) leaf_w[c] = acc;
+}
+__device__ inline void pack_point_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
+                                       const double* __restrict__ xs, const double* __restrict__ ys,
+                                       const double* __restrict__ ws, double x0, double y0, double u,
+                                       float* __restrict__ s32, int64_t stride, double2* __restrict__ s64,
+                                       double* __restrict__ leaf_w) {
+  pack_point_cell(sleaves[wid], lane, t, D, xs, ys, ws, x0, y0, u, s32, stride, s64, leaf_w);
 }
 
 // One wave per target leaf: offsets from the leaf corner (the same FP64
@@ -233,6 +244,15 @@ __device__ inline void run_leaf_pass(const LeafPass& lp, int blk) {
   }
 }
 
+// One wave packs source leaf c, for either kind of source.
+__device__ inline void run_pack_cell(const LeafPass& lp, int c, int lane) {
+  if (lp.kind == 1)
+    pack_leaf_cell(c, lane, lp.t, lp.D, lp.ga.ij, lp.ga.w64, lp.ga.s32, lp.ga.stride, lp.ga.leaf_w);
+  else if (lp.kind == 2)
+    pack_point_cell(c, lane, lp.t, lp.D, lp.pa.fr.xs, lp.pa.fr.ys, lp.pa.fr.ws, lp.pa.fr.x0, lp.pa.fr.y0, lp.pa.fr.u,
+                    lp.pa.s32, lp.pa.stride, lp.pa.s64, lp.pa.leaf_w);
+}
+
 // Host side: the descriptor of the passes for one solve.
 LeafPass leaf_pass_grid(TreeArrays t, int D, const int* sleaves, int nsleaves, const uint32_t* ij, const double* w64,
                         float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
@@ -244,5 +264,15 @@ LeafPass leaf_pass_points(TreeArrays t, int D, double x0, double y0, double u, c
                           double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                           const double* ty, const int* perm, float2* rel32, double2* rel64, int* tleaf,
                           double* self_w);
+// The passes as a launch of their own.
+void leaf_pass_launch(const LeafPass& lp, hipStream_t s);
+// The same passes with the source packing left out (target preparation only).
+LeafPass leaf_pass_prep_only(const LeafPass& lp);
+// Packing of only the source leaves that the near field reads: those in the
+// list (list_src + list_off[A], list_cnt[A] entries) of some target leaf A of
+// tleaves, each packed once (claim: ncells ints, all zero before).  lp: the
+// descriptor of the full passes.
+void pack_listed(const LeafPass& lp, const int* tleaves, int ntleaves, const int* list_off, const int* list_cnt,
+                 const int* list_src, int ncells, int* claim, hipStream_t s);
 
 }  // namespace pp

@@ -56,7 +56,7 @@ enum BufId {
   B_CHCNT, B_CHOFF, B_ITEMS, B_LEAFW, B_REL32, B_REL64, B_TGTLEAF, B_SELFD, B_MP, B_LOC, B_FAR, B_NEAR, B_OWNLOC, B_SPLIT, B_REC, B_PCOUNT,
   B_DSS, B_DTS, B_DFLAG, B_DOFF, B_PSX, B_PSY, B_PW, B_PXS, B_PYS, B_PWS, B_SPERM2, B_SKEY2, B_BOXP, B_BOXC,
   B_S64, B_SELFW, B_FP, B_FNX, B_FNY, B_FDS, B_FSEG, B_FDFX, B_FDFY, B_FOUT,
-  B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY, B_LOGT,
+  B_AU, B_AV, B_ACHI, B_AUS, B_AVS, B_AF, B_VLX, B_VLY, B_LOGT, B_CLAIM,
   B_COUNT
 };
 
@@ -137,6 +137,9 @@ struct pp_ctx {
   // instead of replaying it from a graph (PP_DIRECT_ISSUE=0 replays it)
   int direct_issue = 1;
   int dense_levels = 9;      // levels built from the dense prefix table (PP_DENSE_LEVELS overrides, 0..9)
+  // in the directly issued schedule, pack only the source leaves some near-field list holds (PP_LAZY_PACK=0:
+  // every source leaf)
+  bool lazy_pack = true;
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only, 16 + phase that phase's launches
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
@@ -795,7 +798,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   double *leaf_w = nullptr, *selfd = nullptr, *selfw = nullptr, *far = nullptr, *near = nullptr;
   float2* rel32 = nullptr;
   double2 *rel64 = nullptr, *s64 = nullptr, *mp = nullptr, *loc = nullptr, *own = nullptr;
-  int* tgtleaf = nullptr;
+  int *tgtleaf = nullptr, *claim = nullptr;
   long long* pcount = nullptr;
   reserve(c, [&] {
     // the tree-code variant lists per target leaf (M2P cells, P2P leaves); the
@@ -818,6 +821,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     far = direct ? nullptr : ensure<double>(c, B_FAR, m * far_parts);
     near = ensure<double>(c, B_NEAR, (int64_t)nparts * m);
     pcount = ensure<long long>(c, B_PCOUNT, (int64_t)nparts * std::max(ntl, 1));
+    claim = ensure<int>(c, B_CLAIM, ncells);
   });
   if (resident && exact_lists) {  // the retained two-pass lists
     m2l_src = (int*)c.bufs[B_M2LSRC].p;
@@ -1050,18 +1054,38 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // stream's launches, and the upward pass runs beside the list building
   // (kernels that leave most of the GPU idle) rather than beside the near
   // field, which fills it.
+  // Lazy packing (directly issued schedule, lists on the device, target
+  // leaves few beside the source leaves): the list launch prepares the
+  // targets only, and a launch after it packs just the source leaves that
+  // some near-field list holds (at 4096^2 with surface targets, a fraction of
+  // them), so that less traffic competes with the upward pass.  With targets
+  // spread over the whole grid nearly every leaf is listed, and packing them
+  // all beside the list building is faster.
+  const bool lazy = c.lazy_pack && !direct && (fused || resident) && 4 * (int64_t)ntl < nsl;
+  const LeafPass lpass_prep = leaf_pass_prep_only(lpass);
+  auto do_pack_listed = [&](hipStream_t q) {
+    pack_listed(lpass, tleaves, ntl, op2p, cp2p, p2p_src, ncells, claim, q);
+  };
   auto fork_work = [&] {
     if (fused) {
-      // one launch: the lists, with the packing in extra workgroups
+      // one launch: the lists, with the packing (or the target preparation) in extra workgroups
+      if (lazy) fill_i32(claim, 0, ncells, ss);
       tbegin(PP_PHASE_LISTS, ss);
-      do_lists(ss, &lpass);
+      do_lists(ss, lazy ? &lpass_prep : &lpass);
       tend(PP_PHASE_LISTS, ss);
       do_p2m();
+      if (lazy) do_pack_listed(ss);
       do_m2m();
       return;
     }
     tbegin(PP_PHASE_PACK, ss);
-    do_pack_prep(ss);
+    if (lazy) {  // resident: the retained lists are there already
+      fill_i32(claim, 0, ncells, ss);
+      leaf_pass_launch(lpass_prep, ss);
+      do_pack_listed(ss);
+    } else {
+      do_pack_prep(ss);
+    }
     tend(PP_PHASE_PACK, ss);
     do_p2m();
     tbegin(PP_PHASE_LISTS, ss);
@@ -1311,6 +1335,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DIRECT_ISSUE")) c->direct_issue = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
+  if (const char* e = std::getenv("PP_LAZY_PACK")) c->lazy_pack = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities

@@ -407,7 +407,56 @@ __global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs
   }
 }
 
+// Packing of the listed source leaves: one wave per target leaf claims the
+// leaves of its list that no wave has claimed yet (claim[B] 0 -> 1) and packs
+// each one it claimed, with all lanes.  (Queueing the claimed leaves for a
+// second, wide launch was measured slower at 4096^2: that launch fills the
+// compute units the upward pass is using.)
+__global__ __launch_bounds__(256) void k_pack_listed(LeafPass lp, const int* __restrict__ tleaves, int ntleaves,
+                                                     const int* __restrict__ list_off, const int* __restrict__ list_cnt,
+                                                     const int* __restrict__ list_src, int ncells,
+                                                     int* __restrict__ claim) {
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+  if (wid >= ntleaves) return;
+  const int lane = threadIdx.x % kWave;
+  const int A = tleaves[wid];
+  const int nb = list_cnt[A];
+  const int* lst = list_src + list_off[A];
+  for (int e0 = 0; e0 < nb; e0 += kWave) {
+    const int e = e0 + lane;
+    const int B = e < nb ? lst[e] : -1;
+    const bool mine = (unsigned)B < (unsigned)ncells && atomicExch(&claim[B], 1) == 0;
+    uint64_t m = __ballot(mine);
+    while (m) {  // the leaves this wave claimed, one at a time
+      const int l = __builtin_ctzll(m);
+      m &= m - 1;
+      run_pack_cell(lp, __shfl(B, l, kWave), lane);
+    }
+  }
+}
+
+// The per-leaf passes of a descriptor as a launch of their own.
+__global__ __launch_bounds__(256) void k_leaf_pass(LeafPass lp) { run_leaf_pass(lp, (int)blockIdx.x); }
+
 }  // namespace
+
+void leaf_pass_launch(const LeafPass& lp, hipStream_t s) {
+  const int g = lp.pack_blocks + lp.prep_blocks;
+  if (g > 0) k_leaf_pass<<<(unsigned)g, 256, 0, s>>>(lp);
+}
+
+LeafPass leaf_pass_prep_only(const LeafPass& lp) {
+  LeafPass q = lp;
+  q.pack_blocks = 0;
+  return q;
+}
+
+void pack_listed(const LeafPass& lp, const int* tleaves, int ntleaves, const int* list_off, const int* list_cnt,
+                 const int* list_src, int ncells, int* claim, hipStream_t s) {
+  if (ntleaves <= 0) return;
+  k_pack_listed<<<(unsigned)((ntleaves + 3) / 4), 256, 0, s>>>(lp, tleaves, ntleaves, list_off, list_cnt, list_src,
+                                                                 ncells, claim);
+}
 
 static unsigned level_blocks(int64_t max_cells) {
   const int64_t items = 4 * std::max<int64_t>(max_cells, 1);

@@ -667,3 +667,36 @@ def test_graph_replay_matches_eager(monkeypatch, near_stream, direct_issue, list
     finally:
         fast.close()
         eager.close()
+
+
+@pytest.mark.parametrize("method,precision", [("fmm", "mixed"), ("fmm", "fp64"), ("treecode", "mixed")])
+def test_lazy_packing_matches_full(monkeypatch, method, precision):
+    """Few targets beside many source leaves (a 512^2 vortex source, 600 targets on an ellipse): the near
+    field's source leaves are packed only when some list holds them (claimed once, queued, packed one wave
+    each).  The cold and the resident solve equal, bit for bit, those of a context that packs every leaf."""
+    import paper_1610_04398_amd as pp
+    n = 512
+    g = G.GridSpec(n, n, 1.0 / n)
+    f = G.vortex_source(g, 31, 24)
+    tx, ty = G.ellipse_targets(600)
+    kw = dict(p=12, theta=0.5, leaf_max=64, precision=precision, method=method)
+    monkeypatch.setenv("PP_LAZY_PACK", "0")
+    full = pp.Solver(0)
+    monkeypatch.delenv("PP_LAZY_PACK")
+    lazy = pp.Solver(0)
+    try:
+        fd, txd, tyd = to_dev(f, tx, ty)
+        a = to_host(lazy.solve_grid(fd, g.h, txd, tyd, **kw))
+        b = to_host(full.solve_grid(fd, g.h, txd, tyd, **kw))
+        assert np.array_equal(a, b)
+        st = lazy.stats()
+        assert 4 * st["ntgt_leaves"] < st["nsrc_leaves"]  # the lazy schedule is the one taken
+        f2d = to_dev(1.3 * f)[0]
+        a = to_host(lazy.solve_grid_resident(f2d, txd, tyd))
+        b = to_host(full.solve_grid_resident(f2d, txd, tyd))
+        assert np.array_equal(a, b)
+        ref = direct.direct_grid(1.3 * f, g.h, tx, ty)
+        assert rel_l2(a, ref) < (1e-6 if precision == "mixed" else 1e-8)
+    finally:
+        lazy.close()
+        full.close()
