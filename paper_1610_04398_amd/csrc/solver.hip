@@ -140,6 +140,7 @@ struct pp_ctx {
   // in the directly issued schedule, pack only the source leaves some near-field list holds (PP_LAZY_PACK=0:
   // every source leaf)
   bool lazy_pack = true;
+  bool resident_graph = false;  // PP_RESIDENT_GRAPH=1: a resident solve replayed as one graph
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only, 16 + phase that phase's launches
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
@@ -147,6 +148,7 @@ struct pp_ctx {
   // the same inputs and replayed while they stay the same (PP_GRAPHS=0 disables)
   bool graphs = true;
   uint64_t gen = 0;  // bumped by every device (re)allocation; part of every graph key
+  uint64_t res_gen = 0;  // bumped whenever a solve keeps its tree for resident solves
   // work of calls on the null stream runs on this blocking stream (ordered with the
   // null stream like the null stream itself), which can be captured
   hipStream_t own_stream = nullptr;
@@ -160,10 +162,15 @@ struct pp_ctx {
     std::vector<uint64_t> key;
     int seen = 0;
     hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;  // last use (a counter), to pick the slot to replace
   };
-  // 0: up to the tree read-back; 1: the rest (not replayed in timing mode 2)
-  static constexpr int kSegments = 2;
+  // 0: up to the tree read-back; 1: the rest (not replayed in timing mode 2);
+  // 2..5: whole resident solves, one per set of input and output buffers (a
+  // caller that alternates between buffers replays a graph for each)
+  static constexpr int kResidentSlots = 4;
+  static constexpr int kSegments = 2 + kResidentSlots;
   Segment seg[kSegments];
+  uint64_t seg_clock = 0;
   uint64_t budget = 0;
   size_t held = 0;
   DevBuf bufs[B_COUNT];
@@ -423,6 +430,23 @@ void run_segment(pp_ctx& c, int which, bool allowed, std::vector<uint64_t> key, 
   }
   (void)hipGraphDestroy(graph);
   HIPCHK(hipGraphLaunch(g.exec, s));
+}
+
+// The resident-solve graph slot for key (with the allocation generation
+// appended, as run_segment keys it): the slot that holds it, else the one
+// used least recently.
+int resident_slot(pp_ctx& c, std::vector<uint64_t> key) {
+  key.push_back(c.gen);
+  int pick = 2;
+  for (int i = 2; i < pp_ctx::kSegments; ++i) {
+    if (c.seg[i].key == key) {
+      pick = i;
+      break;
+    }
+    if (c.seg[i].used < c.seg[pick].used) pick = i;
+  }
+  c.seg[pick].used = ++c.seg_clock;
+  return pick;
 }
 
 int root_exponent(int nx, int ny) {
@@ -708,9 +732,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                    direct ? nullptr : &rec0, s);
   };
   const int seq1 = published_seq(c) + 1;
-  if (resident) {
-    // the retained tree: new weights for its sources, and the checks that it
-    // still fits (no new nonzero node, every target in its finest cell)
+  // the retained tree: new weights for its sources, and the checks that it
+  // still fits (no new nonzero node, every target in its finest cell); no
+  // round trip follows, so it is issued with the second segment below
+  auto resident_first = [&] {
     mark(PP_PHASE_INGEST);
     fill_i32(misc, 0, kMiscInts, s);
     tbegin(PP_PHASE_INGEST, s);
@@ -721,7 +746,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     resident_targets(tx_d, ty_d, m, tperm, tkey, x0, y0, unit, k, misc + M_FLAGS, s);
     tend(PP_PHASE_SORT, s);
     mark(PP_PHASE_TREE);
-  } else run_segment(c, 0, replayable, key1, s, [&] {
+  };
+  if (!resident) run_segment(c, 0, replayable, key1, s, [&] {
     mark(PP_PHASE_INGEST);
     if (src.grid) fill_i32(misc, 0, kMiscInts, s);  // scattered input: cleared before its bounding box
     tbegin(PP_PHASE_INGEST, s);
@@ -1095,7 +1121,32 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   };
 
   const int seq2 = published_seq(c) + 1;
-  if (issue2) {
+  // With PP_RESIDENT_GRAPH=1 a resident solve with device inputs and output,
+  // untimed, is one graph: its first launches and the whole second segment,
+  // captured on the second call with the same retained tree and buffers and
+  // replayed after that (the round trip at the end is its only host
+  // synchronisation; up to four sets of buffers keep a graph each).  Off by
+  // default: at 4096^2 the replay was 8 % slower than issuing the launches
+  // (3,449 against 3,766 solves/s, A/B), the graph's executor starting the
+  // side stream's branch before the upward pass.
+  const bool resident_graph = resident && c.resident_graph && c.profiling == 0 && ss != s && f_d == src.f &&
+                              tx_d == tx && ty_d == ty && out_on_device;
+  std::vector<uint64_t> key3;
+  if (resident_graph)
+    key3 = {c.res_gen, bits(f_d), bits(tx_d), bits(ty_d), bits(out_d), (uint64_t)m, (uint64_t)lazy,
+            (uint64_t)c.frontier_boost, (uint64_t)nparts};
+  auto resident_issue = [&](auto&& second) {
+    if (resident_graph) {
+      run_segment(c, resident_slot(c, key3), true, key3, s, [&] {
+        resident_first();
+        second();
+      });
+    } else {
+      if (resident) resident_first();
+      second();
+    }
+  };
+  if (issue2) resident_issue([&] {
     // The schedule of a call with the near field on its own stream (bracketed
     // by events in timing mode 2), every launch of this segment issued directly (a
     // captured graph drops event records, and replaying the pieces around the
@@ -1125,8 +1176,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     do_downward();
     signal(c.ev_join, ss, s);
     do_finalize();
-  } else if (ss == s) {
+  });
+  else if (ss == s) {
     // one stream, phases in order (timing mode 1, or the side stream disabled)
+    if (resident) resident_first();
     run_segment(c, 1, replayable, key2, s, [&] {
       mark(PP_PHASE_LISTS);
       do_lists(s, nullptr);
@@ -1142,6 +1195,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // Captured in phase order: the graph runs the side branch's kernels before
     // the upward pass whatever the order of capture, and a fork at the start of
     // the segment (two root nodes) was measured to delay the first kernels.
+    if (resident) resident_first();
     if (lists_early) do_lists(s, nullptr);
     run_segment(c, 1, replayable, key2, s, [&] {
       do_pack_prep(s);
@@ -1203,6 +1257,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   if (src.grid && !direct && !resident && !c.arena) {
     Resident& r = c.res;
     r.valid = true;
+    ++c.res_gen;
     r.nx = nx;
     r.ny = ny;
     r.x0 = x0;
@@ -1336,6 +1391,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_DIRECT_ISSUE")) c->direct_issue = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
   if (const char* e = std::getenv("PP_LAZY_PACK")) c->lazy_pack = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PP_RESIDENT_GRAPH")) c->resident_graph = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities

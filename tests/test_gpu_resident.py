@@ -165,3 +165,46 @@ def test_resident_multi_group_grid(pp):
     finally:
         s.close()
         ref.close()
+
+
+@pytest.mark.parametrize("method", ["fmm", "treecode"])
+def test_resident_graph_replay(pp, monkeypatch, method):
+    """With PP_RESIDENT_GRAPH=1, repeated resident solves on the same device buffers (f, targets, output
+    changed in place) run as one captured graph from the third call with those buffers on (first launches
+    and the whole second segment, no host round trip inside); two sets of buffers used in turn keep a graph
+    each.  Each of eight calls, with eager device work between them, equals a fresh solve bit for bit; a
+    refused call (a node outside the tree turned nonzero) leaves the output alone and the next one replays
+    again."""
+    import torch
+    monkeypatch.setenv("PP_RESIDENT_GRAPH", "1")
+    s = pp.Solver(0)
+    monkeypatch.delenv("PP_RESIDENT_GRAPH")
+    ref = pp.Solver(0)
+    try:
+        g, f, tx, ty, rng = _case(seed=6)
+        kw = dict(p=12, theta=0.5, leaf_max=32, precision="mixed", method=method)
+        sets = [to_dev(f, tx, ty) + [torch.empty(tx.size, dtype=torch.float64, device="cuda")] for _ in range(2)]
+        s.solve_grid(sets[0][0], g.h, sets[0][1], sets[0][2], **kw)
+        nz = torch.as_tensor(f != 0.0, device="cuda")
+        zero = int(np.argwhere(f.ravel() == 0.0)[0, 0])
+        for it in range(8):
+            fd, txd, tyd, out = sets[it % 2]
+            fd.copy_(torch.as_tensor(f * (1.0 + 0.3 * it), device="cuda"))
+            fd.add_(0.1 * torch.randn_like(fd) * nz)
+            mx, my = _moved_within_cells(tx, ty, g.h, rng)
+            txd.copy_(torch.as_tensor(mx, device="cuda"))
+            tyd.copy_(torch.as_tensor(my, device="cuda"))
+            torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+            if it == 6:
+                fd.view(-1)[zero] = 1.0
+                out.fill_(7.0)
+                with pytest.raises(pp.PPError):
+                    s.solve_grid_resident(fd, txd, tyd, out=out)
+                assert bool(torch.all(out == 7.0))
+                fd.view(-1)[zero] = 0.0
+            s.solve_grid_resident(fd, txd, tyd, out=out)
+            want = to_host(ref.solve_grid(fd, g.h, txd, tyd, **kw))
+            assert np.array_equal(to_host(out), want), it
+    finally:
+        s.close()
+        ref.close()
