@@ -191,6 +191,24 @@ pp_status pp_solve_grid_noalloc(pp_ctx* ctx, int32_t nx, int32_t ny, double x0, 
 pp_status pp_solve_grid_resident(pp_ctx* ctx, const double* f, const double* tx, const double* ty, double* p_out,
                                  void* hip_stream);
 
+/* Several solves of one grid geometry at once (Appendix A's sum for each,
+ * eq. greenSum): request r has its own source f[r] (nx*ny), m[r] targets
+ * (tx[r], ty[r]) and output p_out[r]; nx, ny, x0, y0, h and params are
+ * shared.  The requests are solved as one forest in one set of launches: each
+ * request's grid occupies its own cell of a few extra top levels (4^levels >=
+ * nreq), cells above that level are always split and no interaction crosses
+ * between requests, so each request's tree, lists and arithmetic are those of
+ * its lone pp_solve_grid, and p_out[r] is bitwise that solve's result.  For
+ * serving many requests of one shape (the launches and their latency are
+ * shared).  nreq 1..16 (1 is pp_solve_grid); every pointer device memory
+ * (else PP_ERR_ARG); grids of 33 to 65536 nodes a side with the forest at
+ * most 65536 nodes wide; multipole method only (PP_ERR_ARG otherwise); a
+ * request may have no targets.  Keeps no tree for pp_solve_grid_resident. */
+pp_status pp_solve_grid_batch(pp_ctx* ctx, int32_t nreq, int32_t nx, int32_t ny, double x0, double y0, double h,
+                              const double* const* f, const int64_t* m, const double* const* tx,
+                              const double* const* ty, const pp_params* params, double* const* p_out,
+                              void* hip_stream);
+
 /* All-pairs direct sum of eq. greenSum on the GPU (no expansions): the
  * baseline the tree-code is measured against.  Uses params->precision,
  * params->self_mode and params->leaf_max (tiling); p and theta are ignored. */

@@ -36,6 +36,7 @@ from ._binding import (  # noqa: F401  (same names as the C ABI)
     pp_solve_grid,
     pp_solve_grid_noalloc,
     pp_solve_grid_resident,
+    pp_solve_grid_batch,
     pp_pressure_source,
     pp_solve_points,
     pp_surface_forces,
@@ -138,6 +139,42 @@ class Solver:
         output only); see pp_solve_grid_noalloc in include/pp.h."""
         prm = make_params(p, theta, leaf_max, precision, self_mode, method)
         return self._run(pp_solve_grid_noalloc, f, h, tx, ty, x0, y0, prm, out, stream)
+
+    def solve_grid_batch(self, fs, h, txs, tys, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",
+                         self_mode="skip", outs=None, stream=None):
+        """Several solves of one grid geometry as one forest (device tensors only): fs[r] (ny, nx), targets
+        txs[r], tys[r]; returns the outputs, each bitwise its lone solve_grid's; see pp_solve_grid_batch in
+        include/pp.h."""
+        import torch
+        prm = make_params(p, theta, leaf_max, precision, self_mode, "fmm")
+        n = len(fs)
+        if not (len(txs) == len(tys) == n) or n < 1:
+            raise ValueError("one f, tx and ty per request")
+        shape = tuple(fs[0].shape)
+        if len(shape) != 2 or any(tuple(f.shape) != shape for f in fs):
+            raise ValueError("every f must have the same shape (ny, nx)")
+        ny, nx = shape
+        ms = []
+        for tx, ty in zip(txs, tys):
+            if tx.numel() != ty.numel():
+                raise ValueError("tx and ty differ in length")
+            ms.append(int(tx.numel()))
+        if outs is None:
+            outs = [torch.empty(mm, dtype=torch.float64, device=fs[0].device) for mm in ms]
+        keep = [_ptr(a, "array") for a in (*fs, *txs, *tys, *outs)]
+        fp = [k[0] for k in keep[:n]]
+        xp = [k[0] for k in keep[n:2 * n]]
+        yp = [k[0] for k in keep[2 * n:3 * n]]
+        op = [k[0] for k in keep[3 * n:]]
+        if stream is None:
+            stream = torch.cuda.current_stream(fs[0].device).cuda_stream
+        st = pp_solve_grid_batch(self._ctx, nx, ny, float(x0), float(y0), float(h), fp, ms, xp, yp, prm, op,
+                                 stream)
+        self._resident_shape = None
+        if st != B.PP_OK:
+            raise PPError(st, f"{pp_status_string(st)}: {pp_last_error(self._ctx)}")
+        del keep
+        return outs
 
     def solve_grid_resident(self, f, tx, ty, out=None, stream=None):
         """Pressure with the tree of the last solve_grid kept (new f with no new nonzero node, targets in

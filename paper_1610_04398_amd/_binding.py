@@ -36,7 +36,8 @@ DOUBLE_ARRAYS = {"MULTIPOLE", "LOCAL", "FAR", "NEAR", "LEAF_WNEAR"}
 UNSIGNED_ARRAYS = {"SRC_KEY", "TGT_KEY", "SRC_INDEX"}
 
 #: C symbols the header declares (checked by the CPU test suite)
-EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_solve_grid_noalloc", "pp_solve_grid_resident", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
+EXPORTED = ("pp_create", "pp_destroy", "pp_solve_grid", "pp_solve_grid_noalloc", "pp_solve_grid_resident",
+            "pp_solve_grid_batch", "pp_direct_grid", "pp_solve_points", "pp_direct_points",
             "pp_surface_forces", "pp_pressure_source", "pp_viscous_forces", "pp_get_stats", "pp_set_profiling", "pp_debug_copy", "pp_status_string", "pp_last_error",
             "pp_server_create", "pp_server_submit", "pp_server_wait", "pp_server_cancel", "pp_server_destroy",
             "pp_server_last_error", "pp_server_device_bytes", "pp_footprint_estimate")
@@ -104,6 +105,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.pp_solve_grid_noalloc.restype = i32
     lib.pp_solve_grid_resident.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.pp_solve_grid_resident.restype = i32
+    lib.pp_solve_grid_batch.argtypes = [vp, i32, i32, i32, f64, f64, f64, vp, vp, vp, vp, ctypes.POINTER(pp_params),
+                                        vp, vp]
+    lib.pp_solve_grid_batch.restype = i32
     lib.pp_direct_grid.argtypes = solve_args
     lib.pp_direct_grid.restype = i32
     points_args = [vp, i64, vp, vp, vp, i64, vp, vp, ctypes.POINTER(pp_params), vp, vp]
@@ -182,6 +186,15 @@ def pp_solve_grid_noalloc(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, para
 
 def pp_solve_grid_resident(ctx, f_ptr, tx_ptr, ty_ptr, out_ptr, stream) -> int:
     return lib().pp_solve_grid_resident(ctx, f_ptr, tx_ptr, ty_ptr, out_ptr, stream)
+
+
+def pp_solve_grid_batch(ctx, nx, ny, x0, y0, h, f_ptrs, ms, tx_ptrs, ty_ptrs, params: pp_params, out_ptrs,
+                        stream) -> int:
+    """Pointer lists become the C arrays of pointers and counts."""
+    n = len(f_ptrs)
+    arr = lambda v: (ctypes.c_void_p * n)(*v)
+    return lib().pp_solve_grid_batch(ctx, n, nx, ny, x0, y0, h, arr(f_ptrs), (ctypes.c_int64 * n)(*ms),
+                                     arr(tx_ptrs), arr(ty_ptrs), ctypes.byref(params), arr(out_ptrs), stream)
 
 
 def pp_direct_grid(ctx, nx, ny, x0, y0, h, f_ptr, m, tx_ptr, ty_ptr, params: pp_params, out_ptr, stream) -> int:

@@ -440,7 +440,7 @@ constexpr int kDownLanes = 16;
 template <int PM>
 __global__ __launch_bounds__(kWave) void k_downward(TreeView t, const int* __restrict__ tcells, int n, int p,
                                                     const double2* __restrict__ own, double2* __restrict__ loc,
-                                                    const int* __restrict__ dense_off, int dense_levels) {
+                                                    const int* __restrict__ dense_off, int dense_levels, int top) {
   __shared__ double2 red[kWave][PM + 1];
   const int lane = threadIdx.x;
   const int sub = lane % kDownLanes;
@@ -457,7 +457,10 @@ __global__ __launch_bounds__(kWave) void k_downward(TreeView t, const int* __res
   cplx acc[PM + 1];
 #pragma unroll
   for (int k = 0; k <= PM; ++k) acc[k] = {0.0, 0.0};
-  for (int a = sub; a <= lc; a += kDownLanes) {
+  // ancestors from level top (a forest's request roots; 0 otherwise): the
+  // levels above it have no interactions, and starting there gives each
+  // request's cells the lane assignment (and sums) of its lone solve
+  for (int a = top + sub; a <= lc; a += kDownLanes) {
     if (a == lc) {
 #pragma unroll
       for (int k = 0; k <= PM; ++k)
@@ -727,10 +730,10 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
 }
 
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, const int* dense_off,
-              int dense_levels, hipStream_t s) {
+              int dense_levels, int top, hipStream_t s) {
   if (n <= 0) return;
   const unsigned g = (unsigned)((n + kWave / kDownLanes - 1) / (kWave / kDownLanes));
-  PP_DISPATCH(p, k_downward, g, kWave, s, t, tcells, n, p, own, loc, dense_off, dense_levels);
+  PP_DISPATCH(p, k_downward, g, kWave, s, t, tcells, n, p, own, loc, dense_off, dense_levels, top);
 }
 
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, c
                                                          const double* __restrict__ self_w,
                                                          const double* __restrict__ self_logd, double lnh,
                                                          int self_mode, const int* __restrict__ flags,
-                                                         double* __restrict__ out, FinalizeTotals tot, FarEval fe) {
+                                                         double* __restrict__ out, FinalizeTotals tot, FarEval fe,
+                                                         GridBatch bt) {
   const int64_t tot_n = std::max<int64_t>(tot.pairs ? tot.nwaves : 0, tot.cnt_m ? tot.ncells : 0);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((int64_t)blockIdx.x * kFinBlock < tot_n) {  // uniform per workgroup
@@ -97,18 +98,24 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, c
       v += w * (lg - lnh);
     }
   }
-  out[perm[k]] = v * kInv2Pi;
+  const int o = perm[k];
+  if (bt.nreq) {  // a forest of requests: target o - toff[r] of request r
+    const int r = batch_request(bt, o);
+    bt.out[r][o - bt.toff[r]] = v * kInv2Pi;
+  } else {
+    out[o] = v * kInv2Pi;
+  }
 }
 }  // namespace
 
 void finalize(int64_t m, int nparts, const int* perm, double* far, const double* near_sum,
               const double* self_w, const double* self_logd, double h, int self_mode, const int* flags, double* out,
-              const FinalizeTotals& tot, const FarEval& fe, hipStream_t s) {
+              const FinalizeTotals& tot, const FarEval& fe, const GridBatch* bt, hipStream_t s) {
   const int64_t tot_n = std::max<int64_t>(tot.pairs ? tot.nwaves : 0, tot.cnt_m ? tot.ncells : 0);
   const int64_t blocks = (std::max(m, tot_n) + kFinBlock - 1) / kFinBlock;
   if (blocks <= 0) return;
   k_finalize<<<(unsigned)blocks, kFinBlock, 0, s>>>(m, nparts, perm, far, near_sum, self_w, self_logd, log(h),
-                                                    self_mode, flags, out, tot, fe);
+                                                    self_mode, flags, out, tot, fe, bt ? *bt : GridBatch{});
 }
 
 }  // namespace pp

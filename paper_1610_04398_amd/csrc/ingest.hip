@@ -55,6 +55,28 @@ __device__ inline void load_pair(const double* __restrict__ f, int nx, int ny, i
 // Local Morton index of column x, row y inside a tile.
 __device__ inline uint32_t tile_index(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
 
+// Tile t of the (joint) Morton order: the grid it reads (null: an empty
+// forest cell), the tile's first node (i0, j0) in that grid, its first key
+// and the offset (vx, vy) of the grid's nodes in the joint index space.
+struct TileSrc {
+  const double* f;
+  int i0, j0;
+  uint32_t key0;
+  int vx, vy;
+};
+__device__ inline TileSrc tile_src(const double* f, int64_t t, const GridBatch& b) {
+  if (b.nreq == 0) {
+    const uint32_t m0 = (uint32_t)(t << kTileBits);
+    return {f, (int)compact_bits(m0), (int)compact_bits(m0 >> 1), m0, 0, 0};
+  }
+  const int64_t per = ((int64_t)1 << (2 * b.D)) >> kTileBits;  // tiles per request (b.D >= 6)
+  const int r = (int)(t / per);
+  const uint32_t m0 = (uint32_t)((t - (int64_t)r * per) << kTileBits);
+  return {r < b.nreq ? b.f[r] : nullptr, (int)compact_bits(m0), (int)compact_bits(m0 >> 1),
+          ((uint32_t)r << (2 * b.D)) | m0, (int)compact_bits((uint32_t)r) << b.D,
+          (int)compact_bits((uint32_t)r >> 1) << b.D};
+}
+
 // Tile counts.  Workgroup g counts the nonzero nodes of tiles [g G, g G + G)
 // two tiles at a time (eight row loads in flight per lane), then stores, per
 // tile, the count of the tiles before it in the group (tile_pre) and the group
@@ -62,7 +84,7 @@ __device__ inline uint32_t tile_index(uint32_t x, uint32_t y) { return spread_bi
 template <bool VEC>
 __global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __restrict__ f, int nx, int ny, int G,
                                                              int* __restrict__ tile_pre, int* __restrict__ grp,
-                                                             int* __restrict__ flags) {
+                                                             int* __restrict__ flags, GridBatch bt) {
   extern __shared__ int cnt[];  // G counts
   __shared__ int lds[kIngBlock / kWave + 1];
   const int g = blockIdx.x;
@@ -75,13 +97,12 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __rest
     double a[2][kPasses], b[2][kPasses];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const uint32_t m0 = (uint32_t)(((int64_t)g * G + q + u) << kTileBits);
-      const int i0 = (int)compact_bits(m0), j0 = (int)compact_bits(m0 >> 1);
-      const bool live = q + u < G;
+      const TileSrc ts = tile_src(f, (int64_t)g * G + q + u, bt);
+      const bool live = q + u < G && ts.f;
 #pragma unroll
       for (int s = 0; s < kPasses; ++s) {
         a[u][s] = b[u][s] = 0.0;
-        if (live) load_pair<VEC>(f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[u][s], &b[u][s]);
+        if (live) load_pair<VEC>(ts.f, nx, ny, ts.i0 + 2 * c, ts.j0 + r + s * kRowsPerPass, &a[u][s], &b[u][s]);
       }
     }
 #pragma unroll
@@ -129,13 +150,14 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
                                                             const int* __restrict__ grp, int G,
                                                             int* __restrict__ total_out, uint32_t* __restrict__ key,
                                                             uint32_t* __restrict__ ij, double* __restrict__ w64,
-                                                            int* __restrict__ starts, int sh) {
+                                                            int* __restrict__ starts, int sh, GridBatch bt) {
   __shared__ double wv[kIngTile];     // node values in Morton order, then the kept weights
   __shared__ uint16_t lix[kIngTile];  // local Morton index of each kept node
   __shared__ int lds[kIngBlock / kWave + 1];
   const int64_t t = blockIdx.x;
-  const uint32_t m0 = (uint32_t)(t << kTileBits);
-  const int i0 = (int)compact_bits(m0), j0 = (int)compact_bits(m0 >> 1);
+  const TileSrc ts = tile_src(f, t, bt);
+  const uint32_t m0 = ts.key0;
+  const int i0 = ts.i0, j0 = ts.j0;
   const int c = threadIdx.x % kPairLanes, r = threadIdx.x / kPairLanes;
   // offset of the tile: the group totals before its group (read first, so
   // that adding them up need not wait for the rows) and its prefix in the group
@@ -149,7 +171,10 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
   const int inner = tile_pre[t];
   double a[kPasses], b[kPasses];
 #pragma unroll
-  for (int s = 0; s < kPasses; ++s) load_pair<VEC>(f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
+  for (int s = 0; s < kPasses; ++s) {
+    a[s] = b[s] = 0.0;
+    if (ts.f) load_pair<VEC>(ts.f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
+  }
   int acc = 0;
 #pragma unroll
   for (int u = 0; u < kGroupReads; ++u) acc += gv[u];
@@ -192,7 +217,7 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
     const int64_t o = (int64_t)before + q;
     const uint32_t li = lix[q];
     key[o] = m0 | li;
-    ij[o] = (uint32_t)(i0 + (int)compact_bits(li)) | ((uint32_t)(j0 + (int)compact_bits(li >> 1)) << 16);
+    ij[o] = (uint32_t)(ts.vx + i0 + (int)compact_bits(li)) | ((uint32_t)(ts.vy + j0 + (int)compact_bits(li >> 1)) << 16);
     w64[o] = wv[q];
   }
   if (t == (int64_t)gridDim.x - 1 && threadIdx.x == 0) *total_out = before + total;
@@ -320,27 +345,40 @@ int64_t ingest_count_ints(int k) {
   return nt + nt / group_tiles(k);
 }
 
-void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s) {
+namespace {
+bool vec_ok_all(const double* f, int nx, const GridBatch* bt) {
+  if (!bt || bt->nreq == 0) return vec_ok(f, nx);
+  for (int r = 0; r < bt->nreq; ++r)
+    if (!vec_ok(bt->f[r], nx)) return false;
+  return true;
+}
+}  // namespace
+
+void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, const GridBatch* bt,
+                       hipStream_t s) {
   const int G = group_tiles(k);
   const int64_t nt = ingest_num_tiles(k);
   const unsigned ng = (unsigned)(nt / G);
   const size_t lds = (size_t)G * sizeof(int);
-  if (vec_ok(f, nx))
-    k_ingest_count<true><<<ng, kIngBlock, lds, s>>>(f, nx, ny, G, tile_cnt, tile_cnt + nt, flags);
+  const GridBatch b = bt ? *bt : GridBatch{};
+  if (vec_ok_all(f, nx, bt))
+    k_ingest_count<true><<<ng, kIngBlock, lds, s>>>(f, nx, ny, G, tile_cnt, tile_cnt + nt, flags, b);
   else
-    k_ingest_count<false><<<ng, kIngBlock, lds, s>>>(f, nx, ny, G, tile_cnt, tile_cnt + nt, flags);
+    k_ingest_count<false><<<ng, kIngBlock, lds, s>>>(f, nx, ny, G, tile_cnt, tile_cnt + nt, flags, b);
 }
 
 void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, int* total_out,
-                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s) {
+                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, const GridBatch* bt,
+                      hipStream_t s) {
   const int G = group_tiles(k);
   const int64_t nt = ingest_num_tiles(k);
-  if (vec_ok(f, nx))
+  const GridBatch b = bt ? *bt : GridBatch{};
+  if (vec_ok_all(f, nx, bt))
     k_ingest_emit<true><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_cnt, tile_cnt + nt, G, total_out,
-                                                            key, ij, w64, starts, sh);
+                                                            key, ij, w64, starts, sh, b);
   else
     k_ingest_emit<false><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_cnt, tile_cnt + nt, G, total_out,
-                                                             key, ij, w64, starts, sh);
+                                                             key, ij, w64, starts, sh, b);
 }
 
 void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* key,

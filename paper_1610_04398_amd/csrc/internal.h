@@ -10,6 +10,30 @@
 
 namespace pp {
 
+// Several grid requests of one geometry (nx, ny, x0, y0, h and parameters)
+// solved as one forest: request r's grid lies in cell r (Morton order) of
+// level `levels` of a root 2^levels times as wide, so its sources, targets
+// and cells keep their relative positions, keys and order; every cell above
+// that level is split, and no interaction crosses from one request's cell to
+// another's.  Each request's arithmetic is then that of its lone solve.
+constexpr int kMaxBatch = 16;
+struct GridBatch {
+  int nreq = 0;    // 0: a single solve
+  int levels = 0;  // levels above the requests' roots: 4^levels >= nreq
+  int D = 0;       // root exponent of one request's grid
+  const double* f[kMaxBatch] = {};
+  const double* tx[kMaxBatch] = {};
+  const double* ty[kMaxBatch] = {};
+  double* out[kMaxBatch] = {};
+  int64_t toff[kMaxBatch + 1] = {};  // request r's targets are [toff[r], toff[r + 1]) of the joint order
+};
+// The request of joint target index i.
+__host__ __device__ inline int batch_request(const GridBatch& b, int64_t i) {
+  int r = 0;
+  while (r + 1 < b.nreq && b.toff[r + 1] <= i) ++r;
+  return r;
+}
+
 // ---- scan.hip: exclusive prefix sums and fills --------------------------------
 size_t scan_temp_ints(int64_t n);
 // out[i] = sum_{j<i} in[j]; *total_dev = sum of all (may be null). in == out allowed.
@@ -39,13 +63,17 @@ int64_t ingest_num_tiles(int k);
 // it in its group, then one total per group.
 int64_t ingest_count_ints(int k);
 // First pass: tile counts (tile_cnt: ingest_count_ints(k) ints; no clearing needed).
-void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, hipStream_t s);
+// bt (may be null): a forest of requests (f is then unused; k is the forest's
+// root exponent).
+void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, const GridBatch* bt,
+                       hipStream_t s);
 // Second pass: the sources in Morton order (key, packed node index ij,
 // w = f h^2) and *total_out = their count.  starts (may be null): the source
 // range start of every Morton prefix of 2 * sh bits (cells of the dense table
 // sh levels above the finest).
 void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, int* total_out,
-                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, hipStream_t s);
+                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, const GridBatch* bt,
+                      hipStream_t s);
 // Resident solves (the tree of the last solve kept, new f on the same grid):
 // w = f h^2 of the n retained sources (keys key, tile counts tile_cnt of the
 // retained solve), in one pass over f; kFlagStale when a node outside them is
@@ -80,9 +108,10 @@ void radix_sort_pairs(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_t
                       int* temp, hipStream_t s);
 // Target keys (as target_keys) sorted with their indices (as radix_sort_pairs
 // over 2k bits); the first pass computes the keys while it counts digits.
+// bt (may be null): the joint targets of a forest (tx, ty and k unused).
 void target_keys_sorted(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
                         uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int* temp, int* flags,
-                        hipStream_t s);
+                        const GridBatch* bt, hipStream_t s);
 
 struct LeafPass;  // leafpass.h: per-leaf passes that ride on the list launch (lp may be null)
 // ---- tree.hip: top-down construction, per-leaf packing ------------------------------
@@ -105,13 +134,15 @@ struct TreeArrays {
 // when *deep becomes nonzero (a cell of level Ld holds more than leaf_max
 // sources or targets).  Gives the same cells and numbering as building the
 // levels one at a time from the root.  src_done: ss[0..4^Ld) was written by
-// the grid ingest.
+// the grid ingest.  Cells of the levels above split_above are split whatever
+// they hold (a forest's top levels; split_above <= Ld).
 int64_t tree_dense_cells(int Ld);
 // ints of scan_tmp that tree_dense_top needs (per-workgroup counts of the flags)
 int64_t tree_dense_part_ints(int Ld);
-void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
-                    const int* nsrc_dev, int src_done, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag,
-                    int* off, int* scan_tmp, int* total_slot, int* deep, int* flags, hipStream_t s);
+void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int split_above, int cap,
+                    const uint32_t* skey, const int* nsrc_dev, int src_done, const uint32_t* tkey, int ntgt, int* ss,
+                    int* ts, int* flag, int* off, int* scan_tmp, int* total_slot, int* deep, int* flags,
+                    hipStream_t s);
 // One level of the top-down construction, with no host round trip: the level's
 // cells are [ls[level], ls[level+1]) read on the device; its children are
 // appended and ls[level+2] is written.  max_cells bounds the level's size (grid
@@ -142,7 +173,7 @@ void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const
                     float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                     const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                     double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                    double* self_logd, hipStream_t s);
+                    double* self_logd, const GridBatch* bt, hipStream_t s);
 // Scattered-source counterpart, in one launch: FP32 records and FP64 offsets
 // (units of u) per source leaf; per target leaf the offsets, owning leaf, and
 // the weight of the sources that coincide exactly with the target.
@@ -163,10 +194,12 @@ void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int nt
                          int cap_p, int* flags, int tier_boost, const struct LeafPass* lp, hipStream_t s);
 // emit 0: counts only; 1: write at the exact offsets of a count pass;
 // 2: one pass, counts plus lists at cell * cap (kFlagListOverflow if a list
-// is longer than its capacity; its tail is then dropped).
+// is longer than its capacity; its tail is then dropped).  top > 0: a forest
+// whose requests' roots are at level top (the walk of a target cell starts
+// at its request's root; cells above that level get empty lists).
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
-                int* flags, int tier_boost, const struct LeafPass* lp, hipStream_t s);
+                int* flags, int tier_boost, int top, const struct LeafPass* lp, hipStream_t s);
 // The traversal frontier has three capacity tiers chosen from theta; tier_boost
 // raises it after an overflow.  True when no higher tier is left.
 bool frontier_at_top(int num, int den, int tier_boost);
@@ -202,8 +235,9 @@ void m2p(TreeView t, const int* tleaves, int n, const int* off, const int* cnt, 
 // (`own`) and its ancestors' (exact L2L shifts), one launch.
 // dense_off/dense_levels: the cell numbers of the tree build's dense prefix
 // table (levels 0..dense_levels), where ancestors are looked up directly.
+// top: the first ancestor level with interactions (a forest's request roots; 0 otherwise).
 void downward(TreeView t, const int* tcells, int n, int p, const double2* own, double2* loc, const int* dense_off,
-              int dense_levels, hipStream_t s);
+              int dense_levels, int top, hipStream_t s);
 // far[k] = Re sum_l c'_l u^l for every sorted target k (u: offset from its
 // leaf centre over the leaf side); fp32 != 0 evaluates in FP32.
 void l2p(TreeView t, int64_t m, const int* tleaf, int p, const double2* loc, const double2* rel64, int fp32,
@@ -276,7 +310,7 @@ struct FarEval {
 // coincidence throughout) the log of the distance to that node, -inf if exact.
 void finalize(int64_t m, int nparts, const int* perm, double* far, const double* near_sum,
               const double* self_w, const double* self_logd, double h, int self_mode, const int* flags, double* out,
-              const FinalizeTotals& tot, const FarEval& fe, hipStream_t s);
+              const FinalizeTotals& tot, const FarEval& fe, const GridBatch* bt, hipStream_t s);
 
 // ---- forces.hip: pressure forces on surfaces -----------------------------------------
 // One workgroup per segment seg[s]..seg[s+1] (device array of nseg + 1); dfx/dfy may be null.

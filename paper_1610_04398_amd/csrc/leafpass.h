@@ -47,22 +47,40 @@ __device__ inline double node_coord(double x0, int i, double h) {
 }
 
 // One wave prepares the targets of target leaf tleaves[wid].
+// bt.nreq > 0: a forest of requests; target o is target o - toff[r] of
+// request r, whose grid f[r] sits at offset (vx, vy) of the joint index space,
+// and offsets are formed in the request's own frame (bit for bit its lone
+// solve's).
 __device__ inline void prep_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ tleaves, int D,
                                  const double* __restrict__ tx, const double* __restrict__ ty,
                                  const int* __restrict__ perm, double x0, double y0, double h, int nx, int ny,
                                  double snap_frac2, const double* __restrict__ f, float2* __restrict__ rel32,
                                  double2* __restrict__ rel64, int* __restrict__ tleaf, double* __restrict__ self_w,
-                                 double* __restrict__ self_logd) {
+                                 double* __restrict__ self_logd, const GridBatch& bt) {
 #pragma clang fp contract(off)
   const int c = tleaves[wid];
   const int sh = D - t.lvl[c];
-  const double cx = (double)(t.ix[c] << sh), cy = (double)(t.iy[c] << sh);
   const int tb = t.tb[c], te = t.te[c];
   // squared distance below which a target is snapped onto its nearest node
   const double snap2 = h * h * snap_frac2;
   for (int k = tb + lane; k < te; k += kWave) {
     const int o = perm[k];
-    const double x = tx[o], y = ty[o];
+    double x, y;
+    const double* fr = f;
+    int vx = 0, vy = 0;
+    if (bt.nreq) {
+      const int r = batch_request(bt, o);
+      const int64_t j = o - bt.toff[r];
+      x = bt.tx[r][j];
+      y = bt.ty[r][j];
+      fr = bt.f[r];
+      vx = (int)compact_bits((uint32_t)r) << bt.D;
+      vy = (int)compact_bits((uint32_t)r >> 1) << bt.D;
+    } else {
+      x = tx[o];
+      y = ty[o];
+    }
+    const double cx = (double)((t.ix[c] << sh) - vx), cy = (double)((t.iy[c] << sh) - vy);
     const double ux = (x - x0) / h;
     const double uy = (y - y0) / h;
     double rx = ux - cx, ry = uy - cy;
@@ -75,7 +93,7 @@ __device__ inline void prep_leaf(int wid, int lane, const TreeArrays& t, const i
       const double dy = y - node_coord(y0, j, h);
       const double d2 = dx * dx + dy * dy;
       if (d2 == 0.0 || d2 < snap2) {
-        sw = f[(int64_t)j * nx + i] * (h * h);
+        sw = fr[(int64_t)j * nx + i] * (h * h);
         lg = (d2 == 0.0) ? -INFINITY : 0.5 * log(d2);
         rx = ((double)i + 0.5) - cx;
         ry = ((double)j + 0.5) - cy;
@@ -177,6 +195,7 @@ struct PrepArgs {
   int* tleaf;
   double* self_w;
   double* self_logd;
+  GridBatch bt;
 };
 
 // Arguments of the two passes for scattered sources.
@@ -229,7 +248,7 @@ __device__ inline void run_leaf_pass(const LeafPass& lp, int blk) {
     } else if (wid < lp.gb.nt) {
       const PrepArgs& b = lp.gb;
       prep_leaf(wid, lane, lp.t, b.tleaves, lp.D, b.tx, b.ty, b.perm, b.x0, b.y0, b.h, b.nx, b.ny, b.snap_frac2, b.f,
-                b.rel32, b.rel64, b.tleaf, b.self_w, b.self_logd);
+                b.rel32, b.rel64, b.tleaf, b.self_w, b.self_logd, b.bt);
     }
   } else if (lp.kind == 2) {
     const PointArgs& a = lp.pa;
@@ -258,7 +277,7 @@ LeafPass leaf_pass_grid(TreeArrays t, int D, const int* sleaves, int nsleaves, c
                         float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                         const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                         double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                        double* self_logd);
+                        double* self_logd, const GridBatch* bt);
 LeafPass leaf_pass_points(TreeArrays t, int D, double x0, double y0, double u, const double* xs, const double* ys,
                           const double* ws, const int* sleaves, int nsleaves, float* s32, int64_t stride,
                           double2* s64, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,

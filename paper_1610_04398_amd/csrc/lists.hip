@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
                                                                const int* __restrict__ off_p2p,
                                                                int* __restrict__ m2l_src, int* __restrict__ p2p_src,
                                                                int cap_m, int cap_p, int* __restrict__ flags,
-                                                               LeafPass lp) {
+                                                               int top, LeafPass lp) {
   __shared__ int front[kListWaves][2 * kFrontierCap];
   __shared__ int path[kListWaves][kMaxDepth + 1];
   if constexpr (kLeafPass) {  // the per-leaf passes riding on this launch
@@ -146,8 +146,12 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   int* cur = buf;
   int* nxt = buf + kFrontierCap;
   int ncur = 0;
-  if (rec_has_src(rec[0])) {
-    if (lane == 0) cur[0] = 0;
+  // top > 0 (a forest of requests): the walk starts at A's ancestor of level
+  // top, its request's root, and cells above that level have no lists
+  __syncwarp();
+  const int R0 = lA >= top ? path[w][top] : -1;
+  if (R0 >= 0 && rec_has_src(rec[R0])) {
+    if (lane == 0) cur[0] = R0;
     ncur = 1;
   }
   __syncwarp();
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists(int D, const int4*
   // pair accepted here belongs to X's lists.  A source leaf that is not
   // accepted stays for the next level, any other source cell is replaced by its
   // children with sources.
-  for (int xl = 0; xl < lA && ncur > 0; ++xl) {
+  for (int xl = top; xl < lA && ncur > 0; ++xl) {
     const int4 rX = rec[path[w][xl]];
     int nnext = 0;
     for (int base = 0; base < ncur; base += kWave) {
@@ -287,14 +291,14 @@ __global__ __launch_bounds__(kListWaves * kWave) void k_lists_treecode(
 
 void lists_pass(TreeView t, const int4* rec, const int* tcells, int ntcells, int num, int den, int emit, int* cnt_m2l,
                 int* cnt_p2p, const int* off_m2l, const int* off_p2p, int* m2l_src, int* p2p_src, int cap_m, int cap_p,
-                int* flags, int tier_boost, const LeafPass* lp, hipStream_t s) {
+                int* flags, int tier_boost, int top, const LeafPass* lp, hipStream_t s) {
   const int nlist = std::max(ntcells, 0);
   const int extra = lp ? lp->pack_blocks + lp->prep_blocks : 0;
   const unsigned g = (unsigned)((nlist + kListWaves - 1) / kListWaves + extra);
   if (g == 0) return;
   const int tier = std::min(2, frontier_tier_for(num, den) + tier_boost);
   PP_LIST_TIER(tier, lp != nullptr, k_lists, g, s, t.D, rec, t.parent, tcells, nlist, num, den, emit, cnt_m2l, cnt_p2p, off_m2l,
-               off_p2p, m2l_src, p2p_src, cap_m, cap_p, flags, lp ? *lp : LeafPass{});
+               off_p2p, m2l_src, p2p_src, cap_m, cap_p, flags, top, lp ? *lp : LeafPass{});
 }
 
 void lists_treecode_pass(TreeView t, const int4* rec, const int* tleaves, int ntleaves, int num, int den, int emit,

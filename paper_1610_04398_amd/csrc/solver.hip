@@ -523,8 +523,11 @@ void validate_points(int64_t n, const double* sx, const double* sy, const double
 // otherwise the lists are written in one pass into a fixed capacity per cell,
 // and a list that does not fit makes the solve report kFlagListOverflow (the
 // caller then repeats it with exact lists).
+// batch (may be null): a forest of grid requests (device inputs and outputs;
+// src describes the first request's grid, m is the joint target count).
 pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src, int64_t m, const double* tx,
-                    const double* ty, const pp_params& prm, double* p_out, hipStream_t s, bool resident = false) {
+                    const double* ty, const pp_params& prm, double* p_out, hipStream_t s, bool resident = false,
+                    const GridBatch* batch = nullptr) {
   const auto t_start = std::chrono::steady_clock::now();
   HIPCHK(hipSetDevice(c.device));
   if (s == nullptr) {
@@ -544,7 +547,9 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   }
   const int32_t nx = src.grid ? src.nx : 0, ny = src.grid ? src.ny : 0;
   const int64_t ngrid = src.grid ? (int64_t)nx * ny : 0;
-  const int64_t nmax = src.grid ? ngrid : src.n;  // sources before culling zeros
+  const int nreq = batch ? batch->nreq : 0;
+  const int top = batch ? batch->levels : 0;  // levels above a forest's request roots
+  const int64_t nmax = src.grid ? ngrid * std::max(nreq, 1) : src.n;  // sources before culling zeros
   const int p = prm.p;
   const int g = std::gcd((int)std::lround(prm.theta * 1000.0), 1000);
   const int num = (int)std::lround(prm.theta * 1000.0) / g, den = 1000 / g;
@@ -575,7 +580,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const bool pts_host = !src.grid && src.n > 0 && !is_device_ptr(src.sx);
   const bool ptsy_host = !src.grid && src.n > 0 && !is_device_ptr(src.sy);
   const bool ptsw_host = !src.grid && src.n > 0 && !is_device_ptr(src.w);
-  const int D = src.grid ? root_exponent(nx, ny) : kPointsDepth;
+  const int D = src.grid ? root_exponent(nx, ny) + top : kPointsDepth;
   const int k = D;
   // capacities from the input sizes (the source count is only known on the device)
   int64_t geo = 0;
@@ -709,7 +714,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 
   // ---- segment 1: ingest, target sort, tree, cell lists; ends with the read-back ----
   // (graph replay only for device-resident grid input: host input is staged by copies)
-  const bool replayable = src.grid && !exact_lists && !direct && !resident && !c.arena && f_d == src.f && tx_d == tx &&
+  const bool replayable = src.grid && !batch && !exact_lists && !direct && !resident && !c.arena && f_d == src.f && tx_d == tx &&
                           ty_d == ty && out_on_device && c.profiling != 1 &&
                           !(timed_phase >= PP_PHASE_INGEST && timed_phase <= PP_PHASE_TREE);
   const std::vector<uint64_t> key1 = {(uint64_t)nx, (uint64_t)ny, bits(x0), bits(y0), bits(unit), (uint64_t)m,
@@ -753,8 +758,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     tbegin(PP_PHASE_INGEST, s);
     if (src.grid) {
       // ---- ingest: sources in Morton order (no sort needed for a grid) ----
-      ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, s);
-      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, misc + M_NSRC, skey, sij, sw, dss, D - Ld, s);
+      ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, batch, s);
+      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, misc + M_NSRC, skey, sij, sw, dss, D - Ld, batch, s);
     } else if (src.n > 0) {
       // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
       int* sperm = (int*)sij;
@@ -766,12 +771,13 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // ---- targets: Morton keys and a stable radix sort ----
     mark(PP_PHASE_SORT);
     tbegin(PP_PHASE_SORT, s);
-    target_keys_sorted(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, tkey2, tperm2, sort_tmp, misc + M_FLAGS, s);
+    target_keys_sorted(tx_d, ty_d, m, x0, y0, unit, k, tkey, tperm, tkey2, tperm2, sort_tmp, misc + M_FLAGS, batch,
+                       s);
     tend(PP_PHASE_SORT, s);
     // ---- tree: dense top levels, then (scattered sources) one launch group per level ----
     mark(PP_PHASE_TREE);
     tbegin(PP_PHASE_TREE, s);
-    tree_dense_top(ta, ls_d, D, Ld, lm, (int)cap, skey, misc + M_NSRC, src.grid ? 1 : 0, tkey, (int)m, dss, dts,
+    tree_dense_top(ta, ls_d, D, Ld, lm, top, (int)cap, skey, misc + M_NSRC, src.grid ? 1 : 0, tkey, (int)m, dss, dts,
                    dflag, doff, scan, misc + M_TOT, misc + M_DEEP, misc + M_FLAGS, s);
     // Grid sources: a cell of the dense table's last level holds at most
     // 4^(D - Ld) nodes, so it is split only by its targets, which is rare:
@@ -908,7 +914,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                           c.frontier_boost, lp, q);
     else
       lists_pass(tv, rec, tcells, ntc, num, den, emit, cm2l, cp2p, om, op, ms, ps, cm, cp, misc + M_FLAGS,
-                 c.frontier_boost, lp, q);
+                 c.frontier_boost, top, lp, q);
   };
   std::vector<uint64_t> key2 = key1;
   for (uint64_t v : {(uint64_t)N, (uint64_t)ncells, (uint64_t)nsl, (uint64_t)ntl, (uint64_t)ntc, (uint64_t)depth,
@@ -974,7 +980,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto do_pack_prep = [&](hipStream_t q) {
     if (src.grid)
       leaf_pack_prep(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d, ty_d,
-                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd, q);
+                     tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf, selfw, selfd,
+                     batch, q);
     else
       leaf_pack_prep_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
                             leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw, q);
@@ -992,7 +999,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   const LeafPass lpass =
       src.grid ? leaf_pass_grid(ta, D, sleaves, nsl, sij, sw, s32, std::max<int64_t>(N, 1), leaf_w, tleaves, ntl, tx_d,
                                 ty_d, tperm, x0, y0, unit, nx, ny, mixed ? 0x1p-40 : 0.0, f_d, rel32, rel64, tgtleaf,
-                                selfw, selfd)
+                                selfw, selfd, batch)
                : leaf_pass_points(ta, D, x0, y0, unit, pxs, pys, sw, sleaves, nsl, s32, std::max<int64_t>(N, 1), s64,
                                   leaf_w, tleaves, ntl, tx_d, ty_d, tperm, rel32, rel64, tgtleaf, selfw);
   auto do_p2m = [&] {
@@ -1039,7 +1046,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       tend(PP_PHASE_M2L, s);
       mark(PP_PHASE_L2L);
       tbegin(PP_PHASE_L2L, s);
-      downward(tv, tcells, ntc, p, own, loc, doff, Ld, s);
+      downward(tv, tcells, ntc, p, own, loc, doff, Ld, top, s);
       tend(PP_PHASE_L2L, s);
       mark(PP_PHASE_L2P);
       if (!fuse_l2p) l2p(tv, m, tgtleaf, p, loc, rel64, mixed ? 1 : 0, far, s);
@@ -1069,7 +1076,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       fe.fp32 = mixed ? 1 : 0;
     }
     tbegin(PP_PHASE_FINALIZE, s);
-    finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, fe, s);
+    finalize(m, nparts, tperm, far, near, selfw, selfd, unit, prm.self_mode, misc + M_FLAGS, out_d, tot, fe, batch,
+             s);
     tend(PP_PHASE_FINALIZE, s);
     mark(12);
     publish_enqueue(c, misc, M_PAIRS + 2, s);
@@ -1254,7 +1262,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.stats.n_p2p_pairs = (int64_t)npairs;
   c.stats.ms_total =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-  if (src.grid && !direct && !resident && !c.arena) {
+  if (src.grid && !direct && !resident && !c.arena && !batch) {
     Resident& r = c.res;
     r.valid = true;
     ++c.res_gen;
@@ -1293,7 +1301,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
 }
 
 pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const double* tx, const double* ty,
-                const pp_params* prm, double* p_out, void* stream, bool resident = false) {
+                const pp_params* prm, double* p_out, void* stream, bool resident = false,
+                const GridBatch* batch = nullptr) {
   if (!c) return PP_ERR_ARG;
   if (c->dead) {
     c->err = "context is unusable after a device error";
@@ -1321,7 +1330,7 @@ pp_status guard(pp_ctx* c, bool direct, const Sources& src, int64_t m, const dou
     pp_status st = PP_OK;
     for (;;) {
       try {
-        st = run_solve(*c, direct, exact, src, m, tx, ty, *prm, p_out, (hipStream_t)stream);
+        st = run_solve(*c, direct, exact, src, m, tx, ty, *prm, p_out, (hipStream_t)stream, false, batch);
       } catch (const FrontierRetry&) {
         continue;
       }
@@ -1454,6 +1463,48 @@ void pp_destroy(pp_ctx* c) {
 pp_status pp_solve_grid(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h, const double* f, int64_t m,
                         const double* tx, const double* ty, const pp_params* params, double* p_out, void* stream) {
   return guard(c, false, grid_sources(nx, ny, x0, y0, h, f), m, tx, ty, params, p_out, stream);
+}
+
+pp_status pp_solve_grid_batch(pp_ctx* c, int32_t nreq, int32_t nx, int32_t ny, double x0, double y0, double h,
+                              const double* const* f, const int64_t* m, const double* const* tx,
+                              const double* const* ty, const pp_params* params, double* const* p_out, void* stream) {
+  if (!c) return PP_ERR_ARG;
+  auto refuse = [&](const char* why) {
+    c->err = why;
+    return PP_ERR_ARG;
+  };
+  if (nreq < 1 || nreq > kMaxBatch || !f || !m || !tx || !ty || !p_out || !params)
+    return refuse("batch: 1 to 16 requests, every array given");
+  if (nreq == 1) return pp_solve_grid(c, nx, ny, x0, y0, h, f[0], m[0], tx[0], ty[0], params, p_out[0], stream);
+  if (params->method != PP_METHOD_FMM) return refuse("batch: the multipole method only");
+  int levels = 0;
+  while ((1 << (2 * levels)) < nreq) ++levels;
+  const int D = root_exponent(std::max(nx, 1), std::max(ny, 1));
+  if (D < 6 || D + levels > 16) return refuse("batch: grids of 33 to 65536 nodes a side, and the forest within 65536");
+  if (levels > c->dense_levels) return refuse("batch: the forest's top levels must lie in the dense table");
+  GridBatch b;
+  b.nreq = nreq;
+  b.levels = levels;
+  b.D = D;
+  int64_t M = 0;
+  for (int r = 0; r < nreq; ++r) {
+    if (m[r] < 0) return refuse("batch: negative target count");
+    if (!f[r] || !is_device_ptr(f[r]) || (m[r] > 0 && (!tx[r] || !ty[r] || !p_out[r] || !is_device_ptr(tx[r]) ||
+                                                       !is_device_ptr(ty[r]) || !is_device_ptr(p_out[r]))))
+      return refuse("batch: device memory only, every pointer given");
+    b.f[r] = f[r];
+    b.tx[r] = tx[r];
+    b.ty[r] = ty[r];
+    b.out[r] = p_out[r];
+    b.toff[r] = M;
+    M += m[r];
+  }
+  b.toff[nreq] = M;
+  if (M >= ((int64_t)1 << 31)) return refuse("batch: too many targets");
+  int r0 = 0;  // a request with targets stands for the batch in the argument checks
+  while (r0 + 1 < nreq && m[r0] == 0) ++r0;
+  return guard(c, false, grid_sources(nx, ny, x0, y0, h, f[0]), M, tx[r0], ty[r0], params, p_out[r0], stream, false,
+               &b);
 }
 
 pp_status pp_solve_grid_noalloc(pp_ctx* c, int32_t nx, int32_t ny, double x0, double y0, double h,

@@ -40,11 +40,15 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_hist(const uint32_t* __restr
 // The first pass's histogram fused with the computation of the target keys
 // (finest-cell Morton keys, see target_key): each workgroup computes and stores
 // the keys and indices of its tile and counts their lowest digit.
+// bt.nreq > 0: the targets of a forest of requests, joint index i is target
+// i - toff[r] of request r, whose key is prefixed by r (its cell of the
+// forest's top levels; k is then one request's root exponent).
 template <int BITS>
 __global__ __launch_bounds__(kRsBlock) void k_keys_hist(const double* __restrict__ tx, const double* __restrict__ ty,
                                                         int n, double x0, double y0, double h, int k, int nblocks,
                                                         uint32_t* __restrict__ keys, int* __restrict__ vals,
-                                                        int* __restrict__ hist, int* __restrict__ flags) {
+                                                        int* __restrict__ hist, int* __restrict__ flags,
+                                                        GridBatch bt) {
   constexpr int BINS = 1 << BITS;
   __shared__ int hs[BINS];
   for (int b = threadIdx.x; b < BINS; b += kRsBlock) hs[b] = 0;
@@ -55,7 +59,14 @@ __global__ __launch_bounds__(kRsBlock) void k_keys_hist(const double* __restrict
     const int i = base + q * kRsBlock + threadIdx.x;
     if (i < n) {
       int err = 0;
-      const uint32_t key = target_key(tx[i], ty[i], x0, y0, h, k, &err);
+      uint32_t key;
+      if (bt.nreq) {
+        const int r = batch_request(bt, i);
+        const int64_t j = i - bt.toff[r];
+        key = ((uint32_t)r << (2 * k)) | target_key(bt.tx[r][j], bt.ty[r][j], x0, y0, h, k, &err);
+      } else {
+        key = target_key(tx[i], ty[i], x0, y0, h, k, &err);
+      }
       errs |= err;
       keys[i] = key;
       vals[i] = i;
@@ -188,6 +199,7 @@ struct KeySource {
   double x0 = 0.0, y0 = 0.0, h = 1.0;
   int k = 0;
   int* flags = nullptr;
+  GridBatch bt{};
 };
 
 template <int BITS>
@@ -195,7 +207,7 @@ void radix_pass(uint32_t* ka, int* va, uint32_t* kb, int* vb, int n, int shift, 
                 const KeySource* ks, hipStream_t s) {
   if (ks)
     k_keys_hist<BITS><<<nb, kRsBlock, 0, s>>>(ks->tx, ks->ty, n, ks->x0, ks->y0, ks->h, ks->k, nb, ka, va, table,
-                                              ks->flags);
+                                              ks->flags, ks->bt);
   else
     k_radix_hist<BITS><<<nb, kRsBlock, 0, s>>>(ka, n, shift, nb, table);
   if (nb <= kRsFoldTiles) {
@@ -260,8 +272,19 @@ void radix_sort_pairs(uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_t
 
 void target_keys_sorted(const double* tx, const double* ty, int64_t m, double x0, double y0, double h, int k,
                         uint32_t* keys, int* vals, uint32_t* keys_tmp, int* vals_tmp, int* temp, int* flags,
-                        hipStream_t s) {
+                        const GridBatch* bt, hipStream_t s) {
   if (m <= 0) return;
+  if (bt && bt->nreq) {  // keys of one request's root prefixed by the request's forest cell
+    KeySource ks;
+    ks.x0 = x0;
+    ks.y0 = y0;
+    ks.h = h;
+    ks.k = bt->D;
+    ks.flags = flags;
+    ks.bt = *bt;
+    sort_impl(keys, vals, keys_tmp, vals_tmp, m, 2 * (bt->D + bt->levels), temp, &ks, s);
+    return;
+  }
   if (m == 1 || k <= 0) {
     target_keys(tx, ty, m, x0, y0, h, k, keys, vals, flags, s);
     return;

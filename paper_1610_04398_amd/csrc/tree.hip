@@ -198,9 +198,11 @@ __global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __r
 // Existence flag of every prefix-table cell, and per workgroup (kDenseBlock
 // consecutive cells) the number of cells that exist, for k_dense_offsets.
 constexpr int kDenseBlock = 256;
+// Cells of the levels above split_above are split whatever they hold (the
+// top levels of a forest of requests).
 __global__ __launch_bounds__(kDenseBlock) void k_dense_flags(const int* __restrict__ ss, const int* __restrict__ ts,
-                                                              int D, int Ld, int leaf_max, int* __restrict__ flag,
-                                                              int* __restrict__ part) {
+                                                              int D, int Ld, int leaf_max, int split_above,
+                                                              int* __restrict__ flag, int* __restrict__ part) {
   __shared__ int lds[kDenseBlock / kWave + 1];
   const int64_t F = dense_level_offset(Ld + 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_flags(const int* __restri
       const int64_t Q = P >> 2;
       const int ns = ss[(P + 1) << sh] - ss[P << sh], nt = ts[(P + 1) << sh] - ts[P << sh];
       const int nps = ss[(Q + 1) << shp] - ss[Q << shp], npt = ts[(Q + 1) << shp] - ts[Q << shp];
-      const bool split = L - 1 < D && (nps > leaf_max || npt > leaf_max);
+      const bool split = L - 1 < D && (nps > leaf_max || npt > leaf_max || L - 1 < split_above);
       f = (split && (ns > 0 || nt > 0)) ? 1 : 0;
     }
     flag[idx] = f;
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs
     const int wid = (blockIdx.x - pack_blocks) * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (wid < b.nt)
       prep_leaf(wid, lane, t, b.tleaves, D, b.tx, b.ty, b.perm, b.x0, b.y0, b.h, b.nx, b.ny, b.snap_frac2, b.f,
-                b.rel32, b.rel64, b.tleaf, b.self_w, b.self_logd);
+                b.rel32, b.rel64, b.tleaf, b.self_w, b.self_logd, b.bt);
   }
 }
 
@@ -479,14 +481,15 @@ int64_t tree_dense_part_ints(int Ld) { return (tree_dense_cells(Ld) + kDenseBloc
 
 int64_t tree_dense_cells(int Ld) { return ((((int64_t)1) << (2 * (Ld + 1))) - 1) / 3; }
 
-void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int cap, const uint32_t* skey,
-                    const int* nsrc_dev, int src_done, const uint32_t* tkey, int ntgt, int* ss, int* ts, int* flag,
-                    int* off, int* scan_tmp, int* total_slot, int* deep, int* flags, hipStream_t s) {
+void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int split_above, int cap,
+                    const uint32_t* skey, const int* nsrc_dev, int src_done, const uint32_t* tkey, int ntgt, int* ss,
+                    int* ts, int* flag, int* off, int* scan_tmp, int* total_slot, int* deep, int* flags,
+                    hipStream_t s) {
   const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
   k_dense_starts<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(skey, nsrc_dev, tkey, ntgt, D, Ld, src_done, ss, ts);
   const int64_t F = tree_dense_cells(Ld);
   const unsigned g = (unsigned)((F + kDenseBlock - 1) / kDenseBlock);
-  k_dense_flags<<<g, kDenseBlock, 0, s>>>(ss, ts, D, Ld, leaf_max, flag, scan_tmp);
+  k_dense_flags<<<g, kDenseBlock, 0, s>>>(ss, ts, D, Ld, leaf_max, split_above, flag, scan_tmp);
   k_dense_offsets<<<g, kDenseBlock, 0, s>>>(flag, scan_tmp, Ld, off, total_slot);
   k_dense_write<<<g, 256, 0, s>>>(t, flag, off, total_slot, ss, ts, D, Ld, leaf_max, cap, ls, deep, flags);
 }
@@ -505,7 +508,7 @@ LeafPass leaf_pass_grid(TreeArrays t, int D, const int* sleaves, int nsleaves, c
                         float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                         const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                         double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                        double* self_logd) {
+                        double* self_logd, const GridBatch* bt) {
   LeafPass lp;
   lp.kind = 1;
   lp.pack_blocks = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
@@ -514,7 +517,7 @@ LeafPass leaf_pass_grid(TreeArrays t, int D, const int* sleaves, int nsleaves, c
   lp.D = D;
   lp.ga = PackArgs{sleaves, nsleaves, ij, w64, s32, stride, leaf_w};
   lp.gb = PrepArgs{tleaves, ntleaves, tx, ty, perm, x0, y0, h, nx, ny, snap_frac2, f, rel32, rel64, tleaf, self_w,
-                   self_logd};
+                   self_logd, bt ? *bt : GridBatch{}};
   return lp;
 }
 
@@ -522,13 +525,13 @@ void leaf_pack_prep(TreeArrays t, int D, const int* sleaves, int nsleaves, const
                     float* s32, int64_t stride, double* leaf_w, const int* tleaves, int ntleaves, const double* tx,
                     const double* ty, const int* perm, double x0, double y0, double h, int nx, int ny,
                     double snap_frac2, const double* f, float2* rel32, double2* rel64, int* tleaf, double* self_w,
-                    double* self_logd, hipStream_t s) {
+                    double* self_logd, const GridBatch* bt, hipStream_t s) {
   const int gp = std::max(nsleaves, 0) / 4 + (nsleaves % 4 > 0);
   const int gt = std::max(ntleaves, 0) / 4 + (ntleaves % 4 > 0);
   if (gp + gt <= 0) return;
   const PackArgs a{sleaves, nsleaves, ij, w64, s32, stride, leaf_w};
   const PrepArgs b{tleaves, ntleaves, tx, ty, perm, x0, y0, h, nx, ny, snap_frac2, f, rel32, rel64, tleaf, self_w,
-                   self_logd};
+                   self_logd, bt ? *bt : GridBatch{}};
   k_pack_prep<<<gp + gt, 256, 0, s>>>(t, D, a, gp, b);
 }
 
