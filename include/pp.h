@@ -362,6 +362,17 @@ const char* pp_last_error(const pp_ctx* ctx);
  * is bitwise the result of pp_solve_grid on the same inputs: slots share
  * nothing.
  *
+ * Fused launches (max_batch > 1): when a slot admits the head of the queue it
+ * also takes, in queue order, up to max_batch - 1 more queued requests of the
+ * same shape (nx, ny, x0, y0, h and parameters; multipole method; every input
+ * and output in device memory) while the memory bound leaves room, and solves
+ * them together with pp_solve_grid_batch: one set of launches for all of them,
+ * each result still bitwise its pp_solve_grid result.  The batch counts as its
+ * head's work for the work bound (its time grows far more slowly than its
+ * work).  Should the
+ * batched call fail, its requests are solved one by one, so each gets its own
+ * status.  The requests of a batch start and finish together.
+ *
  * Ownership: host inputs (f, tx, ty) are copied at submission; device inputs
  * and p_out must stay valid until pp_server_wait has returned for the ticket.
  * All server functions are thread-safe.
@@ -372,6 +383,7 @@ typedef struct {
   int32_t max_slots;          /* concurrent solves, 1..64 */
   uint64_t hbm_budget_bytes;  /* admission bound on in-flight footprints (0 = none) */
   uint64_t work_budget_points; /* admission bound on in-flight nx*ny + m (0 = none) */
+  int32_t max_batch;          /* requests fused into one launch set, 0 or 1 = none, up to 16 */
 } pp_server_cfg;
 typedef struct {              /* the arguments of pp_solve_grid */
   int32_t nx, ny;

@@ -402,8 +402,9 @@ class Server:
     submission) or CUDA tensors (kept alive here until the ticket is waited on).
     """
 
-    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0, work_budget_points: int = 0):
-        self._srv = pp_server_create(device, max_slots, hbm_budget_bytes, work_budget_points)
+    def __init__(self, device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0, work_budget_points: int = 0,
+                 max_batch: int = 0):
+        self._srv = pp_server_create(device, max_slots, hbm_budget_bytes, work_budget_points, max_batch)
         self._keep = {}
 
     def submit(self, f, h, tx, ty, out, x0=0.0, y0=0.0, p=12, theta=0.5, leaf_max=64, precision="mixed",

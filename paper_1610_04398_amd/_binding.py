@@ -64,7 +64,7 @@ class pp_force(ctypes.Structure):
 
 class pp_server_cfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
-                ("work_budget_points", ctypes.c_uint64)]
+                ("work_budget_points", ctypes.c_uint64), ("max_batch", ctypes.c_int32)]
 
 
 class pp_request(ctypes.Structure):
@@ -255,8 +255,8 @@ def pp_last_error(ctx) -> str:
 
 
 def pp_server_create(device: int = 0, max_slots: int = 4, hbm_budget_bytes: int = 0,
-                     work_budget_points: int = 0) -> int:
-    cfg = pp_server_cfg(device, max_slots, hbm_budget_bytes, work_budget_points)
+                     work_budget_points: int = 0, max_batch: int = 0) -> int:
+    cfg = pp_server_cfg(device, max_slots, hbm_budget_bytes, work_budget_points, max_batch)
     h = ctypes.c_void_p()
     st = lib().pp_server_create(ctypes.byref(cfg), ctypes.byref(h))
     if st != PP_OK:

@@ -12,6 +12,12 @@
 // dividing the GPU between them, which would stretch each one's latency.  A
 // request's result does not depend on which slot ran it or on what ran beside
 // it: every slot runs the same deterministic kernels on its own buffers.
+//
+// Fused launches: a slot that admits the head of the queue also takes later
+// queued requests of the same shape (device inputs and outputs, multipole
+// method) while the bounds allow, and solves them as one forest with
+// pp_solve_grid_batch: one set of launches, each result still bitwise the
+// request's lone solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +42,7 @@ using clk = std::chrono::steady_clock;
 struct Job {
   uint64_t ticket = 0;
   pp_request req{};
+  bool device_io = false;  // every input and the output in device memory (may join a batch)
   std::vector<double> f_copy, tx_copy, ty_copy;  // host inputs copied at submission
   uint64_t footprint = 0;
   uint64_t work = 0;
@@ -55,6 +62,20 @@ bool host_memory(const void* p) {
     return true;
   }
   return !(a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged);
+}
+
+// A request pp_solve_grid_batch takes (device inputs and output, the
+// multipole method, 33 to 16384 nodes a side), and requests it can solve
+// together (one shape).
+bool batchable(const Job& j) {
+  const int n = std::max(j.req.nx, j.req.ny);
+  return j.device_io && j.req.params.method == PP_METHOD_FMM && n >= 33 && n <= 16384;
+}
+bool same_shape(const pp_request& a, const pp_request& b) {
+  const pp_params &p = a.params, &q = b.params;
+  return a.nx == b.nx && a.ny == b.ny && a.x0 == b.x0 && a.y0 == b.y0 && a.h == b.h && p.p == q.p &&
+         p.theta == q.theta && p.leaf_max == q.leaf_max && p.precision == q.precision && p.self_mode == q.self_mode &&
+         p.method == q.method;
 }
 
 }  // namespace
@@ -104,6 +125,7 @@ void worker_loop(pp_server* s, int slot) {
   (void)hipSetDevice(s->cfg.device);
   pp_ctx* ctx = s->ctxs[slot];
   hipStream_t stream = s->streams[slot];
+  std::vector<std::shared_ptr<Job>> batch;  // the head, then the requests solved with it
   for (;;) {
     std::shared_ptr<Job> job;
     {
@@ -129,37 +151,103 @@ void worker_loop(pp_server* s, int slot) {
       if (s->queue.empty()) return;  // stopping and drained
       job = s->queue.front();
       s->queue.pop_front();
-      s->inflight += 1;
-      s->inflight_bytes += job->footprint;
+      batch.assign(1, job);
+      uint64_t fp = job->footprint;
+      // fused launches: later queued requests of the head's shape join it (in
+      // queue order) while the memory bound leaves room.  The batch is one
+      // solve whose time grows far more slowly than its work (the launch
+      // chain and its host round trips dominate at these sizes), so it counts
+      // as the head's work for the work bound.
+      if (s->cfg.max_batch > 1 && batchable(*job)) {
+        uint64_t others = 0;
+        for (int o = 0; o < (int)s->held.size(); ++o)
+          if (o != slot) others += std::max(s->held[o], s->running_fp[o]);
+        const int cap = std::min<int>(s->cfg.max_batch, pp::kMaxBatch);
+        for (auto it = s->queue.begin(); it != s->queue.end() && (int)batch.size() < cap;) {
+          const Job& o = **it;
+          const bool fits_mem = s->cfg.hbm_budget_bytes == 0 ||
+                                others + std::max(s->held[slot], fp + o.footprint) <= s->cfg.hbm_budget_bytes;
+          if (batchable(o) && same_shape(o.req, job->req) && fits_mem) {
+            fp += o.footprint;
+            batch.push_back(*it);
+            it = s->queue.erase(it);
+          } else {
+            ++it;
+          }
+        }
+      }
+      s->inflight += (int)batch.size();
+      s->inflight_bytes += fp;
       s->inflight_work += job->work;
-      s->running_fp[slot] = job->footprint;
-      job->slot = slot;
-      job->t_start = clk::now();
+      s->running_fp[slot] = fp;
+      const auto now = clk::now();
+      for (auto& b : batch) {
+        b->slot = slot;
+        b->t_start = now;
+      }
       // a request that starts alone on the GPU runs its near field on the
       // context's second stream; beside other requests it keeps one stream
-      if (s->cfg.max_slots > 1) pp::ctx_set_near_stream(ctx, s->inflight == 1);
+      if (s->cfg.max_slots > 1) pp::ctx_set_near_stream(ctx, s->inflight == (int)batch.size());
     }
-    const pp_request& r = job->req;
-    const double* f = job->f_copy.empty() ? r.f : job->f_copy.data();
-    const double* tx = job->tx_copy.empty() ? r.tx : job->tx_copy.data();
-    const double* ty = job->ty_copy.empty() ? r.ty : job->ty_copy.data();
-    const pp_status st =
-        pp_solve_grid(ctx, r.nx, r.ny, r.x0, r.y0, r.h, f, r.m, tx, ty, &r.params, r.p_out, (void*)stream);
+    std::vector<pp_status> sts(batch.size(), PP_OK);
+    std::vector<std::string> errs(batch.size());
+    auto solve_one = [&](size_t i) {
+      const Job& jb = *batch[i];
+      const pp_request& r = jb.req;
+      const double* f = jb.f_copy.empty() ? r.f : jb.f_copy.data();
+      const double* tx = jb.tx_copy.empty() ? r.tx : jb.tx_copy.data();
+      const double* ty = jb.ty_copy.empty() ? r.ty : jb.ty_copy.data();
+      sts[i] = pp_solve_grid(ctx, r.nx, r.ny, r.x0, r.y0, r.h, f, r.m, tx, ty, &r.params, r.p_out, (void*)stream);
+      if (sts[i] != PP_OK) errs[i] = pp_last_error(ctx);
+    };
+    if (batch.size() == 1) {
+      solve_one(0);
+    } else {
+      const int n = (int)batch.size();
+      std::vector<const double*> fs(n), txs(n), tys(n);
+      std::vector<double*> outs(n);
+      std::vector<int64_t> ms(n);
+      for (int i = 0; i < n; ++i) {
+        const pp_request& r = batch[i]->req;
+        fs[i] = r.f;
+        txs[i] = r.tx;
+        tys[i] = r.ty;
+        outs[i] = r.p_out;
+        ms[i] = r.m;
+      }
+      const pp_request& r0 = batch[0]->req;
+      const pp_status st = pp_solve_grid_batch(ctx, n, r0.nx, r0.ny, r0.x0, r0.y0, r0.h, fs.data(), ms.data(),
+                                               txs.data(), tys.data(), &r0.params, outs.data(), (void*)stream);
+      if (st != PP_OK && st != PP_ERR_DEVICE) {
+        for (int i = 0; i < n; ++i) solve_one(i);  // each request gets its own status
+      } else if (st != PP_OK) {
+        for (int i = 0; i < n; ++i) {
+          sts[i] = st;
+          errs[i] = pp_last_error(ctx);
+        }
+      }
+    }
+    pp_status st = PP_OK;
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      job->status = st;
-      if (st != PP_OK) job->err = pp_last_error(ctx);
-      job->t_end = clk::now();
-      job->done = true;
-      job->f_copy.clear();
-      job->f_copy.shrink_to_fit();
-      job->tx_copy.clear();
-      job->tx_copy.shrink_to_fit();
-      job->ty_copy.clear();
-      job->ty_copy.shrink_to_fit();
-      s->inflight -= 1;
-      s->inflight_bytes -= job->footprint;
-      s->inflight_work -= job->work;
+      const auto now = clk::now();
+      for (size_t i = 0; i < batch.size(); ++i) {
+        Job& jb = *batch[i];
+        jb.status = sts[i];
+        if (sts[i] != PP_OK) jb.err = errs[i];
+        if (sts[i] == PP_ERR_DEVICE) st = PP_ERR_DEVICE;
+        jb.t_end = now;
+        jb.done = true;
+        jb.f_copy.clear();
+        jb.f_copy.shrink_to_fit();
+        jb.tx_copy.clear();
+        jb.tx_copy.shrink_to_fit();
+        jb.ty_copy.clear();
+        jb.ty_copy.shrink_to_fit();
+        s->inflight -= 1;
+        s->inflight_bytes -= jb.footprint;
+      }
+      s->inflight_work -= batch[0]->work;
       s->running_fp[slot] = 0;
       // a slot whose buffers push the resident total over the budget (after a
       // request larger than the others) gives them back
@@ -193,7 +281,9 @@ void worker_loop(pp_server* s, int slot) {
 extern "C" {
 
 pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out) {
-  if (!cfg || !out || cfg->max_slots < 1 || cfg->max_slots > 64) return PP_ERR_ARG;
+  if (!cfg || !out || cfg->max_slots < 1 || cfg->max_slots > 64 || cfg->max_batch < 0 ||
+      cfg->max_batch > pp::kMaxBatch)
+    return PP_ERR_ARG;
   *out = nullptr;
   auto* s = new pp_server();
   s->cfg = *cfg;
@@ -236,6 +326,8 @@ pp_status pp_server_submit(pp_server* s, const pp_request* r, uint64_t* ticket) 
   if (host_memory(r->f)) job->f_copy.assign(r->f, r->f + ng);
   if (r->m > 0 && host_memory(r->tx)) job->tx_copy.assign(r->tx, r->tx + r->m);
   if (r->m > 0 && host_memory(r->ty)) job->ty_copy.assign(r->ty, r->ty + r->m);
+  job->device_io = job->f_copy.empty() && job->tx_copy.empty() && job->ty_copy.empty() && r->m > 0 &&
+                   !host_memory(r->p_out);
   job->footprint = pp_footprint_estimate(r->nx, r->ny, r->m, r->params.p, r->params.leaf_max);
   job->work = (uint64_t)ng + (uint64_t)r->m;
   job->t_submit = clk::now();

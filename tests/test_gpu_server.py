@@ -164,3 +164,57 @@ def test_cancel_queued_request(pp):
     with pytest.raises(pp.PPError):  # released by its wait: an unknown ticket now
         srv.cancel(tickets[-1])
     srv.close()
+
+
+def test_fused_batches_equal_alone(pp):
+    """With max_batch = 4 and one slot, queued requests of one shape (device inputs and outputs) are solved
+    together in one set of launches: several tickets share their start and end; every result is bitwise the
+    request's lone solve; a request whose target lies outside its square fails alone (the batch is then
+    solved one request at a time) and the others still succeed; host-input requests are served unbatched."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(12))
+    reqs = []
+    for k in range(11):
+        size = (128, 256)[k % 2] if k < 9 else 128
+        g = G.GridSpec(size, size, 1.0 / size)
+        f = G.vortex_source(g, (12, k), int(rng.integers(8, 24)))
+        tx, ty = G.ellipse_targets(int(rng.integers(300, 2000)))
+        if k == 4:
+            tx = tx.copy()
+            tx[7] = 1.25  # outside the unit square
+        reqs.append(dict(g=g, f=f, tx=tx, ty=ty, host=k == 10))
+    solver = pp.Solver(0)
+    alone = []
+    for r in reqs:
+        try:
+            alone.append(solver.solve_grid(r["f"], r["g"].h, r["tx"], r["ty"]))
+        except pp.PPError as e:
+            alone.append(e.status)
+    solver.close()
+    srv = pp.Server(0, max_slots=1, max_batch=4)
+    outs, tickets = [], []
+    for r in reqs:
+        if r["host"]:
+            f, tx, ty, out = r["f"], r["tx"], r["ty"], np.empty(r["tx"].size)
+        else:
+            f, tx, ty = to_dev(r["f"], r["tx"], r["ty"])
+            out = torch.empty(tx.numel(), dtype=torch.float64, device="cuda")
+        outs.append(out)
+        tickets.append(srv.submit(f, r["g"].h, tx, ty, out))
+    infos = []
+    for k, t in enumerate(tickets):
+        if isinstance(alone[k], int):
+            with pytest.raises(pp.PPError) as e:
+                srv.wait(t)
+            assert e.value.status == alone[k]
+            infos.append(None)
+        else:
+            infos.append(srv.wait(t))
+    srv.close()
+    for k, (a, o) in enumerate(zip(alone, outs)):
+        if isinstance(a, int):
+            continue
+        got = o if isinstance(o, np.ndarray) else to_host(o)
+        assert np.array_equal(a, got), k
+    spans = [(i["start_us"], i["end_us"]) for i in infos if i is not None]
+    assert len(set(spans)) < len(spans)  # some requests ran as one batch
