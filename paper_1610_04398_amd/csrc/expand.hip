@@ -84,17 +84,12 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
+// One source leaf c, LANES lanes (sub = the lane's index in its group); only
+// a group with store set writes the leaf's coefficients.
 template <int PM, int LANES>
-__global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
-                                             const uint32_t* __restrict__ ij, const double* __restrict__ xs,
-                                             const double* __restrict__ ys, double x0, double y0, double u,
-                                             const double* __restrict__ w64, int p, double2* __restrict__ mp) {
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int li = (int)(gtid / LANES);
-  const int sub = (int)(gtid % LANES);
-  // every lane of a group takes part in the group sums: lanes past the last
-  // leaf work on a copy of it and store nothing
-  const int c = sleaves[li < n ? li : n - 1];
+__device__ inline void p2m_leaf(const TreeView& t, int c, int sub, bool store, const uint32_t* __restrict__ ij,
+                                const double* __restrict__ xs, const double* __restrict__ ys, double x0, double y0,
+                                double u, const double* __restrict__ w64, int p, double2* __restrict__ mp) {
   const double side = cell_side(t.D, t.lvl[c]);
   const double inv = 1.0 / side;
   const int sh = t.D - t.lvl[c];
@@ -139,12 +134,141 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
     acc[k].x = group_sum<LANES>(acc[k].x);
     acc[k].y = group_sum<LANES>(acc[k].y);
   }
-  if (li >= n) return;
+  if (!store) return;
   double2* out = mp + (int64_t)c * (p + 1);
 #pragma unroll
   for (int k = 0; k <= PM; ++k)
     if (k <= p && (k % LANES) == sub)
       out[k] = (k == 0) ? make_double2(acc[0].x, 0.0) : make_double2(-acc[k].x / k, -acc[k].y / k);
+}
+
+template <int PM, int LANES>
+__global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__ sleaves, int n,
+                                             const uint32_t* __restrict__ ij, const double* __restrict__ xs,
+                                             const double* __restrict__ ys, double x0, double y0, double u,
+                                             const double* __restrict__ w64, int p, double2* __restrict__ mp) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int li = (int)(gtid / LANES);
+  const int sub = (int)(gtid % LANES);
+  // every lane of a group takes part in the group sums: lanes past the last
+  // leaf work on a copy of it and store nothing
+  const int c = sleaves[li < n ? li : n - 1];
+  p2m_leaf<PM, LANES>(t, c, sub, li < n, ij, xs, ys, x0, y0, u, w64, p, mp);
+}
+
+// P2M of grid leaves 8 nodes wide, the usual leaf of a grid source: the 64
+// node positions of such a leaf, relative to its centre, are the same for
+// every leaf (zeta = ((x + 1/2) / 8 - 1/2, (y + 1/2) / 8 - 1/2), x, y = 0..7).
+// So a'_k = -(1/k) sum_s w_s zeta_s^k (and a'_0 = sum_s w_s) is the product of
+// the leaf's weights by position (zero where a node was culled) with one fixed
+// 64 x 2(p + 1) real matrix Z (columns Re and Im of -zeta^k / k; 1 and 0 for
+// k = 0): a dense contraction, run on the matrix cores as FP64 16x16x4
+// products, 16 leaves per wave (rows), 4 positions per product, 16 columns per
+// tile.  Leaves of other sizes in the wave's 16 are done by the lane-group path
+// above, 8 lanes per leaf.
+template <int PM>
+__global__ __launch_bounds__(256) void k_p2m_lattice(TreeView t, const int* __restrict__ sleaves, int n,
+                                                     const uint32_t* __restrict__ ij, const double* __restrict__ w64,
+                                                     int p, double2* __restrict__ mp) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  constexpr int kCols = 2 * (PM + 1);
+  constexpr int kTiles = (kCols + 15) / 16;
+  constexpr int kZW = kTiles * 16;  // row length of Z
+  constexpr int kWP = 68;           // padded row of a wave's weight block (doubles)
+  __shared__ double zt[64 * kZW];
+  __shared__ double wb[4 * 16 * kWP];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  if (threadIdx.x < 64) {
+    const int pos = threadIdx.x;
+    const cplx z = {((double)(pos & 7) + 0.5) * 0.125 - 0.5, ((double)(pos >> 3) + 0.5) * 0.125 - 0.5};
+    double* row = zt + pos * kZW;
+    row[0] = 1.0;
+    row[1] = 0.0;
+    cplx zk = z;
+#pragma unroll
+    for (int k = 1; k <= PM; ++k) {
+      row[2 * k] = -zk.x / k;
+      row[2 * k + 1] = -zk.y / k;
+      zk = cmul(zk, z);
+    }
+#pragma unroll
+    for (int col = kCols; col < kZW; ++col) row[col] = 0.0;
+  }
+  double* W = wb + wave * 16 * kWP;
+  for (int q = lane; q < 16 * kWP; q += kWave) W[q] = 0.0;
+  // the wave's 16 leaves: lane i < 16 holds leaf i's cell, source range and corner
+  const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  int c = 0, sb = 0, cnt = 0, cx = 0, cy = 0;
+  bool valid = false, lat = false;
+  if (lane < 16 && base + lane < n) {
+    c = sleaves[base + lane];
+    const int sh = t.D - t.lvl[c];
+    sb = t.sb[c];
+    cnt = t.se[c] - sb;
+    cx = t.ix[c] << sh;
+    cy = t.iy[c] << sh;
+    valid = true;
+    lat = sh == 3 && cnt <= 64;
+  }
+  const uint64_t latm = __ballot(lat);
+  const uint64_t genm = __ballot(valid && !lat);
+  uint32_t v[16];
+  double w[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int sbi = __builtin_amdgcn_readlane(sb, i), cnti = __builtin_amdgcn_readlane(cnt, i);
+    const bool ok = ((latm >> i) & 1) && lane < cnti;
+    v[i] = ok ? ij[sbi + lane] : 0u;
+    w[i] = ok ? w64[sbi + lane] : 0.0;
+  }
+  __syncthreads();  // Z and the cleared weight blocks
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int cxi = __builtin_amdgcn_readlane(cx, i), cyi = __builtin_amdgcn_readlane(cy, i);
+    const int cnti = __builtin_amdgcn_readlane(cnt, i);
+    const int dx = (int)(v[i] & 0xFFFFu) - cxi, dy = (int)(v[i] >> 16) - cyi;
+    if (((latm >> i) & 1) && lane < cnti && (unsigned)dx < 8u && (unsigned)dy < 8u) W[i * kWP + dx + 8 * dy] = w[i];
+  }
+  __syncthreads();
+  // D (16 leaves x 16 columns per tile) += A (16 leaves x 4 positions) B (4 positions x 16 columns)
+  const int r16 = lane % 16, kq = lane / 16;
+  v4d acc[kTiles];
+#pragma unroll
+  for (int tl = 0; tl < kTiles; ++tl) acc[tl] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const double a = W[r16 * kWP + 4 * s + kq];
+#pragma unroll
+    for (int tl = 0; tl < kTiles; ++tl) {
+      const double b = zt[(4 * s + kq) * kZW + tl * 16 + r16];
+      acc[tl] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[tl], 0, 0, 0);
+    }
+  }
+  // lane (r16, kq), element e: leaf 4 e + kq, column 16 tl + r16
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = 4 * e + kq;
+    const int ci = __shfl(c, i);
+    if (!((latm >> i) & 1)) continue;
+    double* out = reinterpret_cast<double*>(mp + (int64_t)ci * (p + 1));
+#pragma unroll
+    for (int tl = 0; tl < kTiles; ++tl) {
+      const int col = tl * 16 + r16;
+      if (col < 2 * (p + 1)) out[col] = acc[tl][e];
+    }
+  }
+  // the wave's other leaves, eight at a time, 8 lanes each
+  uint64_t gen = genm;
+  while (gen) {
+    const int grp = lane / 8;
+    uint64_t m = gen;
+    for (int q = 0; q < grp && m; ++q) m &= m - 1;
+    const bool st = m != 0;
+    const int i = st ? __builtin_ctzll(m) : __builtin_ctzll(gen);
+    const int ci = __shfl(c, i);
+    p2m_leaf<PM, 8>(t, ci, lane % 8, st, ij, nullptr, nullptr, 0.0, 0.0, 1.0, w64, p, mp);
+    for (int q = 0; q < 8 && gen; ++q) gen &= gen - 1;
+  }
 }
 
 // M2M as fixed matrices.  With coefficients scaled by the cell side, the shift
@@ -682,6 +806,25 @@ void p2m_lanes(TreeView t, const int* sleaves, int n, const uint32_t* ij, const 
 void p2m(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys, double x0,
          double y0, double u, const double* w64, int p, double2* mp, hipStream_t s) {
   if (n <= 0) return;
+  // grid sources: leaves 8 nodes wide on the matrix cores (PP_P2M_LATTICE=0: lane groups for all)
+  static const bool lattice = [] {
+    const char* e = std::getenv("PP_P2M_LATTICE");
+    return !(e && e[0] == '0');
+  }();
+  if (ij && lattice) {
+    const unsigned g = (unsigned)(((int64_t)n + 63) / 64);
+    if (p <= 4)
+      k_p2m_lattice<4><<<g, 256, 0, s>>>(t, sleaves, n, ij, w64, p, mp);
+    else if (p <= 8)
+      k_p2m_lattice<8><<<g, 256, 0, s>>>(t, sleaves, n, ij, w64, p, mp);
+    else if (p <= 12)
+      k_p2m_lattice<12><<<g, 256, 0, s>>>(t, sleaves, n, ij, w64, p, mp);
+    else if (p <= 16)
+      k_p2m_lattice<16><<<g, 256, 0, s>>>(t, sleaves, n, ij, w64, p, mp);
+    else
+      k_p2m_lattice<kMaxP><<<g, 256, 0, s>>>(t, sleaves, n, ij, w64, p, mp);
+    return;
+  }
   // lanes per leaf: PP_P2M_LANES = 4, 8 (default) or 16
   static const int lanes = [] {
     const char* e = std::getenv("PP_P2M_LANES");

@@ -140,7 +140,8 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_count(const double* __rest
 // pass).  The tile's rows are staged in LDS in Morton order; each thread then
 // takes 8 consecutive indices, the workgroup scans the nonzero counts, the
 // kept nodes are compacted in LDS (weight and local index) and written out
-// with consecutive lanes on consecutive sources.
+// with consecutive lanes on consecutive sources.  A tile the counting pass
+// found empty is not read again (only its prefix starts are written).
 // starts (may be null): for every Morton prefix of 2 * sh bits (the cells of
 // the tree's dense table), the position of its first source, i.e. the number
 // of sources with a smaller key.
@@ -169,25 +170,40 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
     gv[u] = q < g ? grp[q] : 0;
   }
   const int inner = tile_pre[t];
+  const int next = (t + 1) % G == 0 ? grp[g] : tile_pre[t + 1];
+  const bool any = ts.f && next != inner;  // uniform over the workgroup
   double a[kPasses], b[kPasses];
 #pragma unroll
   for (int s = 0; s < kPasses; ++s) {
     a[s] = b[s] = 0.0;
-    if (ts.f) load_pair<VEC>(ts.f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
+    if (any) load_pair<VEC>(ts.f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
   }
   int acc = 0;
 #pragma unroll
   for (int u = 0; u < kGroupReads; ++u) acc += gv[u];
   int before;
-  block_excl_scan<kIngBlock>(acc, lds, &before);
+  block_excl_scan<kIngBlock>(acc, lds, &before);  // ends with a barrier
   before += inner;
+  const uint64_t mend = (uint64_t)1 << (2 * k);
+  const uint32_t pmask = (uint32_t)(((uint64_t)1 << (2 * sh)) - 1);
+  const int l0 = threadIdx.x * kItems;
+  if (!any) {
+    if (starts) {
+#pragma unroll
+      for (int q = 0; q < kItems; ++q) {
+        const uint32_t m = m0 | (uint32_t)(l0 + q);
+        if ((uint64_t)m < mend && (m & pmask) == 0) starts[m >> (2 * sh)] = before;
+      }
+    }
+    if (t == (int64_t)gridDim.x - 1 && threadIdx.x == 0) *total_out = before;
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < kPasses; ++s) {
     const uint32_t li = tile_index(2 * c, r + s * kRowsPerPass);  // even: the pair is adjacent
     *reinterpret_cast<double2*>(&wv[li]) = make_double2(a[s], b[s]);
   }
   __syncthreads();
-  const int l0 = threadIdx.x * kItems;
   double v[kItems];
 #pragma unroll
   for (int q = 0; q < kItems; q += 2) {
@@ -200,8 +216,6 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
   for (int q = 0; q < kItems; ++q) cn += v[q] != 0.0;
   int total;
   int pos = block_excl_scan<kIngBlock>(cn, lds, &total);  // ends with a barrier: wv is free
-  const uint64_t mend = (uint64_t)1 << (2 * k);
-  const uint32_t pmask = (uint32_t)(((uint64_t)1 << (2 * sh)) - 1);
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
     const uint32_t m = m0 | (uint32_t)(l0 + q);

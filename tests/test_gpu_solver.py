@@ -220,6 +220,45 @@ def test_fmm_per_pass_against_reference(solver):
             assert np.max(np.abs(locc[c] - ref_l)) < 1e-10 * scale, c
 
 
+def _case_leaf_widths(seed, n, sparse_zero):
+    """Grid leaves of several widths: 8-node leaves (most of them, some nodes culled), wider leaves in a
+    sparse quadrant (sparse_zero of its nodes zero), and 4-node leaves where a cluster of 150 targets splits
+    an 8-node cell."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = rng.standard_normal((n, n))
+    f[rng.uniform(size=f.shape) < 0.3] = 0.0
+    q = f[n // 2:, n // 2:]
+    q[rng.uniform(size=q.shape) < sparse_zero] = 0.0
+    h = 1.0 / n
+    tx = np.concatenate([(8 + 8 * rng.uniform(size=150)) * h, rng.uniform(0, 1, 300)])
+    ty = np.concatenate([(16 + 8 * rng.uniform(size=150)) * h, rng.uniform(0, 1, 300)])
+    return f, h, np.clip(tx, 0, 1 - 1e-12), np.clip(ty, 0, 1 - 1e-12)
+
+
+@pytest.mark.parametrize("n,p,sparse_zero", [(64, 12, 0.95), (64, 5, 0.95), (64, 17, 0.95), (128, 12, 0.85)])
+def test_p2m_leaf_widths_against_reference(solver, n, p, sparse_zero):
+    """P2M (Appendix A, eq. alphaK) of every source leaf, and M2M above it, against the reference
+    expansions: grid leaves 8 nodes wide (a fixed contraction over their 64 node positions) and leaves of
+    other widths (4, 16 and 32 nodes) in the same launch, several of them in one group of 16 leaves at
+    128^2; p = 5, 12 and 17 (one, two and three 16-column tiles of coefficients)."""
+    f, h, tx, ty = _case_leaf_widths(11 + n, n, sparse_zero)
+    solver.solve_grid(f, h, tx, ty, p=p, theta=0.5, leaf_max=64, precision="fp64")
+    r = fmm_ref.fmm_grid(f, tx, ty, h, p, 0.5, leaf_max=64)
+    t = r["tree"]
+    k = r["info"]["k"]
+    widths = {int(k - t.level[c]) for c in range(t.ncells) if t.leaf[c] and t.nsrc(c) > 0}
+    assert {2, 3} <= widths and max(widths) >= 4, widths
+    mp = solver.debug_array("MULTIPOLE").reshape(t.ncells, p + 1, 2)
+    mpc = mp[..., 0] + 1j * mp[..., 1]
+    kk = np.arange(p + 1)
+    for c in range(t.ncells):
+        if t.nsrc(c) == 0:
+            continue
+        s = h * 2.0 ** (k - t.level[c])
+        ref_a = np.concatenate([[r["S"][c]], -r["alpha"][c][1:]]) / s**kk
+        assert np.allclose(mpc[c], ref_a, rtol=1e-11, atol=1e-13 * abs(ref_a).max() + 1e-300), (c, t.level[c])
+
+
 def test_mixed_l2p_is_compensated(solver):
     """The mixed path's FP32 L2P is a compensated Horner evaluation (u and the coefficients carried as FP32
     pairs).  Both precisions build the same FP64 local expansions, so the mixed far field must equal the
