@@ -31,6 +31,58 @@ __device__ inline void pack_leaf_cell(int c, int lane, const TreeArrays& t, int 
   if (lane == 0) leaf_w[c] = acc;
 }
 
+// One wave packs the grid source leaves cs[0..n) (n <= 4, the same for every
+// lane) with their loads issued together; per leaf the same records and the
+// same weight sum (per-lane order, then the butterfly) as pack_leaf_cell.
+__device__ inline void pack_leaf_cells4(const int* cs, int n, int lane, const TreeArrays& t, int D,
+                                        const uint32_t* __restrict__ ij, const double* __restrict__ w64,
+                                        float* __restrict__ s32, int64_t stride, double* __restrict__ leaf_w) {
+  int cx[4], cy[4], sb[4], se[4];
+  int span = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    cx[q] = cy[q] = sb[q] = se[q] = 0;
+    if (q < n) {
+      const int c = cs[q];
+      const int sh = D - t.lvl[c];
+      cx[q] = t.ix[c] << sh;
+      cy[q] = t.iy[c] << sh;
+      sb[q] = t.sb[c];
+      se[q] = t.se[c];
+      span = max(span, se[q] - sb[q]);
+    }
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int o = lane; o < span; o += kWave) {
+    uint32_t v[4];
+    double w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int s = sb[q] + o;
+      const bool ok = s < se[q];
+      v[q] = ok ? ij[s] : 0u;
+      w[q] = ok ? w64[s] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int s = sb[q] + o;
+      if (s < se[q]) {
+        const int i = (int)(v[q] & 0xFFFFu), j = (int)(v[q] >> 16);
+        s32[s] = (float)(i - cx[q]) + 0.5f;
+        s32[stride + s] = (float)(j - cy[q]) + 0.5f;
+        s32[2 * stride + s] = (float)w[q];
+        acc[q] += w[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, kWave);
+    if (q < n && lane == 0) leaf_w[cs[q]] = acc[q];
+  }
+}
+
 // One wave packs source leaf sleaves[wid].
 __device__ inline void pack_leaf(int wid, int lane, const TreeArrays& t, const int* __restrict__ sleaves, int D,
                                  const uint32_t* __restrict__ ij, const double* __restrict__ w64,

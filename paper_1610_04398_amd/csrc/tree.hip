@@ -411,7 +411,8 @@ __global__ __launch_bounds__(256) void k_pack_prep(TreeArrays t, int D, PackArgs
 
 // Packing of the listed source leaves: one wave per target leaf claims the
 // leaves of its list that no wave has claimed yet (claim[B] 0 -> 1) and packs
-// each one it claimed, with all lanes.  (Queueing the claimed leaves for a
+// the ones it claimed with all lanes, grid leaves four at a time (their loads
+// issued together).  (Queueing the claimed leaves for a
 // second, wide launch was measured slower at 4096^2: that launch fills the
 // compute units the upward pass is using.)
 __global__ __launch_bounds__(256) void k_pack_listed(LeafPass lp, const int* __restrict__ tleaves, int ntleaves,
@@ -429,10 +430,27 @@ __global__ __launch_bounds__(256) void k_pack_listed(LeafPass lp, const int* __r
     const int B = e < nb ? lst[e] : -1;
     const bool mine = (unsigned)B < (unsigned)ncells && atomicExch(&claim[B], 1) == 0;
     uint64_t m = __ballot(mine);
-    while (m) {  // the leaves this wave claimed, one at a time
-      const int l = __builtin_ctzll(m);
-      m &= m - 1;
-      run_pack_cell(lp, __shfl(B, l, kWave), lane);
+    if (lp.kind == 1) {
+      while (m) {  // the leaves this wave claimed, up to four at a time
+        int cs[4];
+        int n = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cs[q] = 0;
+          if (m) {
+            cs[q] = __shfl(B, __builtin_ctzll(m), kWave);
+            m &= m - 1;
+            n = q + 1;
+          }
+        }
+        pack_leaf_cells4(cs, n, lane, lp.t, lp.D, lp.ga.ij, lp.ga.w64, lp.ga.s32, lp.ga.stride, lp.ga.leaf_w);
+      }
+    } else {
+      while (m) {  // the leaves this wave claimed, one at a time
+        const int l = __builtin_ctzll(m);
+        m &= m - 1;
+        run_pack_cell(lp, __shfl(B, l, kWave), lane);
+      }
     }
   }
 }
