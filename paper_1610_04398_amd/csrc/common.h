@@ -65,8 +65,12 @@ __device__ inline float two_prod(float a, float b, float& e) {
 // coefficient are carried as an FP32 pair (high part + rounding remainder),
 // whose low parts enter that error recurrence.  The result is as accurate as
 // an evaluation in twice FP32's precision.
-__device__ inline double l2p_eval(const double2* __restrict__ L, int p, double2 r, int D, int lvl, bool fp32) {
+__device__ inline double l2p_eval(const double2* __restrict__ Lg, int p, double2 r, int D, int lvl, bool fp32) {
   const double side = (double)(1 << (D - lvl)), inv = ldexp(1.0, lvl - D);
+  // every coefficient's load issued before the evaluation needs the first
+  double2 L[kMaxP + 1];
+#pragma unroll
+  for (int l = 0; l <= kMaxP; ++l) L[l] = l <= p ? Lg[l] : make_double2(0.0, 0.0);
   if (fp32) {
 #pragma clang fp contract(off)
     const double uxd = (r.x - 0.5 * side) * inv, uyd = (r.y - 0.5 * side) * inv;
@@ -74,7 +78,9 @@ __device__ inline double l2p_eval(const double2* __restrict__ L, int p, double2 
     const float uxl = (float)(uxd - (double)ux), uyl = (float)(uyd - (double)uy);
     float ax = 0.f, ay = 0.f;  // the running value
     float ex = 0.f, ey = 0.f;  // the running error
-    for (int l = p; l >= 0; --l) {
+#pragma unroll
+    for (int l = kMaxP; l >= 0; --l) {
+      if (l > p) continue;
       const double2 v = L[l];
       const float cx = (float)v.x, cy = (float)v.y;
       const float cxl = (float)(v.x - (double)cx), cyl = (float)(v.y - (double)cy);
@@ -101,7 +107,9 @@ __device__ inline double l2p_eval(const double2* __restrict__ L, int p, double2 
   }
   const cplx u = {(r.x - 0.5 * side) * inv, (r.y - 0.5 * side) * inv};
   cplx acc = {0.0, 0.0};
-  for (int l = p; l >= 0; --l) {
+#pragma unroll
+  for (int l = kMaxP; l >= 0; --l) {
+    if (l > p) continue;
     const double2 v = L[l];
     acc = cadd(cmul(acc, u), {v.x, v.y});
   }

@@ -74,8 +74,14 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(int64_t m, int nparts, c
   }
   if (k >= m) return;
   if (*flags != 0) return;
-  double ns = near_sum[k];
-  for (int q = 1; q < nparts; ++q) ns += near_sum[(int64_t)q * m + k];
+  // the parts' loads issued together, then summed in part order
+  double nsq[kMaxNearParts];
+#pragma unroll
+  for (int q = 0; q < kMaxNearParts; ++q) nsq[q] = q < nparts ? near_sum[(int64_t)q * m + k] : 0.0;
+  double ns = nsq[0];
+#pragma unroll
+  for (int q = 1; q < kMaxNearParts; ++q)
+    if (q < nparts) ns += nsq[q];
   double fv;
   if (fe.loc) {
     const int c = fe.tleaf[k];

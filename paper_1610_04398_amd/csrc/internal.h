@@ -224,6 +224,8 @@ void m2l(TreeView t, const int* tcells, int n, const int* m2l_off, const int* m2
 // List parts per target leaf in the tree-code's M2P (more, shorter waves than
 // one per leaf: the leaves with the longest lists no longer set the time).
 constexpr int kM2PParts = 4;
+// Largest number of near-field list parts per target leaf.
+constexpr int kMaxNearParts = 8;
 // M2P of the tree-code variant: the far field of every target of the n target
 // leaves from the multipoles of their M2P lists (off/cnt by cell id), each list
 // split into nparts parts whose partial sums go to far[part * m + k] (m

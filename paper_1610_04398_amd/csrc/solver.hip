@@ -729,12 +729,13 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
                  misc + M_FLAGS, s);
     }
   };
-  // cell lists over the whole tree (its size is the last level start, on the device)
-  auto classify = [&] {
+  // cell lists over the whole tree (its size is the last level start, on the
+  // device; bound: at least that many cells, the launch's size)
+  auto classify = [&](int64_t bound) {
     const TreeView tv0{D, 0, ta.lvl, ta.ix, ta.iy, ta.sb, ta.se, ta.tb, ta.te, ta.child, ta.nchild, ta.parent};
     const RecordArgs rec0{tv0, rec, cm2l, cp2p, om2l, op2p, cap_far, cap_near};
-    classify_cells(ta, ls_d + D + 1, (int)cap, flag3, sleaves, tleaves, tcells, misc + M_NSL,
-                   direct ? nullptr : &rec0, s);
+    classify_cells(ta, ls_d + D + 1, (int)std::min<int64_t>(bound, cap), flag3, sleaves, tleaves, tcells,
+                   misc + M_NSL, direct ? nullptr : &rec0, s);
   };
   const int seq1 = published_seq(c) + 1;
   // the retained tree: new weights for its sources, and the checks that it
@@ -783,7 +784,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     // 4^(D - Ld) nodes, so it is split only by its targets, which is rare:
     // the levels below are built after the read-back, only if one is.
     if (!src.grid) build_levels_below();
-    classify();
+    // grid sources: every cell so far is a cell of the dense table
+    classify(src.grid ? dense_F : cap);
     tend(PP_PHASE_TREE, s);
     publish_enqueue(c, misc, M_LS + D + 2, s);
   });
@@ -794,7 +796,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
       // a cell of the dense table's last level has more than leaf_max targets
       const int seq_deep = published_seq(c) + 1;
       build_levels_below();
-      classify();
+      classify(cap);
       publish_enqueue(c, misc, M_LS + D + 2, s);
       wait_published(c, s, seq_deep);
       check_flags(c.pinned[M_FLAGS]);
@@ -1395,7 +1397,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return PP_ERR_DEVICE;
   pp_ctx* c = new pp_ctx();
   c->device = device;
-  if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(8, std::max(1, std::atoi(e)));
+  if (const char* e = std::getenv("PP_P2P_PARTS")) c->p2p_parts = std::min(kMaxNearParts, std::max(1, std::atoi(e)));
   if (const char* e = std::getenv("PP_EXACT_LISTS")) c->exact_lists = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DIRECT_ISSUE")) c->direct_issue = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
