@@ -166,6 +166,17 @@ __global__ __launch_bounds__(256) void k_p2m(TreeView t, const int* __restrict__
 // products, 16 leaves per wave (rows), 4 positions per product, 16 columns per
 // tile.  Leaves of other sizes in the wave's 16 are done by the lane-group path
 // above, 8 lanes per leaf.
+// 1 / k, k = 1..kMaxP, each the correctly rounded quotient.
+struct InvIntTable {
+  double v[kMaxP + 1];
+};
+constexpr InvIntTable make_inv_int() {
+  InvIntTable t{};
+  for (int k = 1; k <= kMaxP; ++k) t.v[k] = 1.0 / k;
+  return t;
+}
+__constant__ InvIntTable c_inv_int = make_inv_int();
+
 template <int PM>
 __global__ __launch_bounds__(256) void k_p2m_lattice(TreeView t, const int* __restrict__ sleaves, int n,
                                                      const uint32_t* __restrict__ ij, const double* __restrict__ w64,
@@ -178,24 +189,6 @@ __global__ __launch_bounds__(256) void k_p2m_lattice(TreeView t, const int* __re
   __shared__ double zt[64 * kZW];
   __shared__ double wb[4 * 16 * kWP];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  if (threadIdx.x < 64) {
-    const int pos = threadIdx.x;
-    const cplx z = {((double)(pos & 7) + 0.5) * 0.125 - 0.5, ((double)(pos >> 3) + 0.5) * 0.125 - 0.5};
-    double* row = zt + pos * kZW;
-    row[0] = 1.0;
-    row[1] = 0.0;
-    cplx zk = z;
-#pragma unroll
-    for (int k = 1; k <= PM; ++k) {
-      row[2 * k] = -zk.x / k;
-      row[2 * k + 1] = -zk.y / k;
-      zk = cmul(zk, z);
-    }
-#pragma unroll
-    for (int col = kCols; col < kZW; ++col) row[col] = 0.0;
-  }
-  double* W = wb + wave * 16 * kWP;
-  for (int q = lane; q < 16 * kWP; q += kWave) W[q] = 0.0;
   // the wave's 16 leaves: lane i < 16 holds leaf i's cell, source range and corner
   const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 16;
   int c = 0, sb = 0, cnt = 0, cx = 0, cy = 0;
@@ -221,6 +214,25 @@ __global__ __launch_bounds__(256) void k_p2m_lattice(TreeView t, const int* __re
     v[i] = ok ? ij[sbi + lane] : 0u;
     w[i] = ok ? w64[sbi + lane] : 0.0;
   }
+  // while the loads are in flight: Z (first wave) and the cleared weight blocks
+  if (threadIdx.x < 64) {
+    const int pos = threadIdx.x;
+    const cplx z = {((double)(pos & 7) + 0.5) * 0.125 - 0.5, ((double)(pos >> 3) + 0.5) * 0.125 - 0.5};
+    double* row = zt + pos * kZW;
+    row[0] = 1.0;
+    row[1] = 0.0;
+    cplx zk = z;
+#pragma unroll
+    for (int k = 1; k <= PM; ++k) {
+      row[2 * k] = -zk.x * c_inv_int.v[k];
+      row[2 * k + 1] = -zk.y * c_inv_int.v[k];
+      zk = cmul(zk, z);
+    }
+#pragma unroll
+    for (int col = kCols; col < kZW; ++col) row[col] = 0.0;
+  }
+  double* W = wb + wave * 16 * kWP;
+  for (int q = lane; q < 16 * kWP; q += kWave) W[q] = 0.0;
   __syncthreads();  // Z and the cleared weight blocks
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
