@@ -100,6 +100,16 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __re
   const int t = threadIdx.x;
   const int lane = t % kWave;
   const int w = t / kWave;
+  // the tile's keys and values, loaded before anything waits on them
+  const int base = blockIdx.x * kRsTile;
+  uint32_t kq[kRsItems];
+  int vq[kRsItems];
+#pragma unroll
+  for (int q = 0; q < kRsItems; ++q) {
+    const int i = base + q * kRsBlock + t;
+    kq[q] = i < n ? kin[i] : 0u;
+    vq[q] = i < n ? vin[i] : 0;
+  }
   if (FOLD) {
     // thread t owns digits [t PER, t PER + PER)
     int tot[PER], pre[PER], sum = 0;
@@ -140,16 +150,12 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_scatter(const uint32_t* __re
   }
   __syncthreads();
   const uint64_t lt_mask = (lane == 0) ? 0ull : ((~0ull) >> (kWave - lane));
-  const int base = blockIdx.x * kRsTile;
+#pragma unroll
   for (int q = 0; q < kRsItems; ++q) {
     const int i = base + q * kRsBlock + t;
     const bool valid = i < n;
-    uint32_t key = 0;
-    int val = 0;
-    if (valid) {
-      key = kin[i];
-      val = vin[i];
-    }
+    const uint32_t key = kq[q];
+    const int val = vq[q];
     const int d = (key >> shift) & (BINS - 1);
     // lanes holding the same digit (valid lanes only), in lane order
     uint64_t peers = __ballot(valid);

@@ -237,8 +237,15 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_offsets(const int* __rest
   const int64_t F = dense_level_offset(Ld + 1);
   const int nb = (int)((F + kDenseBlock - 1) / kDenseBlock);
   const int upto = blockIdx.x == 0 ? nb : (int)blockIdx.x;
+  // eight loads in flight per thread, added in index order
   int acc = 0;
-  for (int i = threadIdx.x; i < upto; i += kDenseBlock) acc += part[i];
+  for (int i0 = threadIdx.x; i0 < upto; i0 += 8 * kDenseBlock) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i0 + u * kDenseBlock < upto ? part[i0 + u * kDenseBlock] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
   int before;
   block_excl_scan<kDenseBlock>(acc, lds, &before);
   if (blockIdx.x == 0) {
@@ -352,11 +359,22 @@ __global__ __launch_bounds__(kClsBlock) void k_classify_emit(TreeArrays t, const
   if (blockIdx.x > 0 && base >= n) return;  // uniform per workgroup
   // offsets of this tile (and, in workgroup 0, the totals of all tiles)
   const int upto = blockIdx.x == 0 ? ntiles : (int)blockIdx.x;
+  // four tiles' counts in flight per thread, added in index order
   int p0 = 0, p1 = 0, p2 = 0;
-  for (int i = threadIdx.x; i < upto; i += kClsBlock) {
-    p0 += part[3 * i];
-    p1 += part[3 * i + 1];
-    p2 += part[3 * i + 2];
+  for (int i0 = threadIdx.x; i0 < upto; i0 += 4 * kClsBlock) {
+    int v[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = i0 + u * kClsBlock;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) v[u][r] = i < upto ? part[3 * i + r] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      p0 += v[u][0];
+      p1 += v[u][1];
+      p2 += v[u][2];
+    }
   }
   int s0, s1, s2;
   block_excl_scan<kClsBlock>(p0, lds, &s0);
