@@ -66,15 +66,26 @@ def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
 
+_F64 = None  # torch.float64, looked up once
+
+
 def _ptr(x, name: str):
     """(pointer, keep-alive object) for a float64 contiguous torch tensor or NumPy array."""
+    global _F64
     if _is_torch(x):
-        import torch
-        if x.dtype != torch.float64 or not x.is_contiguous():
+        if _F64 is None:
+            import torch
+            _F64 = torch.float64
+        if x.dtype != _F64 or not x.is_contiguous():
             raise TypeError(f"{name} must be a contiguous float64 tensor")
         return x.data_ptr(), x
     a = np.ascontiguousarray(np.asarray(x), dtype=np.float64)
     return a.ctypes.data, a
+
+
+def _count(x) -> int:
+    """Number of elements of a torch tensor or NumPy array."""
+    return int(x.numel()) if _is_torch(x) else int(x.size)
 
 
 class Solver:
@@ -104,8 +115,8 @@ class Solver:
         ny, nx = fshape
         xp, xk = _ptr(tx, "tx")
         yp, yk = _ptr(ty, "ty")
-        m = int(np.prod(tuple(xk.shape)))
-        if int(np.prod(tuple(yk.shape))) != m:
+        m = _count(xk)
+        if _count(yk) != m:
             raise ValueError("tx and ty differ in length")
         if out is None:
             if torch_mode:
@@ -183,8 +194,8 @@ class Solver:
         fp, fk = _ptr(f, "f")
         xp, xk = _ptr(tx, "tx")
         yp, yk = _ptr(ty, "ty")
-        m = int(np.prod(tuple(xk.shape)))
-        if int(np.prod(tuple(yk.shape))) != m:
+        m = _count(xk)
+        if _count(yk) != m:
             raise ValueError("tx and ty differ in length")
         if out is None:
             if torch_mode:
@@ -195,7 +206,7 @@ class Solver:
         op, ok = _ptr(out, "out")
         shape = getattr(self, "_resident_shape", None)
         if shape is not None and (tuple(fk.shape) != shape[:2] or m != shape[2] or
-                                  int(np.prod(tuple(ok.shape))) != m):
+                                  _count(ok) != m):
             raise ValueError(f"f must have shape {shape[:2]} and there must be {shape[2]} targets and outputs")
         if stream is None:
             stream = 0
@@ -219,13 +230,13 @@ class Solver:
         sxp, sxk = _ptr(sx, "sx")
         syp, syk = _ptr(sy, "sy")
         wp, wk = _ptr(w, "w")
-        n = int(np.prod(tuple(sxk.shape)))
-        if int(np.prod(tuple(syk.shape))) != n or int(np.prod(tuple(wk.shape))) != n:
+        n = _count(sxk)
+        if _count(syk) != n or _count(wk) != n:
             raise ValueError("sx, sy and w differ in length")
         xp, xk = _ptr(tx, "tx")
         yp, yk = _ptr(ty, "ty")
-        m = int(np.prod(tuple(xk.shape)))
-        if int(np.prod(tuple(yk.shape))) != m:
+        m = _count(xk)
+        if _count(yk) != m:
             raise ValueError("tx and ty differ in length")
         if out is None:
             if torch_mode:
@@ -299,7 +310,7 @@ class Solver:
         vp, vk = _ptr(v, "v")
         gy, gx = tuple(uk.shape)
         ptrs = [_ptr(a, nm) for a, nm in ((lx, "lx"), (ly, "ly"), (nx, "nx"), (ny, "ny"), (ds, "ds"))]
-        m = int(np.prod(tuple(ptrs[0][1].shape)))
+        m = _count(ptrs[0][1])
         seg = np.ascontiguousarray(np.asarray(seg_start, dtype=np.int64))
         nseg = seg.size - 1
         res = (B.pp_force * max(nseg, 1))()
@@ -332,7 +343,7 @@ class Solver:
         nxp, nxk = _ptr(nx, "nx")
         nyp, nyk = _ptr(ny, "ny")
         dsp, dsk = _ptr(ds, "ds")
-        m = int(np.prod(tuple(pk.shape)))
+        m = _count(pk)
         seg = np.ascontiguousarray(np.asarray(seg_start, dtype=np.int64))
         nseg = seg.size - 1
         out = (B.pp_force * max(nseg, 1))()
@@ -416,7 +427,7 @@ class Server:
         if ok is not out:
             raise TypeError("out must be a contiguous float64 array or tensor")
         ny, nx = tuple(fk.shape)
-        m = int(np.prod(tuple(xk.shape)))
+        m = _count(xk)
         req = B.pp_request(nx, ny, float(x0), float(y0), float(h), fp, m, xp, yp,
                            make_params(p, theta, leaf_max, precision, self_mode, method), op)
         t = pp_server_submit(self._srv, req)
