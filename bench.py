@@ -88,8 +88,9 @@ def phase_work(st: dict, w: dict, parts: int) -> dict:
     passes = math.ceil(2 * D / 8)
     cp = 16 * (p + 1)  # bytes of one expansion
     return {
-        # read f once, write key, node index and weight of every kept source
-        "ingest": ("hbm", 8 * G + 16 * N, "B"),
+        # read f once, write the node index and weight of every kept source (its key is the Morton index
+        # of the node, formed where needed)
+        "ingest": ("hbm", 8 * G + 12 * N, "B"),
         # target keys from the coordinates, then (key, index) read and written per radix pass
         "sort": ("hbm", 24 * M + passes * 16 * M, "B"),
         # sorted keys read once, cell arrays and list records written once

@@ -149,7 +149,7 @@ template <bool VEC>
 __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restrict__ f, int nx, int ny, int k,
                                                             double h2, const int* __restrict__ tile_pre,
                                                             const int* __restrict__ grp, int G,
-                                                            int* __restrict__ total_out, uint32_t* __restrict__ key,
+                                                            int* __restrict__ total_out,
                                                             uint32_t* __restrict__ ij, double* __restrict__ w64,
                                                             int* __restrict__ starts, int sh, GridBatch bt) {
   __shared__ double wv[kIngTile];     // node values in Morton order, then the kept weights
@@ -230,7 +230,6 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
   for (int q = threadIdx.x; q < total; q += kIngBlock) {
     const int64_t o = (int64_t)before + q;
     const uint32_t li = lix[q];
-    key[o] = m0 | li;
     ij[o] = (uint32_t)(ts.vx + i0 + (int)compact_bits(li)) | ((uint32_t)(ts.vy + j0 + (int)compact_bits(li >> 1)) << 16);
     w64[o] = wv[q];
   }
@@ -238,15 +237,16 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
 }
 
 // Resident weights: tile blockIdx.x of the new f is staged in LDS in Morton
-// order as above; its retained sources (the key range the counting pass of the
-// retained tree gave the tile) take w = f h^2 from it and mark their nodes in
-// a bitmap, and a nonzero node left unmarked (a node outside the retained
-// tree) raises kFlagStale.  Nodes that became zero keep their place with w = 0.
+// order as above; its retained sources (the range the counting pass of the
+// retained tree gave the tile; their node indices locate them in the tile)
+// take w = f h^2 from it and mark their nodes in a bitmap, and a nonzero node
+// left unmarked (a node outside the retained tree) raises kFlagStale.  Nodes
+// that became zero keep their place with w = 0.
 template <bool VEC>
 __global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __restrict__ f, int nx, int ny,
                                                                  double h2, const int* __restrict__ tile_pre,
                                                                  const int* __restrict__ grp, int G,
-                                                                 const uint32_t* __restrict__ key, int64_t n,
+                                                                 const uint32_t* __restrict__ ij, int64_t n,
                                                                  double* __restrict__ w64, int* __restrict__ flags) {
   __shared__ double wv[kIngTile];
   __shared__ uint32_t kept[kIngTile / 32];
@@ -291,11 +291,13 @@ __global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __
       stale = 1;
       break;
     }
-    const uint32_t li = key[o] - m0;
-    if (li >= (uint32_t)kIngTile) {
+    const uint32_t v = ij[o];
+    const uint32_t dx = (v & 0xFFFFu) - (uint32_t)i0, dy = (v >> 16) - (uint32_t)j0;
+    if (dx >= (uint32_t)kTileW || dy >= (uint32_t)kTileH) {
       stale = 1;
       continue;
     }
+    const uint32_t li = tile_index(dx, dy);
     w64[o] = wv[li] * h2;
     atomicOr(&kept[li >> 5], 1u << (li & 31));
   }
@@ -382,28 +384,41 @@ void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, in
 }
 
 void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, int* total_out,
-                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, const GridBatch* bt,
-                      hipStream_t s) {
+                      uint32_t* ij, double* w64, int* starts, int sh, const GridBatch* bt, hipStream_t s) {
   const int G = group_tiles(k);
   const int64_t nt = ingest_num_tiles(k);
   const GridBatch b = bt ? *bt : GridBatch{};
   if (vec_ok_all(f, nx, bt))
     k_ingest_emit<true><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_cnt, tile_cnt + nt, G, total_out,
-                                                            key, ij, w64, starts, sh, b);
+                                                            ij, w64, starts, sh, b);
   else
     k_ingest_emit<false><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, k, h2, tile_cnt, tile_cnt + nt, G, total_out,
-                                                             key, ij, w64, starts, sh, b);
+                                                             ij, w64, starts, sh, b);
 }
 
-void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* key,
+__global__ void k_keys_from_ij(const uint32_t* __restrict__ ij, const int* __restrict__ n_dev, int64_t n,
+                               uint32_t* __restrict__ key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t lim = n_dev ? std::min<int64_t>(*n_dev, n) : n;
+  if (i >= lim) return;
+  const uint32_t v = ij[i];
+  key[i] = spread_bits(v & 0xFFFFu) | (spread_bits(v >> 16) << 1);
+}
+
+void keys_from_ij(const uint32_t* ij, const int* n_dev, int64_t n, uint32_t* key, hipStream_t s) {
+  if (n <= 0) return;
+  k_keys_from_ij<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ij, n_dev, n, key);
+}
+
+void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* ij,
                       int64_t n, double* w64, int* flags, hipStream_t s) {
   const int G = group_tiles(k);
   const int64_t nt = ingest_num_tiles(k);
   if (vec_ok(f, nx))
-    k_resident_weights<true><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, h2, tile_cnt, tile_cnt + nt, G, key, n,
+    k_resident_weights<true><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, h2, tile_cnt, tile_cnt + nt, G, ij, n,
                                                                  w64, flags);
   else
-    k_resident_weights<false><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, h2, tile_cnt, tile_cnt + nt, G, key, n,
+    k_resident_weights<false><<<(unsigned)nt, kIngBlock, 0, s>>>(f, nx, ny, h2, tile_cnt, tile_cnt + nt, G, ij, n,
                                                                   w64, flags);
 }
 

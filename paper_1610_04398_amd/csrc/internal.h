@@ -67,18 +67,21 @@ int64_t ingest_count_ints(int k);
 // root exponent).
 void ingest_grid_count(const double* f, int nx, int ny, int k, int* tile_cnt, int* flags, const GridBatch* bt,
                        hipStream_t s);
-// Second pass: the sources in Morton order (key, packed node index ij,
-// w = f h^2) and *total_out = their count.  starts (may be null): the source
-// range start of every Morton prefix of 2 * sh bits (cells of the dense table
-// sh levels above the finest).
+// Second pass: the sources in Morton order (packed node index ij = i | j << 16
+// in the forest's index space, w = f h^2) and *total_out = their count; a
+// source's key is the Morton index of (i, j) (keys_from_ij).  starts (may be
+// null): the source range start of every Morton prefix of 2 * sh bits (cells
+// of the dense table sh levels above the finest).
 void ingest_grid_emit(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, int* total_out,
-                      uint32_t* key, uint32_t* ij, double* w64, int* starts, int sh, const GridBatch* bt,
-                      hipStream_t s);
+                      uint32_t* ij, double* w64, int* starts, int sh, const GridBatch* bt, hipStream_t s);
+// key[i] = Morton index of source i's node (from ij), i < *n_dev (n_dev may be
+// null: n sources); n bounds *n_dev.
+void keys_from_ij(const uint32_t* ij, const int* n_dev, int64_t n, uint32_t* key, hipStream_t s);
 // Resident solves (the tree of the last solve kept, new f on the same grid):
-// w = f h^2 of the n retained sources (keys key, tile counts tile_cnt of the
-// retained solve), in one pass over f; kFlagStale when a node outside them is
-// nonzero (retained nodes may have become zero).
-void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* key,
+// w = f h^2 of the n retained sources (node indices ij, tile counts tile_cnt
+// of the retained solve), in one pass over f; kFlagStale when a node outside
+// them is nonzero (retained nodes may have become zero).
+void resident_weights(const double* f, int nx, int ny, int k, double h2, const int* tile_cnt, const uint32_t* ij,
                       int64_t n, double* w64, int* flags, hipStream_t s);
 // kFlagStale unless every target (caller index perm[q]) still has the sorted key key[q].
 void resident_targets(const double* tx, const double* ty, int64_t m, const int* perm, const uint32_t* key, double x0,

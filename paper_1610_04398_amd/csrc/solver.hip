@@ -94,6 +94,7 @@ struct Last {
   bool has_locals = false;
   int nparts = 1;
   bool arena = false;  // its arrays are pieces of the workspace (pp_solve_grid_noalloc)
+  bool keys_from_ij = false;  // grid sources: the source keys are formed from the node indices on request
 };
 
 // The tree of the last successful grid solve, kept for resident solves
@@ -745,7 +746,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     mark(PP_PHASE_INGEST);
     fill_i32(misc, 0, kMiscInts, s);
     tbegin(PP_PHASE_INGEST, s);
-    resident_weights(f_d, nx, ny, k, unit * unit, tile, skey, R.N, sw, misc + M_FLAGS, s);
+    resident_weights(f_d, nx, ny, k, unit * unit, tile, sij, R.N, sw, misc + M_FLAGS, s);
     tend(PP_PHASE_INGEST, s);
     mark(PP_PHASE_SORT);
     tbegin(PP_PHASE_SORT, s);
@@ -760,7 +761,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     if (src.grid) {
       // ---- ingest: sources in Morton order (no sort needed for a grid) ----
       ingest_grid_count(f_d, nx, ny, k, tile, misc + M_FLAGS, batch, s);
-      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, misc + M_NSRC, skey, sij, sw, dss, D - Ld, batch, s);
+      ingest_grid_emit(f_d, nx, ny, k, unit * unit, tile, misc + M_NSRC, sij, sw, dss, D - Ld, batch, s);
     } else if (src.n > 0) {
       // ---- ingest: keys of the scattered sources, stable sort, sorted copies ----
       int* sperm = (int*)sij;
@@ -793,8 +794,11 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
     wait_published(c, s, seq1);
     check_flags(c.pinned[M_FLAGS]);
     if (src.grid && c.pinned[M_DEEP]) {
-      // a cell of the dense table's last level has more than leaf_max targets
+      // a cell of the dense table's last level has more than leaf_max targets;
+      // the levels below search the source keys, which the grid ingest leaves
+      // implicit in the node indices
       const int seq_deep = published_seq(c) + 1;
+      keys_from_ij(sij, misc + M_NSRC, nmax, skey, s);
       build_levels_below();
       classify(cap);
       publish_enqueue(c, misc, M_LS + D + 2, s);
@@ -1298,6 +1302,7 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   c.last.has_locals = !direct && !treecode;
   c.last.nparts = nparts;
   c.last.arena = c.arena;
+  c.last.keys_from_ij = src.grid;
   c.cur_stream = nullptr;
   return PP_OK;
 }
@@ -1788,6 +1793,18 @@ pp_status pp_debug_copy(const pp_ctx* cc, int32_t what, void* dst, int64_t capac
   if (length) *length = n;
   const int64_t cnt = std::min(n, std::max<int64_t>(capacity, 0));
   if (cnt <= 0) return PP_OK;
+  DevBuf* bufs = L.arena ? c->abufs : c->bufs;
+  if (what == PP_ARR_SRC_KEY && L.keys_from_ij) {
+    if (hipSetDevice(c->device) != hipSuccess) {
+      c->err = "copy failed";
+      return PP_ERR_DEVICE;
+    }
+    keys_from_ij((const uint32_t*)bufs[B_SIJ].p, nullptr, n, (uint32_t*)bufs[B_SKEY].p, nullptr);
+    if (hipDeviceSynchronize() != hipSuccess) {
+      c->err = "forming the source keys failed";
+      return PP_ERR_DEVICE;
+    }
+  }
   if (hipSetDevice(c->device) != hipSuccess ||
       hipMemcpy(dst, (L.arena ? c->abufs : c->bufs)[id].p, (size_t)cnt * esz, hipMemcpyDeviceToHost) != hipSuccess) {
     c->err = "copy failed";
