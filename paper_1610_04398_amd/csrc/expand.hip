@@ -816,14 +816,11 @@ void p2m_lanes(TreeView t, const int* sleaves, int n, const uint32_t* ij, const 
 }
 
 void p2m(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys, double x0,
-         double y0, double u, const double* w64, int p, double2* mp, hipStream_t s) {
+         double y0, double u, const double* w64, int p, double2* mp, int64_t lattice_min, hipStream_t s) {
   if (n <= 0) return;
-  // grid sources: leaves 8 nodes wide on the matrix cores (PP_P2M_LATTICE=0: lane groups for all)
-  static const bool lattice = [] {
-    const char* e = std::getenv("PP_P2M_LATTICE");
-    return !(e && e[0] == '0');
-  }();
-  if (ij && lattice) {
+  // grid sources with at least lattice_min leaves: leaves 8 nodes wide on
+  // the matrix cores
+  if (ij && lattice_min > 0 && n >= lattice_min) {
     const unsigned g = (unsigned)(((int64_t)n + 63) / 64);
     if (p <= 4)
       k_p2m_lattice<4><<<g, 256, 0, s>>>(t, sleaves, n, ij, w64, p, mp);

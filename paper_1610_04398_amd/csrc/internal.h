@@ -212,7 +212,7 @@ bool frontier_at_top(int num, int den, int tier_boost);
 // by their coordinates xs, ys in a root square anchored at (x0, y0) with
 // finest cell side u.
 void p2m(TreeView t, const int* sleaves, int n, const uint32_t* ij, const double* xs, const double* ys, double x0,
-         double y0, double u, const double* w64, int p, double2* mp, hipStream_t s);
+         double y0, double u, const double* w64, int p, double2* mp, int64_t lattice_min, hipStream_t s);
 // M2M for the `levels` (1..m2m_max_levels()) levels starting at the level
 // whose cells are [c0, c1): one workgroup per cell computes its subtree
 // bottom up.

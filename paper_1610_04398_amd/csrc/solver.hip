@@ -142,6 +142,12 @@ struct pp_ctx {
   // every source leaf)
   bool lazy_pack = true;
   bool resident_graph = false;  // PP_RESIDENT_GRAPH=1: a resident solve replayed as one graph
+  // P2M of grid sources on the matrix cores from this many source leaves up
+  // (PP_P2M_LATTICE; 0: never).  With few leaves its long workgroups (64
+  // leaves each, 51 KB of LDS) leave most of the chip idle and crowd the list
+  // launch beside them: at 512^2 (4,300 leaves) P2M took 17.7 µs against 10.8
+  // for the lane groups and the solve was 4-12 % slower.
+  int64_t p2m_lattice_min = 32768;
   int profiling = 0;  // 0 off, 1 every phase, 2 the near-field launch only, 16 + phase that phase's launches
   hipEvent_t ev[13] = {};
   // launch replay: each of the two segments of a solve (up to the tree read-back, and
@@ -1011,7 +1017,8 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   auto do_p2m = [&] {
     mark(PP_PHASE_P2M);
     tbegin(PP_PHASE_P2M, s);
-    if (!direct) p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, s);
+    if (!direct)
+      p2m(tv, sleaves, nsl, src.grid ? sij : nullptr, pxs, pys, x0, y0, unit, sw, p, mp, c.p2m_lattice_min, s);
     tend(PP_PHASE_P2M, s);
   };
   auto do_m2m = [&] {
@@ -1408,6 +1415,7 @@ pp_status pp_create(int32_t device, uint64_t hbm_budget_bytes, pp_ctx** out) {
   if (const char* e = std::getenv("PP_DENSE_LEVELS")) c->dense_levels = std::min(9, std::max(0, std::atoi(e)));
   if (const char* e = std::getenv("PP_LAZY_PACK")) c->lazy_pack = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_RESIDENT_GRAPH")) c->resident_graph = std::atoi(e) != 0;
+  if (const char* e = std::getenv("PP_P2M_LATTICE")) c->p2m_lattice_min = std::max(0LL, std::atoll(e));
   if (const char* e = std::getenv("PP_GRAPHS")) c->graphs = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_NEAR_STREAM")) c->near_stream = std::atoi(e) != 0;
   if (const char* e = std::getenv("PP_LIST_CAPS")) {  // "m2l,p2p[,m2p,tree-code p2p]" initial capacities

@@ -235,14 +235,30 @@ def _case_leaf_widths(seed, n, sparse_zero):
     return f, h, np.clip(tx, 0, 1 - 1e-12), np.clip(ty, 0, 1 - 1e-12)
 
 
+@pytest.mark.parametrize("lattice", ["1", "0"])
 @pytest.mark.parametrize("n,p,sparse_zero", [(64, 12, 0.95), (64, 5, 0.95), (64, 17, 0.95), (128, 12, 0.85)])
-def test_p2m_leaf_widths_against_reference(solver, n, p, sparse_zero):
+def test_p2m_leaf_widths_against_reference(monkeypatch, lattice, n, p, sparse_zero):
     """P2M (Appendix A, eq. alphaK) of every source leaf, and M2M above it, against the reference
-    expansions: grid leaves 8 nodes wide (a fixed contraction over their 64 node positions) and leaves of
-    other widths (4, 16 and 32 nodes) in the same launch, several of them in one group of 16 leaves at
-    128^2; p = 5, 12 and 17 (one, two and three 16-column tiles of coefficients)."""
+    expansions, with the matrix-core path forced for any number of leaves (grid leaves 8 nodes wide as a
+    fixed contraction over their 64 node positions, leaves of other widths, 4, 16 and 32 nodes, in the same
+    launch, several of them in one group of 16 leaves at 128^2) and with the lane groups for every leaf;
+    p = 5, 12 and 17 (one, two and three 16-column tiles of coefficients)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_04398_amd as pp
+    monkeypatch.setenv("PP_P2M_LATTICE", lattice)
+    solver = pp.Solver(0)
     f, h, tx, ty = _case_leaf_widths(11 + n, n, sparse_zero)
-    solver.solve_grid(f, h, tx, ty, p=p, theta=0.5, leaf_max=64, precision="fp64")
+    try:
+        solver.solve_grid(f, h, tx, ty, p=p, theta=0.5, leaf_max=64, precision="fp64")
+        _check_multipoles(solver, f, h, tx, ty, p)
+    finally:
+        solver.close()
+
+
+def _check_multipoles(solver, f, h, tx, ty, p):
+    """Every cell's scaled multipole coefficients against the reference FMM's, to 1e-11."""
     r = fmm_ref.fmm_grid(f, tx, ty, h, p, 0.5, leaf_max=64)
     t = r["tree"]
     k = r["info"]["k"]
