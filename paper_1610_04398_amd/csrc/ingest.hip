@@ -55,6 +55,18 @@ __device__ inline void load_pair(const double* __restrict__ f, int nx, int ny, i
 // Local Morton index of column x, row y inside a tile.
 __device__ inline uint32_t tile_index(uint32_t x, uint32_t y) { return spread_bits(x) | (spread_bits(y) << 1); }
 
+// Position in the LDS staging array of a tile's node li (Morton order).  The
+// pairs of doubles are permuted (bits 4-7 of the pair index XORed into bits
+// 0-3, a bijection) so that both access patterns spread over the LDS banks:
+// a row pass (32 lanes on the pairs of one row: pair-index bits 1, 3, 5, 7, 9)
+// and the per-thread reads of 8 consecutive nodes (pair-index bits 2-7 from
+// the thread).  Unpermuted, each went to 4 of the 16 bank groups of a pair.
+__device__ inline uint32_t stage_pos(uint32_t li) {
+  const uint32_t d = li >> 1;
+  const uint32_t g = ((d >> 5) & 1u) | (((d >> 4) & 1u) << 1) | (((d >> 7) & 1u) << 2) | (((d >> 6) & 1u) << 3);
+  return ((d ^ g) << 1) | (li & 1u);
+}
+
 // Tile t of the (joint) Morton order: the grid it reads (null: an empty
 // forest cell), the tile's first node (i0, j0) in that grid, its first key
 // and the offset (vx, vy) of the grid's nodes in the joint index space.
@@ -201,13 +213,13 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
 #pragma unroll
   for (int s = 0; s < kPasses; ++s) {
     const uint32_t li = tile_index(2 * c, r + s * kRowsPerPass);  // even: the pair is adjacent
-    *reinterpret_cast<double2*>(&wv[li]) = make_double2(a[s], b[s]);
+    *reinterpret_cast<double2*>(&wv[stage_pos(li)]) = make_double2(a[s], b[s]);
   }
   __syncthreads();
   double v[kItems];
 #pragma unroll
   for (int q = 0; q < kItems; q += 2) {
-    const double2 p = *reinterpret_cast<const double2*>(&wv[l0 + q]);
+    const double2 p = *reinterpret_cast<const double2*>(&wv[stage_pos(l0 + q)]);
     v[q] = p.x;
     v[q + 1] = p.y;
   }
@@ -239,9 +251,10 @@ __global__ __launch_bounds__(kIngBlock) void k_ingest_emit(const double* __restr
 // Resident weights: tile blockIdx.x of the new f is staged in LDS in Morton
 // order as above; its retained sources (the range the counting pass of the
 // retained tree gave the tile; their node indices locate them in the tile)
-// take w = f h^2 from it and mark their nodes in a bitmap, and a nonzero node
-// left unmarked (a node outside the retained tree) raises kFlagStale.  Nodes
-// that became zero keep their place with w = 0.
+// take w = f h^2 from it and mark their nodes (a byte each: plain stores, the
+// retained nodes being distinct), and a nonzero node left unmarked (a node
+// outside the retained tree) raises kFlagStale.  Nodes that became zero keep
+// their place with w = 0.
 template <bool VEC>
 __global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __restrict__ f, int nx, int ny,
                                                                  double h2, const int* __restrict__ tile_pre,
@@ -249,7 +262,7 @@ __global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __
                                                                  const uint32_t* __restrict__ ij, int64_t n,
                                                                  double* __restrict__ w64, int* __restrict__ flags) {
   __shared__ double wv[kIngTile];
-  __shared__ uint32_t kept[kIngTile / 32];
+  __shared__ uint64_t kept[kIngTile / 8];  // a byte per node of the tile
   __shared__ int lds[kIngBlock / kWave + 1];
   const int64_t t = blockIdx.x;
   const uint32_t m0 = (uint32_t)(t << kTileBits);
@@ -267,7 +280,7 @@ __global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __
   double a[kPasses], b[kPasses];
 #pragma unroll
   for (int s = 0; s < kPasses; ++s) load_pair<VEC>(f, nx, ny, i0 + 2 * c, j0 + r + s * kRowsPerPass, &a[s], &b[s]);
-  if (threadIdx.x < kIngTile / 32) kept[threadIdx.x] = 0;
+  kept[threadIdx.x] = 0;  // kIngTile / 8 == kIngBlock
   int acc = 0;
 #pragma unroll
   for (int u = 0; u < kGroupReads; ++u) acc += gv[u];
@@ -280,32 +293,45 @@ __global__ __launch_bounds__(kIngBlock) void k_resident_weights(const double* __
   for (int s = 0; s < kPasses; ++s) {
     bad |= !isfinite(a[s]) || !isfinite(b[s]);
     const uint32_t li = tile_index(2 * c, r + s * kRowsPerPass);
-    *reinterpret_cast<double2*>(&wv[li]) = make_double2(a[s], b[s]);
+    *reinterpret_cast<double2*>(&wv[stage_pos(li)]) = make_double2(a[s], b[s]);
   }
   if (bad) atomicOr(flags, kFlagNonFiniteSource);
   __syncthreads();
   int stale = 0;
-  for (int q = threadIdx.x; q < cnt; q += kIngBlock) {
-    const int64_t o = (int64_t)before + q;
-    if (o >= n) {
-      stale = 1;
-      break;
+  uint8_t* kept8 = reinterpret_cast<uint8_t*>(kept);
+  // the retained node indices of the tile (at most 2048: eight per thread), loaded together
+  for (int q0 = threadIdx.x; q0 < cnt; q0 += kItems * kIngBlock) {
+    uint32_t vq[kItems];
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      const int q = q0 + u * kIngBlock;
+      const int64_t o = (int64_t)before + q;
+      vq[u] = q < cnt && o < n ? ij[o] : 0u;
     }
-    const uint32_t v = ij[o];
-    const uint32_t dx = (v & 0xFFFFu) - (uint32_t)i0, dy = (v >> 16) - (uint32_t)j0;
-    if (dx >= (uint32_t)kTileW || dy >= (uint32_t)kTileH) {
-      stale = 1;
-      continue;
+#pragma unroll
+    for (int u = 0; u < kItems; ++u) {
+      const int q = q0 + u * kIngBlock;
+      if (q >= cnt) continue;
+      const int64_t o = (int64_t)before + q;
+      if (o >= n) {
+        stale = 1;
+        continue;
+      }
+      const uint32_t dx = (vq[u] & 0xFFFFu) - (uint32_t)i0, dy = (vq[u] >> 16) - (uint32_t)j0;
+      if (dx >= (uint32_t)kTileW || dy >= (uint32_t)kTileH) {
+        stale = 1;
+        continue;
+      }
+      const uint32_t li = tile_index(dx, dy);
+      w64[o] = wv[stage_pos(li)] * h2;
+      kept8[li] = 1;
     }
-    const uint32_t li = tile_index(dx, dy);
-    w64[o] = wv[li] * h2;
-    atomicOr(&kept[li >> 5], 1u << (li & 31));
   }
   __syncthreads();
   const int l0 = threadIdx.x * kItems;
-  const uint32_t mask = (kept[l0 >> 5] >> (l0 & 31)) & 0xFFu;
+  const uint64_t mask = kept[threadIdx.x];  // the bytes of nodes l0 .. l0 + 7
 #pragma unroll
-  for (int q = 0; q < kItems; ++q) stale |= wv[l0 + q] != 0.0 && !((mask >> q) & 1u);
+  for (int q = 0; q < kItems; ++q) stale |= wv[stage_pos(l0 + q)] != 0.0 && !((mask >> (8 * q)) & 1u);
   if (stale) atomicOr(flags, kFlagStale);
 }
 
