@@ -487,6 +487,7 @@ __global__ __launch_bounds__(kM2LBlock) void k_m2l(TreeView t, const int* __rest
                                              const double2* __restrict__ mp, double2* __restrict__ loc,
                                              int* __restrict__ flags) {
   static_assert(2 * (PM + 1) <= 2 * G, "two partial values per coefficient and at most two per lane");
+  __builtin_assume(p >= 1);  // the orders the library accepts
   __shared__ double red[kM2LBlock][2 * (PM + 1)];
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int gi = (int)(gtid / G);
@@ -516,18 +517,19 @@ __global__ __launch_bounds__(kM2LBlock) void k_m2l(TreeView t, const int* __rest
     const cplx tt = cscale(inv, sA);
     const cplx mr = cscale(inv, -sB);           // -s_B / z0
     const double2* a = mp + (int64_t)B * (p + 1);
-    const double a0 = a[0].x;
+    // all p + 1 coefficients are requested before the first is used: the
+    // index is clamped to p (inside the cell's own block; p >= 1) and the
+    // terms past p are zeroed, so no load waits behind a branch
+    double2 av[PM + 1];
+#pragma unroll
+    for (int k = 0; k <= PM; ++k) av[k] = a[k <= p ? k : p];
+    const double a0 = av[0].x;
     cplx bk[PM + 1];
     cplx pw = mr;
     cplx sum0 = {a0 * (0.5 * log(r2) + lnh), 0.0};
 #pragma unroll
     for (int k = 1; k <= PM; ++k) {
-      if (k <= p) {
-        const double2 v = a[k];
-        bk[k] = cmul({v.x, v.y}, pw);
-      } else {
-        bk[k] = {0.0, 0.0};
-      }
+      bk[k] = k <= p ? cmul({av[k].x, av[k].y}, pw) : cplx{0.0, 0.0};
       pw = cmul(pw, mr);
       sum0 = cadd(sum0, bk[k]);
     }
