@@ -951,8 +951,10 @@ pp_status run_solve(pp_ctx& c, bool direct, bool exact_lists, const Sources& src
   // (the allocation-free solve keeps one stream: no stream or event is created for it)
   if (c.profiling != 1 && c.near_stream && !c.arena) {
     if (!c.side_stream) HIPCHK(hipStreamCreateWithFlags(&c.side_stream, hipStreamNonBlocking));
+    // the events order work between two streams of one device: a device-scope
+    // release and acquire suffice (the host never inspects them)
     for (hipEvent_t* e : {&c.ev_fork, &c.ev_lists, &c.ev_join})
-      if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+      if (!*e) HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming | hipEventDisableSystemFence));
     ss = c.side_stream;
   }
   // `from` signals `to` through event e (no-op without the side stream)
