@@ -600,12 +600,14 @@ __global__ __launch_bounds__(kWave) void k_downward(TreeView t, const int* __res
   // request's cells the lane assignment (and sums) of its lone solve
   for (int a = top + sub; a <= lc; a += kDownLanes) {
     if (a == lc) {
+      // every coefficient requested before the first is added (index clamped
+      // to p, terms past p dropped), so no load waits behind a branch
+      double2 v[PM + 1];
+#pragma unroll
+      for (int k = 0; k <= PM; ++k) v[k] = own[(int64_t)c * P1 + (k <= p ? k : p)];
 #pragma unroll
       for (int k = 0; k <= PM; ++k)
-        if (k <= p) {
-          const double2 v = own[(int64_t)c * P1 + k];
-          acc[k] = cadd(acc[k], {v.x, v.y});
-        }
+        if (k <= p) acc[k] = cadd(acc[k], {v[k].x, v[k].y});
       continue;
     }
     const int sh = lc - a;
