@@ -29,10 +29,20 @@ __global__ __launch_bounds__(kRsBlock) void k_radix_hist(const uint32_t* __restr
   for (int b = threadIdx.x; b < BINS; b += kRsBlock) h[b] = 0;
   __syncthreads();
   const int base = blockIdx.x * kRsTile;
+  // the tile's keys are all requested before the first count
+  uint32_t kv[kRsItems];
+#pragma unroll
   for (int q = 0; q < kRsItems; ++q) {
     const int i = base + q * kRsBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (BINS - 1)], 1);
+    kv[q] = i < n ? keys[i] : 0u;
   }
+  // (an empty statement that takes the keys keeps the compiler from moving a
+  // load down into the branch of its count)
+#pragma unroll
+  for (int q = 0; q < kRsItems; ++q) asm volatile("" : "+v"(kv[q]));
+#pragma unroll
+  for (int q = 0; q < kRsItems; ++q)
+    if (base + q * kRsBlock + (int)threadIdx.x < n) atomicAdd(&h[(kv[q] >> shift) & (BINS - 1)], 1);
   __syncthreads();
   for (int b = threadIdx.x; b < BINS; b += kRsBlock) hist[b * nblocks + blockIdx.x] = h[b];
 }

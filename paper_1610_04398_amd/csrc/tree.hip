@@ -275,30 +275,40 @@ __global__ void k_dense_write(TreeArrays t, const int* __restrict__ flag, const 
     for (int L = Ld + 1; L <= D + 1; ++L) ls[L] = min(total, cap);
     if (total > cap) atomicOr(flags, kFlagCellOverflow);
   }
-  if (idx >= F || !flag[idx]) return;
-  const int id = off[idx];
-  if (id >= cap) return;
+  if (idx >= F) return;
   const int L = dense_level_of(idx);
   const int64_t P = idx - dense_level_offset(L);
   const int sh = 2 * (Ld - L);
+  // everything the cell's record needs is requested at once (indices that
+  // depend only on its place in the table), before its flag is tested
+  const int fl = flag[idx], id = off[idx];
+  const int sb = ss[P << sh], se = ss[(P + 1) << sh], tb = ts[P << sh], te = ts[(P + 1) << sh];
+  const int par = L == 0 ? -1 : off[dense_level_offset(L - 1) + (P >> 2)];
+  const int64_t c0 = L < Ld ? dense_level_offset(L + 1) + 4 * P : idx;  // (idx: an in-bounds stand-in)
+  const int64_t c1 = L < Ld ? c0 + 1 : idx, c2 = L < Ld ? c0 + 2 : idx, c3 = L < Ld ? c0 + 3 : idx;
+  int f0 = flag[c0], f1 = flag[c1], f2 = flag[c2], f3 = flag[c3], o0 = off[c0];
+  // (an empty statement that takes the values keeps the compiler from moving
+  // these loads behind the test below)
+  asm volatile("" : "+v"(f0), "+v"(f1), "+v"(f2), "+v"(f3), "+v"(o0));
+  const int n4 = f0 + f1 + f2 + f3;
+  if (!fl || id >= cap) return;
   t.lvl[id] = L;
   t.ix[id] = (int)compact_bits((uint32_t)P);
   t.iy[id] = (int)compact_bits((uint32_t)(P >> 1));
-  t.sb[id] = ss[P << sh];
-  t.se[id] = ss[(P + 1) << sh];
-  t.tb[id] = ts[P << sh];
-  t.te[id] = ts[(P + 1) << sh];
-  t.parent[id] = L == 0 ? -1 : off[dense_level_offset(L - 1) + (P >> 2)];
+  t.sb[id] = sb;
+  t.se[id] = se;
+  t.tb[id] = tb;
+  t.te[id] = te;
+  t.parent[id] = par;
   int n = 0, first = -1;
   if (L < Ld) {
-    const int64_t c0 = dense_level_offset(L + 1) + 4 * P;
-    n = flag[c0] + flag[c0 + 1] + flag[c0 + 2] + flag[c0 + 3];
-    first = n > 0 && off[c0] + n <= cap ? off[c0] : -1;
+    n = n4;
+    first = n > 0 && o0 + n <= cap ? o0 : -1;
     if (first < 0) n = 0;
   }
   t.child[id] = first;
   t.nchild[id] = n;
-  if (L == Ld && Ld < D && (t.se[id] - t.sb[id] > leaf_max || t.te[id] - t.tb[id] > leaf_max)) atomicOr(deep, 1);
+  if (L == Ld && Ld < D && (se - sb > leaf_max || te - tb > leaf_max)) atomicOr(deep, 1);
 }
 
 // flag[kind * n + c] for kind 0 = leaf with sources, 1 = leaf with targets,
