@@ -181,18 +181,80 @@ __device__ inline int lower_bound_from(const uint32_t* __restrict__ a, int n, ui
   return (int)lo;
 }
 
+// lower_bound of key in a[0, n) by one wave: 64 lanes probe 64 evenly spaced
+// entries of the bracket [lo, hi) at once and the ballot of "entry < key"
+// narrows it to one gap, so the search takes log64(n) rounds of loads (3 for
+// 32,768 keys) instead of the log2(n) rounds of a bisection.  Every lane
+// returns the same index.
+__device__ inline int wave_lower_bound(const uint32_t* __restrict__ a, int n, uint64_t key) {
+  const int lane = threadIdx.x % kWave;
+  int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+  while (lo < hi) {
+    const int64_t len = hi - lo;
+    const int64_t pos = lo + (len * lane) / kWave;  // < hi
+    const uint64_t below = __ballot((uint64_t)a[pos] < key);
+    const int c = __popcll(below);  // probes 0 .. c-1 lie below the key
+    if (c == 0) {
+      hi = lo;
+    } else {
+      const int64_t plast = lo + (len * (c - 1)) / kWave;
+      hi = c == kWave ? hi : lo + (len * c) / kWave;
+      lo = plast + 1;
+    }
+  }
+  return (int)lo;
+}
+
+// Target starts of one workgroup's kDenseStartsBlock consecutive prefixes:
+// two waves find the range [tlo, thi) of target keys that the workgroup's
+// prefixes span (wave_lower_bound); if it fits, the range is staged in LDS
+// and each thread bisects there, otherwise in global memory within the range.
+constexpr int kDenseStartsBlock = 256;
+constexpr int kDenseStartsLds = 2048;
+
 // src_done: the source starts ss[0..np) were written by the ingest (grid
 // sources, whose ingest visits every Morton index in order); only ss[np].
-__global__ void k_dense_starts(const uint32_t* __restrict__ skey, const int* __restrict__ nsrc_dev,
-                               const uint32_t* __restrict__ tkey, int ntgt, int D, int Ld, int src_done,
-                               int* __restrict__ ss, int* __restrict__ ts) {
+__global__ __launch_bounds__(kDenseStartsBlock) void k_dense_starts(
+    const uint32_t* __restrict__ skey, const int* __restrict__ nsrc_dev, const uint32_t* __restrict__ tkey, int ntgt,
+    int D, int Ld, int src_done, int* __restrict__ ss, int* __restrict__ ts) {
+  __shared__ uint32_t kv[kDenseStartsLds];
+  __shared__ int range[2];
   const int64_t np = (int64_t)1 << (2 * Ld);
-  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sh = 2 * (D - Ld);
+  const int64_t P0 = (int64_t)blockIdx.x * kDenseStartsBlock;
+  const int64_t P = P0 + threadIdx.x;
+  const int w = threadIdx.x / kWave;
+  if (w < 2) {
+    // prefixes P0 and P0 + block (past np the key exceeds every target key)
+    const int64_t Pb = w == 0 ? P0 : P0 + kDenseStartsBlock;
+    const int r = wave_lower_bound(tkey, ntgt, (uint64_t)Pb << sh);
+    if (threadIdx.x % kWave == 0) range[w] = r;
+  }
+  __syncthreads();
+  const int tlo = range[0], thi = range[1];
+  const bool staged = thi - tlo <= kDenseStartsLds;
+  if (staged)
+    for (int i = threadIdx.x; i < thi - tlo; i += kDenseStartsBlock) kv[i] = tkey[tlo + i];
+  __syncthreads();
   if (P > np) return;
-  const uint64_t key = (uint64_t)P << (2 * (D - Ld));
+  const uint64_t key = (uint64_t)P << sh;
   const int ns = *nsrc_dev;
   if (!src_done || P == np) ss[P] = P == np ? ns : lower_bound_from(skey, ns, key, (P * (int64_t)ns) / np);
-  ts[P] = lower_bound_from(tkey, ntgt, key, (P * (int64_t)ntgt) / np);
+  int t;
+  if (staged) {
+    int lo = 0, hi = thi - tlo;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((uint64_t)kv[mid] < key)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    t = tlo + lo;
+  } else {
+    t = tlo + lower_bound_from(tkey + tlo, thi - tlo, key, ((P - P0) * (int64_t)(thi - tlo)) / kDenseStartsBlock);
+  }
+  ts[P] = t;
 }
 
 // Existence flag of every prefix-table cell, and per workgroup (kDenseBlock
@@ -532,7 +594,8 @@ void tree_dense_top(TreeArrays t, int* ls, int D, int Ld, int leaf_max, int spli
                     int* ts, int* flag, int* off, int* scan_tmp, int* total_slot, int* deep, int* flags,
                     hipStream_t s) {
   const int64_t np = ((int64_t)1 << (2 * Ld)) + 1;
-  k_dense_starts<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(skey, nsrc_dev, tkey, ntgt, D, Ld, src_done, ss, ts);
+  k_dense_starts<<<(unsigned)((np + kDenseStartsBlock - 1) / kDenseStartsBlock), kDenseStartsBlock, 0, s>>>(
+      skey, nsrc_dev, tkey, ntgt, D, Ld, src_done, ss, ts);
   const int64_t F = tree_dense_cells(Ld);
   const unsigned g = (unsigned)((F + kDenseBlock - 1) / kDenseBlock);
   k_dense_flags<<<g, kDenseBlock, 0, s>>>(ss, ts, D, Ld, leaf_max, split_above, flag, scan_tmp);
