@@ -102,6 +102,22 @@ def test_tree_bit_exact_adaptive(solver, seed, leaf_max, theta):
     _compare_tree(solver, info, theta, f.shape[1])
 
 
+def test_tree_bit_exact_clustered_targets(solver):
+    """Target starts of the dense prefix table when one workgroup's prefixes hold more targets than it
+    stages in LDS (3,000 targets inside a 3 x 3-cell square, searched in global memory within the
+    bracketed range) beside prefixes with few targets (1,000 spread ones, staged): the tree, the target
+    order and the lists equal the oracle's."""
+    n = 128
+    h = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(77))
+    f = rng.standard_normal((n, n))
+    tx = np.concatenate([rng.uniform(0.40, 0.42, 3000), rng.uniform(0.0, 1.0, 1000)])
+    ty = np.concatenate([rng.uniform(0.60, 0.62, 3000), rng.uniform(0.0, 1.0, 1000)])
+    solver.solve_grid(f, h, tx, ty, p=6, theta=0.5, leaf_max=64, precision="fp64")
+    info = tree_ref.grid_tree(f, tx, ty, h, leaf_max=64)
+    _compare_tree(solver, info, 0.5, n)
+
+
 def test_target_sort_multi_tile(solver):
     """The target sort over many tiles with a ragged tail, a third of the targets repeated (equal keys,
     whose input order the stable sort keeps) and the rest spread: keys and permutation equal the
