@@ -356,8 +356,8 @@ __device__ inline cplx m2m_child(int l, const double2* __restrict__ a, const dou
 // 512 threads: a workgroup of 8 waves finds room on a compute unit as soon as
 // two near-field workgroups (4 waves each) leave it, when the near field runs
 // beside the upward pass on another stream; 1024-thread workgroups waited far
-// longer for a whole free half of a compute unit.  (Launches of few
-// workgroups use 256 threads; see m2m_levels.)
+// longer for a whole free half of a compute unit.  (Launches of a few
+// workgroups, but more than one, use 256 threads; see m2m_levels.)
 constexpr int kM2MThreads = 512;
 constexpr int kM2MLevels = 3;
 constexpr int kM2MSlots = 85;  // 1 + 4 + 16 + 64
@@ -868,8 +868,11 @@ void m2m_levels(TreeView t, int c0, int c1, int L, int levels, int p, double2* m
   // A launch of few workgroups (the top levels) uses 256-thread workgroups:
   // beside the near field they find room on a compute unit sooner.  Alone
   // they are slower (M2M 50.6 -> 56.4 us at 4096^2), beside the near field
-  // faster (cold solves +1.5 %, resident +1.4 %; 128 threads: -5 %).
-  const int th = (c1 - c0) <= 1024 ? 256 : kM2MThreads;
+  // faster (cold solves +1.5 %, resident +1.4 %; 128 threads: -5 %).  A
+  // launch of one workgroup (the root's subtree) keeps 512 threads: its
+  // chain of levels is the whole launch (+0.8 % timed, +1.6 % untimed).
+  const int nb = c1 - c0;
+  const int th = nb > 1 && nb <= 1024 ? 256 : kM2MThreads;
   k_m2m<<<c1 - c0, th, m2m_lds_bytes(p), s>>>(t, c0, c1, L, levels, p, mp, dense_flag, dense_off, dense);
 }
 
